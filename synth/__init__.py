@@ -1,0 +1,106 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module generates inputs only (particle configurations and plain i.i.d.
+normal arrays); it holds none of the sampler's arithmetic.
+
+Configurations follow the paper's workloads (random hard-sphere suspensions,
+Sec. III): random sequential addition (RSA) at volume fraction phi in a cubic
+periodic box, optionally relaxed by hard-sphere Monte Carlo sweeps; uniform
+random points (overlaps allowed, for the overlap cases of the RPY tensor).
+The C part (csrc/hs_gen.c) is compiled on first use with gcc -fopenmp.
+"""
+import ctypes
+import os
+import subprocess
+from math import pi
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "csrc", "hs_gen.c")
+_LIB = os.path.join(_HERE, "_hs_gen.so")
+_lib = None
+
+
+def build(force=False):
+    """Compile the generator library in-tree (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.rsa_fill.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, dp, ctypes.c_longlong]
+        lib.rsa_fill.restype = ctypes.c_int
+        lib.mc_relax.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int, ctypes.c_uint64,
+                                 ctypes.c_double, dp, ctypes.c_int]
+        lib.mc_relax.restype = ctypes.c_double
+        lib.min_pair_distance.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        lib.min_pair_distance.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+def _dp(arr):
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def box_side(n, phi, a=1.0):
+    """Side of the cubic box holding n spheres of radius a at volume fraction phi."""
+    return (n * 4.0 * pi * a**3 / (3.0 * phi)) ** (1.0 / 3.0)
+
+
+def uniform_positions(n, L, seed):
+    """n points uniform in [0, L)^3 (overlaps allowed)."""
+    return np.random.default_rng(seed).uniform(0.0, L, size=(n, 3))
+
+
+def rsa_positions(n, L, a=1.0, seed=0, max_attempts=None):
+    """Random sequential addition of n non-overlapping spheres."""
+    x = np.zeros((n, 3), dtype=np.float64)
+    if max_attempts is None:
+        max_attempts = 2000 * n + 10**6
+    placed = _load().rsa_fill(n, L, a, seed, _dp(x), max_attempts)
+    if placed != n:
+        raise RuntimeError(f"RSA placed only {placed} of {n} spheres (phi too high for RSA)")
+    return x
+
+
+def mc_relax(x, L, a=1.0, sweeps=100, seed=0, target_acc=0.4, adapt_sweeps=None):
+    """Hard-sphere MC displacement sweeps in place; returns (x, step, last acceptance)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    step = ctypes.c_double(0.1 * a)
+    if adapt_sweeps is None:
+        adapt_sweeps = min(sweeps, 50)
+    acc = _load().mc_relax(len(x), L, a, _dp(x), sweeps, seed, target_acc, ctypes.byref(step), adapt_sweeps)
+    return x, step.value, acc
+
+
+def min_pair_distance(x, L, a=1.0):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return _load().min_pair_distance(len(x), L, a, _dp(x))
+
+
+def hard_spheres(n, phi, a=1.0, seed=0, sweeps=0):
+    """RSA at volume fraction phi, then `sweeps` MC sweeps. Returns (x, L)."""
+    L = box_side(n, phi, a)
+    x = rsa_positions(n, L, a, seed)
+    # relabel particles in spatial (cell) order: the same configuration, but
+    # memory-local for the Monte Carlo neighbour checks
+    c = np.floor(x / (3.0 * a)).astype(np.int64)
+    x = np.ascontiguousarray(x[np.lexsort((c[:, 2], c[:, 1], c[:, 0]))])
+    if sweeps:
+        x, _, _ = mc_relax(x, L, a, sweeps, seed + 7919)
+    return x, L
+
+
+def normals(seed, shape):
+    """i.i.d. standard normals (numpy PCG64), float64."""
+    return np.random.default_rng(seed).standard_normal(shape)
