@@ -230,8 +230,11 @@ def _image_shifts(L, rc):
 
 def real_pairs(x, L, xi, a, rc):
     """All (i, j, d) with d = x_i - x_j + R, 0 < |d| <= rc, over every lattice
-    image R (so rc may exceed L/2).  Returns i, j, d (arrays)."""
-    x = np.asarray(x, dtype=np.float64)
+    image R (so rc may exceed L/2).  Returns i, j, d (arrays).
+    Positions are defined modulo L (the Green's function of eq. green is
+    periodic); they are wrapped into [0, L) first so that the image range
+    |R| <= ceil(rc/L) L covers every pair."""
+    x = np.mod(np.asarray(x, dtype=np.float64), L)
     N = len(x)
     shifts = _image_shifts(L, rc)
     I, J, D = [], [], []

@@ -111,3 +111,16 @@ def test_free_rpy_tensor_values():
     T2 = rpy.rpy_free_tensor(np.array([2.0 + 1e-12, 0, 0]), a, 1.0) * 6 * np.pi
     np.testing.assert_allclose(T2, T, atol=1e-11)
     np.testing.assert_allclose(rpy.rpy_free_tensor(np.zeros(3), a, 1.0) * 6 * np.pi, np.eye(3))
+
+
+def test_real_block_is_periodic_in_positions():
+    """Shifting any particle by a lattice vector (several box lengths)
+    leaves M_r unchanged: positions are defined modulo L."""
+    rng = np.random.default_rng(8)
+    L, xi, rc = 10.0, 0.6, 4.5
+    x = rng.uniform(0, L, (12, 3))
+    y = x.copy()
+    y[3] += L * np.array([2, -3, 1])
+    y[7] -= L * np.array([0, 0, 4])
+    np.testing.assert_allclose(rpy.real_block_dense(y, L, 1.0, 1.0, xi, rc),
+                               rpy.real_block_dense(x, L, 1.0, 1.0, xi, rc), atol=1e-15)
