@@ -1,0 +1,174 @@
+/* pse.h — C ABI of the MI355X (gfx950) Positively Split Ewald Brownian sampler.
+ *
+ * Method: Fiore, Balboa Usabiaga, Donev, Swan, "Rapid Sampling of Stochastic
+ * Displacements in Brownian Dynamics Simulations" (arXiv:1611.09322).
+ *
+ * For N equal spheres of radius a in a cubic periodic box of side L, the
+ * library returns displacements
+ *
+ *     dx = dt M F + sqrt(2 kT dt) ( M_r^{1/2} z1 + M_w^{1/2} z2 )      (eqs. langevin, split)
+ *
+ * with M = M_r + M_w the positively split periodic RPY mobility (eqs. Mwave,
+ * Mreal, Appendix A).  M_r^{1/2} z1 is a Lanczos (Krylov) approximation on the
+ * near-field real-space sum (Sec. II B.1); M_w^{1/2} z2 is drawn with Gaussian
+ * spreading/interpolation on an M^3 grid and FFTs (Spectral Ewald, Sec. II B.2).
+ *
+ * Conventions shared by every entry point
+ *  - Memory: every pointer argument named *_dev is device memory owned by the
+ *    caller, read or written on the context's stream; the library never frees
+ *    it.  The context owns all scratch (allocated in pse_create).
+ *  - Element type: double for PSE_FP64, float for PSE_FP32 and PSE_MIXED.
+ *  - Particle vectors (positions, forces, displacements, z1, velocities) are
+ *    n x 3, row-major, in the caller's particle order.
+ *  - Grid noise W is 3 x M x M x M, component-major, z fastest:
+ *    W[((c*M + ix)*M + iy)*M + iz] sits at node (ix, iy, iz) h, h = L/M.
+ *  - Calls are asynchronous on the stream given to pse_create, except where
+ *    noted: pse_set_positions and the sampling calls synchronise once to read
+ *    status (neighbour-list overflow, Lanczos convergence).
+ *  - Errors never abort: every call returns a pse_status.  After a non-zero
+ *    status the outputs are unspecified unless stated.
+ *  - One context per stream; calls on one context must not overlap.
+ */
+#ifndef PSE_H
+#define PSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSE_OK = 0,
+  PSE_ERR_INVALID_ARG = -1,   /* null pointer, n < 1, non-positive size ... */
+  PSE_ERR_OOM = -2,           /* device allocation failed */
+  PSE_ERR_HIP = -3,           /* a HIP runtime call failed */
+  PSE_ERR_PARAMS = -4,        /* parameters the error model rejects:
+                                 rcut >= L/2, eta_SE >= 1, M < P, odd P,
+                                 unsupported grid size */
+  PSE_ERR_NONFINITE = -5,     /* non-finite input or Lanczos scalar */
+  PSE_ERR_NOT_CONVERGED = -6, /* Lanczos hit max_iter; best iterate written */
+  PSE_ERR_NO_POSITIONS = -7,  /* sampling before pse_set_positions */
+  PSE_WARN_PRECOND_FALLBACK = 1
+} pse_status;
+
+typedef enum { PSE_FP64 = 0, PSE_FP32 = 1, PSE_MIXED = 2 } pse_precision;
+
+typedef struct {
+  int32_t n;                /* number of particles (>= 1) */
+  double box;               /* cubic box side L */
+  double a;                 /* sphere radius */
+  double eta;               /* viscosity */
+  double kT;                /* thermal energy */
+  double xi;                /* Ewald splitting parameter (eq. green2, eq. Mwave) */
+  double rcut;              /* real-space cutoff, < L/2 (minimum image) */
+  int32_t grid;             /* M: grid points per side; 8 <= M <= 512,
+                               M = 2^p or 3*2^p */
+  int32_t support;          /* P: Gaussian support points per side, even, <= 16 */
+  double gauss_m;           /* Gaussian truncation in standard deviations;
+                               0 selects sqrt(pi P) (Sec. II C) */
+  double lanczos_tol;       /* successive-iterate tolerance of the Krylov sample */
+  int32_t lanczos_max_iter; /* <= 64 */
+  int32_t precision;        /* pse_precision */
+  int32_t precond;          /* 0: none; 1: learned block preconditioner */
+  uint32_t flags;           /* reserved, 0 */
+} pse_params;
+
+typedef struct {
+  int32_t lanczos_iters;    /* Krylov iterations used by the last real-space sample */
+  int32_t converged;        /* 1 if the tolerance was met */
+  double lanczos_rel_change;/* final ||y_m - y_{m-1}|| / ||y_m|| */
+  int32_t max_neighbors;    /* largest near-field neighbour count */
+  int32_t precond_fallbacks;/* particles whose learned block fell back to I */
+} pse_stats;
+
+typedef struct {
+  double h;                 /* grid spacing L/M */
+  double sigma;             /* Gaussian standard deviation P h / (2 m) */
+  double gauss_m;           /* m actually used */
+  double eta_se;            /* 4 xi^2 sigma^2; must be < 1 */
+  double eps_real;          /* exp(-xi^2 rcut^2)                (Sec. II C) */
+  double eps_wave;          /* analytic k_cut bound, k_cut = pi/h (Sec. II D) */
+  double eps_quad;          /* exp(-pi^2 P^2/2m^2) + erfc(m/sqrt2) (Sec. II C) */
+  int32_t cells;            /* linked cells per side for the near-field sum */
+  double self_real;         /* real-space self mobility, eq. (self), / (6 pi eta a) */
+} pse_derived;
+
+/* Status text for a pse_status value (static string). */
+const char *pse_status_string(pse_status s);
+
+typedef struct pse_ctx pse_ctx;
+
+/* Create a sampling context for the parameters `p` on HIP stream `stream`
+ * (a hipStream_t; NULL = the null stream).  Validates the parameters against
+ * the error model (Sec. II C), builds the real-space F/G table (Appendix A,
+ * evaluated in FP64), and allocates every scratch buffer: sorted particle
+ * arrays, cell list, neighbour list, Lanczos basis (max_iter+1 vectors of 3n)
+ * and the 3 M^3 grid.  *out receives the context (NULL on failure).
+ * Errors: INVALID_ARG (null pointers), PARAMS (see pse_status), OOM, HIP. */
+pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out);
+
+/* Release the context and its scratch.  NULL is accepted. */
+pse_status pse_destroy(pse_ctx *ctx);
+
+/* Derived quantities of the error model for this context (host struct). */
+pse_status pse_get_derived(const pse_ctx *ctx, pse_derived *out);
+
+/* Set the particle positions (pos_dev: n x 3).  Positions are wrapped into
+ * [0, L) (a coordinate equal to L maps to 0); overlapping spheres are allowed
+ * (the RPY form stays SPD, eq. pairmobility).  Builds the linked-cell list,
+ * the sorted particle order and the near-field neighbour list (Sec. III: the
+ * real-space sum uses cell and neighbour lists).  Synchronises once.
+ * Errors: NONFINITE (a coordinate is not finite), OOM (neighbour list). */
+pse_status pse_set_positions(pse_ctx *ctx, const void *pos_dev);
+
+/* One Brownian displacement with the library's own noise:
+ *   disp = dt (M_r + M_w) F + sqrt(2 kT dt)(M_r^{1/2} z1 + M_w^{1/2} z2)
+ * z1 and z2 are drawn from Philox-4x64-10 (Salmon et al., SC'11):
+ *  - uniforms u = ((w >> 11) + 1/2) 2^-53 (FP64) or ((w >> 40) + 1/2) 2^-24
+ *    (FP32/MIXED) from 64-bit words w; Box-Muller on word pairs (wa, wb):
+ *    sqrt(-2 ln ua) (cos, sin)(2 pi ub);
+ *  - z1[q], q = 3 i + d (caller order): key (seed, 0), counter
+ *    (q >> 2, counter, 0, 0), normal number q & 3 of the block;
+ *  - z2 on the stored half spectrum, element e = ((c M + jx) M + jy)(M/2) + jz
+ *    (jz < M/2): key (seed, 1), counter (e >> 1, counter, 0, 0),
+ *    zeta = (n_{2p} + i n_{2p+1})/sqrt 2, p = e & 1; on the plane jz = 0 the
+ *    member of each (k, -k) pair with signed jy > 0 (or jy = 0, jx > 0) draws
+ *    and its partner is the conjugate; k = 0 and Nyquist indices are zero.
+ * The wave
+ * part applies B(k)^{1/2} (eq. Mwave) in k-space and one inverse 3D FFT plus
+ * Gaussian interpolation; with forces the deterministic wave term shares that
+ * inverse FFT (Sec. III, combined FFT pair).  forces_dev may be NULL (then
+ * dt M F is omitted).  disp_dev: n x 3 output.  stats may be NULL.
+ * Errors: NO_POSITIONS, NOT_CONVERGED (disp still written), NONFINITE. */
+pse_status pse_sample(pse_ctx *ctx, uint64_t seed, uint64_t counter, double dt,
+                      const void *forces_dev, void *disp_dev, pse_stats *stats);
+
+/* Same displacement with caller-supplied noise: z1_dev (n x 3 standard
+ * normals) and W_dev (3 x M^3 real standard normals on the grid nodes; the
+ * k-space noise is zeta = DFT(W)/M^{3/2}, fluctuating-hydrodynamics form).
+ * Either may be NULL (that part is omitted).  forces_dev may be NULL. */
+pse_status pse_sample_with_noise(pse_ctx *ctx, const void *z1_dev, const void *W_dev,
+                                 double dt, const void *forces_dev, void *disp_dev,
+                                 pse_stats *stats);
+
+/* w = M_r v (near-field real-space product, eq. Mreal), v_dev/w_dev n x 3. */
+pse_status pse_real_matvec(pse_ctx *ctx, const void *v_dev, void *w_dev);
+
+/* y = M_r^{1/2} z1 by Lanczos (Sec. II B.1), z1_dev/y_dev n x 3. */
+pse_status pse_real_sample(pse_ctx *ctx, const void *z1_dev, void *y_dev, pse_stats *stats);
+
+/* y = M_w^{1/2} z2 with grid noise W_dev (3 x M^3), y_dev n x 3 (Sec. II B.2). */
+pse_status pse_wave_sample(pse_ctx *ctx, const void *W_dev, void *y_dev);
+
+/* u = M_w F (spread, forward FFT, B(k), inverse FFT, interpolate), n x 3. */
+pse_status pse_wave_apply(pse_ctx *ctx, const void *forces_dev, void *u_dev);
+
+/* u = (M_r + M_w) F, the deterministic mobility product (n x 3). */
+pse_status pse_mobility_apply(pse_ctx *ctx, const void *forces_dev, void *u_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

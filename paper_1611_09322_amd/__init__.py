@@ -1,0 +1,284 @@
+"""Python binding of the gfx950 PSE Brownian sampler (libpse.so).
+
+Argument marshalling only: every step of the sampler runs in the HIP library.
+The functions named pse_* mirror the C ABI declared in include/pse.h one to
+one; `Sampler` is a small convenience wrapper over them.  Device memory and
+the stream come from PyTorch (ROCm build): tensors must live on a HIP device
+with the element type of the context's precision (float64 for "fp64",
+float32 for "fp32" and "mixed").  There is no CPU fallback: without the built
+library every call raises.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpse.so")
+
+PSE_OK = 0
+PSE_ERR_NOT_CONVERGED = -6
+PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("box", ctypes.c_double),
+        ("a", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("xi", ctypes.c_double),
+        ("rcut", ctypes.c_double),
+        ("grid", ctypes.c_int32),
+        ("support", ctypes.c_int32),
+        ("gauss_m", ctypes.c_double),
+        ("lanczos_tol", ctypes.c_double),
+        ("lanczos_max_iter", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("lanczos_iters", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("lanczos_rel_change", ctypes.c_double),
+        ("max_neighbors", ctypes.c_int32),
+        ("precond_fallbacks", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Derived(ctypes.Structure):
+    _fields_ = [
+        ("h", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("gauss_m", ctypes.c_double),
+        ("eta_se", ctypes.c_double),
+        ("eps_real", ctypes.c_double),
+        ("eps_wave", ctypes.c_double),
+        ("eps_quad", ctypes.c_double),
+        ("cells", ctypes.c_int32),
+        ("self_real", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PSEError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_SIGS = {
+    "pse_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "pse_create": ([ctypes.POINTER(Params), _VP, ctypes.POINTER(_VP)], ctypes.c_int),
+    "pse_destroy": ([_VP], ctypes.c_int),
+    "pse_get_derived": ([_VP, ctypes.POINTER(Derived)], ctypes.c_int),
+    "pse_set_positions": ([_VP, _VP], ctypes.c_int),
+    "pse_sample": ([_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, _VP, _VP, ctypes.POINTER(Stats)],
+                   ctypes.c_int),
+    "pse_sample_with_noise": ([_VP, _VP, _VP, ctypes.c_double, _VP, _VP, ctypes.POINTER(Stats)], ctypes.c_int),
+    "pse_real_matvec": ([_VP, _VP, _VP], ctypes.c_int),
+    "pse_real_sample": ([_VP, _VP, _VP, ctypes.POINTER(Stats)], ctypes.c_int),
+    "pse_wave_sample": ([_VP, _VP, _VP], ctypes.c_int),
+    "pse_wave_apply": ([_VP, _VP, _VP], ctypes.c_int),
+    "pse_mobility_apply": ([_VP, _VP, _VP], ctypes.c_int),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def load():
+    """Load libpse.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} missing (run __graft_entry__.build())")
+        # PyTorch-ROCm ships its own HIP runtime under the same soname; load it
+        # first so that the library binds to that one runtime (device pointers
+        # and streams from torch are then valid in the library).
+        import torch  # noqa: F401
+
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+def pse_status_string(status):
+    return load().pse_status_string(int(status)).decode()
+
+
+status_string = pse_status_string
+
+
+def _check(status, where, allow=()):
+    if status != PSE_OK and status not in allow:
+        raise PSEError(status, where)
+    return status
+
+
+def _ptr(t, dtype, numel, name):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------- C ABI mirror
+def pse_create(params, stream=None):
+    ctx = _VP()
+    _check(load().pse_create(ctypes.byref(params), _VP(stream or 0), ctypes.byref(ctx)), "pse_create")
+    return ctx
+
+
+def pse_destroy(ctx):
+    return load().pse_destroy(ctx)
+
+
+def pse_get_derived(ctx):
+    d = Derived()
+    _check(load().pse_get_derived(ctx, ctypes.byref(d)), "pse_get_derived")
+    return d
+
+
+def pse_set_positions(ctx, pos_ptr):
+    return _check(load().pse_set_positions(ctx, pos_ptr), "pse_set_positions")
+
+
+def pse_sample(ctx, seed, counter, dt, forces_ptr, disp_ptr):
+    st = Stats()
+    s = load().pse_sample(ctx, seed, counter, dt, forces_ptr, disp_ptr, ctypes.byref(st))
+    _check(s, "pse_sample", allow=(PSE_ERR_NOT_CONVERGED,))
+    return s, st
+
+
+def pse_sample_with_noise(ctx, z1_ptr, W_ptr, dt, forces_ptr, disp_ptr):
+    st = Stats()
+    s = load().pse_sample_with_noise(ctx, z1_ptr, W_ptr, dt, forces_ptr, disp_ptr, ctypes.byref(st))
+    _check(s, "pse_sample_with_noise", allow=(PSE_ERR_NOT_CONVERGED,))
+    return s, st
+
+
+def pse_real_matvec(ctx, v_ptr, w_ptr):
+    return _check(load().pse_real_matvec(ctx, v_ptr, w_ptr), "pse_real_matvec")
+
+
+def pse_real_sample(ctx, z_ptr, y_ptr):
+    st = Stats()
+    s = load().pse_real_sample(ctx, z_ptr, y_ptr, ctypes.byref(st))
+    _check(s, "pse_real_sample", allow=(PSE_ERR_NOT_CONVERGED,))
+    return s, st
+
+
+def pse_wave_sample(ctx, W_ptr, y_ptr):
+    return _check(load().pse_wave_sample(ctx, W_ptr, y_ptr), "pse_wave_sample")
+
+
+def pse_wave_apply(ctx, f_ptr, u_ptr):
+    return _check(load().pse_wave_apply(ctx, f_ptr, u_ptr), "pse_wave_apply")
+
+
+def pse_mobility_apply(ctx, f_ptr, u_ptr):
+    return _check(load().pse_mobility_apply(ctx, f_ptr, u_ptr), "pse_mobility_apply")
+
+
+# ----------------------------------------------------------------- wrapper
+class Sampler:
+    """One sampling context.  Tensors are (n, 3) on the current HIP device;
+    the context runs on torch's current stream at construction."""
+
+    def __init__(self, n, box, a=1.0, eta=1.0, kT=1.0, xi=0.5, rcut=None, grid=64, support=8, gauss_m=0.0,
+                 tol=1e-4, max_iter=64, precision="fp32", stream=None):
+        import torch
+
+        self.torch = torch
+        self.n = int(n)
+        self.grid = int(grid)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        if rcut is None:
+            rcut = 4.0 / xi
+        self.params = Params(self.n, box, a, eta, kT, xi, rcut, self.grid, support, gauss_m, tol, max_iter,
+                             PRECISION[precision], 0, 0)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        self.ctx = pse_create(self.params, stream)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            pse_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def derived(self):
+        return pse_get_derived(self.ctx).as_dict()
+
+    def _vec(self, t, name):
+        return _ptr(t, self.dtype, 3 * self.n, name)
+
+    def _new(self):
+        return self.torch.empty((self.n, 3), dtype=self.dtype, device="cuda")
+
+    def set_positions(self, pos):
+        pse_set_positions(self.ctx, self._vec(pos, "positions"))
+
+    def sample(self, seed, counter, dt=1.0, forces=None, out=None):
+        out = self._new() if out is None else out
+        s, st = pse_sample(self.ctx, seed, counter, dt, self._vec(forces, "forces"), self._vec(out, "out"))
+        return out, st
+
+    def sample_with_noise(self, z1=None, W=None, dt=1.0, forces=None, out=None):
+        out = self._new() if out is None else out
+        Wp = _ptr(W, self.dtype, 3 * self.grid**3, "W")
+        s, st = pse_sample_with_noise(self.ctx, self._vec(z1, "z1"), Wp, dt, self._vec(forces, "forces"),
+                                      self._vec(out, "out"))
+        return out, st
+
+    def real_matvec(self, v, out=None):
+        out = self._new() if out is None else out
+        pse_real_matvec(self.ctx, self._vec(v, "v"), self._vec(out, "out"))
+        return out
+
+    def real_sample(self, z, out=None):
+        out = self._new() if out is None else out
+        s, st = pse_real_sample(self.ctx, self._vec(z, "z"), self._vec(out, "out"))
+        return out, st
+
+    def wave_sample(self, W, out=None):
+        out = self._new() if out is None else out
+        pse_wave_sample(self.ctx, _ptr(W, self.dtype, 3 * self.grid**3, "W"), self._vec(out, "out"))
+        return out
+
+    def wave_apply(self, F, out=None):
+        out = self._new() if out is None else out
+        pse_wave_apply(self.ctx, self._vec(F, "forces"), self._vec(out, "out"))
+        return out
+
+    def mobility_apply(self, F, out=None):
+        out = self._new() if out is None else out
+        pse_mobility_apply(self.ctx, self._vec(F, "forces"), self._vec(out, "out"))
+        return out

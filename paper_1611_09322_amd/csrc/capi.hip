@@ -1,0 +1,462 @@
+// C ABI of the sampler: context life cycle and the composition of the hot path
+//   dx = dt (M_r + M_w) F + sqrt(2 kT dt) (M_r^{1/2} z1 + M_w^{1/2} z2)
+// (eqs. langevin, split).  Real space: cell list -> neighbour list ->
+// Lanczos on the near-field product.  Wave space: [spread F -> forward FFT]
+// -> B(k) scaling + noise (fused with the x pass) -> inverse FFT ->
+// interpolation; the deterministic and stochastic wave terms share one
+// inverse FFT (Sec. III).
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "launch.hpp"
+
+using namespace pse;
+
+namespace {
+
+struct Alloc {
+  pse_status st = PSE_OK;
+  void *dev(size_t bytes) {
+    if (st != PSE_OK) return nullptr;
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
+      st = PSE_ERR_OOM;
+      return nullptr;
+    }
+    return p;
+  }
+  void *host(size_t bytes) {
+    if (st != PSE_OK) return nullptr;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, bytes ? bytes : 16, hipHostMallocDefault) != hipSuccess) {
+      st = PSE_ERR_OOM;
+      return nullptr;
+    }
+    return p;
+  }
+};
+
+inline size_t tsize(const pse_ctx *c) { return c->dbl ? 8 : 4; }
+inline size_t asize(const pse_ctx *c) { return c->acc_dbl ? 8 : 4; }
+
+void free_ctx(pse_ctx *c) {
+  if (!c) return;
+  void *dev[] = {c->pos_w, c->pos_s, c->perm, c->cell_of, c->cell_count, c->cell_start, c->nbr, c->nbr_cnt,
+                 c->flags, c->V, c->lz, c->partials, c->counter, c->table, c->series, c->grid, c->grid2, c->tw_M,
+                 c->tw_H};
+  for (void *p : dev)
+    if (p) hipFree(p);
+  for (void *p : c->vbuf)
+    if (p) hipFree(p);
+  if (c->flags_h) hipHostFree(c->flags_h);
+  if (c->lz_h) hipHostFree(c->lz_h);
+  delete c;
+}
+
+template <typename T> void upload_twiddles(pse_ctx *c, Alloc &al) {
+  using CT = typename vec2<T>::type;
+  const int M = c->p.grid, H = M / 2;
+  std::vector<CT> a(M), b(H);
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < M; ++k) {
+    a[k].x = (T)std::cos(2 * pi * k / M);
+    a[k].y = (T)(-std::sin(2 * pi * k / M));
+  }
+  for (int k = 0; k < H; ++k) {
+    b[k].x = (T)std::cos(2 * pi * k / H);
+    b[k].y = (T)(-std::sin(2 * pi * k / H));
+  }
+  c->tw_M = al.dev(sizeof(CT) * M);
+  c->tw_H = al.dev(sizeof(CT) * H);
+  if (al.st == PSE_OK) {
+    hipMemcpy(c->tw_M, a.data(), sizeof(CT) * M, hipMemcpyHostToDevice);
+    hipMemcpy(c->tw_H, b.data(), sizeof(CT) * H, hipMemcpyHostToDevice);
+  }
+}
+
+// Neighbour-list capacity: expected count in a sphere of radius rc at the
+// mean density, plus margin (grown on overflow in set_positions).
+int nbr_capacity(const pse_ctx *c) {
+  const double vol = c->d.L * c->d.L * c->d.L;
+  const double expect = c->n / vol * 4.18879020478639 * c->p.rcut * c->p.rcut * c->p.rcut;
+  int cap = (int)(1.6 * expect + 48);
+  if (cap > c->n) cap = c->n;
+  return cap < 1 ? 1 : cap;
+}
+
+WaveCoef wave_coef(const pse_ctx *c, double det_scale, double sto_scale, uint64_t seed, uint64_t counter) {
+  const double pi = 3.14159265358979323846;
+  const double M = c->p.grid;
+  WaveCoef w;
+  w.two_pi_over_L = 2 * pi / c->d.L;
+  w.a = c->p.a;
+  w.inv_4xi2 = 1.0 / (4 * c->p.xi * c->p.xi);
+  w.sigma2 = c->d.sigma * c->d.sigma;
+  w.det_scale = det_scale;
+  w.sto_scale = sto_scale;
+  w.w_scale = std::pow(M, -1.5);
+  w.seed = seed;
+  w.counter = counter;
+  w.use_philox = 1;
+  (void)M;
+  return w;
+}
+
+pse_status hip_status(hipError_t e) { return e == hipSuccess ? PSE_OK : PSE_ERR_HIP; }
+
+// ---------------------------------------------------------- hot path
+template <typename T, typename A>
+pse_status real_sample_core(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
+  launch_lz_init<T, A>(c, z_sorted);
+  auto *h = (LzState<A> *)c->lz_h;
+  const int maxit = c->p.lanczos_max_iter;
+  int launched = 0;
+  int chunk = c->last_iters < 2 ? 2 : c->last_iters;
+  while (launched < maxit) {
+    const int k = chunk < maxit - launched ? chunk : maxit - launched;
+    for (int i = 0; i < k; ++i) launch_lz_iter<T, A>(c, launched + i, z_sorted);
+    launched += k;
+    hipMemcpyAsync(h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+    if (h->done) break;
+    chunk = 1;
+  }
+  launch_lz_combine<T, A>(c, y_sorted);
+  c->last_iters = h->m;
+  if (stats) {
+    stats->lanczos_iters = h->m;
+    stats->converged = h->converged;
+    stats->lanczos_rel_change = (double)h->rel_change;
+  }
+  if (h->nonfinite) return PSE_ERR_NONFINITE;
+  if (!h->converged) return PSE_ERR_NOT_CONVERGED;
+  return PSE_OK;
+}
+
+// Wave-space velocity/displacement in sorted order into `out`:
+//   forces (sorted, or null) enter with det_scale, noise with sto_scale.
+template <typename T>
+pse_status wave_core(pse_ctx *c, const void *f_sorted, int noise, const void *W, const WaveCoef &wc, void *out) {
+  const size_t M3 = (size_t)c->p.grid * c->p.grid * c->p.grid;
+  if (!f_sorted && noise == 0) {
+    return hip_status(hipMemsetAsync(out, 0, sizeof(T) * 3 * c->n, c->stream));
+  }
+  if (noise == 2) {
+    if (!c->grid2) {
+      if (hipMalloc(&c->grid2, sizeof(T) * 3 * M3) != hipSuccess) {
+        c->grid2 = nullptr;
+        return PSE_ERR_OOM;
+      }
+    }
+    launch_grid_op<T>(c, GridOp::FftZ, W, c->grid2, nullptr, -1, 0);
+    launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid2, nullptr, 1, -1);
+    launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid2, nullptr, 0, -1);
+  }
+  if (f_sorted) {
+    hipMemsetAsync(c->grid, 0, sizeof(T) * 3 * M3, c->stream);
+    launch_spread_interp<T>(c, true, f_sorted, c->grid);
+    launch_grid_op<T>(c, GridOp::FftZ, c->grid, c->grid, nullptr, -1, 0);
+    launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid, nullptr, 1, -1);
+  }
+  launch_grid_op<T>(c, GridOp::XFused, noise == 2 ? c->grid2 : nullptr, c->grid, &wc, f_sorted ? 1 : 0, noise);
+  launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid, nullptr, 1, +1);
+  launch_grid_op<T>(c, GridOp::FftZ, c->grid, c->grid, nullptr, +1, 0);
+  launch_spread_interp<T>(c, false, c->grid, out);
+  return hip_status(hipGetLastError());
+}
+
+// Full displacement.  z1: caller-order real noise (device) or null with
+// use_philox; W: grid noise or null.
+template <typename T, typename A>
+pse_status sample_impl(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter, const void *z1, const void *W,
+                       double dt, const void *forces, void *disp, pse_stats *stats) {
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  if (!disp || !(dt >= 0)) return PSE_ERR_INVALID_ARG;
+  const double pi = 3.14159265358979323846;
+  const double cr = std::sqrt(2.0 * c->p.kT * dt);
+  void *z_s = c->vbuf[0], *yr = c->vbuf[1], *wave = c->vbuf[4], *tmp = c->vbuf[5], *f_s = c->vbuf[6],
+       *ur = c->vbuf[7];
+  pse_status st = PSE_OK;
+  bool have_real = false;
+  if (philox) {
+    launch_real_noise<T>(c, tmp, seed, counter);
+    launch_gather3<T>(c, tmp, z_s);
+    have_real = true;
+  } else if (z1) {
+    launch_gather3<T>(c, z1, z_s);
+    have_real = true;
+  }
+  if (have_real && cr > 0) {
+    st = real_sample_core<T, A>(c, z_s, yr, stats);
+    if (st != PSE_OK && st != PSE_ERR_NOT_CONVERGED) return st;
+  } else if (stats) {
+    stats->lanczos_iters = 0;
+    stats->converged = 1;
+    stats->lanczos_rel_change = 0;
+  }
+  if (forces && dt > 0) {
+    launch_gather3<T>(c, forces, f_s);
+    launch_spmv<T, A>(c, f_s, ur, false, nullptr);
+  }
+  const double V = c->d.L * c->d.L * c->d.L;
+  const double M3 = (double)c->p.grid * c->p.grid * c->p.grid;
+  WaveCoef wc = wave_coef(c, dt / (c->p.eta * M3), cr / std::sqrt(c->p.eta * V), seed, counter);
+  const int noise = (cr > 0) ? (philox ? 1 : (W ? 2 : 0)) : 0;
+  const pse_status sw = wave_core<T>(c, (forces && dt > 0) ? f_s : nullptr, noise, W, wc, wave);
+  if (sw != PSE_OK) return sw;
+  launch_finalize<T>(c, (have_real && cr > 0) ? yr : nullptr, cr, (forces && dt > 0) ? ur : nullptr, dt, wave, disp);
+  if (stats) stats->max_neighbors = c->flags_h[1];
+  (void)pi;
+  const pse_status se = hip_status(hipGetLastError());
+  return se != PSE_OK ? se : st;
+}
+
+#define DISPATCH(ctx, CALL)                                   \
+  do {                                                        \
+    if ((ctx)->dbl) {                                         \
+      using T = double;                                       \
+      using A = double;                                       \
+      return CALL;                                            \
+    } else if ((ctx)->acc_dbl) {                              \
+      using T = float;                                        \
+      using A = double;                                       \
+      return CALL;                                            \
+    } else {                                                  \
+      using T = float;                                        \
+      using A = float;                                        \
+      return CALL;                                            \
+    }                                                         \
+  } while (0)
+
+template <typename T>
+pse_status set_positions_impl(pse_ctx *c, const void *pos) {
+  launch_bin<T>(c, pos);
+  launch_nbr<T>(c);
+  hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+  if (c->flags_h[0]) {
+    c->have_pos = false;
+    return PSE_ERR_NONFINITE;
+  }
+  if (c->flags_h[1] > c->nbr_cap) {
+    const int cap = c->flags_h[1] + 32;
+    hipFree(c->nbr);
+    c->nbr = nullptr;
+    if (hipMalloc(&c->nbr, sizeof(int) * (size_t)cap * c->n) != hipSuccess) {
+      c->nbr = nullptr;
+      c->nbr_cap = 0;
+      c->have_pos = false;
+      return PSE_ERR_OOM;
+    }
+    c->nbr_cap = cap;
+    hipMemsetAsync(c->flags, 0, sizeof(int) * 4, c->stream);
+    launch_nbr<T>(c);
+    hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+  }
+  c->have_pos = true;
+  return hip_status(hipGetLastError());
+}
+
+template <typename T, typename A>
+pse_status real_matvec_impl(pse_ctx *c, const void *v, void *w) {
+  launch_gather3<T>(c, v, c->vbuf[0]);
+  launch_spmv<T, A>(c, c->vbuf[0], c->vbuf[7], false, nullptr);
+  launch_finalize<T>(c, nullptr, 0.0, c->vbuf[7], 1.0, nullptr, w);
+  return hip_status(hipGetLastError());
+}
+
+template <typename T, typename A>
+pse_status real_sample_impl(pse_ctx *c, const void *z, void *y, pse_stats *stats) {
+  launch_gather3<T>(c, z, c->vbuf[0]);
+  pse_status st = real_sample_core<T, A>(c, c->vbuf[0], c->vbuf[1], stats);
+  if (st != PSE_OK && st != PSE_ERR_NOT_CONVERGED) return st;
+  launch_finalize<T>(c, c->vbuf[1], 1.0, nullptr, 0.0, nullptr, y);
+  const pse_status se = hip_status(hipGetLastError());
+  return se != PSE_OK ? se : st;
+}
+
+template <typename T>
+pse_status wave_sample_impl(pse_ctx *c, const void *W, void *y) {
+  const double V = c->d.L * c->d.L * c->d.L;
+  WaveCoef wc = wave_coef(c, 0.0, 1.0 / std::sqrt(c->p.eta * V), 0, 0);
+  pse_status st = wave_core<T>(c, nullptr, 2, W, wc, c->vbuf[4]);
+  if (st != PSE_OK) return st;
+  launch_finalize<T>(c, nullptr, 0.0, nullptr, 0.0, c->vbuf[4], y);
+  return hip_status(hipGetLastError());
+}
+
+template <typename T, typename A>
+pse_status wave_apply_impl(pse_ctx *c, const void *F, void *u, bool with_real) {
+  const double M3 = (double)c->p.grid * c->p.grid * c->p.grid;
+  launch_gather3<T>(c, F, c->vbuf[6]);
+  WaveCoef wc = wave_coef(c, 1.0 / (c->p.eta * M3), 0.0, 0, 0);
+  pse_status st = wave_core<T>(c, c->vbuf[6], 0, nullptr, wc, c->vbuf[4]);
+  if (st != PSE_OK) return st;
+  if (with_real) launch_spmv<T, A>(c, c->vbuf[6], c->vbuf[7], false, nullptr);
+  launch_finalize<T>(c, nullptr, 0.0, with_real ? c->vbuf[7] : nullptr, 1.0, c->vbuf[4], u);
+  return hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pse_status_string(pse_status s) {
+  switch (s) {
+    case PSE_OK: return "ok";
+    case PSE_ERR_INVALID_ARG: return "invalid argument";
+    case PSE_ERR_OOM: return "device allocation failed";
+    case PSE_ERR_HIP: return "HIP runtime error";
+    case PSE_ERR_PARAMS: return "parameters rejected by the error model";
+    case PSE_ERR_NONFINITE: return "non-finite value";
+    case PSE_ERR_NOT_CONVERGED: return "Lanczos did not converge within max_iter";
+    case PSE_ERR_NO_POSITIONS: return "positions not set";
+    case PSE_WARN_PRECOND_FALLBACK: return "learned preconditioner fell back to identity";
+  }
+  return "unknown status";
+}
+
+pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
+  if (!p || !out) return PSE_ERR_INVALID_ARG;
+  *out = nullptr;
+  Derived d;
+  const pse_status ps = derive_params(*p, &d);
+  if (ps != PSE_OK) return ps;
+  if (p->precond != 0) return PSE_ERR_PARAMS;
+  pse_ctx *c = new (std::nothrow) pse_ctx();
+  if (!c) return PSE_ERR_OOM;
+  c->p = *p;
+  c->d = d;
+  c->stream = (hipStream_t)stream;
+  c->dbl = p->precision == PSE_FP64;
+  c->acc_dbl = p->precision != PSE_FP32;
+  c->n = p->n;
+  c->ncell = d.nc * d.nc * d.nc;
+  Alloc al;
+  const size_t n = (size_t)p->n, T = tsize(c), A = asize(c);
+  c->pos_w = al.dev(4 * T * n);
+  c->pos_s = al.dev(4 * T * n);
+  c->perm = (int *)al.dev(sizeof(int) * n);
+  c->cell_of = (int *)al.dev(sizeof(int) * n);
+  c->cell_count = (int *)al.dev(sizeof(int) * 2 * c->ncell);
+  c->cell_start = (int *)al.dev(sizeof(int) * (c->ncell + 1));
+  c->nbr_cap = nbr_capacity(c);
+  c->nbr = (int *)al.dev(sizeof(int) * (size_t)c->nbr_cap * n);
+  c->nbr_cnt = (int *)al.dev(sizeof(int) * n);
+  c->flags = (int *)al.dev(sizeof(int) * 4);
+  c->flags_h = (int *)al.host(sizeof(int) * 4);
+  for (auto &v : c->vbuf) v = al.dev(3 * T * n);
+  c->V = al.dev(3 * T * n * (size_t)(kMaxIter + 1));
+  const size_t lzbytes = c->acc_dbl ? sizeof(LzState<double>) : sizeof(LzState<float>);
+  c->lz = al.dev(lzbytes);
+  c->lz_h = al.host(lzbytes);
+  const size_t nparts = std::max<size_t>(kRedBlock, (n + 255) / 256);
+  c->partials = al.dev(A * nparts);
+  c->counter = (unsigned *)al.dev(sizeof(unsigned));
+  const size_t M3 = (size_t)p->grid * p->grid * p->grid;
+  c->grid = al.dev(3 * T * M3);
+  // real-space tables (FP64 host evaluation of Appendix A)
+  double serF[kSeriesTerms], serG[kSeriesTerms];
+  fg_series_coeffs(p->xi, p->a, serF, serG);
+  for (int i = 0; i < kSeriesTerms; ++i) {
+    c->series_h[i] = serF[i];
+    c->series_h[kSeriesTerms + i] = serG[i];
+  }
+  const double thr = fg_small_r_threshold(p->xi, p->a);
+  c->small_r2 = thr * thr;
+  c->series = (double *)al.dev(sizeof(double) * 2 * kSeriesTerms);
+  if (!c->dbl) c->table = (float4 *)al.dev(sizeof(float4) * (kTableK + 1));
+  if (c->dbl) upload_twiddles<double>(c, al);
+  else upload_twiddles<float>(c, al);
+  if (al.st != PSE_OK) {
+    free_ctx(c);
+    return al.st;
+  }
+  hipError_t e = hipMemcpy(c->series, c->series_h, sizeof(double) * 2 * kSeriesTerms, hipMemcpyHostToDevice);
+  if (!c->dbl && e == hipSuccess) {
+    std::vector<float4> tab(kTableK + 1);
+    fg_build_table(p->xi, p->a, p->rcut, d.mu0, serF, serG, tab.data());
+    e = hipMemcpy(c->table, tab.data(), sizeof(float4) * (kTableK + 1), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemset(c->counter, 0, sizeof(unsigned));
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return PSE_ERR_HIP;
+  }
+  *out = c;
+  return PSE_OK;
+}
+
+pse_status pse_destroy(pse_ctx *ctx) {
+  if (ctx) hipStreamSynchronize(ctx->stream);
+  free_ctx(ctx);
+  return PSE_OK;
+}
+
+pse_status pse_get_derived(const pse_ctx *c, pse_derived *o) {
+  if (!c || !o) return PSE_ERR_INVALID_ARG;
+  o->h = c->d.h;
+  o->sigma = c->d.sigma;
+  o->gauss_m = c->d.gm;
+  o->eta_se = c->d.eta_se;
+  o->eps_real = c->d.eps_real;
+  o->eps_wave = c->d.eps_wave;
+  o->eps_quad = c->d.eps_quad;
+  o->cells = c->d.nc;
+  o->self_real = c->d.self_r;
+  return PSE_OK;
+}
+
+pse_status pse_set_positions(pse_ctx *c, const void *pos) {
+  if (!c || !pos) return PSE_ERR_INVALID_ARG;
+  if (c->dbl) return set_positions_impl<double>(c, pos);
+  return set_positions_impl<float>(c, pos);
+}
+
+pse_status pse_sample(pse_ctx *c, uint64_t seed, uint64_t counter, double dt, const void *forces, void *disp,
+                      pse_stats *stats) {
+  if (!c) return PSE_ERR_INVALID_ARG;
+  DISPATCH(c, (sample_impl<T, A>(c, true, seed, counter, nullptr, nullptr, dt, forces, disp, stats)));
+}
+
+pse_status pse_sample_with_noise(pse_ctx *c, const void *z1, const void *W, double dt, const void *forces, void *disp,
+                                 pse_stats *stats) {
+  if (!c) return PSE_ERR_INVALID_ARG;
+  DISPATCH(c, (sample_impl<T, A>(c, false, 0, 0, z1, W, dt, forces, disp, stats)));
+}
+
+pse_status pse_real_matvec(pse_ctx *c, const void *v, void *w) {
+  if (!c || !v || !w) return PSE_ERR_INVALID_ARG;
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  DISPATCH(c, (real_matvec_impl<T, A>(c, v, w)));
+}
+
+pse_status pse_real_sample(pse_ctx *c, const void *z, void *y, pse_stats *stats) {
+  if (!c || !z || !y) return PSE_ERR_INVALID_ARG;
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  DISPATCH(c, (real_sample_impl<T, A>(c, z, y, stats)));
+}
+
+pse_status pse_wave_sample(pse_ctx *c, const void *W, void *y) {
+  if (!c || !W || !y) return PSE_ERR_INVALID_ARG;
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  if (c->dbl) return wave_sample_impl<double>(c, W, y);
+  return wave_sample_impl<float>(c, W, y);
+}
+
+pse_status pse_wave_apply(pse_ctx *c, const void *F, void *u) {
+  if (!c || !F || !u) return PSE_ERR_INVALID_ARG;
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  DISPATCH(c, (wave_apply_impl<T, A>(c, F, u, false)));
+}
+
+pse_status pse_mobility_apply(pse_ctx *c, const void *F, void *u) {
+  if (!c || !F || !u) return PSE_ERR_INVALID_ARG;
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  DISPATCH(c, (wave_apply_impl<T, A>(c, F, u, true)));
+}
+
+}  // extern "C"

@@ -1,0 +1,590 @@
+// Grid-side kernels of the wave-space part (Sec. II B.2, Spectral Ewald):
+// Gaussian spreading S and interpolation S^T (truncated to P^3 nodes), the 3D
+// FFT as three 1D passes (z: real <-> half complex, then y and x strided), and
+// the fused x pass that applies the split kernel B(k) (eq. Mwave), the
+// projector (I - kk), the Gaussian deconvolution and draws the k-space noise.
+//
+// Grid layout (per component c, planar): real u[c][ix][iy][iz], z fastest.
+// Spectrum in place of it: S[c][jx][jy][jz], jz < M/2 (the Nyquist plane
+// jz = M/2 is never used: Nyquist modes are outside the k-set).
+#include "launch.hpp"
+
+namespace pse {
+
+template <typename T> using C = typename vec2<T>::type;
+#define DI __device__ __forceinline__
+
+template <typename T> DI C<T> cmk(T x, T y) {
+  C<T> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+#define PSE_COMPLEX_OPS(CT, RT)                                                                     \
+  DI CT cadd(CT a, CT b) { return cmk<RT>(a.x + b.x, a.y + b.y); }                                   \
+  DI CT csub(CT a, CT b) { return cmk<RT>(a.x - b.x, a.y - b.y); }                                   \
+  DI CT cmul(CT a, CT b) { return cmk<RT>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }           \
+  DI CT cconj(CT a) { return cmk<RT>(a.x, -a.y); }                                                   \
+  DI CT cscale(CT a, RT s) { return cmk<RT>(a.x * s, a.y * s); }
+PSE_COMPLEX_OPS(float2, float)
+PSE_COMPLEX_OPS(double2, double)
+
+// ------------------------------------------------ compile-time twiddles
+constexpr double kPiC = 3.14159265358979323846;
+constexpr double ct_sin(double x) {
+  while (x > kPiC) x -= 2 * kPiC;
+  while (x < -kPiC) x += 2 * kPiC;
+  double term = x, sum = x;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_cos(double x) {
+  while (x > kPiC) x -= 2 * kPiC;
+  while (x < -kPiC) x += 2 * kPiC;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+template <int R> struct RegTw {
+  double c[R / 2 > 0 ? R / 2 : 1], s[R / 2 > 0 ? R / 2 : 1];
+  constexpr RegTw() : c(), s() {
+    for (int k = 0; k < R / 2; ++k) {
+      c[k] = ct_cos(2.0 * kPiC * k / R);
+      s[k] = ct_sin(2.0 * kPiC * k / R);
+    }
+  }
+};
+
+// DFT of R points held in registers, natural order in and out.
+// DIR = -1: X_k = sum x_n e^{-2 pi i nk/R};  DIR = +1: e^{+2 pi i nk/R}.
+template <typename T, int R, int DIR> struct DFT {
+  static DI void run(C<T> *v) {
+    static_assert((R & (R - 1)) == 0, "power of two");
+    C<T> e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = v[2 * i];
+      o[i] = v[2 * i + 1];
+    }
+    DFT<T, R / 2, DIR>::run(e);
+    DFT<T, R / 2, DIR>::run(o);
+    constexpr RegTw<R> tw{};
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      const T c = (T)tw.c[k], s = (T)(DIR * tw.s[k]);
+      const C<T> t = cmk<T>(o[k].x * c - o[k].y * s, o[k].x * s + o[k].y * c);
+      v[k] = cadd(e[k], t);
+      v[k + R / 2] = csub(e[k], t);
+    }
+  }
+};
+template <typename T, int DIR> struct DFT<T, 1, DIR> {
+  static DI void run(C<T> *) {}
+};
+template <typename T, int DIR> struct DFT<T, 2, DIR> {
+  static DI void run(C<T> *v) {
+    const C<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+template <typename T, int DIR> struct DFT<T, 3, DIR> {
+  static DI void run(C<T> *v) {
+    const T h = (T)0.86602540378443864676 * (T)DIR;  // DIR sqrt(3)/2
+    const C<T> a = v[0], b = v[1], c = v[2];
+    const C<T> t1 = cadd(b, c);
+    const C<T> t2 = cmk<T>(a.x - (T)0.5 * t1.x, a.y - (T)0.5 * t1.y);
+    const C<T> dbc = csub(b, c);
+    const C<T> t3 = cmk<T>(-h * dbc.y, h * dbc.x);  // i DIR sqrt3/2 (b - c)
+    v[0] = cadd(a, t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+  }
+};
+
+// One Stockham autosort stage of radix R on NCOLS columns of length N held
+// in LDS as buf[n * NCOLS + col].  Ns = product of the radices already done.
+// tw[k] = exp(-2 pi i k / N) (conjugated for DIR = +1).
+template <typename T, int N, int R, int DIR, int NCOLS, int BLOCK>
+DI void stockham_stage(C<T> *buf, const C<T> *tw, int Ns) {
+  constexpr int NB = (N / R) * NCOLS;
+  constexpr int BPT = (NB + BLOCK - 1) / BLOCK;
+  C<T> v[BPT][R];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * BLOCK;
+    if (b < NB) {
+      const int col = b % NCOLS, j = b / NCOLS;
+      const int jm = j % Ns;
+      const int tstep = jm * (N / (Ns * R));
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C<T> x = buf[(j + r * (N / R)) * NCOLS + col];
+        if (r > 0) {
+          C<T> w = tw[tstep * r];
+          if (DIR > 0) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[q][r] = x;
+      }
+      DFT<T, R, DIR>::run(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * BLOCK;
+    if (b < NB) {
+      const int col = b % NCOLS, j = b / NCOLS;
+      const int jm = j % Ns;
+      const int idxD = (j / Ns) * Ns * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(idxD + r * Ns) * NCOLS + col] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Radix plans (product = N).
+template <int N> struct Plan;
+template <> struct Plan<4> { static constexpr int n = 1, r[3] = {4, 1, 1}; };
+template <> struct Plan<8> { static constexpr int n = 1, r[3] = {8, 1, 1}; };
+template <> struct Plan<16> { static constexpr int n = 1, r[3] = {16, 1, 1}; };
+template <> struct Plan<32> { static constexpr int n = 2, r[3] = {8, 4, 1}; };
+template <> struct Plan<64> { static constexpr int n = 2, r[3] = {8, 8, 1}; };
+template <> struct Plan<128> { static constexpr int n = 2, r[3] = {16, 8, 1}; };
+template <> struct Plan<256> { static constexpr int n = 2, r[3] = {16, 16, 1}; };
+template <> struct Plan<512> { static constexpr int n = 3, r[3] = {8, 8, 8}; };
+
+template <typename T, int N, int DIR, int NCOLS, int BLOCK>
+DI void fft_lds(C<T> *buf, const C<T> *tw) {
+  using PL = Plan<N>;
+  stockham_stage<T, N, PL::r[0], DIR, NCOLS, BLOCK>(buf, tw, 1);
+  if constexpr (PL::n > 1) stockham_stage<T, N, PL::r[1], DIR, NCOLS, BLOCK>(buf, tw, PL::r[0]);
+  if constexpr (PL::n > 2) stockham_stage<T, N, PL::r[2], DIR, NCOLS, BLOCK>(buf, tw, PL::r[0] * PL::r[1]);
+}
+
+// ------------------------------------------------------------- z pass
+// Lines of M reals (= M/2 complex), contiguous.  Forward: real -> half
+// spectrum jz = 0 .. M/2-1 (packing the real line as M/2 complex pairs,
+// one M/2-point FFT, then the split into even/odd parts).  Inverse: the
+// adjoint route, unnormalised, with the Nyquist value taken as 0 and the
+// jz = 0 value as real.  In place or out of place (src -> dst).
+template <typename T, int M, int DIR, int NL, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fft_z(const C<T> *__restrict__ src, C<T> *__restrict__ dst,
+                                                 const C<T> *__restrict__ twH_g, const C<T> *__restrict__ twM_g) {
+  constexpr int H = M / 2;
+  __shared__ C<T> buf[H * NL];
+  __shared__ C<T> twH[H];
+  __shared__ C<T> twM[H];
+  for (int i = threadIdx.x; i < H; i += BLOCK) {
+    twH[i] = twH_g[i];
+    twM[i] = twM_g[i];
+  }
+  const size_t line0 = (size_t)blockIdx.x * NL;
+  __syncthreads();
+  for (int e = threadIdx.x; e < H * NL; e += BLOCK) {
+    const int k = e % H, l = e / H;
+    const C<T> *ln = src + (line0 + l) * H;
+    if (DIR < 0) {
+      buf[k * NL + l] = ln[k];
+    } else {
+      C<T> xk = ln[k];
+      C<T> xm = k == 0 ? cmk<T>(T(0), T(0)) : ln[H - k];
+      if (k == 0) xk.y = T(0);
+      const C<T> s = cadd(xk, cconj(xm));
+      const C<T> dd = csub(xk, cconj(xm));
+      const C<T> w = cconj(twM[k]);  // e^{+2 pi i k / M}
+      const C<T> t = cmul(w, dd);
+      buf[k * NL + l] = cmk<T>(s.x - t.y, s.y + t.x);  // s + i t
+    }
+  }
+  __syncthreads();
+  fft_lds<T, H, DIR, NL, BLOCK>(buf, twH);
+  for (int e = threadIdx.x; e < H * NL; e += BLOCK) {
+    const int k = e % H, l = e / H;
+    C<T> *ln = dst + (line0 + l) * H;
+    if (DIR < 0) {
+      const C<T> zk = buf[k * NL + l];
+      const C<T> zm = cconj(buf[((H - k) % H) * NL + l]);
+      const C<T> s = cadd(zk, zm);
+      const C<T> dd = csub(zk, zm);
+      const C<T> t = cmul(twM[k], dd);                              // w^k (Z_k - conj Z_{H-k})
+      ln[k] = cmk<T>((T)0.5 * (s.x + t.y), (T)0.5 * (s.y - t.x));  // (s - i t)/2
+    } else {
+      ln[k] = buf[k * NL + l];
+    }
+  }
+}
+
+// ------------------------------------------------------- strided passes
+// 1D FFTs of length N along a strided axis for a tile of TZ consecutive jz
+// columns and NCOMP components: element n of column (comp, col) is at
+// data[(comp0+comp)*s_comp + o*s_outer + n*s_fft + z0 + col].
+template <typename T, int N, int TZ, int NCOMP>
+DI void tile_load(C<T> *buf, const C<T> *data, size_t base, size_t s_fft, size_t s_comp, int block) {
+  constexpr int NCOLS = TZ * NCOMP;
+  for (int e = threadIdx.x; e < N * NCOLS; e += block) {
+    const int col = e % TZ, rest = e / TZ, cc = rest % NCOMP, nn = rest / NCOMP;
+    buf[nn * NCOLS + cc * TZ + col] = data[base + cc * s_comp + (size_t)nn * s_fft + col];
+  }
+}
+template <typename T, int N, int TZ, int NCOMP>
+DI void tile_store(const C<T> *buf, C<T> *data, size_t base, size_t s_fft, size_t s_comp, int block) {
+  constexpr int NCOLS = TZ * NCOMP;
+  for (int e = threadIdx.x; e < N * NCOLS; e += block) {
+    const int col = e % TZ, rest = e / TZ, cc = rest % NCOMP, nn = rest / NCOMP;
+    data[base + cc * s_comp + (size_t)nn * s_fft + col] = buf[nn * NCOLS + cc * TZ + col];
+  }
+}
+
+template <typename T, int N, int DIR, int TZ, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fft_strided(C<T> *__restrict__ data, size_t s_fft, size_t s_outer,
+                                                       size_t s_comp, const C<T> *__restrict__ tw_g) {
+  __shared__ C<T> buf[N * TZ];
+  __shared__ C<T> tw[N];
+  for (int i = threadIdx.x; i < N; i += BLOCK) tw[i] = tw_g[i];
+  const size_t base = (size_t)blockIdx.z * s_comp + (size_t)blockIdx.y * s_outer + (size_t)blockIdx.x * TZ;
+  tile_load<T, N, TZ, 1>(buf, data, base, s_fft, s_comp, BLOCK);
+  __syncthreads();
+  fft_lds<T, N, DIR, TZ, BLOCK>(buf, tw);
+  tile_store<T, N, TZ, 1>(buf, data, base, s_fft, s_comp, BLOCK);
+}
+
+// --------------------------------------------------- Philox k-space noise
+DI void philox4x64_10g(uint64_t c[4], uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B97F4A7C15ull;
+      k1 += 0xBB67AE8584CAA73Bull;
+    }
+    const uint64_t lo0 = 0xD2E7470EE14C6C93ull * c[0], hi0 = __umul64hi(0xD2E7470EE14C6C93ull, c[0]);
+    const uint64_t lo1 = 0xCA5A826395121157ull * c[2], hi1 = __umul64hi(0xCA5A826395121157ull, c[2]);
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+template <typename T> DI C<T> zeta_at(uint64_t e, uint64_t seed, uint64_t sample);
+template <> DI C<double> zeta_at<double>(uint64_t e, uint64_t seed, uint64_t sample) {
+  uint64_t c[4] = {e >> 1, sample, 0ull, 0ull};
+  philox4x64_10g(c, seed, 1ull);
+  const uint64_t wa = (e & 1) ? c[2] : c[0], wb = (e & 1) ? c[3] : c[1];
+  const double ua = ((double)(wa >> 11) + 0.5) * 0x1.0p-53;
+  const double ub = ((double)(wb >> 11) + 0.5) * 0x1.0p-53;
+  const double rho = sqrt(-2.0 * log(ua)) * 0.70710678118654752440;
+  double sn, cs;
+  sincospi(2.0 * ub, &sn, &cs);
+  return cmk<double>(rho * cs, rho * sn);
+}
+template <> DI C<float> zeta_at<float>(uint64_t e, uint64_t seed, uint64_t sample) {
+  uint64_t c[4] = {e >> 1, sample, 0ull, 0ull};
+  philox4x64_10g(c, seed, 1ull);
+  const uint64_t wa = (e & 1) ? c[2] : c[0], wb = (e & 1) ? c[3] : c[1];
+  const float ua = ((float)(uint32_t)(wa >> 40) + 0.5f) * 0x1.0p-24f;
+  const float ub = ((float)(uint32_t)(wb >> 40) + 0.5f) * 0x1.0p-24f;
+  const float rho = sqrtf(-2.0f * logf(ua)) * 0.70710678f;
+  float sn, cs;
+  sincospif(2.0f * ub, &sn, &cs);
+  return cmk<float>(rho * cs, rho * sn);
+}
+
+// ------------------------------------------------------ fused x pass
+// For a tile (jy = blockIdx.y, jz in [z0, z0+TZ)) and all jx:
+//   [FORCES] forward x-FFT of the spread-force spectrum (z, y already done);
+//   Uhat(k) = (I - kk/k^2) [ det_scale B ghat^-2 Fhat + sto_scale sqrt(B) ghat^-1 zeta ]
+//   with B = sinc^2(ka) H(k, xi) / k^2 (eq. Mwave), ghat = exp(-k^2 sigma^2 / 2);
+//   inverse x-FFT; store.  zeta: Philox (NOISE = 1) or the transformed grid
+//   noise times M^{-3/2} (NOISE = 2).  k = 0 and Nyquist indices give 0.
+template <typename T, int M, int TZ, int BLOCK, bool FORCES, int NOISE>
+__global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, const C<T> *__restrict__ specW,
+                                                       WaveCoef wc, const C<T> *__restrict__ tw_g) {
+  constexpr int H = M / 2;
+  constexpr int NCOLS = 3 * TZ;
+  __shared__ C<T> buf[M * NCOLS];
+  __shared__ C<T> tw[M];
+  for (int i = threadIdx.x; i < M; i += BLOCK) tw[i] = tw_g[i];
+  const size_t s_fft = (size_t)M * H, s_comp = (size_t)M * M * H;
+  const int jy = blockIdx.y, z0 = blockIdx.x * TZ;
+  const size_t base = (size_t)jy * H + z0;
+  if (FORCES) {
+    tile_load<T, M, TZ, 3>(buf, data, base, s_fft, s_comp, BLOCK);
+    __syncthreads();
+    fft_lds<T, M, -1, NCOLS, BLOCK>(buf, tw);
+  } else {
+    __syncthreads();
+  }
+  const T tpl = (T)wc.two_pi_over_L;
+  const int sy = jy < H ? jy : jy - M;
+  for (int e = threadIdx.x; e < M * TZ; e += BLOCK) {
+    const int col = e % TZ, jx = e / TZ;
+    const int jz = z0 + col;
+    const int sx = jx < H ? jx : jx - M;
+    C<T> out[3] = {cmk<T>(0, 0), cmk<T>(0, 0), cmk<T>(0, 0)};
+    const bool nyq = (jx == H) || (jy == H);
+    if (!nyq && (sx | sy | jz)) {
+      const T kx = tpl * sx, ky = tpl * sy, kz = tpl * jz;
+      const T k2 = kx * kx + ky * ky + kz * kz;
+      const T kk = sqrt(k2);
+      const T ka = kk * (T)wc.a;
+      const T sinc = sin(ka) / ka;
+      const T q = k2 * (T)wc.inv_4xi2;
+      const T gs = k2 * (T)wc.sigma2;
+      C<T> v[3];
+      for (int c = 0; c < 3; ++c) v[c] = cmk<T>(0, 0);
+      if (FORCES) {
+        const T det = (T)wc.det_scale * sinc * sinc * (T(1) + q) / k2 * exp(gs - q);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = cscale(buf[jx * NCOLS + c * TZ + col], det);
+      }
+      if (NOISE) {
+        // B^{1/2} is the non-negative root: |sinc(ka)| (sinc changes sign for ka > pi)
+        const T sto = (T)wc.sto_scale * fabs(sinc) * sqrt(T(1) + q) / kk * exp(T(0.5) * (gs - q));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          C<T> z;
+          if (NOISE == 1) {
+            const bool canon = jz > 0 || sy > 0 || (sy == 0 && sx > 0);
+            if (canon) {
+              z = zeta_at<T>((((uint64_t)c * M + jx) * M + jy) * H + jz, wc.seed, wc.counter);
+            } else {
+              const int px = (M - jx) % M, py = (M - jy) % M;
+              z = cconj(zeta_at<T>((((uint64_t)c * M + px) * M + py) * H + 0, wc.seed, wc.counter));
+            }
+          } else {
+            z = cscale(specW[c * s_comp + (size_t)jx * s_fft + base + col], (T)wc.w_scale);
+          }
+          v[c] = cadd(v[c], cscale(z, sto));
+        }
+      }
+      const C<T> kdv = cmk<T>(kx * v[0].x + ky * v[1].x + kz * v[2].x, kx * v[0].y + ky * v[1].y + kz * v[2].y);
+      const T ik2 = T(1) / k2;
+      out[0] = csub(v[0], cscale(kdv, kx * ik2));
+      out[1] = csub(v[1], cscale(kdv, ky * ik2));
+      out[2] = csub(v[2], cscale(kdv, kz * ik2));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) buf[jx * NCOLS + c * TZ + col] = out[c];
+  }
+  __syncthreads();
+  fft_lds<T, M, +1, NCOLS, BLOCK>(buf, tw);
+  tile_store<T, M, TZ, 3>(buf, data, base, s_fft, s_comp, BLOCK);
+}
+
+// --------------------------------------------------- spread / interpolate
+// One wavefront per (sorted) particle; lane -> (ix, iy) pairs of the P x P
+// support columns, loop over the P z-nodes.  Support nodes along each axis:
+// g = floor(x/h) - P/2 + 1 ... floor(x/h) + P/2 (wrapped mod M); weight
+// = normalised Gaussian of standard deviation sigma (separable).
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__restrict__ pos,
+                                                const T *__restrict__ f, int n, T *__restrict__ grid, int M, T h,
+                                                T invh, T inv2s2, T norm) {
+  const int s = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (s >= n) return;
+  const auto p = pos[s];
+  const int bx = min((int)(p.x * invh), M - 1), by = min((int)(p.y * invh), M - 1), bz = min((int)(p.z * invh), M - 1);
+  const int gx0 = bx - P / 2 + 1, gy0 = by - P / 2 + 1, gz0 = bz - P / 2 + 1;
+  const T fx = f[3 * s], fy = f[3 * s + 1], fz = f[3 * s + 2];
+  const size_t M3 = (size_t)M * M * M;
+  T wz[P];
+  int iz_m[P];
+#pragma unroll
+  for (int iz = 0; iz < P; ++iz) {
+    const int gz = gz0 + iz;
+    const T dz = (T)gz * h - p.z;
+    wz[iz] = exp(-dz * dz * inv2s2);
+    iz_m[iz] = (gz + M) % M;
+  }
+  for (int pr = lane; pr < P * P; pr += 64) {
+    const int ix = pr / P, iy = pr % P;
+    const int gx = gx0 + ix, gy = gy0 + iy;
+    const T dx = (T)gx * h - p.x, dy = (T)gy * h - p.y;
+    const T wxy = norm * exp(-(dx * dx + dy * dy) * inv2s2);
+    const size_t row = ((size_t)((gx + M) % M) * M + (size_t)((gy + M) % M)) * M;
+#pragma unroll
+    for (int iz = 0; iz < P; ++iz) {
+      const T w = wxy * wz[iz];
+      const size_t g = row + iz_m[iz];
+      unsafeAtomicAdd(&grid[g], w * fx);
+      unsafeAtomicAdd(&grid[M3 + g], w * fy);
+      unsafeAtomicAdd(&grid[2 * M3 + g], w * fz);
+    }
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__restrict__ pos,
+                                                const T *__restrict__ grid, int n, T *__restrict__ out, int M, T h,
+                                                T invh, T inv2s2, T norm_h3) {
+  const int s = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (s >= n) return;
+  const auto p = pos[s];
+  const int bx = min((int)(p.x * invh), M - 1), by = min((int)(p.y * invh), M - 1), bz = min((int)(p.z * invh), M - 1);
+  const int gx0 = bx - P / 2 + 1, gy0 = by - P / 2 + 1, gz0 = bz - P / 2 + 1;
+  const size_t M3 = (size_t)M * M * M;
+  T wz[P];
+  int iz_m[P];
+#pragma unroll
+  for (int iz = 0; iz < P; ++iz) {
+    const int gz = gz0 + iz;
+    const T dz = (T)gz * h - p.z;
+    wz[iz] = exp(-dz * dz * inv2s2);
+    iz_m[iz] = (gz + M) % M;
+  }
+  T ax = 0, ay = 0, az = 0;
+  for (int pr = lane; pr < P * P; pr += 64) {
+    const int ix = pr / P, iy = pr % P;
+    const int gx = gx0 + ix, gy = gy0 + iy;
+    const T dx = (T)gx * h - p.x, dy = (T)gy * h - p.y;
+    const T wxy = exp(-(dx * dx + dy * dy) * inv2s2);
+    const size_t row = ((size_t)((gx + M) % M) * M + (size_t)((gy + M) % M)) * M;
+#pragma unroll
+    for (int iz = 0; iz < P; ++iz) {
+      const T w = wxy * wz[iz];
+      const size_t g = row + iz_m[iz];
+      ax += w * grid[g];
+      ay += w * grid[M3 + g];
+      az += w * grid[2 * M3 + g];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    ax += __shfl_xor(ax, off, 64);
+    ay += __shfl_xor(ay, off, 64);
+    az += __shfl_xor(az, off, 64);
+  }
+  if (lane == 0) {
+    out[3 * s] = norm_h3 * ax;
+    out[3 * s + 1] = norm_h3 * ay;
+    out[3 * s + 2] = norm_h3 * az;
+  }
+}
+
+// ----------------------------------------------------------- launchers
+template <typename T, int M> struct GridCfg {
+  static constexpr int TZ = (sizeof(T) == 4) ? ((4096 / M) < (M / 2) ? (4096 / M) : (M / 2))
+                                             : ((2048 / M) < (M / 2) ? (2048 / M) : (M / 2));
+  static constexpr int TZ1 = (sizeof(T) == 4) ? ((8192 / M) < (M / 2) ? (8192 / M) : (M / 2))
+                                              : ((4096 / M) < (M / 2) ? (4096 / M) : (M / 2));
+  static constexpr int NL = (sizeof(T) == 4) ? ((8192 / M) < 64 ? (8192 / M) : 64) : ((4096 / M) < 64 ? (4096 / M) : 64);
+};
+
+template <typename T, int M>
+static void fft_z(pse_ctx *c, const void *src, void *dst, int dir) {
+  using CT = C<T>;
+  constexpr int NL = GridCfg<T, M>::NL;
+  const int nlines = 3 * M * M;
+  const dim3 g(nlines / NL);
+  if (dir < 0)
+    k_fft_z<T, M, -1, NL, 256><<<g, 256, 0, c->stream>>>((const CT *)src, (CT *)dst, (const CT *)c->tw_H,
+                                                         (const CT *)c->tw_M);
+  else
+    k_fft_z<T, M, +1, NL, 256><<<g, 256, 0, c->stream>>>((const CT *)src, (CT *)dst, (const CT *)c->tw_H,
+                                                         (const CT *)c->tw_M);
+}
+
+template <typename T, int M>
+static void fft_strided(pse_ctx *c, void *data, int axis, int dir) {
+  using CT = C<T>;
+  constexpr int H = M / 2;
+  constexpr int TZ = GridCfg<T, M>::TZ1;
+  const size_t s_comp = (size_t)M * M * H;
+  const size_t s_fft = axis == 0 ? (size_t)M * H : (size_t)H;
+  const size_t s_outer = axis == 0 ? (size_t)H : (size_t)M * H;
+  const dim3 g(H / TZ, M, 3);
+  if (dir < 0)
+    k_fft_strided<T, M, -1, TZ, 256><<<g, 256, 0, c->stream>>>((CT *)data, s_fft, s_outer, s_comp, (const CT *)c->tw_M);
+  else
+    k_fft_strided<T, M, +1, TZ, 256><<<g, 256, 0, c->stream>>>((CT *)data, s_fft, s_outer, s_comp, (const CT *)c->tw_M);
+}
+
+template <typename T, int M>
+static void xpass(pse_ctx *c, void *data, const void *specW, const WaveCoef &wc, bool forces, int noise) {
+  using CT = C<T>;
+  constexpr int H = M / 2;
+  constexpr int TZ = GridCfg<T, M>::TZ;
+  const dim3 g(H / TZ, M);
+  auto *d = (CT *)data;
+  auto *w = (const CT *)specW;
+  auto *tw = (const CT *)c->tw_M;
+  if (forces) {
+    if (noise == 1) k_xpass_fused<T, M, TZ, 256, true, 1><<<g, 256, 0, c->stream>>>(d, w, wc, tw);
+    else if (noise == 2) k_xpass_fused<T, M, TZ, 256, true, 2><<<g, 256, 0, c->stream>>>(d, w, wc, tw);
+    else k_xpass_fused<T, M, TZ, 256, true, 0><<<g, 256, 0, c->stream>>>(d, w, wc, tw);
+  } else {
+    if (noise == 1) k_xpass_fused<T, M, TZ, 256, false, 1><<<g, 256, 0, c->stream>>>(d, w, wc, tw);
+    else if (noise == 2) k_xpass_fused<T, M, TZ, 256, false, 2><<<g, 256, 0, c->stream>>>(d, w, wc, tw);
+    else k_xpass_fused<T, M, TZ, 256, false, 0><<<g, 256, 0, c->stream>>>(d, w, wc, tw);
+  }
+}
+
+template <typename T, int M>
+static void dispatch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoef *wc, int x, int y) {
+  switch (op) {
+    case GridOp::FftZ: fft_z<T, M>(c, a, b, x); break;
+    case GridOp::FftStrided: fft_strided<T, M>(c, b, x, y); break;
+    case GridOp::XFused: xpass<T, M>(c, b, a, *wc, x != 0, y); break;
+  }
+}
+
+template <typename T>
+void launch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoef *wc, int x, int y) {
+  switch (c->p.grid) {
+    case 16: dispatch_grid_op<T, 16>(c, op, a, b, wc, x, y); break;
+    case 32: dispatch_grid_op<T, 32>(c, op, a, b, wc, x, y); break;
+    case 64: dispatch_grid_op<T, 64>(c, op, a, b, wc, x, y); break;
+    case 128: dispatch_grid_op<T, 128>(c, op, a, b, wc, x, y); break;
+    case 256: dispatch_grid_op<T, 256>(c, op, a, b, wc, x, y); break;
+    case 512: dispatch_grid_op<T, 512>(c, op, a, b, wc, x, y); break;
+    default: break;
+  }
+}
+
+template <typename T, int P>
+static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid_or_out) {
+  using T4 = typename vec4<T>::type;
+  const int n = c->n, M = c->p.grid;
+  const double h = c->d.h, s2 = c->d.sigma * c->d.sigma;
+  const double norm = std::pow(2.0 * 3.14159265358979323846 * s2, -1.5);
+  const int blocks = (int)(((long)n * 64 + 255) / 256);
+  if (spread)
+    k_spread<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T *)vec, n, (T *)grid_or_out, M, (T)h,
+                                                  (T)(1.0 / h), (T)(0.5 / s2), (T)norm);
+  else
+    k_interp<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T *)vec, n, (T *)grid_or_out, M,
+                                                  (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)(norm * h * h * h));
+}
+
+template <typename T>
+void launch_spread_interp(pse_ctx *c, bool spread, const void *vec, void *grid_or_out) {
+  switch (c->p.support) {
+    case 2: spread_interp_P<T, 2>(c, spread, vec, grid_or_out); break;
+    case 4: spread_interp_P<T, 4>(c, spread, vec, grid_or_out); break;
+    case 6: spread_interp_P<T, 6>(c, spread, vec, grid_or_out); break;
+    case 8: spread_interp_P<T, 8>(c, spread, vec, grid_or_out); break;
+    case 10: spread_interp_P<T, 10>(c, spread, vec, grid_or_out); break;
+    case 12: spread_interp_P<T, 12>(c, spread, vec, grid_or_out); break;
+    case 14: spread_interp_P<T, 14>(c, spread, vec, grid_or_out); break;
+    case 16: spread_interp_P<T, 16>(c, spread, vec, grid_or_out); break;
+    default: break;
+  }
+}
+
+template void launch_grid_op<float>(pse_ctx *, GridOp, const void *, void *, const WaveCoef *, int, int);
+template void launch_grid_op<double>(pse_ctx *, GridOp, const void *, void *, const WaveCoef *, int, int);
+template void launch_spread_interp<float>(pse_ctx *, bool, const void *, void *);
+template void launch_spread_interp<double>(pse_ctx *, bool, const void *, void *);
+
+}  // namespace pse

@@ -1,0 +1,757 @@
+// Particle-side kernels: wrapping and linked-cell binning, the sorted order,
+// the near-field neighbour list, the real-space product w = M_r v
+// (eq. Mreal, Appendix A) and the Lanczos square-root iteration (Sec. II B.1).
+#include "launch.hpp"
+
+namespace pse {
+
+// ------------------------------------------------------------- reductions
+template <typename A> __device__ __forceinline__ A wave_sum(A v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  sh >= 16 entries.
+template <typename A> __device__ __forceinline__ A block_sum(A v, A *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  A r = 0;
+  if (wid == 0) {
+    r = lane < (int)(blockDim.x >> 6) ? sh[lane] : A(0);
+    r = wave_sum(r);
+  }
+  __syncthreads();
+  return r;
+}
+
+template <typename T> __device__ __forceinline__ T wrap_coord(T x, T L, T invL) {
+  x = x - L * floor(x * invL);
+  if (x >= L || x < T(0)) x = T(0);  // x == L (or rounding just past it) maps to 0
+  return x;
+}
+
+template <typename T> __device__ __forceinline__ T min_image(T d, T L, T invL) { return d - L * rint(d * invL); }
+
+// --------------------------------------------------------------- binning
+template <typename T>
+__global__ void k_wrap_bin(const T *__restrict__ pos, int n, T L, T invL, T inv_cs, int nc,
+                           typename vec4<T>::type *__restrict__ pos_w, int *__restrict__ cell_of,
+                           int *__restrict__ cell_count, int *__restrict__ flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+    atomicOr(&flags[0], 1);
+    x = y = z = T(0);
+  }
+  x = wrap_coord(x, L, invL);
+  y = wrap_coord(y, L, invL);
+  z = wrap_coord(z, L, invL);
+  const int cx = min((int)(x * inv_cs), nc - 1);
+  const int cy = min((int)(y * inv_cs), nc - 1);
+  const int cz = min((int)(z * inv_cs), nc - 1);
+  const int c = (cx * nc + cy) * nc + cz;
+  cell_of[i] = c;
+  atomicAdd(&cell_count[c], 1);
+  typename vec4<T>::type q;
+  q.x = x; q.y = y; q.z = z; q.w = T(0);
+  pos_w[i] = q;
+}
+
+// Exclusive scan of the cell counts (one block of 1024 threads).
+__global__ void k_scan_cells(const int *__restrict__ count, int *__restrict__ start, int *__restrict__ fill, int ncell) {
+  __shared__ int sh[1024];
+  const int per = (ncell + blockDim.x - 1) / blockDim.x;
+  const int b = threadIdx.x * per, e = min(b + per, ncell);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += count[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int v = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;
+  for (int i = b; i < e; ++i) {
+    start[i] = run;
+    run += count[i];
+    fill[i] = 0;
+  }
+  if (threadIdx.x == blockDim.x - 1) start[ncell] = sh[threadIdx.x];
+}
+
+__global__ void k_scatter(const int *__restrict__ cell_of, const int *__restrict__ start, int *__restrict__ fill,
+                          int *__restrict__ perm, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell_of[i];
+  perm[start[c] + atomicAdd(&fill[c], 1)] = i;
+}
+
+// Order each cell's members by caller index: the sorted order (and with it
+// every summation order downstream) is then deterministic.
+__global__ void k_cell_sort(const int *__restrict__ start, int *__restrict__ perm, int ncell) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int b = start[c], e = start[c + 1];
+  for (int i = b + 1; i < e; ++i) {
+    const int v = perm[i];
+    int j = i - 1;
+    while (j >= b && perm[j] > v) {
+      perm[j + 1] = perm[j];
+      --j;
+    }
+    perm[j + 1] = v;
+  }
+}
+
+template <typename T4>
+__global__ void k_gather_pos(const T4 *__restrict__ pos_w, const int *__restrict__ perm, T4 *__restrict__ pos_s, int n) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) pos_s[s] = pos_w[perm[s]];
+}
+
+// Near-field neighbour list (ELL layout nbr[k * n + s], sorted indices):
+// every t != s with minimum-image distance <= rc, scanning the 27 adjacent
+// cells (fewer when a side has < 3 cells, so no cell is visited twice).
+template <typename T>
+__global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, const int *__restrict__ start, int n,
+                            int nc, T L, T invL, T inv_cs, T rc2, int *__restrict__ nbr, int *__restrict__ cnt_out,
+                            int cap, int *__restrict__ flags) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const auto p = pos[s];
+  const int cx = min((int)(p.x * inv_cs), nc - 1);
+  const int cy = min((int)(p.y * inv_cs), nc - 1);
+  const int cz = min((int)(p.z * inv_cs), nc - 1);
+  const int lo = nc >= 3 ? -1 : 0, hi = nc >= 2 ? 1 : 0;
+  int cnt = 0;
+  for (int dx = lo; dx <= hi; ++dx) {
+    const int ax = (cx + dx + nc) % nc;
+    for (int dy = lo; dy <= hi; ++dy) {
+      const int ay = (cy + dy + nc) % nc;
+      for (int dz = lo; dz <= hi; ++dz) {
+        const int c = (ax * nc + ay) * nc + (cz + dz + nc) % nc;
+        const int e = start[c + 1];
+        for (int t = start[c]; t < e; ++t) {
+          if (t == s) continue;
+          const auto q = pos[t];
+          const T ddx = min_image(p.x - q.x, L, invL);
+          const T ddy = min_image(p.y - q.y, L, invL);
+          const T ddz = min_image(p.z - q.z, L, invL);
+          const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          if (r2 <= rc2) {
+            if (cnt < cap) nbr[(size_t)cnt * n + s] = t;
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  cnt_out[s] = cnt;
+  atomicMax(&flags[1], cnt);
+}
+
+// ------------------------------------------------------- F, G evaluation
+// FP32 modes: linear interpolation in an LDS table of (mu0 F, mu0 (G-F)).
+struct FGTable {
+  const float4 *tab;  // LDS
+  float inv_dr;
+  __device__ __forceinline__ void eval(float r2, float rinv, float &Fm, float &Dm) const {
+    const float u = r2 * rinv * inv_dr;
+    int k = (int)u;
+    k = min(k, kTableK - 1);
+    const float f = u - (float)k;
+    const float4 e = tab[k];
+    Fm = fmaf(f, e.z, e.x);
+    Dm = fmaf(f, e.w, e.y);
+  }
+};
+
+// FP64 mode: Appendix A closed forms on the fly (Case 1 / Case 2), with the
+// series of the wave complement below the small-r threshold.
+struct FGExact {
+  const double *ser;  // [2 * kSeriesTerms]: F then G series coefficients
+  double xi, a, mu0, small_r2;
+  __device__ __forceinline__ void eval(double r2, double rinv, double &Fm, double &Dm) const {
+    const double r = r2 * rinv;
+    double F, G;
+    if (r2 < small_r2) {
+      double Ff, Gf;
+      if (r > 2.0 * a) {
+        const double ci = 0.75 * a / r + 0.5 * a * a * a / (r * r2);
+        F = ci;
+        G = ci + 0.75 * a / r - 1.5 * a * a * a / (r * r2);
+      } else {
+        F = 1.0 - 9.0 * r / (32.0 * a);
+        G = 1.0 - 3.0 * r / (16.0 * a);
+      }
+      Ff = 0.0;
+      Gf = 0.0;
+      for (int n = kSeriesTerms - 1; n >= 0; --n) {
+        Ff = Ff * r2 + ser[n];
+        Gf = Gf * r2 + ser[kSeriesTerms + n];
+      }
+      F -= Ff;
+      G -= Gf;
+    } else {
+      const double sp = 1.7724538509055160273;
+      const double x = xi, x2 = x * x, x3 = x2 * x, x4 = x2 * x2;
+      const double r3 = r2 * r, r4 = r2 * r2, a2 = a * a;
+      const double rm = r - 2.0 * a, rp = r + 2.0 * a;
+      const double qp = 4.0 * a2 + 4.0 * a * r + 9.0 * r2, qm = 4.0 * a2 - 4.0 * a * r + 9.0 * r2;
+      const double e1 = exp(-r2 * x2), e2 = exp(-rm * rm * x2), e3 = exp(-rp * rp * x2);
+      const double c1 = erfc(r * x), c2 = erfc(rm * x), c3 = erfc(rp * x);
+      const double i64 = 1.0 / (64.0 * sp * a * r3 * x3), i128 = 0.5 * i64;
+      const double f1 = (18.0 * r2 * x2 + 3.0) / (64.0 * sp * a * r2 * x3);
+      const double f2 = (2.0 * x2 * (2.0 * a - r) * qp - 2.0 * a - 3.0 * r) * i128;
+      const double f3 = (-2.0 * x2 * rp * qm + 2.0 * a - 3.0 * r) * i128;
+      const double f4 = (3.0 - 36.0 * r4 * x4) / (128.0 * a * r3 * x4);
+      const double f5 = (4.0 * x4 * rm * rm * qp - 3.0) / (256.0 * a * r3 * x4);
+      const double f6 = (4.0 * x4 * rp * rp * qm - 3.0) / (256.0 * a * r3 * x4);
+      const double g1 = (6.0 * r2 * x2 - 3.0) / (32.0 * sp * a * r2 * x3);
+      const double g2 = (-2.0 * x2 * rm * rm * (2.0 * a + 3.0 * r) + 2.0 * a + 3.0 * r) * i64;
+      const double g3 = (2.0 * x2 * rp * rp * (2.0 * a - 3.0 * r) - 2.0 * a + 3.0 * r) * i64;
+      const double g4 = -(3.0 * (4.0 * r4 * x4 + 1.0)) / (64.0 * a * r3 * x4);
+      const double tm = 2.0 * a - r;
+      const double g5 = (3.0 - 4.0 * x4 * tm * tm * tm * (2.0 * a + 3.0 * r)) / (128.0 * a * r3 * x4);
+      const double g6 = (3.0 - 4.0 * x4 * (2.0 * a - 3.0 * r) * rp * rp * rp) / (128.0 * a * r3 * x4);
+      double f0 = 0.0, g0 = 0.0;
+      if (r <= 2.0 * a) {
+        f0 = -rm * rm * qp / (32.0 * a * r3);
+        g0 = tm * tm * tm * (2.0 * a + 3.0 * r) / (16.0 * a * r3);
+      }
+      F = f0 + f1 * e1 + f2 * e2 + f3 * e3 + f4 * c1 + f5 * c2 + f6 * c3;
+      G = g0 + g1 * e1 + g2 * e2 + g3 * e3 + g4 * c1 + g5 * c2 + g6 * c3;
+    }
+    Fm = F * mu0;
+    Dm = (G - F) * mu0;
+  }
+};
+
+// --------------------------------------------------- near-field product
+// One thread per sorted particle s:
+//   out_s = scale * ( self * v_s + sum_{t in nbr(s)} mu0 [F v_t + (G-F)(d.v_t) d / r^2] )
+// with v = src (times `scale`).  In the Lanczos variant the scale is the
+// device-side 1/beta, the thread also stores the basis vector V_m = scale*src
+// and the block reduces V_m . out toward alpha_m (last block finishes it).
+template <typename T, typename A, typename FG, bool LZ>
+__device__ __forceinline__ void spmv_body(const typename vec4<T>::type *__restrict__ pos, const int *__restrict__ nbr,
+                                          const int *__restrict__ cnt, int n, T L, T invL, const FG &fg, T self_r,
+                                          const T *__restrict__ src, T scale, T *__restrict__ out,
+                                          T *__restrict__ vm_out, A &dot) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  dot = A(0);
+  if (s >= n) return;
+  const auto p = pos[s];
+  const T vx = src[3 * s], vy = src[3 * s + 1], vz = src[3 * s + 2];
+  T ax = self_r * vx, ay = self_r * vy, az = self_r * vz;
+  const int c = cnt[s];
+  for (int k = 0; k < c; ++k) {
+    const int t = nbr[(size_t)k * n + s];
+    const auto q = pos[t];
+    const T dx = min_image(p.x - q.x, L, invL);
+    const T dy = min_image(p.y - q.y, L, invL);
+    const T dz = min_image(p.z - q.z, L, invL);
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    const T wx = src[3 * t], wy = src[3 * t + 1], wz = src[3 * t + 2];
+    T Fm, Dm, rinv;
+    if (r2 > T(1e-24)) {
+      rinv = T(1) / sqrt(r2);
+      fg.eval(r2, rinv, Fm, Dm);
+    } else {  // coincident spheres: the r -> 0 limit is isotropic
+      Fm = self_r;
+      Dm = T(0);
+      rinv = T(0);
+    }
+    const T pr = Dm * rinv * rinv * (dx * wx + dy * wy + dz * wz);
+    ax += Fm * wx + pr * dx;
+    ay += Fm * wy + pr * dy;
+    az += Fm * wz + pr * dz;
+  }
+  ax *= scale;
+  ay *= scale;
+  az *= scale;
+  out[3 * s] = ax;
+  out[3 * s + 1] = ay;
+  out[3 * s + 2] = az;
+  if (LZ) {
+    const T ux = vx * scale, uy = vy * scale, uz = vz * scale;
+    vm_out[3 * s] = ux;
+    vm_out[3 * s + 1] = uy;
+    vm_out[3 * s + 2] = uz;
+    dot = (A)ux * (A)ax + (A)uy * (A)ay + (A)uz * (A)az;
+  }
+}
+
+template <typename T, typename A, bool LZ>
+__global__ __launch_bounds__(256) void k_spmv_table(const float4 *__restrict__ pos, const int *__restrict__ nbr,
+                                                    const int *__restrict__ cnt, int n, float L, float invL,
+                                                    const float4 *__restrict__ tab_g, float inv_dr, float self_r,
+                                                    const float *__restrict__ src, float scale, float *__restrict__ out,
+                                                    float *__restrict__ vm_out, LzState<A> *st, A *partials,
+                                                    unsigned *counter) {
+  __shared__ float4 tab[kTableK + 1];
+  __shared__ A sh[16];
+  __shared__ int last;
+  if (LZ) {
+    if (st->done) return;
+    scale = (float)st->inv_beta;
+  }
+  for (int i = threadIdx.x; i <= kTableK; i += blockDim.x) tab[i] = tab_g[i];
+  __syncthreads();
+  FGTable fg{tab, inv_dr};
+  A dot;
+  spmv_body<float, A, FGTable, LZ>(pos, nbr, cnt, n, L, invL, fg, self_r, src, scale, out, vm_out, dot);
+  if (!LZ) return;
+  A bs = block_sum(dot, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = bs;
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    A v = 0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) v += partials[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+      st->alpha[st->m] = v;
+      *counter = 0u;
+    }
+  }
+}
+
+template <bool LZ>
+__global__ __launch_bounds__(256) void k_spmv_exact(const double4 *__restrict__ pos, const int *__restrict__ nbr,
+                                                    const int *__restrict__ cnt, int n, double L, double invL,
+                                                    const double *__restrict__ ser, double xi, double a, double mu0,
+                                                    double small_r2, double self_r, const double *__restrict__ src,
+                                                    double scale, double *__restrict__ out, double *__restrict__ vm_out,
+                                                    LzState<double> *st, double *partials, unsigned *counter) {
+  __shared__ double sh[16];
+  __shared__ int last;
+  if (LZ) {
+    if (st->done) return;
+    scale = st->inv_beta;
+  }
+  FGExact fg{ser, xi, a, mu0, small_r2};
+  double dot;
+  spmv_body<double, double, FGExact, LZ>(pos, nbr, cnt, n, L, invL, fg, self_r, src, scale, out, vm_out, dot);
+  if (!LZ) return;
+  double bs = block_sum(dot, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = bs;
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    double v = 0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) v += partials[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+      st->alpha[st->m] = v;
+      *counter = 0u;
+    }
+  }
+}
+
+// ------------------------------------------------------------- Lanczos
+// Block partial sums of |z|^2 (sorted order vector of length 3n).
+template <typename T, typename A>
+__global__ void k_norm2_partial(const T *__restrict__ z, int len, A *__restrict__ partials) {
+  __shared__ A sh[16];
+  A v = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) v += (A)z[i] * (A)z[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+template <typename A>
+__global__ void k_lz_init(const A *__restrict__ partials, int nparts, LzState<A> *st) {
+  __shared__ A sh[16];
+  A v = 0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += partials[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    const A b0 = sqrt(v);
+    st->beta[0] = b0;
+    st->m = 0;
+    st->rel_change = A(1);
+    st->converged = 0;
+    st->nonfinite = !isfinite(b0);
+    st->done = (b0 == A(0)) || !isfinite(b0);
+    if (b0 == A(0)) st->converged = 1;
+    st->inv_beta = b0 > A(0) ? A(1) / b0 : A(0);
+  }
+}
+
+// w = t - alpha_m v_m - beta_m v_{m-1}; block partials of |w|^2.
+template <typename T, typename A>
+__global__ void k_lz_update(const T *__restrict__ t, const T *__restrict__ vm, const T *__restrict__ vprev,
+                            T *__restrict__ w, int len, LzState<A> *st, A *__restrict__ partials) {
+  __shared__ A sh[16];
+  if (st->done) return;
+  const int m = st->m;
+  const T al = (T)st->alpha[m];
+  const T be = m > 0 ? (T)st->beta[m] : T(0);
+  A v = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
+    T x = t[i] - al * vm[i];
+    if (m > 0) x -= be * vprev[i];
+    w[i] = x;
+    v += (A)x * (A)x;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+// s = T^{1/2} e_1 for the n x n tridiagonal T (diag d, off-diagonal e with
+// e[i] coupling i, i+1), by implicit QL with Wilkinson-type shifts.  One
+// wavefront: lane j holds d[j], e[j]; lane k owns row k of the eigenvector
+// matrix Q (stored column-major in LDS).  Returns s_k in lane k.
+template <typename A>
+__device__ A tridiag_sqrt_e1(int n, A d, A e, A *Q, int &ok) {
+  const int lane = threadIdx.x & 63;
+  const A eps = sizeof(A) == 8 ? A(2.2e-16) : A(1.2e-7);
+  for (int j = 0; j < n; ++j) Q[j * 64 + lane] = (lane == j) ? A(1) : A(0);
+  auto gd = [&](int i) { return __shfl(d, i, 64); };
+  auto ge = [&](int i) { return __shfl(e, i, 64); };
+  ok = 1;
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    while (true) {
+      int mm;
+      for (mm = l; mm < n - 1; ++mm) {
+        const A dd = fabs(gd(mm)) + fabs(gd(mm + 1));
+        if (fabs(ge(mm)) <= eps * dd) break;
+      }
+      if (mm == l) break;
+      if (++iter > 60) {
+        ok = 0;
+        break;
+      }
+      A g = (gd(l + 1) - gd(l)) / (A(2) * ge(l));
+      A r = hypot(g, A(1));
+      g = gd(mm) - gd(l) + ge(l) / (g + copysign(r, g));
+      A s = 1, c = 1, p = 0;
+      bool early = false;
+      for (int i = mm - 1; i >= l; --i) {
+        const A f = s * ge(i), b = c * ge(i);
+        r = hypot(f, g);
+        if (lane == i + 1) e = r;
+        if (r == A(0)) {
+          const A v = gd(i + 1) - p;
+          if (lane == i + 1) d = v;
+          if (lane == mm) e = A(0);
+          early = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = gd(i + 1) - p;
+        r = (gd(i) - g) * s + A(2) * c * b;
+        p = s * r;
+        const A nd = g + p;
+        if (lane == i + 1) d = nd;
+        g = c * r - b;
+        const A qi1 = Q[(i + 1) * 64 + lane], qi = Q[i * 64 + lane];
+        Q[(i + 1) * 64 + lane] = s * qi + c * qi1;
+        Q[i * 64 + lane] = c * qi - s * qi1;
+      }
+      if (early) continue;
+      const A nl = gd(l) - p;
+      if (lane == l) {
+        d = nl;
+        e = g;
+      }
+      if (lane == mm) e = A(0);
+    }
+    if (!ok) break;
+  }
+  __builtin_amdgcn_wave_barrier();
+  A acc = 0;
+  for (int j = 0; j < n; ++j) {
+    const A lam = gd(j);
+    acc += Q[j * 64 + lane] * sqrt(lam > A(0) ? lam : A(0)) * Q[j * 64];
+  }
+  return acc;
+}
+
+// After iteration m: beta_{m+1} = |w|, s = T_{m+1}^{1/2} e_1, convergence test
+// |s_{m+1} - s_m| <= tol |s_{m+1}| (successive iterates; V orthonormal), and
+// the scale 1/beta_{m+1} of the next Lanczos vector.  One wavefront.
+template <typename A>
+__global__ __launch_bounds__(64) void k_lz_check(const A *__restrict__ partials, int nparts, LzState<A> *st, A tol,
+                                                 int max_iter) {
+  __shared__ A Q[kMaxIter * 64];
+  if (st->done) return;
+  const int lane = threadIdx.x;
+  A v = 0;
+  for (int i = lane; i < nparts; i += 64) v += partials[i];
+  v = wave_sum(v);
+  const A bb = sqrt(v);
+  const int m = st->m;
+  const int nn = m + 1;
+  A d = lane < nn ? st->alpha[lane] : A(0);
+  A e = lane < nn - 1 ? st->beta[lane + 1] : A(0);
+  int ok;
+  const A sk = tridiag_sqrt_e1<A>(nn, d, e, Q, ok);
+  const A sold = (lane < m) ? st->s[lane] : A(0);
+  const A dif = lane < nn ? (sk - sold) : A(0);
+  const A num = wave_sum(dif * dif);
+  const A den = wave_sum(lane < nn ? sk * sk : A(0));
+  const A rel = den > A(0) ? sqrt(num / den) : A(0);
+  A scale2 = 0;
+  for (int j = 0; j < nn; ++j) {
+    const A aj = __shfl(d, j, 64);
+    scale2 += aj * aj;
+  }
+  const A bdn = (sizeof(A) == 8 ? A(1e-11) : A(1e-6)) * sqrt(scale2 + bb * bb);
+  const bool finite = isfinite(bb) && isfinite(den) && ok;
+  if (lane < nn) st->s[lane] = sk;
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) {
+    st->beta[nn] = bb;
+    st->rel_change = m > 0 ? rel : A(1);
+    st->m = nn;
+    const bool conv = (m > 0 && rel <= tol) || (bb <= bdn);
+    st->converged = conv && finite;
+    st->nonfinite = !finite;
+    st->done = conv || !finite || nn >= max_iter;
+    st->inv_beta = bb > A(0) ? A(1) / bb : A(0);
+  }
+}
+
+// y = beta_0 sum_{j < m} V_j s_j  (sorted order, length 3n)
+template <typename T, typename A>
+__global__ void k_lz_combine(const T *__restrict__ V, size_t ld, int len, const LzState<A> *st, T *__restrict__ y) {
+  __shared__ A sc[kMaxIter];
+  const int m = st->m;
+  if (threadIdx.x < (unsigned)m) sc[threadIdx.x] = st->beta[0] * st->s[threadIdx.x];
+  __syncthreads();
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
+    A acc = 0;
+    for (int j = 0; j < m; ++j) acc += sc[j] * (A)V[(size_t)j * ld + i];
+    y[i] = (T)acc;
+  }
+}
+
+// ------------------------------------------------------------- vectors
+template <typename T>
+__global__ void k_gather3(const T *__restrict__ in, const int *__restrict__ perm, T *__restrict__ out, int n) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int i = perm[s];
+  out[3 * s] = in[3 * i];
+  out[3 * s + 1] = in[3 * i + 1];
+  out[3 * s + 2] = in[3 * i + 2];
+}
+
+// out[perm[s]] = cr * yr[s] + dt * ur[s] + wv[s]   (null terms omitted)
+template <typename T>
+__global__ void k_finalize(const int *__restrict__ perm, const T *__restrict__ yr, T cr, const T *__restrict__ ur, T dt,
+                           const T *__restrict__ wv, T *__restrict__ out, int n) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int i = perm[s];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    T v = T(0);
+    if (yr) v += cr * yr[3 * s + d];
+    if (ur) v += dt * ur[3 * s + d];
+    if (wv) v += wv[3 * s + d];
+    out[3 * i + d] = v;
+  }
+}
+
+// ------------------------------------------------ Philox noise for z1
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B97F4A7C15ull;
+      k1 += 0xBB67AE8584CAA73Bull;
+    }
+    const uint64_t lo0 = 0xD2E7470EE14C6C93ull * c[0], hi0 = __umul64hi(0xD2E7470EE14C6C93ull, c[0]);
+    const uint64_t lo1 = 0xCA5A826395121157ull * c[2], hi1 = __umul64hi(0xCA5A826395121157ull, c[2]);
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+template <typename T> __device__ __forceinline__ void box_muller(uint64_t wa, uint64_t wb, T &na, T &nb);
+template <> __device__ __forceinline__ void box_muller<double>(uint64_t wa, uint64_t wb, double &na, double &nb) {
+  const double ua = ((double)(wa >> 11) + 0.5) * 0x1.0p-53;
+  const double ub = ((double)(wb >> 11) + 0.5) * 0x1.0p-53;
+  const double rho = sqrt(-2.0 * log(ua));
+  double sn, cs;
+  sincospi(2.0 * ub, &sn, &cs);
+  na = rho * cs;
+  nb = rho * sn;
+}
+template <> __device__ __forceinline__ void box_muller<float>(uint64_t wa, uint64_t wb, float &na, float &nb) {
+  const float ua = ((float)(uint32_t)(wa >> 40) + 0.5f) * 0x1.0p-24f;
+  const float ub = ((float)(uint32_t)(wb >> 40) + 0.5f) * 0x1.0p-24f;
+  const float rho = sqrtf(-2.0f * logf(ua));
+  float sn, cs;
+  sincospif(2.0f * ub, &sn, &cs);
+  na = rho * cs;
+  nb = rho * sn;
+}
+
+// z1 in caller order: block b covers elements 4b .. 4b+3 (key (seed, 0)).
+template <typename T>
+__global__ void k_real_noise(T *__restrict__ z, int len, uint64_t seed, uint64_t sample) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (4 * b >= len) return;
+  uint64_t c[4] = {(uint64_t)b, sample, 0ull, 0ull};
+  philox4x64_10(c, seed, 0ull);
+  T n0, n1, n2, n3;
+  box_muller<T>(c[0], c[1], n0, n1);
+  box_muller<T>(c[2], c[3], n2, n3);
+  const int q = 4 * b;
+  z[q] = n0;
+  if (q + 1 < len) z[q + 1] = n1;
+  if (q + 2 < len) z[q + 2] = n2;
+  if (q + 3 < len) z[q + 3] = n3;
+}
+
+// ----------------------------------------------------------- launchers
+static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+
+template <typename T>
+void launch_bin(pse_ctx *c, const void *pos) {
+  using T4 = typename vec4<T>::type;
+  const int n = c->n;
+  const T L = (T)c->d.L, invL = (T)(1.0 / c->d.L), inv_cs = (T)(1.0 / c->d.cs);
+  hipMemsetAsync(c->cell_count, 0, sizeof(int) * c->ncell, c->stream);
+  hipMemsetAsync(c->flags, 0, sizeof(int) * 4, c->stream);
+  k_wrap_bin<T><<<nblk(n, 256), 256, 0, c->stream>>>((const T *)pos, n, L, invL, inv_cs, c->d.nc, (T4 *)c->pos_w,
+                                                     c->cell_of, c->cell_count, c->flags);
+  k_scan_cells<<<1, 1024, 0, c->stream>>>(c->cell_count, c->cell_start, c->cell_count + c->ncell, c->ncell);
+  k_scatter<<<nblk(n, 256), 256, 0, c->stream>>>(c->cell_of, c->cell_start, c->cell_count + c->ncell, c->perm, n);
+  k_cell_sort<<<nblk(c->ncell, 256), 256, 0, c->stream>>>(c->cell_start, c->perm, c->ncell);
+  k_gather_pos<T4><<<nblk(n, 256), 256, 0, c->stream>>>((const T4 *)c->pos_w, c->perm, (T4 *)c->pos_s, n);
+}
+
+template <typename T>
+void launch_nbr(pse_ctx *c) {
+  using T4 = typename vec4<T>::type;
+  const int n = c->n;
+  const T L = (T)c->d.L, invL = (T)(1.0 / c->d.L), inv_cs = (T)(1.0 / c->d.cs);
+  const T rc2 = (T)(c->p.rcut * c->p.rcut);
+  k_nbr_build<T><<<nblk(n, 128), 128, 0, c->stream>>>((const T4 *)c->pos_s, c->cell_start, n, c->d.nc, L, invL,
+                                                       inv_cs, rc2, c->nbr, c->nbr_cnt, c->nbr_cap, c->flags);
+}
+
+template <typename T, typename A>
+void launch_spmv(pse_ctx *c, const void *src, void *out, bool lz, void *vm_out) {
+  const int n = c->n;
+  const int nb = nblk(n, 256);
+  if constexpr (sizeof(T) == 8) {
+    k_spmv_exact<false><<<nb, 256, 0, c->stream>>>(
+        (const double4 *)c->pos_s, c->nbr, c->nbr_cnt, n, c->d.L, 1.0 / c->d.L, c->series, c->p.xi, c->p.a, c->d.mu0,
+        c->small_r2, c->d.self_r, (const double *)src, 1.0, (double *)out, nullptr, nullptr, nullptr, nullptr);
+    (void)lz; (void)vm_out;
+  } else {
+    (void)lz; (void)vm_out;
+    k_spmv_table<float, A, false><<<nb, 256, 0, c->stream>>>(
+        (const float4 *)c->pos_s, c->nbr, c->nbr_cnt, n, (float)c->d.L, (float)(1.0 / c->d.L), c->table,
+        (float)(kTableK / c->p.rcut), (float)c->d.self_r, (const float *)src, 1.0f, (float *)out, nullptr, nullptr,
+        nullptr, nullptr);
+  }
+}
+
+template <typename T, typename A>
+void launch_lz_init(pse_ctx *c, const void *z) {
+  const int len = 3 * c->n;
+  k_norm2_partial<T, A><<<kRedBlock, 256, 0, c->stream>>>((const T *)z, len, (A *)c->partials);
+  k_lz_init<A><<<1, 256, 0, c->stream>>>((const A *)c->partials, kRedBlock, (LzState<A> *)c->lz);
+}
+
+// One Lanczos iteration: SpMV (+alpha), update (+|w|^2 partials), check.
+// src = z (m = 0) or the previous residual w.
+template <typename T, typename A>
+void launch_lz_iter(pse_ctx *c, int m, const void *z) {
+  const int n = c->n, len = 3 * n;
+  const size_t ld = (size_t)len;
+  T *V = (T *)c->V;
+  T *t = (T *)c->vbuf[2];
+  T *w = (T *)c->vbuf[3];
+  const T *src = m == 0 ? (const T *)z : w;
+  const int nb = nblk(n, 256);
+  auto *st = (LzState<A> *)c->lz;
+  if constexpr (sizeof(T) == 8) {
+    k_spmv_exact<true><<<nb, 256, 0, c->stream>>>((const double4 *)c->pos_s, c->nbr, c->nbr_cnt, n, c->d.L,
+                                                   1.0 / c->d.L, c->series, c->p.xi, c->p.a, c->d.mu0, c->small_r2,
+                                                   c->d.self_r, (const double *)src, 1.0, (double *)t,
+                                                   (double *)(V + (size_t)m * ld), st, (double *)c->partials,
+                                                   c->counter);
+  } else {
+    k_spmv_table<float, A, true><<<nb, 256, 0, c->stream>>>(
+        (const float4 *)c->pos_s, c->nbr, c->nbr_cnt, n, (float)c->d.L, (float)(1.0 / c->d.L), c->table,
+        (float)(kTableK / c->p.rcut), (float)c->d.self_r, (const float *)src, 1.0f, (float *)t,
+        (float *)(V + (size_t)m * ld), st, (A *)c->partials, c->counter);
+  }
+  const T *vprev = m > 0 ? V + (size_t)(m - 1) * ld : V;
+  k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * ld, vprev, w, len, st, (A *)c->partials);
+  k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, st, (A)c->p.lanczos_tol,
+                                         c->p.lanczos_max_iter);
+}
+
+template <typename T, typename A>
+void launch_lz_combine(pse_ctx *c, void *y) {
+  const int len = 3 * c->n;
+  k_lz_combine<T, A><<<nblk(len, 256) < 2048 ? nblk(len, 256) : 2048, 256, 0, c->stream>>>(
+      (const T *)c->V, (size_t)len, len, (const LzState<A> *)c->lz, (T *)y);
+}
+
+template <typename T>
+void launch_gather3(pse_ctx *c, const void *in, void *out) {
+  k_gather3<T><<<nblk(c->n, 256), 256, 0, c->stream>>>((const T *)in, c->perm, (T *)out, c->n);
+}
+
+template <typename T>
+void launch_finalize(pse_ctx *c, const void *yr, double cr, const void *ur, double dt, const void *wv, void *out) {
+  k_finalize<T><<<nblk(c->n, 256), 256, 0, c->stream>>>(c->perm, (const T *)yr, (T)cr, (const T *)ur, (T)dt,
+                                                        (const T *)wv, (T *)out, c->n);
+}
+
+template <typename T>
+void launch_real_noise(pse_ctx *c, void *z, uint64_t seed, uint64_t sample) {
+  const int len = 3 * c->n;
+  k_real_noise<T><<<nblk((len + 3) / 4, 256), 256, 0, c->stream>>>((T *)z, len, seed, sample);
+}
+
+#define INST_T(T)                                                                                  \
+  template void launch_bin<T>(pse_ctx *, const void *);                                            \
+  template void launch_nbr<T>(pse_ctx *);                                                          \
+  template void launch_gather3<T>(pse_ctx *, const void *, void *);                                \
+  template void launch_finalize<T>(pse_ctx *, const void *, double, const void *, double, const void *, void *); \
+  template void launch_real_noise<T>(pse_ctx *, void *, uint64_t, uint64_t);
+INST_T(float)
+INST_T(double)
+#define INST_TA(T, A)                                                           \
+  template void launch_spmv<T, A>(pse_ctx *, const void *, void *, bool, void *); \
+  template void launch_lz_init<T, A>(pse_ctx *, const void *);                  \
+  template void launch_lz_iter<T, A>(pse_ctx *, int, const void *);             \
+  template void launch_lz_combine<T, A>(pse_ctx *, void *);
+INST_TA(float, float)
+INST_TA(float, double)
+INST_TA(double, double)
+
+}  // namespace pse

@@ -1,0 +1,29 @@
+// Kernel launchers shared between the kernel sources and the C ABI.
+#pragma once
+#include "pse_internal.hpp"
+
+namespace pse {
+
+enum class GridOp { FftZ, FftStrided, XFused };
+
+// particle side (k_particles.hip)
+template <typename T> void launch_bin(pse_ctx *c, const void *pos);
+template <typename T> void launch_nbr(pse_ctx *c);
+template <typename T, typename A> void launch_spmv(pse_ctx *c, const void *src, void *out, bool lz, void *vm_out);
+template <typename T, typename A> void launch_lz_init(pse_ctx *c, const void *z);
+template <typename T, typename A> void launch_lz_iter(pse_ctx *c, int m, const void *z);
+template <typename T, typename A> void launch_lz_combine(pse_ctx *c, void *y);
+template <typename T> void launch_gather3(pse_ctx *c, const void *in, void *out);
+template <typename T>
+void launch_finalize(pse_ctx *c, const void *yr, double cr, const void *ur, double dt, const void *wv, void *out);
+template <typename T> void launch_real_noise(pse_ctx *c, void *z, uint64_t seed, uint64_t sample);
+
+// grid side (k_grid.hip)
+//   FftZ:       a = src, b = dst, x = direction (-1 forward R2C, +1 inverse C2R)
+//   FftStrided: b = data, x = axis (0: x, 1: y), y = direction
+//   XFused:     a = transformed grid-noise spectrum (or null), b = data,
+//               x = forces present, y = noise (0 none, 1 Philox, 2 grid noise)
+template <typename T> void launch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoef *wc, int x, int y);
+template <typename T> void launch_spread_interp(pse_ctx *c, bool spread, const void *vec, void *grid_or_out);
+
+}  // namespace pse

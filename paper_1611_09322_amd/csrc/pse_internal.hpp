@@ -1,0 +1,108 @@
+// Internal declarations of the gfx950 PSE sampler library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+
+#include "../../include/pse.h"
+
+namespace pse {
+
+constexpr int kMaxIter = 64;     // Lanczos basis capacity
+constexpr int kTableK = 2048;    // F/G table intervals on [0, rcut]
+constexpr int kSeriesTerms = 16; // small-r series terms of the wave complement
+constexpr int kRedBlock = 256;   // threads per block of reduction kernels
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+template <typename T> struct vec4;
+template <> struct vec4<float> { using type = float4; };
+template <> struct vec4<double> { using type = double4; };
+
+// Lanczos state kept in device memory (A = accumulation precision).
+template <typename A> struct LzState {
+  A alpha[kMaxIter];
+  A beta[kMaxIter + 1];  // beta[0] = |z|, beta[m+1] couples v_m and v_{m+1}
+  A s[kMaxIter];         // T_m^{1/2} e_1 of the latest iterate
+  A rel_change;          // |s_m - s_{m-1}| / |s_m|
+  A inv_beta;            // scale of the next Lanczos vector
+  int m;                 // completed iterations
+  int done;              // 1: converged (or broke down / max_iter reached)
+  int converged;         // 1: tolerance met or invariant subspace
+  int nonfinite;
+};
+
+// Coefficients of the wave-space scaling applied per k (fused x pass).
+struct WaveCoef {
+  double two_pi_over_L;  // k = 2 pi j / L
+  double a;              // sphere radius
+  double inv_4xi2;       // 1/(4 xi^2)
+  double sigma2;         // Gaussian variance
+  double det_scale;      // dt / (eta M^3): deterministic factor before B/ghat^2
+  double sto_scale;      // sqrt(2 kT dt) / sqrt(eta V): stochastic factor before sqrt(B)/ghat
+  double w_scale;        // M^{-3/2}: grid noise DFT normalisation
+  uint64_t seed, counter;
+  int use_philox;        // noise from Philox (key (seed,1))
+};
+
+// ---------------------------------------------------------------- host side
+struct Derived {
+  double L, h, sigma, gm, eta_se, eps_real, eps_wave, eps_quad;
+  double mu0;      // 1 / (6 pi eta a)
+  double self_r;   // F_self * mu0
+  double cs;       // cell side
+  int nc;          // cells per side
+};
+
+// Appendix A closed forms and the small-r series, FP64 (fg_host.cpp)
+void fg_eval_host(double r, double xi, double a, const double *serF, const double *serG, double *F, double *G);
+double fg_self(double xi, double a);
+void fg_series_coeffs(double xi, double a, double *serF, double *serG);
+double fg_small_r_threshold(double xi, double a);
+void fg_build_table(double xi, double a, double rc, double mu0, const double *serF, const double *serG,
+                    float4 *tab);
+pse_status derive_params(const pse_params &p, Derived *d);
+bool fft_size_supported(int M);
+
+}  // namespace pse
+
+struct pse_ctx {
+  pse_params p;
+  pse::Derived d;
+  hipStream_t stream = nullptr;
+  bool dbl = false;     // FP64 storage
+  bool acc_dbl = true;  // FP64 Lanczos scalars
+  int n = 0;
+  int ncell = 0;
+  bool have_pos = false;
+  int last_iters = 4;
+  // device buffers
+  void *pos_w = nullptr;    // T4 [n], caller order, wrapped
+  void *pos_s = nullptr;    // T4 [n], sorted
+  int *perm = nullptr;      // sorted -> caller index
+  int *cell_of = nullptr;
+  int *cell_count = nullptr;
+  int *cell_start = nullptr;
+  int *nbr = nullptr;
+  int *nbr_cnt = nullptr;
+  int nbr_cap = 0;
+  int *flags = nullptr;     // [0] nonfinite, [1] max neighbours
+  int *flags_h = nullptr;   // pinned copy
+  void *vbuf[8] = {};       // T [3n] work vectors (sorted order)
+  void *V = nullptr;        // T [(kMaxIter+1) 3n]
+  void *lz = nullptr;       // LzState<A>
+  void *lz_h = nullptr;     // pinned copy
+  void *partials = nullptr; // A [max blocks]
+  unsigned *counter = nullptr;
+  float4 *table = nullptr;  // F/G table (FP32 modes)
+  double *series = nullptr; // [2*kSeriesTerms] series coefficients (device)
+  double series_h[2 * pse::kSeriesTerms];
+  double small_r2 = 0;      // r^2 below which the series is used
+  void *grid = nullptr;     // T [3 M^3]
+  void *grid2 = nullptr;    // T [3 M^3] (grid-noise path, lazily)
+  void *tw_M = nullptr;     // T2 [M] twiddles exp(-2 pi i k / M)
+  void *tw_H = nullptr;     // T2 [M/2]
+};
