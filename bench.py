@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Throughput of the PSE Brownian sampler on one MI355X.
+
+One step = one Brownian displacement of every particle with the whole hot
+path: wrap + linked-cell sort + neighbour list (positions change every step),
+real-space Philox noise, Lanczos M_r^{1/2} z1, the near-field product M_r F,
+Gaussian spreading of the (random) forces, forward FFT, B(k) scaling with the
+k-space noise, inverse FFT, interpolation and the final combine
+(dx = dt M F + sqrt(2 kT dt) M^{1/2} dW, the combined FFT pair of Sec. III).
+
+Workload (default): N = 1,000,000 hard spheres a = 1 at volume fraction 0.3
+(random sequential addition + Monte Carlo sweeps), cubic periodic box,
+256^3 grid, P = 8, xi a = 0.5, rc = 8a, relative tolerance 1e-3.
+
+Prints one JSON line.  Metric: samples x particles per second.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "samples·particles/s, N=1M φ=0.3 @1e-3 err: plain FP32 vs mixed+learned precond"
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(stage, n, grid, pairs, lanczos):
+    """Algorithmic HBM bytes of one launch of a stage (FP32 storage):
+    every operand read once and every result written once."""
+    g = 3 * grid**3 * 4  # one 3-component real grid (= the half spectrum)
+    if stage == "spmv":
+        # positions (float4) + source vector + neighbour count + result
+        # (+ the stored Lanczos basis vector) + one 4-byte index per pair
+        return n * (16 + 12 + 4 + 12 + (12 if lanczos else 0)) + 4 * pairs
+    if stage == "fft":
+        return 2 * g
+    if stage == "xfused":
+        return 2 * g
+    if stage == "spread":
+        return n * (16 + 12) + g
+    if stage == "interp":
+        return g + n * (16 + 12)
+    if stage == "nbr":
+        return n * (16 + 4) + 4 * pairs
+    return None
+
+
+def make_workload(args):
+    import numpy as np
+
+    import synth
+
+    t0 = time.time()
+    x, L = synth.hard_spheres(args.n, args.phi, a=1.0, seed=1003, sweeps=args.sweeps)
+    # caller order is arbitrary: shuffle so that the library's own sort is exercised
+    perm = np.random.default_rng(7).permutation(len(x))
+    x = np.ascontiguousarray(x[perm])
+    F = synth.normals(8, (len(x), 3))
+    print(f"[bench] workload: N={len(x)} phi={args.phi} L={L:.3f} sweeps={args.sweeps} "
+          f"generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    return x, L, F
+
+
+def run_variant(pse, torch, x, L, F, args, precision):
+    s = pse.Sampler(len(x), L, a=1.0, eta=1.0, kT=1.0, xi=args.xi, rcut=args.rc, grid=args.grid,
+                    support=args.support, tol=args.tol, max_iter=64, precision=precision)
+    pos = torch.as_tensor(x, dtype=torch.float32, device="cuda")
+    frc = torch.as_tensor(F, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(pos)
+    counter = [0]
+
+    def step():
+        s.set_positions(pos)
+        _, st = s.sample(2024, counter[0], dt=1e-3, forces=frc, out=out)
+        counter[0] += 1
+        return st
+
+    # warm-up with every stage timed: find where the GPU time goes
+    s.profile(list(pse.STAGES))
+    for _ in range(args.warmup):
+        st = step()
+    torch.cuda.synchronize()
+    breakdown = s.profile_read()
+    total = sum(v[0] for v in breakdown.values())
+    dom = max((k for k in breakdown if stage_bytes(k, 1, 1, 1, False) is not None), key=lambda k: breakdown[k][0])
+    # timed region: events only around the dominant kernel's launches
+    s.profile([dom])
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+        iters.append(st.lanczos_iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dom_t = s.profile_read()[dom]
+    s.profile([])
+    ms_step = 1e3 * dt / args.steps
+    res = {
+        "value": len(x) * args.steps / dt,
+        "ms_per_step": ms_step,
+        "lanczos_iters_mean": sum(iters) / len(iters),
+        "neighbor_pairs": st.neighbor_pairs,
+        "max_neighbors": st.max_neighbors,
+        "warmup_breakdown_ms_per_step": {k: round(v[0] / max(args.warmup, 1), 4) for k, v in breakdown.items()},
+        "warmup_gpu_ms_per_step": total / max(args.warmup, 1),
+        "dominant": dom,
+        "dominant_ms_avg": dom_t[0] / max(dom_t[1], 1),
+        "dominant_launches_per_step": dom_t[1] / args.steps,
+        "dominant_share": breakdown[dom][0] / total if total else None,
+    }
+    s.close()
+    return res
+
+
+def cpu_baseline(args):
+    """The FP64 oracle (dense M_r + eigendecomposition root + direct Fourier
+    sums), timed on a bounded sample of the same workload: an independent
+    1000-particle periodic box at the same volume fraction, xi, rc, P and
+    about the same grid spacing."""
+    import numpy as np
+
+    import synth
+    from oracle import sampler
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        blas_threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:  # pragma: no cover
+        blas_threads = None
+    n = 1000
+    x, L = synth.hard_spheres(n, args.phi, seed=1099, sweeps=50)
+    p = sampler.Params(L=L, xi=args.xi, rc=args.rc, M=32)
+    F = synth.normals(9, (n, 3))
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        sampler.displacement_philox(x, p, 2024, reps, dt=1e-3, forces=F, bits=24)
+        reps += 1
+        if time.perf_counter() - t0 > args.cpu_seconds:
+            break
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": n * reps / dt,
+        "unit": "samples·particles/s",
+        "cores": blas_threads or cores,
+        "kind": "oracle",
+        "sample": f"FP64 oracle, {reps} displacement(s) of an independent N={n} box at phi={args.phi} "
+                  f"(L={L:.2f}a, 32^3 k-set, xi a={args.xi}, rc={args.rc}a) with forces; "
+                  f"{cores} host cores visible, BLAS threads {blas_threads}",
+        "seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--phi", type=float, default=0.3)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--support", type=int, default=8)
+    ap.add_argument("--xi", type=float, default=0.5)
+    ap.add_argument("--rc", type=float, default=8.0)
+    ap.add_argument("--tol", type=float, default=1e-3)
+    ap.add_argument("--sweeps", type=int, default=2000, help="Monte Carlo relaxation sweeps after RSA")
+    ap.add_argument("--variants", default="fp32,mixed")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1611_09322_amd as pse
+
+    pse.load()
+    torch.cuda.set_device(0)
+    x, L, F = make_workload(args)
+    variants = {}
+    for v in args.variants.split(","):
+        print(f"[bench] variant {v}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+        variants[v] = run_variant(pse, torch, x, L, F, args, v)
+        print(f"[bench] variant {v}: {json.dumps(variants[v])}", file=sys.stderr, flush=True)
+    head = "mixed" if "mixed" in variants else next(iter(variants))
+    hv = variants[head]
+    dom = hv["dominant"]
+    nbytes = stage_bytes(dom, args.n, args.grid, hv["neighbor_pairs"], lanczos=(dom == "spmv"))
+    achieved = nbytes / (hv["dominant_ms_avg"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": hv["dominant_ms_avg"]}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    line = {
+        "metric": METRIC,
+        "value": hv["value"],
+        "unit": "samples·particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hv["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"PSE Brownian displacement with random forces, N={args.n} hard spheres a=1, "
+                        f"phi={args.phi} (RSA + {args.sweeps} MC sweeps), grid {args.grid}^3, P={args.support}, "
+                        f"xi a={args.xi}, rc={args.rc}a, tol {args.tol}",
+            "variant": head,
+            "precond": "none",
+        },
+        "variants": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
+                         "lanczos_iters_mean": v["lanczos_iters_mean"],
+                         "breakdown_ms": v["warmup_breakdown_ms_per_step"]} for k, v in variants.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

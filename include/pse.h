@@ -81,7 +81,23 @@ typedef struct {
   double lanczos_rel_change;/* final ||y_m - y_{m-1}|| / ||y_m|| */
   int32_t max_neighbors;    /* largest near-field neighbour count */
   int32_t precond_fallbacks;/* particles whose learned block fell back to I */
+  int64_t neighbor_pairs;   /* ordered near-field pairs (sum of neighbour counts) */
 } pse_stats;
+
+/* Stages of the hot path, for GPU-time accounting (pse_profile). */
+typedef enum {
+  PSE_STAGE_BIN = 0,      /* wrap, linked-cell counting sort, sorted gather */
+  PSE_STAGE_NBR = 1,      /* near-field neighbour list */
+  PSE_STAGE_SPMV = 2,     /* one near-field product M_r v (Lanczos or forces) */
+  PSE_STAGE_LANCZOS = 3,  /* Lanczos vector update, reductions, tridiagonal solve, combine */
+  PSE_STAGE_NOISE = 4,    /* real-space Philox noise */
+  PSE_STAGE_SPREAD = 5,   /* Gaussian spreading of forces */
+  PSE_STAGE_FFT = 6,      /* z and y FFT passes (forward and inverse) */
+  PSE_STAGE_XFUSED = 7,   /* x pass with B(k), projection, noise */
+  PSE_STAGE_INTERP = 8,   /* Gaussian interpolation */
+  PSE_STAGE_OTHER = 9,    /* gathers, final combine, grid clears */
+  PSE_NSTAGES = 10
+} pse_stage;
 
 typedef struct {
   double h;                 /* grid spacing L/M */
@@ -167,6 +183,17 @@ pse_status pse_wave_apply(pse_ctx *ctx, const void *forces_dev, void *u_dev);
 
 /* u = (M_r + M_w) F, the deterministic mobility product (n x 3). */
 pse_status pse_mobility_apply(pse_ctx *ctx, const void *forces_dev, void *u_dev);
+
+/* GPU-time accounting: for every stage whose bit (1 << pse_stage) is set in
+ * stage_mask, each kernel launch of that stage is bracketed by HIP events on
+ * the context stream.  0 switches accounting off.  Events are recorded only
+ * for selected stages, so unselected stages run exactly as without it. */
+pse_status pse_profile(pse_ctx *ctx, uint32_t stage_mask);
+
+/* Elapsed GPU milliseconds and launch counts per stage since the last read
+ * (arrays of PSE_NSTAGES entries, host memory).  Synchronises the stream and
+ * resets the accumulators. */
+pse_status pse_profile_read(pse_ctx *ctx, double *ms, int32_t *launches);
 
 #ifdef __cplusplus
 }

@@ -46,6 +46,7 @@ class Stats(ctypes.Structure):
         ("lanczos_rel_change", ctypes.c_double),
         ("max_neighbors", ctypes.c_int32),
         ("precond_fallbacks", ctypes.c_int32),
+        ("neighbor_pairs", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -91,7 +92,10 @@ _SIGS = {
     "pse_wave_sample": ([_VP, _VP, _VP], ctypes.c_int),
     "pse_wave_apply": ([_VP, _VP, _VP], ctypes.c_int),
     "pse_mobility_apply": ([_VP, _VP, _VP], ctypes.c_int),
+    "pse_profile": ([_VP, ctypes.c_uint32], ctypes.c_int),
+    "pse_profile_read": ([_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
 }
+STAGES = ("bin", "nbr", "spmv", "lanczos", "noise", "spread", "fft", "xfused", "interp", "other")
 EXPORTED = tuple(_SIGS)
 
 
@@ -200,6 +204,17 @@ def pse_mobility_apply(ctx, f_ptr, u_ptr):
     return _check(load().pse_mobility_apply(ctx, f_ptr, u_ptr), "pse_mobility_apply")
 
 
+def pse_profile(ctx, mask):
+    return _check(load().pse_profile(ctx, mask), "pse_profile")
+
+
+def pse_profile_read(ctx):
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (ctypes.c_int32 * len(STAGES))()
+    _check(load().pse_profile_read(ctx, ms, cnt), "pse_profile_read")
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
+
+
 # ----------------------------------------------------------------- wrapper
 class Sampler:
     """One sampling context.  Tensors are (n, 3) on the current HIP device;
@@ -233,6 +248,13 @@ class Sampler:
             self.close()
         except Exception:
             pass
+
+    def profile(self, stages):
+        """Time the named stages with HIP events (see STAGES); [] = off."""
+        pse_profile(self.ctx, sum(1 << STAGES.index(s) for s in stages))
+
+    def profile_read(self):
+        return pse_profile_read(self.ctx)
 
     def derived(self):
         return pse_get_derived(self.ctx).as_dict()

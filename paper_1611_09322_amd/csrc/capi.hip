@@ -47,11 +47,12 @@ void free_ctx(pse_ctx *c) {
                  c->flags, c->V, c->lz, c->partials, c->counter, c->table, c->series, c->grid, c->grid2, c->tw_M,
                  c->tw_H};
   for (void *p : dev)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   for (void *p : c->vbuf)
-    if (p) hipFree(p);
-  if (c->flags_h) hipHostFree(c->flags_h);
-  if (c->lz_h) hipHostFree(c->lz_h);
+    if (p) (void)hipFree(p);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->flags_h) (void)hipHostFree(c->flags_h);
+  if (c->lz_h) (void)hipHostFree(c->lz_h);
   delete c;
 }
 
@@ -71,19 +72,22 @@ template <typename T> void upload_twiddles(pse_ctx *c, Alloc &al) {
   c->tw_M = al.dev(sizeof(CT) * M);
   c->tw_H = al.dev(sizeof(CT) * H);
   if (al.st == PSE_OK) {
-    hipMemcpy(c->tw_M, a.data(), sizeof(CT) * M, hipMemcpyHostToDevice);
-    hipMemcpy(c->tw_H, b.data(), sizeof(CT) * H, hipMemcpyHostToDevice);
+    if (hipMemcpy(c->tw_M, a.data(), sizeof(CT) * M, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->tw_H, b.data(), sizeof(CT) * H, hipMemcpyHostToDevice) != hipSuccess)
+      al.st = PSE_ERR_HIP;
   }
 }
 
 // Neighbour-list capacity: expected count in a sphere of radius rc at the
 // mean density, plus margin (grown on overflow in set_positions).
+// Always a multiple of 8 (the 16-bit list is stored in chunks of 8).
 int nbr_capacity(const pse_ctx *c) {
   const double vol = c->d.L * c->d.L * c->d.L;
   const double expect = c->n / vol * 4.18879020478639 * c->p.rcut * c->p.rcut * c->p.rcut;
   int cap = (int)(1.6 * expect + 48);
   if (cap > c->n) cap = c->n;
-  return cap < 1 ? 1 : cap;
+  if (cap < 8) cap = 8;
+  return (cap + 7) & ~7;
 }
 
 WaveCoef wave_coef(const pse_ctx *c, double det_scale, double sto_scale, uint64_t seed, uint64_t counter) {
@@ -106,6 +110,15 @@ WaveCoef wave_coef(const pse_ctx *c, double det_scale, double sto_scale, uint64_
 
 pse_status hip_status(hipError_t e) { return e == hipSuccess ? PSE_OK : PSE_ERR_HIP; }
 
+hipEvent_t next_event(pse_ctx *c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
 // ---------------------------------------------------------- hot path
 template <typename T, typename A>
 pse_status real_sample_core(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
@@ -118,8 +131,9 @@ pse_status real_sample_core(pse_ctx *c, const void *z_sorted, void *y_sorted, ps
     const int k = chunk < maxit - launched ? chunk : maxit - launched;
     for (int i = 0; i < k; ++i) launch_lz_iter<T, A>(c, launched + i, z_sorted);
     launched += k;
-    hipMemcpyAsync(h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream);
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+    if (hipMemcpyAsync(h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return PSE_ERR_HIP;
     if (h->done) break;
     chunk = 1;
   }
@@ -141,7 +155,8 @@ template <typename T>
 pse_status wave_core(pse_ctx *c, const void *f_sorted, int noise, const void *W, const WaveCoef &wc, void *out) {
   const size_t M3 = (size_t)c->p.grid * c->p.grid * c->p.grid;
   if (!f_sorted && noise == 0) {
-    return hip_status(hipMemsetAsync(out, 0, sizeof(T) * 3 * c->n, c->stream));
+    ProfScope ps(c, PSE_STAGE_OTHER);
+    return hip_status(hipMemsetAsync(out, 0, sizeof(T) * 4 * c->n, c->stream));
   }
   if (noise == 2) {
     if (!c->grid2) {
@@ -155,7 +170,6 @@ pse_status wave_core(pse_ctx *c, const void *f_sorted, int noise, const void *W,
     launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid2, nullptr, 0, -1);
   }
   if (f_sorted) {
-    hipMemsetAsync(c->grid, 0, sizeof(T) * 3 * M3, c->stream);
     launch_spread_interp<T>(c, true, f_sorted, c->grid);
     launch_grid_op<T>(c, GridOp::FftZ, c->grid, c->grid, nullptr, -1, 0);
     launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid, nullptr, 1, -1);
@@ -207,7 +221,10 @@ pse_status sample_impl(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter,
   const pse_status sw = wave_core<T>(c, (forces && dt > 0) ? f_s : nullptr, noise, W, wc, wave);
   if (sw != PSE_OK) return sw;
   launch_finalize<T>(c, (have_real && cr > 0) ? yr : nullptr, cr, (forces && dt > 0) ? ur : nullptr, dt, wave, disp);
-  if (stats) stats->max_neighbors = c->flags_h[1];
+  if (stats) {
+    stats->max_neighbors = c->flags_h[1];
+    stats->neighbor_pairs = c->pairs;
+  }
   (void)pi;
   const pse_status se = hip_status(hipGetLastError());
   return se != PSE_OK ? se : st;
@@ -230,31 +247,65 @@ pse_status sample_impl(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter,
     }                                                         \
   } while (0)
 
+// Largest dynamic LDS used by one workgroup of the staged near-field kernels.
+constexpr size_t kLdsBudget = 150 * 1024;
+
+template <typename T>
+pse_status build_neighbors(pse_ctx *c) {
+  if (c->lds_B) launch_nbr_lds(c);
+  else launch_nbr<T>(c);
+  if (hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return PSE_ERR_HIP;
+  return PSE_OK;
+}
+
 template <typename T>
 pse_status set_positions_impl(pse_ctx *c, const void *pos) {
+  c->have_pos = false;
   launch_bin<T>(c, pos);
-  launch_nbr<T>(c);
-  hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream);
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
-  if (c->flags_h[0]) {
-    c->have_pos = false;
-    return PSE_ERR_NONFINITE;
+  // FP32 storage: stage the near-field halo in LDS when it fits
+  c->lds_B = 0;
+  if (sizeof(T) == 4) {
+    for (int B = 2; B >= 1; --B) {
+      if (c->d.nc < B + 2) continue;
+      if (hipMemsetAsync(c->flags + 4, 0, sizeof(int), c->stream) != hipSuccess) return PSE_ERR_HIP;
+      launch_halo_size(c, B);
+      if (hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+          hipStreamSynchronize(c->stream) != hipSuccess)
+        return PSE_ERR_HIP;
+      if (c->flags_h[0]) return PSE_ERR_NONFINITE;
+      const int hmax = c->flags_h[4];
+      if (hmax <= 65535 && 2 * sizeof(float4) * (size_t)hmax <= kLdsBudget) {
+        c->lds_B = B;
+        c->hcap = hmax > 0 ? hmax : 1;
+        const int nb = (c->d.nc + B - 1) / B;
+        c->lds_blocks = nb * nb * nb;
+        break;
+      }
+    }
   }
+  pse_status st = build_neighbors<T>(c);
+  if (st != PSE_OK) return st;
+  if (c->flags_h[0]) return PSE_ERR_NONFINITE;
   if (c->flags_h[1] > c->nbr_cap) {
-    const int cap = c->flags_h[1] + 32;
-    hipFree(c->nbr);
+    const int cap = (c->flags_h[1] + 32 + 7) & ~7;
+    (void)hipFree(c->nbr);
     c->nbr = nullptr;
     if (hipMalloc(&c->nbr, sizeof(int) * (size_t)cap * c->n) != hipSuccess) {
       c->nbr = nullptr;
       c->nbr_cap = 0;
-      c->have_pos = false;
       return PSE_ERR_OOM;
     }
     c->nbr_cap = cap;
-    hipMemsetAsync(c->flags, 0, sizeof(int) * 4, c->stream);
-    launch_nbr<T>(c);
-    hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 4, hipMemcpyDeviceToHost, c->stream);
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+    if (hipMemsetAsync(c->flags, 0, sizeof(int) * 4, c->stream) != hipSuccess) return PSE_ERR_HIP;
+    st = build_neighbors<T>(c);
+    if (st != PSE_OK) return st;
+  }
+  {
+    int64_t pairs;
+    std::memcpy(&pairs, c->flags_h + 2, sizeof pairs);
+    c->pairs = pairs;
   }
   c->have_pos = true;
   return hip_status(hipGetLastError());
@@ -302,6 +353,24 @@ pse_status wave_apply_impl(pse_ctx *c, const void *F, void *u, bool with_real) {
 
 }  // namespace
 
+namespace pse {
+void prof_begin(pse_ctx *c, int stage) {
+  if (!(c->prof_mask & (1u << stage)) || c->ev_open >= 0) return;
+  hipEvent_t e = next_event(c);
+  if (!e) return;
+  (void)hipEventRecord(e, c->stream);
+  c->ev_open = (int)c->ev_used - 1;
+  c->ev_stage.push_back(stage);
+}
+void prof_end(pse_ctx *c, int stage) {
+  if (!(c->prof_mask & (1u << stage)) || c->ev_open < 0 || c->ev_stage.back() != stage) return;
+  hipEvent_t e = next_event(c);
+  if (!e) return;
+  (void)hipEventRecord(e, c->stream);
+  c->ev_open = -1;
+}
+}  // namespace pse
+
 extern "C" {
 
 const char *pse_status_string(pse_status s) {
@@ -346,14 +415,16 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   c->nbr_cap = nbr_capacity(c);
   c->nbr = (int *)al.dev(sizeof(int) * (size_t)c->nbr_cap * n);
   c->nbr_cnt = (int *)al.dev(sizeof(int) * n);
-  c->flags = (int *)al.dev(sizeof(int) * 4);
-  c->flags_h = (int *)al.host(sizeof(int) * 4);
-  for (auto &v : c->vbuf) v = al.dev(3 * T * n);
-  c->V = al.dev(3 * T * n * (size_t)(kMaxIter + 1));
+  c->flags = (int *)al.dev(sizeof(int) * 8);
+  c->flags_h = (int *)al.host(sizeof(int) * 8);
+  for (auto &v : c->vbuf) v = al.dev(4 * T * n);
+  c->V = al.dev(4 * T * n * (size_t)(kMaxIter + 1));
   const size_t lzbytes = c->acc_dbl ? sizeof(LzState<double>) : sizeof(LzState<float>);
   c->lz = al.dev(lzbytes);
   c->lz_h = al.host(lzbytes);
-  const size_t nparts = std::max<size_t>(kRedBlock, (n + 255) / 256);
+  // partial sums: one per block of the widest reduction (256-particle
+  // blocks, or one per LDS target block of edge 1 cell)
+  const size_t nparts = std::max<size_t>(std::max<size_t>(kRedBlock, (n + 255) / 256), (size_t)c->ncell);
   c->partials = al.dev(A * nparts);
   c->counter = (unsigned *)al.dev(sizeof(unsigned));
   const size_t M3 = (size_t)p->grid * p->grid * p->grid;
@@ -391,7 +462,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
 }
 
 pse_status pse_destroy(pse_ctx *ctx) {
-  if (ctx) hipStreamSynchronize(ctx->stream);
+  if (ctx) (void)hipStreamSynchronize(ctx->stream);
   free_ctx(ctx);
   return PSE_OK;
 }
@@ -451,6 +522,32 @@ pse_status pse_wave_apply(pse_ctx *c, const void *F, void *u) {
   if (!c || !F || !u) return PSE_ERR_INVALID_ARG;
   if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
   DISPATCH(c, (wave_apply_impl<T, A>(c, F, u, false)));
+}
+
+pse_status pse_profile(pse_ctx *c, uint32_t mask) {
+  if (!c) return PSE_ERR_INVALID_ARG;
+  c->prof_mask = mask & ((1u << PSE_NSTAGES) - 1);
+  return PSE_OK;
+}
+
+pse_status pse_profile_read(pse_ctx *c, double *ms, int32_t *launches) {
+  if (!c || !ms || !launches) return PSE_ERR_INVALID_ARG;
+  for (int i = 0; i < PSE_NSTAGES; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+  const size_t npairs = c->ev_stage.size();
+  for (size_t i = 0; i < npairs && 2 * i + 1 < c->ev_used; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]) != hipSuccess) return PSE_ERR_HIP;
+    ms[c->ev_stage[i]] += t;
+    launches[c->ev_stage[i]] += 1;
+  }
+  c->ev_used = 0;
+  c->ev_stage.clear();
+  c->ev_open = -1;
+  return PSE_OK;
 }
 
 pse_status pse_mobility_apply(pse_ctx *c, const void *F, void *u) {

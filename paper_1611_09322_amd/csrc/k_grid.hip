@@ -7,6 +7,8 @@
 // Grid layout (per component c, planar): real u[c][ix][iy][iz], z fastest.
 // Spectrum in place of it: S[c][jx][jy][jz], jz < M/2 (the Nyquist plane
 // jz = M/2 is never used: Nyquist modes are outside the k-set).
+#include <type_traits>
+
 #include "launch.hpp"
 
 namespace pse {
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, 
 // = normalised Gaussian of standard deviation sigma (separable).
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__restrict__ pos,
-                                                const T *__restrict__ f, int n, T *__restrict__ grid, int M, T h,
+                                                const typename vec4<T>::type *__restrict__ f, int n, T *__restrict__ grid, int M, T h,
                                                 T invh, T inv2s2, T norm) {
   const int s = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -395,7 +397,8 @@ __global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__
   const auto p = pos[s];
   const int bx = min((int)(p.x * invh), M - 1), by = min((int)(p.y * invh), M - 1), bz = min((int)(p.z * invh), M - 1);
   const int gx0 = bx - P / 2 + 1, gy0 = by - P / 2 + 1, gz0 = bz - P / 2 + 1;
-  const T fx = f[3 * s], fy = f[3 * s + 1], fz = f[3 * s + 2];
+  const auto fv = f[s];
+  const T fx = fv.x, fy = fv.y, fz = fv.z;
   const size_t M3 = (size_t)M * M * M;
   T wz[P];
   int iz_m[P];
@@ -423,9 +426,12 @@ __global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__
   }
 }
 
+// Interpolation: one wavefront per particle; lane -> (iz, ix) of the support
+// (consecutive lanes read consecutive z nodes of one grid row), loop over iy.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__restrict__ pos,
-                                                const T *__restrict__ grid, int n, T *__restrict__ out, int M, T h,
+                                                const T *__restrict__ grid, int n,
+                                                typename vec4<T>::type *__restrict__ out, int M, T h,
                                                 T invh, T inv2s2, T norm_h3) {
   const int s = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -434,26 +440,27 @@ __global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__
   const int bx = min((int)(p.x * invh), M - 1), by = min((int)(p.y * invh), M - 1), bz = min((int)(p.z * invh), M - 1);
   const int gx0 = bx - P / 2 + 1, gy0 = by - P / 2 + 1, gz0 = bz - P / 2 + 1;
   const size_t M3 = (size_t)M * M * M;
-  T wz[P];
-  int iz_m[P];
+  T wy[P];
+  int ym[P];
 #pragma unroll
-  for (int iz = 0; iz < P; ++iz) {
-    const int gz = gz0 + iz;
-    const T dz = (T)gz * h - p.z;
-    wz[iz] = exp(-dz * dz * inv2s2);
-    iz_m[iz] = (gz + M) % M;
+  for (int iy = 0; iy < P; ++iy) {
+    const int gy = gy0 + iy;
+    const T dy = (T)gy * h - p.y;
+    wy[iy] = exp(-dy * dy * inv2s2);
+    ym[iy] = (gy + M) % M;
   }
   T ax = 0, ay = 0, az = 0;
   for (int pr = lane; pr < P * P; pr += 64) {
-    const int ix = pr / P, iy = pr % P;
-    const int gx = gx0 + ix, gy = gy0 + iy;
-    const T dx = (T)gx * h - p.x, dy = (T)gy * h - p.y;
-    const T wxy = exp(-(dx * dx + dy * dy) * inv2s2);
-    const size_t row = ((size_t)((gx + M) % M) * M + (size_t)((gy + M) % M)) * M;
+    const int iz = pr % P, ix = pr / P;
+    const int gx = gx0 + ix, gz = gz0 + iz;
+    const T dx = (T)gx * h - p.x, dz = (T)gz * h - p.z;
+    const T wxz = exp(-(dx * dx + dz * dz) * inv2s2);
+    const size_t xrow = (size_t)((gx + M) % M) * M;
+    const int zm = (gz + M) % M;
 #pragma unroll
-    for (int iz = 0; iz < P; ++iz) {
-      const T w = wxy * wz[iz];
-      const size_t g = row + iz_m[iz];
+    for (int iy = 0; iy < P; ++iy) {
+      const T w = wxz * wy[iy];
+      const size_t g = (xrow + ym[iy]) * M + zm;
       ax += w * grid[g];
       ay += w * grid[M3 + g];
       az += w * grid[2 * M3 + g];
@@ -466,10 +473,155 @@ __global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__
     az += __shfl_xor(az, off, 64);
   }
   if (lane == 0) {
-    out[3 * s] = norm_h3 * ax;
-    out[3 * s + 1] = norm_h3 * ay;
-    out[3 * s + 2] = norm_h3 * az;
+    typename vec4<T>::type o;
+    o.x = norm_h3 * ax;
+    o.y = norm_h3 * ay;
+    o.z = norm_h3 * az;
+    o.w = T(0);
+    out[s] = o;
   }
+}
+
+// Spreading, owner computes, no atomics: one workgroup owns a tile of
+// 8 x 8 x (8 NW) grid nodes; wavefront w owns the 8 x 8 x 8 sub-tile of z
+// nodes [8w, 8w + 8), lane (lx, ly) one column of it, and accumulates its
+// 8 nodes x 3 components in registers.  Particles whose P^3 support overlaps
+// the tile are found from the linked cells covering the tile plus the
+// support reach, one (x, y) cell column at a time (one candidate per thread,
+// hits compacted into an LDS list).  For each listed particle the wavefront
+// evaluates the 3P separable Gaussian weights with one exp per lane and
+// reads them across lanes.  Every node is written once, deterministically
+// (fixed particle order), with no grid clear.  Needs M >= 2 max(8, 8 NW) + P
+// so that the nearest periodic image of a base node relative to the tile is
+// unique.
+template <typename T, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>::type *__restrict__ pos,
+                                                         const typename vec4<T>::type *__restrict__ f,
+                                                         const int *__restrict__ cell_start, int nc, T cs, int M,
+                                                         T h, T invh, T inv2s2, T norm, T *__restrict__ grid) {
+  constexpr int TX = 8, TY = 8, TZ = 8 * NW;
+  constexpr int NT = 64 * NW;
+  static_assert(3 * P <= 64, "weights of one particle must fit one wavefront");
+  __shared__ int ls0[3][NT];
+  __shared__ T lpu[3][NT];
+  __shared__ T lf[3][NT];
+  __shared__ int nlist;
+  if (threadIdx.x == 0) nlist = 0;
+  __syncthreads();
+  const int t0x = blockIdx.z * TX, t0y = blockIdx.y * TY, t0z = blockIdx.x * TZ;
+  const int t0[3] = {t0x, t0y, t0z}, tt[3] = {TX, TY, TZ};
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lx = lane >> 3, ly = lane & 7;
+  const int zw = wave * 8;  // first z node (tile-local) of this wavefront
+  const int half = M / 2;
+  T acc[3][8];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[c][q] = T(0);
+  // cell ranges holding every base node b in [t0 - P/2, t0 + T - 2 + P/2]
+  int cl[3], cn[3];
+  {
+    const T inv_cs = T(1) / cs;
+    for (int d = 0; d < 3; ++d) {
+      const T lo = (T)(t0[d] - P / 2) * h, hi = (T)(t0[d] + tt[d] - 1 + P / 2) * h;
+      const int a = (int)floor(lo * inv_cs - T(1e-4)), b = (int)floor(hi * inv_cs + T(1e-4));
+      if (b - a + 1 >= nc) {
+        cl[d] = 0;
+        cn[d] = nc;
+      } else {
+        cl[d] = ((a % nc) + nc) % nc;
+        cn[d] = b - a + 1;
+      }
+    }
+  }
+  for (int kx = 0; kx < cn[0]; ++kx) {
+    const int cx = (cl[0] + kx) % nc;
+    for (int ky = 0; ky < cn[1]; ++ky) {
+      const int cy = (cl[1] + ky) % nc;
+      const int base = (cx * nc + cy) * nc;
+      // z cells cl[2] .. cl[2]+cn[2]-1 (mod nc): one or two contiguous runs
+      const int z1 = cl[2] + cn[2] - 1;
+      const int a1 = cell_start[base + cl[2]];
+      const int b1 = cell_start[base + (z1 >= nc ? nc - 1 : z1) + 1];
+      const int a2 = cell_start[base];
+      const int b2 = z1 >= nc ? cell_start[base + (z1 - nc) + 1] : a2;
+      const int n1 = b1 - a1, ntot = n1 + (b2 - a2);
+      for (int c0 = 0; c0 < ntot; c0 += NT) {
+        const int ci = c0 + (int)threadIdx.x;
+        if (ci < ntot) {
+          const int t = ci < n1 ? a1 + ci : a2 + (ci - n1);
+          const auto q = pos[t];
+          const T qc[3] = {q.x, q.y, q.z};
+          int s0[3];
+          T pu[3];
+          bool hit = true;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const int b = min((int)(qc[d] * invh), M - 1);
+            const int dd = ((b - t0[d] + half + M) % M) - half;  // nearest image, in [-M/2, M/2)
+            s0[d] = dd - P / 2 + 1;                              // first support node, tile-local
+            pu[d] = qc[d] + (T)(t0[d] + dd - b) * h;             // coordinate of that image
+            hit = hit && (s0[d] <= tt[d] - 1) && (s0[d] + P - 1 >= 0);
+          }
+          if (hit) {
+            const int e = atomicAdd(&nlist, 1);
+            const auto fv = f[t];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              ls0[d][e] = s0[d];
+              lpu[d][e] = pu[d];
+            }
+            lf[0][e] = fv.x;
+            lf[1][e] = fv.y;
+            lf[2][e] = fv.z;
+          }
+        }
+        __syncthreads();
+        const int nl = nlist;
+        for (int e = 0; e < nl; ++e) {
+          const int sz = ls0[2][e];
+          if (sz > zw + 7 || sz + P - 1 < zw) continue;  // support misses this wavefront's z slab
+          const int sx = ls0[0][e], sy = ls0[1][e];
+          // lanes 0..3P-1: the separable weights along x, y, z
+          T wv = T(0);
+          if (lane < 3 * P) {
+            const int d = lane / P, j = lane % P;
+            const int s0d = d == 0 ? sx : (d == 1 ? sy : sz);
+            const T dd = (T)(t0[d] + s0d + j) * h - lpu[d][e];
+            wv = exp(-dd * dd * inv2s2);
+          }
+          const int ix = lx - sx, iy = ly - sy;
+          const bool in = ix >= 0 && ix < P && iy >= 0 && iy < P;
+          const T wxy = norm * __shfl(wv, in ? ix : 0, 64) * __shfl(wv, in ? P + iy : 0, 64);
+          const T fx = lf[0][e], fy = lf[1][e], fz = lf[2][e];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int iz = zw + q - sz;  // uniform across the wavefront
+            if (iz >= 0 && iz < P) {
+              // cross-lane read first, by every lane: a shuffle under a lane
+              // condition would read inactive source lanes
+              const T wzq = __shfl(wv, 2 * P + iz, 64);
+              const T w = in ? wxy * wzq : T(0);
+              acc[0][q] += w * fx;
+              acc[1][q] += w * fy;
+              acc[2][q] += w * fz;
+            }
+          }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) nlist = 0;
+        __syncthreads();
+      }
+    }
+  }
+  const size_t M3 = (size_t)M * M * M;
+  const size_t col = ((size_t)(t0x + lx) * M + (t0y + ly)) * M + t0z + zw;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) grid[c * M3 + col + q] = acc[c][q];
 }
 
 // ----------------------------------------------------------- launchers
@@ -487,6 +639,7 @@ static void fft_z(pse_ctx *c, const void *src, void *dst, int dir) {
   constexpr int NL = GridCfg<T, M>::NL;
   const int nlines = 3 * M * M;
   const dim3 g(nlines / NL);
+  ProfScope ps(c, PSE_STAGE_FFT);
   if (dir < 0)
     k_fft_z<T, M, -1, NL, 256><<<g, 256, 0, c->stream>>>((const CT *)src, (CT *)dst, (const CT *)c->tw_H,
                                                          (const CT *)c->tw_M);
@@ -504,6 +657,7 @@ static void fft_strided(pse_ctx *c, void *data, int axis, int dir) {
   const size_t s_fft = axis == 0 ? (size_t)M * H : (size_t)H;
   const size_t s_outer = axis == 0 ? (size_t)H : (size_t)M * H;
   const dim3 g(H / TZ, M, 3);
+  ProfScope ps(c, PSE_STAGE_FFT);
   if (dir < 0)
     k_fft_strided<T, M, -1, TZ, 256><<<g, 256, 0, c->stream>>>((CT *)data, s_fft, s_outer, s_comp, (const CT *)c->tw_M);
   else
@@ -519,6 +673,7 @@ static void xpass(pse_ctx *c, void *data, const void *specW, const WaveCoef &wc,
   auto *d = (CT *)data;
   auto *w = (const CT *)specW;
   auto *tw = (const CT *)c->tw_M;
+  ProfScope ps(c, PSE_STAGE_XFUSED);
   if (forces) {
     if (noise == 1) k_xpass_fused<T, M, TZ, 256, true, 1><<<g, 256, 0, c->stream>>>(d, w, wc, tw);
     else if (noise == 2) k_xpass_fused<T, M, TZ, 256, true, 2><<<g, 256, 0, c->stream>>>(d, w, wc, tw);
@@ -552,6 +707,15 @@ void launch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoe
   }
 }
 
+// Tiled spreading needs M >= 2 max(TX, TY, TZ) + P (unique nearest image);
+// the tile edge along z is min(64, M/4) and 8 along x and y.
+static bool spread_tiled(int M, int P) {
+  const int tz = M >= 256 ? 64 : (M >= 128 ? 32 : (M >= 64 ? 16 : 8));
+  const int tmax = tz > 8 ? tz : 8;
+  return M >= 32 && M >= 2 * tmax + P;
+}
+bool spread_writes_whole_grid(int M, int P) { return spread_tiled(M, P); }
+
 template <typename T, int P>
 static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid_or_out) {
   using T4 = typename vec4<T>::type;
@@ -559,11 +723,27 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
   const double h = c->d.h, s2 = c->d.sigma * c->d.sigma;
   const double norm = std::pow(2.0 * 3.14159265358979323846 * s2, -1.5);
   const int blocks = (int)(((long)n * 64 + 255) / 256);
-  if (spread)
-    k_spread<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T *)vec, n, (T *)grid_or_out, M, (T)h,
-                                                  (T)(1.0 / h), (T)(0.5 / s2), (T)norm);
-  else
-    k_interp<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T *)vec, n, (T *)grid_or_out, M,
+  ProfScope ps(c, spread ? PSE_STAGE_SPREAD : PSE_STAGE_INTERP);
+  if (spread) {
+    if (spread_tiled(M, P)) {
+      auto go = [&](auto nw) {
+        constexpr int NW = decltype(nw)::value;
+        const dim3 g(M / (8 * NW), M / 8, M / 8);
+        k_spread_tile<T, P, NW><<<g, 64 * NW, 0, c->stream>>>(
+            (const T4 *)c->pos_s, (const T4 *)vec, c->cell_start, c->d.nc, (T)c->d.cs, M, (T)h, (T)(1.0 / h),
+            (T)(0.5 / s2), (T)norm, (T *)grid_or_out);
+      };
+      if (M >= 256) go(std::integral_constant<int, 8>{});
+      else if (M >= 128) go(std::integral_constant<int, 4>{});
+      else if (M >= 64) go(std::integral_constant<int, 2>{});
+      else go(std::integral_constant<int, 1>{});
+    } else {
+      (void)hipMemsetAsync(grid_or_out, 0, sizeof(T) * 3 * (size_t)M * M * M, c->stream);
+      k_spread<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T4 *)vec, n, (T *)grid_or_out, M,
+                                                    (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)norm);
+    }
+  } else
+    k_interp<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T *)vec, n, (T4 *)grid_or_out, M,
                                                   (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)(norm * h * h * h));
 }
 

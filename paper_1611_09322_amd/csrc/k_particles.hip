@@ -124,13 +124,13 @@ __global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, cons
                             int nc, T L, T invL, T inv_cs, T rc2, int *__restrict__ nbr, int *__restrict__ cnt_out,
                             int cap, int *__restrict__ flags) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+  int cnt = 0;
+  if (s < n) {
   const auto p = pos[s];
   const int cx = min((int)(p.x * inv_cs), nc - 1);
   const int cy = min((int)(p.y * inv_cs), nc - 1);
   const int cz = min((int)(p.z * inv_cs), nc - 1);
   const int lo = nc >= 3 ? -1 : 0, hi = nc >= 2 ? 1 : 0;
-  int cnt = 0;
   for (int dx = lo; dx <= hi; ++dx) {
     const int ax = (cx + dx + nc) % nc;
     for (int dy = lo; dy <= hi; ++dy) {
@@ -155,6 +155,10 @@ __global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, cons
   }
   cnt_out[s] = cnt;
   atomicMax(&flags[1], cnt);
+  }
+  // total ordered pairs: one 64-bit atomic per wavefront
+  const unsigned long long tot = wave_sum((unsigned long long)cnt);
+  if ((threadIdx.x & 63) == 0 && tot) atomicAdd((unsigned long long *)(flags + 2), tot);
 }
 
 // ------------------------------------------------------- F, G evaluation
@@ -243,23 +247,27 @@ struct FGExact {
 template <typename T, typename A, typename FG, bool LZ>
 __device__ __forceinline__ void spmv_body(const typename vec4<T>::type *__restrict__ pos, const int *__restrict__ nbr,
                                           const int *__restrict__ cnt, int n, T L, T invL, const FG &fg, T self_r,
-                                          const T *__restrict__ src, T scale, T *__restrict__ out,
-                                          T *__restrict__ vm_out, A &dot) {
+                                          const typename vec4<T>::type *__restrict__ src, T scale,
+                                          typename vec4<T>::type *__restrict__ out,
+                                          typename vec4<T>::type *__restrict__ vm_out, A &dot) {
+  using T4 = typename vec4<T>::type;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   dot = A(0);
   if (s >= n) return;
-  const auto p = pos[s];
-  const T vx = src[3 * s], vy = src[3 * s + 1], vz = src[3 * s + 2];
-  T ax = self_r * vx, ay = self_r * vy, az = self_r * vz;
+  const T4 p = pos[s];
+  const T4 v = src[s];
+  T ax = self_r * v.x, ay = self_r * v.y, az = self_r * v.z;
   const int c = cnt[s];
+  const int *nb = nbr + s;
+#pragma unroll 4
   for (int k = 0; k < c; ++k) {
-    const int t = nbr[(size_t)k * n + s];
-    const auto q = pos[t];
+    const int t = nb[(size_t)k * n];
+    const T4 q = pos[t];
+    const T4 w = src[t];
     const T dx = min_image(p.x - q.x, L, invL);
     const T dy = min_image(p.y - q.y, L, invL);
     const T dz = min_image(p.z - q.z, L, invL);
     const T r2 = dx * dx + dy * dy + dz * dz;
-    const T wx = src[3 * t], wy = src[3 * t + 1], wz = src[3 * t + 2];
     T Fm, Dm, rinv;
     if (r2 > T(1e-24)) {
       rinv = T(1) / sqrt(r2);
@@ -269,23 +277,25 @@ __device__ __forceinline__ void spmv_body(const typename vec4<T>::type *__restri
       Dm = T(0);
       rinv = T(0);
     }
-    const T pr = Dm * rinv * rinv * (dx * wx + dy * wy + dz * wz);
-    ax += Fm * wx + pr * dx;
-    ay += Fm * wy + pr * dy;
-    az += Fm * wz + pr * dz;
+    const T pr = Dm * rinv * rinv * (dx * w.x + dy * w.y + dz * w.z);
+    ax += Fm * w.x + pr * dx;
+    ay += Fm * w.y + pr * dy;
+    az += Fm * w.z + pr * dz;
   }
-  ax *= scale;
-  ay *= scale;
-  az *= scale;
-  out[3 * s] = ax;
-  out[3 * s + 1] = ay;
-  out[3 * s + 2] = az;
+  T4 o;
+  o.x = ax * scale;
+  o.y = ay * scale;
+  o.z = az * scale;
+  o.w = T(0);
+  out[s] = o;
   if (LZ) {
-    const T ux = vx * scale, uy = vy * scale, uz = vz * scale;
-    vm_out[3 * s] = ux;
-    vm_out[3 * s + 1] = uy;
-    vm_out[3 * s + 2] = uz;
-    dot = (A)ux * (A)ax + (A)uy * (A)ay + (A)uz * (A)az;
+    T4 u;
+    u.x = v.x * scale;
+    u.y = v.y * scale;
+    u.z = v.z * scale;
+    u.w = T(0);
+    vm_out[s] = u;
+    dot = (A)u.x * (A)o.x + (A)u.y * (A)o.y + (A)u.z * (A)o.z;
   }
 }
 
@@ -293,8 +303,8 @@ template <typename T, typename A, bool LZ>
 __global__ __launch_bounds__(256) void k_spmv_table(const float4 *__restrict__ pos, const int *__restrict__ nbr,
                                                     const int *__restrict__ cnt, int n, float L, float invL,
                                                     const float4 *__restrict__ tab_g, float inv_dr, float self_r,
-                                                    const float *__restrict__ src, float scale, float *__restrict__ out,
-                                                    float *__restrict__ vm_out, LzState<A> *st, A *partials,
+                                                    const float4 *__restrict__ src, float scale, float4 *__restrict__ out,
+                                                    float4 *__restrict__ vm_out, LzState<A> *st, A *partials,
                                                     unsigned *counter) {
   __shared__ float4 tab[kTableK + 1];
   __shared__ A sh[16];
@@ -333,8 +343,8 @@ template <bool LZ>
 __global__ __launch_bounds__(256) void k_spmv_exact(const double4 *__restrict__ pos, const int *__restrict__ nbr,
                                                     const int *__restrict__ cnt, int n, double L, double invL,
                                                     const double *__restrict__ ser, double xi, double a, double mu0,
-                                                    double small_r2, double self_r, const double *__restrict__ src,
-                                                    double scale, double *__restrict__ out, double *__restrict__ vm_out,
+                                                    double small_r2, double self_r, const double4 *__restrict__ src,
+                                                    double scale, double4 *__restrict__ out, double4 *__restrict__ vm_out,
                                                     LzState<double> *st, double *partials, unsigned *counter) {
   __shared__ double sh[16];
   __shared__ int last;
@@ -357,6 +367,277 @@ __global__ __launch_bounds__(256) void k_spmv_exact(const double4 *__restrict__ 
   if (last) {
     __threadfence();
     double v = 0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) v += partials[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+      st->alpha[st->m] = v;
+      *counter = 0u;
+    }
+  }
+}
+
+// ------------------------------------------- LDS-staged near-field kernels
+// Target blocks of B x B x B linked cells.  The block's halo, the (B+2)^3
+// cells within one cell of its own, is staged in LDS once; the neighbour
+// list then holds 16-bit LDS indices, so the product reads neighbours from
+// LDS instead of gathering 16-byte records from global memory per pair.
+// List layout: chunks of 8 indices, chunk q of sorted particle s at 16-byte
+// slot (q * n + s): one coalesced 16-byte load per lane per 8 neighbours.
+// Needs nc >= B + 2 (no halo cell appears twice).
+template <int B> struct Halo {
+  static constexpr int HB = B + 2;
+  static constexpr int NH = HB * HB * HB;  // 27 or 64 (one wavefront scans it)
+};
+
+struct HaloTab {
+  int start[64];  // global sorted index of each halo cell's first particle
+  int base[65];   // exclusive prefix of the halo cell counts (LDS offsets)
+  int tcell[8];   // halo index of each target cell
+  int tpre[9];    // exclusive prefix of the target cell counts
+  int ntc;        // number of target cells (< B^3 at the partial last block)
+};
+
+template <int B>
+__device__ __forceinline__ void halo_setup(const int *__restrict__ cell_start, int nc, HaloTab &ht) {
+  constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
+  const int nb = (nc + B - 1) / B;
+  const int blk = blockIdx.x;
+  const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
+  if (threadIdx.x < 64) {
+    const int h = threadIdx.x;
+    int cnt = 0;
+    if (h < NH) {
+      const int hx = h / (HB * HB), hy = (h / HB) % HB, hz = h % HB;
+      const int gx = (bx * B - 1 + hx + nc) % nc, gy = (by * B - 1 + hy + nc) % nc, gz = (bz * B - 1 + hz + nc) % nc;
+      const int c = (gx * nc + gy) * nc + gz;
+      const int a = cell_start[c];
+      cnt = cell_start[c + 1] - a;
+      ht.start[h] = a;
+    }
+    int v = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(v, off, 64);
+      if (h >= off) v += u;
+    }
+    if (h < NH) ht.base[h + 1] = v;
+    if (h == 0) ht.base[0] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int k = 0, acc = 0;
+    for (int ox = 0; ox < B; ++ox)
+      for (int oy = 0; oy < B; ++oy)
+        for (int oz = 0; oz < B; ++oz) {
+          if (bx * B + ox >= nc || by * B + oy >= nc || bz * B + oz >= nc) continue;
+          const int h = ((ox + 1) * HB + (oy + 1)) * HB + (oz + 1);
+          ht.tcell[k] = h;
+          ht.tpre[k] = acc;
+          acc += ht.base[h + 1] - ht.base[h];
+          ++k;
+        }
+    ht.tpre[k] = acc;
+    ht.ntc = k;
+  }
+  __syncthreads();
+}
+
+// LDS index e -> halo cell (largest h with base[h] <= e).
+template <int NH> __device__ __forceinline__ int halo_cell_of(const HaloTab &ht, int e) {
+  int lo = 0, hi = NH;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ht.base[mid] <= e) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int NH>
+__device__ __forceinline__ void halo_stage(const float4 *__restrict__ g, float4 *l, const HaloTab &ht) {
+  const int total = ht.base[NH];
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int h = halo_cell_of<NH>(ht, e);
+    l[e] = g[ht.start[h] + (e - ht.base[h])];
+  }
+}
+
+// target i of the block -> (halo cell index, LDS index, global sorted index)
+__device__ __forceinline__ void target_of(const HaloTab &ht, int i, int &h, int &li, int &s) {
+  int j = 0;
+  while (j + 1 < ht.ntc && ht.tpre[j + 1] <= i) ++j;
+  h = ht.tcell[j];
+  const int off = i - ht.tpre[j];
+  li = ht.base[h] + off;
+  s = ht.start[h] + off;
+}
+
+// Per-block halo sizes (largest goes to flags[4]) for sizing the LDS.
+template <int B>
+__global__ void k_halo_size(const int *__restrict__ cell_start, int nc, int *__restrict__ flags) {
+  constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
+  const int nb = (nc + B - 1) / B;
+  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= nb * nb * nb) return;
+  const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
+  int tot = 0;
+  for (int h = 0; h < NH; ++h) {
+    const int hx = h / (HB * HB), hy = (h / HB) % HB, hz = h % HB;
+    const int gx = (bx * B - 1 + hx + nc) % nc, gy = (by * B - 1 + hy + nc) % nc, gz = (bz * B - 1 + hz + nc) % nc;
+    const int c = (gx * nc + gy) * nc + gz;
+    tot += cell_start[c + 1] - cell_start[c];
+  }
+  atomicMax(&flags[4], tot);
+}
+
+template <int B>
+__global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
+                                                 int nc, int n, float L, float invL, float rc2,
+                                                 uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
+                                                 int *__restrict__ flags) {
+  constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
+  extern __shared__ float4 hpos[];
+  __shared__ HaloTab ht;
+  halo_setup<B>(cell_start, nc, ht);
+  halo_stage<NH>(pos, hpos, ht);
+  __syncthreads();
+  const int ntarg = ht.tpre[ht.ntc];
+  unsigned long long mine = 0;
+  int mx = 0;
+  for (int i = threadIdx.x; i < ntarg; i += blockDim.x) {
+    int h, li, s;
+    target_of(ht, i, h, li, s);
+    const int ox = h / (HB * HB) - 1, oy = (h / HB) % HB - 1, oz = h % HB - 1;
+    const float4 p = hpos[li];
+    int k = 0;
+    uint64_t lo = 0, hi = 0;  // the current chunk of 8 packed 16-bit indices
+    uint4 *row = (uint4 *)nbr;
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          const int hh = ((ox + 1 + dx) * HB + (oy + 1 + dy)) * HB + (oz + 1 + dz);
+          const int e = ht.base[hh + 1];
+          for (int j = ht.base[hh]; j < e; ++j) {
+            if (j == li) continue;
+            const float4 q = hpos[j];
+            const float ddx = min_image(p.x - q.x, L, invL);
+            const float ddy = min_image(p.y - q.y, L, invL);
+            const float ddz = min_image(p.z - q.z, L, invL);
+            if (ddx * ddx + ddy * ddy + ddz * ddz <= rc2) {
+              const int slot = k & 7;
+              const uint64_t v = (uint64_t)j << (16 * (slot & 3));
+              if (slot < 4) lo |= v;
+              else hi |= v;
+              if (slot == 7) {
+                if ((k >> 3) < (cap >> 3))
+                  row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
+                                                             (uint32_t)(hi >> 32));
+                lo = hi = 0;
+              }
+              ++k;
+            }
+          }
+        }
+    if ((k & 7) && (k >> 3) < (cap >> 3))
+      row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+    cnt_out[s] = k;
+    mine += (unsigned long long)k;
+    mx = max(mx, k);
+  }
+  const unsigned long long tot = wave_sum(mine);
+  int wmx = mx;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) wmx = max(wmx, __shfl_xor(wmx, off, 64));
+  if ((threadIdx.x & 63) == 0) {
+    if (tot) atomicAdd((unsigned long long *)(flags + 2), tot);
+    atomicMax(&flags[1], wmx);
+  }
+}
+
+template <int B, typename A, bool LZ>
+__global__ __launch_bounds__(512) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
+                                                  const int *__restrict__ cell_start, int nc, int n, int hcap,
+                                                  float L, float invL, const uint16_t *__restrict__ nbr,
+                                                  const int *__restrict__ cnt, const float4 *__restrict__ tab,
+                                                  float inv_dr, float self_r, float scale, float4 *__restrict__ out,
+                                                  float4 *__restrict__ vm_out, LzState<A> *st, A *partials,
+                                                  unsigned *counter) {
+  constexpr int NH = Halo<B>::NH;
+  extern __shared__ float4 smem[];
+  float4 *hpos = smem, *hsrc = smem + hcap;
+  __shared__ HaloTab ht;
+  __shared__ A sh[16];
+  __shared__ int last;
+  if (LZ) {
+    if (st->done) return;
+    scale = (float)st->inv_beta;
+  }
+  halo_setup<B>(cell_start, nc, ht);
+  halo_stage<NH>(pos, hpos, ht);
+  halo_stage<NH>(src, hsrc, ht);
+  __syncthreads();
+  const int ntarg = ht.tpre[ht.ntc];
+  A dot = 0;
+  for (int i = threadIdx.x; i < ntarg; i += blockDim.x) {
+    int h, li, s;
+    target_of(ht, i, h, li, s);
+    const float4 p = hpos[li];
+    const float4 v = hsrc[li];
+    float ax = self_r * v.x, ay = self_r * v.y, az = self_r * v.z;
+    const int c = cnt[s];
+    const uint4 *row = (const uint4 *)nbr + s;
+    for (int kb = 0; kb < c; kb += 8) {
+      const uint4 pk = row[(size_t)(kb >> 3) * n];
+      const uint32_t wd[4] = {pk.x, pk.y, pk.z, pk.w};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+      if (kb + u >= c) break;
+      const int j = (wd[u >> 1] >> (16 * (u & 1))) & 0xFFFF;
+      const float4 q = hpos[j];
+      const float4 w = hsrc[j];
+      const float dx = min_image(p.x - q.x, L, invL);
+      const float dy = min_image(p.y - q.y, L, invL);
+      const float dz = min_image(p.z - q.z, L, invL);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      float Fm, Dm, rinv;
+      if (r2 > 1e-24f) {
+        rinv = 1.0f / sqrtf(r2);
+        const float u = r2 * rinv * inv_dr;
+        const int kk = min((int)u, kTableK - 1);
+        const float f = u - (float)kk;
+        const float4 e = tab[kk];
+        Fm = fmaf(f, e.z, e.x);
+        Dm = fmaf(f, e.w, e.y);
+      } else {
+        Fm = self_r;
+        Dm = 0.0f;
+        rinv = 0.0f;
+      }
+      const float pr = Dm * rinv * rinv * (dx * w.x + dy * w.y + dz * w.z);
+      ax += Fm * w.x + pr * dx;
+      ay += Fm * w.y + pr * dy;
+      az += Fm * w.z + pr * dz;
+      }
+    }
+    out[s] = make_float4(ax * scale, ay * scale, az * scale, 0.0f);
+    if (LZ) {
+      const float4 u = make_float4(v.x * scale, v.y * scale, v.z * scale, 0.0f);
+      vm_out[s] = u;
+      dot += (A)u.x * (A)(ax * scale) + (A)u.y * (A)(ay * scale) + (A)u.z * (A)(az * scale);
+    }
+  }
+  if (!LZ) return;
+  const A bs = block_sum(dot, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = bs;
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    A v = 0;
     for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) v += partials[i];
     v = block_sum(v, sh);
     if (threadIdx.x == 0) {
@@ -548,31 +829,52 @@ __global__ void k_lz_combine(const T *__restrict__ V, size_t ld, int len, const 
 }
 
 // ------------------------------------------------------------- vectors
+// Caller-order n x 3 -> sorted (x, y, z, 0).
 template <typename T>
-__global__ void k_gather3(const T *__restrict__ in, const int *__restrict__ perm, T *__restrict__ out, int n) {
+__global__ void k_gather3(const T *__restrict__ in, const int *__restrict__ perm, typename vec4<T>::type *__restrict__ out,
+                          int n) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = perm[s];
-  out[3 * s] = in[3 * i];
-  out[3 * s + 1] = in[3 * i + 1];
-  out[3 * s + 2] = in[3 * i + 2];
+  typename vec4<T>::type v;
+  v.x = in[3 * i];
+  v.y = in[3 * i + 1];
+  v.z = in[3 * i + 2];
+  v.w = T(0);
+  out[s] = v;
 }
 
-// out[perm[s]] = cr * yr[s] + dt * ur[s] + wv[s]   (null terms omitted)
+// out[perm[s]] = cr * yr[s] + dt * ur[s] + wv[s]   (null terms omitted;
+// sorted inputs are (x, y, z, 0), the output is caller-order n x 3)
 template <typename T>
-__global__ void k_finalize(const int *__restrict__ perm, const T *__restrict__ yr, T cr, const T *__restrict__ ur, T dt,
-                           const T *__restrict__ wv, T *__restrict__ out, int n) {
+__global__ void k_finalize(const int *__restrict__ perm, const typename vec4<T>::type *__restrict__ yr, T cr,
+                           const typename vec4<T>::type *__restrict__ ur, T dt,
+                           const typename vec4<T>::type *__restrict__ wv, T *__restrict__ out, int n) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = perm[s];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    T v = T(0);
-    if (yr) v += cr * yr[3 * s + d];
-    if (ur) v += dt * ur[3 * s + d];
-    if (wv) v += wv[3 * s + d];
-    out[3 * i + d] = v;
+  T x = 0, y = 0, z = 0;
+  if (yr) {
+    const auto a = yr[s];
+    x += cr * a.x;
+    y += cr * a.y;
+    z += cr * a.z;
   }
+  if (ur) {
+    const auto a = ur[s];
+    x += dt * a.x;
+    y += dt * a.y;
+    z += dt * a.z;
+  }
+  if (wv) {
+    const auto a = wv[s];
+    x += a.x;
+    y += a.y;
+    z += a.z;
+  }
+  out[3 * i] = x;
+  out[3 * i + 1] = y;
+  out[3 * i + 2] = z;
 }
 
 // ------------------------------------------------ Philox noise for z1
@@ -638,8 +940,9 @@ void launch_bin(pse_ctx *c, const void *pos) {
   using T4 = typename vec4<T>::type;
   const int n = c->n;
   const T L = (T)c->d.L, invL = (T)(1.0 / c->d.L), inv_cs = (T)(1.0 / c->d.cs);
-  hipMemsetAsync(c->cell_count, 0, sizeof(int) * c->ncell, c->stream);
-  hipMemsetAsync(c->flags, 0, sizeof(int) * 4, c->stream);
+  ProfScope ps(c, PSE_STAGE_BIN);
+  (void)hipMemsetAsync(c->cell_count, 0, sizeof(int) * c->ncell, c->stream);
+  (void)hipMemsetAsync(c->flags, 0, sizeof(int) * 8, c->stream);
   k_wrap_bin<T><<<nblk(n, 256), 256, 0, c->stream>>>((const T *)pos, n, L, invL, inv_cs, c->d.nc, (T4 *)c->pos_w,
                                                      c->cell_of, c->cell_count, c->flags);
   k_scan_cells<<<1, 1024, 0, c->stream>>>(c->cell_count, c->cell_start, c->cell_count + c->ncell, c->ncell);
@@ -654,31 +957,95 @@ void launch_nbr(pse_ctx *c) {
   const int n = c->n;
   const T L = (T)c->d.L, invL = (T)(1.0 / c->d.L), inv_cs = (T)(1.0 / c->d.cs);
   const T rc2 = (T)(c->p.rcut * c->p.rcut);
+  ProfScope ps(c, PSE_STAGE_NBR);
   k_nbr_build<T><<<nblk(n, 128), 128, 0, c->stream>>>((const T4 *)c->pos_s, c->cell_start, n, c->d.nc, L, invL,
                                                        inv_cs, rc2, c->nbr, c->nbr_cnt, c->nbr_cap, c->flags);
+}
+
+static int lds_nblocks(int nc, int B) {
+  const int nb = (nc + B - 1) / B;
+  return nb * nb * nb;
+}
+
+void launch_halo_size(pse_ctx *c, int B) {
+  ProfScope ps(c, PSE_STAGE_NBR);
+  const int nblocks = lds_nblocks(c->d.nc, B);
+  if (B == 2) k_halo_size<2><<<nblk(nblocks, 256), 256, 0, c->stream>>>(c->cell_start, c->d.nc, c->flags);
+  else k_halo_size<1><<<nblk(nblocks, 256), 256, 0, c->stream>>>(c->cell_start, c->d.nc, c->flags);
+}
+
+template <typename K> static void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+void launch_nbr_lds(pse_ctx *c) {
+  ProfScope ps(c, PSE_STAGE_NBR);
+  const size_t smem = sizeof(float4) * (size_t)c->hcap;
+  const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L), rc2 = (float)(c->p.rcut * c->p.rcut);
+  auto *nb = (uint16_t *)c->nbr;
+  if (c->lds_B == 2) {
+    allow_lds(k_nbr_lds<2>, smem);
+    k_nbr_lds<2><<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, c->n, L,
+                                                         invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags);
+  } else {
+    allow_lds(k_nbr_lds<1>, smem);
+    k_nbr_lds<1><<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, c->n, L,
+                                                         invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags);
+  }
+}
+
+template <typename A, bool LZ>
+static void spmv_lds(pse_ctx *c, const float4 *src, float4 *out, float4 *vm_out, LzState<A> *st) {
+  const size_t smem = 2 * sizeof(float4) * (size_t)c->hcap;
+  const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L);
+  const auto *nb = (const uint16_t *)c->nbr;
+  const float inv_dr = (float)(kTableK / c->p.rcut), self_r = (float)c->d.self_r;
+  if (c->lds_B == 2) {
+    allow_lds(k_spmv_lds<2, A, LZ>, smem);
+    k_spmv_lds<2, A, LZ><<<c->lds_blocks, 512, smem, c->stream>>>(
+        (const float4 *)c->pos_s, src, c->cell_start, c->d.nc, c->n, c->hcap, L, invL, nb, c->nbr_cnt, c->table,
+        inv_dr, self_r, 1.0f, out, vm_out, st, (A *)c->partials, c->counter);
+  } else {
+    allow_lds(k_spmv_lds<1, A, LZ>, smem);
+    k_spmv_lds<1, A, LZ><<<c->lds_blocks, 512, smem, c->stream>>>(
+        (const float4 *)c->pos_s, src, c->cell_start, c->d.nc, c->n, c->hcap, L, invL, nb, c->nbr_cnt, c->table,
+        inv_dr, self_r, 1.0f, out, vm_out, st, (A *)c->partials, c->counter);
+  }
 }
 
 template <typename T, typename A>
 void launch_spmv(pse_ctx *c, const void *src, void *out, bool lz, void *vm_out) {
   const int n = c->n;
   const int nb = nblk(n, 256);
+  (void)lz;
+  (void)vm_out;
+  ProfScope ps(c, PSE_STAGE_SPMV);
+  if constexpr (sizeof(T) == 4) {
+    if (c->lds_B) {
+      spmv_lds<A, false>(c, (const float4 *)src, (float4 *)out, nullptr, nullptr);
+      return;
+    }
+  }
   if constexpr (sizeof(T) == 8) {
     k_spmv_exact<false><<<nb, 256, 0, c->stream>>>(
         (const double4 *)c->pos_s, c->nbr, c->nbr_cnt, n, c->d.L, 1.0 / c->d.L, c->series, c->p.xi, c->p.a, c->d.mu0,
-        c->small_r2, c->d.self_r, (const double *)src, 1.0, (double *)out, nullptr, nullptr, nullptr, nullptr);
-    (void)lz; (void)vm_out;
+        c->small_r2, c->d.self_r, (const double4 *)src, 1.0, (double4 *)out, nullptr, nullptr, nullptr, nullptr);
   } else {
-    (void)lz; (void)vm_out;
     k_spmv_table<float, A, false><<<nb, 256, 0, c->stream>>>(
         (const float4 *)c->pos_s, c->nbr, c->nbr_cnt, n, (float)c->d.L, (float)(1.0 / c->d.L), c->table,
-        (float)(kTableK / c->p.rcut), (float)c->d.self_r, (const float *)src, 1.0f, (float *)out, nullptr, nullptr,
+        (float)(kTableK / c->p.rcut), (float)c->d.self_r, (const float4 *)src, 1.0f, (float4 *)out, nullptr, nullptr,
         nullptr, nullptr);
   }
 }
 
+// Sorted particle vectors are (x, y, z, 0): the reductions and updates run
+// over the flat 4n scalars (the zero lanes stay zero).
 template <typename T, typename A>
 void launch_lz_init(pse_ctx *c, const void *z) {
-  const int len = 3 * c->n;
+  const int len = 4 * c->n;
+  ProfScope ps(c, PSE_STAGE_LANCZOS);
   k_norm2_partial<T, A><<<kRedBlock, 256, 0, c->stream>>>((const T *)z, len, (A *)c->partials);
   k_lz_init<A><<<1, 256, 0, c->stream>>>((const A *)c->partials, kRedBlock, (LzState<A> *)c->lz);
 }
@@ -687,53 +1054,63 @@ void launch_lz_init(pse_ctx *c, const void *z) {
 // src = z (m = 0) or the previous residual w.
 template <typename T, typename A>
 void launch_lz_iter(pse_ctx *c, int m, const void *z) {
-  const int n = c->n, len = 3 * n;
-  const size_t ld = (size_t)len;
-  T *V = (T *)c->V;
-  T *t = (T *)c->vbuf[2];
-  T *w = (T *)c->vbuf[3];
-  const T *src = m == 0 ? (const T *)z : w;
+  using T4 = typename vec4<T>::type;
+  const int n = c->n, len = 4 * n;
+  T4 *V = (T4 *)c->V;
+  T4 *t = (T4 *)c->vbuf[2];
+  T4 *w = (T4 *)c->vbuf[3];
+  const T4 *src = m == 0 ? (const T4 *)z : w;
   const int nb = nblk(n, 256);
   auto *st = (LzState<A> *)c->lz;
+  prof_begin(c, PSE_STAGE_SPMV);
   if constexpr (sizeof(T) == 8) {
     k_spmv_exact<true><<<nb, 256, 0, c->stream>>>((const double4 *)c->pos_s, c->nbr, c->nbr_cnt, n, c->d.L,
                                                    1.0 / c->d.L, c->series, c->p.xi, c->p.a, c->d.mu0, c->small_r2,
-                                                   c->d.self_r, (const double *)src, 1.0, (double *)t,
-                                                   (double *)(V + (size_t)m * ld), st, (double *)c->partials,
-                                                   c->counter);
+                                                   c->d.self_r, src, 1.0, t, V + (size_t)m * n, st,
+                                                   (double *)c->partials, c->counter);
+  } else if (c->lds_B) {
+    spmv_lds<A, true>(c, src, t, V + (size_t)m * n, st);
   } else {
     k_spmv_table<float, A, true><<<nb, 256, 0, c->stream>>>(
         (const float4 *)c->pos_s, c->nbr, c->nbr_cnt, n, (float)c->d.L, (float)(1.0 / c->d.L), c->table,
-        (float)(kTableK / c->p.rcut), (float)c->d.self_r, (const float *)src, 1.0f, (float *)t,
-        (float *)(V + (size_t)m * ld), st, (A *)c->partials, c->counter);
+        (float)(kTableK / c->p.rcut), (float)c->d.self_r, src, 1.0f, t, V + (size_t)m * n, st, (A *)c->partials,
+        c->counter);
   }
-  const T *vprev = m > 0 ? V + (size_t)(m - 1) * ld : V;
-  k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * ld, vprev, w, len, st, (A *)c->partials);
+  prof_end(c, PSE_STAGE_SPMV);
+  const T4 *vprev = m > 0 ? V + (size_t)(m - 1) * n : V;
+  ProfScope ps(c, PSE_STAGE_LANCZOS);
+  k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>((const T *)t, (const T *)(V + (size_t)m * n),
+                                                      (const T *)vprev, (T *)w, len, st, (A *)c->partials);
   k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, st, (A)c->p.lanczos_tol,
                                          c->p.lanczos_max_iter);
 }
 
 template <typename T, typename A>
 void launch_lz_combine(pse_ctx *c, void *y) {
-  const int len = 3 * c->n;
+  const int len = 4 * c->n;
+  ProfScope ps(c, PSE_STAGE_LANCZOS);
   k_lz_combine<T, A><<<nblk(len, 256) < 2048 ? nblk(len, 256) : 2048, 256, 0, c->stream>>>(
       (const T *)c->V, (size_t)len, len, (const LzState<A> *)c->lz, (T *)y);
 }
 
 template <typename T>
 void launch_gather3(pse_ctx *c, const void *in, void *out) {
-  k_gather3<T><<<nblk(c->n, 256), 256, 0, c->stream>>>((const T *)in, c->perm, (T *)out, c->n);
+  ProfScope ps(c, PSE_STAGE_OTHER);
+  k_gather3<T><<<nblk(c->n, 256), 256, 0, c->stream>>>((const T *)in, c->perm, (typename vec4<T>::type *)out, c->n);
 }
 
 template <typename T>
 void launch_finalize(pse_ctx *c, const void *yr, double cr, const void *ur, double dt, const void *wv, void *out) {
-  k_finalize<T><<<nblk(c->n, 256), 256, 0, c->stream>>>(c->perm, (const T *)yr, (T)cr, (const T *)ur, (T)dt,
-                                                        (const T *)wv, (T *)out, c->n);
+  using T4 = typename vec4<T>::type;
+  ProfScope ps(c, PSE_STAGE_OTHER);
+  k_finalize<T><<<nblk(c->n, 256), 256, 0, c->stream>>>(c->perm, (const T4 *)yr, (T)cr, (const T4 *)ur, (T)dt,
+                                                        (const T4 *)wv, (T *)out, c->n);
 }
 
 template <typename T>
 void launch_real_noise(pse_ctx *c, void *z, uint64_t seed, uint64_t sample) {
   const int len = 3 * c->n;
+  ProfScope ps(c, PSE_STAGE_NOISE);
   k_real_noise<T><<<nblk((len + 3) / 4, 256), 256, 0, c->stream>>>((T *)z, len, seed, sample);
 }
 

@@ -6,9 +6,23 @@ namespace pse {
 
 enum class GridOp { FftZ, FftStrided, XFused };
 
+// Bracket the launches of one stage with events (no-op unless selected).
+void prof_begin(pse_ctx *c, int stage);
+void prof_end(pse_ctx *c, int stage);
+struct ProfScope {
+  pse_ctx *c;
+  int stage;
+  ProfScope(pse_ctx *c_, int s) : c(c_), stage(s) { prof_begin(c, stage); }
+  ~ProfScope() { prof_end(c, stage); }
+};
+
 // particle side (k_particles.hip)
 template <typename T> void launch_bin(pse_ctx *c, const void *pos);
 template <typename T> void launch_nbr(pse_ctx *c);
+// LDS-staged near-field path (FP32): halo sizes into flags[4] for block edge B;
+// neighbour build with 16-bit LDS indices
+void launch_halo_size(pse_ctx *c, int B);
+void launch_nbr_lds(pse_ctx *c);
 template <typename T, typename A> void launch_spmv(pse_ctx *c, const void *src, void *out, bool lz, void *vm_out);
 template <typename T, typename A> void launch_lz_init(pse_ctx *c, const void *z);
 template <typename T, typename A> void launch_lz_iter(pse_ctx *c, int m, const void *z);
@@ -25,5 +39,8 @@ template <typename T> void launch_real_noise(pse_ctx *c, void *z, uint64_t seed,
 //               x = forces present, y = noise (0 none, 1 Philox, 2 grid noise)
 template <typename T> void launch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoef *wc, int x, int y);
 template <typename T> void launch_spread_interp(pse_ctx *c, bool spread, const void *vec, void *grid_or_out);
+// Spreading clears the grid itself (every node written once, or cleared
+// before the atomic fallback): no separate clear is needed.
+bool spread_writes_whole_grid(int M, int P);
 
 }  // namespace pse

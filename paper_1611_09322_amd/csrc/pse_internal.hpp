@@ -5,13 +5,14 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <vector>
 
 #include "../../include/pse.h"
 
 namespace pse {
 
 constexpr int kMaxIter = 64;     // Lanczos basis capacity
-constexpr int kTableK = 2048;    // F/G table intervals on [0, rcut]
+constexpr int kTableK = 1024;    // F/G table intervals on [0, rcut]
 constexpr int kSeriesTerms = 16; // small-r series terms of the wave complement
 constexpr int kRedBlock = 256;   // threads per block of reduction kernels
 
@@ -89,10 +90,10 @@ struct pse_ctx {
   int *nbr = nullptr;
   int *nbr_cnt = nullptr;
   int nbr_cap = 0;
-  int *flags = nullptr;     // [0] nonfinite, [1] max neighbours
+  int *flags = nullptr;     // [0] nonfinite, [1] max neighbours, [2..3] pairs, [4] max halo
   int *flags_h = nullptr;   // pinned copy
-  void *vbuf[8] = {};       // T [3n] work vectors (sorted order)
-  void *V = nullptr;        // T [(kMaxIter+1) 3n]
+  void *vbuf[8] = {};       // T4 [n] work vectors (sorted order, (x, y, z, 0))
+  void *V = nullptr;        // T4 [(kMaxIter+1) n] Lanczos basis
   void *lz = nullptr;       // LzState<A>
   void *lz_h = nullptr;     // pinned copy
   void *partials = nullptr; // A [max blocks]
@@ -105,4 +106,16 @@ struct pse_ctx {
   void *grid2 = nullptr;    // T [3 M^3] (grid-noise path, lazily)
   void *tw_M = nullptr;     // T2 [M] twiddles exp(-2 pi i k / M)
   void *tw_H = nullptr;     // T2 [M/2]
+  // GPU-time accounting (pse_profile)
+  uint32_t prof_mask = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_stage;   // stage of each recorded (begin, end) pair
+  int ev_open = -1;            // index of the open begin event, -1 if none
+  int64_t pairs = 0;
+  // LDS-staged near-field path (FP32 storage): block edge B (0 = global path),
+  // halo capacity (particles) and number of target blocks
+  int lds_B = 0;
+  int hcap = 0;
+  int lds_blocks = 0;
 };

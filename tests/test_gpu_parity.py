@@ -51,7 +51,10 @@ def make(gpu_lib, n, L, precision, grid=M0, tol=1e-6, xi=XI, rc=RC, support=P, m
                            max_iter=max_iter, precision=precision)
 
 
-@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("fp32", 2e-6), ("mixed", 2e-6)])
+# FP32 bar: linear interpolation in a 1024-interval table of F, G on [0, rc]
+# errs by at most max|F''| dr^2 / 8 ~ 0.4 (8/1024)^2 / 8 ~ 3e-6, plus FP32
+# rounding; 1e-5 leaves margin and stays far below the 1e-4 sample tolerance.
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("fp32", 1e-5), ("mixed", 1e-5)])
 def test_real_matvec_matches_dense_oracle(gpu_lib, cfg0, precision, bar):
     x, L, Mr = cfg0
     s = make(gpu_lib, len(x), L, precision)
