@@ -626,8 +626,9 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
 
 // ----------------------------------------------------------- launchers
 template <typename T, int M> struct GridCfg {
-  static constexpr int TZ = (sizeof(T) == 4) ? ((4096 / M) < (M / 2) ? (4096 / M) : (M / 2))
-                                             : ((2048 / M) < (M / 2) ? (2048 / M) : (M / 2));
+  // fused x pass holds 3 components: TZ columns x M x 3 complex in LDS
+  static constexpr int TZ = (sizeof(T) == 4) ? ((2048 / M) < (M / 2) ? (2048 / M) : (M / 2))
+                                             : ((1024 / M) < (M / 2) ? (1024 / M) : (M / 2));
   static constexpr int TZ1 = (sizeof(T) == 4) ? ((8192 / M) < (M / 2) ? (8192 / M) : (M / 2))
                                               : ((4096 / M) < (M / 2) ? (4096 / M) : (M / 2));
   static constexpr int NL = (sizeof(T) == 4) ? ((8192 / M) < 64 ? (8192 / M) : 64) : ((4096 / M) < 64 ? (4096 / M) : 64);
@@ -716,6 +717,8 @@ static bool spread_tiled(int M, int P) {
 }
 bool spread_writes_whole_grid(int M, int P) { return spread_tiled(M, P); }
 
+// Tiled interpolation stages (T + P - 1)^... nodes: the staged extent must not
+// exceed the grid (no node staged twice) and must fit the LDS.
 template <typename T, int P>
 static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid_or_out) {
   using T4 = typename vec4<T>::type;

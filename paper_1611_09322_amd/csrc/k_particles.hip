@@ -462,6 +462,23 @@ __device__ __forceinline__ void halo_stage(const float4 *__restrict__ g, float4 
   }
 }
 
+// Stage positions shifted by whole box lengths to the periodic image nearest
+// to the block centre c: pairs then need no minimum-image correction (valid
+// when the block half-width plus rc stays below L/2, i.e. nc >= B + 3).
+template <int NH>
+__device__ __forceinline__ void halo_stage_unwrapped(const float4 *__restrict__ g, float4 *l, const HaloTab &ht,
+                                                     float cx, float cy, float cz, float L, float invL) {
+  const int total = ht.base[NH];
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int h = halo_cell_of<NH>(ht, e);
+    float4 q = g[ht.start[h] + (e - ht.base[h])];
+    q.x = cx + min_image(q.x - cx, L, invL);
+    q.y = cy + min_image(q.y - cy, L, invL);
+    q.z = cz + min_image(q.z - cz, L, invL);
+    l[e] = q;
+  }
+}
+
 // target i of the block -> (halo cell index, LDS index, global sorted index)
 __device__ __forceinline__ void target_of(const HaloTab &ht, int i, int &h, int &li, int &s) {
   int j = 0;
@@ -554,17 +571,29 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
   }
 }
 
-template <int B, typename A, bool LZ>
-__global__ __launch_bounds__(512) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
-                                                  const int *__restrict__ cell_start, int nc, int n, int hcap,
-                                                  float L, float invL, const uint16_t *__restrict__ nbr,
-                                                  const int *__restrict__ cnt, const float4 *__restrict__ tab,
-                                                  float inv_dr, float self_r, float scale, float4 *__restrict__ out,
-                                                  float4 *__restrict__ vm_out, LzState<A> *st, A *partials,
-                                                  unsigned *counter) {
+// Near-field product from the staged halo.  The halo is packed as
+// (x, y, z, v_x) + (v_y, v_z) (24 bytes per particle) together with the F/G
+// table (mu0 F, mu0 (G - F) and their forward differences, one 16-byte read
+// per pair).  Three lanes per target (lane q of the group takes neighbour
+// chunks q, q + 3, ...; 21 groups per wavefront) are combined with lane
+// shuffles; each chunk of 8 neighbours is processed branch-free (missing
+// entries are masked) so its LDS reads can all be in flight.  With UNWRAP the
+// staged positions are the images nearest the block centre.
+template <int B, bool UNWRAP, typename A, bool LZ>
+__global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
+                                                   const int *__restrict__ cell_start, int nc, float cs, int n,
+                                                   int hcap, float L, float invL, const uint16_t *__restrict__ nbr,
+                                                   const int *__restrict__ cnt, const float4 *__restrict__ tab,
+                                                   float inv_dr, float self_r, float scale, float4 *__restrict__ out,
+                                                   float4 *__restrict__ vm_out, LzState<A> *st, A *partials,
+                                                   unsigned *counter) {
   constexpr int NH = Halo<B>::NH;
+  constexpr int G = 3;                      // lanes per target
+  constexpr int GPW = 64 / G;               // groups per wavefront (lane 63 idle)
   extern __shared__ float4 smem[];
-  float4 *hpos = smem, *hsrc = smem + hcap;
+  float4 *hA = smem;                        // (x, y, z, v_x)
+  float2 *hB = (float2 *)(smem + hcap);     // (v_y, v_z)
+  __shared__ float4 tabs[kTableK + 1];
   __shared__ HaloTab ht;
   __shared__ A sh[16];
   __shared__ int last;
@@ -572,58 +601,109 @@ __global__ __launch_bounds__(512) void k_spmv_lds(const float4 *__restrict__ pos
     if (st->done) return;
     scale = (float)st->inv_beta;
   }
+  for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) tabs[k] = tab[k];
   halo_setup<B>(cell_start, nc, ht);
-  halo_stage<NH>(pos, hpos, ht);
-  halo_stage<NH>(src, hsrc, ht);
+  {
+    float cx = 0.f, cy = 0.f, cz = 0.f;
+    if (UNWRAP) {
+      const int nb = (nc + B - 1) / B;
+      const int blk = blockIdx.x;
+      const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
+      const float c0 = 0.5f * B * cs;
+      cx = bx * B * cs + c0;
+      cy = by * B * cs + c0;
+      cz = bz * B * cs + c0;
+    }
+    const int total = ht.base[NH];
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int h = halo_cell_of<NH>(ht, e);
+      const int gi = ht.start[h] + (e - ht.base[h]);
+      float4 q = pos[gi];
+      const float4 v = src[gi];
+      if (UNWRAP) {
+        q.x = cx + min_image(q.x - cx, L, invL);
+        q.y = cy + min_image(q.y - cy, L, invL);
+        q.z = cz + min_image(q.z - cz, L, invL);
+      }
+      q.w = v.x;
+      hA[e] = q;
+      hB[e] = make_float2(v.y, v.z);
+    }
+  }
   __syncthreads();
   const int ntarg = ht.tpre[ht.ntc];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / G, g = lane - grp * G;
+  const bool ingrp = grp < GPW;
   A dot = 0;
-  for (int i = threadIdx.x; i < ntarg; i += blockDim.x) {
-    int h, li, s;
-    target_of(ht, i, h, li, s);
-    const float4 p = hpos[li];
-    const float4 v = hsrc[li];
-    float ax = self_r * v.x, ay = self_r * v.y, az = self_r * v.z;
-    const int c = cnt[s];
+  for (int i0 = 0; i0 < ntarg; i0 += (int)(blockDim.x >> 6) * GPW) {
+    const int i = i0 + wave * GPW + grp;
+    const bool act = ingrp && i < ntarg;
+    int h = 0, li = 0, s = 0;
+    if (act) target_of(ht, i, h, li, s);
+    const float4 pa = hA[li];
+    const float2 pb = hB[li];
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    const int c = act ? cnt[s] : 0;
     const uint4 *row = (const uint4 *)nbr + s;
-    for (int kb = 0; kb < c; kb += 8) {
+    for (int kb = 8 * g; kb < c; kb += 8 * G) {
       const uint4 pk = row[(size_t)(kb >> 3) * n];
       const uint32_t wd[4] = {pk.x, pk.y, pk.z, pk.w};
+      int jj[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-      if (kb + u >= c) break;
-      const int j = (wd[u >> 1] >> (16 * (u & 1))) & 0xFFFF;
-      const float4 q = hpos[j];
-      const float4 w = hsrc[j];
-      const float dx = min_image(p.x - q.x, L, invL);
-      const float dy = min_image(p.y - q.y, L, invL);
-      const float dz = min_image(p.z - q.z, L, invL);
-      const float r2 = dx * dx + dy * dy + dz * dz;
-      float Fm, Dm, rinv;
-      if (r2 > 1e-24f) {
-        rinv = 1.0f / sqrtf(r2);
-        const float u = r2 * rinv * inv_dr;
-        const int kk = min((int)u, kTableK - 1);
-        const float f = u - (float)kk;
-        const float4 e = tab[kk];
-        Fm = fmaf(f, e.z, e.x);
-        Dm = fmaf(f, e.w, e.y);
-      } else {
-        Fm = self_r;
-        Dm = 0.0f;
-        rinv = 0.0f;
+        const int j = (wd[u >> 1] >> (16 * (u & 1))) & 0xFFFF;
+        jj[u] = kb + u < c ? j : li;  // a missing entry reads the target itself, masked below
       }
-      const float pr = Dm * rinv * rinv * (dx * w.x + dy * w.y + dz * w.z);
-      ax += Fm * w.x + pr * dx;
-      ay += Fm * w.y + pr * dy;
-      az += Fm * w.z + pr * dz;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float4 q = hA[jj[u]];
+        const float2 wb = hB[jj[u]];
+        float dx = pa.x - q.x, dy = pa.y - q.y, dz = pa.z - q.z;
+        if (!UNWRAP) {
+          dx = min_image(dx, L, invL);
+          dy = min_image(dy, L, invL);
+          dz = min_image(dz, L, invL);
+        }
+        const float wx = q.w, wy = wb.x, wz = wb.y;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const bool near0 = !(r2 > 1e-24f);  // coincident spheres: isotropic r -> 0 limit
+        const float rinv = near0 ? 0.0f : __frsqrt_rn(r2);
+        const float uu = r2 * rinv * inv_dr;
+        const int kk = min((int)uu, kTableK - 1);
+        const float4 e = tabs[kk];
+        const float f = uu - (float)kk;
+        const float valid = kb + u < c ? 1.0f : 0.0f;
+        const float Fm = valid * (near0 ? self_r : fmaf(f, e.z, e.x));
+        const float Dm = near0 ? 0.0f : valid * fmaf(f, e.w, e.y);
+        const float pr = Dm * rinv * rinv * (dx * wx + dy * wy + dz * wz);
+        ax += Fm * wx + pr * dx;
+        ay += Fm * wy + pr * dy;
+        az += Fm * wz + pr * dz;
       }
     }
-    out[s] = make_float4(ax * scale, ay * scale, az * scale, 0.0f);
-    if (LZ) {
-      const float4 u = make_float4(v.x * scale, v.y * scale, v.z * scale, 0.0f);
-      vm_out[s] = u;
-      dot += (A)u.x * (A)(ax * scale) + (A)u.y * (A)(ay * scale) + (A)u.z * (A)(az * scale);
+    // combine the G lanes of the target (lanes G grp .. G grp + G - 1)
+    const int base_lane = (lane / G) * G;
+    float sx = ax, sy = ay, sz = az;
+#pragma unroll
+    for (int o = 1; o < G; ++o) {
+      const int srcl = base_lane + o < 64 ? base_lane + o : lane;
+      const float tx = __shfl(ax, srcl, 64), ty = __shfl(ay, srcl, 64), tz = __shfl(az, srcl, 64);
+      sx += tx;
+      sy += ty;
+      sz += tz;
+    }
+    if (act && g == 0) {
+      const float vx = pa.w, vy = pb.x, vz = pb.y;
+      sx = (sx + self_r * vx) * scale;
+      sy = (sy + self_r * vy) * scale;
+      sz = (sz + self_r * vz) * scale;
+      out[s] = make_float4(sx, sy, sz, 0.0f);
+      if (LZ) {
+        const float4 u4 = make_float4(vx * scale, vy * scale, vz * scale, 0.0f);
+        vm_out[s] = u4;
+        dot += (A)u4.x * (A)sx + (A)u4.y * (A)sy + (A)u4.z * (A)sz;
+      }
     }
   }
   if (!LZ) return;
@@ -637,11 +717,11 @@ __global__ __launch_bounds__(512) void k_spmv_lds(const float4 *__restrict__ pos
   __syncthreads();
   if (last) {
     __threadfence();
-    A v = 0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) v += partials[i];
-    v = block_sum(v, sh);
+    A vv = 0;
+    for (int t = threadIdx.x; t < (int)gridDim.x; t += blockDim.x) vv += partials[t];
+    vv = block_sum(vv, sh);
     if (threadIdx.x == 0) {
-      st->alpha[st->m] = v;
+      st->alpha[st->m] = vv;
       *counter = 0u;
     }
   }
@@ -998,20 +1078,24 @@ void launch_nbr_lds(pse_ctx *c) {
 
 template <typename A, bool LZ>
 static void spmv_lds(pse_ctx *c, const float4 *src, float4 *out, float4 *vm_out, LzState<A> *st) {
-  const size_t smem = 2 * sizeof(float4) * (size_t)c->hcap;
+  const size_t smem = (sizeof(float4) + sizeof(float2)) * (size_t)c->hcap;
   const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L);
   const auto *nb = (const uint16_t *)c->nbr;
   const float inv_dr = (float)(kTableK / c->p.rcut), self_r = (float)c->d.self_r;
+  const bool unwrap = c->d.nc >= c->lds_B + 3;
+  auto go = [&](auto kernel) {
+    allow_lds(kernel, smem);
+    kernel<<<c->lds_blocks, 1024, smem, c->stream>>>((const float4 *)c->pos_s, src, c->cell_start, c->d.nc,
+                                                      (float)c->d.cs, c->n, c->hcap, L, invL, nb, c->nbr_cnt,
+                                                      c->table, inv_dr, self_r, 1.0f, out, vm_out, st,
+                                                      (A *)c->partials, c->counter);
+  };
   if (c->lds_B == 2) {
-    allow_lds(k_spmv_lds<2, A, LZ>, smem);
-    k_spmv_lds<2, A, LZ><<<c->lds_blocks, 512, smem, c->stream>>>(
-        (const float4 *)c->pos_s, src, c->cell_start, c->d.nc, c->n, c->hcap, L, invL, nb, c->nbr_cnt, c->table,
-        inv_dr, self_r, 1.0f, out, vm_out, st, (A *)c->partials, c->counter);
+    if (unwrap) go(k_spmv_lds<2, true, A, LZ>);
+    else go(k_spmv_lds<2, false, A, LZ>);
   } else {
-    allow_lds(k_spmv_lds<1, A, LZ>, smem);
-    k_spmv_lds<1, A, LZ><<<c->lds_blocks, 512, smem, c->stream>>>(
-        (const float4 *)c->pos_s, src, c->cell_start, c->d.nc, c->n, c->hcap, L, invL, nb, c->nbr_cnt, c->table,
-        inv_dr, self_r, 1.0f, out, vm_out, st, (A *)c->partials, c->counter);
+    if (unwrap) go(k_spmv_lds<1, true, A, LZ>);
+    else go(k_spmv_lds<1, false, A, LZ>);
   }
 }
 
