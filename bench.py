@@ -25,16 +25,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "samples·particles/s, N=1M φ=0.3 @1e-3 err: plain FP32 vs mixed+learned precond"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFS = 157.3
+SPMV_FLOPS_PER_PAIR = 36
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by the same counters on a copy of known size; the
+# summary records the hash of the kernel source it was taken on.
+TRAFFIC_SUMMARY = {"spmv": ("profiles/spmv_lds_n1M_phi03_traffic.txt", "paper_1611_09322_amd/csrc/k_particles.hip")}
 
 
-def stage_bytes(stage, n, grid, pairs, lanczos):
+def stage_bytes(stage, n, grid, pairs, lanczos, index_bytes=4):
     """Algorithmic HBM bytes of one launch of a stage (FP32 storage):
     every operand read once and every result written once."""
     g = 3 * grid**3 * 4  # one 3-component real grid (= the half spectrum)
     if stage == "spmv":
         # positions (float4) + source vector + neighbour count + result
-        # (+ the stored Lanczos basis vector) + one 4-byte index per pair
-        return n * (16 + 12 + 4 + 12 + (12 if lanczos else 0)) + 4 * pairs
+        # (+ the stored Lanczos basis vector) + one stored index per pair
+        return n * (16 + 12 + 4 + 12 + (12 if lanczos else 0)) + index_bytes * pairs
     if stage == "fft":
         return 2 * g
     if stage == "xfused":
@@ -48,13 +54,48 @@ def stage_bytes(stage, n, grid, pairs, lanczos):
     return None
 
 
+def measured_traffic(stage):
+    """Counter-measured HBM bytes per launch, or None when no summary exists
+    or the kernel source changed since the counters were taken."""
+    import hashlib
+
+    if stage not in TRAFFIC_SUMMARY:
+        return None
+    summ, src = (os.path.join(ROOT, p) for p in TRAFFIC_SUMMARY[stage])
+    if not os.path.exists(summ):
+        return None
+    fields = {}
+    with open(summ) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("kernel_source_sha256") != digest or "hbm_bytes_per_launch" not in fields:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
+def copy_calibration(torch):
+    """One elementwise pass over 512 MiB (read 512 MiB, write 512 MiB), for
+    scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    a = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    print("[bench] copy calibration: 536870912 bytes read, 536870912 bytes written", file=sys.stderr, flush=True)
+
+
 def make_workload(args):
     import numpy as np
 
     import synth
 
     t0 = time.time()
-    x, L = synth.hard_spheres(args.n, args.phi, a=1.0, seed=1003, sweeps=args.sweeps)
+    x, L = synth.hard_spheres(args.n, args.phi, a=1.0, seed=1003, sweeps=args.sweeps,
+                              progress=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     # caller order is arbitrary: shuffle so that the library's own sort is exercised
     perm = np.random.default_rng(7).permutation(len(x))
     x = np.ascontiguousarray(x[perm])
@@ -104,6 +145,7 @@ def run_variant(pse, torch, x, L, F, args, precision):
         "ms_per_step": ms_step,
         "lanczos_iters_mean": sum(iters) / len(iters),
         "neighbor_pairs": st.neighbor_pairs,
+        "nbr_index_bytes": st.nbr_index_bytes,
         "max_neighbors": st.max_neighbors,
         "warmup_breakdown_ms_per_step": {k: round(v[0] / max(args.warmup, 1), 4) for k, v in breakdown.items()},
         "warmup_gpu_ms_per_step": total / max(args.warmup, 1),
@@ -173,6 +215,8 @@ def main():
     ap.add_argument("--variants", default="fp32,mixed")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 512 MiB elementwise copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -194,11 +238,21 @@ def main():
     head = "mixed" if "mixed" in variants else next(iter(variants))
     hv = variants[head]
     dom = hv["dominant"]
-    nbytes = stage_bytes(dom, args.n, args.grid, hv["neighbor_pairs"], lanczos=(dom == "spmv"))
+    nbytes = stage_bytes(dom, args.n, args.grid, hv["neighbor_pairs"], lanczos=(dom == "spmv"),
+                         index_bytes=hv["nbr_index_bytes"])
     achieved = nbytes / (hv["dominant_ms_avg"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
                 "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": hv["dominant_ms_avg"]}
+    if dom == "spmv":
+        # the same launches against the FP32 vector peak (matrix-free F/G
+        # evaluation per pair; count per pair derived in the design notes)
+        roofline["alu_flops_per_pair"] = SPMV_FLOPS_PER_PAIR
+        roofline["alu_frac"] = (SPMV_FLOPS_PER_PAIR * hv["neighbor_pairs"] / (hv["dominant_ms_avg"] * 1e-3)
+                                / 1e12 / FP32_PEAK_TFS)
+    roofline["traffic"] = measured_traffic(dom)
+    if args.copy_calibration:
+        copy_calibration(torch)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     line = {
         "metric": METRIC,

@@ -82,6 +82,8 @@ typedef struct {
   int32_t max_neighbors;    /* largest near-field neighbour count */
   int32_t precond_fallbacks;/* particles whose learned block fell back to I */
   int64_t neighbor_pairs;   /* ordered near-field pairs (sum of neighbour counts) */
+  int32_t nbr_index_bytes;  /* bytes per stored neighbour index: 2 on the LDS-staged
+                               FP32 path (halo-local), 4 otherwise (global) */
 } pse_stats;
 
 /* Stages of the hot path, for GPU-time accounting (pse_profile). */

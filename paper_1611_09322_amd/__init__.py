@@ -47,6 +47,7 @@ class Stats(ctypes.Structure):
         ("max_neighbors", ctypes.c_int32),
         ("precond_fallbacks", ctypes.c_int32),
         ("neighbor_pairs", ctypes.c_int64),
+        ("nbr_index_bytes", ctypes.c_int32),
     ]
 
     def as_dict(self):

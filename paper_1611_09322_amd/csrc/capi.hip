@@ -224,6 +224,7 @@ pse_status sample_impl(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter,
   if (stats) {
     stats->max_neighbors = c->flags_h[1];
     stats->neighbor_pairs = c->pairs;
+    stats->nbr_index_bytes = c->lds_B ? 2 : 4;
   }
   (void)pi;
   const pse_status se = hip_status(hipGetLastError());
@@ -276,7 +277,7 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
         return PSE_ERR_HIP;
       if (c->flags_h[0]) return PSE_ERR_NONFINITE;
       const int hmax = c->flags_h[4];
-      if (hmax <= 65535 && (sizeof(float4) + sizeof(float2)) * (size_t)hmax + sizeof(float4) * (kTableK + 1) <= kLdsBudget) {
+      if (hmax <= 65535 && (sizeof(float4) + sizeof(float2)) * (size_t)hmax + sizeof(float4) * (kTableK + 2) <= kLdsBudget) {
         c->lds_B = B;
         c->hcap = hmax > 0 ? hmax : 1;
         const int nb = (c->d.nc + B - 1) / B;

@@ -301,7 +301,7 @@ template <> DI C<float> zeta_at<float>(uint64_t e, uint64_t seed, uint64_t sampl
 }
 
 // ------------------------------------------------------ fused x pass
-// For a tile (jy = blockIdx.y, jz in [z0, z0+TZ)) and all jx:
+// For a tile (one jy, jz in [z0, z0+TZ)) and all jx:
 //   [FORCES] forward x-FFT of the spread-force spectrum (z, y already done);
 //   Uhat(k) = (I - kk/k^2) [ det_scale B ghat^-2 Fhat + sto_scale sqrt(B) ghat^-1 zeta ]
 //   with B = sinc^2(ka) H(k, xi) / k^2 (eq. Mwave), ghat = exp(-k^2 sigma^2 / 2);
@@ -316,7 +316,9 @@ __global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, 
   __shared__ C<T> tw[M];
   for (int i = threadIdx.x; i < M; i += BLOCK) tw[i] = tw_g[i];
   const size_t s_fft = (size_t)M * H, s_comp = (size_t)M * M * H;
-  const int jy = blockIdx.y, z0 = blockIdx.x * TZ;
+  // adjacent z tiles share cache lines: keep them on one XCD
+  const int lin = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  const int jy = lin / gridDim.x, z0 = (lin % gridDim.x) * TZ;
   const size_t base = (size_t)jy * H + z0;
   if (FORCES) {
     tile_load<T, M, TZ, 3>(buf, data, base, s_fft, s_comp, BLOCK);
@@ -391,7 +393,9 @@ template <typename T, int P>
 __global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__restrict__ pos,
                                                 const typename vec4<T>::type *__restrict__ f, int n, T *__restrict__ grid, int M, T h,
                                                 T invh, T inv2s2, T norm) {
-  const int s = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // particles are in cell order: XCD-contiguous ranges keep the grid
+  // nodes of neighbouring particles within one L2
+  const int s = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (s >= n) return;
   const auto p = pos[s];
@@ -433,7 +437,9 @@ __global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__
                                                 const T *__restrict__ grid, int n,
                                                 typename vec4<T>::type *__restrict__ out, int M, T h,
                                                 T invh, T inv2s2, T norm_h3) {
-  const int s = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // particles are in cell order: XCD-contiguous ranges keep the grid
+  // nodes of neighbouring particles within one L2
+  const int s = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (s >= n) return;
   const auto p = pos[s];
@@ -508,7 +514,11 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
   __shared__ int nlist;
   if (threadIdx.x == 0) nlist = 0;
   __syncthreads();
-  const int t0x = blockIdx.z * TX, t0y = blockIdx.y * TY, t0z = blockIdx.x * TZ;
+  // neighbouring tiles read the same cells: keep them on one XCD
+  const int lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                            gridDim.x * gridDim.y * gridDim.z);
+  const int t0x = (lin / (gridDim.x * gridDim.y)) * TX, t0y = ((lin / gridDim.x) % gridDim.y) * TY,
+            t0z = (lin % gridDim.x) * TZ;
   const int t0[3] = {t0x, t0y, t0z}, tt[3] = {TX, TY, TZ};
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;

@@ -401,7 +401,7 @@ template <int B>
 __device__ __forceinline__ void halo_setup(const int *__restrict__ cell_start, int nc, HaloTab &ht) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   const int nb = (nc + B - 1) / B;
-  const int blk = blockIdx.x;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
   if (threadIdx.x < 64) {
     const int h = threadIdx.x;
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
   extern __shared__ float4 smem[];
   float4 *hA = smem;                        // (x, y, z, v_x)
   float2 *hB = (float2 *)(smem + hcap);     // (v_y, v_z)
-  __shared__ float4 tabs[kTableK + 1];
+  __shared__ float4 tabs[kTableK + 2];
   __shared__ HaloTab ht;
   __shared__ A sh[16];
   __shared__ int last;
@@ -602,12 +602,13 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
     scale = (float)st->inv_beta;
   }
   for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) tabs[k] = tab[k];
+  if (threadIdx.x == 0) tabs[kTableK + 1] = make_float4(self_r, 0.0f, 0.0f, 0.0f);
   halo_setup<B>(cell_start, nc, ht);
   {
     float cx = 0.f, cy = 0.f, cz = 0.f;
     if (UNWRAP) {
       const int nb = (nc + B - 1) / B;
-      const int blk = blockIdx.x;
+      const int blk = xcd_block(blockIdx.x, gridDim.x);
       const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
       const float c0 = 0.5f * B * cs;
       cx = bx * B * cs + c0;
@@ -646,8 +647,11 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
     float ax = 0.f, ay = 0.f, az = 0.f;
     const int c = act ? cnt[s] : 0;
     const uint4 *row = (const uint4 *)nbr + s;
+    // the next chunk of indices is loaded while the current one is used
+    uint4 nxt = 8 * g < c ? row[(size_t)g * n] : make_uint4(0, 0, 0, 0);
     for (int kb = 8 * g; kb < c; kb += 8 * G) {
-      const uint4 pk = row[(size_t)(kb >> 3) * n];
+      const uint4 pk = nxt;
+      if (kb + 8 * G < c) nxt = row[(size_t)((kb >> 3) + G) * n];
       const uint32_t wd[4] = {pk.x, pk.y, pk.z, pk.w};
       int jj[8];
 #pragma unroll
@@ -655,31 +659,50 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
         const int j = (wd[u >> 1] >> (16 * (u & 1))) & 0xFFFF;
         jj[u] = kb + u < c ? j : li;  // a missing entry reads the target itself, masked below
       }
+      // all halo reads of the chunk first, then all table reads: two LDS
+      // round trips per chunk instead of two per neighbour
+      float4 q[8];
+      float2 wb[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const float4 q = hA[jj[u]];
-        const float2 wb = hB[jj[u]];
-        float dx = pa.x - q.x, dy = pa.y - q.y, dz = pa.z - q.z;
+        q[u] = hA[jj[u]];
+        wb[u] = hB[jj[u]];
+      }
+      float dx[8], dy[8], dz[8], rinv[8], fr[8];
+      int kk[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        dx[u] = pa.x - q[u].x;
+        dy[u] = pa.y - q[u].y;
+        dz[u] = pa.z - q[u].z;
         if (!UNWRAP) {
-          dx = min_image(dx, L, invL);
-          dy = min_image(dy, L, invL);
-          dz = min_image(dz, L, invL);
+          dx[u] = min_image(dx[u], L, invL);
+          dy[u] = min_image(dy[u], L, invL);
+          dz[u] = min_image(dz[u], L, invL);
         }
-        const float wx = q.w, wy = wb.x, wz = wb.y;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const bool near0 = !(r2 > 1e-24f);  // coincident spheres: isotropic r -> 0 limit
-        const float rinv = near0 ? 0.0f : __frsqrt_rn(r2);
-        const float uu = r2 * rinv * inv_dr;
-        const int kk = min((int)uu, kTableK - 1);
-        const float4 e = tabs[kk];
-        const float f = uu - (float)kk;
+        const float r2 = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
+        // coincident spheres take the isotropic r -> 0 limit from the extra
+        // table entry (self_r, 0, 0, 0): every lane reads the table, no branch
+        const bool near0 = !(r2 > 1e-24f);
+        const float rs = __frsqrt_rn(fmaxf(r2, 1e-24f));  // unconditional: no branch around it
+        rinv[u] = near0 ? 0.0f : rs;
+        const float uu = r2 * rinv[u] * inv_dr;
+        kk[u] = near0 ? kTableK + 1 : min((int)uu, kTableK - 1);
+        fr[u] = near0 ? 0.0f : uu - (float)kk[u];
+      }
+      float4 e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = tabs[kk[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float wx = q[u].w, wy = wb[u].x, wz = wb[u].y;
         const float valid = kb + u < c ? 1.0f : 0.0f;
-        const float Fm = valid * (near0 ? self_r : fmaf(f, e.z, e.x));
-        const float Dm = near0 ? 0.0f : valid * fmaf(f, e.w, e.y);
-        const float pr = Dm * rinv * rinv * (dx * wx + dy * wy + dz * wz);
-        ax += Fm * wx + pr * dx;
-        ay += Fm * wy + pr * dy;
-        az += Fm * wz + pr * dz;
+        const float Fm = valid * fmaf(fr[u], e[u].z, e[u].x);
+        const float Dm = valid * fmaf(fr[u], e[u].w, e[u].y);
+        const float pr = Dm * rinv[u] * rinv[u] * (dx[u] * wx + dy[u] * wy + dz[u] * wz);
+        ax += Fm * wx + pr * dx[u];
+        ay += Fm * wy + pr * dy[u];
+        az += Fm * wz + pr * dz[u];
       }
     }
     // combine the G lanes of the target (lanes G grp .. G grp + G - 1)

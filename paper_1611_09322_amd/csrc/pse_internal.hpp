@@ -24,6 +24,15 @@ template <> struct vec4<float> { using type = float4; };
 template <> struct vec4<double> { using type = double4; };
 
 // Lanczos state kept in device memory (A = accumulation precision).
+// Workgroups go to the 8 XCDs round-robin (workgroup b to XCD b % 8), and
+// each XCD has its own L2.  xcd_block renumbers them so that each XCD works
+// through one contiguous range of logical workgroups: neighbouring tiles,
+// which read overlapping data, then share an L2.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 template <typename A> struct LzState {
   A alpha[kMaxIter];
   A beta[kMaxIter + 1];  // beta[0] = |z|, beta[m+1] couples v_m and v_{m+1}

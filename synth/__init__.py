@@ -88,16 +88,31 @@ def min_pair_distance(x, L, a=1.0):
     return _load().min_pair_distance(len(x), L, a, _dp(x))
 
 
-def hard_spheres(n, phi, a=1.0, seed=0, sweeps=0):
-    """RSA at volume fraction phi, then `sweeps` MC sweeps. Returns (x, L)."""
+def hard_spheres(n, phi, a=1.0, seed=0, sweeps=0, progress=None):
+    """RSA at volume fraction phi, then `sweeps` MC sweeps. Returns (x, L).
+
+    With `progress` (a callable taking a message) the sweeps run in chunks of
+    250 (each chunk its own random streams, step carried over) and each chunk
+    is reported."""
     L = box_side(n, phi, a)
     x = rsa_positions(n, L, a, seed)
     # relabel particles in spatial (cell) order: the same configuration, but
     # memory-local for the Monte Carlo neighbour checks
     c = np.floor(x / (3.0 * a)).astype(np.int64)
     x = np.ascontiguousarray(x[np.lexsort((c[:, 2], c[:, 1], c[:, 0]))])
-    if sweeps:
+    if sweeps and progress is None:
         x, _, _ = mc_relax(x, L, a, sweeps, seed + 7919)
+    elif sweeps:
+        done, step = 0, 0.1 * a
+        while done < sweeps:
+            k = min(250, sweeps - done)
+            x = np.ascontiguousarray(x, dtype=np.float64)
+            st = ctypes.c_double(step)
+            acc = _load().mc_relax(len(x), L, a, _dp(x), k, seed + 7919 + 104729 * done, 0.4, ctypes.byref(st),
+                                   min(k, 50) if done == 0 else 0)
+            step = st.value
+            done += k
+            progress(f"MC sweeps {done}/{sweeps} (step {step:.3f}a, acceptance {acc:.2f})")
     return x, L
 
 
