@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "samples·particles/s, N=1M φ=0.3 @1e-3 err: plain FP32 vs mixed+learned precond"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFS = 157.3
-SPMV_FLOPS_PER_PAIR = 36
+SPMV_FLOPS_PER_PAIR = 35
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by the same counters on a copy of known size; the
 # summary records the hash of the kernel source it was taken on.

@@ -507,16 +507,24 @@ __global__ void k_halo_size(const int *__restrict__ cell_start, int nc, int *__r
   atomicMax(&flags[4], tot);
 }
 
-template <int B>
+template <int B, bool UNWRAP>
 __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
-                                                 int nc, int n, float L, float invL, float rc2,
+                                                 int nc, float cs, int n, float L, float invL, float rc2,
                                                  uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
                                                  int *__restrict__ flags) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   extern __shared__ float4 hpos[];
   __shared__ HaloTab ht;
   halo_setup<B>(cell_start, nc, ht);
-  halo_stage<NH>(pos, hpos, ht);
+  if (UNWRAP) {
+    const int nb = (nc + B - 1) / B;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
+    const float c0 = 0.5f * B * cs;
+    halo_stage_unwrapped<NH>(pos, hpos, ht, bx * B * cs + c0, by * B * cs + c0, bz * B * cs + c0, L, invL);
+  } else {
+    halo_stage<NH>(pos, hpos, ht);
+  }
   __syncthreads();
   const int ntarg = ht.tpre[ht.ntc];
   unsigned long long mine = 0;
@@ -534,24 +542,38 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
         for (int dz = -1; dz <= 1; ++dz) {
           const int hh = ((ox + 1 + dx) * HB + (oy + 1 + dy)) * HB + (oz + 1 + dz);
           const int e = ht.base[hh + 1];
-          for (int j = ht.base[hh]; j < e; ++j) {
-            if (j == li) continue;
-            const float4 q = hpos[j];
-            const float ddx = min_image(p.x - q.x, L, invL);
-            const float ddy = min_image(p.y - q.y, L, invL);
-            const float ddz = min_image(p.z - q.z, L, invL);
-            if (ddx * ddx + ddy * ddy + ddz * ddz <= rc2) {
-              const int slot = k & 7;
-              const uint64_t v = (uint64_t)j << (16 * (slot & 3));
-              if (slot < 4) lo |= v;
-              else hi |= v;
-              if (slot == 7) {
-                if ((k >> 3) < (cap >> 3))
-                  row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
-                                                             (uint32_t)(hi >> 32));
-                lo = hi = 0;
+          // four candidates per step: their LDS reads are in flight together
+          for (int j0 = ht.base[hh]; j0 < e; j0 += 4) {
+            float4 q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = hpos[min(j0 + u, e - 1)];
+            unsigned hit = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              float ddx = p.x - q[u].x, ddy = p.y - q[u].y, ddz = p.z - q[u].z;
+              if (!UNWRAP) {
+                ddx = min_image(ddx, L, invL);
+                ddy = min_image(ddy, L, invL);
+                ddz = min_image(ddz, L, invL);
               }
-              ++k;
+              const int j = j0 + u;
+              if (j < e && j != li && ddx * ddx + ddy * ddy + ddz * ddz <= rc2) hit |= 1u << u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (hit & (1u << u)) {
+                const int slot = k & 7;
+                const uint64_t v = (uint64_t)(j0 + u) << (16 * (slot & 3));
+                if (slot < 4) lo |= v;
+                else hi |= v;
+                if (slot == 7) {
+                  if ((k >> 3) < (cap >> 3))
+                    row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
+                                                               (uint32_t)(hi >> 32));
+                  lo = hi = 0;
+                }
+                ++k;
+              }
             }
           }
         }
@@ -1088,14 +1110,18 @@ void launch_nbr_lds(pse_ctx *c) {
   const size_t smem = sizeof(float4) * (size_t)c->hcap;
   const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L), rc2 = (float)(c->p.rcut * c->p.rcut);
   auto *nb = (uint16_t *)c->nbr;
+  const bool unwrap = c->d.nc >= c->lds_B + 3;
+  auto go = [&](auto kern) {
+    allow_lds(kern, smem);
+    kern<<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
+                                                  c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags);
+  };
   if (c->lds_B == 2) {
-    allow_lds(k_nbr_lds<2>, smem);
-    k_nbr_lds<2><<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, c->n, L,
-                                                         invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags);
+    if (unwrap) go(k_nbr_lds<2, true>);
+    else go(k_nbr_lds<2, false>);
   } else {
-    allow_lds(k_nbr_lds<1>, smem);
-    k_nbr_lds<1><<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, c->n, L,
-                                                         invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags);
+    if (unwrap) go(k_nbr_lds<1, true>);
+    else go(k_nbr_lds<1, false>);
   }
 }
 
