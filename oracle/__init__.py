@@ -18,6 +18,9 @@ Modules
            the Box-Muller normals and Hermitian k-space noise built from it.
   lanczos  Krylov square-root iterate (Chow-Saad) with full
            re-orthogonalisation, and the eigendecomposition square root.
+  precond  the learned block preconditioner of the Krylov sample: geometry
+           features, the bf16 MLP, the per-particle fallback, the
+           preconditioned root P^-1 (P M_r P^T)^1/2 z and the training target.
   sampler  the composed sample Delta x = sqrt(2 kT dt)(y_r + y_w) + dt M F
            (eqs. langevin, split) and the truncation-error bounds.
 
