@@ -105,9 +105,36 @@ def make_workload(args):
     return x, L, F
 
 
-def run_variant(pse, torch, x, L, F, args, precision):
+def train_precond(pse, torch, args):
+    """Learned block preconditioner for this workload's parameters, trained
+    (untimed) on small independent boxes at the same volume fraction."""
+    import numpy as np
+
+    import synth
+    from paper_1611_09322_amd import precond as ppc
+
+    t0 = time.time()
+    tr = ppc.Trainer(torch, seed=3, lr=3e-3)
+    for k in range(args.train_boxes):
+        x, L = synth.hard_spheres(args.train_n, args.phi, a=1.0, seed=2100 + k, sweeps=100)
+        s = pse.Sampler(len(x), L, a=1.0, eta=1.0, kT=1.0, xi=args.xi, rcut=args.rc, grid=64, support=args.support,
+                        tol=args.tol, max_iter=64, precision="mixed", precond=1)
+        s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+        idx = np.random.default_rng(k).choice(len(x), args.train_rows, replace=False).astype(np.int32)
+        tr.add(s, x, idx)
+        s.close()
+    hist = tr.fit(args.train_epochs)
+    print(f"[bench] preconditioner trained on {args.train_boxes} x {args.train_rows} rows in {time.time() - t0:.1f}s:"
+          f" loss {hist[0]:.3e} -> {hist[-1]:.3e}", file=sys.stderr, flush=True)
+    return tr.weights_bits(), hist
+
+
+def run_variant(pse, torch, x, L, F, args, variant, weights=None):
+    precision, precond = (variant.split("+")[0], 1) if variant.endswith("+precond") else (variant, 0)
     s = pse.Sampler(len(x), L, a=1.0, eta=1.0, kT=1.0, xi=args.xi, rcut=args.rc, grid=args.grid,
-                    support=args.support, tol=args.tol, max_iter=64, precision=precision)
+                    support=args.support, tol=args.tol, max_iter=64, precision=precision, precond=precond)
+    if precond:
+        s.set_precond_weights(weights)
     pos = torch.as_tensor(x, dtype=torch.float32, device="cuda")
     frc = torch.as_tensor(F, dtype=torch.float32, device="cuda")
     out = torch.empty_like(pos)
@@ -141,6 +168,7 @@ def run_variant(pse, torch, x, L, F, args, precision):
     s.profile([])
     ms_step = 1e3 * dt / args.steps
     res = {
+        "precond_fallbacks": st.precond_fallbacks,
         "value": len(x) * args.steps / dt,
         "ms_per_step": ms_step,
         "lanczos_iters_mean": sum(iters) / len(iters),
@@ -212,7 +240,12 @@ def main():
     ap.add_argument("--rc", type=float, default=8.0)
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--sweeps", type=int, default=2000, help="Monte Carlo relaxation sweeps after RSA")
-    ap.add_argument("--variants", default="fp32,mixed")
+    ap.add_argument("--variants", default="fp32,mixed,mixed+precond",
+                    help="comma list of fp32, mixed, fp64 and <precision>+precond")
+    ap.add_argument("--train-boxes", type=int, default=2)
+    ap.add_argument("--train-n", type=int, default=3000)
+    ap.add_argument("--train-rows", type=int, default=500)
+    ap.add_argument("--train-epochs", type=int, default=300)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -231,11 +264,15 @@ def main():
     torch.cuda.set_device(0)
     x, L, F = make_workload(args)
     variants = {}
+    weights, train_hist = None, None
     for v in args.variants.split(","):
+        if v.endswith("+precond") and weights is None:
+            weights, train_hist = train_precond(pse, torch, args)
         print(f"[bench] variant {v}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-        variants[v] = run_variant(pse, torch, x, L, F, args, v)
+        variants[v] = run_variant(pse, torch, x, L, F, args, v, weights)
         print(f"[bench] variant {v}: {json.dumps(variants[v])}", file=sys.stderr, flush=True)
-    head = "mixed" if "mixed" in variants else next(iter(variants))
+    # the metric's subject: mixed precision with the learned preconditioner
+    head = next((k for k in ("mixed+precond", "mixed", "fp32") if k in variants), next(iter(variants)))
     hv = variants[head]
     dom = hv["dominant"]
     nbytes = stage_bytes(dom, args.n, args.grid, hv["neighbor_pairs"], lanczos=(dom == "spmv"),
@@ -272,11 +309,15 @@ def main():
                         f"phi={args.phi} (RSA + {args.sweeps} MC sweeps), grid {args.grid}^3, P={args.support}, "
                         f"xi a={args.xi}, rc={args.rc}a, tol {args.tol}",
             "variant": head,
-            "precond": "none",
+            "precond": "learned (trained before timing)" if head.endswith("+precond") else "none",
         },
         "variants": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
                          "lanczos_iters_mean": v["lanczos_iters_mean"],
+                         "precond_fallbacks": v["precond_fallbacks"],
                          "breakdown_ms": v["warmup_breakdown_ms_per_step"]} for k, v in variants.items()},
+        "precond_training": None if train_hist is None else {
+            "boxes": args.train_boxes, "n": args.train_n, "rows_per_box": args.train_rows,
+            "epochs": args.train_epochs, "loss_first": train_hist[0], "loss_last": train_hist[-1]},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -98,7 +98,8 @@ typedef enum {
   PSE_STAGE_XFUSED = 7,   /* x pass with B(k), projection, noise */
   PSE_STAGE_INTERP = 8,   /* Gaussian interpolation */
   PSE_STAGE_OTHER = 9,    /* gathers, final combine, grid clears */
-  PSE_NSTAGES = 10
+  PSE_STAGE_PRECOND = 10, /* learned preconditioner: MLP, blocks, P^-1 y */
+  PSE_NSTAGES = 11
 } pse_stage;
 
 typedef struct {
@@ -185,6 +186,83 @@ pse_status pse_wave_apply(pse_ctx *ctx, const void *forces_dev, void *u_dev);
 
 /* u = (M_r + M_w) F, the deterministic mobility product (n x 3). */
 pse_status pse_mobility_apply(pse_ctx *ctx, const void *forces_dev, void *u_dev);
+
+/* ---------------------------------------------------------------------
+ * Learned block preconditioner of the real-space Krylov sample.
+ *
+ * With params.precond = 1 the Lanczos iteration of Sec. II B.1 runs on
+ * A = P M_r P^T with P block diagonal (one 3 x 3 block P_i per particle) and
+ * the real-space sample is y = P^{-1} A^{1/2} z1; its covariance is still
+ * M_r (P^{-1} A P^{-T} = M_r), so the output law is unchanged.  The paper
+ * uses no preconditioner: the features, network and training target are
+ * this library's (defined below).  P_i = I + reshape(y_i), y_i the output of
+ * an MLP 24 -> 64 -> 64 -> 9 (relu; bf16 weights, inputs and hidden values,
+ * fp32 sums on the matrix cores) applied to 24 features of the particle's
+ * near field, accumulated during pse_set_positions:
+ *   0..3   #{r < 2.2a}/4, #{r < 3a}/8, #{r < 4.5a}/16, #{r <= rc}/128
+ *   4      sum F / 8
+ *   5..10  sum (G - F) dh dh^T        (xx, yy, zz, xy, xz, yz)
+ *   11..16 sum_{r < 3a} dh dh^T / 4   (same order)
+ *   17..19 sum_{r < 3a} dh / 4
+ *   20     sum (G - F);  21  min r / rc (1 without neighbours)
+ *   22     sum_{r < 3a} (3a - r) / a / 4;  23  F_self (eq. self)
+ * over neighbours j (minimum image, r <= rc, d = x_i - x_j, dh = d / r or 0
+ * at r = 0), F and G the dimensionless functions of Appendix A.
+ * A block falls back to I if it is not finite, |det P_i| < 1e-6 or
+ * |P_i|_F |P_i^{-1}|_F > 1e3.  Without weights every block is I (global
+ * fallback).  Sampling calls return PSE_WARN_PRECOND_FALLBACK when any block
+ * fell back; pse_stats.precond_fallbacks counts them.
+ *
+ * Weights: one bf16 array of PSE_MLP_NPARAM elements, in this order:
+ *   W1 [64][32] (input columns 24..31 must be 0), b1 [64], W2 [64][64],
+ *   b2 [64], W3 [16][64] (rows 9..15 must be 0), b3 [16] (9..15 must be 0).
+ * Device arrays passed to the pse_mlp_* calls must be 16-byte aligned.
+ * ------------------------------------------------------------------- */
+#define PSE_MLP_NPARAM 7312
+#define PSE_MLP_NFEAT 24
+#define PSE_MLP_NHIDDEN 64
+#define PSE_MLP_NOUT 9
+
+/* Copy the bf16 weights (host, bytes = 2 * PSE_MLP_NPARAM) into the context;
+ * the blocks of the current positions are recomputed.  PSE_ERR_PARAMS if
+ * the context was created with precond = 0. */
+pse_status pse_precond_set_weights(pse_ctx *ctx, const void *weights_host, size_t bytes);
+
+/* Features of the current positions, n x 24 bf16 (device, caller order). */
+pse_status pse_precond_features(pse_ctx *ctx, void *feat_dev);
+
+/* The blocks P_i in use, n x 9 fp32 row-major (device, caller order), and
+ * the number of fallback blocks (host, may be NULL). */
+pse_status pse_precond_blocks(pse_ctx *ctx, void *P_dev, int32_t *fallbacks);
+
+/* Training targets (host, FP64, no GPU): for each caller index idx[q] the
+ * symmetric square root of the ii block of M_patch^{-1}, M_patch = M_r
+ * restricted to i and the particles within `radius` of it (<= 0: rc),
+ * times (mu0 F_self)^{1/2} (an isolated particle gives I); out is m x 9
+ * row-major.  pos_host is n x 3 (caller order).  PSE_ERR_NOT_CONVERGED if a
+ * patch matrix is not positive definite. */
+pse_status pse_precond_targets(const pse_params *params, const double *pos_host, const int32_t *idx, int32_t m,
+                               double radius, double *out_host);
+
+/* y = MLP(x): x n x 24 bf16, y n x 9 fp32 (device).  act_cache (device,
+ * n x 128 bf16: the hidden activations h1, h2 of each row) may be NULL; the
+ * backward pass needs it.  Runs on `stream` (NULL: default stream). */
+pse_status pse_mlp_forward(const void *weights_dev, const void *x_dev, int32_t n, void *y_dev, void *act_cache_dev,
+                           void *stream);
+
+/* Bytes of device workspace pse_mlp_backward needs for n rows. */
+size_t pse_mlp_backward_workspace(int32_t n);
+
+/* dw (device, PSE_MLP_NPARAM fp32) = gradient of sum_rows <dy, y> with
+ * respect to every weight, from the forward pass's x and act_cache; padding
+ * entries get 0.  Deterministic (fixed summation order). */
+pse_status pse_mlp_backward(const void *weights_dev, const void *x_dev, const void *act_cache_dev, const void *dy_dev,
+                            int32_t n, void *dw_dev, void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8, step
+ * t >= 1) on the fp32 master weights, with the bf16 copy rewritten. */
+pse_status pse_mlp_adam(void *w_master_dev, void *w_bf16_dev, const void *dw_dev, void *m_dev, void *v_dev, float lr,
+                        int32_t t, void *stream);
 
 /* GPU-time accounting: for every stage whose bit (1 << pse_stage) is set in
  * stage_mask, each kernel launch of that stage is bracketed by HIP events on

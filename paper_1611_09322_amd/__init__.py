@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libpse.so")
 
 PSE_OK = 0
 PSE_ERR_NOT_CONVERGED = -6
+PSE_WARN_PRECOND_FALLBACK = 1
+MLP_NPARAM = 7312
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 
 
@@ -93,10 +95,19 @@ _SIGS = {
     "pse_wave_sample": ([_VP, _VP, _VP], ctypes.c_int),
     "pse_wave_apply": ([_VP, _VP, _VP], ctypes.c_int),
     "pse_mobility_apply": ([_VP, _VP, _VP], ctypes.c_int),
+    "pse_precond_set_weights": ([_VP, _VP, ctypes.c_size_t], ctypes.c_int),
+    "pse_precond_features": ([_VP, _VP], ctypes.c_int),
+    "pse_precond_blocks": ([_VP, _VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "pse_precond_targets": ([ctypes.POINTER(Params), _VP, _VP, ctypes.c_int32, ctypes.c_double, _VP], ctypes.c_int),
+    "pse_mlp_forward": ([_VP, _VP, ctypes.c_int32, _VP, _VP, _VP], ctypes.c_int),
+    "pse_mlp_backward_workspace": ([ctypes.c_int32], ctypes.c_size_t),
+    "pse_mlp_backward": ([_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
+    "pse_mlp_adam": ([_VP, _VP, _VP, _VP, _VP, ctypes.c_float, ctypes.c_int32, _VP], ctypes.c_int),
     "pse_profile": ([_VP, ctypes.c_uint32], ctypes.c_int),
     "pse_profile_read": ([_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
 }
-STAGES = ("bin", "nbr", "spmv", "lanczos", "noise", "spread", "fft", "xfused", "interp", "other")
+STAGES = ("bin", "nbr", "spmv", "lanczos", "noise", "spread", "fft", "xfused", "interp", "other", "precond")
+SAMPLE_OK = (PSE_ERR_NOT_CONVERGED, PSE_WARN_PRECOND_FALLBACK)
 EXPORTED = tuple(_SIGS)
 
 
@@ -171,14 +182,14 @@ def pse_set_positions(ctx, pos_ptr):
 def pse_sample(ctx, seed, counter, dt, forces_ptr, disp_ptr):
     st = Stats()
     s = load().pse_sample(ctx, seed, counter, dt, forces_ptr, disp_ptr, ctypes.byref(st))
-    _check(s, "pse_sample", allow=(PSE_ERR_NOT_CONVERGED,))
+    _check(s, "pse_sample", allow=SAMPLE_OK)
     return s, st
 
 
 def pse_sample_with_noise(ctx, z1_ptr, W_ptr, dt, forces_ptr, disp_ptr):
     st = Stats()
     s = load().pse_sample_with_noise(ctx, z1_ptr, W_ptr, dt, forces_ptr, disp_ptr, ctypes.byref(st))
-    _check(s, "pse_sample_with_noise", allow=(PSE_ERR_NOT_CONVERGED,))
+    _check(s, "pse_sample_with_noise", allow=SAMPLE_OK)
     return s, st
 
 
@@ -189,7 +200,7 @@ def pse_real_matvec(ctx, v_ptr, w_ptr):
 def pse_real_sample(ctx, z_ptr, y_ptr):
     st = Stats()
     s = load().pse_real_sample(ctx, z_ptr, y_ptr, ctypes.byref(st))
-    _check(s, "pse_real_sample", allow=(PSE_ERR_NOT_CONVERGED,))
+    _check(s, "pse_real_sample", allow=SAMPLE_OK)
     return s, st
 
 
@@ -203,6 +214,56 @@ def pse_wave_apply(ctx, f_ptr, u_ptr):
 
 def pse_mobility_apply(ctx, f_ptr, u_ptr):
     return _check(load().pse_mobility_apply(ctx, f_ptr, u_ptr), "pse_mobility_apply")
+
+
+def pse_precond_set_weights(ctx, w_bits):
+    """w_bits: numpy uint16 array of MLP_NPARAM bf16 bit patterns (host)."""
+    import numpy as np
+
+    w = np.ascontiguousarray(w_bits, dtype=np.uint16)
+    if w.size != MLP_NPARAM:
+        raise ValueError(f"weights must have {MLP_NPARAM} entries")
+    return _check(load().pse_precond_set_weights(ctx, w.ctypes.data_as(_VP), w.nbytes), "pse_precond_set_weights")
+
+
+def pse_precond_features(ctx, feat_ptr):
+    return _check(load().pse_precond_features(ctx, feat_ptr), "pse_precond_features")
+
+
+def pse_precond_blocks(ctx, P_ptr):
+    nf = ctypes.c_int32(0)
+    _check(load().pse_precond_blocks(ctx, P_ptr, ctypes.byref(nf)), "pse_precond_blocks")
+    return nf.value
+
+
+def pse_precond_targets(params, pos, idx, radius=0.0):
+    """Host FP64 training targets: pos (n, 3) float64, idx int array -> (m, 3, 3)."""
+    import numpy as np
+
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    out = np.empty((len(idx), 9), dtype=np.float64)
+    _check(load().pse_precond_targets(ctypes.byref(params), pos.ctypes.data_as(_VP), idx.ctypes.data_as(_VP),
+                                      len(idx), radius, out.ctypes.data_as(_VP)), "pse_precond_targets")
+    return out.reshape(-1, 3, 3)
+
+
+def pse_mlp_forward(w_ptr, x_ptr, n, y_ptr, cache_ptr=None, stream=None):
+    return _check(load().pse_mlp_forward(w_ptr, x_ptr, n, y_ptr, cache_ptr, _VP(stream or 0)), "pse_mlp_forward")
+
+
+def pse_mlp_backward_workspace(n):
+    return load().pse_mlp_backward_workspace(n)
+
+
+def pse_mlp_backward(w_ptr, x_ptr, cache_ptr, dy_ptr, n, dw_ptr, work_ptr, work_bytes, stream=None):
+    return _check(load().pse_mlp_backward(w_ptr, x_ptr, cache_ptr, dy_ptr, n, dw_ptr, work_ptr, work_bytes,
+                                          _VP(stream or 0)), "pse_mlp_backward")
+
+
+def pse_mlp_adam(wm_ptr, wb_ptr, dw_ptr, m_ptr, v_ptr, lr, t, stream=None):
+    return _check(load().pse_mlp_adam(wm_ptr, wb_ptr, dw_ptr, m_ptr, v_ptr, lr, t, _VP(stream or 0)),
+                  "pse_mlp_adam")
 
 
 def pse_profile(ctx, mask):
@@ -222,7 +283,7 @@ class Sampler:
     the context runs on torch's current stream at construction."""
 
     def __init__(self, n, box, a=1.0, eta=1.0, kT=1.0, xi=0.5, rcut=None, grid=64, support=8, gauss_m=0.0,
-                 tol=1e-4, max_iter=64, precision="fp32", stream=None):
+                 tol=1e-4, max_iter=64, precision="fp32", precond=0, stream=None):
         import torch
 
         self.torch = torch
@@ -233,7 +294,7 @@ class Sampler:
         if rcut is None:
             rcut = 4.0 / xi
         self.params = Params(self.n, box, a, eta, kT, xi, rcut, self.grid, support, gauss_m, tol, max_iter,
-                             PRECISION[precision], 0, 0)
+                             PRECISION[precision], int(precond), 0)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
@@ -305,3 +366,19 @@ class Sampler:
         out = self._new() if out is None else out
         pse_mobility_apply(self.ctx, self._vec(F, "forces"), self._vec(out, "out"))
         return out
+
+    # learned block preconditioner (precond=1)
+    def set_precond_weights(self, w_bits):
+        pse_precond_set_weights(self.ctx, w_bits)
+
+    def precond_features(self, out=None):
+        """(n, 24) bfloat16 features of the current positions (caller order)."""
+        out = self.torch.empty((self.n, 24), dtype=self.torch.bfloat16, device="cuda") if out is None else out
+        pse_precond_features(self.ctx, _ptr(out, self.torch.bfloat16, 24 * self.n, "out"))
+        return out
+
+    def precond_blocks(self, out=None):
+        """((n, 3, 3) float32 blocks in use, number of fallback blocks)."""
+        out = self.torch.empty((self.n, 3, 3), dtype=self.torch.float32, device="cuda") if out is None else out
+        nf = pse_precond_blocks(self.ctx, _ptr(out, self.torch.float32, 9 * self.n, "out"))
+        return out, nf

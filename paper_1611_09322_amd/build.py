@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpse.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["capi.hip", "k_particles.hip", "k_grid.hip", "fg_host.cpp"]
+SOURCES = ["capi.hip", "k_particles.hip", "k_grid.hip", "k_precond.hip", "fg_host.cpp", "precond_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-result", "-I" + os.path.join(ROOT, "include")]
@@ -43,7 +43,7 @@ def build(verbose=False):
     if failed:
         raise RuntimeError("HIP build failed")
     tmp = OUT + ".tmp%d" % os.getpid()
-    subprocess.check_call([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs)
+    subprocess.check_call([HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", "-o", tmp] + objs)
     os.replace(tmp, OUT)
     return OUT
 

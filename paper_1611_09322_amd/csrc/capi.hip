@@ -5,6 +5,8 @@
 // -> B(k) scaling + noise (fused with the x pass) -> inverse FFT ->
 // interpolation; the deterministic and stochastic wave terms share one
 // inverse FFT (Sec. III).
+#include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -45,7 +47,7 @@ void free_ctx(pse_ctx *c) {
   if (!c) return;
   void *dev[] = {c->pos_w, c->pos_s, c->perm, c->cell_of, c->cell_count, c->cell_start, c->nbr, c->nbr_cnt,
                  c->flags, c->V, c->lz, c->partials, c->counter, c->table, c->series, c->grid, c->grid2, c->tw_M,
-                 c->tw_H};
+                 c->tw_H, c->pc_w, c->pc_feat, c->pc_y, c->pc_P, c->pc_Pinv};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   for (void *p : c->vbuf)
@@ -124,12 +126,17 @@ template <typename T, typename A>
 pse_status real_sample_core(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
   launch_lz_init<T, A>(c, z_sorted);
   auto *h = (LzState<A> *)c->lz_h;
+  // without weights every block is I: the plain iteration is the same sample
+  const bool pc = c->pc_on && c->pc_have_w;
   const int maxit = c->p.lanczos_max_iter;
   int launched = 0;
   int chunk = c->last_iters < 2 ? 2 : c->last_iters;
   while (launched < maxit) {
     const int k = chunk < maxit - launched ? chunk : maxit - launched;
-    for (int i = 0; i < k; ++i) launch_lz_iter<T, A>(c, launched + i, z_sorted);
+    for (int i = 0; i < k; ++i) {
+      if (pc) launch_lz_iter_pc<T, A>(c, launched + i, z_sorted);
+      else launch_lz_iter<T, A>(c, launched + i, z_sorted);
+    }
     launched += k;
     if (hipMemcpyAsync(h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
@@ -138,14 +145,17 @@ pse_status real_sample_core(pse_ctx *c, const void *z_sorted, void *y_sorted, ps
     chunk = 1;
   }
   launch_lz_combine<T, A>(c, y_sorted);
+  if (pc) launch_pc_apply_inv<T>(c, y_sorted);  // y = P^-1 A^1/2 z
   c->last_iters = h->m;
   if (stats) {
     stats->lanczos_iters = h->m;
     stats->converged = h->converged;
     stats->lanczos_rel_change = (double)h->rel_change;
+    stats->precond_fallbacks = c->pc_on ? c->pc_fallbacks : 0;
   }
   if (h->nonfinite) return PSE_ERR_NONFINITE;
   if (!h->converged) return PSE_ERR_NOT_CONVERGED;
+  if (c->pc_on && c->pc_fallbacks > 0) return PSE_WARN_PRECOND_FALLBACK;
   return PSE_OK;
 }
 
@@ -204,7 +214,7 @@ pse_status sample_impl(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter,
   }
   if (have_real && cr > 0) {
     st = real_sample_core<T, A>(c, z_s, yr, stats);
-    if (st != PSE_OK && st != PSE_ERR_NOT_CONVERGED) return st;
+    if (st < 0 && st != PSE_ERR_NOT_CONVERGED) return st;  // warnings (> 0) continue
   } else if (stats) {
     stats->lanczos_iters = 0;
     stats->converged = 1;
@@ -308,6 +318,14 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
     std::memcpy(&pairs, c->flags_h + 2, sizeof pairs);
     c->pairs = pairs;
   }
+  if (c->pc_on) {
+    // features came with the neighbour list; network, blocks, fallbacks
+    launch_pc_blocks<T>(c);
+    if (hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return PSE_ERR_HIP;
+    c->pc_fallbacks = c->flags_h[6];
+  }
   c->have_pos = true;
   return hip_status(hipGetLastError());
 }
@@ -324,7 +342,7 @@ template <typename T, typename A>
 pse_status real_sample_impl(pse_ctx *c, const void *z, void *y, pse_stats *stats) {
   launch_gather3<T>(c, z, c->vbuf[0]);
   pse_status st = real_sample_core<T, A>(c, c->vbuf[0], c->vbuf[1], stats);
-  if (st != PSE_OK && st != PSE_ERR_NOT_CONVERGED) return st;
+  if (st < 0 && st != PSE_ERR_NOT_CONVERGED) return st;  // warnings (> 0) continue
   launch_finalize<T>(c, c->vbuf[1], 1.0, nullptr, 0.0, nullptr, y);
   const pse_status se = hip_status(hipGetLastError());
   return se != PSE_OK ? se : st;
@@ -395,7 +413,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   Derived d;
   const pse_status ps = derive_params(*p, &d);
   if (ps != PSE_OK) return ps;
-  if (p->precond != 0) return PSE_ERR_PARAMS;
+  if (p->precond != 0 && p->precond != 1) return PSE_ERR_PARAMS;
   pse_ctx *c = new (std::nothrow) pse_ctx();
   if (!c) return PSE_ERR_OOM;
   c->p = *p;
@@ -430,6 +448,14 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   c->counter = (unsigned *)al.dev(sizeof(unsigned));
   const size_t M3 = (size_t)p->grid * p->grid * p->grid;
   c->grid = al.dev(3 * T * M3);
+  if (p->precond == 1) {
+    c->pc_on = true;
+    c->pc_w = (uint16_t *)al.dev(sizeof(uint16_t) * kWTotal);
+    c->pc_feat = (uint16_t *)al.dev(sizeof(uint16_t) * kNFeat * n);
+    c->pc_y = (float *)al.dev(sizeof(float) * kNOut * n);
+    c->pc_P = al.dev(12 * T * n);
+    c->pc_Pinv = al.dev(12 * T * n);
+  }
   // real-space tables (FP64 host evaluation of Appendix A)
   double serF[kSeriesTerms], serG[kSeriesTerms];
   fg_series_coeffs(p->xi, p->a, serF, serG);
@@ -454,6 +480,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
     e = hipMemcpy(c->table, tab.data(), sizeof(float4) * (kTableK + 1), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipMemset(c->counter, 0, sizeof(unsigned));
+  if (e == hipSuccess && c->pc_w) e = hipMemset(c->pc_w, 0, sizeof(uint16_t) * kWTotal);
   if (e != hipSuccess) {
     free_ctx(c);
     return PSE_ERR_HIP;
@@ -549,6 +576,96 @@ pse_status pse_profile_read(pse_ctx *c, double *ms, int32_t *launches) {
   c->ev_stage.clear();
   c->ev_open = -1;
   return PSE_OK;
+}
+
+pse_status pse_precond_set_weights(pse_ctx *c, const void *w_host, size_t bytes) {
+  if (!c || !w_host) return PSE_ERR_INVALID_ARG;
+  if (!c->pc_on) return PSE_ERR_PARAMS;
+  if (bytes != sizeof(uint16_t) * kWTotal) return PSE_ERR_INVALID_ARG;
+  if (hipMemcpyAsync(c->pc_w, w_host, bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return PSE_ERR_HIP;
+  c->pc_have_w = true;
+  if (!c->have_pos) return PSE_OK;
+  // blocks of the current configuration follow the new weights
+  if (hipMemsetAsync(c->flags + 6, 0, sizeof(int), c->stream) != hipSuccess) return PSE_ERR_HIP;
+  if (c->dbl) launch_pc_blocks<double>(c);
+  else launch_pc_blocks<float>(c);
+  if (hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return PSE_ERR_HIP;
+  c->pc_fallbacks = c->flags_h[6];
+  return hip_status(hipGetLastError());
+}
+
+pse_status pse_precond_features(pse_ctx *c, void *feat_out) {
+  if (!c || !feat_out) return PSE_ERR_INVALID_ARG;
+  if (!c->pc_on) return PSE_ERR_PARAMS;
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  launch_unsort_features(c, feat_out);
+  return hip_status(hipGetLastError());
+}
+
+pse_status pse_precond_blocks(pse_ctx *c, void *P_out, int32_t *fallbacks) {
+  if (!c || !P_out) return PSE_ERR_INVALID_ARG;
+  if (!c->pc_on) return PSE_ERR_PARAMS;
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  if (c->dbl) launch_unsort_blocks<double>(c, (float *)P_out);
+  else launch_unsort_blocks<float>(c, (float *)P_out);
+  if (fallbacks) *fallbacks = c->pc_fallbacks;
+  return hip_status(hipGetLastError());
+}
+
+pse_status pse_precond_targets(const pse_params *p, const double *pos_host, const int32_t *idx, int32_t m,
+                               double radius, double *out) {
+  if (!p || !pos_host || (m > 0 && (!idx || !out)) || m < 0) return PSE_ERR_INVALID_ARG;
+  Derived d;
+  const pse_status ps = derive_params(*p, &d);
+  if (ps != PSE_OK) return ps;
+  if (!(radius > 0)) radius = p->rcut;
+  for (int q = 0; q < m; ++q)
+    if (idx[q] < 0 || idx[q] >= p->n) return PSE_ERR_INVALID_ARG;
+  std::vector<double> x(3 * (size_t)p->n);
+  for (size_t k = 0; k < x.size(); ++k) {
+    if (!std::isfinite(pos_host[k])) return PSE_ERR_NONFINITE;
+    double v = std::fmod(pos_host[k], d.L);
+    x[k] = v < 0 ? v + d.L : v;
+  }
+  double serF[kSeriesTerms], serG[kSeriesTerms];
+  fg_series_coeffs(p->xi, p->a, serF, serG);
+  if (!precond_targets(x.data(), p->n, d.L, p->a, p->xi, p->rcut, d.mu0, serF, serG, idx, m, radius, out))
+    return PSE_ERR_NOT_CONVERGED;
+  return PSE_OK;
+}
+
+pse_status pse_mlp_forward(const void *w, const void *x, int32_t n, void *y, void *act_cache, void *stream) {
+  if (!w || n < 0 || (n > 0 && (!x || !y))) return PSE_ERR_INVALID_ARG;
+  if (((uintptr_t)w | (uintptr_t)x | (uintptr_t)act_cache) & 15) return PSE_ERR_INVALID_ARG;
+  if (n == 0) return PSE_OK;
+  launch_mlp_fwd((const uint16_t *)w, (const uint16_t *)x, n, (float *)y, (uint16_t *)act_cache,
+                 (hipStream_t)stream);
+  return hip_status(hipGetLastError());
+}
+
+size_t pse_mlp_backward_workspace(int32_t n) {
+  return sizeof(float) * kWTotal * (size_t)mlp_bwd_parts(n < 1 ? 1 : n);
+}
+
+pse_status pse_mlp_backward(const void *w, const void *x, const void *act_cache, const void *dy, int32_t n, void *dw,
+                            void *workspace, size_t workspace_bytes, void *stream) {
+  if (!w || !x || !act_cache || !dy || !dw || !workspace || n < 1) return PSE_ERR_INVALID_ARG;
+  if (workspace_bytes < pse_mlp_backward_workspace(n)) return PSE_ERR_INVALID_ARG;
+  launch_mlp_bwd((const uint16_t *)w, (const uint16_t *)x, (const uint16_t *)act_cache, (const float *)dy, n,
+                 (float *)dw, (float *)workspace, (hipStream_t)stream);
+  return hip_status(hipGetLastError());
+}
+
+pse_status pse_mlp_adam(void *w_master, void *w_bf16, const void *dw, void *m, void *v, float lr, int32_t t,
+                        void *stream) {
+  if (!w_master || !w_bf16 || !dw || !m || !v || t < 1 || !(lr >= 0)) return PSE_ERR_INVALID_ARG;
+  launch_mlp_adam((float *)w_master, (uint16_t *)w_bf16, (const float *)dw, (float *)m, (float *)v, lr, t,
+                  (hipStream_t)stream);
+  return hip_status(hipGetLastError());
 }
 
 pse_status pse_mobility_apply(pse_ctx *c, const void *F, void *u) {

@@ -5,28 +5,6 @@
 
 namespace pse {
 
-// ------------------------------------------------------------- reductions
-template <typename A> __device__ __forceinline__ A wave_sum(A v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sum over the block; the result is valid in thread 0.  sh >= 16 entries.
-template <typename A> __device__ __forceinline__ A block_sum(A v, A *sh) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  A r = 0;
-  if (wid == 0) {
-    r = lane < (int)(blockDim.x >> 6) ? sh[lane] : A(0);
-    r = wave_sum(r);
-  }
-  __syncthreads();
-  return r;
-}
-
 template <typename T> __device__ __forceinline__ T wrap_coord(T x, T L, T invL) {
   x = x - L * floor(x * invL);
   if (x >= L || x < T(0)) x = T(0);  // x == L (or rounding just past it) maps to 0
@@ -116,51 +94,6 @@ __global__ void k_gather_pos(const T4 *__restrict__ pos_w, const int *__restrict
   if (s < n) pos_s[s] = pos_w[perm[s]];
 }
 
-// Near-field neighbour list (ELL layout nbr[k * n + s], sorted indices):
-// every t != s with minimum-image distance <= rc, scanning the 27 adjacent
-// cells (fewer when a side has < 3 cells, so no cell is visited twice).
-template <typename T>
-__global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, const int *__restrict__ start, int n,
-                            int nc, T L, T invL, T inv_cs, T rc2, int *__restrict__ nbr, int *__restrict__ cnt_out,
-                            int cap, int *__restrict__ flags) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  int cnt = 0;
-  if (s < n) {
-  const auto p = pos[s];
-  const int cx = min((int)(p.x * inv_cs), nc - 1);
-  const int cy = min((int)(p.y * inv_cs), nc - 1);
-  const int cz = min((int)(p.z * inv_cs), nc - 1);
-  const int lo = nc >= 3 ? -1 : 0, hi = nc >= 2 ? 1 : 0;
-  for (int dx = lo; dx <= hi; ++dx) {
-    const int ax = (cx + dx + nc) % nc;
-    for (int dy = lo; dy <= hi; ++dy) {
-      const int ay = (cy + dy + nc) % nc;
-      for (int dz = lo; dz <= hi; ++dz) {
-        const int c = (ax * nc + ay) * nc + (cz + dz + nc) % nc;
-        const int e = start[c + 1];
-        for (int t = start[c]; t < e; ++t) {
-          if (t == s) continue;
-          const auto q = pos[t];
-          const T ddx = min_image(p.x - q.x, L, invL);
-          const T ddy = min_image(p.y - q.y, L, invL);
-          const T ddz = min_image(p.z - q.z, L, invL);
-          const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          if (r2 <= rc2) {
-            if (cnt < cap) nbr[(size_t)cnt * n + s] = t;
-            ++cnt;
-          }
-        }
-      }
-    }
-  }
-  cnt_out[s] = cnt;
-  atomicMax(&flags[1], cnt);
-  }
-  // total ordered pairs: one 64-bit atomic per wavefront
-  const unsigned long long tot = wave_sum((unsigned long long)cnt);
-  if ((threadIdx.x & 63) == 0 && tot) atomicAdd((unsigned long long *)(flags + 2), tot);
-}
-
 // ------------------------------------------------------- F, G evaluation
 // FP32 modes: linear interpolation in an LDS table of (mu0 F, mu0 (G-F)).
 struct FGTable {
@@ -237,6 +170,126 @@ struct FGExact {
     Dm = (G - F) * mu0;
   }
 };
+
+// ------------------------------------------ learned-preconditioner features
+// 24 geometry features of one particle, accumulated over its neighbours
+// (minimum image, r <= rc; d = x_i - x_j, dh = d / r, dh = 0 at r = 0) with
+// the dimensionless F, G of Appendix A:
+//   0..3   #{r < 2.2a}/4, #{r < 3a}/8, #{r < 4.5a}/16, #{r <= rc}/128
+//   4      sum F / 8
+//   5..10  sum (G - F) dh dh^T (xx, yy, zz, xy, xz, yz)
+//   11..16 sum_{r < 3a} dh dh^T / 4
+//   17..19 sum_{r < 3a} dh / 4
+//   20     sum (G - F)
+//   21     min r / rc (1 without neighbours)
+//   22     sum_{r < 3a} (3a - r) / a / 4
+//   23     F_self (eq. self)
+template <typename T> struct FeatAcc {
+  T f[kNFeat];
+  __device__ __forceinline__ void init(T fself) {
+#pragma unroll
+    for (int k = 0; k < kNFeat; ++k) f[k] = T(0);
+    f[21] = T(1);
+    f[23] = fself;
+  }
+  // one neighbour: separation d, r^2, dimensionless F and G - F
+  __device__ __forceinline__ void add(T dx, T dy, T dz, T r2, T Fd, T Dd, T a, T inv_rc) {
+    const T r = sqrt(r2);
+    const T ir = r > T(0) ? T(1) / r : T(0);
+    const T hx = dx * ir, hy = dy * ir, hz = dz * ir;
+    f[0] += r < T(2.2) * a ? T(0.25) : T(0);
+    const bool nr = r < T(3) * a;
+    f[1] += nr ? T(0.125) : T(0);
+    f[2] += r < T(4.5) * a ? T(0.0625) : T(0);
+    f[3] += T(1.0 / 128);
+    f[4] += Fd * T(0.125);
+    f[5] += Dd * hx * hx;
+    f[6] += Dd * hy * hy;
+    f[7] += Dd * hz * hz;
+    f[8] += Dd * hx * hy;
+    f[9] += Dd * hx * hz;
+    f[10] += Dd * hy * hz;
+    const T q = nr ? T(0.25) : T(0);
+    f[11] += q * hx * hx;
+    f[12] += q * hy * hy;
+    f[13] += q * hz * hz;
+    f[14] += q * hx * hy;
+    f[15] += q * hx * hz;
+    f[16] += q * hy * hz;
+    f[17] += q * hx;
+    f[18] += q * hy;
+    f[19] += q * hz;
+    f[20] += Dd;
+    f[21] = min(f[21], r * inv_rc);
+    f[22] += nr ? (T(3) * a - r) / a * T(0.25) : T(0);
+  }
+  __device__ __forceinline__ void store(uint16_t *__restrict__ out) const {
+    uint32_t w[kNFeat / 2];
+#pragma unroll
+    for (int k = 0; k < kNFeat / 2; ++k)
+      w[k] = (uint32_t)f32_to_bf16((float)f[2 * k]) | ((uint32_t)f32_to_bf16((float)f[2 * k + 1]) << 16);
+    uint4 *o = (uint4 *)out;  // 48 bytes per particle: three 16-byte stores
+    o[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    o[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    o[2] = make_uint4(w[8], w[9], w[10], w[11]);
+  }
+};
+
+// Near-field neighbour list (ELL layout nbr[k * n + s], sorted indices):
+// every t != s with minimum-image distance <= rc, scanning the 27 adjacent
+// cells (fewer when a side has < 3 cells, so no cell is visited twice).
+// With FEAT the learned-preconditioner features of s are accumulated from
+// the same hits (fg gives mu0 F and mu0 (G - F); FeatAcc).
+template <typename T, bool FEAT, typename FG>
+__global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, const int *__restrict__ start, int n,
+                            int nc, T L, T invL, T inv_cs, T rc2, int *__restrict__ nbr, int *__restrict__ cnt_out,
+                            int cap, int *__restrict__ flags, FG fg, T inv_mu0, T fself, T a, T inv_rc,
+                            uint16_t *__restrict__ feat) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  int cnt = 0;
+  if (s < n) {
+  FeatAcc<T> acc;
+  if (FEAT) acc.init(fself);
+  const auto p = pos[s];
+  const int cx = min((int)(p.x * inv_cs), nc - 1);
+  const int cy = min((int)(p.y * inv_cs), nc - 1);
+  const int cz = min((int)(p.z * inv_cs), nc - 1);
+  const int lo = nc >= 3 ? -1 : 0, hi = nc >= 2 ? 1 : 0;
+  for (int dx = lo; dx <= hi; ++dx) {
+    const int ax = (cx + dx + nc) % nc;
+    for (int dy = lo; dy <= hi; ++dy) {
+      const int ay = (cy + dy + nc) % nc;
+      for (int dz = lo; dz <= hi; ++dz) {
+        const int c = (ax * nc + ay) * nc + (cz + dz + nc) % nc;
+        const int e = start[c + 1];
+        for (int t = start[c]; t < e; ++t) {
+          if (t == s) continue;
+          const auto q = pos[t];
+          const T ddx = min_image(p.x - q.x, L, invL);
+          const T ddy = min_image(p.y - q.y, L, invL);
+          const T ddz = min_image(p.z - q.z, L, invL);
+          const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          if (r2 <= rc2) {
+            if (cnt < cap) nbr[(size_t)cnt * n + s] = t;
+            ++cnt;
+            if (FEAT) {
+              T Fm = fself / inv_mu0, Dm = T(0);
+              if (r2 > T(1e-24)) fg.eval(r2, T(1) / sqrt(r2), Fm, Dm);
+              acc.add(ddx, ddy, ddz, r2, Fm * inv_mu0, Dm * inv_mu0, a, inv_rc);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (FEAT) acc.store(feat + (size_t)s * kNFeat);
+  cnt_out[s] = cnt;
+  atomicMax(&flags[1], cnt);
+  }
+  // total ordered pairs: one 64-bit atomic per wavefront
+  const unsigned long long tot = wave_sum((unsigned long long)cnt);
+  if ((threadIdx.x & 63) == 0 && tot) atomicAdd((unsigned long long *)(flags + 2), tot);
+}
 
 // --------------------------------------------------- near-field product
 // One thread per sorted particle s:
@@ -507,11 +560,12 @@ __global__ void k_halo_size(const int *__restrict__ cell_start, int nc, int *__r
   atomicMax(&flags[4], tot);
 }
 
-template <int B, bool UNWRAP>
+template <int B, bool UNWRAP, bool FEAT>
 __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
                                                  int nc, float cs, int n, float L, float invL, float rc2,
                                                  uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
-                                                 int *__restrict__ flags) {
+                                                 int *__restrict__ flags, FGTable fg, float inv_mu0, float fself,
+                                                 float a, float inv_rc, uint16_t *__restrict__ feat) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   extern __shared__ float4 hpos[];
   __shared__ HaloTab ht;
@@ -537,6 +591,8 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
     int k = 0;
     uint64_t lo = 0, hi = 0;  // the current chunk of 8 packed 16-bit indices
     uint4 *row = (uint4 *)nbr;
+    FeatAcc<float> acc;
+    if (FEAT) acc.init(fself);
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dz = -1; dz <= 1; ++dz) {
@@ -548,20 +604,29 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
 #pragma unroll
             for (int u = 0; u < 4; ++u) q[u] = hpos[min(j0 + u, e - 1)];
             unsigned hit = 0;
+            float ddx[4], ddy[4], ddz[4], rr[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              float ddx = p.x - q[u].x, ddy = p.y - q[u].y, ddz = p.z - q[u].z;
+              ddx[u] = p.x - q[u].x;
+              ddy[u] = p.y - q[u].y;
+              ddz[u] = p.z - q[u].z;
               if (!UNWRAP) {
-                ddx = min_image(ddx, L, invL);
-                ddy = min_image(ddy, L, invL);
-                ddz = min_image(ddz, L, invL);
+                ddx[u] = min_image(ddx[u], L, invL);
+                ddy[u] = min_image(ddy[u], L, invL);
+                ddz[u] = min_image(ddz[u], L, invL);
               }
+              rr[u] = ddx[u] * ddx[u] + ddy[u] * ddy[u] + ddz[u] * ddz[u];
               const int j = j0 + u;
-              if (j < e && j != li && ddx * ddx + ddy * ddy + ddz * ddz <= rc2) hit |= 1u << u;
+              if (j < e && j != li && rr[u] <= rc2) hit |= 1u << u;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               if (hit & (1u << u)) {
+                if (FEAT) {
+                  float Fm = fself / inv_mu0, Dm = 0.0f;
+                  if (rr[u] > 1e-24f) fg.eval(rr[u], __frsqrt_rn(rr[u]), Fm, Dm);
+                  acc.add(ddx[u], ddy[u], ddz[u], rr[u], Fm * inv_mu0, Dm * inv_mu0, a, inv_rc);
+                }
                 const int slot = k & 7;
                 const uint64_t v = (uint64_t)(j0 + u) << (16 * (slot & 3));
                 if (slot < 4) lo |= v;
@@ -579,6 +644,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
         }
     if ((k & 7) && (k >> 3) < (cap >> 3))
       row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+    if (FEAT) acc.store(feat + (size_t)s * kNFeat);
     cnt_out[s] = k;
     mine += (unsigned long long)k;
     mx = max(mx, k);
@@ -1083,8 +1149,22 @@ void launch_nbr(pse_ctx *c) {
   const T L = (T)c->d.L, invL = (T)(1.0 / c->d.L), inv_cs = (T)(1.0 / c->d.cs);
   const T rc2 = (T)(c->p.rcut * c->p.rcut);
   ProfScope ps(c, PSE_STAGE_NBR);
-  k_nbr_build<T><<<nblk(n, 128), 128, 0, c->stream>>>((const T4 *)c->pos_s, c->cell_start, n, c->d.nc, L, invL,
-                                                       inv_cs, rc2, c->nbr, c->nbr_cnt, c->nbr_cap, c->flags);
+  const T inv_mu0 = (T)(1.0 / c->d.mu0), fself = (T)(c->d.self_r / c->d.mu0), a = (T)c->p.a,
+          inv_rc = (T)(1.0 / c->p.rcut);
+  auto go = [&](auto kern, auto fg) {
+    kern<<<nblk(n, 128), 128, 0, c->stream>>>((const T4 *)c->pos_s, c->cell_start, n, c->d.nc, L, invL, inv_cs, rc2,
+                                              c->nbr, c->nbr_cnt, c->nbr_cap, c->flags, fg, inv_mu0, fself, a, inv_rc,
+                                              c->pc_feat);
+  };
+  if constexpr (sizeof(T) == 8) {
+    const FGExact fg{c->series, c->p.xi, c->p.a, c->d.mu0, c->small_r2};
+    if (c->pc_on) go(k_nbr_build<double, true, FGExact>, fg);
+    else go(k_nbr_build<double, false, FGExact>, fg);
+  } else {
+    const FGTable fg{c->table, (float)(kTableK / c->p.rcut)};
+    if (c->pc_on) go(k_nbr_build<float, true, FGTable>, fg);
+    else go(k_nbr_build<float, false, FGTable>, fg);
+  }
 }
 
 static int lds_nblocks(int nc, int B) {
@@ -1111,17 +1191,31 @@ void launch_nbr_lds(pse_ctx *c) {
   const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L), rc2 = (float)(c->p.rcut * c->p.rcut);
   auto *nb = (uint16_t *)c->nbr;
   const bool unwrap = c->d.nc >= c->lds_B + 3;
+  const FGTable fg{c->table, (float)(kTableK / c->p.rcut)};
+  const float inv_mu0 = (float)(1.0 / c->d.mu0), fself = (float)(c->d.self_r / c->d.mu0);
   auto go = [&](auto kern) {
     allow_lds(kern, smem);
     kern<<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
-                                                  c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags);
+                                                  c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags, fg,
+                                                  inv_mu0, fself, (float)c->p.a, (float)(1.0 / c->p.rcut),
+                                                  c->pc_feat);
   };
-  if (c->lds_B == 2) {
-    if (unwrap) go(k_nbr_lds<2, true>);
-    else go(k_nbr_lds<2, false>);
+  if (c->pc_on) {
+    if (c->lds_B == 2) {
+      if (unwrap) go(k_nbr_lds<2, true, true>);
+      else go(k_nbr_lds<2, false, true>);
+    } else {
+      if (unwrap) go(k_nbr_lds<1, true, true>);
+      else go(k_nbr_lds<1, false, true>);
+    }
   } else {
-    if (unwrap) go(k_nbr_lds<1, true>);
-    else go(k_nbr_lds<1, false>);
+    if (c->lds_B == 2) {
+      if (unwrap) go(k_nbr_lds<2, true, false>);
+      else go(k_nbr_lds<2, false, false>);
+    } else {
+      if (unwrap) go(k_nbr_lds<1, true, false>);
+      else go(k_nbr_lds<1, false, false>);
+    }
   }
 }
 
@@ -1218,6 +1312,34 @@ void launch_lz_iter(pse_ctx *c, int m, const void *z) {
                                          c->p.lanczos_max_iter);
 }
 
+// Lanczos step on A = P M_r P^T: u = P^T r, t' = M_r u, then the basis
+// vector, A v_m and alpha_m from t' (k_pc_post), then the usual update and
+// check.  The product runs unconditionally; the other kernels skip once the
+// iteration is done.
+template <typename T, typename A>
+void launch_lz_iter_pc(pse_ctx *c, int m, const void *z) {
+  using T4 = typename vec4<T>::type;
+  T4 *V = (T4 *)c->V;
+  T4 *t = (T4 *)c->vbuf[2];
+  T4 *w = (T4 *)c->vbuf[3];
+  T4 *u = (T4 *)c->vbuf[4];
+  T4 *tp = (T4 *)c->vbuf[5];
+  const T4 *src = m == 0 ? (const T4 *)z : w;
+  {
+    ProfScope ps(c, PSE_STAGE_PRECOND);
+    launch_pc_pre<T, A>(c, src, u);
+  }
+  launch_spmv<T, A>(c, u, tp, false, nullptr);
+  ProfScope ps(c, PSE_STAGE_LANCZOS);
+  launch_pc_post<T, A>(c, tp, src, t, V + (size_t)m * c->n);
+  const T4 *vprev = m > 0 ? V + (size_t)(m - 1) * c->n : V;
+  k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>((const T *)t, (const T *)(V + (size_t)m * c->n),
+                                                      (const T *)vprev, (T *)w, 4 * c->n, (LzState<A> *)c->lz,
+                                                      (A *)c->partials);
+  k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, (LzState<A> *)c->lz,
+                                         (A)c->p.lanczos_tol, c->p.lanczos_max_iter);
+}
+
 template <typename T, typename A>
 void launch_lz_combine(pse_ctx *c, void *y) {
   const int len = 4 * c->n;
@@ -1259,6 +1381,7 @@ INST_T(double)
   template void launch_spmv<T, A>(pse_ctx *, const void *, void *, bool, void *); \
   template void launch_lz_init<T, A>(pse_ctx *, const void *);                  \
   template void launch_lz_iter<T, A>(pse_ctx *, int, const void *);             \
+  template void launch_lz_iter_pc<T, A>(pse_ctx *, int, const void *);          \
   template void launch_lz_combine<T, A>(pse_ctx *, void *);
 INST_TA(float, float)
 INST_TA(float, double)

@@ -32,6 +32,21 @@ template <typename T>
 void launch_finalize(pse_ctx *c, const void *yr, double cr, const void *ur, double dt, const void *wv, void *out);
 template <typename T> void launch_real_noise(pse_ctx *c, void *z, uint64_t seed, uint64_t sample);
 
+// learned block preconditioner (k_precond.hip)
+void launch_mlp_fwd(const uint16_t *w, const uint16_t *x, int n, float *y, uint16_t *cache, hipStream_t stream);
+int mlp_bwd_parts(int n);  // fp32 slots of kWTotal needed by launch_mlp_bwd's workspace
+void launch_mlp_bwd(const uint16_t *w, const uint16_t *x, const uint16_t *cache, const float *dy, int n, float *dw,
+                    float *work, hipStream_t stream);
+void launch_mlp_adam(float *wm, uint16_t *wb, const float *g, float *m, float *v, float lr, int t, hipStream_t stream);
+template <typename T> void launch_pc_blocks(pse_ctx *c);           // features -> MLP -> P, P^-1 (fallbacks in flags[6])
+template <typename T, typename A> void launch_pc_pre(pse_ctx *c, const void *src, void *u);  // u = P^T src
+template <typename T, typename A>
+void launch_pc_post(pse_ctx *c, const void *tp, const void *src, void *out, void *vm_out);
+template <typename T> void launch_pc_apply_inv(pse_ctx *c, void *y);  // y = P^-1 y
+void launch_unsort_features(pse_ctx *c, void *out);
+template <typename T> void launch_unsort_blocks(pse_ctx *c, float *out);
+template <typename T, typename A> void launch_lz_iter_pc(pse_ctx *c, int m, const void *z);
+
 // grid side (k_grid.hip)
 //   FftZ:       a = src, b = dst, x = direction (-1 forward R2C, +1 inverse C2R)
 //   FftStrided: b = data, x = axis (0: x, 1: y), y = direction

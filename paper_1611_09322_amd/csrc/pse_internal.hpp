@@ -14,7 +14,13 @@ namespace pse {
 constexpr int kMaxIter = 64;     // Lanczos basis capacity
 constexpr int kTableK = 1024;    // F/G table intervals on [0, rcut]
 constexpr int kSeriesTerms = 16; // small-r series terms of the wave complement
-constexpr int kRedBlock = 256;   // threads per block of reduction kernels
+constexpr int kRedBlock = 256;
+// Learned preconditioner: 24 features, MLP 24 -> 64 -> 64 -> 9.  Weights are
+// one bf16 array: W1 [64][32] (inputs 24..31 zero), b1 [64], W2 [64][64],
+// b2 [64], W3 [16][64] (rows 9..15 zero), b3 [16] (entries 9..15 zero).
+constexpr int kNFeat = 24, kNHid = 64, kNOut = 9;
+constexpr int kW1 = 0, kB1 = kW1 + 64 * 32, kW2 = kB1 + 64, kB2 = kW2 + 64 * 64, kW3 = kB2 + 64,
+              kB3 = kW3 + 16 * 64, kWTotal = kB3 + 16;   // threads per block of reduction kernels
 
 template <typename T> struct vec2;
 template <> struct vec2<float> { using type = float2; };
@@ -23,7 +29,6 @@ template <typename T> struct vec4;
 template <> struct vec4<float> { using type = float4; };
 template <> struct vec4<double> { using type = double4; };
 
-// Lanczos state kept in device memory (A = accumulation precision).
 // Workgroups go to the 8 XCDs round-robin (workgroup b to XCD b % 8), and
 // each XCD has its own L2.  xcd_block renumbers them so that each XCD works
 // through one contiguous range of logical workgroups: neighbouring tiles,
@@ -33,6 +38,44 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// ------------------------------------------------------------- reductions
+template <typename A> __device__ __forceinline__ A wave_sum(A v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  sh >= 16 entries.
+template <typename A> __device__ __forceinline__ A block_sum(A v, A *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  A r = 0;
+  if (wid == 0) {
+    r = lane < (int)(blockDim.x >> 6) ? sh[lane] : A(0);
+    r = wave_sum(r);
+  }
+  __syncthreads();
+  return r;
+}
+
+// bfloat16 <-> float: round to nearest, ties to even; NaN stays NaN.
+__host__ __device__ __forceinline__ uint16_t f32_to_bf16(float x) {
+  uint32_t u;
+  __builtin_memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float x;
+  __builtin_memcpy(&x, &u, 4);
+  return x;
+}
+
+// Lanczos state kept in device memory (A = accumulation precision).
 template <typename A> struct LzState {
   A alpha[kMaxIter];
   A beta[kMaxIter + 1];  // beta[0] = |z|, beta[m+1] couples v_m and v_{m+1}
@@ -75,6 +118,10 @@ double fg_small_r_threshold(double xi, double a);
 void fg_build_table(double xi, double a, double rc, double mu0, const double *serF, const double *serG,
                     float4 *tab);
 pse_status derive_params(const pse_params &p, Derived *d);
+// learned-preconditioner training targets (precond_host.cpp); false if a
+// patch matrix is not positive definite
+bool precond_targets(const double *x, int n, double L, double a, double xi, double rc, double mu0,
+                     const double *serF, const double *serG, const int *idx, int m, double radius, double *out);
 bool fft_size_supported(int M);
 
 }  // namespace pse
@@ -127,4 +174,13 @@ struct pse_ctx {
   int lds_B = 0;
   int hcap = 0;
   int lds_blocks = 0;
+  // learned block preconditioner (params.precond == 1)
+  bool pc_on = false;
+  bool pc_have_w = false;
+  uint16_t *pc_w = nullptr;    // bf16 [kWTotal]
+  uint16_t *pc_feat = nullptr; // bf16 [n][24], sorted order
+  float *pc_y = nullptr;       // [n][9] network output, sorted order
+  void *pc_P = nullptr;        // T [n][12]: rows of P_i as (x, y, z, 0)
+  void *pc_Pinv = nullptr;     // T [n][12]: rows of P_i^-1
+  int pc_fallbacks = 0;        // blocks replaced by I at the last set_positions
 };

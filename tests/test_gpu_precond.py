@@ -1,0 +1,244 @@
+"""Learned block preconditioner on the GPU (through the C ABI) against the
+FP64 oracle: features, the bf16 MFMA network, backward pass and Adam, the
+blocks with their fallback, and the preconditioned Krylov sample
+y = P^-1 (P M_r P^T)^1/2 z with the blocks the GPU used."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lanczos, precond as opc, rpy
+
+pytestmark = pytest.mark.gpu
+
+XI, RC = 0.6, 6.0
+
+
+def host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.float().double().cpu().numpy() if t.dtype == torch.bfloat16 else t.double().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def bits_tensor(bits):
+    import torch
+
+    return torch.tensor(np.asarray(bits, np.uint16).view(np.int16), dtype=torch.int16,
+                        device="cuda").view(torch.bfloat16)
+
+
+def weights(seed, scale):
+    from paper_1611_09322_amd import precond as ppc
+
+    w = opc.init_weights(seed, scale=scale)
+    bits = ppc.bf16_bits(ppc.pack(w))
+    wr = {k: opc.bf16_round(v) for k, v in w.items()}  # what the device uses
+    return bits, wr
+
+
+@pytest.fixture(scope="module")
+def dense():
+    x, L = synth.hard_spheres(600, 0.3, seed=1201, sweeps=20)
+    return x, L, rpy.real_block_dense(x, L, 1.0, 1.0, XI, RC)
+
+
+def sampler(gpu_lib, x, L, precision, precond=1, tol=1e-8):
+    import torch
+
+    grid = 32 if L / 32 <= 0.7 else 64  # keeps eta_SE = 4 xi^2 sigma^2 below 1
+    s = gpu_lib.Sampler(len(x), L, a=1.0, eta=1.0, kT=1.0, xi=XI, rcut=RC, grid=grid, support=8, tol=tol,
+                        max_iter=64, precision=precision, precond=precond)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    s.set_positions(torch.as_tensor(x, dtype=dt, device="cuda"))
+    return s
+
+
+@pytest.mark.parametrize("n,phi,precision", [(600, 0.3, "fp32"), (600, 0.3, "fp64"), (200, 0.3, "fp32"),
+                                             (1000, 0.1, "mixed")])
+def test_features_match_oracle(gpu_lib, n, phi, precision):
+    """LDS-staged build (n = 600, 1000), global build (n = 200: two cells a
+    side) and the FP64 build; bf16 output, so one bf16 ulp is allowed."""
+    x, L = synth.hard_spheres(n, phi, seed=1300 + n, sweeps=10)
+    s = sampler(gpu_lib, x, L, precision)
+    got = host(s.precond_features())
+    ref = opc.features(x, L, 1.0, XI, RC)
+    err = np.abs(got - ref) - (2.0**-7 * np.abs(ref) + 2e-5)
+    print(f"features {precision} n={n}: max excess {err.max():.3e}")
+    assert err.max() <= 0, np.unravel_index(np.argmax(err), err.shape)
+    s.close()
+
+
+@pytest.mark.parametrize("n", [1, 16, 1003])
+def test_mlp_forward_matches_oracle(gpu_lib, n):
+    import torch
+
+    bits, wr = weights(5, 0.25)
+    xf = opc.bf16_round(np.random.default_rng(6).standard_normal((n, 24)))
+    X = bits_tensor(bits_of(xf))
+    w = bits_tensor(bits)
+    y = torch.empty((n, 9), dtype=torch.float32, device="cuda")
+    cache = torch.empty((n, 128), dtype=torch.bfloat16, device="cuda")
+    gpu_lib.pse_mlp_forward(ptr(w), ptr(X), n, ptr(y), ptr(cache))
+    yr, (_, h1, h2) = opc.mlp_forward(wr, xf, bf16=True)
+    e = rel(host(y), yr)
+    hc = host(cache)
+    mism = np.mean(np.abs(np.concatenate([hc[:, :64] - h1, hc[:, 64:] - h2])) > 2.0**-7 * np.abs(
+        np.concatenate([h1, h2])) + 1e-30)
+    print(f"mlp forward n={n}: rel err {e:.2e}, activation mismatches {mism:.2e}")
+    assert e < 3e-3
+    assert mism < 0.01
+
+
+def bits_of(v):
+    from paper_1611_09322_amd import precond as ppc
+
+    return ppc.bf16_bits(v)
+
+
+def ptr(t):
+    import ctypes
+
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def test_mlp_backward_and_adam_match_oracle(gpu_lib):
+    import torch
+    from paper_1611_09322_amd import precond as ppc
+
+    n = 777
+    bits, wr = weights(7, 0.3)
+    xf = opc.bf16_round(np.random.default_rng(8).standard_normal((n, 24)))
+    X, w = bits_tensor(bits_of(xf)), bits_tensor(bits)
+    y = torch.empty((n, 9), dtype=torch.float32, device="cuda")
+    cache = torch.empty((n, 128), dtype=torch.bfloat16, device="cuda")
+    gpu_lib.pse_mlp_forward(ptr(w), ptr(X), n, ptr(y), ptr(cache))
+    dyh = np.random.default_rng(9).standard_normal((n, 9))
+    dy = torch.as_tensor(dyh, dtype=torch.float32, device="cuda")
+    dw = torch.empty(7312, dtype=torch.float32, device="cuda")
+    nb = gpu_lib.pse_mlp_backward_workspace(n)
+    work = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+    gpu_lib.pse_mlp_backward(ptr(w), ptr(X), ptr(cache), ptr(dy), n, ptr(dw), ptr(work), nb)
+    hc = host(cache)
+    g = opc.mlp_backward(wr, (xf, hc[:, :64], hc[:, 64:]), dyh.astype(np.float32).astype(np.float64))
+    gg = ppc.unpack(host(dw))
+    for k in g:
+        e = rel(gg[k], g[k])
+        print(f"grad {k}: rel err {e:.2e}")
+        assert e < 1e-4, k
+    flat = host(dw)
+    assert not np.any(flat[0:2048].reshape(64, 32)[:, 24:]) and not np.any(flat[6272:7296].reshape(16, 64)[9:])
+    # three Adam steps against the oracle's update
+    p0 = ppc.pack(opc.init_weights(10, 0.2)).astype(np.float64)
+    wm = torch.as_tensor(p0, dtype=torch.float32, device="cuda")
+    wb = torch.empty(7312, dtype=torch.bfloat16, device="cuda")
+    m = torch.zeros(7312, dtype=torch.float32, device="cuda")
+    v = torch.zeros(7312, dtype=torch.float32, device="cuda")
+    pr, mr, vr = p0.astype(np.float32).astype(np.float64), np.zeros(7312), np.zeros(7312)
+    for t in (1, 2, 3):
+        gstep = (flat * (1 + 0.1 * t)).astype(np.float32)
+        gd = torch.as_tensor(gstep, device="cuda")
+        gpu_lib.pse_mlp_adam(ptr(wm), ptr(wb), ptr(gd), ptr(m), ptr(v), 1e-2, t)
+        opc.adam_step(pr, gstep.astype(np.float64), mr, vr, t, 1e-2)
+    e = np.max(np.abs(host(wm) - pr))
+    print(f"adam: max abs diff {e:.2e}")
+    assert e < 1e-5
+    np.testing.assert_array_equal(host(wb), opc.bf16_round(host(wm)))
+
+
+@pytest.mark.parametrize("precision,tol,bar", [("fp64", 1e-9, 1e-6), ("mixed", 1e-6, 1e-4), ("fp32", 1e-5, 3e-4)])
+def test_preconditioned_sample_matches_oracle(gpu_lib, dense, precision, tol, bar):
+    """The blocks in use are the oracle's blocks of the GPU network output;
+    the sample is P^-1 (P M_r P^T)^1/2 z with those blocks."""
+    import torch
+
+    x, L, Mr = dense
+    bits, _ = weights(11, 0.06)
+    s = sampler(gpu_lib, x, L, precision, tol=tol)
+    s.set_precond_weights(bits)
+    P, nf = s.precond_blocks()
+    feats = s.precond_features()
+    y = torch.empty((len(x), 9), dtype=torch.float32, device="cuda")
+    gpu_lib.pse_mlp_forward(ptr(bits_tensor(bits)), ptr(feats), len(x), ptr(y))
+    Pref, bad = opc.blocks_from_output(host(y))
+    np.testing.assert_allclose(host(P), Pref, atol=1e-6)
+    assert nf == int(bad.sum())
+    Pg = host(P)
+    assert np.max(np.abs(Pg - np.eye(3)[None])) > 0.05  # a real preconditioner, not I
+    z = synth.normals(12, (len(x), 3))
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    out, st = s.real_sample(torch.as_tensor(z, dtype=dt, device="cuda"))
+    ref = opc.precond_real_sample(Mr, Pg, z.ravel())
+    e = rel(host(out), ref)
+    s0 = sampler(gpu_lib, x, L, precision, precond=0, tol=tol)
+    _, st0 = s0.real_sample(torch.as_tensor(z, dtype=dt, device="cuda"))
+    print(f"precond sample {precision}: rel err {e:.2e}, iterations {st.lanczos_iters} (plain {st0.lanczos_iters}),"
+          f" fallbacks {st.precond_fallbacks}")
+    assert e < bar
+    s.close()
+    s0.close()
+
+
+def test_identity_blocks_reproduce_the_plain_sample(gpu_lib, dense):
+    """No weights: every block is I and the plain iteration runs (bit-equal,
+    with the fallback warning); zero weights: P = I through the
+    preconditioned iteration (equal up to summation order)."""
+    import torch
+    from paper_1611_09322_amd import precond as ppc
+
+    x, L, _ = dense
+    z = torch.as_tensor(synth.normals(13, (len(x), 3)), dtype=torch.float64, device="cuda")
+    plain = sampler(gpu_lib, x, L, "fp64", precond=0)
+    y0, _ = plain.real_sample(z)
+    s = sampler(gpu_lib, x, L, "fp64")
+    y1, st1 = s.real_sample(z)
+    assert st1.precond_fallbacks == len(x)
+    assert torch.equal(y0, y1)
+    zero = {k: np.zeros_like(v) for k, v in opc.init_weights(0).items()}
+    s.set_precond_weights(ppc.bf16_bits(ppc.pack(zero)))
+    P, nf = s.precond_blocks()
+    assert nf == 0 and np.array_equal(host(P), np.tile(np.eye(3), (len(x), 1, 1)))
+    y2, st2 = s.real_sample(z)
+    assert st2.precond_fallbacks == 0
+    assert rel(host(y2), host(y0)) < 1e-13
+    # non-finite weights: every block falls back to I
+    nanw = {k: np.full_like(v, np.nan) for k, v in zero.items()}
+    s.set_precond_weights(ppc.bf16_bits(ppc.pack(nanw)))
+    _, nf = s.precond_blocks()
+    assert nf == len(x)
+    y3, st3 = s.real_sample(z)
+    assert st3.precond_fallbacks == len(x) and rel(host(y3), host(y0)) < 1e-13
+    s.close()
+    plain.close()
+
+
+def test_training_fits_the_targets(gpu_lib):
+    """A few hundred Adam steps on 600 target rows from two configurations
+    cut the training loss by more than half."""
+    import torch
+    from paper_1611_09322_amd import precond as ppc
+
+    tr = ppc.Trainer(torch, seed=1, lr=3e-3)
+    for seed in (1401, 1402):
+        x, L = synth.hard_spheres(600, 0.3, seed=seed, sweeps=20)
+        s = sampler(gpu_lib, x, L, "mixed")
+        tr.add(s, x, np.arange(0, 600, 2, dtype=np.int32))
+        s.close()
+    hist = tr.fit(300)
+    print(f"training loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    assert hist[-1] < 0.5 * hist[0]
+    x, L = synth.hard_spheres(600, 0.3, seed=1403, sweeps=20)
+    s = sampler(gpu_lib, x, L, "mixed", tol=1e-4)
+    s.set_precond_weights(tr.weights_bits())
+    z = torch.as_tensor(synth.normals(14, (len(x), 3)), dtype=torch.float32, device="cuda")
+    _, st = s.real_sample(z)
+    s0 = sampler(gpu_lib, x, L, "mixed", precond=0, tol=1e-4)
+    _, st0 = s0.real_sample(z)
+    print(f"held-out configuration: iterations {st.lanczos_iters} with the trained blocks, {st0.lanczos_iters} plain,"
+          f" fallbacks {st.precond_fallbacks}")
+    assert st.converged and st.precond_fallbacks < len(x) // 10
+    s.close()
+    s0.close()
