@@ -118,6 +118,7 @@ typedef struct {
 const char *pse_status_string(pse_status s);
 
 typedef struct pse_ctx pse_ctx;
+typedef struct pse_batch pse_batch;
 
 /* Create a sampling context for the parameters `p` on HIP stream `stream`
  * (a hipStream_t; NULL = the null stream).  Validates the parameters against
@@ -263,6 +264,38 @@ pse_status pse_mlp_backward(const void *weights_dev, const void *x_dev, const vo
  * t >= 1) on the fp32 master weights, with the bf16 copy rewritten. */
 pse_status pse_mlp_adam(void *w_master_dev, void *w_bf16_dev, const void *dw_dev, void *m_dev, void *v_dev, float lr,
                         int32_t t, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Batches of independent systems (replicas), each with its own parameters
+ * and context.  The library spreads the replicas over up to 8 internal
+ * streams (default priority) and queues each stream's replicas from its own
+ * host thread: the Krylov stopping decision is taken once per stream, not
+ * once per replica, and replicas on different streams overlap on the GPU.
+ * Calls are ordered after prior work on the caller's stream and later work
+ * on that stream waits for them.  Replica r draws its Philox noise with key
+ * seed + r (pse_sample's specification otherwise).
+ * ------------------------------------------------------------------- */
+
+/* n_rep contexts from params[0 .. n_rep-1]; `stream` is the caller's stream. */
+pse_status pse_batch_create(const pse_params *params, int32_t n_rep, void *stream, pse_batch **out);
+pse_status pse_batch_destroy(pse_batch *batch);
+
+/* The context of replica r (owned by the batch; for weights, derived
+ * parameters or single-replica calls, which run on the replica's stream). */
+pse_status pse_batch_replica(pse_batch *batch, int32_t r, pse_ctx **out);
+
+/* pos[r]: device positions of replica r (as pse_set_positions). */
+pse_status pse_batch_set_positions(pse_batch *batch, const void *const *pos);
+
+/* One displacement per replica, as pse_sample: forces may be NULL (no
+ * forces anywhere) or hold NULL entries; disp[r] device outputs; stats
+ * (host, n_rep entries) may be NULL.  Returns the worst status. */
+pse_status pse_batch_sample(pse_batch *batch, uint64_t seed, uint64_t counter, double dt, const void *const *forces,
+                            void *const *disp, pse_stats *stats);
+
+/* GPU milliseconds from the start of the last pse_batch_sample to the end
+ * of each replica's displacement (host array of n_rep; waits for them). */
+pse_status pse_batch_latency(pse_batch *batch, float *ms);
 
 /* GPU-time accounting: for every stage whose bit (1 << pse_stage) is set in
  * stage_mask, each kernel launch of that stage is bracketed by HIP events on

@@ -103,6 +103,13 @@ _SIGS = {
     "pse_mlp_backward_workspace": ([ctypes.c_int32], ctypes.c_size_t),
     "pse_mlp_backward": ([_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "pse_mlp_adam": ([_VP, _VP, _VP, _VP, _VP, ctypes.c_float, ctypes.c_int32, _VP], ctypes.c_int),
+    "pse_batch_create": ([ctypes.POINTER(Params), ctypes.c_int32, _VP, ctypes.POINTER(_VP)], ctypes.c_int),
+    "pse_batch_destroy": ([_VP], ctypes.c_int),
+    "pse_batch_replica": ([_VP, ctypes.c_int32, ctypes.POINTER(_VP)], ctypes.c_int),
+    "pse_batch_set_positions": ([_VP, ctypes.POINTER(_VP)], ctypes.c_int),
+    "pse_batch_sample": ([_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_VP),
+                          ctypes.POINTER(_VP), ctypes.POINTER(Stats)], ctypes.c_int),
+    "pse_batch_latency": ([_VP, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "pse_profile": ([_VP, ctypes.c_uint32], ctypes.c_int),
     "pse_profile_read": ([_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
 }
@@ -266,6 +273,44 @@ def pse_mlp_adam(wm_ptr, wb_ptr, dw_ptr, m_ptr, v_ptr, lr, t, stream=None):
                   "pse_mlp_adam")
 
 
+def pse_batch_create(params_list, stream=None):
+    arr = (Params * len(params_list))(*params_list)
+    b = _VP()
+    _check(load().pse_batch_create(arr, len(params_list), _VP(stream or 0), ctypes.byref(b)), "pse_batch_create")
+    return b
+
+
+def pse_batch_destroy(b):
+    return load().pse_batch_destroy(b)
+
+
+def pse_batch_replica(b, r):
+    c = _VP()
+    _check(load().pse_batch_replica(b, r, ctypes.byref(c)), "pse_batch_replica")
+    return c
+
+
+def pse_batch_set_positions(b, pos_ptrs):
+    arr = (_VP * len(pos_ptrs))(*pos_ptrs)
+    return _check(load().pse_batch_set_positions(b, arr), "pse_batch_set_positions")
+
+
+def pse_batch_sample(b, seed, counter, dt, force_ptrs, disp_ptrs):
+    n = len(disp_ptrs)
+    farr = None if force_ptrs is None else (_VP * n)(*force_ptrs)
+    darr = (_VP * n)(*disp_ptrs)
+    st = (Stats * n)()
+    s = load().pse_batch_sample(b, seed, counter, dt, farr, darr, st)
+    _check(s, "pse_batch_sample", allow=SAMPLE_OK)
+    return s, list(st)
+
+
+def pse_batch_latency(b, n):
+    ms = (ctypes.c_float * n)()
+    _check(load().pse_batch_latency(b, ms), "pse_batch_latency")
+    return list(ms)
+
+
 def pse_profile(ctx, mask):
     return _check(load().pse_profile(ctx, mask), "pse_profile")
 
@@ -382,3 +427,55 @@ class Sampler:
         out = self.torch.empty((self.n, 3, 3), dtype=self.torch.float32, device="cuda") if out is None else out
         nf = pse_precond_blocks(self.ctx, _ptr(out, self.torch.float32, 9 * self.n, "out"))
         return out, nf
+
+
+class Batch:
+    """Independent replicas sampled together (pse_batch_*).  `specs` is a
+    list of dicts with the Sampler keyword arguments plus n and box."""
+
+    def __init__(self, specs, stream=None):
+        import torch
+
+        self.torch = torch
+        self.params = []
+        self.n = []
+        self.dtypes = []
+        for sp in specs:
+            prec = sp.get("precision", "fp32")
+            rc = sp.get("rcut") or 4.0 / sp.get("xi", 0.5)
+            self.params.append(Params(int(sp["n"]), sp["box"], sp.get("a", 1.0), sp.get("eta", 1.0),
+                                      sp.get("kT", 1.0), sp.get("xi", 0.5), rc, int(sp.get("grid", 64)),
+                                      int(sp.get("support", 8)), sp.get("gauss_m", 0.0), sp.get("tol", 1e-4),
+                                      int(sp.get("max_iter", 64)), PRECISION[prec], int(sp.get("precond", 0)), 0))
+            self.n.append(int(sp["n"]))
+            self.dtypes.append(torch.float64 if prec == "fp64" else torch.float32)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.b = pse_batch_create(self.params, stream)
+
+    def close(self):
+        if getattr(self, "b", None):
+            pse_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, ts, name):
+        return [_ptr(t, dt, 3 * n, f"{name}[{r}]") for r, (t, dt, n) in enumerate(zip(ts, self.dtypes, self.n))]
+
+    def set_positions(self, pos):
+        pse_batch_set_positions(self.b, self._ptrs(pos, "positions"))
+
+    def sample(self, seed, counter, dt=1.0, forces=None, out=None):
+        if out is None:
+            out = [self.torch.empty((n, 3), dtype=dt_, device="cuda") for n, dt_ in zip(self.n, self.dtypes)]
+        fp = None if forces is None else self._ptrs(forces, "forces")
+        s, st = pse_batch_sample(self.b, seed, counter, dt, fp, self._ptrs(out, "out"))
+        return out, st
+
+    def latency(self):
+        return pse_batch_latency(self.b, len(self.n))

@@ -9,7 +9,9 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "launch.hpp"
@@ -122,27 +124,39 @@ hipEvent_t next_event(pse_ctx *c) {
 }
 
 // ---------------------------------------------------------- hot path
+// The Krylov sample in two halves.  lz_start launches the first chunk of
+// iterations (as many as the previous sample needed; the kernels stop
+// themselves once converged) and queues the read-back of the state;
+// lz_finish, after the stream has been synchronised, continues one
+// iteration at a time if needed and combines the iterate.  Split so that a
+// batch of contexts needs one synchronisation per stream, not per context.
 template <typename T, typename A>
-pse_status real_sample_core(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
+pse_status lz_start(pse_ctx *c, const void *z_sorted) {
   launch_lz_init<T, A>(c, z_sorted);
+  const bool pc = c->pc_on && c->pc_have_w;  // without weights every block is I
+  const int maxit = c->p.lanczos_max_iter;
+  int k = c->last_iters < 2 ? 2 : c->last_iters;
+  if (k > maxit) k = maxit;
+  for (int i = 0; i < k; ++i) {
+    if (pc) launch_lz_iter_pc<T, A>(c, i, z_sorted);
+    else launch_lz_iter<T, A>(c, i, z_sorted);
+  }
+  c->lz_launched = k;
+  return hip_status(hipMemcpyAsync(c->lz_h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream));
+}
+
+template <typename T, typename A>
+pse_status lz_finish(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
   auto *h = (LzState<A> *)c->lz_h;
-  // without weights every block is I: the plain iteration is the same sample
   const bool pc = c->pc_on && c->pc_have_w;
   const int maxit = c->p.lanczos_max_iter;
-  int launched = 0;
-  int chunk = c->last_iters < 2 ? 2 : c->last_iters;
-  while (launched < maxit) {
-    const int k = chunk < maxit - launched ? chunk : maxit - launched;
-    for (int i = 0; i < k; ++i) {
-      if (pc) launch_lz_iter_pc<T, A>(c, launched + i, z_sorted);
-      else launch_lz_iter<T, A>(c, launched + i, z_sorted);
-    }
-    launched += k;
+  while (!h->done && c->lz_launched < maxit) {
+    if (pc) launch_lz_iter_pc<T, A>(c, c->lz_launched, z_sorted);
+    else launch_lz_iter<T, A>(c, c->lz_launched, z_sorted);
+    ++c->lz_launched;
     if (hipMemcpyAsync(h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
       return PSE_ERR_HIP;
-    if (h->done) break;
-    chunk = 1;
   }
   launch_lz_combine<T, A>(c, y_sorted);
   if (pc) launch_pc_apply_inv<T>(c, y_sorted);  // y = P^-1 A^1/2 z
@@ -157,6 +171,14 @@ pse_status real_sample_core(pse_ctx *c, const void *z_sorted, void *y_sorted, ps
   if (!h->converged) return PSE_ERR_NOT_CONVERGED;
   if (c->pc_on && c->pc_fallbacks > 0) return PSE_WARN_PRECOND_FALLBACK;
   return PSE_OK;
+}
+
+template <typename T, typename A>
+pse_status real_sample_core(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
+  pse_status st = lz_start<T, A>(c, z_sorted);
+  if (st != PSE_OK) return st;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+  return lz_finish<T, A>(c, z_sorted, y_sorted, stats);
 }
 
 // Wave-space velocity/displacement in sorted order into `out`:
@@ -192,53 +214,81 @@ pse_status wave_core(pse_ctx *c, const void *f_sorted, int noise, const void *W,
 }
 
 // Full displacement.  z1: caller-order real noise (device) or null with
-// use_philox; W: grid noise or null.
+// use_philox; W: grid noise or null.  sample_begin queues everything that
+// does not wait for the Krylov stopping decision (noise, the first chunk of
+// Lanczos iterations, M_r F, the whole wave-space part); sample_end, after
+// the stream is synchronised, finishes the Krylov sample and combines.
+struct SampleState {
+  bool real = false;   // a real-space sample is part of this call
+  bool forces = false; // dt M F is part of this call
+  double cr = 0.0;     // sqrt(2 kT dt)
+};
+
 template <typename T, typename A>
-pse_status sample_impl(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter, const void *z1, const void *W,
-                       double dt, const void *forces, void *disp, pse_stats *stats) {
+pse_status sample_begin(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter, const void *z1, const void *W,
+                        double dt, const void *forces, SampleState &ss) {
   if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
-  if (!disp || !(dt >= 0)) return PSE_ERR_INVALID_ARG;
-  const double pi = 3.14159265358979323846;
-  const double cr = std::sqrt(2.0 * c->p.kT * dt);
-  void *z_s = c->vbuf[0], *yr = c->vbuf[1], *wave = c->vbuf[4], *tmp = c->vbuf[5], *f_s = c->vbuf[6],
-       *ur = c->vbuf[7];
-  pse_status st = PSE_OK;
-  bool have_real = false;
+  if (!(dt >= 0)) return PSE_ERR_INVALID_ARG;
+  ss.cr = std::sqrt(2.0 * c->p.kT * dt);
+  void *z_s = c->vbuf[0], *wave = c->vbuf[4], *tmp = c->vbuf[5], *f_s = c->vbuf[6], *ur = c->vbuf[7];
+  ss.real = false;
   if (philox) {
     launch_real_noise<T>(c, tmp, seed, counter);
     launch_gather3<T>(c, tmp, z_s);
-    have_real = true;
+    ss.real = true;
   } else if (z1) {
     launch_gather3<T>(c, z1, z_s);
-    have_real = true;
+    ss.real = true;
   }
-  if (have_real && cr > 0) {
-    st = real_sample_core<T, A>(c, z_s, yr, stats);
-    if (st < 0 && st != PSE_ERR_NOT_CONVERGED) return st;  // warnings (> 0) continue
-  } else if (stats) {
-    stats->lanczos_iters = 0;
-    stats->converged = 1;
-    stats->lanczos_rel_change = 0;
+  ss.real = ss.real && ss.cr > 0;
+  if (ss.real) {
+    const pse_status st = lz_start<T, A>(c, z_s);
+    if (st != PSE_OK) return st;
   }
-  if (forces && dt > 0) {
+  ss.forces = forces && dt > 0;
+  if (ss.forces) {
     launch_gather3<T>(c, forces, f_s);
     launch_spmv<T, A>(c, f_s, ur, false, nullptr);
   }
   const double V = c->d.L * c->d.L * c->d.L;
   const double M3 = (double)c->p.grid * c->p.grid * c->p.grid;
-  WaveCoef wc = wave_coef(c, dt / (c->p.eta * M3), cr / std::sqrt(c->p.eta * V), seed, counter);
-  const int noise = (cr > 0) ? (philox ? 1 : (W ? 2 : 0)) : 0;
-  const pse_status sw = wave_core<T>(c, (forces && dt > 0) ? f_s : nullptr, noise, W, wc, wave);
-  if (sw != PSE_OK) return sw;
-  launch_finalize<T>(c, (have_real && cr > 0) ? yr : nullptr, cr, (forces && dt > 0) ? ur : nullptr, dt, wave, disp);
+  WaveCoef wc = wave_coef(c, dt / (c->p.eta * M3), ss.cr / std::sqrt(c->p.eta * V), seed, counter);
+  const int noise = (ss.cr > 0) ? (philox ? 1 : (W ? 2 : 0)) : 0;
+  return wave_core<T>(c, ss.forces ? f_s : nullptr, noise, W, wc, wave);
+}
+
+template <typename T, typename A>
+pse_status sample_end(pse_ctx *c, const SampleState &ss, double dt, void *disp, pse_stats *stats) {
+  void *z_s = c->vbuf[0], *yr = c->vbuf[1], *wave = c->vbuf[4], *ur = c->vbuf[7];
+  pse_status st = PSE_OK;
+  if (ss.real) {
+    st = lz_finish<T, A>(c, z_s, yr, stats);
+    if (st < 0 && st != PSE_ERR_NOT_CONVERGED) return st;  // warnings (> 0) continue
+  } else if (stats) {
+    stats->lanczos_iters = 0;
+    stats->converged = 1;
+    stats->lanczos_rel_change = 0;
+    stats->precond_fallbacks = 0;
+  }
+  launch_finalize<T>(c, ss.real ? yr : nullptr, ss.cr, ss.forces ? ur : nullptr, dt, wave, disp);
   if (stats) {
     stats->max_neighbors = c->flags_h[1];
     stats->neighbor_pairs = c->pairs;
     stats->nbr_index_bytes = c->lds_B ? 2 : 4;
   }
-  (void)pi;
   const pse_status se = hip_status(hipGetLastError());
   return se != PSE_OK ? se : st;
+}
+
+template <typename T, typename A>
+pse_status sample_impl(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter, const void *z1, const void *W,
+                       double dt, const void *forces, void *disp, pse_stats *stats) {
+  if (!disp) return PSE_ERR_INVALID_ARG;
+  SampleState ss;
+  const pse_status sb = sample_begin<T, A>(c, philox, seed, counter, z1, W, dt, forces, ss);
+  if (sb != PSE_OK) return sb;
+  if (ss.real && hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+  return sample_end<T, A>(c, ss, dt, disp, stats);
 }
 
 #define DISPATCH(ctx, CALL)                                   \
@@ -390,6 +440,89 @@ void prof_end(pse_ctx *c, int stage) {
 }
 }  // namespace pse
 
+// ---------------------------------------------------------------- batches
+// Independent replicas (each its own context) share S streams; one host
+// thread per stream queues its replicas' work, so a batch sample needs one
+// synchronisation per stream (the Krylov stopping decision) instead of one
+// per replica, and the replicas of different streams run concurrently.
+struct pse_batch {
+  std::vector<pse_ctx *> ctx;
+  std::vector<hipStream_t> streams;
+  hipStream_t user = nullptr;
+  int device = 0;
+  hipEvent_t start = nullptr;
+  std::vector<hipEvent_t> done;  // per replica: end of its last sample
+  std::vector<hipEvent_t> join;  // per stream
+};
+
+namespace pse {
+
+static pse_status ctx_begin(pse_ctx *c, uint64_t seed, uint64_t counter, double dt, const void *f, SampleState &ss) {
+  if (c->dbl) return sample_begin<double, double>(c, true, seed, counter, nullptr, nullptr, dt, f, ss);
+  if (c->acc_dbl) return sample_begin<float, double>(c, true, seed, counter, nullptr, nullptr, dt, f, ss);
+  return sample_begin<float, float>(c, true, seed, counter, nullptr, nullptr, dt, f, ss);
+}
+
+static pse_status ctx_end(pse_ctx *c, const SampleState &ss, double dt, void *disp, pse_stats *stats) {
+  if (c->dbl) return sample_end<double, double>(c, ss, dt, disp, stats);
+  if (c->acc_dbl) return sample_end<float, double>(c, ss, dt, disp, stats);
+  return sample_end<float, float>(c, ss, dt, disp, stats);
+}
+
+// Worse of two statuses: any error beats a warning beats OK.
+static pse_status worse(pse_status a, pse_status b) {
+  if (a < 0) return a;
+  if (b < 0) return b;
+  return a > b ? a : b;
+}
+
+// Run fn(stream index, replica) for every replica, one host thread per
+// stream, replicas of a stream in order; returns the worst status.
+template <typename F> static pse_status for_streams(pse_batch *b, F fn) {
+  const int S = (int)b->streams.size(), R = (int)b->ctx.size();
+  std::vector<pse_status> st(S, PSE_OK);
+  std::vector<std::thread> th;
+  for (int q = 0; q < S; ++q)
+    th.emplace_back([&, q] {
+      if (hipSetDevice(b->device) != hipSuccess) {
+        st[q] = PSE_ERR_HIP;
+        return;
+      }
+      st[q] = fn(q, R);
+    });
+  for (auto &t : th) t.join();
+  pse_status w = PSE_OK;
+  for (pse_status x : st) w = worse(w, x);
+  return w;
+}
+
+static pse_status fork(pse_batch *b) {
+  if (hipEventRecord(b->start, b->user) != hipSuccess) return PSE_ERR_HIP;
+  for (hipStream_t s : b->streams)
+    if (hipStreamWaitEvent(s, b->start, 0) != hipSuccess) return PSE_ERR_HIP;
+  return PSE_OK;
+}
+
+static pse_status join(pse_batch *b) {
+  for (size_t q = 0; q < b->streams.size(); ++q)
+    if (hipEventRecord(b->join[q], b->streams[q]) != hipSuccess ||
+        hipStreamWaitEvent(b->user, b->join[q], 0) != hipSuccess)
+      return PSE_ERR_HIP;
+  return PSE_OK;
+}
+
+static void free_batch(pse_batch *b) {
+  if (!b) return;
+  for (pse_ctx *c : b->ctx) free_ctx(c);
+  for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+  if (b->start) (void)hipEventDestroy(b->start);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  delete b;
+}
+
+}  // namespace pse
+
 extern "C" {
 
 const char *pse_status_string(pse_status s) {
@@ -436,7 +569,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   c->nbr_cnt = (int *)al.dev(sizeof(int) * n);
   c->flags = (int *)al.dev(sizeof(int) * 8);
   c->flags_h = (int *)al.host(sizeof(int) * 8);
-  for (auto &v : c->vbuf) v = al.dev(4 * T * n);
+  for (auto &v : c->vbuf) v = al.dev(4 * T * n);  // [8], [9]: preconditioned Lanczos
   c->V = al.dev(4 * T * n * (size_t)(kMaxIter + 1));
   const size_t lzbytes = c->acc_dbl ? sizeof(LzState<double>) : sizeof(LzState<float>);
   c->lz = al.dev(lzbytes);
@@ -575,6 +708,116 @@ pse_status pse_profile_read(pse_ctx *c, double *ms, int32_t *launches) {
   c->ev_used = 0;
   c->ev_stage.clear();
   c->ev_open = -1;
+  return PSE_OK;
+}
+
+pse_status pse_batch_create(const pse_params *p, int32_t n_rep, void *stream, pse_batch **out) {
+  if (!p || !out || n_rep < 1) return PSE_ERR_INVALID_ARG;
+  *out = nullptr;
+  for (int r = 0; r < n_rep; ++r) {
+    Derived d;
+    const pse_status ps = derive_params(p[r], &d);
+    if (ps != PSE_OK) return ps;
+  }
+  pse_batch *b = new (std::nothrow) pse_batch();
+  if (!b) return PSE_ERR_OOM;
+  b->user = (hipStream_t)stream;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return PSE_ERR_HIP;
+  }
+  const int S = std::min(n_rep, 8);
+  b->streams.resize(S, nullptr);
+  b->join.resize(S, nullptr);
+  b->done.resize(n_rep, nullptr);
+  bool ok = hipEventCreate(&b->start) == hipSuccess;
+  for (int q = 0; ok && q < S; ++q)
+    ok = hipStreamCreateWithFlags(&b->streams[q], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->join[q], hipEventDisableTiming) == hipSuccess;
+  for (int r = 0; ok && r < n_rep; ++r) ok = hipEventCreate(&b->done[r]) == hipSuccess;
+  if (!ok) {
+    free_batch(b);
+    return PSE_ERR_HIP;
+  }
+  for (int r = 0; r < n_rep; ++r) {
+    pse_ctx *c = nullptr;
+    const pse_status st = pse_create(&p[r], b->streams[r % S], &c);
+    if (st != PSE_OK) {
+      free_batch(b);
+      return st;
+    }
+    b->ctx.push_back(c);
+  }
+  *out = b;
+  return PSE_OK;
+}
+
+pse_status pse_batch_destroy(pse_batch *b) {
+  if (!b) return PSE_OK;
+  for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+  free_batch(b);
+  return PSE_OK;
+}
+
+pse_status pse_batch_replica(pse_batch *b, int32_t r, pse_ctx **out) {
+  if (!b || !out || r < 0 || r >= (int)b->ctx.size()) return PSE_ERR_INVALID_ARG;
+  *out = b->ctx[r];
+  return PSE_OK;
+}
+
+pse_status pse_batch_set_positions(pse_batch *b, const void *const *pos) {
+  if (!b || !pos) return PSE_ERR_INVALID_ARG;
+  for (size_t r = 0; r < b->ctx.size(); ++r)
+    if (!pos[r]) return PSE_ERR_INVALID_ARG;
+  pse_status st = fork(b);
+  if (st != PSE_OK) return st;
+  const int S = (int)b->streams.size();
+  st = for_streams(b, [&](int q, int R) {
+    pse_status w = PSE_OK;
+    for (int r = q; r < R; r += S) w = worse(w, pse_set_positions(b->ctx[r], pos[r]));
+    return w;
+  });
+  const pse_status sj = join(b);
+  return st != PSE_OK ? st : sj;
+}
+
+pse_status pse_batch_sample(pse_batch *b, uint64_t seed, uint64_t counter, double dt, const void *const *forces,
+                            void *const *disp, pse_stats *stats) {
+  if (!b || !disp) return PSE_ERR_INVALID_ARG;
+  const int R = (int)b->ctx.size(), S = (int)b->streams.size();
+  for (int r = 0; r < R; ++r)
+    if (!disp[r]) return PSE_ERR_INVALID_ARG;
+  pse_status st = fork(b);
+  if (st != PSE_OK) return st;
+  st = for_streams(b, [&](int q, int) {
+    pse_status w = PSE_OK;
+    std::vector<SampleState> ss(R);
+    std::vector<pse_status> sb(R, PSE_OK);
+    bool any_real = false;
+    for (int r = q; r < R; r += S) {
+      sb[r] = ctx_begin(b->ctx[r], seed + (uint64_t)r, counter, dt, forces ? forces[r] : nullptr, ss[r]);
+      any_real = any_real || ss[r].real;
+    }
+    if (any_real && hipStreamSynchronize(b->streams[q]) != hipSuccess) return PSE_ERR_HIP;
+    for (int r = q; r < R; r += S) {
+      pse_status x = sb[r];
+      if (x == PSE_OK) x = ctx_end(b->ctx[r], ss[r], dt, disp[r], stats ? &stats[r] : nullptr);
+      if (hipEventRecord(b->done[r], b->streams[q]) != hipSuccess) x = worse(x, PSE_ERR_HIP);
+      w = worse(w, x);
+    }
+    return w;
+  });
+  const pse_status sj = join(b);
+  return st != PSE_OK ? st : sj;
+}
+
+pse_status pse_batch_latency(pse_batch *b, float *ms) {
+  if (!b || !ms) return PSE_ERR_INVALID_ARG;
+  for (size_t r = 0; r < b->ctx.size(); ++r) {
+    if (hipEventSynchronize(b->done[r]) != hipSuccess ||
+        hipEventElapsedTime(&ms[r], b->start, b->done[r]) != hipSuccess)
+      return PSE_ERR_HIP;
+  }
   return PSE_OK;
 }
 

@@ -511,9 +511,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
   __shared__ int ls0[3][NT];
   __shared__ T lpu[3][NT];
   __shared__ T lf[3][NT];
-  __shared__ int nlist;
-  if (threadIdx.x == 0) nlist = 0;
-  __syncthreads();
+  __shared__ int wcnt[NW];
   // neighbouring tiles read the same cells: keep them on one XCD
   const int lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
                             gridDim.x * gridDim.y * gridDim.z);
@@ -560,13 +558,14 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
       const int n1 = b1 - a1, ntot = n1 + (b2 - a2);
       for (int c0 = 0; c0 < ntot; c0 += NT) {
         const int ci = c0 + (int)threadIdx.x;
+        int t = 0, s0[3] = {0, 0, 0};
+        T pu[3] = {T(0), T(0), T(0)};
+        bool hit = false;
         if (ci < ntot) {
-          const int t = ci < n1 ? a1 + ci : a2 + (ci - n1);
+          t = ci < n1 ? a1 + ci : a2 + (ci - n1);
           const auto q = pos[t];
           const T qc[3] = {q.x, q.y, q.z};
-          int s0[3];
-          T pu[3];
-          bool hit = true;
+          hit = true;
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
             const int b = min((int)(qc[d] * invh), M - 1);
@@ -575,21 +574,32 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
             pu[d] = qc[d] + (T)(t0[d] + dd - b) * h;             // coordinate of that image
             hit = hit && (s0[d] <= tt[d] - 1) && (s0[d] + P - 1 >= 0);
           }
-          if (hit) {
-            const int e = atomicAdd(&nlist, 1);
-            const auto fv = f[t];
+        }
+        // ordered compaction (ballot + prefix over wavefronts): the list,
+        // and with it every summation order, is the candidates' order
+        const unsigned long long bal = __ballot(hit);
+        if (lane == 0) wcnt[wave] = __popcll(bal);
+        __syncthreads();
+        int nl = 0, base = 0;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              ls0[d][e] = s0[d];
-              lpu[d][e] = pu[d];
-            }
-            lf[0][e] = fv.x;
-            lf[1][e] = fv.y;
-            lf[2][e] = fv.z;
+        for (int w = 0; w < NW; ++w) {
+          const int cw = wcnt[w];
+          base += w < wave ? cw : 0;
+          nl += cw;
+        }
+        if (hit) {
+          const int e = base + __popcll(bal & ((1ull << lane) - 1ull));
+          const auto fv = f[t];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            ls0[d][e] = s0[d];
+            lpu[d][e] = pu[d];
           }
+          lf[0][e] = fv.x;
+          lf[1][e] = fv.y;
+          lf[2][e] = fv.z;
         }
         __syncthreads();
-        const int nl = nlist;
         for (int e = 0; e < nl; ++e) {
           const int sz = ls0[2][e];
           if (sz > zw + 7 || sz + P - 1 < zw) continue;  // support misses this wavefront's z slab
@@ -620,9 +630,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
             }
           }
         }
-        __syncthreads();
-        if (threadIdx.x == 0) nlist = 0;
-        __syncthreads();
+        __syncthreads();  // the list and the counts are rewritten next
       }
     }
   }

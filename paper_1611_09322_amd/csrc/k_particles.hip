@@ -192,38 +192,41 @@ template <typename T> struct FeatAcc {
     f[21] = T(1);
     f[23] = fself;
   }
-  // one neighbour: separation d, r^2, dimensionless F and G - F
-  __device__ __forceinline__ void add(T dx, T dy, T dz, T r2, T Fd, T Dd, T a, T inv_rc) {
-    const T r = sqrt(r2);
-    const T ir = r > T(0) ? T(1) / r : T(0);
+  // one neighbour: separation d, r and 1/r (0 at r = 0), dimensionless F
+  // and G - F.  f3 (the count) and the 1/8 of f4 are applied in store().
+  __device__ __forceinline__ void add(T dx, T dy, T dz, T r, T ir, T Fd, T Dd, T a, T inv_rc) {
     const T hx = dx * ir, hy = dy * ir, hz = dz * ir;
     f[0] += r < T(2.2) * a ? T(0.25) : T(0);
-    const bool nr = r < T(3) * a;
-    f[1] += nr ? T(0.125) : T(0);
     f[2] += r < T(4.5) * a ? T(0.0625) : T(0);
-    f[3] += T(1.0 / 128);
-    f[4] += Fd * T(0.125);
-    f[5] += Dd * hx * hx;
-    f[6] += Dd * hy * hy;
-    f[7] += Dd * hz * hz;
-    f[8] += Dd * hx * hy;
-    f[9] += Dd * hx * hz;
-    f[10] += Dd * hy * hz;
-    const T q = nr ? T(0.25) : T(0);
-    f[11] += q * hx * hx;
-    f[12] += q * hy * hy;
-    f[13] += q * hz * hz;
-    f[14] += q * hx * hy;
-    f[15] += q * hx * hz;
-    f[16] += q * hy * hz;
-    f[17] += q * hx;
-    f[18] += q * hy;
-    f[19] += q * hz;
+    f[3] += T(1);
+    f[4] += Fd;
+    const T ex = Dd * hx, ey = Dd * hy, ez = Dd * hz;
+    f[5] += ex * hx;
+    f[6] += ey * hy;
+    f[7] += ez * hz;
+    f[8] += ex * hy;
+    f[9] += ex * hz;
+    f[10] += ey * hz;
     f[20] += Dd;
     f[21] = min(f[21], r * inv_rc);
-    f[22] += nr ? (T(3) * a - r) / a * T(0.25) : T(0);
+    if (r < T(3) * a) {  // close neighbours (a small fraction of the hits)
+      f[1] += T(0.125);
+      const T qx = T(0.25) * hx, qy = T(0.25) * hy, qz = T(0.25) * hz;
+      f[11] += qx * hx;
+      f[12] += qy * hy;
+      f[13] += qz * hz;
+      f[14] += qx * hy;
+      f[15] += qx * hz;
+      f[16] += qy * hz;
+      f[17] += qx;
+      f[18] += qy;
+      f[19] += qz;
+      f[22] += (T(3) * a - r) / a * T(0.25);
+    }
   }
-  __device__ __forceinline__ void store(uint16_t *__restrict__ out) const {
+  __device__ __forceinline__ void store(uint16_t *__restrict__ out) {
+    f[3] *= T(1.0 / 128);
+    f[4] *= T(0.125);
     uint32_t w[kNFeat / 2];
 #pragma unroll
     for (int k = 0; k < kNFeat / 2; ++k)
@@ -273,9 +276,13 @@ __global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, cons
             if (cnt < cap) nbr[(size_t)cnt * n + s] = t;
             ++cnt;
             if (FEAT) {
-              T Fm = fself / inv_mu0, Dm = T(0);
-              if (r2 > T(1e-24)) fg.eval(r2, T(1) / sqrt(r2), Fm, Dm);
-              acc.add(ddx, ddy, ddz, r2, Fm * inv_mu0, Dm * inv_mu0, a, inv_rc);
+              T Fm = fself / inv_mu0, Dm = T(0), r = T(0), ir = T(0);
+              if (r2 > T(1e-24)) {
+                r = sqrt(r2);
+                ir = T(1) / r;
+                fg.eval(r2, ir, Fm, Dm);
+              }
+              acc.add(ddx, ddy, ddz, r, ir, Fm * inv_mu0, Dm * inv_mu0, a, inv_rc);
             }
           }
         }
@@ -569,6 +576,9 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   extern __shared__ float4 hpos[];
   __shared__ HaloTab ht;
+  __shared__ float4 ftab[FEAT ? kTableK + 1 : 1];  // F/G table for the features
+  if (FEAT)
+    for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) ftab[k] = fg.tab[k];
   halo_setup<B>(cell_start, nc, ht);
   if (UNWRAP) {
     const int nb = (nc + B - 1) / B;
@@ -623,9 +633,11 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
             for (int u = 0; u < 4; ++u) {
               if (hit & (1u << u)) {
                 if (FEAT) {
+                  const bool nz = rr[u] > 1e-24f;
+                  const float ir = nz ? __frsqrt_rn(rr[u]) : 0.0f;
                   float Fm = fself / inv_mu0, Dm = 0.0f;
-                  if (rr[u] > 1e-24f) fg.eval(rr[u], __frsqrt_rn(rr[u]), Fm, Dm);
-                  acc.add(ddx[u], ddy[u], ddz[u], rr[u], Fm * inv_mu0, Dm * inv_mu0, a, inv_rc);
+                  if (nz) FGTable{ftab, fg.inv_dr}.eval(rr[u], ir, Fm, Dm);
+                  acc.add(ddx[u], ddy[u], ddz[u], rr[u] * ir, ir, Fm * inv_mu0, Dm * inv_mu0, a, inv_rc);
                 }
                 const int slot = k & 7;
                 const uint64_t v = (uint64_t)(j0 + u) << (16 * (slot & 3));
@@ -667,14 +679,18 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
 // shuffles; each chunk of 8 neighbours is processed branch-free (missing
 // entries are masked) so its LDS reads can all be in flight.  With UNWRAP the
 // staged positions are the images nearest the block centre.
-template <int B, bool UNWRAP, typename A, bool LZ>
+// With PC (Lanczos on A = P M_r P^T): src holds u = P^T r, and the
+// epilogue forms out = P (M_r u) / beta, v_m = r / beta (r from rsrc) and
+// alpha_m = <v_m, out>; Pm holds the rows of P_i as (x, y, z, 0).
+template <int B, bool UNWRAP, typename A, bool LZ, bool PC = false>
 __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
                                                    const int *__restrict__ cell_start, int nc, float cs, int n,
                                                    int hcap, float L, float invL, const uint16_t *__restrict__ nbr,
                                                    const int *__restrict__ cnt, const float4 *__restrict__ tab,
                                                    float inv_dr, float self_r, float scale, float4 *__restrict__ out,
                                                    float4 *__restrict__ vm_out, LzState<A> *st, A *partials,
-                                                   unsigned *counter) {
+                                                   unsigned *counter, const float4 *__restrict__ Pm = nullptr,
+                                                   const float4 *__restrict__ rsrc = nullptr) {
   constexpr int NH = Halo<B>::NH;
   constexpr int G = 3;                      // lanes per target
   constexpr int GPW = 64 / G;               // groups per wavefront (lane 63 idle)
@@ -806,12 +822,23 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
     }
     if (act && g == 0) {
       const float vx = pa.w, vy = pb.x, vz = pb.y;
-      sx = (sx + self_r * vx) * scale;
-      sy = (sy + self_r * vy) * scale;
-      sz = (sz + self_r * vz) * scale;
+      float4 u4;
+      if (PC) {
+        const float tx = sx + self_r * vx, ty = sy + self_r * vy, tz = sz + self_r * vz;
+        const float4 p0 = Pm[3 * (size_t)s], p1 = Pm[3 * (size_t)s + 1], p2 = Pm[3 * (size_t)s + 2];
+        sx = (p0.x * tx + p0.y * ty + p0.z * tz) * scale;
+        sy = (p1.x * tx + p1.y * ty + p1.z * tz) * scale;
+        sz = (p2.x * tx + p2.y * ty + p2.z * tz) * scale;
+        const float4 r = rsrc[s];
+        u4 = make_float4(r.x * scale, r.y * scale, r.z * scale, 0.0f);
+      } else {
+        sx = (sx + self_r * vx) * scale;
+        sy = (sy + self_r * vy) * scale;
+        sz = (sz + self_r * vz) * scale;
+        u4 = make_float4(vx * scale, vy * scale, vz * scale, 0.0f);
+      }
       out[s] = make_float4(sx, sy, sz, 0.0f);
       if (LZ) {
-        const float4 u4 = make_float4(vx * scale, vy * scale, vz * scale, 0.0f);
         vm_out[s] = u4;
         dot += (A)u4.x * (A)sx + (A)u4.y * (A)sy + (A)u4.z * (A)sz;
       }
@@ -883,6 +910,47 @@ __global__ void k_lz_update(const T *__restrict__ t, const T *__restrict__ vm, c
     if (m > 0) x -= be * vprev[i];
     w[i] = x;
     v += (A)x * (A)x;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+// Preconditioned variant, per particle: w as above, and u = P^T w, the
+// source of the next product (P rows as (x, y, z, 0), 12 values each).
+template <typename T, typename A>
+__global__ void k_lz_update_pc(const typename vec4<T>::type *__restrict__ t,
+                               const typename vec4<T>::type *__restrict__ vm,
+                               const typename vec4<T>::type *__restrict__ vprev, typename vec4<T>::type *__restrict__ w,
+                               const T *__restrict__ P, typename vec4<T>::type *__restrict__ u, int n,
+                               LzState<A> *st, A *__restrict__ partials) {
+  __shared__ A sh[16];
+  if (st->done) return;
+  const int m = st->m;
+  const T al = (T)st->alpha[m];
+  const T be = m > 0 ? (T)st->beta[m] : T(0);
+  A v = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const auto a = t[i], b = vm[i];
+    typename vec4<T>::type x;
+    x.x = a.x - al * b.x;
+    x.y = a.y - al * b.y;
+    x.z = a.z - al * b.z;
+    if (m > 0) {
+      const auto c = vprev[i];
+      x.x -= be * c.x;
+      x.y -= be * c.y;
+      x.z -= be * c.z;
+    }
+    x.w = T(0);
+    w[i] = x;
+    v += (A)x.x * (A)x.x + (A)x.y * (A)x.y + (A)x.z * (A)x.z;
+    const T *p = P + (size_t)i * 12;
+    typename vec4<T>::type o;
+    o.x = p[0] * x.x + p[4] * x.y + p[8] * x.z;
+    o.y = p[1] * x.x + p[5] * x.y + p[9] * x.z;
+    o.z = p[2] * x.x + p[6] * x.y + p[10] * x.z;
+    o.w = T(0);
+    u[i] = o;
   }
   v = block_sum(v, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
@@ -1219,8 +1287,9 @@ void launch_nbr_lds(pse_ctx *c) {
   }
 }
 
-template <typename A, bool LZ>
-static void spmv_lds(pse_ctx *c, const float4 *src, float4 *out, float4 *vm_out, LzState<A> *st) {
+template <typename A, bool LZ, bool PC = false>
+static void spmv_lds(pse_ctx *c, const float4 *src, float4 *out, float4 *vm_out, LzState<A> *st,
+                     const float4 *rsrc = nullptr) {
   const size_t smem = (sizeof(float4) + sizeof(float2)) * (size_t)c->hcap;
   const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L);
   const auto *nb = (const uint16_t *)c->nbr;
@@ -1231,14 +1300,14 @@ static void spmv_lds(pse_ctx *c, const float4 *src, float4 *out, float4 *vm_out,
     kernel<<<c->lds_blocks, 1024, smem, c->stream>>>((const float4 *)c->pos_s, src, c->cell_start, c->d.nc,
                                                       (float)c->d.cs, c->n, c->hcap, L, invL, nb, c->nbr_cnt,
                                                       c->table, inv_dr, self_r, 1.0f, out, vm_out, st,
-                                                      (A *)c->partials, c->counter);
+                                                      (A *)c->partials, c->counter, (const float4 *)c->pc_P, rsrc);
   };
   if (c->lds_B == 2) {
-    if (unwrap) go(k_spmv_lds<2, true, A, LZ>);
-    else go(k_spmv_lds<2, false, A, LZ>);
+    if (unwrap) go(k_spmv_lds<2, true, A, LZ, PC>);
+    else go(k_spmv_lds<2, false, A, LZ, PC>);
   } else {
-    if (unwrap) go(k_spmv_lds<1, true, A, LZ>);
-    else go(k_spmv_lds<1, false, A, LZ>);
+    if (unwrap) go(k_spmv_lds<1, true, A, LZ, PC>);
+    else go(k_spmv_lds<1, false, A, LZ, PC>);
   }
 }
 
@@ -1322,9 +1391,31 @@ void launch_lz_iter_pc(pse_ctx *c, int m, const void *z) {
   T4 *V = (T4 *)c->V;
   T4 *t = (T4 *)c->vbuf[2];
   T4 *w = (T4 *)c->vbuf[3];
-  T4 *u = (T4 *)c->vbuf[4];
-  T4 *tp = (T4 *)c->vbuf[5];
+  T4 *u = (T4 *)c->vbuf[8];
+  T4 *tp = (T4 *)c->vbuf[9];
   const T4 *src = m == 0 ? (const T4 *)z : w;
+  if constexpr (sizeof(T) == 4) {
+    if (c->lds_B) {
+      // u = P^T r comes from the previous update (from z at m = 0); P and
+      // alpha_m are applied in the product's epilogue
+      if (m == 0) {
+        ProfScope ps(c, PSE_STAGE_PRECOND);
+        launch_pc_pre<T, A>(c, src, u);
+      }
+      {
+        ProfScope ps(c, PSE_STAGE_SPMV);
+        spmv_lds<A, true, true>(c, (const float4 *)u, (float4 *)t, (float4 *)(V + (size_t)m * c->n),
+                                (LzState<A> *)c->lz, (const float4 *)src);
+      }
+      ProfScope ps(c, PSE_STAGE_LANCZOS);
+      const T4 *vprev = m > 0 ? V + (size_t)(m - 1) * c->n : V;
+      k_lz_update_pc<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * c->n, vprev, w, (const T *)c->pc_P,
+                                                             u, c->n, (LzState<A> *)c->lz, (A *)c->partials);
+      k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, (LzState<A> *)c->lz,
+                                             (A)c->p.lanczos_tol, c->p.lanczos_max_iter);
+      return;
+    }
+  }
   {
     ProfScope ps(c, PSE_STAGE_PRECOND);
     launch_pc_pre<T, A>(c, src, u);

@@ -136,6 +136,7 @@ struct pse_ctx {
   int ncell = 0;
   bool have_pos = false;
   int last_iters = 4;
+  int lz_launched = 0;      // Lanczos iterations launched in the current sample
   // device buffers
   void *pos_w = nullptr;    // T4 [n], caller order, wrapped
   void *pos_s = nullptr;    // T4 [n], sorted
@@ -148,7 +149,7 @@ struct pse_ctx {
   int nbr_cap = 0;
   int *flags = nullptr;     // [0] nonfinite, [1] max neighbours, [2..3] pairs, [4] max halo
   int *flags_h = nullptr;   // pinned copy
-  void *vbuf[8] = {};       // T4 [n] work vectors (sorted order, (x, y, z, 0))
+  void *vbuf[10] = {};      // T4 [n] work vectors (sorted order, (x, y, z, 0))
   void *V = nullptr;        // T4 [(kMaxIter+1) n] Lanczos basis
   void *lz = nullptr;       // LzState<A>
   void *lz_h = nullptr;     // pinned copy

@@ -1,0 +1,74 @@
+"""Batched replicas (pse_batch_*): every replica's displacement equals the
+one its own context gives alone with key seed + r (same kernels, same
+order: bit-identical), one replica against the FP64 oracle, and the
+per-replica completion times."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import sampler
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [(700, 0.1, 64, "fp64"), (1500, 0.3, 64, "mixed"), (300, 0.2, 32, "fp32"), (2500, 0.05, 64, "mixed"),
+         (1000, 0.35, 32, "mixed")]
+
+
+@pytest.fixture(scope="module")
+def systems():
+    out = []
+    for k, (n, phi, M, prec) in enumerate(SPECS):
+        x, L = synth.hard_spheres(n, phi, seed=1500 + k, sweeps=10)
+        out.append(dict(x=x, L=L, spec=dict(n=n, box=L, xi=0.5, rcut=8.0 if L > 16.5 else 0.49 * L, grid=M,
+                                           support=8, tol=1e-6, precision=prec)))
+    return out
+
+
+def test_batch_equals_single_contexts(gpu_lib, systems):
+    import torch
+
+    b = gpu_lib.Batch([s["spec"] for s in systems])
+    dts = [torch.float64 if s["spec"]["precision"] == "fp64" else torch.float32 for s in systems]
+    pos = [torch.as_tensor(s["x"], dtype=dt, device="cuda") for s, dt in zip(systems, dts)]
+    F = [torch.as_tensor(synth.normals(60 + r, (s["spec"]["n"], 3)), dtype=dt, device="cuda")
+         for r, (s, dt) in enumerate(zip(systems, dts))]
+    b.set_positions(pos)
+    out, st = b.sample(77, 3, dt=0.01, forces=F)
+    torch.cuda.synchronize()
+    lat = b.latency()
+    print("batch latencies (ms):", [round(v, 3) for v in lat])
+    assert all(v > 0 for v in lat)
+    for r, s in enumerate(systems):
+        sp = s["spec"]
+        one = gpu_lib.Sampler(sp["n"], sp["box"], xi=sp["xi"], rcut=sp["rcut"], grid=sp["grid"], support=8,
+                              tol=sp["tol"], precision=sp["precision"])
+        one.set_positions(pos[r])
+        ref, st1 = one.sample(77 + r, 3, dt=0.01, forces=F[r])
+        torch.cuda.synchronize()
+        assert torch.equal(out[r], ref), r
+        assert st[r].lanczos_iters == st1.lanczos_iters
+        one.close()
+    # a second call with the same batch reuses every buffer
+    out2, _ = b.sample(77, 4, dt=0.01, forces=F)
+    torch.cuda.synchronize()
+    assert not torch.equal(out2[1], out[1])
+    b.close()
+
+
+def test_batch_replica_matches_oracle(gpu_lib, systems):
+    import torch
+
+    s = systems[0]
+    sp = s["spec"]
+    b = gpu_lib.Batch([t["spec"] for t in systems[:2]])
+    pos = [torch.as_tensor(systems[0]["x"], dtype=torch.float64, device="cuda"),
+           torch.as_tensor(systems[1]["x"], dtype=torch.float32, device="cuda")]
+    b.set_positions(pos)
+    out, st = b.sample(2024, 9, dt=1.0)
+    torch.cuda.synchronize()
+    ref = sampler.displacement_philox(s["x"], sampler.Params(L=s["L"], xi=sp["xi"], rc=sp["rcut"], M=sp["grid"]),
+                                      2024, 9, bits=53)
+    e = np.linalg.norm(out[0].cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"batch replica 0 vs oracle: rel err {e:.2e}")
+    assert e < 1e-4
+    b.close()

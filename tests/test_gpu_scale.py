@@ -1,0 +1,155 @@
+"""Parity at the benchmark's full size (N = 10^6 hard spheres at volume
+fraction 0.3, 256^3 grid, P = 8, xi a = 0.5, rc = 8a, the launch
+configuration bench.py times) on outputs the oracle computes one at a time,
+plus an independent 2000-sphere box at the same volume fraction checked
+against the full oracle.
+
+- near-field rows: brute-force rows of M_r v (exact definition, eq. Mreal);
+- wave-space rows: direct non-uniform Fourier sums with the same k-space noise
+  (zeta = DFT(W)/M^{3/2} of the same grid noise W);
+- the Krylov sample at tol 1e-3 against the same sampler converged in FP64
+  (self-convergence; no dense root exists at this size).
+The structure comes from RSA plus a few Monte Carlo sweeps (the kernels see
+the same sizes, densities and neighbour counts as after 2000 sweeps)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ewald, rpy, sampler
+
+pytestmark = pytest.mark.gpu
+
+N, PHI, M, XI, RC = 1_000_000, 0.3, 256, 0.5, 8.0
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def big():
+    x, L = synth.hard_spheres(N, PHI, a=1.0, seed=1003, sweeps=5)
+    rows = np.random.default_rng(77).choice(N, 48, replace=False)
+    print(f"[scale] N={N} L={L:.3f}", flush=True)
+    return x, L, rows
+
+
+def make(gpu_lib, L, precision, tol=1e-3, n=N, grid=M):
+    return gpu_lib.Sampler(n, L, a=1.0, eta=1.0, kT=1.0, xi=XI, rcut=RC, grid=grid, support=8, tol=tol,
+                           max_iter=64, precision=precision)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32"])
+def test_near_field_rows_at_full_size(gpu_lib, big, precision):
+    import torch
+
+    x, L, rows = big
+    s = make(gpu_lib, L, precision)
+    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    v = synth.normals(31, (N, 3))
+    w = host(s.real_matvec(torch.as_tensor(v, dtype=torch.float32, device="cuda")))
+    ref = rpy.real_matvec_rows(x, v, rows, L, 1.0, 1.0, XI, RC)
+    e = rel(w[rows], ref)
+    print(f"[scale] M_r v rows ({precision}): rel err {e:.2e}")
+    assert e < 1e-5
+    s.close()
+
+
+def se_aliasing_estimate(L, M, xi, P, a=1.0):
+    """Relative error of a spectral-Ewald wave sample from aliasing: the
+    interpolation with the Gaussian window g (std sigma = P h / 2m,
+    m = sqrt(pi P)) sees each grid mode k also at k + 2 pi n / h, with
+    amplitude ratio ghat(k + 2 pi n / h) / ghat(k).  Weighted by B(k) over the
+    k-set, with the first alias shell (n in {-1, 0, 1}^3, n != 0):
+        err^2 ~ sum_k B(k) sum_n (ghat(k + 2 pi n/h) / ghat(k))^2 / sum_k B(k).
+    At h = 0.94a (256^3 in a 240.8a box) the modes near the Nyquist frequency
+    still carry weight and this is ~5e-4; at h = 0.54a it is ~3e-5."""
+    h = L / M
+    s = P * h / (2.0 * np.sqrt(np.pi * P))
+    j = np.fft.fftfreq(M, 1.0 / M)
+    k1 = 2 * np.pi * j / L
+    ok1 = np.abs(j) < M // 2
+    KX, KY, KZ = np.meshgrid(k1, k1, k1, indexing="ij")
+    K2 = KX**2 + KY**2 + KZ**2
+    ok = ok1[:, None, None] & ok1[None, :, None] & ok1[None, None, :] & (K2 > 0)
+    B = np.zeros_like(K2)
+    B[ok] = ewald.B_kernel(K2[ok], a, xi)
+    r2 = lambda k, n: np.exp(-((k + 2 * np.pi * n / h) ** 2 - k**2) * s * s)
+    tot = np.zeros_like(K2)
+    for nx in (-1, 0, 1):
+        for ny in (-1, 0, 1):
+            for nz in (-1, 0, 1):
+                if nx or ny or nz:
+                    tot += r2(KX, nx) * r2(KY, ny) * r2(KZ, nz)
+    return float(np.sqrt((B * tot)[ok].sum() / B[ok].sum()))
+
+
+def test_wave_rows_at_full_size(gpu_lib, big):
+    """Bar: the aliasing error the grid spacing implies (estimated above
+    from the window and B(k) alone, no GPU data), within the 1e-3
+    tolerance of the sampled displacement."""
+    import torch
+
+    x, L, rows = big
+    s = make(gpu_lib, L, "mixed")
+    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    W = np.random.default_rng(32).standard_normal((3, M, M, M)).astype(np.float32)
+    y = host(s.wave_sample(torch.as_tensor(W, device="cuda")))
+    s.close()
+    zeta = ewald.zeta_from_grid_noise(W.astype(np.float64))
+    del W
+    ref = ewald.wave_sample_direct(x[rows[:24]], zeta, L, 1.0, 1.0, XI)
+    e = rel(y[rows[:24]], ref)
+    est = se_aliasing_estimate(L, M, XI, 8)
+    print(f"[scale] wave-space rows: rel err {e:.2e} (aliasing estimate {est:.2e})")
+    assert e < 1e-3
+    assert e < max(1e-4, 1.5 * est)
+
+
+def test_krylov_sample_at_full_size_converges(gpu_lib, big):
+    """The tol-1e-3 mixed sample against the FP64 sampler at tol 1e-8 on the
+    same z: the error of the stopped iterate stays below the tolerance."""
+    import torch
+
+    x, L, _ = big
+    z = synth.normals(33, (N, 3))
+    s = make(gpu_lib, L, "mixed", tol=1e-3)
+    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    y, st = s.real_sample(torch.as_tensor(z, dtype=torch.float32, device="cuda"))
+    y = host(y)
+    s.close()
+    r = make(gpu_lib, L, "fp64", tol=1e-8)
+    r.set_positions(torch.as_tensor(x, dtype=torch.float64, device="cuda"))
+    yr, str_ = r.real_sample(torch.as_tensor(z, dtype=torch.float64, device="cuda"))
+    yr = host(yr)
+    r.close()
+    e = rel(y, yr)
+    print(f"[scale] Krylov sample: {st.lanczos_iters} iterations at tol 1e-3 vs {str_.lanczos_iters} at 1e-8,"
+          f" rel err {e:.2e}")
+    assert st.converged and str_.converged
+    assert e < 1e-3
+
+
+def test_independent_2000_sphere_box_full_oracle(gpu_lib):
+    """N = 2000 at volume fraction 0.3 (L = 30.34a), 64^3 grid (h = 0.47a):
+    the whole displacement with forces, Philox noise on both sides."""
+    import torch
+
+    x, L = synth.hard_spheres(2000, PHI, a=1.0, seed=1099, sweeps=200)
+    F = synth.normals(34, (2000, 3))
+    s = make(gpu_lib, L, "mixed", tol=1e-6, n=2000, grid=64)
+    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    out, st = s.sample(2024, 5, dt=1e-3, forces=torch.as_tensor(F, dtype=torch.float32, device="cuda"))
+    got = host(out)
+    s.close()
+    ref = sampler.displacement_philox(x, sampler.Params(L=L, xi=XI, rc=RC, M=64), 2024, 5, dt=1e-3, forces=F, bits=24)
+    e = rel(got, ref)
+    print(f"[scale] N=2000 box: rel err {e:.2e} ({st.lanczos_iters} iterations)")
+    assert e < 1e-4
