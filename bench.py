@@ -186,6 +186,72 @@ def run_variant(pse, torch, x, L, F, args, variant, weights=None):
     return res
 
 
+def run_batch(pse, torch, args):
+    """Many small independent systems per call (replicas): N log-uniform in
+    [1e3, 2e4], volume fraction uniform in [0.05, 0.35], grid the smallest
+    power of two with h <= 0.65a.  Each step sets new positions and samples
+    every replica; compared with the same replicas sampled one after another
+    through their own contexts.  Grids are capped at 128^3 (h up to 0.93a for
+    the largest dilute boxes)."""
+    import numpy as np
+
+    import synth
+
+    t0 = time.time()
+    rng = np.random.default_rng(20000)
+    specs, pos = [], []
+    for r in range(args.batch_replicas):
+        n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(2e4)))))
+        phi = float(rng.uniform(0.05, 0.35))
+        x, L = synth.hard_spheres(n, phi, a=1.0, seed=20000 + r, sweeps=20)
+        M = next((m for m in (32, 64, 128) if L / m <= 0.65), 128)
+        specs.append(dict(n=n, box=L, xi=args.xi, rcut=args.rc, grid=M, support=args.support, tol=args.tol,
+                          precision="mixed"))
+        pos.append(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    total = sum(sp["n"] for sp in specs)
+    print(f"[bench] batch: {len(specs)} replicas, {total} particles, generated in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    b = pse.Batch(specs)
+    for k in range(args.warmup):
+        b.set_positions(pos)
+        b.sample(11, k, dt=1e-3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.batch_steps):
+        b.set_positions(pos)
+        _, st = b.sample(11, 1000 + k, dt=1e-3)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t1) / args.batch_steps
+    lat = np.array(b.latency())
+    # the same replicas one after another, each through its own context
+    ctxs = [pse.pse_batch_replica(b.b, r) for r in range(len(specs))]
+    outs = [torch.empty((sp["n"], 3), dtype=torch.float32, device="cuda") for sp in specs]
+    seq = []
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for r, c in enumerate(ctxs):
+        ta = time.perf_counter()
+        pse.pse_set_positions(c, pse._ptr(pos[r], torch.float32, 3 * specs[r]["n"], "pos"))
+        pse.pse_sample(c, 11 + r, 2000, 1e-3, None, pse._ptr(outs[r], torch.float32, 3 * specs[r]["n"], "out"))
+        torch.cuda.synchronize()
+        seq.append(1e3 * (time.perf_counter() - ta))
+    dt_s = time.perf_counter() - t2
+    seq = np.array(seq)
+    cum = np.cumsum(seq)
+    b.close()
+    pct = lambda a, q: float(np.percentile(a, q))
+    return {
+        "replicas": len(specs), "particles": total, "steps": args.batch_steps,
+        "grids": {str(m): sum(1 for sp in specs if sp["grid"] == m) for m in (32, 64, 128)},
+        "value": total / dt_b, "unit": "samples·particles/s", "ms_per_step": 1e3 * dt_b,
+        "completion_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "lanczos_iters_mean": float(np.mean([s.lanczos_iters for s in st])),
+        "sequential": {"value": total / dt_s, "ms_per_step": 1e3 * dt_s,
+                       "service_ms": {"p50": pct(seq, 50), "p99": pct(seq, 99)},
+                       "completion_ms": {"p50": pct(cum, 50), "p99": pct(cum, 99)}},
+    }
+
+
 def cpu_baseline(args):
     """The FP64 oracle (dense M_r + eigendecomposition root + direct Fourier
     sums), timed on a bounded sample of the same workload: an independent
@@ -242,6 +308,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=2000, help="Monte Carlo relaxation sweeps after RSA")
     ap.add_argument("--variants", default="fp32,mixed,mixed+precond",
                     help="comma list of fp32, mixed, fp64 and <precision>+precond")
+    ap.add_argument("--batch-replicas", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--train-boxes", type=int, default=2)
     ap.add_argument("--train-n", type=int, default=3000)
     ap.add_argument("--train-rows", type=int, default=500)
@@ -290,6 +359,9 @@ def main():
     roofline["traffic"] = measured_traffic(dom)
     if args.copy_calibration:
         copy_calibration(torch)
+    batched = None if args.no_batch else run_batch(pse, torch, args)
+    if batched:
+        print(f"[bench] batch: {json.dumps(batched)}", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     line = {
         "metric": METRIC,
@@ -319,6 +391,7 @@ def main():
             "boxes": args.train_boxes, "n": args.train_n, "rows_per_box": args.train_rows,
             "epochs": args.train_epochs, "loss_first": train_hist[0], "loss_last": train_hist[-1]},
         "roofline": roofline,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -337,9 +337,11 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
         return PSE_ERR_HIP;
       if (c->flags_h[0]) return PSE_ERR_NONFINITE;
       const int hmax = c->flags_h[4];
-      if (hmax <= 65535 && (sizeof(float4) + sizeof(float2)) * (size_t)hmax + sizeof(float4) * (kTableK + 2) <= kLdsBudget) {
+      // one halo slot more: the zero source read by padding entries
+      if (hmax <= 65535 && (sizeof(float4) + sizeof(float2)) * (size_t)(hmax + 1) + sizeof(float4) * (kTableK + 1) <=
+                               kLdsBudget) {
         c->lds_B = B;
-        c->hcap = hmax > 0 ? hmax : 1;
+        c->hcap = hmax + 1;
         const int nb = (c->d.nc + B - 1) / B;
         c->lds_blocks = nb * nb * nb;
         break;

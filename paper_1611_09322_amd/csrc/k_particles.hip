@@ -697,7 +697,7 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
   extern __shared__ float4 smem[];
   float4 *hA = smem;                        // (x, y, z, v_x)
   float2 *hB = (float2 *)(smem + hcap);     // (v_y, v_z)
-  __shared__ float4 tabs[kTableK + 2];
+  __shared__ float4 tabs[kTableK + 1];
   __shared__ HaloTab ht;
   __shared__ A sh[16];
   __shared__ int last;
@@ -706,20 +706,20 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
     scale = (float)st->inv_beta;
   }
   for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) tabs[k] = tab[k];
-  if (threadIdx.x == 0) tabs[kTableK + 1] = make_float4(self_r, 0.0f, 0.0f, 0.0f);
   halo_setup<B>(cell_start, nc, ht);
   {
-    float cx = 0.f, cy = 0.f, cz = 0.f;
-    if (UNWRAP) {
-      const int nb = (nc + B - 1) / B;
-      const int blk = xcd_block(blockIdx.x, gridDim.x);
-      const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
-      const float c0 = 0.5f * B * cs;
-      cx = bx * B * cs + c0;
-      cy = by * B * cs + c0;
-      cz = bz * B * cs + c0;
-    }
+    const int nb = (nc + B - 1) / B;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
+    const float c0 = 0.5f * B * cs;
+    const float cx = bx * B * cs + c0, cy = by * B * cs + c0, cz = bz * B * cs + c0;
     const int total = ht.base[NH];
+    // slot `total`: a source with zero vector at the block centre, read by
+    // the padding entries of the neighbour chunks (contributes exactly 0)
+    if (threadIdx.x == 0) {
+      hA[total] = make_float4(cx, cy, cz, 0.0f);
+      hB[total] = make_float2(0.0f, 0.0f);
+    }
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int h = halo_cell_of<NH>(ht, e);
       const int gi = ht.start[h] + (e - ht.base[h]);
@@ -758,10 +758,11 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
       if (kb + 8 * G < c) nxt = row[(size_t)((kb >> 3) + G) * n];
       const uint32_t wd[4] = {pk.x, pk.y, pk.z, pk.w};
       int jj[8];
+      const int sentinel = ht.base[NH];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int j = (wd[u >> 1] >> (16 * (u & 1))) & 0xFFFF;
-        jj[u] = kb + u < c ? j : li;  // a missing entry reads the target itself, masked below
+        jj[u] = kb + u < c ? j : sentinel;  // padding reads the zero source
       }
       // all halo reads of the chunk first, then all table reads: two LDS
       // round trips per chunk instead of two per neighbour
@@ -784,15 +785,14 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
           dy[u] = min_image(dy[u], L, invL);
           dz[u] = min_image(dz[u], L, invL);
         }
-        const float r2 = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
-        // coincident spheres take the isotropic r -> 0 limit from the extra
-        // table entry (self_r, 0, 0, 0): every lane reads the table, no branch
-        const bool near0 = !(r2 > 1e-24f);
-        const float rs = __frsqrt_rn(fmaxf(r2, 1e-24f));  // unconditional: no branch around it
-        rinv[u] = near0 ? 0.0f : rs;
+        // r^2 floored at 1e-24: coincident spheres land on table entry 0,
+        // which holds the r -> 0 limit (mu0 F_self, 0), and d = 0 there
+        // makes the (G - F) term vanish; no branch and no select
+        const float r2 = fmaxf(dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u], 1e-24f);
+        rinv[u] = __frsqrt_rn(r2);
         const float uu = r2 * rinv[u] * inv_dr;
-        kk[u] = near0 ? kTableK + 1 : min((int)uu, kTableK - 1);
-        fr[u] = near0 ? 0.0f : uu - (float)kk[u];
+        kk[u] = min((int)uu, kTableK);
+        fr[u] = uu - (float)kk[u];
       }
       float4 e[8];
 #pragma unroll
@@ -800,13 +800,12 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const float wx = q[u].w, wy = wb[u].x, wz = wb[u].y;
-        const float valid = kb + u < c ? 1.0f : 0.0f;
-        const float Fm = valid * fmaf(fr[u], e[u].z, e[u].x);
-        const float Dm = valid * fmaf(fr[u], e[u].w, e[u].y);
+        const float Fm = fmaf(fr[u], e[u].z, e[u].x);
+        const float Dm = fmaf(fr[u], e[u].w, e[u].y);
         const float pr = Dm * rinv[u] * rinv[u] * (dx[u] * wx + dy[u] * wy + dz[u] * wz);
-        ax += Fm * wx + pr * dx[u];
-        ay += Fm * wy + pr * dy[u];
-        az += Fm * wz + pr * dz[u];
+        ax = fmaf(pr, dx[u], fmaf(Fm, wx, ax));
+        ay = fmaf(pr, dy[u], fmaf(Fm, wy, ay));
+        az = fmaf(pr, dz[u], fmaf(Fm, wz, az));
       }
     }
     // combine the G lanes of the target (lanes G grp .. G grp + G - 1)
