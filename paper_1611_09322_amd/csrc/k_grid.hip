@@ -575,20 +575,13 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
             hit = hit && (s0[d] <= tt[d] - 1) && (s0[d] + P - 1 >= 0);
           }
         }
-        // ordered compaction (ballot + prefix over wavefronts): the list,
-        // and with it every summation order, is the candidates' order
+        // ordered compaction: wavefront w packs its hits (ballot + lane
+        // prefix) into list slots [64 w, 64 w + count); the list, and with it
+        // every summation order, follows the candidates' order
         const unsigned long long bal = __ballot(hit);
         if (lane == 0) wcnt[wave] = __popcll(bal);
-        __syncthreads();
-        int nl = 0, base = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          const int cw = wcnt[w];
-          base += w < wave ? cw : 0;
-          nl += cw;
-        }
         if (hit) {
-          const int e = base + __popcll(bal & ((1ull << lane) - 1ull));
+          const int e = 64 * wave + __popcll(bal & ((1ull << lane) - 1ull));
           const auto fv = f[t];
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
@@ -600,7 +593,9 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
           lf[2][e] = fv.z;
         }
         __syncthreads();
-        for (int e = 0; e < nl; ++e) {
+        for (int from = 0; from < NW; ++from) {
+        const int e1 = 64 * from + wcnt[from];
+        for (int e = 64 * from; e < e1; ++e) {
           const int sz = ls0[2][e];
           if (sz > zw + 7 || sz + P - 1 < zw) continue;  // support misses this wavefront's z slab
           const int sx = ls0[0][e], sy = ls0[1][e];
@@ -629,6 +624,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
               acc[2][q] += w * fz;
             }
           }
+        }
         }
         __syncthreads();  // the list and the counts are rewritten next
       }
