@@ -205,10 +205,11 @@ pse_status pse_mobility_apply(pse_ctx *ctx, const void *forces_dev, void *u_dev)
  *   5..10  sum (G - F) dh dh^T        (xx, yy, zz, xy, xz, yz)
  *   11..16 sum_{r < 3a} dh dh^T / 4   (same order)
  *   17..19 sum_{r < 3a} dh / 4
- *   20     sum (G - F);  21  min r / rc (1 without neighbours)
+ *   20     sum (G - F);  21  min r / 4.5a (1 without near neighbours)
  *   22     sum_{r < 3a} (3a - r) / a / 4;  23  F_self (eq. self)
- * over neighbours j (minimum image, r <= rc, d = x_i - x_j, dh = d / r or 0
- * at r = 0), F and G the dimensionless functions of Appendix A.
+ * over near neighbours j (minimum image, r < 4.5a; f3 alone counts all
+ * within rc; d = x_i - x_j, dh = d / r or 0 at r = 0), F and G the
+ * dimensionless functions of Appendix A.
  * A block falls back to I if it is not finite, |det P_i| < 1e-6 or
  * |P_i|_F |P_i^{-1}|_F > 1e3.  Without weights every block is I (global
  * fallback).  Sampling calls return PSE_WARN_PRECOND_FALLBACK when any block

@@ -16,9 +16,10 @@ preconditioner; the features, the network and the training target below are
 this library's definitions (stated in the design notes), restated here in
 plain FP64 so that the device kernels can be checked against them.
 
-Features of particle i, over its neighbours j (minimum image, 0 <= r <= rc,
-d = x_i - x_j, r = |d|, dh = d / r, and dh = 0 when r = 0), with F, G the
-dimensionless Appendix A functions:
+Features of particle i, over its near neighbours j (minimum image,
+0 <= r < 4.5a, d = x_i - x_j, r = |d|, dh = d / r, and dh = 0 when r = 0),
+with F, G the dimensionless Appendix A functions; only f3 counts every
+neighbour within rc:
 
     f0..f3    #{r < 2.2a} / 4, #{r < 3a} / 8, #{r < 4.5a} / 16, #{r <= rc} / 128
     f4        sum F(r) / 8
@@ -26,7 +27,7 @@ dimensionless Appendix A functions:
     f11..f16  sum_{r < 3a} dh dh^T      (xx, yy, zz, xy, xz, yz) / 4
     f17..f19  sum_{r < 3a} dh           / 4
     f20       sum (G - F)(r)
-    f21       min(r) / rc  (1 if there is no neighbour)
+    f21       min(r) / 4.5a  (1 if there is no near neighbour)
     f22       sum_{r < 3a} (3a - r) / a / 4
     f23       F_self (eq. self)
 
@@ -68,6 +69,8 @@ def features(x, L, a, xi, rc):
         d -= L * np.round(d / L)
         r = np.sqrt(np.einsum("nk,nk->n", d, d))
         sel = (r <= rc) & (np.arange(N) != i)
+        nall = int(np.sum(sel))
+        sel &= r < 4.5 * a
         d, r = d[sel], r[sel]
         F, G = rpy.real_FG(r, xi, a) if len(r) else (np.zeros(0), np.zeros(0))
         with np.errstate(invalid="ignore", divide="ignore"):
@@ -79,13 +82,13 @@ def features(x, L, a, xi, rc):
         f[i, 0] = np.sum(r < 2.2 * a) / 4.0
         f[i, 1] = np.sum(near) / 8.0
         f[i, 2] = np.sum(r < 4.5 * a) / 16.0
-        f[i, 3] = len(r) / 128.0
+        f[i, 3] = nall / 128.0
         f[i, 4] = np.sum(F) / 8.0
         f[i, 5:11] = comps(G - F, dh)
         f[i, 11:17] = comps(near.astype(np.float64), dh) / 4.0
         f[i, 17:20] = np.sum(dh[near], axis=0) / 4.0
         f[i, 20] = np.sum(G - F)
-        f[i, 21] = (np.min(r) / rc) if len(r) else 1.0
+        f[i, 21] = (np.min(r) / (4.5 * a)) if len(r) else 1.0
         f[i, 22] = np.sum((3.0 * a - r[near]) / a) / 4.0
         f[i, 23] = Fs
     return f

@@ -172,16 +172,17 @@ struct FGExact {
 };
 
 // ------------------------------------------ learned-preconditioner features
-// 24 geometry features of one particle, accumulated over its neighbours
-// (minimum image, r <= rc; d = x_i - x_j, dh = d / r, dh = 0 at r = 0) with
-// the dimensionless F, G of Appendix A:
+// 24 geometry features of one particle, accumulated over its near
+// neighbours (minimum image, r < 4.5a; d = x_i - x_j, dh = d / r, dh = 0 at
+// r = 0) with the dimensionless F, G of Appendix A; f3 alone counts every
+// neighbour within rc:
 //   0..3   #{r < 2.2a}/4, #{r < 3a}/8, #{r < 4.5a}/16, #{r <= rc}/128
 //   4      sum F / 8
 //   5..10  sum (G - F) dh dh^T (xx, yy, zz, xy, xz, yz)
 //   11..16 sum_{r < 3a} dh dh^T / 4
 //   17..19 sum_{r < 3a} dh / 4
 //   20     sum (G - F)
-//   21     min r / rc (1 without neighbours)
+//   21     min r / 4.5a (1 without near neighbours)
 //   22     sum_{r < 3a} (3a - r) / a / 4
 //   23     F_self (eq. self)
 template <typename T> struct FeatAcc {
@@ -192,13 +193,13 @@ template <typename T> struct FeatAcc {
     f[21] = T(1);
     f[23] = fself;
   }
-  // one neighbour: separation d, r and 1/r (0 at r = 0), dimensionless F
-  // and G - F.  f3 (the count) and the 1/8 of f4 are applied in store().
-  __device__ __forceinline__ void add(T dx, T dy, T dz, T r, T ir, T Fd, T Dd, T a, T inv_rc) {
+  // one near neighbour (r < 4.5a): separation d, r and 1/r (0 at r = 0),
+  // dimensionless F and G - F.  The 1/8 of f4 is applied in store(), f3
+  // comes from the neighbour count there.
+  __device__ __forceinline__ void add(T dx, T dy, T dz, T r, T ir, T Fd, T Dd, T a, T inv_near) {
     const T hx = dx * ir, hy = dy * ir, hz = dz * ir;
     f[0] += r < T(2.2) * a ? T(0.25) : T(0);
-    f[2] += r < T(4.5) * a ? T(0.0625) : T(0);
-    f[3] += T(1);
+    f[2] += T(0.0625);
     f[4] += Fd;
     const T ex = Dd * hx, ey = Dd * hy, ez = Dd * hz;
     f[5] += ex * hx;
@@ -208,7 +209,7 @@ template <typename T> struct FeatAcc {
     f[9] += ex * hz;
     f[10] += ey * hz;
     f[20] += Dd;
-    f[21] = min(f[21], r * inv_rc);
+    f[21] = min(f[21], r * inv_near);
     if (r < T(3) * a) {  // close neighbours (a small fraction of the hits)
       f[1] += T(0.125);
       const T qx = T(0.25) * hx, qy = T(0.25) * hy, qz = T(0.25) * hz;
@@ -224,8 +225,8 @@ template <typename T> struct FeatAcc {
       f[22] += (T(3) * a - r) / a * T(0.25);
     }
   }
-  __device__ __forceinline__ void store(uint16_t *__restrict__ out) {
-    f[3] *= T(1.0 / 128);
+  __device__ __forceinline__ void store(uint16_t *__restrict__ out, int count) {
+    f[3] = T(count) * T(1.0 / 128);
     f[4] *= T(0.125);
     uint32_t w[kNFeat / 2];
 #pragma unroll
@@ -275,21 +276,21 @@ __global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, cons
           if (r2 <= rc2) {
             if (cnt < cap) nbr[(size_t)cnt * n + s] = t;
             ++cnt;
-            if (FEAT) {
+            if (FEAT && r2 < T(20.25) * a * a) {  // near shell r < 4.5a
               T Fm = fself / inv_mu0, Dm = T(0), r = T(0), ir = T(0);
               if (r2 > T(1e-24)) {
                 r = sqrt(r2);
                 ir = T(1) / r;
                 fg.eval(r2, ir, Fm, Dm);
               }
-              acc.add(ddx, ddy, ddz, r, ir, Fm * inv_mu0, Dm * inv_mu0, a, inv_rc);
+              acc.add(ddx, ddy, ddz, r, ir, Fm * inv_mu0, Dm * inv_mu0, a, T(1) / (T(4.5) * a));
             }
           }
         }
       }
     }
   }
-  if (FEAT) acc.store(feat + (size_t)s * kNFeat);
+  if (FEAT) acc.store(feat + (size_t)s * kNFeat, cnt);
   cnt_out[s] = cnt;
   atomicMax(&flags[1], cnt);
   }
@@ -632,12 +633,12 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               if (hit & (1u << u)) {
-                if (FEAT) {
+                if (FEAT && rr[u] < 20.25f * a * a) {  // near shell r < 4.5a
                   const bool nz = rr[u] > 1e-24f;
                   const float ir = nz ? __frsqrt_rn(rr[u]) : 0.0f;
                   float Fm = fself / inv_mu0, Dm = 0.0f;
                   if (nz) FGTable{ftab, fg.inv_dr}.eval(rr[u], ir, Fm, Dm);
-                  acc.add(ddx[u], ddy[u], ddz[u], rr[u] * ir, ir, Fm * inv_mu0, Dm * inv_mu0, a, inv_rc);
+                  acc.add(ddx[u], ddy[u], ddz[u], rr[u] * ir, ir, Fm * inv_mu0, Dm * inv_mu0, a, 1.0f / (4.5f * a));
                 }
                 const int slot = k & 7;
                 const uint64_t v = (uint64_t)(j0 + u) << (16 * (slot & 3));
@@ -656,7 +657,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
         }
     if ((k & 7) && (k >> 3) < (cap >> 3))
       row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
-    if (FEAT) acc.store(feat + (size_t)s * kNFeat);
+    if (FEAT) acc.store(feat + (size_t)s * kNFeat, k);
     cnt_out[s] = k;
     mine += (unsigned long long)k;
     mx = max(mx, k);

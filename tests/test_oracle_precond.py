@@ -25,13 +25,25 @@ def test_pair_features_closed_form():
     exp0[11] = 1 / 4             # dh_x dh_x for r < 3a
     exp0[17] = +1 / 4            # dh = (x0 - x1)/r = +e_x
     exp0[20] = G - F
-    exp0[21] = r / RC
+    exp0[21] = r / 4.5
     exp0[22] = (3 - r) / 4
     exp0[23] = rpy.real_self(XI, A)
     np.testing.assert_allclose(f[0], exp0, atol=1e-15)
     exp1 = exp0.copy()
     exp1[17] = -1 / 4
     np.testing.assert_allclose(f[1], exp1, atol=1e-15)
+
+
+def test_features_count_far_neighbours_only_in_f3():
+    """A neighbour at 5a (inside rc = 6a, outside the 4.5a near shell) enters
+    f3 alone."""
+    x = np.array([[5.0, 5.0, 5.0], [10.0, 5.0, 5.0]])
+    f = precond.features(x, L, A, XI, RC)
+    exp = np.zeros(24)
+    exp[3] = 1 / 128
+    exp[21] = 1.0
+    exp[23] = rpy.real_self(XI, A)
+    np.testing.assert_allclose(f, np.stack([exp, exp]), atol=1e-15)
 
 
 def test_features_isolated_particle():
