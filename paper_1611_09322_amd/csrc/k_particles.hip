@@ -717,8 +717,10 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
     const int total = ht.base[NH];
     // slot `total`: a source with zero vector at the block centre, read by
     // the padding entries of the neighbour chunks (contributes exactly 0)
+    // coordinates are staged in units of the table spacing rc / kTableK:
+    // r is then the table coordinate itself (the (G - F) term is invariant)
     if (threadIdx.x == 0) {
-      hA[total] = make_float4(cx, cy, cz, 0.0f);
+      hA[total] = make_float4(cx * inv_dr, cy * inv_dr, cz * inv_dr, 0.0f);
       hB[total] = make_float2(0.0f, 0.0f);
     }
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
@@ -731,6 +733,9 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
         q.y = cy + min_image(q.y - cy, L, invL);
         q.z = cz + min_image(q.z - cz, L, invL);
       }
+      q.x *= inv_dr;
+      q.y *= inv_dr;
+      q.z *= inv_dr;
       q.w = v.x;
       hA[e] = q;
       hB[e] = make_float2(v.y, v.z);
@@ -738,6 +743,7 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
   }
   __syncthreads();
   const int ntarg = ht.tpre[ht.ntc];
+  const float Ls = L * inv_dr, invLs = invL / inv_dr;  // box in table units
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / G, g = lane - grp * G;
   const bool ingrp = grp < GPW;
@@ -782,18 +788,18 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
         dy[u] = pa.y - q[u].y;
         dz[u] = pa.z - q[u].z;
         if (!UNWRAP) {
-          dx[u] = min_image(dx[u], L, invL);
-          dy[u] = min_image(dy[u], L, invL);
-          dz[u] = min_image(dz[u], L, invL);
+          dx[u] = min_image(dx[u], Ls, invLs);
+          dy[u] = min_image(dy[u], Ls, invLs);
+          dz[u] = min_image(dz[u], Ls, invLs);
         }
-        // r^2 floored at 1e-24: coincident spheres land on table entry 0,
+        // r^2 floored at 1e-20 (table units): coincident spheres land on table entry 0,
         // which holds the r -> 0 limit (mu0 F_self, 0), and d = 0 there
         // makes the (G - F) term vanish; no branch and no select
-        const float r2 = fmaxf(dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u], 1e-24f);
+        const float r2 = fmaxf(dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u], 1e-20f);
         rinv[u] = __frsqrt_rn(r2);
-        const float uu = r2 * rinv[u] * inv_dr;
+        const float uu = r2 * rinv[u];  // r in table units
         kk[u] = min((int)uu, kTableK);
-        fr[u] = uu - (float)kk[u];
+        fr[u] = __builtin_amdgcn_fractf(uu);
       }
       float4 e[8];
 #pragma unroll
