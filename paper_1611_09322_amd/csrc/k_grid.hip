@@ -511,7 +511,8 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
   __shared__ int ls0[3][NT];
   __shared__ T lpu[3][NT];
   __shared__ T lf[3][NT];
-  __shared__ int wcnt[NW];
+  __shared__ uint16_t sidx[NW][NT];  // per z slab: list entries whose support reaches it
+  __shared__ int scnt[NW][NW];       // [slab][wavefront that listed them]
   // neighbouring tiles read the same cells: keep them on one XCD
   const int lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
                             gridDim.x * gridDim.y * gridDim.z);
@@ -576,12 +577,22 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
           }
         }
         // ordered compaction: wavefront w packs its hits (ballot + lane
-        // prefix) into list slots [64 w, 64 w + count); the list, and with it
-        // every summation order, follows the candidates' order
+        // prefix) into list slots [64 w, 64 w + count), and every z slab
+        // gets the indices of the entries whose support reaches it (at most
+        // ceil((P + 7) / 8) slabs each); lists and summation orders follow
+        // the candidates' order
+        const unsigned long long below = (1ull << lane) - 1ull;
         const unsigned long long bal = __ballot(hit);
-        if (lane == 0) wcnt[wave] = __popcll(bal);
+        const int e = 64 * wave + __popcll(bal & below);
+        const int slo = s0[2] > 0 ? s0[2] >> 3 : 0, shi = min(NW - 1, (s0[2] + P - 1) >> 3);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const bool inw = hit && w >= slo && w <= shi;
+          const unsigned long long bw = __ballot(inw);
+          if (lane == 0) scnt[w][wave] = __popcll(bw);
+          if (inw) sidx[w][64 * wave + __popcll(bw & below)] = (uint16_t)e;
+        }
         if (hit) {
-          const int e = 64 * wave + __popcll(bal & ((1ull << lane) - 1ull));
           const auto fv = f[t];
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
@@ -594,10 +605,10 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
         }
         __syncthreads();
         for (int from = 0; from < NW; ++from) {
-        const int e1 = 64 * from + wcnt[from];
-        for (int e = 64 * from; e < e1; ++e) {
+        const int nf = scnt[wave][from];
+        for (int k = 0; k < nf; ++k) {
+          const int e = sidx[wave][64 * from + k];
           const int sz = ls0[2][e];
-          if (sz > zw + 7 || sz + P - 1 < zw) continue;  // support misses this wavefront's z slab
           const int sx = ls0[0][e], sy = ls0[1][e];
           // lanes 0..3P-1: the separable weights along x, y, z
           T wv = T(0);
