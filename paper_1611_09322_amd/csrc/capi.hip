@@ -48,7 +48,7 @@ inline size_t asize(const pse_ctx *c) { return c->acc_dbl ? 8 : 4; }
 void free_ctx(pse_ctx *c) {
   if (!c) return;
   void *dev[] = {c->pos_w, c->pos_s, c->perm, c->cell_of, c->cell_count, c->cell_start, c->nbr, c->nbr_cnt,
-                 c->flags, c->V, c->lz, c->partials, c->counter, c->table, c->series, c->grid, c->grid2, c->tw_M,
+                 c->flags, c->V, c->lz, c->partials, c->counter, c->table, c->series, c->grid, c->rgrid, c->grid2, c->tw_M,
                  c->tw_H, c->pc_w, c->pc_feat, c->pc_y, c->pc_P, c->pc_Pinv};
   for (void *p : dev)
     if (p) (void)hipFree(p);
@@ -202,14 +202,14 @@ pse_status wave_core(pse_ctx *c, const void *f_sorted, int noise, const void *W,
     launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid2, nullptr, 0, -1);
   }
   if (f_sorted) {
-    launch_spread_interp<T>(c, true, f_sorted, c->grid);
-    launch_grid_op<T>(c, GridOp::FftZ, c->grid, c->grid, nullptr, -1, 0);
+    launch_spread_interp<T>(c, true, f_sorted, c->rgrid);
+    launch_grid_op<T>(c, GridOp::FftZAos, c->rgrid, c->grid, nullptr, -1, 0);
     launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid, nullptr, 1, -1);
   }
   launch_grid_op<T>(c, GridOp::XFused, noise == 2 ? c->grid2 : nullptr, c->grid, &wc, f_sorted ? 1 : 0, noise);
   launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid, nullptr, 1, +1);
-  launch_grid_op<T>(c, GridOp::FftZ, c->grid, c->grid, nullptr, +1, 0);
-  launch_spread_interp<T>(c, false, c->grid, out);
+  launch_grid_op<T>(c, GridOp::FftZAos, c->grid, c->rgrid, nullptr, +1, 0);
+  launch_spread_interp<T>(c, false, c->rgrid, out);
   return hip_status(hipGetLastError());
 }
 
@@ -583,6 +583,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   c->counter = (unsigned *)al.dev(sizeof(unsigned));
   const size_t M3 = (size_t)p->grid * p->grid * p->grid;
   c->grid = al.dev(3 * T * M3);
+  c->rgrid = al.dev(4 * T * M3);
   if (p->precond == 1) {
     c->pc_on = true;
     c->pc_w = (uint16_t *)al.dev(sizeof(uint16_t) * kWTotal);

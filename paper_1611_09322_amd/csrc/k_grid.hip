@@ -225,6 +225,82 @@ __global__ __launch_bounds__(BLOCK) void k_fft_z(const C<T> *__restrict__ src, C
   }
 }
 
+// z pass between the interleaved real grid (one (c0, c1, c2, 0) vector per
+// node, nodes [x][y][z]) and the planar half spectrum: the three component
+// lines of NXY (x, y) columns are transformed together, so every node vector
+// is read or written once, whole.  Forward (DIR < 0): real -> spectrum;
+// inverse (DIR > 0): spectrum -> real, with the same packing as k_fft_z.
+template <typename T, int M, int DIR, int NXY, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fft_z_aos(const void *__restrict__ src, void *__restrict__ dst,
+                                                     const C<T> *__restrict__ twH_g, const C<T> *__restrict__ twM_g) {
+  using T4 = typename vec4<T>::type;
+  constexpr int H = M / 2, NL = 3 * NXY;
+  __shared__ C<T> buf[H * NL];
+  __shared__ C<T> twH[H];
+  __shared__ C<T> twM[H];
+  for (int i = threadIdx.x; i < H; i += BLOCK) {
+    twH[i] = twH_g[i];
+    twM[i] = twM_g[i];
+  }
+  const size_t xy0 = (size_t)blockIdx.x * NXY;
+  const size_t s_comp = (size_t)M * M;  // spectrum lines per component
+  __syncthreads();
+  if (DIR < 0) {
+    for (int e = threadIdx.x; e < H * NXY; e += BLOCK) {
+      const int k = e % H, l = e / H;
+      const T4 *ln = (const T4 *)src + (xy0 + l) * M;
+      const T4 a = ln[2 * k], b = ln[2 * k + 1];
+      buf[k * NL + l] = cmk<T>(a.x, b.x);
+      buf[k * NL + NXY + l] = cmk<T>(a.y, b.y);
+      buf[k * NL + 2 * NXY + l] = cmk<T>(a.z, b.z);
+    }
+  } else {
+    for (int e = threadIdx.x; e < H * NL; e += BLOCK) {
+      const int k = e % H, l = e / H, cc = l / NXY, lxy = l % NXY;
+      const C<T> *ln = (const C<T> *)src + (cc * s_comp + xy0 + lxy) * H;
+      C<T> xk = ln[k];
+      C<T> xm = k == 0 ? cmk<T>(T(0), T(0)) : ln[H - k];
+      if (k == 0) xk.y = T(0);
+      const C<T> sm = cadd(xk, cconj(xm));
+      const C<T> dd = csub(xk, cconj(xm));
+      const C<T> w = cconj(twM[k]);  // e^{+2 pi i k / M}
+      const C<T> t = cmul(w, dd);
+      buf[k * NL + l] = cmk<T>(sm.x - t.y, sm.y + t.x);  // s + i t
+    }
+  }
+  __syncthreads();
+  fft_lds<T, H, DIR, NL, BLOCK>(buf, twH);
+  if (DIR < 0) {
+    for (int e = threadIdx.x; e < H * NL; e += BLOCK) {
+      const int k = e % H, l = e / H, cc = l / NXY, lxy = l % NXY;
+      const C<T> zk = buf[k * NL + l];
+      const C<T> zm = cconj(buf[((H - k) % H) * NL + l]);
+      const C<T> sm = cadd(zk, zm);
+      const C<T> dd = csub(zk, zm);
+      const C<T> t = cmul(twM[k], dd);
+      C<T> *ln = (C<T> *)dst + (cc * s_comp + xy0 + lxy) * H;
+      ln[k] = cmk<T>((T)0.5 * (sm.x + t.y), (T)0.5 * (sm.y - t.x));
+    }
+  } else {
+    for (int e = threadIdx.x; e < H * NXY; e += BLOCK) {
+      const int k = e % H, l = e / H;
+      const C<T> u0 = buf[k * NL + l], u1 = buf[k * NL + NXY + l], u2 = buf[k * NL + 2 * NXY + l];
+      T4 *ln = (T4 *)dst + (xy0 + l) * M;
+      T4 a, b;
+      a.x = u0.x;
+      a.y = u1.x;
+      a.z = u2.x;
+      a.w = T(0);
+      b.x = u0.y;
+      b.y = u1.y;
+      b.z = u2.y;
+      b.w = T(0);
+      ln[2 * k] = a;
+      ln[2 * k + 1] = b;
+    }
+  }
+}
+
 // ------------------------------------------------------- strided passes
 // 1D FFTs of length N along a strided axis for a tile of TZ consecutive jz
 // columns and NCOMP components: element n of column (comp, col) is at
@@ -423,15 +499,16 @@ __global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__
     for (int iz = 0; iz < P; ++iz) {
       const T w = wxy * wz[iz];
       const size_t g = row + iz_m[iz];
-      unsafeAtomicAdd(&grid[g], w * fx);
-      unsafeAtomicAdd(&grid[M3 + g], w * fy);
-      unsafeAtomicAdd(&grid[2 * M3 + g], w * fz);
+      unsafeAtomicAdd(&grid[4 * g], w * fx);  // interleaved nodes (c0, c1, c2, 0)
+      unsafeAtomicAdd(&grid[4 * g + 1], w * fy);
+      unsafeAtomicAdd(&grid[4 * g + 2], w * fz);
     }
   }
 }
 
 // Interpolation: one wavefront per particle; lane -> (iz, ix) of the support
-// (consecutive lanes read consecutive z nodes of one grid row), loop over iy.
+// (consecutive lanes read consecutive z nodes of one grid row, one
+// (c0, c1, c2, 0) vector per node of the interleaved grid), loop over iy.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__restrict__ pos,
                                                 const T *__restrict__ grid, int n,
@@ -445,7 +522,7 @@ __global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__
   const auto p = pos[s];
   const int bx = min((int)(p.x * invh), M - 1), by = min((int)(p.y * invh), M - 1), bz = min((int)(p.z * invh), M - 1);
   const int gx0 = bx - P / 2 + 1, gy0 = by - P / 2 + 1, gz0 = bz - P / 2 + 1;
-  const size_t M3 = (size_t)M * M * M;
+  auto *g4 = (const typename vec4<T>::type *)grid;  // interleaved nodes (c0, c1, c2, 0)
   T wy[P];
   int ym[P];
 #pragma unroll
@@ -466,10 +543,10 @@ __global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__
 #pragma unroll
     for (int iy = 0; iy < P; ++iy) {
       const T w = wxz * wy[iy];
-      const size_t g = (xrow + ym[iy]) * M + zm;
-      ax += w * grid[g];
-      ay += w * grid[M3 + g];
-      az += w * grid[2 * M3 + g];
+      const auto v = g4[(xrow + ym[iy]) * M + zm];
+      ax += w * v.x;
+      ay += w * v.y;
+      az += w * v.z;
     }
   }
 #pragma unroll
@@ -641,12 +718,17 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
       }
     }
   }
-  const size_t M3 = (size_t)M * M * M;
   const size_t col = ((size_t)(t0x + lx) * M + (t0y + ly)) * M + t0z + zw;
+  auto *g4 = (typename vec4<T>::type *)grid;  // interleaved nodes
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) grid[c * M3 + col + q] = acc[c][q];
+  for (int q = 0; q < 8; ++q) {
+    typename vec4<T>::type v;
+    v.x = acc[0][q];
+    v.y = acc[1][q];
+    v.z = acc[2][q];
+    v.w = T(0);
+    g4[col + q] = v;
+  }
 }
 
 // ----------------------------------------------------------- launchers
@@ -672,6 +754,21 @@ static void fft_z(pse_ctx *c, const void *src, void *dst, int dir) {
   else
     k_fft_z<T, M, +1, NL, 256><<<g, 256, 0, c->stream>>>((const CT *)src, (CT *)dst, (const CT *)c->tw_H,
                                                          (const CT *)c->tw_M);
+}
+
+// z pass on the interleaved real grid: NXY (x, y) columns (3 NXY lines) per
+// workgroup, at most 48 KB of LDS
+template <typename T, int M>
+static void fft_z_aos(pse_ctx *c, const void *src, void *dst, int dir) {
+  using CT = C<T>;
+  constexpr int NX0 = 49152 / (3 * M * (int)sizeof(T));
+  constexpr int NXY = NX0 >= 16 ? 16 : (NX0 >= 8 ? 8 : (NX0 >= 4 ? 4 : (NX0 >= 2 ? 2 : 1)));
+  const dim3 g(M * M / NXY);
+  ProfScope ps(c, PSE_STAGE_FFT);
+  if (dir < 0)
+    k_fft_z_aos<T, M, -1, NXY, 256><<<g, 256, 0, c->stream>>>(src, dst, (const CT *)c->tw_H, (const CT *)c->tw_M);
+  else
+    k_fft_z_aos<T, M, +1, NXY, 256><<<g, 256, 0, c->stream>>>(src, dst, (const CT *)c->tw_H, (const CT *)c->tw_M);
 }
 
 template <typename T, int M>
@@ -715,6 +812,7 @@ template <typename T, int M>
 static void dispatch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoef *wc, int x, int y) {
   switch (op) {
     case GridOp::FftZ: fft_z<T, M>(c, a, b, x); break;
+    case GridOp::FftZAos: fft_z_aos<T, M>(c, a, b, x); break;
     case GridOp::FftStrided: fft_strided<T, M>(c, b, x, y); break;
     case GridOp::XFused: xpass<T, M>(c, b, a, *wc, x != 0, y); break;
   }
@@ -766,7 +864,7 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
       else if (M >= 64) go(std::integral_constant<int, 2>{});
       else go(std::integral_constant<int, 1>{});
     } else {
-      (void)hipMemsetAsync(grid_or_out, 0, sizeof(T) * 3 * (size_t)M * M * M, c->stream);
+      (void)hipMemsetAsync(grid_or_out, 0, sizeof(T) * 4 * (size_t)M * M * M, c->stream);
       k_spread<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T4 *)vec, n, (T *)grid_or_out, M,
                                                     (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)norm);
     }

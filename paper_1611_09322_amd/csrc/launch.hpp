@@ -4,7 +4,7 @@
 
 namespace pse {
 
-enum class GridOp { FftZ, FftStrided, XFused };
+enum class GridOp { FftZ, FftZAos, FftStrided, XFused };
 
 // Bracket the launches of one stage with events (no-op unless selected).
 void prof_begin(pse_ctx *c, int stage);
@@ -49,13 +49,16 @@ template <typename T, typename A> void launch_lz_iter_pc(pse_ctx *c, int m, cons
 
 // grid side (k_grid.hip)
 //   FftZ:       a = src, b = dst, x = direction (-1 forward R2C, +1 inverse C2R)
+//   FftZAos:    as FftZ with the real side interleaved (one (c0, c1, c2, 0)
+//               vector per node): forward reads it, inverse writes it
 //   FftStrided: b = data, x = axis (0: x, 1: y), y = direction
 //   XFused:     a = transformed grid-noise spectrum (or null), b = data,
 //               x = forces present, y = noise (0 none, 1 Philox, 2 grid noise)
 template <typename T> void launch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoef *wc, int x, int y);
 template <typename T> void launch_spread_interp(pse_ctx *c, bool spread, const void *vec, void *grid_or_out);
-// Spreading clears the grid itself (every node written once, or cleared
-// before the atomic fallback): no separate clear is needed.
+// Spreading writes the interleaved real grid (one (c0, c1, c2, 0) vector per
+// node) and clears it itself (every node written once, or cleared before the
+// atomic fallback): no separate clear is needed.  Interpolation reads it.
 bool spread_writes_whole_grid(int M, int P);
 
 }  // namespace pse

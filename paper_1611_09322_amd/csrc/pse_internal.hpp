@@ -159,7 +159,8 @@ struct pse_ctx {
   double *series = nullptr; // [2*kSeriesTerms] series coefficients (device)
   double series_h[2 * pse::kSeriesTerms];
   double small_r2 = 0;      // r^2 below which the series is used
-  void *grid = nullptr;     // T [3 M^3]
+  void *grid = nullptr;     // T [3 M^3]: planar half spectrum [c][jx][jy][jz < M/2] (complex)
+  void *rgrid = nullptr;    // T4 [M^3]: interleaved real grid, nodes [x][y][z] of (c0, c1, c2, 0)
   void *grid2 = nullptr;    // T [3 M^3] (grid-noise path, lazily)
   void *tw_M = nullptr;     // T2 [M] twiddles exp(-2 pi i k / M)
   void *tw_H = nullptr;     // T2 [M/2]
