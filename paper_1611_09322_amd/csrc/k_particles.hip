@@ -292,11 +292,17 @@ __global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, cons
   }
   if (FEAT) acc.store(feat + (size_t)s * kNFeat, cnt);
   cnt_out[s] = cnt;
-  atomicMax(&flags[1], cnt);
   }
-  // total ordered pairs: one 64-bit atomic per wavefront
+  // total ordered pairs and the largest count: one set of atomics per wavefront
   const unsigned long long tot = wave_sum((unsigned long long)cnt);
-  if ((threadIdx.x & 63) == 0 && tot) atomicAdd((unsigned long long *)(flags + 2), tot);
+  int mx = cnt;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) {
+    if (tot) atomicAdd((unsigned long long *)(flags + 2), tot);
+    atomicMax(&flags[1], mx);  // capacity needed
+    atomicMax(&flags[5], mx);  // largest neighbour count
+  }
 }
 
 // --------------------------------------------------- near-field product
@@ -568,18 +574,20 @@ __global__ void k_halo_size(const int *__restrict__ cell_start, int nc, int *__r
   atomicMax(&flags[4], tot);
 }
 
-template <int B, bool UNWRAP, bool FEAT>
+// With NEAR (learned preconditioner on), the neighbours closer than 4.5a
+// (the shell its features use) are also packed into a second, short list
+// nbr_nr (chunks of 8, chunk q of s at q * n + s, capacity cap_nr entries)
+// with counts cnt_nr.  flags[1]: capacity needed; flags[5]: largest count;
+// flags[7]: largest near count.
+template <int B, bool UNWRAP, bool NEAR>
 __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
                                                  int nc, float cs, int n, float L, float invL, float rc2,
                                                  uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
-                                                 int *__restrict__ flags, FGTable fg, float inv_mu0, float fself,
-                                                 float a, float inv_rc, uint16_t *__restrict__ feat) {
+                                                 int *__restrict__ flags, float near2, uint16_t *__restrict__ nbr_nr,
+                                                 int *__restrict__ cnt_nr, int cap_nr) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   extern __shared__ float4 hpos[];
   __shared__ HaloTab ht;
-  __shared__ float4 ftab[FEAT ? kTableK + 1 : 1];  // F/G table for the features
-  if (FEAT)
-    for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) ftab[k] = fg.tab[k];
   halo_setup<B>(cell_start, nc, ht);
   if (UNWRAP) {
     const int nb = (nc + B - 1) / B;
@@ -593,17 +601,17 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
   __syncthreads();
   const int ntarg = ht.tpre[ht.ntc];
   unsigned long long mine = 0;
-  int mx = 0;
+  int mx = 0, mxn = 0;
+  uint4 *row = (uint4 *)nbr;
+  uint4 *rown = (uint4 *)nbr_nr;
   for (int i = threadIdx.x; i < ntarg; i += blockDim.x) {
     int h, li, s;
     target_of(ht, i, h, li, s);
     const int ox = h / (HB * HB) - 1, oy = (h / HB) % HB - 1, oz = h % HB - 1;
     const float4 p = hpos[li];
-    int k = 0;
-    uint64_t lo = 0, hi = 0;  // the current chunk of 8 packed 16-bit indices
-    uint4 *row = (uint4 *)nbr;
-    FeatAcc<float> acc;
-    if (FEAT) acc.init(fself);
+    int k = 0, kn = 0;
+    uint64_t lo = 0, hi = 0;    // the current chunk of 8 packed 16-bit indices
+    uint64_t nlo = 0, nhi = 0;  // the same for the near list
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dz = -1; dz <= 1; ++dz) {
@@ -614,32 +622,25 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
             float4 q[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) q[u] = hpos[min(j0 + u, e - 1)];
-            unsigned hit = 0;
-            float ddx[4], ddy[4], ddz[4], rr[4];
+            unsigned hit = 0, isnear = 0;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              ddx[u] = p.x - q[u].x;
-              ddy[u] = p.y - q[u].y;
-              ddz[u] = p.z - q[u].z;
+              float ddx = p.x - q[u].x, ddy = p.y - q[u].y, ddz = p.z - q[u].z;
               if (!UNWRAP) {
-                ddx[u] = min_image(ddx[u], L, invL);
-                ddy[u] = min_image(ddy[u], L, invL);
-                ddz[u] = min_image(ddz[u], L, invL);
+                ddx = min_image(ddx, L, invL);
+                ddy = min_image(ddy, L, invL);
+                ddz = min_image(ddz, L, invL);
               }
-              rr[u] = ddx[u] * ddx[u] + ddy[u] * ddy[u] + ddz[u] * ddz[u];
+              const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
               const int j = j0 + u;
-              if (j < e && j != li && rr[u] <= rc2) hit |= 1u << u;
+              if (j < e && j != li && r2 <= rc2) {
+                hit |= 1u << u;
+                if (NEAR && r2 < near2) isnear |= 1u << u;
+              }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               if (hit & (1u << u)) {
-                if (FEAT && rr[u] < 20.25f * a * a) {  // near shell r < 4.5a
-                  const bool nz = rr[u] > 1e-24f;
-                  const float ir = nz ? __frsqrt_rn(rr[u]) : 0.0f;
-                  float Fm = fself / inv_mu0, Dm = 0.0f;
-                  if (nz) FGTable{ftab, fg.inv_dr}.eval(rr[u], ir, Fm, Dm);
-                  acc.add(ddx[u], ddy[u], ddz[u], rr[u] * ir, ir, Fm * inv_mu0, Dm * inv_mu0, a, 1.0f / (4.5f * a));
-                }
                 const int slot = k & 7;
                 const uint64_t v = (uint64_t)(j0 + u) << (16 * (slot & 3));
                 if (slot < 4) lo |= v;
@@ -652,23 +653,125 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
                 }
                 ++k;
               }
+              if (NEAR && (isnear & (1u << u))) {
+                const int slot = kn & 7;
+                const uint64_t v = (uint64_t)(j0 + u) << (16 * (slot & 3));
+                if (slot < 4) nlo |= v;
+                else nhi |= v;
+                if (slot == 7) {
+                  if ((kn >> 3) < (cap_nr >> 3))
+                    rown[(size_t)(kn >> 3) * n + s] = make_uint4((uint32_t)nlo, (uint32_t)(nlo >> 32),
+                                                                 (uint32_t)nhi, (uint32_t)(nhi >> 32));
+                  nlo = nhi = 0;
+                }
+                ++kn;
+              }
             }
           }
         }
     if ((k & 7) && (k >> 3) < (cap >> 3))
       row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
-    if (FEAT) acc.store(feat + (size_t)s * kNFeat, k);
     cnt_out[s] = k;
+    if (NEAR) {
+      if ((kn & 7) && (kn >> 3) < (cap_nr >> 3))
+        rown[(size_t)(kn >> 3) * n + s] = make_uint4((uint32_t)nlo, (uint32_t)(nlo >> 32), (uint32_t)nhi,
+                                                     (uint32_t)(nhi >> 32));
+      cnt_nr[s] = kn;
+      mxn = max(mxn, kn);
+    }
     mine += (unsigned long long)k;
     mx = max(mx, k);
   }
+  // one set of atomics per workgroup: every wavefront hitting the same
+  // flags serialises at the L2
   const unsigned long long tot = wave_sum(mine);
-  int wmx = mx;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) wmx = max(wmx, __shfl_xor(wmx, off, 64));
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = max(mx, __shfl_xor(mx, off, 64));
+    mxn = max(mxn, __shfl_xor(mxn, off, 64));
+  }
+  __shared__ unsigned long long wtot[8];
+  __shared__ int wmx[8], wmxn[8];
+  const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    if (tot) atomicAdd((unsigned long long *)(flags + 2), tot);
-    atomicMax(&flags[1], wmx);
+    wtot[wave] = tot;
+    wmx[wave] = mx;
+    wmxn[wave] = mxn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    int m = 0, mn = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      t += wtot[w];
+      m = max(m, wmx[w]);
+      mn = max(mn, wmxn[w]);
+    }
+    if (t) atomicAdd((unsigned long long *)(flags + 2), t);
+    atomicMax(&flags[1], m);
+    atomicMax(&flags[5], m);
+    if (NEAR) atomicMax(&flags[7], mn);
+  }
+}
+
+// Preconditioner features from the near list, one thread per target
+// (FeatAcc; F, G from the LDS table).
+template <int B, bool UNWRAP>
+__global__ __launch_bounds__(512) void k_feat_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
+                                                  int nc, float cs, int n, float L, float invL,
+                                                  const uint16_t *__restrict__ nbr_nr, const int *__restrict__ cnt,
+                                                  const int *__restrict__ cnt_nr, const float4 *__restrict__ tab,
+                                                  float inv_dr, float inv_mu0, float fself, float a,
+                                                  uint16_t *__restrict__ feat) {
+  constexpr int NH = Halo<B>::NH;
+  extern __shared__ float4 hpos[];
+  __shared__ HaloTab ht;
+  __shared__ float4 ftab[kTableK + 1];
+  for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) ftab[k] = tab[k];
+  halo_setup<B>(cell_start, nc, ht);
+  if (UNWRAP) {
+    const int nb = (nc + B - 1) / B;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
+    const float c0 = 0.5f * B * cs;
+    halo_stage_unwrapped<NH>(pos, hpos, ht, bx * B * cs + c0, by * B * cs + c0, bz * B * cs + c0, L, invL);
+  } else {
+    halo_stage<NH>(pos, hpos, ht);
+  }
+  __syncthreads();
+  const FGTable fg{ftab, inv_dr};
+  const int ntarg = ht.tpre[ht.ntc];
+  const uint4 *row = (const uint4 *)nbr_nr;
+  for (int i = threadIdx.x; i < ntarg; i += blockDim.x) {
+    int h, li, s;
+    target_of(ht, i, h, li, s);
+    const float4 p = hpos[li];
+    FeatAcc<float> acc;
+    acc.init(fself);
+    const int kn = cnt_nr[s];
+    for (int kb = 0; kb < kn; kb += 8) {
+      const uint4 pk = row[(size_t)(kb >> 3) * n + s];
+      const uint32_t wd[4] = {pk.x, pk.y, pk.z, pk.w};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (kb + u < kn) {
+          const float4 q = hpos[(wd[u >> 1] >> (16 * (u & 1))) & 0xFFFF];
+          float ddx = p.x - q.x, ddy = p.y - q.y, ddz = p.z - q.z;
+          if (!UNWRAP) {
+            ddx = min_image(ddx, L, invL);
+            ddy = min_image(ddy, L, invL);
+            ddz = min_image(ddz, L, invL);
+          }
+          const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          const bool nz = r2 > 1e-24f;
+          const float ir = nz ? __frsqrt_rn(r2) : 0.0f;
+          float Fm = fself / inv_mu0, Dm = 0.0f;
+          if (nz) fg.eval(r2, ir, Fm, Dm);
+          acc.add(ddx, ddy, ddz, r2 * ir, ir, Fm * inv_mu0, Dm * inv_mu0, a, 1.0f / (4.5f * a));
+        }
+      }
+    }
+    acc.store(feat + (size_t)s * kNFeat, cnt[s]);
   }
 }
 
@@ -1263,16 +1366,14 @@ void launch_nbr_lds(pse_ctx *c) {
   ProfScope ps(c, PSE_STAGE_NBR);
   const size_t smem = sizeof(float4) * (size_t)c->hcap;
   const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L), rc2 = (float)(c->p.rcut * c->p.rcut);
+  const float near2 = (float)(20.25 * c->p.a * c->p.a);  // r < 4.5a
   auto *nb = (uint16_t *)c->nbr;
   const bool unwrap = c->d.nc >= c->lds_B + 3;
-  const FGTable fg{c->table, (float)(kTableK / c->p.rcut)};
-  const float inv_mu0 = (float)(1.0 / c->d.mu0), fself = (float)(c->d.self_r / c->d.mu0);
   auto go = [&](auto kern) {
     allow_lds(kern, smem);
     kern<<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
-                                                  c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags, fg,
-                                                  inv_mu0, fself, (float)c->p.a, (float)(1.0 / c->p.rcut),
-                                                  c->pc_feat);
+                                                  c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags, near2,
+                                                  c->nbr_nr, c->nbr_nr_cnt, c->nbr_nr_cap);
   };
   if (c->pc_on) {
     if (c->lds_B == 2) {
@@ -1290,6 +1391,29 @@ void launch_nbr_lds(pse_ctx *c) {
       if (unwrap) go(k_nbr_lds<1, true, false>);
       else go(k_nbr_lds<1, false, false>);
     }
+  }
+}
+
+// Preconditioner features on the LDS path, from the near list.
+void launch_feat_lds(pse_ctx *c) {
+  ProfScope ps(c, PSE_STAGE_PRECOND);
+  const size_t smem = sizeof(float4) * (size_t)c->hcap;
+  const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L);
+  const bool unwrap = c->d.nc >= c->lds_B + 3;
+  const float inv_mu0 = (float)(1.0 / c->d.mu0), fself = (float)(c->d.self_r / c->d.mu0);
+  auto go = [&](auto kern) {
+    allow_lds(kern, smem);
+    kern<<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
+                                                  c->n, L, invL, (const uint16_t *)c->nbr_nr, c->nbr_cnt,
+                                                  c->nbr_nr_cnt, c->table, (float)(kTableK / c->p.rcut), inv_mu0,
+                                                  fself, (float)c->p.a, c->pc_feat);
+  };
+  if (c->lds_B == 2) {
+    if (unwrap) go(k_feat_lds<2, true>);
+    else go(k_feat_lds<2, false>);
+  } else {
+    if (unwrap) go(k_feat_lds<1, true>);
+    else go(k_feat_lds<1, false>);
   }
 }
 

@@ -146,8 +146,12 @@ struct pse_ctx {
   int *cell_start = nullptr;
   int *nbr = nullptr;
   int *nbr_cnt = nullptr;
+  uint16_t *nbr_nr = nullptr;  // LDS path with the preconditioner: neighbours closer than 4.5a
+  int *nbr_nr_cnt = nullptr;
+  int nbr_nr_cap = 0;
   int nbr_cap = 0;
-  int *flags = nullptr;     // [0] nonfinite, [1] max neighbours, [2..3] pairs, [4] max halo
+  int *flags = nullptr;     // [0] nonfinite, [1] list slots needed, [2..3] pairs, [4] max halo,
+                            // [5] max neighbours, [6] preconditioner fallbacks
   int *flags_h = nullptr;   // pinned copy
   void *vbuf[10] = {};      // T4 [n] work vectors (sorted order, (x, y, z, 0))
   void *V = nullptr;        // T4 [(kMaxIter+1) n] Lanczos basis
