@@ -1004,21 +1004,33 @@ __global__ void k_lz_init(const A *__restrict__ partials, int nparts, LzState<A>
   }
 }
 
-// w = t - alpha_m v_m - beta_m v_{m-1}; block partials of |w|^2.
+// w = t - alpha_m v_m - beta_m v_{m-1}, one particle (x, y, z, 0) per
+// step; block partials of |w|^2.
 template <typename T, typename A>
-__global__ void k_lz_update(const T *__restrict__ t, const T *__restrict__ vm, const T *__restrict__ vprev,
-                            T *__restrict__ w, int len, LzState<A> *st, A *__restrict__ partials) {
+__global__ void k_lz_update(const typename vec4<T>::type *__restrict__ t, const typename vec4<T>::type *__restrict__ vm,
+                            const typename vec4<T>::type *__restrict__ vprev, typename vec4<T>::type *__restrict__ w,
+                            int n, LzState<A> *st, A *__restrict__ partials) {
   __shared__ A sh[16];
   if (st->done) return;
   const int m = st->m;
   const T al = (T)st->alpha[m];
   const T be = m > 0 ? (T)st->beta[m] : T(0);
   A v = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
-    T x = t[i] - al * vm[i];
-    if (m > 0) x -= be * vprev[i];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const auto a = t[i], b = vm[i];
+    typename vec4<T>::type x;
+    x.x = a.x - al * b.x;
+    x.y = a.y - al * b.y;
+    x.z = a.z - al * b.z;
+    if (m > 0) {
+      const auto c = vprev[i];
+      x.x -= be * c.x;
+      x.y -= be * c.y;
+      x.z -= be * c.z;
+    }
+    x.w = T(0);
     w[i] = x;
-    v += (A)x * (A)x;
+    v += (A)x.x * (A)x.x + (A)x.y * (A)x.y + (A)x.z * (A)x.z;
   }
   v = block_sum(v, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
@@ -1505,8 +1517,7 @@ void launch_lz_iter(pse_ctx *c, int m, const void *z) {
   prof_end(c, PSE_STAGE_SPMV);
   const T4 *vprev = m > 0 ? V + (size_t)(m - 1) * n : V;
   ProfScope ps(c, PSE_STAGE_LANCZOS);
-  k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>((const T *)t, (const T *)(V + (size_t)m * n),
-                                                      (const T *)vprev, (T *)w, len, st, (A *)c->partials);
+  k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * n, vprev, w, n, st, (A *)c->partials);
   k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, st, (A)c->p.lanczos_tol,
                                          c->p.lanczos_max_iter);
 }
@@ -1554,8 +1565,7 @@ void launch_lz_iter_pc(pse_ctx *c, int m, const void *z) {
   ProfScope ps(c, PSE_STAGE_LANCZOS);
   launch_pc_post<T, A>(c, tp, src, t, V + (size_t)m * c->n);
   const T4 *vprev = m > 0 ? V + (size_t)(m - 1) * c->n : V;
-  k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>((const T *)t, (const T *)(V + (size_t)m * c->n),
-                                                      (const T *)vprev, (T *)w, 4 * c->n, (LzState<A> *)c->lz,
+  k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * c->n, vprev, w, c->n, (LzState<A> *)c->lz,
                                                       (A *)c->partials);
   k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, (LzState<A> *)c->lz,
                                          (A)c->p.lanczos_tol, c->p.lanczos_max_iter);

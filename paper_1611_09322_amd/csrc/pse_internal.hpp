@@ -14,13 +14,13 @@ namespace pse {
 constexpr int kMaxIter = 64;     // Lanczos basis capacity
 constexpr int kTableK = 1024;    // F/G table intervals on [0, rcut]
 constexpr int kSeriesTerms = 16; // small-r series terms of the wave complement
-constexpr int kRedBlock = 256;
+constexpr int kRedBlock = 1024;  // workgroups (partial sums) of the vector reductions
 // Learned preconditioner: 24 features, MLP 24 -> 64 -> 64 -> 9.  Weights are
 // one bf16 array: W1 [64][32] (inputs 24..31 zero), b1 [64], W2 [64][64],
 // b2 [64], W3 [16][64] (rows 9..15 zero), b3 [16] (entries 9..15 zero).
 constexpr int kNFeat = 24, kNHid = 64, kNOut = 9;
 constexpr int kW1 = 0, kB1 = kW1 + 64 * 32, kW2 = kB1 + 64, kB2 = kW2 + 64 * 64, kW3 = kB2 + 64,
-              kB3 = kW3 + 16 * 64, kWTotal = kB3 + 16;   // threads per block of reduction kernels
+              kB3 = kW3 + 16 * 64, kWTotal = kB3 + 16;
 
 template <typename T> struct vec2;
 template <> struct vec2<float> { using type = float2; };
