@@ -94,6 +94,8 @@ def make_workload(args):
     import synth
 
     t0 = time.time()
+    print(f"[bench] generating N={args.n} hard spheres at phi={args.phi} (RSA, then {args.sweeps} MC sweeps)",
+          file=sys.stderr, flush=True)
     x, L = synth.hard_spheres(args.n, args.phi, a=1.0, seed=1003, sweeps=args.sweeps,
                               progress=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     # caller order is arbitrary: shuffle so that the library's own sort is exercised
