@@ -352,11 +352,9 @@ DI void philox4x64_10g(uint64_t c[4], uint64_t k0, uint64_t k1) {
     c[3] = lo0;
   }
 }
-template <typename T> DI C<T> zeta_at(uint64_t e, uint64_t seed, uint64_t sample);
-template <> DI C<double> zeta_at<double>(uint64_t e, uint64_t seed, uint64_t sample) {
-  uint64_t c[4] = {e >> 1, sample, 0ull, 0ull};
-  philox4x64_10g(c, seed, 1ull);
-  const uint64_t wa = (e & 1) ? c[2] : c[0], wb = (e & 1) ? c[3] : c[1];
+// Box-Muller of one 64-bit pair (the precision's uniform construction)
+template <typename T> DI C<T> zeta_from(uint64_t wa, uint64_t wb);
+template <> DI C<double> zeta_from<double>(uint64_t wa, uint64_t wb) {
   const double ua = ((double)(wa >> 11) + 0.5) * 0x1.0p-53;
   const double ub = ((double)(wb >> 11) + 0.5) * 0x1.0p-53;
   const double rho = sqrt(-2.0 * log(ua)) * 0.70710678118654752440;
@@ -364,16 +362,25 @@ template <> DI C<double> zeta_at<double>(uint64_t e, uint64_t seed, uint64_t sam
   sincospi(2.0 * ub, &sn, &cs);
   return cmk<double>(rho * cs, rho * sn);
 }
-template <> DI C<float> zeta_at<float>(uint64_t e, uint64_t seed, uint64_t sample) {
-  uint64_t c[4] = {e >> 1, sample, 0ull, 0ull};
-  philox4x64_10g(c, seed, 1ull);
-  const uint64_t wa = (e & 1) ? c[2] : c[0], wb = (e & 1) ? c[3] : c[1];
+template <> DI C<float> zeta_from<float>(uint64_t wa, uint64_t wb) {
   const float ua = ((float)(uint32_t)(wa >> 40) + 0.5f) * 0x1.0p-24f;
   const float ub = ((float)(uint32_t)(wb >> 40) + 0.5f) * 0x1.0p-24f;
   const float rho = sqrtf(-2.0f * logf(ua)) * 0.70710678f;
   float sn, cs;
   sincospif(2.0f * ub, &sn, &cs);
   return cmk<float>(rho * cs, rho * sn);
+}
+// zeta of the even element 2q and the odd element 2q + 1 from one block
+template <typename T> DI void zeta_pair(uint64_t e_even, uint64_t seed, uint64_t sample, C<T> &z0, C<T> &z1) {
+  uint64_t c[4] = {e_even >> 1, sample, 0ull, 0ull};
+  philox4x64_10g(c, seed, 1ull);
+  z0 = zeta_from<T>(c[0], c[1]);
+  z1 = zeta_from<T>(c[2], c[3]);
+}
+template <typename T> DI C<T> zeta_at(uint64_t e, uint64_t seed, uint64_t sample) {
+  uint64_t c[4] = {e >> 1, sample, 0ull, 0ull};
+  philox4x64_10g(c, seed, 1ull);
+  return (e & 1) ? zeta_from<T>(c[2], c[3]) : zeta_from<T>(c[0], c[1]);
 }
 
 // ------------------------------------------------------ fused x pass
@@ -405,55 +412,65 @@ __global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, 
   }
   const T tpl = (T)wc.two_pi_over_L;
   const int sy = jy < H ? jy : jy - M;
-  for (int e = threadIdx.x; e < M * TZ; e += BLOCK) {
-    const int col = e % TZ, jx = e / TZ;
-    const int jz = z0 + col;
+  // two adjacent jz per thread: one Philox block gives the noise of both
+  // (its elements 2q, 2q + 1; z0 and TZ are even)
+  for (int e = threadIdx.x; e < M * (TZ / 2); e += BLOCK) {
+    const int col0 = 2 * (e % (TZ / 2)), jx = e / (TZ / 2);
     const int sx = jx < H ? jx : jx - M;
-    C<T> out[3] = {cmk<T>(0, 0), cmk<T>(0, 0), cmk<T>(0, 0)};
     const bool nyq = (jx == H) || (jy == H);
-    if (!nyq && (sx | sy | jz)) {
-      const T kx = tpl * sx, ky = tpl * sy, kz = tpl * jz;
-      const T k2 = kx * kx + ky * ky + kz * kz;
-      const T kk = sqrt(k2);
-      const T ka = kk * (T)wc.a;
-      const T sinc = sin(ka) / ka;
-      const T q = k2 * (T)wc.inv_4xi2;
-      const T gs = k2 * (T)wc.sigma2;
-      C<T> v[3];
-      for (int c = 0; c < 3; ++c) v[c] = cmk<T>(0, 0);
-      if (FORCES) {
-        const T det = (T)wc.det_scale * sinc * sinc * (T(1) + q) / k2 * exp(gs - q);
+    C<T> zeta[2][3];
+    if (NOISE == 1 && !nyq) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = cscale(buf[jx * NCOLS + c * TZ + col], det);
-      }
-      if (NOISE) {
-        // B^{1/2} is the non-negative root: |sinc(ka)| (sinc changes sign for ka > pi)
-        const T sto = (T)wc.sto_scale * fabs(sinc) * sqrt(T(1) + q) / kk * exp(T(0.5) * (gs - q));
+      for (int c = 0; c < 3; ++c)
+        zeta_pair<T>((((uint64_t)c * M + jx) * M + jy) * H + z0 + col0, wc.seed, wc.counter, zeta[0][c], zeta[1][c]);
+      if (z0 + col0 == 0 && !(sy > 0 || (sy == 0 && sx > 0))) {
+        // jz = 0 outside the canonical half: the conjugate of the partner
+        const int px = (M - jx) % M, py = (M - jy) % M;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          C<T> z;
-          if (NOISE == 1) {
-            const bool canon = jz > 0 || sy > 0 || (sy == 0 && sx > 0);
-            if (canon) {
-              z = zeta_at<T>((((uint64_t)c * M + jx) * M + jy) * H + jz, wc.seed, wc.counter);
-            } else {
-              const int px = (M - jx) % M, py = (M - jy) % M;
-              z = cconj(zeta_at<T>((((uint64_t)c * M + px) * M + py) * H + 0, wc.seed, wc.counter));
-            }
-          } else {
-            z = cscale(specW[c * s_comp + (size_t)jx * s_fft + base + col], (T)wc.w_scale);
-          }
-          v[c] = cadd(v[c], cscale(z, sto));
-        }
+        for (int c = 0; c < 3; ++c)
+          zeta[0][c] = cconj(zeta_at<T>((((uint64_t)c * M + px) * M + py) * H + 0, wc.seed, wc.counter));
       }
-      const C<T> kdv = cmk<T>(kx * v[0].x + ky * v[1].x + kz * v[2].x, kx * v[0].y + ky * v[1].y + kz * v[2].y);
-      const T ik2 = T(1) / k2;
-      out[0] = csub(v[0], cscale(kdv, kx * ik2));
-      out[1] = csub(v[1], cscale(kdv, ky * ik2));
-      out[2] = csub(v[2], cscale(kdv, kz * ik2));
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) buf[jx * NCOLS + c * TZ + col] = out[c];
+    for (int hh = 0; hh < 2; ++hh) {
+      const int col = col0 + hh;
+      const int jz = z0 + col;
+      C<T> out[3] = {cmk<T>(0, 0), cmk<T>(0, 0), cmk<T>(0, 0)};
+      if (!nyq && (sx | sy | jz)) {
+        const T kx = tpl * sx, ky = tpl * sy, kz = tpl * jz;
+        const T k2 = kx * kx + ky * ky + kz * kz;
+        const T kk = sqrt(k2);
+        const T ka = kk * (T)wc.a;
+        const T sinc = sin(ka) / ka;
+        const T q = k2 * (T)wc.inv_4xi2;
+        const T gs = k2 * (T)wc.sigma2;
+        C<T> v[3];
+        for (int c = 0; c < 3; ++c) v[c] = cmk<T>(0, 0);
+        if (FORCES) {
+          const T det = (T)wc.det_scale * sinc * sinc * (T(1) + q) / k2 * exp(gs - q);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[c] = cscale(buf[jx * NCOLS + c * TZ + col], det);
+        }
+        if (NOISE) {
+          // B^{1/2} is the non-negative root: |sinc(ka)| (sinc changes sign for ka > pi)
+          const T sto = (T)wc.sto_scale * fabs(sinc) * sqrt(T(1) + q) / kk * exp(T(0.5) * (gs - q));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            C<T> z;
+            if (NOISE == 1) z = zeta[hh][c];
+            else z = cscale(specW[c * s_comp + (size_t)jx * s_fft + base + col], (T)wc.w_scale);
+            v[c] = cadd(v[c], cscale(z, sto));
+          }
+        }
+        const C<T> kdv = cmk<T>(kx * v[0].x + ky * v[1].x + kz * v[2].x, kx * v[0].y + ky * v[1].y + kz * v[2].y);
+        const T ik2 = T(1) / k2;
+        out[0] = csub(v[0], cscale(kdv, kx * ik2));
+        out[1] = csub(v[1], cscale(kdv, ky * ik2));
+        out[2] = csub(v[2], cscale(kdv, kz * ik2));
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) buf[jx * NCOLS + c * TZ + col] = out[c];
+    }
   }
   __syncthreads();
   fft_lds<T, M, +1, NCOLS, BLOCK>(buf, tw);
