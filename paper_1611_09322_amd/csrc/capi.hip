@@ -48,7 +48,6 @@ inline size_t asize(const pse_ctx *c) { return c->acc_dbl ? 8 : 4; }
 void free_ctx(pse_ctx *c) {
   if (!c) return;
   void *dev[] = {c->pos_w, c->pos_s, c->perm, c->cell_of, c->cell_count, c->cell_start, c->nbr, c->nbr_cnt,
-                 c->nbr_nr, c->nbr_nr_cnt,
                  c->flags, c->V, c->lz, c->partials, c->counter, c->table, c->series, c->grid, c->rgrid, c->grid2, c->tw_M,
                  c->tw_H, c->pc_w, c->pc_feat, c->pc_y, c->pc_P, c->pc_Pinv};
   for (void *p : dev)
@@ -352,30 +351,16 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
   pse_status st = build_neighbors<T>(c);
   if (st != PSE_OK) return st;
   if (c->flags_h[0]) return PSE_ERR_NONFINITE;
-  const bool grow_nr = c->lds_B && c->pc_on && c->flags_h[7] > c->nbr_nr_cap;
-  if (c->flags_h[1] > c->nbr_cap || grow_nr) {
-    if (c->flags_h[1] > c->nbr_cap) {
-      const int cap = (c->flags_h[1] + 32 + 7) & ~7;
-      (void)hipFree(c->nbr);
+  if (c->flags_h[1] > c->nbr_cap) {
+    const int cap = (c->flags_h[1] + 32 + 7) & ~7;
+    (void)hipFree(c->nbr);
+    c->nbr = nullptr;
+    if (hipMalloc(&c->nbr, sizeof(int) * (size_t)cap * c->n) != hipSuccess) {
       c->nbr = nullptr;
-      if (hipMalloc(&c->nbr, sizeof(int) * (size_t)cap * c->n) != hipSuccess) {
-        c->nbr = nullptr;
-        c->nbr_cap = 0;
-        return PSE_ERR_OOM;
-      }
-      c->nbr_cap = cap;
+      c->nbr_cap = 0;
+      return PSE_ERR_OOM;
     }
-    if (grow_nr) {
-      const int cap = (c->flags_h[7] + 16 + 7) & ~7;
-      (void)hipFree(c->nbr_nr);
-      c->nbr_nr = nullptr;
-      if (hipMalloc(&c->nbr_nr, sizeof(uint16_t) * (size_t)cap * c->n) != hipSuccess) {
-        c->nbr_nr = nullptr;
-        c->nbr_nr_cap = 0;
-        return PSE_ERR_OOM;
-      }
-      c->nbr_nr_cap = cap;
-    }
+    c->nbr_cap = cap;
     if (hipMemsetAsync(c->flags, 0, sizeof(int) * 8, c->stream) != hipSuccess) return PSE_ERR_HIP;
     st = build_neighbors<T>(c);
     if (st != PSE_OK) return st;
@@ -386,7 +371,7 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
     c->pairs = pairs;
   }
   if (c->pc_on) {
-    // features (the LDS path reads them from the near chunks; the global
+    // features (the LDS path from the list and the staged halo; the global
     // build accumulated them itself), network, blocks, fallbacks
     if (c->lds_B) launch_feat_lds(c);
     launch_pc_blocks<T>(c);
@@ -604,9 +589,6 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   c->rgrid = al.dev(4 * T * M3);
   if (p->precond == 1) {
     c->pc_on = true;
-    c->nbr_nr_cap = 64;  // grown like the main list
-    c->nbr_nr = (uint16_t *)al.dev(sizeof(uint16_t) * (size_t)c->nbr_nr_cap * n);
-    c->nbr_nr_cnt = (int *)al.dev(sizeof(int) * n);
     c->pc_w = (uint16_t *)al.dev(sizeof(uint16_t) * kWTotal);
     c->pc_feat = (uint16_t *)al.dev(sizeof(uint16_t) * kNFeat * n);
     c->pc_y = (float *)al.dev(sizeof(float) * kNOut * n);

@@ -97,7 +97,7 @@ __global__ void k_gather_pos(const T4 *__restrict__ pos_w, const int *__restrict
 // ------------------------------------------------------- F, G evaluation
 // FP32 modes: linear interpolation in an LDS table of (mu0 F, mu0 (G-F)).
 struct FGTable {
-  const float4 *tab;  // LDS
+  const float4 *tab;  // LDS or global
   float inv_dr;
   __device__ __forceinline__ void eval(float r2, float rinv, float &Fm, float &Dm) const {
     const float u = r2 * rinv * inv_dr;
@@ -450,6 +450,8 @@ __global__ __launch_bounds__(256) void k_spmv_exact(const double4 *__restrict__ 
 // LDS instead of gathering 16-byte records from global memory per pair.
 // List layout: chunks of 8 indices, chunk q of sorted particle s at 16-byte
 // slot (q * n + s): one coalesced 16-byte load per lane per 8 neighbours.
+// The last chunk is padded with the index one past the halo (the product's
+// zero source).
 // Needs nc >= B + 2 (no halo cell appears twice).
 template <int B> struct Halo {
   static constexpr int HB = B + 2;
@@ -574,20 +576,29 @@ __global__ void k_halo_size(const int *__restrict__ cell_start, int nc, int *__r
   atomicMax(&flags[4], tot);
 }
 
-// With NEAR (learned preconditioner on), the neighbours closer than 4.5a
-// (the shell its features use) are also packed into a second, short list
-// nbr_nr (chunks of 8, chunk q of s at q * n + s, capacity cap_nr entries)
-// with counts cnt_nr.  flags[1]: capacity needed; flags[5]: largest count;
-// flags[7]: largest near count.
-template <int B, bool UNWRAP, bool NEAR>
+// flags[1]: list capacity needed; flags[5]: largest count.
+template <int B, bool UNWRAP>
 __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
                                                  int nc, float cs, int n, float L, float invL, float rc2,
                                                  uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
-                                                 int *__restrict__ flags, float near2, uint16_t *__restrict__ nbr_nr,
-                                                 int *__restrict__ cnt_nr, int cap_nr) {
+                                                 int *__restrict__ flags) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   extern __shared__ float4 hpos[];
   __shared__ HaloTab ht;
+  // for each 4-bit hit mask: (offsets of the set bits in 16-bit fields, low
+  // and high word; 0xFFFF in each used field, low and high word)
+  __shared__ uint4 pack_tab[16];
+  if (threadIdx.x < 16) {
+    uint64_t pat = 0, msk = 0;
+    int f = 0;
+    for (int u = 0; u < 4; ++u)
+      if (threadIdx.x & (1 << u)) {
+        pat |= (uint64_t)u << (16 * f);
+        msk |= 0xFFFFull << (16 * f);
+        ++f;
+      }
+    pack_tab[threadIdx.x] = make_uint4((uint32_t)pat, (uint32_t)(pat >> 32), (uint32_t)msk, (uint32_t)(msk >> 32));
+  }
   halo_setup<B>(cell_start, nc, ht);
   if (UNWRAP) {
     const int nb = (nc + B - 1) / B;
@@ -601,28 +612,28 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
   __syncthreads();
   const int ntarg = ht.tpre[ht.ntc];
   unsigned long long mine = 0;
-  int mx = 0, mxn = 0;
+  int mx = 0;
   uint4 *row = (uint4 *)nbr;
-  uint4 *rown = (uint4 *)nbr_nr;
   for (int i = threadIdx.x; i < ntarg; i += blockDim.x) {
     int h, li, s;
     target_of(ht, i, h, li, s);
     const int ox = h / (HB * HB) - 1, oy = (h / HB) % HB - 1, oz = h % HB - 1;
     const float4 p = hpos[li];
-    int k = 0, kn = 0;
-    uint64_t lo = 0, hi = 0;    // the current chunk of 8 packed 16-bit indices
-    uint64_t nlo = 0, nhi = 0;  // the same for the near list
+    int k = 0;
+    uint64_t lo = 0, hi = 0;  // the current chunk of 8 packed 16-bit indices
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dz = -1; dz <= 1; ++dz) {
           const int hh = ((ox + 1 + dx) * HB + (oy + 1 + dy)) * HB + (oz + 1 + dz);
           const int e = ht.base[hh + 1];
           // four candidates per step: their LDS reads are in flight together
+          // (up to 3 past the cell, into the next cell or the 3 padding slots
+          // after the halo; masked out below)
           for (int j0 = ht.base[hh]; j0 < e; j0 += 4) {
             float4 q[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) q[u] = hpos[min(j0 + u, e - 1)];
-            unsigned hit = 0, isnear = 0;
+            for (int u = 0; u < 4; ++u) q[u] = hpos[j0 + u];
+            unsigned hit = 0;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               float ddx = p.x - q[u].x, ddy = p.y - q[u].y, ddz = p.z - q[u].z;
@@ -633,52 +644,46 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
               }
               const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
               const int j = j0 + u;
-              if (j < e && j != li && r2 <= rc2) {
-                hit |= 1u << u;
-                if (NEAR && r2 < near2) isnear |= 1u << u;
-              }
+              hit |= (j < e && j != li && r2 <= rc2) ? 1u << u : 0u;
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              if (hit & (1u << u)) {
-                const int slot = k & 7;
-                const uint64_t v = (uint64_t)(j0 + u) << (16 * (slot & 3));
-                if (slot < 4) lo |= v;
-                else hi |= v;
-                if (slot == 7) {
-                  if ((k >> 3) < (cap >> 3))
-                    row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
-                                                               (uint32_t)(hi >> 32));
-                  lo = hi = 0;
-                }
-                ++k;
-              }
-              if (NEAR && (isnear & (1u << u))) {
-                const int slot = kn & 7;
-                const uint64_t v = (uint64_t)(j0 + u) << (16 * (slot & 3));
-                if (slot < 4) nlo |= v;
-                else nhi |= v;
-                if (slot == 7) {
-                  if ((kn >> 3) < (cap_nr >> 3))
-                    rown[(size_t)(kn >> 3) * n + s] = make_uint4((uint32_t)nlo, (uint32_t)(nlo >> 32),
-                                                                 (uint32_t)nhi, (uint32_t)(nhi >> 32));
-                  nlo = nhi = 0;
-                }
-                ++kn;
-              }
+            // the hits of the step, compacted: field f of V is j0 plus the
+            // offset of the f-th set bit (pattern table), then V is
+            // shifted into the chunk at field k & 7; fields past 8 carry
+            // into the next chunk
+            const uint4 tb = pack_tab[hit];
+            const uint32_t X = (uint32_t)j0 * 0x10001u;
+            const uint64_t V = ((uint64_t)((X & tb.w) + tb.y) << 32) | (uint64_t)((X & tb.z) + tb.x);
+            const int sh = 16 * (k & 7);
+            const bool upper = sh >= 64;
+            const int s2 = upper ? sh - 64 : sh;
+            const uint64_t vs = V << s2, spill = s2 ? V >> (64 - s2) : 0ull;
+            lo |= upper ? 0ull : vs;
+            hi |= upper ? vs : spill;
+            const int k1 = k + __builtin_popcount(hit);
+            if ((k1 >> 3) != (k >> 3)) {
+              if ((k >> 3) < (cap >> 3))
+                row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
+                                                           (uint32_t)(hi >> 32));
+              lo = upper ? spill : 0ull;
+              hi = 0;
             }
+            k = k1;
           }
         }
-    if ((k & 7) && (k >> 3) < (cap >> 3))
+    if ((k & 7) && (k >> 3) < (cap >> 3)) {
+      // the rest of the last chunk points at the zero-source slot the
+      // product stages after the halo (index = halo size)
+      const uint64_t sent = (uint64_t)ht.base[NH];
+#pragma unroll
+      for (int sl = 1; sl < 8; ++sl) {
+        if (sl < (k & 7)) continue;
+        const uint64_t v = sent << (16 * (sl & 3));
+        if (sl < 4) lo |= v;
+        else hi |= v;
+      }
       row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
-    cnt_out[s] = k;
-    if (NEAR) {
-      if ((kn & 7) && (kn >> 3) < (cap_nr >> 3))
-        rown[(size_t)(kn >> 3) * n + s] = make_uint4((uint32_t)nlo, (uint32_t)(nlo >> 32), (uint32_t)nhi,
-                                                     (uint32_t)(nhi >> 32));
-      cnt_nr[s] = kn;
-      mxn = max(mxn, kn);
     }
+    cnt_out[s] = k;
     mine += (unsigned long long)k;
     mx = max(mx, k);
   }
@@ -686,46 +691,49 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
   // flags serialises at the L2
   const unsigned long long tot = wave_sum(mine);
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    mx = max(mx, __shfl_xor(mx, off, 64));
-    mxn = max(mxn, __shfl_xor(mxn, off, 64));
-  }
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
   __shared__ unsigned long long wtot[8];
-  __shared__ int wmx[8], wmxn[8];
+  __shared__ int wmx[8];
   const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     wtot[wave] = tot;
     wmx[wave] = mx;
-    wmxn[wave] = mxn;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long t = 0;
-    int m = 0, mn = 0;
+    int m = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
       t += wtot[w];
       m = max(m, wmx[w]);
-      mn = max(mn, wmxn[w]);
     }
     if (t) atomicAdd((unsigned long long *)(flags + 2), t);
     atomicMax(&flags[1], m);
     atomicMax(&flags[5], m);
-    if (NEAR) atomicMax(&flags[7], mn);
   }
 }
 
-// Preconditioner features from the near list, one thread per target
-// (FeatAcc; F, G from the LDS table).
+// Preconditioner features (FeatAcc; F, G from the LDS table).  Three lanes
+// per target, as in the product:
+// lane q of a group scans neighbour chunks q, q + 3, ... against the staged
+// halo and queues every entry closer than 4.5a in its column of an LDS
+// queue.  The queue is drained (one FeatAcc.add per entry) when some lane of
+// the wavefront could overflow it, and at the end, so a wavefront spends on
+// the features about its largest near count rather than the largest per
+// chunk summed over chunks.  The three partial sums are then combined with
+// lane shuffles (the minimum for f21).
+constexpr int kFeatQ = 16;  // queue entries per lane
 template <int B, bool UNWRAP>
-__global__ __launch_bounds__(512) void k_feat_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
-                                                  int nc, float cs, int n, float L, float invL,
-                                                  const uint16_t *__restrict__ nbr_nr, const int *__restrict__ cnt,
-                                                  const int *__restrict__ cnt_nr, const float4 *__restrict__ tab,
-                                                  float inv_dr, float inv_mu0, float fself, float a,
-                                                  uint16_t *__restrict__ feat) {
+__global__ __launch_bounds__(1024) void k_feat_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
+                                                   int nc, float cs, int n, float L, float invL,
+                                                   const uint16_t *__restrict__ nbr, const int *__restrict__ cnt,
+                                                   const float4 *__restrict__ tab, float inv_dr, float inv_mu0,
+                                                   float fself, float a, float near2, uint16_t *__restrict__ feat) {
   constexpr int NH = Halo<B>::NH;
+  constexpr int G = 3, GPW = 64 / G;
   extern __shared__ float4 hpos[];
   __shared__ HaloTab ht;
+  __shared__ uint16_t queue[kFeatQ * 1024];
   __shared__ float4 ftab[kTableK + 1];
   for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) ftab[k] = tab[k];
   halo_setup<B>(cell_start, nc, ht);
@@ -741,37 +749,88 @@ __global__ __launch_bounds__(512) void k_feat_lds(const float4 *__restrict__ pos
   __syncthreads();
   const FGTable fg{ftab, inv_dr};
   const int ntarg = ht.tpre[ht.ntc];
-  const uint4 *row = (const uint4 *)nbr_nr;
-  for (int i = threadIdx.x; i < ntarg; i += blockDim.x) {
-    int h, li, s;
-    target_of(ht, i, h, li, s);
+  const uint4 *row = (const uint4 *)nbr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / G, g = lane - grp * G;
+  const bool ingrp = grp < GPW;
+  uint16_t *myq = queue + threadIdx.x;  // entry t at myq[1024 t]
+  for (int i0 = 0; i0 < ntarg; i0 += (int)(blockDim.x >> 6) * GPW) {
+    const int i = i0 + wave * GPW + grp;
+    const bool act = ingrp && i < ntarg;
+    int h = 0, li = 0, s = 0;
+    if (act) target_of(ht, i, h, li, s);
     const float4 p = hpos[li];
     FeatAcc<float> acc;
-    acc.init(fself);
-    const int kn = cnt_nr[s];
-    for (int kb = 0; kb < kn; kb += 8) {
-      const uint4 pk = row[(size_t)(kb >> 3) * n + s];
+    acc.init(0.0f);
+    int nq = 0;
+    // one near pair into the sums (F, G - F from the LDS table)
+    auto add = [&](const float4 &q) {
+      float ddx = p.x - q.x, ddy = p.y - q.y, ddz = p.z - q.z;
+      if (!UNWRAP) {
+        ddx = min_image(ddx, L, invL);
+        ddy = min_image(ddy, L, invL);
+        ddz = min_image(ddz, L, invL);
+      }
+      const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+      const bool nz = r2 > 1e-24f;
+      const float ir = nz ? __frsqrt_rn(r2) : 0.0f;
+      float Fm = fself / inv_mu0, Dm = 0.0f;
+      if (nz) fg.eval(r2, ir, Fm, Dm);
+      acc.add(ddx, ddy, ddz, r2 * ir, ir, Fm * inv_mu0, Dm * inv_mu0, a, 1.0f / (4.5f * a));
+    };
+    // two queue entries per pass: their LDS reads are in flight together
+    auto drain = [&]() {
+      for (int t = 0; t < nq; t += 2) {
+        const bool two = t + 1 < nq;
+        const int j0 = myq[1024 * t], j1 = myq[1024 * (two ? t + 1 : t)];
+        const float4 q0 = hpos[j0], q1 = hpos[j1];
+        add(q0);
+        if (two) add(q1);
+      }
+      nq = 0;
+    };
+    const int c = act ? cnt[s] : 0;
+    uint4 nxt = 8 * g < c ? row[(size_t)g * n + s] : make_uint4(0, 0, 0, 0);
+    for (int kb = 8 * g; kb < c; kb += 8 * G) {
+      const uint4 pk = nxt;
+      if (kb + 8 * G < c) nxt = row[(size_t)((kb >> 3) + G) * n + s];
       const uint32_t wd[4] = {pk.x, pk.y, pk.z, pk.w};
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        if (kb + u < kn) {
-          const float4 q = hpos[(wd[u >> 1] >> (16 * (u & 1))) & 0xFFFF];
-          float ddx = p.x - q.x, ddy = p.y - q.y, ddz = p.z - q.z;
-          if (!UNWRAP) {
-            ddx = min_image(ddx, L, invL);
-            ddy = min_image(ddy, L, invL);
-            ddz = min_image(ddz, L, invL);
-          }
-          const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          const bool nz = r2 > 1e-24f;
-          const float ir = nz ? __frsqrt_rn(r2) : 0.0f;
-          float Fm = fself / inv_mu0, Dm = 0.0f;
-          if (nz) fg.eval(r2, ir, Fm, Dm);
-          acc.add(ddx, ddy, ddz, r2 * ir, ir, Fm * inv_mu0, Dm * inv_mu0, a, 1.0f / (4.5f * a));
+        const int j = (wd[u >> 1] >> (16 * (u & 1))) & 0xFFFF;
+        const float4 q = hpos[kb + u < c ? j : li];
+        float ddx = p.x - q.x, ddy = p.y - q.y, ddz = p.z - q.z;
+        if (!UNWRAP) {
+          ddx = min_image(ddx, L, invL);
+          ddy = min_image(ddy, L, invL);
+          ddz = min_image(ddz, L, invL);
+        }
+        const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+        if (kb + u < c && r2 < near2) {
+          myq[1024 * nq] = (uint16_t)j;
+          ++nq;
         }
       }
+      // the next chunk adds at most 8 entries
+      if (__any(nq > kFeatQ - 8)) drain();
     }
-    acc.store(feat + (size_t)s * kNFeat, cnt[s]);
+    drain();
+    // combine the G lanes of the target (lanes G grp .. G grp + G - 1)
+    const int base_lane = (lane / G) * G;
+#pragma unroll
+    for (int k = 0; k < kNFeat; ++k) {
+      if (k == 3 || k == 23) continue;  // set by store() / the self value
+      float v = acc.f[k];
+#pragma unroll
+      for (int o = 1; o < G; ++o) {
+        const int srcl = base_lane + o < 64 ? base_lane + o : lane;
+        const float t = __shfl(acc.f[k], srcl, 64);
+        v = k == 21 ? fminf(v, t) : v + t;
+      }
+      acc.f[k] = v;
+    }
+    acc.f[23] = fself;
+    if (act && g == 0) acc.store(feat + (size_t)s * kNFeat, c);
   }
 }
 
@@ -780,14 +839,17 @@ __global__ __launch_bounds__(512) void k_feat_lds(const float4 *__restrict__ pos
 // table (mu0 F, mu0 (G - F) and their forward differences, one 16-byte read
 // per pair).  Three lanes per target (lane q of the group takes neighbour
 // chunks q, q + 3, ...; 21 groups per wavefront) are combined with lane
-// shuffles; each chunk of 8 neighbours is processed branch-free (missing
-// entries are masked) so its LDS reads can all be in flight.  With UNWRAP the
-// staged positions are the images nearest the block centre.
+// shuffles; each chunk of 8 neighbours is processed branch-free in two
+// halves of 4 (padding entries read the zero source), the LDS reads of a half
+// in flight together.  Registers are held to 64 so that two 1024-lane
+// workgroups share a compute unit: one stages its halo while the other
+// computes.  With UNWRAP the staged positions are the images nearest the
+// block centre.
 // With PC (Lanczos on A = P M_r P^T): src holds u = P^T r, and the
 // epilogue forms out = P (M_r u) / beta, v_m = r / beta (r from rsrc) and
 // alpha_m = <v_m, out>; Pm holds the rows of P_i as (x, y, z, 0).
 template <int B, bool UNWRAP, typename A, bool LZ, bool PC = false>
-__global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
                                                    const int *__restrict__ cell_start, int nc, float cs, int n,
                                                    int hcap, float L, float invL, const uint16_t *__restrict__ nbr,
                                                    const int *__restrict__ cnt, const float4 *__restrict__ tab,
@@ -867,55 +929,51 @@ __global__ __launch_bounds__(1024) void k_spmv_lds(const float4 *__restrict__ po
       const uint4 pk = nxt;
       if (kb + 8 * G < c) nxt = row[(size_t)((kb >> 3) + G) * n];
       const uint32_t wd[4] = {pk.x, pk.y, pk.z, pk.w};
-      int jj[8];
-      const int sentinel = ht.base[NH];
+      // entries past the count in the last chunk hold the zero-source slot;
+      // two halves of 4: all halo reads of a half first, then its table reads
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = (wd[u >> 1] >> (16 * (u & 1))) & 0xFFFF;
-        jj[u] = kb + u < c ? j : sentinel;  // padding reads the zero source
-      }
-      // all halo reads of the chunk first, then all table reads: two LDS
-      // round trips per chunk instead of two per neighbour
-      float4 q[8];
-      float2 wb[8];
+      for (int hf = 0; hf < 2; ++hf) {
+        int jj[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        q[u] = hA[jj[u]];
-        wb[u] = hB[jj[u]];
-      }
-      float dx[8], dy[8], dz[8], rinv[8], fr[8];
-      int kk[8];
+        for (int u = 0; u < 4; ++u) jj[u] = (wd[2 * hf + (u >> 1)] >> (16 * (u & 1))) & 0xFFFF;
+        float4 q[4];
+        float2 wb[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        dx[u] = pa.x - q[u].x;
-        dy[u] = pa.y - q[u].y;
-        dz[u] = pa.z - q[u].z;
-        if (!UNWRAP) {
-          dx[u] = min_image(dx[u], Ls, invLs);
-          dy[u] = min_image(dy[u], Ls, invLs);
-          dz[u] = min_image(dz[u], Ls, invLs);
+        for (int u = 0; u < 4; ++u) {
+          q[u] = hA[jj[u]];
+          wb[u] = hB[jj[u]];
         }
-        // r^2 floored at 1e-20 (table units): coincident spheres land on table entry 0,
-        // which holds the r -> 0 limit (mu0 F_self, 0), and d = 0 there
-        // makes the (G - F) term vanish; no branch and no select
-        const float r2 = fmaxf(dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u], 1e-20f);
-        rinv[u] = __frsqrt_rn(r2);
-        const float uu = r2 * rinv[u];  // r in table units
-        kk[u] = min((int)uu, kTableK);
-        fr[u] = __builtin_amdgcn_fractf(uu);
-      }
-      float4 e[8];
+        float dx[4], dy[4], dz[4], rinv[4], fr[4];
+        int kk[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) e[u] = tabs[kk[u]];
+        for (int u = 0; u < 4; ++u) {
+          dx[u] = pa.x - q[u].x;
+          dy[u] = pa.y - q[u].y;
+          dz[u] = pa.z - q[u].z;
+          if (!UNWRAP) {
+            dx[u] = min_image(dx[u], Ls, invLs);
+            dy[u] = min_image(dy[u], Ls, invLs);
+            dz[u] = min_image(dz[u], Ls, invLs);
+          }
+          const float r2 = fmaxf(dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u], 1e-20f);
+          rinv[u] = __frsqrt_rn(r2);
+          const float uu = r2 * rinv[u];
+          kk[u] = min((int)uu, kTableK);
+          fr[u] = __builtin_amdgcn_fractf(uu);
+        }
+        float4 e[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const float wx = q[u].w, wy = wb[u].x, wz = wb[u].y;
-        const float Fm = fmaf(fr[u], e[u].z, e[u].x);
-        const float Dm = fmaf(fr[u], e[u].w, e[u].y);
-        const float pr = Dm * rinv[u] * rinv[u] * (dx[u] * wx + dy[u] * wy + dz[u] * wz);
-        ax = fmaf(pr, dx[u], fmaf(Fm, wx, ax));
-        ay = fmaf(pr, dy[u], fmaf(Fm, wy, ay));
-        az = fmaf(pr, dz[u], fmaf(Fm, wz, az));
+        for (int u = 0; u < 4; ++u) e[u] = tabs[kk[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float wx = q[u].w, wy = wb[u].x, wz = wb[u].y;
+          const float Fm = fmaf(fr[u], e[u].z, e[u].x);
+          const float Dm = fmaf(fr[u], e[u].w, e[u].y);
+          const float pr = Dm * rinv[u] * rinv[u] * (dx[u] * wx + dy[u] * wy + dz[u] * wz);
+          ax = fmaf(pr, dx[u], fmaf(Fm, wx, ax));
+          ay = fmaf(pr, dy[u], fmaf(Fm, wy, ay));
+          az = fmaf(pr, dz[u], fmaf(Fm, wz, az));
+        }
       }
     }
     // combine the G lanes of the target (lanes G grp .. G grp + G - 1)
@@ -1376,49 +1434,38 @@ template <typename K> static void allow_lds(K kernel, size_t bytes) {
 
 void launch_nbr_lds(pse_ctx *c) {
   ProfScope ps(c, PSE_STAGE_NBR);
-  const size_t smem = sizeof(float4) * (size_t)c->hcap;
+  const size_t smem = sizeof(float4) * (size_t)(c->hcap + 3);  // 3 slots read past the last cell
   const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L), rc2 = (float)(c->p.rcut * c->p.rcut);
-  const float near2 = (float)(20.25 * c->p.a * c->p.a);  // r < 4.5a
   auto *nb = (uint16_t *)c->nbr;
   const bool unwrap = c->d.nc >= c->lds_B + 3;
   auto go = [&](auto kern) {
     allow_lds(kern, smem);
     kern<<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
-                                                  c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags, near2,
-                                                  c->nbr_nr, c->nbr_nr_cnt, c->nbr_nr_cap);
+                                                  c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags);
   };
-  if (c->pc_on) {
-    if (c->lds_B == 2) {
-      if (unwrap) go(k_nbr_lds<2, true, true>);
-      else go(k_nbr_lds<2, false, true>);
-    } else {
-      if (unwrap) go(k_nbr_lds<1, true, true>);
-      else go(k_nbr_lds<1, false, true>);
-    }
+  if (c->lds_B == 2) {
+    if (unwrap) go(k_nbr_lds<2, true>);
+    else go(k_nbr_lds<2, false>);
   } else {
-    if (c->lds_B == 2) {
-      if (unwrap) go(k_nbr_lds<2, true, false>);
-      else go(k_nbr_lds<2, false, false>);
-    } else {
-      if (unwrap) go(k_nbr_lds<1, true, false>);
-      else go(k_nbr_lds<1, false, false>);
-    }
+    if (unwrap) go(k_nbr_lds<1, true>);
+    else go(k_nbr_lds<1, false>);
   }
 }
 
-// Preconditioner features on the LDS path, from the near list.
+// Preconditioner features on the LDS path, from the list and the staged halo.
 void launch_feat_lds(pse_ctx *c) {
   ProfScope ps(c, PSE_STAGE_PRECOND);
   const size_t smem = sizeof(float4) * (size_t)c->hcap;
   const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L);
   const bool unwrap = c->d.nc >= c->lds_B + 3;
   const float inv_mu0 = (float)(1.0 / c->d.mu0), fself = (float)(c->d.self_r / c->d.mu0);
+  const float near2 = (float)(20.25 * c->p.a * c->p.a);  // r < 4.5a
   auto go = [&](auto kern) {
     allow_lds(kern, smem);
-    kern<<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
-                                                  c->n, L, invL, (const uint16_t *)c->nbr_nr, c->nbr_cnt,
-                                                  c->nbr_nr_cnt, c->table, (float)(kTableK / c->p.rcut), inv_mu0,
-                                                  fself, (float)c->p.a, c->pc_feat);
+    kern<<<c->lds_blocks, 1024, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
+                                                  c->n, L, invL, (const uint16_t *)c->nbr, c->nbr_cnt,
+                                                  (const float4 *)c->table, (float)(kTableK / c->p.rcut), inv_mu0,
+                                                  fself, (float)c->p.a, near2, c->pc_feat);
   };
   if (c->lds_B == 2) {
     if (unwrap) go(k_feat_lds<2, true>);

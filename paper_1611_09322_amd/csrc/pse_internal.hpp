@@ -146,9 +146,6 @@ struct pse_ctx {
   int *cell_start = nullptr;
   int *nbr = nullptr;
   int *nbr_cnt = nullptr;
-  uint16_t *nbr_nr = nullptr;  // LDS path with the preconditioner: neighbours closer than 4.5a
-  int *nbr_nr_cnt = nullptr;
-  int nbr_nr_cap = 0;
   int nbr_cap = 0;
   int *flags = nullptr;     // [0] nonfinite, [1] list slots needed, [2..3] pairs, [4] max halo,
                             // [5] max neighbours, [6] preconditioner fallbacks
