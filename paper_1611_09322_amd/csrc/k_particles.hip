@@ -39,28 +39,58 @@ __global__ void k_wrap_bin(const T *__restrict__ pos, int n, T L, T invL, T inv_
   pos_w[i] = q;
 }
 
-// Exclusive scan of the cell counts (one block of 1024 threads).
-__global__ void k_scan_cells(const int *__restrict__ count, int *__restrict__ start, int *__restrict__ fill, int ncell) {
-  __shared__ int sh[1024];
-  const int per = (ncell + blockDim.x - 1) / blockDim.x;
-  const int b = threadIdx.x * per, e = min(b + per, ncell);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += count[i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const int v = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+// Exclusive scan of the cell counts, one workgroup of 1024 threads: the
+// counts pass through LDS in tiles of 16 per thread (coalesced loads and
+// stores), each thread sums its 16, the 1024 sums are scanned across
+// wavefronts, and a running carry links the tiles.  Also clears fill[].
+constexpr int kScanPer = 16;
+__global__ __launch_bounds__(1024) void k_scan_cells(const int *__restrict__ count, int *__restrict__ start,
+                                                     int *__restrict__ fill, int ncell) {
+  constexpr int TILE = 1024 * kScanPer;
+  __shared__ int tile[TILE];
+  __shared__ int wsum[16];
+  __shared__ int carry_sh;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int carry = 0;
+  for (int base = 0; base < ncell; base += TILE) {
+    for (int k = t; k < TILE; k += 1024) {
+      const int i = base + k;
+      tile[k] = i < ncell ? count[i] : 0;
+      if (i < ncell) fill[i] = 0;
+    }
     __syncthreads();
-    sh[threadIdx.x] += v;
+    int loc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) loc += tile[t * kScanPer + k];
+    // inclusive scan of the per-thread sums: within the wavefront, then
+    // across the 16 wavefronts
+    int v = loc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(v, off, 64);
+      if (lane >= off) v += u;
+    }
+    if (lane == 63) wsum[wave] = v;
     __syncthreads();
+    int wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += wsum[w];
+    int run = carry + wpre + v - loc;  // exclusive prefix of this thread's first cell
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int cnt = tile[t * kScanPer + k];
+      tile[t * kScanPer + k] = run;
+      run += cnt;
+    }
+    if (t == 1023) carry_sh = run;
+    __syncthreads();
+    for (int k = t; k < TILE; k += 1024) {
+      const int i = base + k;
+      if (i < ncell) start[i] = tile[k];
+    }
+    carry = carry_sh;
+    __syncthreads();  // the tile and carry_sh are rewritten next
   }
-  int run = sh[threadIdx.x] - s;
-  for (int i = b; i < e; ++i) {
-    start[i] = run;
-    run += count[i];
-    fill[i] = 0;
-  }
-  if (threadIdx.x == blockDim.x - 1) start[ncell] = sh[threadIdx.x];
+  if (t == 0) start[ncell] = carry;
 }
 
 __global__ void k_scatter(const int *__restrict__ cell_of, const int *__restrict__ start, int *__restrict__ fill,
@@ -72,11 +102,23 @@ __global__ void k_scatter(const int *__restrict__ cell_of, const int *__restrict
 }
 
 // Order each cell's members by caller index: the sorted order (and with it
-// every summation order downstream) is then deterministic.
-__global__ void k_cell_sort(const int *__restrict__ start, int *__restrict__ perm, int ncell) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// every summation order downstream) is then deterministic.  One wavefront
+// per cell: with at most 64 members each lane holds one and its rank is the
+// number of smaller indices (the indices are distinct); larger cells fall
+// back to an insertion sort by lane 0.
+__global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start, int *__restrict__ perm, int ncell) {
+  const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
   if (c >= ncell) return;
-  const int b = start[c], e = start[c + 1];
+  const int b = start[c], e = start[c + 1], m = e - b;
+  if (m <= 64) {
+    const int v = lane < m ? perm[b + lane] : 0x7FFFFFFF;
+    int rank = 0;
+    for (int j = 0; j < m; ++j) rank += __shfl(v, j, 64) < v ? 1 : 0;
+    if (lane < m) perm[b + rank] = v;
+    return;
+  }
+  if (lane != 0) return;
   for (int i = b + 1; i < e; ++i) {
     const int v = perm[i];
     int j = i - 1;
@@ -1385,7 +1427,7 @@ void launch_bin(pse_ctx *c, const void *pos) {
                                                      c->cell_of, c->cell_count, c->flags);
   k_scan_cells<<<1, 1024, 0, c->stream>>>(c->cell_count, c->cell_start, c->cell_count + c->ncell, c->ncell);
   k_scatter<<<nblk(n, 256), 256, 0, c->stream>>>(c->cell_of, c->cell_start, c->cell_count + c->ncell, c->perm, n);
-  k_cell_sort<<<nblk(c->ncell, 256), 256, 0, c->stream>>>(c->cell_start, c->perm, c->ncell);
+  k_cell_sort<<<nblk(c->ncell, 4), 256, 0, c->stream>>>(c->cell_start, c->perm, c->ncell);
   k_gather_pos<T4><<<nblk(n, 256), 256, 0, c->stream>>>((const T4 *)c->pos_w, c->perm, (T4 *)c->pos_s, n);
 }
 
