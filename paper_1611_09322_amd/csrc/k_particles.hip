@@ -33,7 +33,21 @@ __global__ void k_wrap_bin(const T *__restrict__ pos, int n, T L, T invL, T inv_
   const int cz = min((int)(z * inv_cs), nc - 1);
   const int c = (cx * nc + cy) * nc + cz;
   cell_of[i] = c;
-  atomicAdd(&cell_count[c], 1);
+  // one atomic per distinct cell of the wavefront (consecutive particles
+  // often share cells): the lanes of the lowest pending lane's cell go
+  // together
+  const int lane = threadIdx.x & 63;
+  bool done = false;
+  while (true) {
+    const unsigned long long rem = __ballot(!done);
+    if (!rem) break;
+    const int leader = __ffsll((long long)rem) - 1;
+    const int c0 = __shfl(c, leader, 64);
+    const bool mine = !done && c == c0;
+    const unsigned long long m = __ballot(mine);
+    if (lane == leader) atomicAdd(&cell_count[c0], __popcll(m));
+    done = done || mine;
+  }
   typename vec4<T>::type q;
   q.x = x; q.y = y; q.z = z; q.w = T(0);
   pos_w[i] = q;
@@ -98,7 +112,26 @@ __global__ void k_scatter(const int *__restrict__ cell_of, const int *__restrict
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int c = cell_of[i];
-  perm[start[c] + atomicAdd(&fill[c], 1)] = i;
+  // slots reserved per distinct cell of the wavefront (as in k_wrap_bin);
+  // the order inside a cell is fixed afterwards by k_cell_sort
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  bool done = false;
+  int slot = 0;
+  while (true) {
+    const unsigned long long rem = __ballot(!done);
+    if (!rem) break;
+    const int leader = __ffsll((long long)rem) - 1;
+    const int c0 = __shfl(c, leader, 64);
+    const bool mine = !done && c == c0;
+    const unsigned long long m = __ballot(mine);
+    int b = 0;
+    if (lane == leader) b = atomicAdd(&fill[c0], __popcll(m));
+    b = __shfl(b, leader, 64);
+    if (mine) slot = b + __popcll(m & below);
+    done = done || mine;
+  }
+  perm[start[c] + slot] = i;
 }
 
 // Order each cell's members by caller index: the sorted order (and with it
@@ -764,9 +797,10 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
 // the features about its largest near count rather than the largest per
 // chunk summed over chunks.  The three partial sums are then combined with
 // lane shuffles (the minimum for f21).
-constexpr int kFeatQ = 16;  // queue entries per lane
+constexpr int kFeatQ = 16;    // queue entries per lane
+constexpr int kFeatNT = 512;  // lanes per workgroup (two workgroups per CU)
 template <int B, bool UNWRAP>
-__global__ __launch_bounds__(1024) void k_feat_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
+__global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
                                                    int nc, float cs, int n, float L, float invL,
                                                    const uint16_t *__restrict__ nbr, const int *__restrict__ cnt,
                                                    const float4 *__restrict__ tab, float inv_dr, float inv_mu0,
@@ -775,7 +809,7 @@ __global__ __launch_bounds__(1024) void k_feat_lds(const float4 *__restrict__ po
   constexpr int G = 3, GPW = 64 / G;
   extern __shared__ float4 hpos[];
   __shared__ HaloTab ht;
-  __shared__ uint16_t queue[kFeatQ * 1024];
+  __shared__ uint16_t queue[kFeatQ * kFeatNT];
   __shared__ float4 ftab[kTableK + 1];
   for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) ftab[k] = tab[k];
   halo_setup<B>(cell_start, nc, ht);
@@ -795,7 +829,7 @@ __global__ __launch_bounds__(1024) void k_feat_lds(const float4 *__restrict__ po
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / G, g = lane - grp * G;
   const bool ingrp = grp < GPW;
-  uint16_t *myq = queue + threadIdx.x;  // entry t at myq[1024 t]
+  uint16_t *myq = queue + threadIdx.x;  // entry t at myq[kFeatNT t]
   for (int i0 = 0; i0 < ntarg; i0 += (int)(blockDim.x >> 6) * GPW) {
     const int i = i0 + wave * GPW + grp;
     const bool act = ingrp && i < ntarg;
@@ -824,7 +858,7 @@ __global__ __launch_bounds__(1024) void k_feat_lds(const float4 *__restrict__ po
     auto drain = [&]() {
       for (int t = 0; t < nq; t += 2) {
         const bool two = t + 1 < nq;
-        const int j0 = myq[1024 * t], j1 = myq[1024 * (two ? t + 1 : t)];
+        const int j0 = myq[kFeatNT * t], j1 = myq[kFeatNT * (two ? t + 1 : t)];
         const float4 q0 = hpos[j0], q1 = hpos[j1];
         add(q0);
         if (two) add(q1);
@@ -849,7 +883,7 @@ __global__ __launch_bounds__(1024) void k_feat_lds(const float4 *__restrict__ po
         }
         const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
         if (kb + u < c && r2 < near2) {
-          myq[1024 * nq] = (uint16_t)j;
+          myq[kFeatNT * nq] = (uint16_t)j;
           ++nq;
         }
       }
@@ -1504,8 +1538,8 @@ void launch_feat_lds(pse_ctx *c) {
   const float near2 = (float)(20.25 * c->p.a * c->p.a);  // r < 4.5a
   auto go = [&](auto kern) {
     allow_lds(kern, smem);
-    kern<<<c->lds_blocks, 1024, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
-                                                  c->n, L, invL, (const uint16_t *)c->nbr, c->nbr_cnt,
+    kern<<<c->lds_blocks, kFeatNT, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc,
+                                                     (float)c->d.cs, c->n, L, invL, (const uint16_t *)c->nbr, c->nbr_cnt,
                                                   (const float4 *)c->table, (float)(kTableK / c->p.rcut), inv_mu0,
                                                   fself, (float)c->p.a, near2, c->pc_feat);
   };
