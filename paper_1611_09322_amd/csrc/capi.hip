@@ -56,6 +56,7 @@ void free_ctx(pse_ctx *c) {
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->flags_h) (void)hipHostFree(c->flags_h);
+  if (c->pc_fb_h) (void)hipHostFree(c->pc_fb_h);
   if (c->lz_h) (void)hipHostFree(c->lz_h);
   delete c;
 }
@@ -145,8 +146,19 @@ pse_status lz_start(pse_ctx *c, const void *z_sorted) {
   return hip_status(hipMemcpyAsync(c->lz_h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream));
 }
 
+// The fallback count of the last set_positions, once its copy has landed
+// (the caller has synchronised the stream since, or `synced` is false and
+// this waits).
+void take_pc_fallbacks(pse_ctx *c, bool synced) {
+  if (!c->pc_fb_pending) return;
+  if (!synced) (void)hipStreamSynchronize(c->stream);
+  c->pc_fallbacks = *c->pc_fb_h;
+  c->pc_fb_pending = false;
+}
+
 template <typename T, typename A>
 pse_status lz_finish(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
+  take_pc_fallbacks(c, true);
   auto *h = (LzState<A> *)c->lz_h;
   const bool pc = c->pc_on && c->pc_have_w;
   const int maxit = c->p.lanczos_max_iter;
@@ -375,10 +387,10 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
     // build accumulated them itself), network, blocks, fallbacks
     if (c->lds_B) launch_feat_lds(c);
     launch_pc_blocks<T>(c);
-    if (hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
+    // the count is taken after the next synchronisation (no wait here)
+    if (hipMemcpyAsync(c->pc_fb_h, c->flags + 6, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
       return PSE_ERR_HIP;
-    c->pc_fallbacks = c->flags_h[6];
+    c->pc_fb_pending = true;
   }
   c->have_pos = true;
   return hip_status(hipGetLastError());
@@ -574,6 +586,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
 
   c->flags = (int *)al.dev(sizeof(int) * 8);
   c->flags_h = (int *)al.host(sizeof(int) * 8);
+  c->pc_fb_h = (int *)al.host(sizeof(int));
   for (auto &v : c->vbuf) v = al.dev(4 * T * n);  // [8], [9]: preconditioned Lanczos
   c->V = al.dev(4 * T * n * (size_t)(kMaxIter + 1));
   const size_t lzbytes = c->acc_dbl ? sizeof(LzState<double>) : sizeof(LzState<float>);
@@ -844,6 +857,7 @@ pse_status pse_precond_set_weights(pse_ctx *c, const void *w_host, size_t bytes)
       hipStreamSynchronize(c->stream) != hipSuccess)
     return PSE_ERR_HIP;
   c->pc_fallbacks = c->flags_h[6];
+  c->pc_fb_pending = false;
   return hip_status(hipGetLastError());
 }
 
@@ -861,6 +875,7 @@ pse_status pse_precond_blocks(pse_ctx *c, void *P_out, int32_t *fallbacks) {
   if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
   if (c->dbl) launch_unsort_blocks<double>(c, (float *)P_out);
   else launch_unsort_blocks<float>(c, (float *)P_out);
+  take_pc_fallbacks(c, false);
   if (fallbacks) *fallbacks = c->pc_fallbacks;
   return hip_status(hipGetLastError());
 }

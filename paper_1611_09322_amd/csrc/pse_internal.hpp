@@ -186,4 +186,6 @@ struct pse_ctx {
   void *pc_P = nullptr;        // T [n][12]: rows of P_i as (x, y, z, 0)
   void *pc_Pinv = nullptr;     // T [n][12]: rows of P_i^-1
   int pc_fallbacks = 0;        // blocks replaced by I at the last set_positions
+  int *pc_fb_h = nullptr;      // pinned: the device count, copied back without a wait
+  bool pc_fb_pending = false;  // pc_fb_h not yet taken into pc_fallbacks
 };
