@@ -605,9 +605,10 @@ __global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__
 // 8 nodes x 3 components in registers.  Particles whose P^3 support overlaps
 // the tile are found from the linked cells covering the tile plus the
 // support reach, one (x, y) cell column at a time (one candidate per thread,
-// hits compacted into an LDS list).  For each listed particle the wavefront
-// evaluates the 3P separable Gaussian weights with one exp per lane and
-// reads them across lanes.  Every node is written once, deterministically
+// hits compacted into an LDS list).  For each listed particle every lane
+// evaluates its own weights: the (x, y) factor with one exponential, the z
+// factors of the wavefront's overlapping nodes by the Gaussian recurrence
+// (two exponentials); no cross-lane reads.  Every node is written once, deterministically
 // (fixed particle order), with no grid clear.  Needs M >= 2 max(8, 8 NW) + P
 // so that the nearest periodic image of a base node relative to the tile is
 // unique.
@@ -619,9 +620,10 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
   constexpr int TX = 8, TY = 8, TZ = 8 * NW;
   constexpr int NT = 64 * NW;
   static_assert(3 * P <= 64, "weights of one particle must fit one wavefront");
-  __shared__ int ls0[3][NT];
-  __shared__ T lpu[3][NT];
-  __shared__ T lf[3][NT];
+  using T4 = typename vec4<T>::type;
+  __shared__ T4 lpu[NT];  // image coordinate of the particle nearest the tile
+  __shared__ T4 lf[NT];   // its force
+  __shared__ int ls0[NT];  // first support node per axis (tile-local) + 64, 8 bits each
   __shared__ uint16_t sidx[NW][NT];  // per z slab: list entries whose support reaches it
   __shared__ int scnt[NW][NW];       // [slab][wavefront that listed them]
   // neighbouring tiles read the same cells: keep them on one XCD
@@ -635,6 +637,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
   const int lx = lane >> 3, ly = lane & 7;
   const int zw = wave * 8;  // first z node (tile-local) of this wavefront
   const int half = M / 2;
+  const T qz = gauss_exp(T(-2) * h * h * inv2s2);  // ratio step of the z-weight recurrence
   T acc[3][8];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -704,46 +707,43 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
           if (inw) sidx[w][64 * wave + __popcll(bw & below)] = (uint16_t)e;
         }
         if (hit) {
-          const auto fv = f[t];
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            ls0[d][e] = s0[d];
-            lpu[d][e] = pu[d];
-          }
-          lf[0][e] = fv.x;
-          lf[1][e] = fv.y;
-          lf[2][e] = fv.z;
+          T4 pv, fv = f[t];
+          pv.x = pu[0];
+          pv.y = pu[1];
+          pv.z = pu[2];
+          pv.w = T(0);
+          fv.w = T(0);
+          lpu[e] = pv;
+          lf[e] = fv;
+          ls0[e] = (s0[0] + 64) | ((s0[1] + 64) << 8) | ((s0[2] + 64) << 16);
         }
         __syncthreads();
         for (int from = 0; from < NW; ++from) {
         const int nf = scnt[wave][from];
         for (int k = 0; k < nf; ++k) {
           const int e = sidx[wave][64 * from + k];
-          const int sz = ls0[2][e];
-          const int sx = ls0[0][e], sy = ls0[1][e];
-          // lanes 0..3P-1: the separable weights along x, y, z
-          T wv = T(0);
-          if (lane < 3 * P) {
-            const int d = lane / P, j = lane % P;
-            const int s0d = d == 0 ? sx : (d == 1 ? sy : sz);
-            const T dd = (T)(t0[d] + s0d + j) * h - lpu[d][e];
-            wv = gauss_exp(-dd * dd * inv2s2);
-          }
+          const int sp = ls0[e];
+          const T4 pv = lpu[e], fv = lf[e];
+          const int sx = (sp & 255) - 64, sy = ((sp >> 8) & 255) - 64, sz = ((sp >> 16) & 255) - 64;
           const int ix = lx - sx, iy = ly - sy;
           const bool in = ix >= 0 && ix < P && iy >= 0 && iy < P;
-          const T wxy = norm * __shfl(wv, in ? ix : 0, 64) * __shfl(wv, in ? P + iy : 0, 64);
-          const T fx = lf[0][e], fy = lf[1][e], fz = lf[2][e];
+          const T dx = (T)(t0x + lx) * h - pv.x, dy = (T)(t0y + ly) * h - pv.y;
+          const T wxy = in ? norm * gauss_exp(-(dx * dx + dy * dy) * inv2s2) : T(0);
+          // z weights from the wavefront's first node inside the support
+          // (uniform): w_{q+1} = w_q r_q, r_{q+1} = r_q qz
+          const int q0 = max(0, sz - zw);
+          const T dz0 = (T)(t0z + zw + q0) * h - pv.z;
+          T wz = gauss_exp(-dz0 * dz0 * inv2s2), rz = gauss_exp(-(T(2) * dz0 + h) * h * inv2s2);
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             const int iz = zw + q - sz;  // uniform across the wavefront
             if (iz >= 0 && iz < P) {
-              // cross-lane read first, by every lane: a shuffle under a lane
-              // condition would read inactive source lanes
-              const T wzq = __shfl(wv, 2 * P + iz, 64);
-              const T w = in ? wxy * wzq : T(0);
-              acc[0][q] += w * fx;
-              acc[1][q] += w * fy;
-              acc[2][q] += w * fz;
+              const T w = wxy * wz;
+              acc[0][q] += w * fv.x;
+              acc[1][q] += w * fv.y;
+              acc[2][q] += w * fv.z;
+              wz *= rz;
+              rz *= qz;
             }
           }
         }
