@@ -619,7 +619,6 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
                                                          T h, T invh, T inv2s2, T norm, T *__restrict__ grid) {
   constexpr int TX = 8, TY = 8, TZ = 8 * NW;
   constexpr int NT = 64 * NW;
-  static_assert(3 * P <= 64, "weights of one particle must fit one wavefront");
   using T4 = typename vec4<T>::type;
   __shared__ T4 lpu[NT];  // image coordinate of the particle nearest the tile
   __shared__ T4 lf[NT];   // its force
@@ -768,10 +767,13 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
 // ----------------------------------------------------------- launchers
 template <typename T, int M> struct GridCfg {
   // fused x pass holds 3 components: TZ columns x M x 3 complex in LDS
-  static constexpr int TZ = (sizeof(T) == 4) ? ((2048 / M) < (M / 2) ? (2048 / M) : (M / 2))
+  // (24 KB at M = 256 FP32)
+  static constexpr int TZ = (sizeof(T) == 4) ? ((1024 / M) < (M / 2) ? (1024 / M) : (M / 2))
                                              : ((1024 / M) < (M / 2) ? (1024 / M) : (M / 2));
-  static constexpr int TZ1 = (sizeof(T) == 4) ? ((8192 / M) < (M / 2) ? (8192 / M) : (M / 2))
-                                              : ((4096 / M) < (M / 2) ? (4096 / M) : (M / 2));
+  // strided y pass: TZ1 columns x M complex in LDS (32 KB at M = 256 FP32:
+  // four workgroups per CU keep enough loads in flight)
+  static constexpr int TZ1 = (sizeof(T) == 4) ? ((4096 / M) < (M / 2) ? (4096 / M) : (M / 2))
+                                              : ((2048 / M) < (M / 2) ? (2048 / M) : (M / 2));
   static constexpr int NL = (sizeof(T) == 4) ? ((8192 / M) < 64 ? (8192 / M) : 64) : ((4096 / M) < 64 ? (4096 / M) : 64);
 };
 
@@ -791,11 +793,11 @@ static void fft_z(pse_ctx *c, const void *src, void *dst, int dir) {
 }
 
 // z pass on the interleaved real grid: NXY (x, y) columns (3 NXY lines) per
-// workgroup, at most 48 KB of LDS
+// workgroup, at most 24 KB of LDS (six workgroups per CU)
 template <typename T, int M>
 static void fft_z_aos(pse_ctx *c, const void *src, void *dst, int dir) {
   using CT = C<T>;
-  constexpr int NX0 = 49152 / (3 * M * (int)sizeof(T));
+  constexpr int NX0 = 24576 / (3 * M * (int)sizeof(T));
   constexpr int NXY = NX0 >= 16 ? 16 : (NX0 >= 8 ? 8 : (NX0 >= 4 ? 4 : (NX0 >= 2 ? 2 : 1)));
   const dim3 g(M * M / NXY);
   ProfScope ps(c, PSE_STAGE_FFT);
