@@ -597,20 +597,25 @@ template <int NH> __device__ __forceinline__ int halo_cell_of(const HaloTab &ht,
   return lo;
 }
 
-template <int NH>
-__device__ __forceinline__ void halo_stage(const float4 *__restrict__ g, float4 *l, const HaloTab &ht) {
+// LDS halo records: positions as float4, or as float3 where only the
+// coordinates are read (12 bytes: more workgroups per CU)
+__device__ __forceinline__ void halo_put(float4 *l, int e, const float4 &q) { l[e] = q; }
+__device__ __forceinline__ void halo_put(float3 *l, int e, const float4 &q) { l[e] = make_float3(q.x, q.y, q.z); }
+
+template <int NH, typename LT>
+__device__ __forceinline__ void halo_stage(const float4 *__restrict__ g, LT *l, const HaloTab &ht) {
   const int total = ht.base[NH];
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int h = halo_cell_of<NH>(ht, e);
-    l[e] = g[ht.start[h] + (e - ht.base[h])];
+    halo_put(l, e, g[ht.start[h] + (e - ht.base[h])]);
   }
 }
 
 // Stage positions shifted by whole box lengths to the periodic image nearest
 // to the block centre c: pairs then need no minimum-image correction (valid
 // when the block half-width plus rc stays below L/2, i.e. nc >= B + 3).
-template <int NH>
-__device__ __forceinline__ void halo_stage_unwrapped(const float4 *__restrict__ g, float4 *l, const HaloTab &ht,
+template <int NH, typename LT>
+__device__ __forceinline__ void halo_stage_unwrapped(const float4 *__restrict__ g, LT *l, const HaloTab &ht,
                                                      float cx, float cy, float cz, float L, float invL) {
   const int total = ht.base[NH];
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
@@ -619,7 +624,7 @@ __device__ __forceinline__ void halo_stage_unwrapped(const float4 *__restrict__ 
     q.x = cx + min_image(q.x - cx, L, invL);
     q.y = cy + min_image(q.y - cy, L, invL);
     q.z = cz + min_image(q.z - cz, L, invL);
-    l[e] = q;
+    halo_put(l, e, q);
   }
 }
 
@@ -658,7 +663,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
                                                  uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
                                                  int *__restrict__ flags) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
-  extern __shared__ float4 hpos[];
+  extern __shared__ float3 hpos3[];  // coordinates only
   __shared__ HaloTab ht;
   // for each 4-bit hit mask: (offsets of the set bits in 16-bit fields, low
   // and high word; 0xFFFF in each used field, low and high word)
@@ -680,9 +685,9 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
     const float c0 = 0.5f * B * cs;
-    halo_stage_unwrapped<NH>(pos, hpos, ht, bx * B * cs + c0, by * B * cs + c0, bz * B * cs + c0, L, invL);
+    halo_stage_unwrapped<NH>(pos, hpos3, ht, bx * B * cs + c0, by * B * cs + c0, bz * B * cs + c0, L, invL);
   } else {
-    halo_stage<NH>(pos, hpos, ht);
+    halo_stage<NH>(pos, hpos3, ht);
   }
   __syncthreads();
   const int ntarg = ht.tpre[ht.ntc];
@@ -693,7 +698,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
     int h, li, s;
     target_of(ht, i, h, li, s);
     const int ox = h / (HB * HB) - 1, oy = (h / HB) % HB - 1, oz = h % HB - 1;
-    const float4 p = hpos[li];
+    const float3 p = hpos3[li];
     int k = 0;
     uint64_t lo = 0, hi = 0;  // the current chunk of 8 packed 16-bit indices
     for (int dx = -1; dx <= 1; ++dx)
@@ -705,9 +710,9 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
           // (up to 3 past the cell, into the next cell or the 3 padding slots
           // after the halo; masked out below)
           for (int j0 = ht.base[hh]; j0 < e; j0 += 4) {
-            float4 q[4];
+            float3 q[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) q[u] = hpos[j0 + u];
+            for (int u = 0; u < 4; ++u) q[u] = hpos3[j0 + u];
             unsigned hit = 0;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -1510,7 +1515,7 @@ template <typename K> static void allow_lds(K kernel, size_t bytes) {
 
 void launch_nbr_lds(pse_ctx *c) {
   ProfScope ps(c, PSE_STAGE_NBR);
-  const size_t smem = sizeof(float4) * (size_t)(c->hcap + 3);  // 3 slots read past the last cell
+  const size_t smem = sizeof(float3) * (size_t)(c->hcap + 3);  // 3 slots read past the last cell
   const float L = (float)c->d.L, invL = (float)(1.0 / c->d.L), rc2 = (float)(c->p.rcut * c->p.rcut);
   auto *nb = (uint16_t *)c->nbr;
   const bool unwrap = c->d.nc >= c->lds_B + 3;
