@@ -1204,11 +1204,12 @@ __global__ void k_lz_update_pc(const typename vec4<T>::type *__restrict__ t,
     x.w = T(0);
     w[i] = x;
     v += (A)x.x * (A)x.x + (A)x.y * (A)x.y + (A)x.z * (A)x.z;
-    const T *p = P + (size_t)i * 12;
+    const auto *pr = (const typename vec4<T>::type *)(P + (size_t)i * 12);  // rows of P_i
+    const auto r0 = pr[0], r1 = pr[1], r2 = pr[2];
     typename vec4<T>::type o;
-    o.x = p[0] * x.x + p[4] * x.y + p[8] * x.z;
-    o.y = p[1] * x.x + p[5] * x.y + p[9] * x.z;
-    o.z = p[2] * x.x + p[6] * x.y + p[10] * x.z;
+    o.x = r0.x * x.x + r1.x * x.y + r2.x * x.z;
+    o.y = r0.y * x.x + r1.y * x.y + r2.y * x.z;
+    o.z = r0.z * x.x + r1.z * x.y + r2.z * x.z;
     o.w = T(0);
     u[i] = o;
   }

@@ -251,16 +251,22 @@ __global__ void k_pc_blocks(const float *__restrict__ y, int n, T *__restrict__ 
     } else {
       bad = 1;
     }
-    T *pp = P + (size_t)s * 12, *qq = Pinv + (size_t)s * 12;
+    // rows as (x, y, z, 0): one vector store each
+    using T4 = typename vec4<T>::type;
+    T4 *pp = (T4 *)(P + (size_t)s * 12), *qq = (T4 *)(Pinv + (size_t)s * 12);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        pp[4 * r + k] = m[3 * r + k];
-        qq[4 * r + k] = q[3 * r + k];
-      }
-      pp[4 * r + 3] = T(0);
-      qq[4 * r + 3] = T(0);
+      T4 u, v;
+      u.x = m[3 * r];
+      u.y = m[3 * r + 1];
+      u.z = m[3 * r + 2];
+      u.w = T(0);
+      v.x = q[3 * r];
+      v.y = q[3 * r + 1];
+      v.z = q[3 * r + 2];
+      v.w = T(0);
+      pp[r] = u;
+      qq[r] = v;
     }
   }
   unsigned long long b = (unsigned long long)bad;
@@ -278,11 +284,12 @@ __global__ void k_pc_pre(const typename vec4<T>::type *__restrict__ src, const T
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const auto v = src[s];
-  const T *p = P + (size_t)s * 12;
+  const auto *pr = (const typename vec4<T>::type *)(P + (size_t)s * 12);  // rows of P_s
+  const auto r0 = pr[0], r1 = pr[1], r2 = pr[2];
   typename vec4<T>::type o;
-  o.x = p[0] * v.x + p[4] * v.y + p[8] * v.z;
-  o.y = p[1] * v.x + p[5] * v.y + p[9] * v.z;
-  o.z = p[2] * v.x + p[6] * v.y + p[10] * v.z;
+  o.x = r0.x * v.x + r1.x * v.y + r2.x * v.z;
+  o.y = r0.y * v.x + r1.y * v.y + r2.y * v.z;
+  o.z = r0.z * v.x + r1.z * v.y + r2.z * v.z;
   o.w = T(0);
   u[s] = o;
 }
@@ -306,11 +313,12 @@ __global__ __launch_bounds__(256) void k_pc_post(const typename vec4<T>::type *_
   if (s < n) {
     const auto t = tp[s];
     const auto v = src[s];
-    const T *p = P + (size_t)s * 12;
+    const auto *pr = (const typename vec4<T>::type *)(P + (size_t)s * 12);  // rows of P_s
+    const auto r0 = pr[0], r1 = pr[1], r2 = pr[2];
     typename vec4<T>::type o, u;
-    o.x = (p[0] * t.x + p[1] * t.y + p[2] * t.z) * sc;
-    o.y = (p[4] * t.x + p[5] * t.y + p[6] * t.z) * sc;
-    o.z = (p[8] * t.x + p[9] * t.y + p[10] * t.z) * sc;
+    o.x = (r0.x * t.x + r0.y * t.y + r0.z * t.z) * sc;
+    o.y = (r1.x * t.x + r1.y * t.y + r1.z * t.z) * sc;
+    o.z = (r2.x * t.x + r2.y * t.y + r2.z * t.z) * sc;
     o.w = T(0);
     u.x = v.x * sc;
     u.y = v.y * sc;
@@ -346,11 +354,12 @@ __global__ void k_pc_apply(const T *__restrict__ Q, int n, typename vec4<T>::typ
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const auto v = y[s];
-  const T *q = Q + (size_t)s * 12;
+  const auto *qr = (const typename vec4<T>::type *)(Q + (size_t)s * 12);  // rows of P_s^-1
+  const auto r0 = qr[0], r1 = qr[1], r2 = qr[2];
   typename vec4<T>::type o;
-  o.x = q[0] * v.x + q[1] * v.y + q[2] * v.z;
-  o.y = q[4] * v.x + q[5] * v.y + q[6] * v.z;
-  o.z = q[8] * v.x + q[9] * v.y + q[10] * v.z;
+  o.x = r0.x * v.x + r0.y * v.y + r0.z * v.z;
+  o.y = r1.x * v.x + r1.y * v.y + r1.z * v.z;
+  o.z = r2.x * v.x + r2.y * v.y + r2.z * v.z;
   o.w = T(0);
   y[s] = o;
 }
