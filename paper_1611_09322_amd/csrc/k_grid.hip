@@ -531,11 +531,12 @@ __global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__
   }
 }
 
-// Interpolation: one wavefront per particle; lane -> (iz, ix) of the support
+// Interpolation: one wavefront per particle (16 per workgroup, neighbours in
+// cell order, so their support rows are shared in the L1); lane -> (iz, ix) of the support
 // (consecutive lanes read consecutive z nodes of one grid row, one
 // (c0, c1, c2, 0) vector per node of the interleaved grid), loop over iy.
 template <typename T, int P>
-__global__ __launch_bounds__(256) void k_interp(const typename vec4<T>::type *__restrict__ pos,
+__global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *__restrict__ pos,
                                                 const T *__restrict__ grid, int n,
                                                 typename vec4<T>::type *__restrict__ out, int M, T h,
                                                 T invh, T inv2s2, T norm_h3) {
@@ -904,9 +905,12 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
       k_spread<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T4 *)vec, n, (T *)grid_or_out, M,
                                                     (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)norm);
     }
-  } else
-    k_interp<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T *)vec, n, (T4 *)grid_or_out, M,
-                                                  (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)(norm * h * h * h));
+  } else {
+    // 16 particles (consecutive in cell order) per workgroup share the L1
+    k_interp<T, P><<<(int)(((long)n * 64 + 1023) / 1024), 1024, 0, c->stream>>>(
+        (const T4 *)c->pos_s, (const T *)vec, n, (T4 *)grid_or_out, M, (T)h, (T)(1.0 / h), (T)(0.5 / s2),
+        (T)(norm * h * h * h));
+  }
 }
 
 template <typename T>
