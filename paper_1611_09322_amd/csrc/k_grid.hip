@@ -871,14 +871,12 @@ void launch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoe
 // Tiled spreading needs M >= 2 max(TX, TY, TZ) + P (unique nearest image);
 // the tile edge along z is min(64, M/4) and 8 along x and y.
 static bool spread_tiled(int M, int P) {
-  const int tz = M >= 256 ? 64 : (M >= 128 ? 32 : (M >= 64 ? 16 : 8));
+  const int tz = M >= 128 ? 32 : (M >= 64 ? 16 : 8);  // tile depth 8 NW of the launch below
   const int tmax = tz > 8 ? tz : 8;
   return M >= 32 && M >= 2 * tmax + P;
 }
 bool spread_writes_whole_grid(int M, int P) { return spread_tiled(M, P); }
 
-// Tiled interpolation stages (T + P - 1)^... nodes: the staged extent must not
-// exceed the grid (no node staged twice) and must fit the LDS.
 template <typename T, int P>
 static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid_or_out) {
   using T4 = typename vec4<T>::type;
@@ -896,8 +894,9 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
             (const T4 *)c->pos_s, (const T4 *)vec, c->cell_start, c->d.nc, (T)c->d.cs, M, (T)h, (T)(1.0 / h),
             (T)(0.5 / s2), (T)norm, (T *)grid_or_out);
       };
-      if (M >= 256) go(std::integral_constant<int, 8>{});
-      else if (M >= 128) go(std::integral_constant<int, 4>{});
+      // tiles 8 x 8 x 32 from 128^3 up (measured best at 256^3 against
+      // depths 16 and 64)
+      if (M >= 128) go(std::integral_constant<int, 4>{});
       else if (M >= 64) go(std::integral_constant<int, 2>{});
       else go(std::integral_constant<int, 1>{});
     } else {
