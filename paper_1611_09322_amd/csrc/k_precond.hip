@@ -5,7 +5,7 @@
 // y = P^{-1} A^{1/2} z, whose covariance is M_r.  P_i = I + y_i, where y_i
 // is the output of a 24 -> 64 -> 64 -> 9 MLP (bf16 weights and activations,
 // fp32 sums on the MFMA units) applied to geometry features of the
-// particle's near field (accumulated during the neighbour build).  Blocks
+// particle's near field (computed from the neighbour list).  Blocks
 // that are not finite, nearly singular or ill conditioned fall back to I.
 // Training kernels (backward pass, Adam) run off the sampling path.
 #include "launch.hpp"

@@ -23,7 +23,7 @@ template <typename T> void launch_nbr(pse_ctx *c);
 // neighbour build with 16-bit LDS indices
 void launch_halo_size(pse_ctx *c, int B);
 void launch_nbr_lds(pse_ctx *c);
-void launch_feat_lds(pse_ctx *c);  // preconditioner features from the near chunks
+void launch_feat_lds(pse_ctx *c);  // preconditioner features from the list and the staged halo
 template <typename T, typename A> void launch_spmv(pse_ctx *c, const void *src, void *out, bool lz, void *vm_out);
 template <typename T, typename A> void launch_lz_init(pse_ctx *c, const void *z);
 template <typename T, typename A> void launch_lz_iter(pse_ctx *c, int m, const void *z);
