@@ -148,9 +148,11 @@ def run_variant(pse, torch, x, L, F, args, variant, weights=None):
         counter[0] += 1
         return st
 
-    # warm-up with every stage timed (after one untimed step that absorbs
-    # first-launch costs): find where the GPU time goes
+    # one untimed step absorbs first-launch costs; the library then picks its
+    # spreading / interpolation launch shapes on these positions (untimed);
+    # the warm-up runs with every stage timed: where the GPU time goes
     st = step()
+    tuned = s.autotune()
     s.profile(list(pse.STAGES))
     for _ in range(max(args.warmup - 1, 1)):
         st = step()
@@ -172,6 +174,7 @@ def run_variant(pse, torch, x, L, F, args, variant, weights=None):
     s.profile([])
     ms_step = 1e3 * dt / args.steps
     res = {
+        "autotune": {"spread_tile_depth": tuned[0], "interp_lanes": tuned[1]},
         "precond_fallbacks": st.precond_fallbacks,
         "value": len(x) * args.steps / dt,
         "ms_per_step": ms_step,
@@ -218,6 +221,8 @@ def run_batch(pse, torch, args):
     b = pse.Batch(specs)
     for k in range(args.warmup):
         b.set_positions(pos)
+        if k == 0:
+            b.autotune()  # untimed: launch shapes per grid size
         b.sample(11, k, dt=1e-3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()

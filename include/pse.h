@@ -294,9 +294,28 @@ pse_status pse_batch_set_positions(pse_batch *batch, const void *const *pos);
 pse_status pse_batch_sample(pse_batch *batch, uint64_t seed, uint64_t counter, double dt, const void *const *forces,
                             void *const *disp, pse_stats *stats);
 
+/* pse_autotune for the batch: the first replica of each (grid, support,
+ * precision) group is tuned on its positions (pse_batch_set_positions
+ * first) and the others take its choice.  Synchronises every stream. */
+pse_status pse_batch_autotune(pse_batch *batch);
+
 /* GPU milliseconds from the start of the last pse_batch_sample to the end
  * of each replica's displacement (host array of n_rep; waits for them). */
 pse_status pse_batch_latency(pse_batch *batch, float *ms);
+
+/* Launch-shape autotuning.  Times, on the context's current positions
+ * (pse_set_positions first; PSE_ERR_NO_POSITIONS otherwise), every valid
+ * depth of the owner-computes spreading tiles (8 x 8 x D nodes, D in 8, 16,
+ * 32, 64: D divides M and M >= 2 max(8, D) + P) and the interpolation
+ * workgroup sizes 256, 512 and 1024 lanes, three timed launches each after
+ * a warm-up, and keeps the fastest for later calls.  Synchronises the
+ * stream; uses the context's grid scratch only.  choice (host, 2 entries,
+ * may be NULL) receives D (0 when the grid is too small for tiles and
+ * spreading uses atomics) and the interpolation lanes.  Results after
+ * tuning may differ from those before in the last bits (spreading sums
+ * each node's particles in an order that follows the tile's cell scan);
+ * they stay deterministic for a given choice. */
+pse_status pse_autotune(pse_ctx *ctx, int32_t *choice);
 
 /* GPU-time accounting: for every stage whose bit (1 << pse_stage) is set in
  * stage_mask, each kernel launch of that stage is bracketed by HIP events on

@@ -110,6 +110,8 @@ _SIGS = {
     "pse_batch_sample": ([_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_VP),
                           ctypes.POINTER(_VP), ctypes.POINTER(Stats)], ctypes.c_int),
     "pse_batch_latency": ([_VP, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "pse_batch_autotune": ([_VP], ctypes.c_int),
+    "pse_autotune": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "pse_profile": ([_VP, ctypes.c_uint32], ctypes.c_int),
     "pse_profile_read": ([_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
 }
@@ -311,6 +313,18 @@ def pse_batch_latency(b, n):
     return list(ms)
 
 
+def pse_autotune(ctx):
+    """Pick the fastest spreading tile depth and interpolation workgroup size
+    on the current positions; returns (depth, lanes)."""
+    ch = (ctypes.c_int32 * 2)()
+    _check(load().pse_autotune(ctx, ch), "pse_autotune")
+    return int(ch[0]), int(ch[1])
+
+
+def pse_batch_autotune(b):
+    return _check(load().pse_batch_autotune(b), "pse_batch_autotune")
+
+
 def pse_profile(ctx, mask):
     return _check(load().pse_profile(ctx, mask), "pse_profile")
 
@@ -355,6 +369,11 @@ class Sampler:
             self.close()
         except Exception:
             pass
+
+    def autotune(self):
+        """Launch-shape autotuning on the current positions: returns the
+        spreading tile depth (0 without tiles) and interpolation lanes."""
+        return pse_autotune(self.ctx)
 
     def profile(self, stages):
         """Time the named stages with HIP events (see STAGES); [] = off."""
@@ -479,3 +498,7 @@ class Batch:
 
     def latency(self):
         return pse_batch_latency(self.b, len(self.n))
+
+    def autotune(self):
+        """pse_batch_autotune (after set_positions)."""
+        pse_batch_autotune(self.b)

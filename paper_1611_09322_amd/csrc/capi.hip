@@ -704,6 +704,13 @@ pse_status pse_wave_apply(pse_ctx *c, const void *F, void *u) {
   DISPATCH(c, (wave_apply_impl<T, A>(c, F, u, false)));
 }
 
+pse_status pse_autotune(pse_ctx *c, int32_t *choice) {
+  if (!c) return PSE_ERR_INVALID_ARG;
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  if (c->dbl) return autotune_grid<double>(c, choice);
+  return autotune_grid<float>(c, choice);
+}
+
 pse_status pse_profile(pse_ctx *c, uint32_t mask) {
   if (!c) return PSE_ERR_INVALID_ARG;
   c->prof_mask = mask & ((1u << PSE_NSTAGES) - 1);
@@ -828,6 +835,28 @@ pse_status pse_batch_sample(pse_batch *b, uint64_t seed, uint64_t counter, doubl
   });
   const pse_status sj = join(b);
   return st != PSE_OK ? st : sj;
+}
+
+pse_status pse_batch_autotune(pse_batch *b) {
+  if (!b) return PSE_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(b->user) != hipSuccess) return PSE_ERR_HIP;
+  for (size_t r = 0; r < b->ctx.size(); ++r) {
+    pse_ctx *c = b->ctx[r];
+    if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+    const pse_ctx *ref = nullptr;  // an earlier replica of the same group
+    for (size_t q = 0; q < r && !ref; ++q) {
+      const pse_ctx *o = b->ctx[q];
+      if (o->p.grid == c->p.grid && o->p.support == c->p.support && o->p.precision == c->p.precision) ref = o;
+    }
+    if (ref) {
+      c->tune_spread_nw = ref->tune_spread_nw;
+      c->tune_interp_threads = ref->tune_interp_threads;
+      continue;
+    }
+    const pse_status st = pse_autotune(c, nullptr);
+    if (st != PSE_OK) return st;
+  }
+  return PSE_OK;
 }
 
 pse_status pse_batch_latency(pse_batch *b, float *ms) {

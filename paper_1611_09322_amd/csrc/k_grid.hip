@@ -894,10 +894,12 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
             (const T4 *)c->pos_s, (const T4 *)vec, c->cell_start, c->d.nc, (T)c->d.cs, M, (T)h, (T)(1.0 / h),
             (T)(0.5 / s2), (T)norm, (T *)grid_or_out);
       };
-      // tiles 8 x 8 x 32 from 128^3 up (measured best at 256^3 against
-      // depths 16 and 64)
-      if (M >= 128) go(std::integral_constant<int, 4>{});
-      else if (M >= 64) go(std::integral_constant<int, 2>{});
+      // built-in: tiles 8 x 8 x 32 from 128^3 up (measured best at 256^3
+      // against depths 16 and 64); pse_autotune may pick another valid depth
+      const int nw = c->tune_spread_nw ? c->tune_spread_nw : (M >= 128 ? 4 : (M >= 64 ? 2 : 1));
+      if (nw == 8) go(std::integral_constant<int, 8>{});
+      else if (nw == 4) go(std::integral_constant<int, 4>{});
+      else if (nw == 2) go(std::integral_constant<int, 2>{});
       else go(std::integral_constant<int, 1>{});
     } else {
       (void)hipMemsetAsync(grid_or_out, 0, sizeof(T) * 4 * (size_t)M * M * M, c->stream);
@@ -905,8 +907,10 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
                                                     (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)norm);
     }
   } else {
-    // 16 particles (consecutive in cell order) per workgroup share the L1
-    k_interp<T, P><<<(int)(((long)n * 64 + 1023) / 1024), 1024, 0, c->stream>>>(
+    // built-in: 16 particles (consecutive in cell order) per workgroup share
+    // the L1
+    const int nt = c->tune_interp_threads ? c->tune_interp_threads : 1024;
+    k_interp<T, P><<<(int)(((long)n * 64 + nt - 1) / nt), nt, 0, c->stream>>>(
         (const T4 *)c->pos_s, (const T *)vec, n, (T4 *)grid_or_out, M, (T)h, (T)(1.0 / h), (T)(0.5 / s2),
         (T)(norm * h * h * h));
   }
@@ -930,6 +934,80 @@ void launch_spread_interp(pse_ctx *c, bool spread, const void *vec, void *grid_o
 template void launch_grid_op<float>(pse_ctx *, GridOp, const void *, void *, const WaveCoef *, int, int);
 template void launch_grid_op<double>(pse_ctx *, GridOp, const void *, void *, const WaveCoef *, int, int);
 template void launch_spread_interp<float>(pse_ctx *, bool, const void *, void *);
+
+// Spreading tile depth nw is valid when the tile (8 x 8 x 8 nw) divides the
+// grid and the nearest periodic image stays unique: M >= 2 max(8, 8 nw) + P.
+static bool spread_nw_valid(int M, int P, int nw) {
+  const int tz = 8 * nw, tmax = tz > 8 ? tz : 8;
+  return M % tz == 0 && M >= 2 * tmax + P;
+}
+
+template <typename T> pse_status autotune_grid(pse_ctx *c, int32_t *choice) {
+  const int M = c->p.grid, P = c->p.support;
+  const uint32_t mask = c->prof_mask;
+  c->prof_mask = 0;  // the trial launches are not stage time
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return PSE_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return PSE_ERR_HIP;
+  }
+  // any finite per-particle vector serves as the spread source: the sorted
+  // positions; the grid and vbuf[5] are scratch that every sample rewrites
+  auto time_it = [&](auto launch) -> float {
+    launch();  // warm-up
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      float ms = 1e30f;
+      if (hipEventRecord(e0, c->stream) != hipSuccess) return 1e30f;
+      launch();
+      if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return 1e30f;
+      best = ms < best ? ms : best;
+    }
+    return best;
+  };
+  const int keep_nw = c->tune_spread_nw, keep_nt = c->tune_interp_threads;
+  int best_nw = 0, best_nt = 0;
+  if (spread_tiled(M, P)) {
+    float tbest = 1e30f;
+    for (int nw : {1, 2, 4, 8}) {
+      if (!spread_nw_valid(M, P, nw)) continue;
+      c->tune_spread_nw = nw;
+      const float t = time_it([&] { launch_spread_interp<T>(c, true, c->pos_s, c->rgrid); });
+      if (t < tbest) {
+        tbest = t;
+        best_nw = nw;
+      }
+    }
+  }
+  {
+    float tbest = 1e30f;
+    for (int nt : {256, 512, 1024}) {
+      c->tune_interp_threads = nt;
+      const float t = time_it([&] { launch_spread_interp<T>(c, false, c->rgrid, c->vbuf[5]); });
+      if (t < tbest) {
+        tbest = t;
+        best_nt = nt;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->prof_mask = mask;
+  const pse_status st = hipGetLastError() == hipSuccess ? PSE_OK : PSE_ERR_HIP;
+  c->tune_spread_nw = st == PSE_OK && best_nw ? best_nw : keep_nw;
+  c->tune_interp_threads = st == PSE_OK && best_nt ? best_nt : keep_nt;
+  if (choice) {
+    choice[0] = 8 * (c->tune_spread_nw ? c->tune_spread_nw : (M >= 128 ? 4 : (M >= 64 ? 2 : 1)));
+    choice[1] = c->tune_interp_threads ? c->tune_interp_threads : 1024;
+    if (!spread_tiled(M, P)) choice[0] = 0;
+  }
+  return st;
+}
+template pse_status autotune_grid<float>(pse_ctx *, int32_t *);
+template pse_status autotune_grid<double>(pse_ctx *, int32_t *);
 template void launch_spread_interp<double>(pse_ctx *, bool, const void *, void *);
 
 }  // namespace pse

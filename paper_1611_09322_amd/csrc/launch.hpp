@@ -61,5 +61,8 @@ template <typename T> void launch_spread_interp(pse_ctx *c, bool spread, const v
 // node) and clears it itself (every node written once, or cleared before the
 // atomic fallback): no separate clear is needed.  Interpolation reads it.
 bool spread_writes_whole_grid(int M, int P);
+// times the valid spreading tile depths and interpolation workgroup sizes on
+// the current positions and keeps the fastest (c->tune_*)
+template <typename T> pse_status autotune_grid(pse_ctx *c, int32_t *choice);
 
 }  // namespace pse

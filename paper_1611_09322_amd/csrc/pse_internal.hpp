@@ -174,6 +174,11 @@ struct pse_ctx {
   int64_t pairs = 0;
   // LDS-staged near-field path (FP32 storage): block edge B (0 = global path),
   // halo capacity (particles) and number of target blocks
+  // launch shapes picked by pse_autotune (0: the built-in choice): depth
+  // of the spreading tiles (8 x 8 x 8 nw nodes) and lanes per interpolation
+  // workgroup
+  int tune_spread_nw = 0;
+  int tune_interp_threads = 0;
   int lds_B = 0;
   int hcap = 0;
   int lds_blocks = 0;
