@@ -175,3 +175,30 @@ def test_target_pair_closed_form():
     Fs = rpy.real_self(XI, A)
     exp = np.diag(1.0 / np.sqrt(1.0 - (np.array([G[0], F[0], F[0]]) / Fs) ** 2))
     np.testing.assert_allclose(T, exp, atol=1e-12)
+
+
+def test_ideal_block_preconditioner_leaves_the_krylov_work_unchanged():
+    """Hard spheres at phi = 0.3 (xi a = 0.5, rc = 8a): every diagonal block
+    of M_r is the self term, and the spread of its spectrum comes from pair
+    coupling.  Even the ideal block preconditioner, the symmetric root of the
+    ii block of M_r^{-1}, leaves kappa(P M_r P^T) no smaller than kappa(M_r),
+    and the tol-1e-3 Krylov sample needs as many iterations.  This is why
+    the learned blocks cannot pay for themselves at the benchmark's
+    parameters."""
+    import synth
+
+    x, Lb = synth.hard_spheres(300, 0.3, a=1.0, seed=3, sweeps=20)
+    Mr = rpy.real_block_dense(x, Lb, A, ETA, XI, RC)
+    Minv = np.linalg.inv(Mr)
+    P = np.array([precond._sqrtm_spd(Minv[3 * i:3 * i + 3, 3 * i:3 * i + 3]) for i in range(len(x))])
+    B = precond.block_diag(P)
+    Ap = B @ Mr @ B.T
+    lam0 = np.linalg.eigvalsh(Mr)
+    lam1 = np.linalg.eigvalsh(0.5 * (Ap + Ap.T))
+    k0, k1 = lam0[-1] / lam0[0], lam1[-1] / lam1[0]
+    z = np.random.default_rng(1).standard_normal(3 * len(x))
+    _, m0, _ = lanczos.lanczos_sqrt(lambda v: Mr @ v, z, 1e-3)
+    _, m1, _ = lanczos.lanczos_sqrt(lambda v: Ap @ v, z, 1e-3)
+    print(f"kappa {k0:.3f} -> {k1:.3f}, iterations {m0} -> {m1}")
+    assert k1 >= 0.95 * k0
+    assert m1 >= m0
