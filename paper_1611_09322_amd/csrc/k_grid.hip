@@ -633,7 +633,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
             t0z = (lin % gridDim.x) * TZ;
   const int t0[3] = {t0x, t0y, t0z}, tt[3] = {TX, TY, TZ};
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lx = lane >> 3, ly = lane & 7;
   const int zw = wave * 8;  // first z node (tile-local) of this wavefront
   const int half = M / 2;
@@ -721,8 +721,10 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
         for (int from = 0; from < NW; ++from) {
         const int nf = scnt[wave][from];
         for (int k = 0; k < nf; ++k) {
-          const int e = sidx[wave][64 * from + k];
-          const int sp = ls0[e];
+          // the entry and its support offsets are the same for the whole
+          // wavefront: scalar values, so the z tests below are scalar branches
+          const int e = __builtin_amdgcn_readfirstlane(sidx[wave][64 * from + k]);
+          const int sp = __builtin_amdgcn_readfirstlane(ls0[e]);
           const T4 pv = lpu[e], fv = lf[e];
           const int sx = (sp & 255) - 64, sy = ((sp >> 8) & 255) - 64, sz = ((sp >> 16) & 255) - 64;
           const int ix = lx - sx, iy = ly - sy;
