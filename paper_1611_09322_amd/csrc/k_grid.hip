@@ -541,12 +541,15 @@ __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *_
                                                 typename vec4<T>::type *__restrict__ out, int M, T h,
                                                 T invh, T inv2s2, T norm_h3) {
   // particles are in cell order: XCD-contiguous ranges keep the grid
-  // nodes of neighbouring particles within one L2
-  const int s = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
+  // nodes of neighbouring particles within one L2.  The particle is the
+  // wavefront's: its index and support origin are scalar values.
+  const int s = __builtin_amdgcn_readfirstlane((xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (s >= n) return;
   const auto p = pos[s];
-  const int bx = min((int)(p.x * invh), M - 1), by = min((int)(p.y * invh), M - 1), bz = min((int)(p.z * invh), M - 1);
+  const int bx = __builtin_amdgcn_readfirstlane(min((int)(p.x * invh), M - 1));
+  const int by = __builtin_amdgcn_readfirstlane(min((int)(p.y * invh), M - 1));
+  const int bz = __builtin_amdgcn_readfirstlane(min((int)(p.z * invh), M - 1));
   const int gx0 = bx - P / 2 + 1, gy0 = by - P / 2 + 1, gz0 = bz - P / 2 + 1;
   // M is a power of two: wrap with a mask, node index (x, y, z) by shifts
   const int wrap = M - 1, lg = __builtin_ctz((unsigned)M);
