@@ -242,11 +242,10 @@ pse_status sample_begin(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter
   if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
   if (!(dt >= 0)) return PSE_ERR_INVALID_ARG;
   ss.cr = std::sqrt(2.0 * c->p.kT * dt);
-  void *z_s = c->vbuf[0], *wave = c->vbuf[4], *tmp = c->vbuf[5], *f_s = c->vbuf[6], *ur = c->vbuf[7];
+  void *z_s = c->vbuf[0], *wave = c->vbuf[4], *f_s = c->vbuf[6], *ur = c->vbuf[7];
   ss.real = false;
   if (philox) {
-    launch_real_noise<T>(c, tmp, seed, counter);
-    launch_gather3<T>(c, tmp, z_s);
+    launch_real_noise<T>(c, z_s, seed, counter);  // caller-order noise, written in sorted order
     ss.real = true;
   } else if (z1) {
     launch_gather3<T>(c, z1, z_s);

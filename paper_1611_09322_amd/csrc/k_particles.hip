@@ -1435,21 +1435,38 @@ template <> __device__ __forceinline__ void box_muller<float>(uint64_t wa, uint6
   nb = rho * sn;
 }
 
-// z1 in caller order: block b covers elements 4b .. 4b+3 (key (seed, 0)).
+// z1 is defined in caller order: Philox block b (key (seed, 0), counter
+// (b, sample)) gives elements 4b .. 4b+3 of the 3n vector.  It is written
+// straight into sorted order: sorted particle s (caller index i = perm[s])
+// takes elements 3i .. 3i+2, i.e. the normals of block (3i) >> 2 and, when
+// they straddle, of the next.
 template <typename T>
-__global__ void k_real_noise(T *__restrict__ z, int len, uint64_t seed, uint64_t sample) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (4 * b >= len) return;
-  uint64_t c[4] = {(uint64_t)b, sample, 0ull, 0ull};
-  philox4x64_10(c, seed, 0ull);
-  T n0, n1, n2, n3;
-  box_muller<T>(c[0], c[1], n0, n1);
-  box_muller<T>(c[2], c[3], n2, n3);
-  const int q = 4 * b;
-  z[q] = n0;
-  if (q + 1 < len) z[q + 1] = n1;
-  if (q + 2 < len) z[q + 2] = n2;
-  if (q + 3 < len) z[q + 3] = n3;
+__global__ void k_real_noise_sorted(const int *__restrict__ perm, int n, uint64_t seed, uint64_t sample,
+                                    typename vec4<T>::type *__restrict__ z) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint64_t e0 = 3ull * (uint64_t)perm[s];
+  const uint64_t b0 = e0 >> 2;
+  const int off = (int)(e0 & 3);
+  T v[8];
+  {
+    uint64_t c[4] = {b0, sample, 0ull, 0ull};
+    philox4x64_10(c, seed, 0ull);
+    box_muller<T>(c[0], c[1], v[0], v[1]);
+    box_muller<T>(c[2], c[3], v[2], v[3]);
+  }
+  if (off >= 2) {
+    uint64_t c[4] = {b0 + 1, sample, 0ull, 0ull};
+    philox4x64_10(c, seed, 0ull);
+    box_muller<T>(c[0], c[1], v[4], v[5]);
+    box_muller<T>(c[2], c[3], v[6], v[7]);
+  }
+  typename vec4<T>::type o;
+  o.x = off == 0 ? v[0] : (off == 1 ? v[1] : (off == 2 ? v[2] : v[3]));
+  o.y = off == 0 ? v[1] : (off == 1 ? v[2] : (off == 2 ? v[3] : v[4]));
+  o.z = off == 0 ? v[2] : (off == 1 ? v[3] : (off == 2 ? v[4] : v[5]));
+  o.w = T(0);
+  z[s] = o;
 }
 
 // ----------------------------------------------------------- launchers
@@ -1723,10 +1740,10 @@ void launch_finalize(pse_ctx *c, const void *yr, double cr, const void *ur, doub
 }
 
 template <typename T>
-void launch_real_noise(pse_ctx *c, void *z, uint64_t seed, uint64_t sample) {
-  const int len = 3 * c->n;
+void launch_real_noise(pse_ctx *c, void *z_sorted, uint64_t seed, uint64_t sample) {
   ProfScope ps(c, PSE_STAGE_NOISE);
-  k_real_noise<T><<<nblk((len + 3) / 4, 256), 256, 0, c->stream>>>((T *)z, len, seed, sample);
+  k_real_noise_sorted<T><<<nblk(c->n, 256), 256, 0, c->stream>>>(c->perm, c->n, seed, sample,
+                                                                  (typename vec4<T>::type *)z_sorted);
 }
 
 #define INST_T(T)                                                                                  \
