@@ -395,7 +395,8 @@ def main():
         "variants": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
                          "lanczos_iters_mean": v["lanczos_iters_mean"],
                          "precond_fallbacks": v["precond_fallbacks"],
-                         "breakdown_ms": v["warmup_breakdown_ms_per_step"]} for k, v in variants.items()},
+                         "autotune": v["autotune"], "breakdown_ms": v["warmup_breakdown_ms_per_step"]}
+                     for k, v in variants.items()},
         "precond_training": None if train_hist is None else {
             "boxes": args.train_boxes, "n": args.train_n, "rows_per_box": args.train_rows,
             "epochs": args.train_epochs, "loss_first": train_hist[0], "loss_last": train_hist[-1]},
