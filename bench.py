@@ -330,8 +330,8 @@ def main():
                     help="also run one 512 MiB elementwise copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the sampler runs on one GPU; --gpus {args.gpus} is not supported "
+              "(no multi-GPU sharding is implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
