@@ -125,7 +125,7 @@ def load():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"HIP library not built: {LIB_PATH} missing (run __graft_entry__.build())")
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} missing (run python paper_1611_09322_amd/build.py)")
         # PyTorch-ROCm ships its own HIP runtime under the same soname; load it
         # first so that the library binds to that one runtime (device pointers
         # and streams from torch are then valid in the library).
