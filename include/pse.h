@@ -63,8 +63,8 @@ typedef struct {
   double kT;                /* thermal energy */
   double xi;                /* Ewald splitting parameter (eq. green2, eq. Mwave) */
   double rcut;              /* real-space cutoff, < L/2 (minimum image) */
-  int32_t grid;             /* M: grid points per side; 8 <= M <= 512,
-                               M = 2^p or 3*2^p */
+  int32_t grid;             /* M: grid points per side, a power of two,
+                               16 <= M <= 512 (PSE_ERR_PARAMS otherwise) */
   int32_t support;          /* P: Gaussian support points per side, even, <= 16 */
   double gauss_m;           /* Gaussian truncation in standard deviations;
                                0 selects sqrt(pi P) (Sec. II C) */

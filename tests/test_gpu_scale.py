@@ -16,6 +16,7 @@ import pytest
 
 import synth
 from oracle import ewald, rpy, sampler
+from se_error import se_aliasing_estimate
 
 pytestmark = pytest.mark.gpu
 
@@ -60,35 +61,6 @@ def test_near_field_rows_at_full_size(gpu_lib, big, precision):
     print(f"[scale] M_r v rows ({precision}): rel err {e:.2e}")
     assert e < 1e-5
     s.close()
-
-
-def se_aliasing_estimate(L, M, xi, P, a=1.0):
-    """Relative error of a spectral-Ewald wave sample from aliasing: the
-    interpolation with the Gaussian window g (std sigma = P h / 2m,
-    m = sqrt(pi P)) sees each grid mode k also at k + 2 pi n / h, with
-    amplitude ratio ghat(k + 2 pi n / h) / ghat(k).  Weighted by B(k) over the
-    k-set, with the first alias shell (n in {-1, 0, 1}^3, n != 0):
-        err^2 ~ sum_k B(k) sum_n (ghat(k + 2 pi n/h) / ghat(k))^2 / sum_k B(k).
-    At h = 0.94a (256^3 in a 240.8a box) the modes near the Nyquist frequency
-    still carry weight and this is ~5e-4; at h = 0.54a it is ~3e-5."""
-    h = L / M
-    s = P * h / (2.0 * np.sqrt(np.pi * P))
-    j = np.fft.fftfreq(M, 1.0 / M)
-    k1 = 2 * np.pi * j / L
-    ok1 = np.abs(j) < M // 2
-    KX, KY, KZ = np.meshgrid(k1, k1, k1, indexing="ij")
-    K2 = KX**2 + KY**2 + KZ**2
-    ok = ok1[:, None, None] & ok1[None, :, None] & ok1[None, None, :] & (K2 > 0)
-    B = np.zeros_like(K2)
-    B[ok] = ewald.B_kernel(K2[ok], a, xi)
-    r2 = lambda k, n: np.exp(-((k + 2 * np.pi * n / h) ** 2 - k**2) * s * s)
-    tot = np.zeros_like(K2)
-    for nx in (-1, 0, 1):
-        for ny in (-1, 0, 1):
-            for nz in (-1, 0, 1):
-                if nx or ny or nz:
-                    tot += r2(KX, nx) * r2(KY, ny) * r2(KZ, nz)
-    return float(np.sqrt((B * tot)[ok].sum() / B[ok].sum()))
 
 
 def test_wave_rows_at_full_size(gpu_lib, big):
