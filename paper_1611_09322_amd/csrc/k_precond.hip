@@ -173,12 +173,19 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w,
   if (lane < 16) out[kB3 + lane] = lane < kNOut ? gb3 : 0.f;
 }
 
+// Eight interleaved partial sums (slot q goes to sum q mod 8) keep eight
+// loads in flight; the order is fixed, so the result is deterministic.
 __global__ void k_mlp_reduce(const float *__restrict__ partial, int nparts, float *__restrict__ dw) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kWTotal) return;
-  float v = 0.f;
-  for (int q = 0; q < nparts; ++q) v += partial[(size_t)q * kWTotal + e];
-  dw[e] = v;
+  float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int q = 0;
+  for (; q + 8 <= nparts; q += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += partial[(size_t)(q + u) * kWTotal + e];
+  }
+  for (; q < nparts; ++q) v[q & 7] += partial[(size_t)q * kWTotal + e];
+  dw[e] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
 }
 
 // Adam (Kingma and Ba) on the fp32 master weights; c1 = 1/(1 - b1^t),
@@ -397,8 +404,10 @@ void launch_mlp_fwd(const uint16_t *w, const uint16_t *x, int n, float *y, uint1
   k_mlp_fwd<<<blocks, 256, 0, stream>>>(w, x, n, y, cache);
 }
 
+// About 8 rows per wavefront (each row is a chain of dependent lane
+// shuffles), up to 256 wavefronts; one fp32 slot of kWTotal per wavefront.
 int mlp_bwd_parts(int n) {
-  int blocks = nblk(n, 4 * 64);
+  int blocks = nblk(n, 4 * 8);
   if (blocks > 64) blocks = 64;
   if (blocks < 1) blocks = 1;
   return blocks * 4;
