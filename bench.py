@@ -174,7 +174,7 @@ def run_variant(pse, torch, x, L, F, args, variant, weights=None):
     s.profile([])
     ms_step = 1e3 * dt / args.steps
     res = {
-        "autotune": {"spread_tile_depth": tuned[0], "interp_lanes": tuned[1]},
+        "autotune": {"spread_tile_depth": tuned[0], "interp_lanes": tuned[1], "product_lanes_per_target": tuned[2]},
         "precond_fallbacks": st.precond_fallbacks,
         "value": len(x) * args.steps / dt,
         "ms_per_step": ms_step,
@@ -222,7 +222,7 @@ def run_batch(pse, torch, args):
     for k in range(args.warmup):
         b.set_positions(pos)
         if k == 0:
-            b.autotune()  # untimed: launch shapes per grid size
+            b.autotune()  # untimed: launch shapes per grid size and per replica
         b.sample(11, k, dt=1e-3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()

@@ -294,9 +294,10 @@ pse_status pse_batch_set_positions(pse_batch *batch, const void *const *pos);
 pse_status pse_batch_sample(pse_batch *batch, uint64_t seed, uint64_t counter, double dt, const void *const *forces,
                             void *const *disp, pse_stats *stats);
 
-/* pse_autotune for the batch: the first replica of each (grid, support,
- * precision) group is tuned on its positions (pse_batch_set_positions
- * first) and the others take its choice.  Synchronises every stream. */
+/* pse_autotune for the batch: the grid shapes are tuned on the first
+ * replica of each (grid, support, precision) group (pse_batch_set_positions
+ * first) and the others take its choice; the near-field product is tuned
+ * on every replica's own positions.  Synchronises every stream. */
 pse_status pse_batch_autotune(pse_batch *batch);
 
 /* GPU milliseconds from the start of the last pse_batch_sample to the end
@@ -306,16 +307,30 @@ pse_status pse_batch_latency(pse_batch *batch, float *ms);
 /* Launch-shape autotuning.  Times, on the context's current positions
  * (pse_set_positions first; PSE_ERR_NO_POSITIONS otherwise), every valid
  * depth of the owner-computes spreading tiles (8 x 8 x D nodes, D in 8, 16,
- * 32, 64: D divides M and M >= 2 max(8, D) + P) and the interpolation
- * workgroup sizes 256, 512 and 1024 lanes, three timed launches each after
- * a warm-up, and keeps the fastest for later calls.  Synchronises the
- * stream; uses the context's grid scratch only.  choice (host, 2 entries,
- * may be NULL) receives D (0 when the grid is too small for tiles and
- * spreading uses atomics) and the interpolation lanes.  Results after
- * tuning may differ from those before in the last bits (spreading sums
- * each node's particles in an order that follows the tile's cell scan);
- * they stay deterministic for a given choice. */
+ * 32, 64: D divides M and M >= 2 max(8, D) + P), the interpolation
+ * workgroup sizes 256, 512 and 1024 lanes, and 2, 3 and 4 lanes per target
+ * particle in the LDS near-field product (FP32 storage), three timed
+ * launches each after a warm-up, and keeps the fastest for later calls.
+ * Synchronises the stream; uses the context's scratch only.  choice (host,
+ * 3 entries, may be NULL) receives D (0 when the grid is too small for
+ * tiles and spreading uses atomics), the interpolation lanes, and the
+ * product's lanes per target (0 where the product has no LDS path: FP64,
+ * or no LDS block fits).  Results after tuning may differ from those
+ * before in the last bits (spreading sums each node's particles in an
+ * order that follows the tile's cell scan, and the product splits each
+ * row's neighbour chunks over its lanes); they stay deterministic for a
+ * given choice. */
 pse_status pse_autotune(pse_ctx *ctx, int32_t *choice);
+
+/* Applies a launch-shape choice without timing (one from pse_autotune,
+ * kept from an earlier run, or a fixed one): choice (host, 3 entries) holds
+ * the spreading tile depth, the interpolation lanes and the product's lanes
+ * per target as pse_autotune reports them, with 0 for the built-in choice
+ * of an entry.  PSE_ERR_INVALID_ARG (and nothing changed) when the tile
+ * depth is not valid for the grid (see pse_autotune), the interpolation
+ * lanes are not 256, 512 or 1024, or the product lanes are not 2, 3 or 4.
+ * Takes effect for later calls on the context; no synchronisation. */
+pse_status pse_set_launch_shape(pse_ctx *ctx, const int32_t *choice);
 
 /* GPU-time accounting: for every stage whose bit (1 << pse_stage) is set in
  * stage_mask, each kernel launch of that stage is bracketed by HIP events on

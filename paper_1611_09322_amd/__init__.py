@@ -112,6 +112,7 @@ _SIGS = {
     "pse_batch_latency": ([_VP, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "pse_batch_autotune": ([_VP], ctypes.c_int),
     "pse_autotune": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "pse_set_launch_shape": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "pse_profile": ([_VP, ctypes.c_uint32], ctypes.c_int),
     "pse_profile_read": ([_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
 }
@@ -314,11 +315,18 @@ def pse_batch_latency(b, n):
 
 
 def pse_autotune(ctx):
-    """Pick the fastest spreading tile depth and interpolation workgroup size
-    on the current positions; returns (depth, lanes)."""
-    ch = (ctypes.c_int32 * 2)()
+    """Pick the fastest spreading tile depth, interpolation workgroup size
+    and near-field lanes per target on the current positions; returns
+    (depth, interpolation lanes, product lanes per target)."""
+    ch = (ctypes.c_int32 * 3)()
     _check(load().pse_autotune(ctx, ch), "pse_autotune")
-    return int(ch[0]), int(ch[1])
+    return int(ch[0]), int(ch[1]), int(ch[2])
+
+
+def pse_set_launch_shape(ctx, depth, interp_lanes, product_lanes):
+    """Apply a launch-shape choice (0 = built-in for an entry)."""
+    ch = (ctypes.c_int32 * 3)(int(depth), int(interp_lanes), int(product_lanes))
+    return _check(load().pse_set_launch_shape(ctx, ch), "pse_set_launch_shape")
 
 
 def pse_batch_autotune(b):
@@ -372,8 +380,13 @@ class Sampler:
 
     def autotune(self):
         """Launch-shape autotuning on the current positions: returns the
-        spreading tile depth (0 without tiles) and interpolation lanes."""
+        spreading tile depth (0 without tiles), the interpolation lanes and
+        the near-field product's lanes per target (0 without the LDS path)."""
         return pse_autotune(self.ctx)
+
+    def set_launch_shape(self, depth=0, interp_lanes=0, product_lanes=0):
+        """Apply a launch-shape choice without timing (0 = built-in)."""
+        pse_set_launch_shape(self.ctx, depth, interp_lanes, product_lanes)
 
     def profile(self, stages):
         """Time the named stages with HIP events (see STAGES); [] = off."""

@@ -706,8 +706,20 @@ pse_status pse_wave_apply(pse_ctx *c, const void *F, void *u) {
 pse_status pse_autotune(pse_ctx *c, int32_t *choice) {
   if (!c) return PSE_ERR_INVALID_ARG;
   if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
-  if (c->dbl) return autotune_grid<double>(c, choice);
-  return autotune_grid<float>(c, choice);
+  const pse_status st = c->dbl ? autotune_grid<double>(c, choice) : autotune_grid<float>(c, choice);
+  if (st != PSE_OK) return st;
+  return autotune_spmv(c, choice ? choice + 2 : nullptr);
+}
+
+pse_status pse_set_launch_shape(pse_ctx *c, const int32_t *choice) {
+  if (!c || !choice) return PSE_ERR_INVALID_ARG;
+  const int depth = choice[0], il = choice[1], pl = choice[2];
+  if (!grid_shape_valid(c->p.grid, c->p.support, depth, il)) return PSE_ERR_INVALID_ARG;
+  if (pl != 0 && pl != 2 && pl != 3 && pl != 4) return PSE_ERR_INVALID_ARG;
+  c->tune_spread_nw = depth / 8;
+  c->tune_interp_threads = il;
+  c->tune_spmv_lanes = pl;
+  return PSE_OK;
 }
 
 pse_status pse_profile(pse_ctx *c, uint32_t mask) {
@@ -850,9 +862,12 @@ pse_status pse_batch_autotune(pse_batch *b) {
     if (ref) {
       c->tune_spread_nw = ref->tune_spread_nw;
       c->tune_interp_threads = ref->tune_interp_threads;
-      continue;
+    } else {
+      const pse_status st = c->dbl ? autotune_grid<double>(c, nullptr) : autotune_grid<float>(c, nullptr);
+      if (st != PSE_OK) return st;
     }
-    const pse_status st = pse_autotune(c, nullptr);
+    // the product depends on the replica's own density: tuned per replica
+    const pse_status st = autotune_spmv(c, nullptr);
     if (st != PSE_OK) return st;
   }
   return PSE_OK;

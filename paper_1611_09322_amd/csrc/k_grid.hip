@@ -949,6 +949,15 @@ static bool spread_nw_valid(int M, int P, int nw) {
   return M % tz == 0 && M >= 2 * tmax + P;
 }
 
+bool grid_shape_valid(int M, int P, int depth, int interp_lanes) {
+  if (depth != 0) {
+    const int nw = depth / 8;
+    if (depth % 8 || (nw != 1 && nw != 2 && nw != 4 && nw != 8)) return false;
+    if (!spread_tiled(M, P) || !spread_nw_valid(M, P, nw)) return false;
+  }
+  return interp_lanes == 0 || interp_lanes == 256 || interp_lanes == 512 || interp_lanes == 1024;
+}
+
 template <typename T> pse_status autotune_grid(pse_ctx *c, int32_t *choice) {
   const int M = c->p.grid, P = c->p.support;
   const uint32_t mask = c->prof_mask;

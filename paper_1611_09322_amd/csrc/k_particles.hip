@@ -1,6 +1,8 @@
 // Particle-side kernels: wrapping and linked-cell binning, the sorted order,
 // the near-field neighbour list, the real-space product w = M_r v
 // (eq. Mreal, Appendix A) and the Lanczos square-root iteration (Sec. II B.1).
+#include <type_traits>
+
 #include "launch.hpp"
 
 namespace pse {
@@ -918,9 +920,9 @@ __global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__
 // Near-field product from the staged halo.  The halo is packed as
 // (x, y, z, v_x) + (v_y, v_z) (24 bytes per particle) together with the F/G
 // table (mu0 F, mu0 (G - F) and their forward differences, one 16-byte read
-// per pair).  Three lanes per target (lane q of the group takes neighbour
-// chunks q, q + 3, ...; 21 groups per wavefront) are combined with lane
-// shuffles; each chunk of 8 neighbours is processed branch-free in two
+// per pair).  G lanes per target (lane q of the group takes neighbour chunks
+// q, q + G, ...; 64 / G groups per wavefront; 3 unless pse_autotune picks 2
+// or 4) are combined with lane shuffles; each chunk of 8 neighbours is processed branch-free in two
 // halves of 4 (padding entries read the zero source), the LDS reads of a half
 // in flight together.  Registers are held to 64 so that two 1024-lane
 // workgroups share a compute unit: one stages its halo while the other
@@ -929,7 +931,7 @@ __global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__
 // With PC (Lanczos on A = P M_r P^T): src holds u = P^T r, and the
 // epilogue forms out = P (M_r u) / beta, v_m = r / beta (r from rsrc) and
 // alpha_m = <v_m, out>; Pm holds the rows of P_i as (x, y, z, 0).
-template <int B, bool UNWRAP, typename A, bool LZ, bool PC = false>
+template <int B, bool UNWRAP, typename A, bool LZ, bool PC = false, int G = 3>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
                                                    const int *__restrict__ cell_start, int nc, float cs, int n,
                                                    int hcap, float L, float invL, const uint16_t *__restrict__ nbr,
@@ -939,8 +941,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
                                                    unsigned *counter, const float4 *__restrict__ Pm = nullptr,
                                                    const float4 *__restrict__ rsrc = nullptr) {
   constexpr int NH = Halo<B>::NH;
-  constexpr int G = 3;                      // lanes per target
-  constexpr int GPW = 64 / G;               // groups per wavefront (lane 63 idle)
+  static_assert(G >= 2 && G <= 4, "lanes per target");
+  constexpr int GPW = 64 / G;               // groups per wavefront (lane 63 idle at G = 3)
   extern __shared__ float4 smem[];
   float4 *hA = smem;                        // (x, y, z, v_x)
   float2 *hB = (float2 *)(smem + hcap);     // (v_y, v_z)
@@ -1590,13 +1592,77 @@ static void spmv_lds(pse_ctx *c, const float4 *src, float4 *out, float4 *vm_out,
                                                       c->table, inv_dr, self_r, 1.0f, out, vm_out, st,
                                                       (A *)c->partials, c->counter, (const float4 *)c->pc_P, rsrc);
   };
-  if (c->lds_B == 2) {
-    if (unwrap) go(k_spmv_lds<2, true, A, LZ, PC>);
-    else go(k_spmv_lds<2, false, A, LZ, PC>);
-  } else {
-    if (unwrap) go(k_spmv_lds<1, true, A, LZ, PC>);
-    else go(k_spmv_lds<1, false, A, LZ, PC>);
+  auto pick = [&](auto g) {
+    constexpr int G = decltype(g)::value;
+    if (c->lds_B == 2) {
+      if (unwrap) go(k_spmv_lds<2, true, A, LZ, PC, G>);
+      else go(k_spmv_lds<2, false, A, LZ, PC, G>);
+    } else {
+      if (unwrap) go(k_spmv_lds<1, true, A, LZ, PC, G>);
+      else go(k_spmv_lds<1, false, A, LZ, PC, G>);
+    }
+  };
+  // lanes per target: 3 built in (the best measured at phi = 0.3 with
+  // r_c = 8a), 2 or 4 when pse_autotune found them faster
+  if (c->tune_spmv_lanes == 2) pick(std::integral_constant<int, 2>{});
+  else if (c->tune_spmv_lanes == 4) pick(std::integral_constant<int, 4>{});
+  else pick(std::integral_constant<int, 3>{});
+}
+
+// The fused Lanczos product (5 of the 6 product launches of a sample) is
+// timed: the Krylov state is initialised from the sorted positions as the
+// start vector (finite, nonzero), so every trial is iteration 0 and writes
+// alpha_0, the basis slot 0 and vbuf[5], scratch that every sample
+// re-initialises or rewrites.
+template <typename A> static pse_status autotune_spmv_impl(pse_ctx *c) {
+  launch_lz_init<float, A>(c, c->pos_s);
+  auto *st = (LzState<A> *)c->lz;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return PSE_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return PSE_ERR_HIP;
   }
+  const int keep = c->tune_spmv_lanes;
+  int best = 0;
+  float tbest = 1e30f;
+  for (int g : {2, 3, 4}) {
+    c->tune_spmv_lanes = g;
+    auto launch = [&] {
+      spmv_lds<A, true>(c, (const float4 *)c->pos_s, (float4 *)c->vbuf[5], (float4 *)c->V, st);
+    };
+    launch();  // warm-up
+    float t = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      float ms = 1e30f;
+      if (hipEventRecord(e0, c->stream) != hipSuccess) break;
+      launch();
+      if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        break;
+      t = ms < t ? ms : t;
+    }
+    if (t < tbest) {
+      tbest = t;
+      best = g;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const pse_status st_ = hipGetLastError() == hipSuccess ? PSE_OK : PSE_ERR_HIP;
+  c->tune_spmv_lanes = st_ == PSE_OK && best ? best : keep;
+  return st_;
+}
+
+pse_status autotune_spmv(pse_ctx *c, int32_t *lanes) {
+  if (lanes) *lanes = 0;
+  if (c->dbl || !c->lds_B) return PSE_OK;
+  const uint32_t mask = c->prof_mask;
+  c->prof_mask = 0;  // the trial launches are not stage time
+  const pse_status st = c->acc_dbl ? autotune_spmv_impl<double>(c) : autotune_spmv_impl<float>(c);
+  c->prof_mask = mask;
+  if (lanes) *lanes = c->tune_spmv_lanes ? c->tune_spmv_lanes : 3;
+  return st;
 }
 
 template <typename T, typename A>

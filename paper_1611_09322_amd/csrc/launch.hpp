@@ -64,5 +64,12 @@ bool spread_writes_whole_grid(int M, int P);
 // times the valid spreading tile depths and interpolation workgroup sizes on
 // the current positions and keeps the fastest (c->tune_*)
 template <typename T> pse_status autotune_grid(pse_ctx *c, int32_t *choice);
+// Times the LDS near-field product at 2, 3 and 4 lanes per target and keeps
+// the fastest; *lanes receives the kept value (0 where the product does not
+// use the LDS path: FP64, or no LDS block fits).
+pse_status autotune_spmv(pse_ctx *c, int32_t *lanes);
+// A spreading tile depth (0: built-in) and interpolation workgroup size
+// (0: built-in) that the grid's launches accept.
+bool grid_shape_valid(int M, int P, int depth, int interp_lanes);
 
 }  // namespace pse

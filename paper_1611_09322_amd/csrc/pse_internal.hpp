@@ -179,6 +179,8 @@ struct pse_ctx {
   // workgroup
   int tune_spread_nw = 0;
   int tune_interp_threads = 0;
+  // lanes per target of the LDS near-field product (2, 3 or 4; 0: 3)
+  int tune_spmv_lanes = 0;
   int lds_B = 0;
   int hcap = 0;
   int lds_blocks = 0;

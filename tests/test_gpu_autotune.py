@@ -1,13 +1,14 @@
 """Launch-shape autotuning (pse_autotune, pse_batch_autotune): the choices
-are valid launch shapes for the grid, the tuned wave-space sample agrees
-with the built-in one to rounding (only the order in which a node sums its
-particles may change), and stays within the oracle bar of the direct
-Fourier sum."""
+are valid launch shapes for the grid, the tuned wave-space sample and
+near-field product agree with the built-in ones to rounding (only the order
+in which a node sums its particles, or a row its neighbour chunks, may
+change), and stay within the oracle bars of the direct Fourier sum and the
+dense real-space block."""
 import numpy as np
 import pytest
 
 import synth
-from oracle import ewald
+from oracle import ewald, rpy
 
 pytestmark = pytest.mark.gpu
 
@@ -38,18 +39,24 @@ def test_autotune_choice_valid_and_sample_unchanged(gpu_lib, n, phi, grid, preci
     s.set_positions(torch.as_tensor(x, dtype=dt, device="cuda"))
     W = synth.normals(2200 + n, (3, grid, grid, grid))
     Wd = torch.as_tensor(W, dtype=dt, device="cuda")
-    y0 = host(s.wave_sample(Wd))
-    depth, lanes = s.autotune()
-    print(f"n={n} M={grid} {precision}: spreading tile depth {depth}, interpolation lanes {lanes}", flush=True)
+    v = synth.normals(2250 + n, (n, 3))
+    vd = torch.as_tensor(v, dtype=dt, device="cuda")
+    y0, w0 = host(s.wave_sample(Wd)), host(s.real_matvec(vd))
+    depth, lanes, plane = s.autotune()
+    print(f"n={n} M={grid} {precision}: spreading tile depth {depth}, interpolation lanes {lanes},"
+          f" product lanes per target {plane}", flush=True)
     assert lanes in (256, 512, 1024)
     assert depth in (8, 16, 32, 64)
     assert grid % depth == 0 and grid >= 2 * max(8, depth) + P
-    y1 = host(s.wave_sample(Wd))
+    assert plane in ((0,) if precision == "fp64" else (0, 2, 3, 4))
+    y1, w1 = host(s.wave_sample(Wd)), host(s.real_matvec(vd))
     tol = 1e-12 if precision == "fp64" else 1e-6
-    assert rel(y1, y0) < tol
+    assert rel(y1, y0) < tol and rel(w1, w0) < tol
     if n <= 1000:
         y_ref = ewald.wave_sample_direct(x, ewald.zeta_from_grid_noise(W), L, 1.0, 1.0, XI)
         assert rel(y1, y_ref) < 1e-4
+        w_ref = rpy.real_block_dense(x, L, 1.0, 1.0, XI, RC) @ v.ravel()
+        assert rel(w1, w_ref) < (1e-12 if precision == "fp64" else 1e-5)
     s.close()
 
 
@@ -80,3 +87,48 @@ def test_batch_autotune(gpu_lib):
         assert np.all(np.isfinite(y1))
         assert rel(y1, y0[r]) < 1e-5, r
     b.close()
+
+
+@pytest.mark.parametrize("plane", [2, 3, 4])
+@pytest.mark.parametrize("n,phi,precision", [(1000, 0.1, "fp32"), (1000, 0.1, "mixed"), (6000, 0.3, "mixed")])
+def test_product_lanes_per_target_match_oracle(gpu_lib, n, phi, precision, plane):
+    """Each lanes-per-target variant of the LDS product (forces product and
+    the fused Lanczos product inside a Krylov sample) against the oracle:
+    brute-force rows of M_r v (wrapped halo at N = 1000, 4^3 cells;
+    unwrapped at N = 6000, 5^3 cells) within the FP32 table bar, and the
+    Krylov sample against the dense symmetric root at N = 1000."""
+    import torch
+
+    x, L = synth.hard_spheres(n, phi, seed=2500 + n, sweeps=5)
+    s = gpu_lib.Sampler(n, L, xi=XI, rcut=RC, grid=64, support=P, tol=1e-6, precision=precision)
+    s.set_launch_shape(0, 0, plane)
+    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    v = synth.normals(2600 + n, (n, 3))
+    w = host(s.real_matvec(torch.as_tensor(v, dtype=torch.float32, device="cuda")))
+    rows = np.random.default_rng(n).choice(n, 64, replace=False)
+    e = rel(w[rows], rpy.real_matvec_rows(x, v, rows, L, 1.0, 1.0, XI, RC))
+    msg = f"n={n} {precision} lanes {plane}: rows {e:.2e}"
+    assert e < 1e-5
+    if n <= 1000:
+        z = synth.normals(2700 + n, (n, 3))
+        y, st = s.real_sample(torch.as_tensor(z, dtype=torch.float32, device="cuda"))
+        Mr = rpy.real_block_dense(x, L, 1.0, 1.0, XI, RC)
+        lam, Q = np.linalg.eigh(Mr)
+        ref = Q @ (np.sqrt(lam) * (Q.T @ z.ravel()))
+        e2 = rel(host(y), ref)
+        msg += f", Krylov sample {e2:.2e} ({st.lanczos_iters} iterations)"
+        assert st.converged and e2 < 1e-4
+    print(msg, flush=True)
+    s.close()
+
+
+def test_set_launch_shape_rejects_invalid_shapes(gpu_lib):
+    x, L = synth.hard_spheres(500, 0.1, seed=2800)
+    s = gpu_lib.Sampler(500, L, xi=XI, rcut=RC, grid=64, support=P, precision="fp32")
+    for bad in [(12, 0, 0), (128, 0, 0), (0, 384, 0), (0, 0, 5), (0, 0, 1)]:
+        with pytest.raises(gpu_lib.PSEError) as e:
+            s.set_launch_shape(*bad)
+        assert e.value.status == -1, bad
+    s.set_launch_shape(16, 512, 2)
+    s.set_launch_shape(0, 0, 0)
+    s.close()
