@@ -310,7 +310,9 @@ pse_status pse_batch_latency(pse_batch *batch, float *ms);
  * 32, 64: D divides M and M >= 2 max(8, D) + P), the interpolation
  * workgroup sizes 256, 512 and 1024 lanes, and 2, 3 and 4 lanes per target
  * particle in the LDS near-field product (FP32 storage), three timed
- * launches each after a warm-up, and keeps the fastest for later calls.
+ * launches each after a warm-up, and keeps the fastest for later calls
+ * (the product keeps its built-in 3 lanes unless 2 or 4 is more than 3 %
+ * faster).
  * Synchronises the stream; uses the context's scratch only.  choice (host,
  * 3 entries, may be NULL) receives D (0 when the grid is too small for
  * tiles and spreading uses atomics), the interpolation lanes, and the
