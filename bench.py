@@ -31,6 +31,8 @@ SPMV_FLOPS_PER_PAIR = 35
 # WRITE_SIZE passes scaled by the same counters on a copy of known size; the
 # summary records the hash of the kernel source it was taken on.
 TRAFFIC_SUMMARY = {"spmv": ("profiles/spmv_lds_n1M_phi03_traffic.txt", "paper_1611_09322_amd/csrc/k_particles.hip")}
+# the workload those counters were taken on; other workloads report null
+TRAFFIC_WORKLOAD = {"n": 1_000_000, "phi": 0.3, "grid": 256, "support": 8, "xi": 0.5, "rc": 8.0}
 
 
 def stage_bytes(stage, n, grid, pairs, lanczos, index_bytes=4):
@@ -54,12 +56,20 @@ def stage_bytes(stage, n, grid, pairs, lanczos, index_bytes=4):
     return None
 
 
-def measured_traffic(stage):
-    """Counter-measured HBM bytes per launch, or None when no summary exists
-    or the kernel source changed since the counters were taken."""
+def start_of(phi):
+    """How the generator starts a configuration at this volume fraction."""
+    import synth
+
+    return "RSA" if phi <= synth.RSA_MAX_PHI else "randomly vacated FCC lattice"
+
+
+def measured_traffic(stage, args):
+    """Counter-measured HBM bytes per launch, or None when no summary exists,
+    the workload is not the one the counters were taken on, or the kernel
+    source changed since."""
     import hashlib
 
-    if stage not in TRAFFIC_SUMMARY:
+    if stage not in TRAFFIC_SUMMARY or any(getattr(args, k) != v for k, v in TRAFFIC_WORKLOAD.items()):
         return None
     summ, src = (os.path.join(ROOT, p) for p in TRAFFIC_SUMMARY[stage])
     if not os.path.exists(summ):
@@ -94,7 +104,7 @@ def make_workload(args):
     import synth
 
     t0 = time.time()
-    print(f"[bench] generating N={args.n} hard spheres at phi={args.phi} (RSA, then {args.sweeps} MC sweeps)",
+    print(f"[bench] generating N={args.n} hard spheres at phi={args.phi} ({start_of(args.phi)}, then {args.sweeps} MC sweeps)",
           file=sys.stderr, flush=True)
     x, L = synth.hard_spheres(args.n, args.phi, a=1.0, seed=1003, sweeps=args.sweeps,
                               progress=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
@@ -314,7 +324,7 @@ def main():
     ap.add_argument("--xi", type=float, default=0.5)
     ap.add_argument("--rc", type=float, default=8.0)
     ap.add_argument("--tol", type=float, default=1e-3)
-    ap.add_argument("--sweeps", type=int, default=2000, help="Monte Carlo relaxation sweeps after RSA")
+    ap.add_argument("--sweeps", type=int, default=2000, help="Monte Carlo relaxation sweeps after the start (RSA, or an FCC lattice above phi 0.35)")
     ap.add_argument("--variants", default="fp32,mixed,mixed+precond",
                     help="comma list of fp32, mixed, fp64 and <precision>+precond")
     ap.add_argument("--batch-replicas", type=int, default=256)
@@ -365,7 +375,7 @@ def main():
         roofline["alu_flops_per_pair"] = SPMV_FLOPS_PER_PAIR
         roofline["alu_frac"] = (SPMV_FLOPS_PER_PAIR * hv["neighbor_pairs"] / (hv["dominant_ms_avg"] * 1e-3)
                                 / 1e12 / FP32_PEAK_TFS)
-    roofline["traffic"] = measured_traffic(dom)
+    roofline["traffic"] = measured_traffic(dom, args)
     if args.copy_calibration:
         copy_calibration(torch)
     batched = None if args.no_batch else run_batch(pse, torch, args)
@@ -387,7 +397,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"PSE Brownian displacement with random forces, N={args.n} hard spheres a=1, "
-                        f"phi={args.phi} (RSA + {args.sweeps} MC sweeps), grid {args.grid}^3, P={args.support}, "
+                        f"phi={args.phi} ({start_of(args.phi)} + {args.sweeps} MC sweeps), grid {args.grid}^3, P={args.support}, "
                         f"xi a={args.xi}, rc={args.rc}a, tol {args.tol}",
             "variant": head,
             "precond": "learned (trained before timing)" if head.endswith("+precond") else "none",
