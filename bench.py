@@ -205,7 +205,7 @@ def run_variant(pse, torch, x, L, F, args, variant, weights=None):
 
 def run_batch(pse, torch, args):
     """Many small independent systems per call (replicas): N log-uniform in
-    [1e3, 2e4], volume fraction uniform in [0.05, 0.35], grid the smallest
+    [1e3, 2e4], volume fraction uniform in [0.05, 0.4], grid the smallest
     power of two with h <= 0.65a.  Each step sets new positions and samples
     every replica; compared with the same replicas sampled one after another
     through their own contexts.  Grids are capped at 128^3 (h up to 0.93a for
@@ -219,7 +219,7 @@ def run_batch(pse, torch, args):
     specs, pos = [], []
     for r in range(args.batch_replicas):
         n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(2e4)))))
-        phi = float(rng.uniform(0.05, 0.35))
+        phi = float(rng.uniform(0.05, 0.4))
         x, L = synth.hard_spheres(n, phi, a=1.0, seed=20000 + r, sweeps=20)
         M = next((m for m in (32, 64, 128) if L / m <= 0.65), 128)
         specs.append(dict(n=n, box=L, xi=args.xi, rcut=args.rc, grid=M, support=args.support, tol=args.tol,
