@@ -109,12 +109,14 @@ def test_krylov_sample_at_full_size_converges(gpu_lib, big):
     assert e < 1e-3
 
 
-def test_independent_2000_sphere_box_full_oracle(gpu_lib):
-    """N = 2000 at volume fraction 0.3 (L = 30.34a), 64^3 grid (h = 0.47a):
-    the whole displacement with forces, Philox noise on both sides."""
+@pytest.mark.parametrize("phi", [PHI, 0.4])
+def test_independent_2000_sphere_box_full_oracle(gpu_lib, phi):
+    """N = 2000 at volume fraction 0.3 (L = 30.34a, RSA start) and 0.4
+    (L = 27.57a, FCC start), 64^3 grid (h = 0.47a, 0.43a): the whole
+    displacement with forces, Philox noise on both sides."""
     import torch
 
-    x, L = synth.hard_spheres(2000, PHI, a=1.0, seed=1099, sweeps=200)
+    x, L = synth.hard_spheres(2000, phi, a=1.0, seed=1099, sweeps=200)
     F = synth.normals(34, (2000, 3))
     s = make(gpu_lib, L, "mixed", tol=1e-6, n=2000, grid=64)
     s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
@@ -123,7 +125,7 @@ def test_independent_2000_sphere_box_full_oracle(gpu_lib):
     s.close()
     ref = sampler.displacement_philox(x, sampler.Params(L=L, xi=XI, rc=RC, M=64), 2024, 5, dt=1e-3, forces=F, bits=24)
     e = rel(got, ref)
-    print(f"[scale] N=2000 box: rel err {e:.2e} ({st.lanczos_iters} iterations)")
+    print(f"[scale] N=2000 box at phi={phi}: rel err {e:.2e} ({st.lanczos_iters} iterations)")
     assert e < 1e-4
 
 
