@@ -515,3 +515,7 @@ class Batch:
     def autotune(self):
         """pse_batch_autotune (after set_positions)."""
         pse_batch_autotune(self.b)
+
+    def set_precond_weights(self, r, w_bits):
+        """Learned-preconditioner weights of replica r (created with precond=1)."""
+        pse_precond_set_weights(pse_batch_replica(self.b, r), w_bits)

@@ -72,3 +72,40 @@ def test_batch_replica_matches_oracle(gpu_lib, systems):
     print(f"batch replica 0 vs oracle: rel err {e:.2e}")
     assert e < 1e-4
     b.close()
+
+
+def test_batch_with_a_preconditioned_replica(gpu_lib):
+    """A replica created with the learned preconditioner (weights set through
+    its replica context) gives, inside the batch, the displacement of its own
+    context with the same weights, bit for bit; so does a plain replica next
+    to it."""
+    import torch
+
+    from oracle import precond as opc
+    from paper_1611_09322_amd import precond as ppc
+
+    bits = ppc.bf16_bits(ppc.pack(opc.init_weights(41, scale=0.1)))
+    specs, pos, F = [], [], []
+    for k, (n, phi, M, prec, pc) in enumerate([(1500, 0.3, 64, "mixed", 1), (900, 0.2, 64, "fp32", 0)]):
+        x, L = synth.hard_spheres(n, phi, seed=1700 + k, sweeps=10)
+        specs.append(dict(n=n, box=L, xi=0.5, rcut=8.0, grid=M, support=8, tol=1e-6, precision=prec, precond=pc))
+        pos.append(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+        F.append(torch.as_tensor(synth.normals(1800 + k, (n, 3)), dtype=torch.float32, device="cuda"))
+    b = gpu_lib.Batch(specs)
+    b.set_precond_weights(0, bits)
+    b.set_positions(pos)
+    out, st = b.sample(91, 2, dt=0.01, forces=F)
+    torch.cuda.synchronize()
+    for r, sp in enumerate(specs):
+        one = gpu_lib.Sampler(sp["n"], sp["box"], xi=0.5, rcut=8.0, grid=sp["grid"], support=8, tol=1e-6,
+                              precision=sp["precision"], precond=sp["precond"])
+        if sp["precond"]:
+            one.set_precond_weights(bits)
+        one.set_positions(pos[r])
+        ref, st1 = one.sample(91 + r, 2, dt=0.01, forces=F[r])
+        torch.cuda.synchronize()
+        print(f"replica {r}: {st[r].lanczos_iters} iterations, {st[r].precond_fallbacks} fallbacks", flush=True)
+        assert torch.equal(out[r], ref), r
+        assert st[r].lanczos_iters == st1.lanczos_iters and st[r].precond_fallbacks == st1.precond_fallbacks
+        one.close()
+    b.close()
