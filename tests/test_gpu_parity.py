@@ -150,17 +150,20 @@ def test_grid_noise_sample_equals_parts(gpu_lib, cfg0):
 
 
 # ------------------------------------------------------------- edge cases
-def test_ragged_overlapping_unwrapped_positions(gpu_lib):
+@pytest.mark.parametrize("precision,bar_r", [("fp64", 1e-12), ("fp32", 1e-5), ("mixed", 1e-5)])
+def test_ragged_overlapping_unwrapped_positions(gpu_lib, precision, bar_r):
     """N = 1001 (ragged against every block size), uniform positions with
     overlaps and one coincident pair, coordinates outside [0, L) and exactly
-    at L (maps to 0)."""
+    at L (maps to 0).  The 20a box holds 2^3 cells of the cell list, too few
+    for LDS blocks: FP32 storage takes the global neighbour list and table
+    product here."""
     L, M = 20.0, 32
     x = synth.uniform_positions(1001, L, seed=9)
     x[1] = x[0]                      # coincident spheres
     x[2] = x[3] + [0.3, -0.2, 0.1]   # strong overlap
     x[10:20] += L * np.array([1, -1, 2])
     x[30] = [L, 0.0, L]
-    s = make(gpu_lib, len(x), L, "fp64", grid=M)
+    s = make(gpu_lib, len(x), L, precision, grid=M)
     s.set_positions(to_dev(x, s.dtype))
     Mr = rpy.real_block_dense(x, L, 1.0, 1.0, XI, RC)
     v = synth.normals(10, (len(x), 3))
@@ -168,8 +171,8 @@ def test_ragged_overlapping_unwrapped_positions(gpu_lib):
     W = synth.normals(11, (3, M, M, M))
     y = host(s.wave_sample(to_dev(W, s.dtype)))
     err_w = rel(y, ewald.wave_sample_direct(x, ewald.zeta_from_grid_noise(W), L, 1.0, 1.0, XI))
-    print(f"ragged/overlap: real {err_r:.2e} wave {err_w:.2e}", flush=True)
-    assert err_r < 1e-12 and err_w < 1e-4
+    print(f"ragged/overlap {precision}: real {err_r:.2e} wave {err_w:.2e}", flush=True)
+    assert err_r < bar_r and err_w < 1e-4
 
 
 def test_single_particle(gpu_lib):
