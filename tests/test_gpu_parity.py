@@ -234,3 +234,20 @@ def test_sample_covariance_is_mobility(gpu_lib):
     sig = np.sqrt((np.outer(d, d) ** 2 + Mt**2) / n)
     assert np.all(np.abs(C - Mt) < 5 * sig)
     assert np.all(np.abs(Y.mean(0)) < 5 * d / np.sqrt(n))
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_zero_temperature_gives_the_deterministic_drift(gpu_lib, cfg0, precision, bar):
+    """kT = 0 removes both noise terms of eq. split: the displacement is
+    dt (M_r + M_w) F, the mobility product; without forces it is zero."""
+    x, L, Mr = cfg0
+    s = make(gpu_lib, len(x), L, precision, kT=0.0)
+    s.set_positions(to_dev(x, s.dtype))
+    F = synth.normals(12, (len(x), 3))
+    d, _ = s.sample(5, 9, dt=0.25, forces=to_dev(F, s.dtype))
+    u = host(s.mobility_apply(to_dev(F, s.dtype)))
+    err = rel(host(d), 0.25 * u)
+    d0, _ = s.sample(5, 10, dt=0.25)
+    print(f"kT = 0 {precision}: drift rel err {err:.2e}", flush=True)
+    assert err < bar
+    assert not np.any(host(d0))
