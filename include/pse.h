@@ -211,9 +211,13 @@ pse_status pse_mobility_apply(pse_ctx *ctx, const void *forces_dev, void *u_dev)
  * within rc; d = x_i - x_j, dh = d / r or 0 at r = 0), F and G the
  * dimensionless functions of Appendix A.
  * A block falls back to I if it is not finite, |det P_i| < 1e-6 or
- * |P_i|_F |P_i^{-1}|_F > 1e3.  Without weights every block is I (global
- * fallback).  Sampling calls return PSE_WARN_PRECOND_FALLBACK when any block
- * fell back; pse_stats.precond_fallbacks counts them.
+ * |P_i|_F |P_i^{-1}|_F > 1e3.  Without weights every block is I.  Global
+ * fallback: when the preconditioned Krylov sample fails (a non-finite
+ * scalar, or the tolerance not met within lanczos_max_iter), the same z1 is
+ * sampled again with P = I, and precond_fallbacks reports n.  Sampling
+ * calls return PSE_WARN_PRECOND_FALLBACK when any block fell back (or the
+ * status of the plain sample when that fails too); pse_stats.precond_fallbacks
+ * counts the blocks.
  *
  * Weights: one bf16 array of PSE_MLP_NPARAM elements, in this order:
  *   W1 [64][32] (input columns 24..31 must be 0), b1 [64], W2 [64][64],

@@ -134,7 +134,8 @@ hipEvent_t next_event(pse_ctx *c) {
 template <typename T, typename A>
 pse_status lz_start(pse_ctx *c, const void *z_sorted) {
   launch_lz_init<T, A>(c, z_sorted);
-  const bool pc = c->pc_on && c->pc_have_w;  // without weights every block is I
+  // without weights every block is I; pc_suspend: the global fallback below
+  const bool pc = c->pc_on && c->pc_have_w && !c->pc_suspend;
   const int maxit = c->p.lanczos_max_iter;
   int k = c->last_iters < 2 ? 2 : c->last_iters;
   if (k > maxit) k = maxit;
@@ -160,7 +161,7 @@ template <typename T, typename A>
 pse_status lz_finish(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
   take_pc_fallbacks(c, true);
   auto *h = (LzState<A> *)c->lz_h;
-  const bool pc = c->pc_on && c->pc_have_w;
+  const bool pc = c->pc_on && c->pc_have_w && !c->pc_suspend;
   const int maxit = c->p.lanczos_max_iter;
   while (!h->done && c->lz_launched < maxit) {
     if (pc) launch_lz_iter_pc<T, A>(c, c->lz_launched, z_sorted);
@@ -169,6 +170,18 @@ pse_status lz_finish(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats
     if (hipMemcpyAsync(h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
       return PSE_ERR_HIP;
+  }
+  if (pc && (h->nonfinite || !h->converged)) {
+    // global fallback: the preconditioned iteration failed (non-finite, or
+    // the tolerance not met within max_iter), so the same z is sampled
+    // again with P = I, and every particle counts as fallen back
+    c->pc_suspend = true;
+    pse_status st = lz_start<T, A>(c, z_sorted);
+    if (st == PSE_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = PSE_ERR_HIP;
+    if (st == PSE_OK) st = lz_finish<T, A>(c, z_sorted, y_sorted, stats);
+    c->pc_suspend = false;
+    if (stats) stats->precond_fallbacks = c->n;
+    return st == PSE_OK || st == PSE_WARN_PRECOND_FALLBACK ? PSE_WARN_PRECOND_FALLBACK : st;
   }
   launch_lz_combine<T, A>(c, y_sorted);
   if (pc) launch_pc_apply_inv<T>(c, y_sorted);  // y = P^-1 A^1/2 z

@@ -184,7 +184,9 @@ struct pse_ctx {
   int lds_B = 0;
   int hcap = 0;
   int lds_blocks = 0;
-  // learned block preconditioner (params.precond == 1)
+  // learned block preconditioner (params.precond == 1); pc_suspend is set
+  // while a failed preconditioned sample is redone with P = I
+  bool pc_suspend = false;
   bool pc_on = false;
   bool pc_have_w = false;
   uint16_t *pc_w = nullptr;    // bf16 [kWTotal]

@@ -242,3 +242,37 @@ def test_training_fits_the_targets(gpu_lib):
     assert st.converged and st.precond_fallbacks < len(x) // 10
     s.close()
     s0.close()
+
+
+def test_global_fallback_when_the_preconditioned_sample_fails(gpu_lib):
+    """Weights that make P M_r P^T much worse conditioned (random, scale 0.1)
+    keep the preconditioned Krylov sample from meeting tol 1e-6 within 14
+    iterations, which the plain sample meets in fewer.  The call then samples
+    the same z1 with P = I: its displacement equals the plain sampler's bit
+    for bit, with PSE_WARN_PRECOND_FALLBACK and every particle counted."""
+    import torch
+
+    from paper_1611_09322_amd import precond as ppc
+
+    x, L = synth.hard_spheres(1500, 0.3, seed=1700, sweeps=10)
+    bits = ppc.bf16_bits(ppc.pack(opc.init_weights(41, scale=0.1)))
+    pos = torch.as_tensor(x, dtype=torch.float32, device="cuda")
+    kw = dict(xi=XI, rcut=RC, grid=64, support=8, tol=1e-6, max_iter=14, precision="mixed")
+    plain = gpu_lib.Sampler(len(x), L, **kw)
+    plain.set_positions(pos)
+    ref, st0 = plain.sample(91, 2, dt=0.01)
+    torch.cuda.synchronize()
+    pc = gpu_lib.Sampler(len(x), L, precond=1, **kw)
+    pc.set_precond_weights(bits)
+    pc.set_positions(pos)
+    out = torch.empty_like(pos)
+    status, st1 = gpu_lib.pse_sample(pc.ctx, 91, 2, 0.01, None, pc._vec(out, "out"))
+    torch.cuda.synchronize()
+    print(f"plain: {st0.lanczos_iters} iterations; preconditioned: status {status},"
+          f" {st1.lanczos_iters} iterations, {st1.precond_fallbacks} fallbacks", flush=True)
+    assert st0.converged and st0.lanczos_iters < 14
+    assert status == gpu_lib.PSE_WARN_PRECOND_FALLBACK
+    assert st1.precond_fallbacks == len(x) and st1.converged and st1.lanczos_iters == st0.lanczos_iters
+    assert torch.equal(out, ref)
+    plain.close()
+    pc.close()
