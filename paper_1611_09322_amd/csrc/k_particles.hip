@@ -1300,8 +1300,15 @@ __global__ __launch_bounds__(64) void k_lz_check(const A *__restrict__ partials,
   __shared__ A Q[kMaxIter * 64];
   if (st->done) return;
   const int lane = threadIdx.x;
-  A v = 0;
-  for (int i = lane; i < nparts; i += 64) v += partials[i];
+  // eight interleaved sums keep eight loads in flight (fixed order)
+  A vs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int i = lane;
+  for (; i + 7 * 64 < nparts; i += 8 * 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) vs[u] += partials[i + u * 64];
+  }
+  for (; i < nparts; i += 64) vs[0] += partials[i];
+  A v = ((vs[0] + vs[1]) + (vs[2] + vs[3])) + ((vs[4] + vs[5]) + (vs[6] + vs[7]));
   v = wave_sum(v);
   const A bb = sqrt(v);
   const int m = st->m;
