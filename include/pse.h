@@ -46,7 +46,8 @@ typedef enum {
   PSE_ERR_HIP = -3,           /* a HIP runtime call failed */
   PSE_ERR_PARAMS = -4,        /* parameters the error model rejects:
                                  rcut >= L/2, eta_SE >= 1, M < P, odd P,
-                                 unsupported grid size */
+                                 unsupported grid size, or an error estimate
+                                 above params.tol */
   PSE_ERR_NONFINITE = -5,     /* non-finite input or Lanczos scalar */
   PSE_ERR_NOT_CONVERGED = -6, /* Lanczos hit max_iter; best iterate written */
   PSE_ERR_NO_POSITIONS = -7,  /* sampling before pse_set_positions */
@@ -73,6 +74,11 @@ typedef struct {
   int32_t precision;        /* pse_precision */
   int32_t precond;          /* 0: none; 1: learned block preconditioner */
   uint32_t flags;           /* reserved, 0 */
+  double tol;               /* requested relative error (Sec. II C); when > 0,
+                               parameters whose estimates exceed it are
+                               rejected: eps_real, eps_wave, and
+                               eps_quad + eps_alias (pse_derived) must each be
+                               <= tol.  0: not checked */
 } pse_params;
 
 typedef struct {
@@ -112,6 +118,13 @@ typedef struct {
   double eps_quad;          /* exp(-pi^2 P^2/2m^2) + erfc(m/sqrt2) (Sec. II C) */
   int32_t cells;            /* linked cells per side for the near-field sum */
   double self_real;         /* real-space self mobility, eq. (self), / (6 pi eta a) */
+  double eps_alias;         /* aliasing estimate of the Gaussian window on the
+                               grid: relative error of the wave sample,
+                               sqrt(sum_k B(k) sum_{n != 0} rho(k, n)^2 / sum_k B(k)),
+                               rho(k, n) = ghat(k + 2 pi n / h) / ghat(k), over
+                               the grid k-set and the first alias shell
+                               n in {-1, 0, 1}^3 (grids above 96^3: summed on
+                               blocks of ceil(M / 96) indices per axis) */
 } pse_derived;
 
 /* Status text for a pse_status value (static string). */
@@ -134,6 +147,50 @@ pse_status pse_destroy(pse_ctx *ctx);
 
 /* Derived quantities of the error model for this context (host struct). */
 pse_status pse_get_derived(const pse_ctx *ctx, pse_derived *out);
+
+/* The same quantities for a parameter set, without a context or a GPU
+ * (host only).  Returns the status pse_create would return for `p` on
+ * parameter validation (PARAMS, INVALID_ARG); *out is filled on PSE_OK. */
+pse_status pse_derive(const pse_params *p, pse_derived *out);
+
+/* Parameter choice (Sec. II C-D): the four error sources are controlled
+ * separately, so for a tolerance tol every one is held at or below it:
+ *   rc = sqrt(-ln tol) / xi                         (eps_real = tol)
+ *   k_cut: the smallest with the Sec. II D bound <= tol; the grid M is the
+ *          smallest supported size with pi / h >= k_cut, or larger
+ *   P: even, with eps_quad(P, m = sqrt(pi P)) + eps_alias <= tol and
+ *      eta_SE = 4 xi^2 sigma^2 < 1
+ * and xi minimises the work model of eq. (work) for this implementation:
+ *   t = c_pair pairs (n_iter + [forces] + 2) + c_node N P^3 (1 + [forces])
+ *       + c_fft M^3 log2 M^3 + c_particle N,
+ * pairs = N (N / V)(4 pi / 3) rc^3 (hard-sphere structure), scanned over
+ * xi a = 0.15 ... 1.5 in steps of 0.01 (or the caller's xi).  The constants
+ * are seconds per near-field pair per product, per particle-node of one
+ * spreading or interpolation, per M^3 log2 M^3 of the FFT set, per
+ * particle; 0 selects values measured on MI355X at 10^6 spheres
+ * (1.96e-12, 1.05e-12, 1.5e-12, 0).  Host only, no GPU. */
+typedef struct {
+  double tol;          /* target relative error of every source, (0, 1) */
+  double xi;           /* > 0: keep this xi; 0: choose it */
+  double n_iter;       /* Lanczos iterations the model assumes (0: 5) */
+  double c_pair, c_node, c_fft, c_particle;  /* work-model constants (0: built-in) */
+  int32_t max_grid;    /* largest grid to consider (0: 512) */
+  int32_t with_forces; /* 1: the step includes dt M F (spreading + one more product) */
+} pse_tuning;
+
+typedef struct {
+  double model_seconds;       /* work-model time of the chosen parameters */
+  double eps_real, eps_wave, eps_quad, eps_alias;
+  double pairs_per_particle;  /* model neighbour count (N / V)(4 pi / 3) rc^3 */
+  double xi_star;             /* eq. (xistar): the large-N asymptote of the
+                                 optimum for the same constants (d_f = 3) */
+} pse_tuning_info;
+
+/* base: n, box, a, eta, kT, lanczos_max_iter, precision, precond, flags are
+ * kept; xi, rcut, grid, support, gauss_m (0), lanczos_tol and tol (= t->tol)
+ * are chosen.  Errors: INVALID_ARG, PARAMS (no feasible choice, e.g. a box
+ * too small for rc < L/2 at any xi). */
+pse_status pse_choose_params(const pse_params *base, const pse_tuning *t, pse_params *out, pse_tuning_info *info);
 
 /* Set the particle positions (pos_dev: n x 3).  Positions are wrapped into
  * [0, L) (a coordinate equal to L maps to 0); overlapping spheres are allowed

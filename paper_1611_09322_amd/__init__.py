@@ -38,7 +38,11 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("precond", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("tol", ctypes.c_double),
     ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Stats(ctypes.Structure):
@@ -67,6 +71,36 @@ class Derived(ctypes.Structure):
         ("eps_quad", ctypes.c_double),
         ("cells", ctypes.c_int32),
         ("self_real", ctypes.c_double),
+        ("eps_alias", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("xi", ctypes.c_double),
+        ("n_iter", ctypes.c_double),
+        ("c_pair", ctypes.c_double),
+        ("c_node", ctypes.c_double),
+        ("c_fft", ctypes.c_double),
+        ("c_particle", ctypes.c_double),
+        ("max_grid", ctypes.c_int32),
+        ("with_forces", ctypes.c_int32),
+    ]
+
+
+class TuningInfo(ctypes.Structure):
+    _fields_ = [
+        ("model_seconds", ctypes.c_double),
+        ("eps_real", ctypes.c_double),
+        ("eps_wave", ctypes.c_double),
+        ("eps_quad", ctypes.c_double),
+        ("eps_alias", ctypes.c_double),
+        ("pairs_per_particle", ctypes.c_double),
+        ("xi_star", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -86,6 +120,9 @@ _SIGS = {
     "pse_create": ([ctypes.POINTER(Params), _VP, ctypes.POINTER(_VP)], ctypes.c_int),
     "pse_destroy": ([_VP], ctypes.c_int),
     "pse_get_derived": ([_VP, ctypes.POINTER(Derived)], ctypes.c_int),
+    "pse_derive": ([ctypes.POINTER(Params), ctypes.POINTER(Derived)], ctypes.c_int),
+    "pse_choose_params": ([ctypes.POINTER(Params), ctypes.POINTER(Tuning), ctypes.POINTER(Params),
+                           ctypes.POINTER(TuningInfo)], ctypes.c_int),
     "pse_set_positions": ([_VP, _VP], ctypes.c_int),
     "pse_sample": ([_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, _VP, _VP, ctypes.POINTER(Stats)],
                    ctypes.c_int),
@@ -183,6 +220,32 @@ def pse_get_derived(ctx):
     d = Derived()
     _check(load().pse_get_derived(ctx, ctypes.byref(d)), "pse_get_derived")
     return d
+
+
+def pse_derive(params):
+    """Error-model quantities of a parameter set (host only, no GPU)."""
+    d = Derived()
+    _check(load().pse_derive(ctypes.byref(params), ctypes.byref(d)), "pse_derive")
+    return d
+
+
+def pse_choose_params(base, tuning):
+    """(chosen Params, TuningInfo) for a tolerance (host only, no GPU)."""
+    out, info = Params(), TuningInfo()
+    _check(load().pse_choose_params(ctypes.byref(base), ctypes.byref(tuning), ctypes.byref(out),
+                                    ctypes.byref(info)), "pse_choose_params")
+    return out, info
+
+
+def make_params(n, box, a=1.0, eta=1.0, kT=1.0, xi=0.5, rcut=None, grid=64, support=8, gauss_m=0.0, tol=1e-4,
+                max_iter=64, precision="fp32", precond=0, flags=0, err_tol=0.0):
+    """Params from keyword arguments (rcut defaults to 4 / xi; tol is the
+    Lanczos tolerance, err_tol the error-model bound, 0 = unchecked)."""
+    if rcut is None:
+        rcut = 4.0 / xi
+    return Params(int(n), box, a, eta, kT, xi, rcut, int(grid), int(support), gauss_m, tol, int(max_iter),
+                  PRECISION[precision] if isinstance(precision, str) else int(precision), int(precond), int(flags),
+                  err_tol)
 
 
 def pse_set_positions(ctx, pos_ptr):
@@ -350,18 +413,19 @@ class Sampler:
     the context runs on torch's current stream at construction."""
 
     def __init__(self, n, box, a=1.0, eta=1.0, kT=1.0, xi=0.5, rcut=None, grid=64, support=8, gauss_m=0.0,
-                 tol=1e-4, max_iter=64, precision="fp32", precond=0, stream=None):
+                 tol=1e-4, max_iter=64, precision="fp32", precond=0, stream=None, flags=0, err_tol=0.0,
+                 params=None):
         import torch
 
         self.torch = torch
-        self.n = int(n)
-        self.grid = int(grid)
-        self.precision = precision
-        self.dtype = torch.float64 if precision == "fp64" else torch.float32
-        if rcut is None:
-            rcut = 4.0 / xi
-        self.params = Params(self.n, box, a, eta, kT, xi, rcut, self.grid, support, gauss_m, tol, max_iter,
-                             PRECISION[precision], int(precond), 0)
+        if params is None:
+            params = make_params(n, box, a, eta, kT, xi, rcut, grid, support, gauss_m, tol, max_iter, precision,
+                                 precond, flags, err_tol)
+        self.params = params
+        self.n = int(params.n)
+        self.grid = int(params.grid)
+        self.precision = {v: k for k, v in PRECISION.items()}[int(params.precision)]
+        self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
@@ -478,7 +542,8 @@ class Batch:
             self.params.append(Params(int(sp["n"]), sp["box"], sp.get("a", 1.0), sp.get("eta", 1.0),
                                       sp.get("kT", 1.0), sp.get("xi", 0.5), rc, int(sp.get("grid", 64)),
                                       int(sp.get("support", 8)), sp.get("gauss_m", 0.0), sp.get("tol", 1e-4),
-                                      int(sp.get("max_iter", 64)), PRECISION[prec], int(sp.get("precond", 0)), 0))
+                                      int(sp.get("max_iter", 64)), PRECISION[prec], int(sp.get("precond", 0)),
+                                      int(sp.get("flags", 0)), sp.get("err_tol", 0.0)))
             self.n.append(int(sp["n"]))
             self.dtypes.append(torch.float64 if prec == "fp64" else torch.float32)
         if stream is None:

@@ -332,9 +332,6 @@ pse_status sample_impl(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter,
     }                                                         \
   } while (0)
 
-// Largest dynamic LDS used by one workgroup of the staged near-field kernels.
-constexpr size_t kLdsBudget = 150 * 1024;
-
 template <typename T>
 pse_status build_neighbors(pse_ctx *c) {
   if (c->lds_B) launch_nbr_lds(c);
@@ -670,7 +667,31 @@ pse_status pse_get_derived(const pse_ctx *c, pse_derived *o) {
   o->eps_quad = c->d.eps_quad;
   o->cells = c->d.nc;
   o->self_real = c->d.self_r;
+  o->eps_alias = c->d.eps_alias;
   return PSE_OK;
+}
+
+pse_status pse_derive(const pse_params *p, pse_derived *o) {
+  if (!p || !o) return PSE_ERR_INVALID_ARG;
+  Derived d;
+  const pse_status st = derive_params(*p, &d);
+  if (st != PSE_OK) return st;
+  o->h = d.h;
+  o->sigma = d.sigma;
+  o->gauss_m = d.gm;
+  o->eta_se = d.eta_se;
+  o->eps_real = d.eps_real;
+  o->eps_wave = d.eps_wave;
+  o->eps_quad = d.eps_quad;
+  o->cells = d.nc;
+  o->self_real = d.self_r;
+  o->eps_alias = d.eps_alias;
+  return PSE_OK;
+}
+
+pse_status pse_choose_params(const pse_params *base, const pse_tuning *t, pse_params *out, pse_tuning_info *info) {
+  if (!base || !t || !out) return PSE_ERR_INVALID_ARG;
+  return choose_params(*base, *t, out, info);
 }
 
 pse_status pse_set_positions(pse_ctx *c, const void *pos) {

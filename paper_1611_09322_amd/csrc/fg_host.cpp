@@ -1,6 +1,5 @@
 // Host-side FP64 pieces: the real-space scalar functions F, G of Appendix A,
-// their small-r series, the FP32 interpolation table, and the parameter /
-// error model of Sec. II C-D.
+// their small-r series and the FP32 interpolation table.
 #include <cmath>
 #include <vector>
 
@@ -167,42 +166,6 @@ void fg_build_table(double xi, double a, double rc, double mu0, const double *se
   for (int k = 0; k <= kTableK; ++k) {
     tab[k] = make_float4((float)Fv[k], (float)Dv[k], (float)(Fv[k + 1] - Fv[k]), (float)(Dv[k + 1] - Dv[k]));
   }
-}
-
-bool fft_size_supported(int M) {
-  switch (M) {
-    case 16: case 32: case 64: case 128: case 256: case 512: return true;
-    default: return false;
-  }
-}
-
-pse_status derive_params(const pse_params &p, Derived *d) {
-  if (p.n < 1 || !(p.box > 0) || !(p.a > 0) || !(p.eta > 0) || !(p.kT >= 0) || !(p.xi > 0) || !(p.rcut > 0))
-    return PSE_ERR_INVALID_ARG;
-  if (p.precision < PSE_FP64 || p.precision > PSE_MIXED) return PSE_ERR_INVALID_ARG;
-  if (p.lanczos_max_iter < 1 || p.lanczos_max_iter > kMaxIter || !(p.lanczos_tol > 0)) return PSE_ERR_PARAMS;
-  if (!(p.rcut < 0.5 * p.box)) return PSE_ERR_PARAMS;
-  if (p.support < 2 || p.support % 2 || p.support > 16 || p.grid < p.support) return PSE_ERR_PARAMS;
-  if (!fft_size_supported(p.grid)) return PSE_ERR_PARAMS;
-  d->L = p.box;
-  d->h = p.box / p.grid;
-  d->gm = p.gauss_m > 0 ? p.gauss_m : std::sqrt(kPi * p.support);
-  d->sigma = p.support * d->h / (2.0 * d->gm);
-  d->eta_se = 4.0 * p.xi * p.xi * d->sigma * d->sigma;
-  if (!(d->eta_se < 1.0)) return PSE_ERR_PARAMS;
-  d->eps_real = std::exp(-p.xi * p.xi * p.rcut * p.rcut);
-  const double kc = kPi / d->h;
-  d->eps_wave = (4.0 / kc * std::exp(-kc * kc / (4 * p.xi * p.xi)) - std::sqrt(kPi) / p.xi * std::erfc(kc / (2 * p.xi))) /
-                (2 * kPi * p.a);
-  d->eps_quad = std::exp(-kPi * kPi * p.support * p.support / (2 * d->gm * d->gm)) + std::erfc(d->gm / std::sqrt(2.0));
-  d->mu0 = 1.0 / (6.0 * kPi * p.eta * p.a);
-  d->self_r = fg_self(p.xi, p.a) * d->mu0;
-  int nc = (int)std::floor(p.box / p.rcut);
-  if (nc < 1) nc = 1;
-  if (nc > 128) nc = 128;
-  d->nc = nc;
-  d->cs = p.box / nc;
-  return PSE_OK;
 }
 
 }  // namespace pse

@@ -1,7 +1,9 @@
 // Particle-side kernels: wrapping and linked-cell binning, the sorted order,
 // the near-field neighbour list, the real-space product w = M_r v
 // (eq. Mreal, Appendix A) and the Lanczos square-root iteration (Sec. II B.1).
+#include <mutex>
 #include <type_traits>
+#include <unordered_set>
 
 #include "launch.hpp"
 
@@ -1534,10 +1536,20 @@ void launch_halo_size(pse_ctx *c, int B) {
   else k_halo_size<1><<<nblk(nblocks, 256), 256, 0, c->stream>>>(c->cell_start, c->d.nc, c->flags);
 }
 
+// Dynamic LDS above 64 KB needs a per-kernel attribute.  It is set once per
+// kernel, to everything the CU's LDS leaves beside the kernel's static LDS,
+// so that launches from several host threads (batches) with different halo
+// sizes never lower it under one another.
 template <typename K> static void allow_lds(K kernel, size_t bytes) {
-  if (bytes > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)bytes);
+  if (bytes <= 64 * 1024) return;
+  static std::mutex mu;
+  static std::unordered_set<const void *> done;
+  const void *k = reinterpret_cast<const void *>(kernel);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!done.insert(k).second) return;
+  hipFuncAttributes fa{};
+  const size_t stat = hipFuncGetAttributes(&fa, k) == hipSuccess ? fa.sharedSizeBytes : 32 * 1024;
+  (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsPerCU - stat));
 }
 
 void launch_nbr_lds(pse_ctx *c) {

@@ -1,0 +1,241 @@
+// Host-side FP64 error model and parameter choice (Sec. II C-D).
+//
+// Four error sources are controlled separately (Sec. II C): the real-space
+// truncation eps_R = exp(-xi^2 rc^2), the wave-space truncation at
+// k_cut = pi / h (bound of Sec. II D), the spectral-Ewald quadrature
+// exp(-pi^2 P^2 / 2m^2) + erfc(m / sqrt 2), and the aliasing of the Gaussian
+// window by the grid (an estimate over the grid's k-set, below).  The
+// parameter choice minimises the work model of eq. (work) over xi with
+// every source at or below the tolerance.
+#include <algorithm>
+#include <cmath>
+#include <thread>
+#include <vector>
+
+#include "pse_internal.hpp"
+
+namespace pse {
+
+static const double kPi = 3.14159265358979323846;
+
+// Sec. II D, last display: bound on the relative self-mobility error of
+// truncating the wave sum at kc (PSE kernel, sinc^2 bounded by (ka)^-2).
+double eps_wave_bound(double kc, double xi, double a) {
+  return (4.0 / kc * std::exp(-kc * kc / (4 * xi * xi)) - std::sqrt(kPi) / xi * std::erfc(kc / (2 * xi))) /
+         (2 * kPi * a);
+}
+
+// Sec. II C: quadrature error of the Gaussian window truncated at m standard
+// deviations over P nodes.
+double eps_quad_bound(int P, double m) {
+  return std::exp(-kPi * kPi * P * P / (2 * m * m)) + std::erfc(m / std::sqrt(2.0));
+}
+
+// Smallest kc with eps_wave_bound(kc) <= tol (the bound decreases with kc).
+double kcut_for(double tol, double xi, double a) {
+  double lo = 1e-6 * xi, hi = 2.0 * xi;
+  while (eps_wave_bound(hi, xi, a) > tol && hi < 1e6 * xi) hi *= 2.0;
+  for (int it = 0; it < 100; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (eps_wave_bound(mid, xi, a) > tol) lo = mid;
+    else hi = mid;
+  }
+  return hi;
+}
+
+// Aliasing estimate of the spectral-Ewald wave sample.  Interpolating the
+// grid field with the Gaussian window (standard deviation sigma, grid
+// spacing h) returns each grid mode k together with its images
+// k + 2 pi n / h, weighted by ghat(k + 2 pi n / h) / ghat(k) after the
+// deconvolution; with independent k-space noise the relative variance of
+// that error is
+//   sum_k B(k) sum_{n != 0} rho(k, n)^2 / sum_k B(k),
+//   rho(k, n)^2 = prod_d exp(-sigma^2 ((k_d + 2 pi n_d / h)^2 - k_d^2)),
+// over the grid k-set (k = 0 and Nyquist indices excluded), first alias
+// shell n in {-1, 0, 1}^3.  The shell sum factorises over the axes,
+// prod_d (1 + rho_d(-1)^2 + rho_d(+1)^2) - 1.  Summed over one octant with
+// sign multiplicities; above 96 frequencies per axis the octant is sampled
+// at the midpoints of blocks of s consecutive indices (s = ceil(M / 96)),
+// each weighted by its index count.  Returns the relative error (the square
+// root).
+double alias_estimate(double L, int M, double xi, double a, double sigma) {
+  const int H = M / 2;  // signed indices 0 .. H - 1 per axis (Nyquist excluded)
+  const int s = std::max(1, (M + 95) / 96);
+  const int nq = (H + s - 1) / s;
+  std::vector<double> k(nq), wt(nq), f1(nq);
+  const double dk = 2.0 * kPi / L, h = L / M, s2 = sigma * sigma;
+  for (int q = 0; q < nq; ++q) {
+    const int j0 = q * s, j1 = std::min(H, j0 + s);
+    const double jm = s == 1 ? (double)j0 : 0.5 * (j0 + j1 - 1);
+    k[q] = jm * dk;
+    // +-j for j > 0, j = 0 once
+    wt[q] = 2.0 * (j1 - j0) - (j0 == 0 ? 1.0 : 0.0);
+    const double g = 2.0 * kPi / h;
+    const double rm = std::exp(-s2 * ((k[q] - g) * (k[q] - g) - k[q] * k[q]));
+    const double rp = std::exp(-s2 * ((k[q] + g) * (k[q] + g) - k[q] * k[q]));
+    f1[q] = 1.0 + rm + rp;
+  }
+  const double inv4x2 = 1.0 / (4.0 * xi * xi);
+  const int nth = std::max(1, std::min(8, nq));
+  std::vector<double> num(nth, 0.0), den(nth, 0.0);
+  auto work = [&](int t) {
+    for (int qx = t; qx < nq; qx += nth)
+      for (int qy = 0; qy < nq; ++qy)
+        for (int qz = 0; qz < nq; ++qz) {
+          const double k2 = k[qx] * k[qx] + k[qy] * k[qy] + k[qz] * k[qz];
+          if (k2 <= 0.0) continue;
+          const double kk = std::sqrt(k2), ka = kk * a;
+          const double sinc = std::sin(ka) / ka;
+          const double B = sinc * sinc * (1.0 + k2 * inv4x2) * std::exp(-k2 * inv4x2) / k2;
+          const double w = wt[qx] * wt[qy] * wt[qz] * B;
+          den[t] += w;
+          num[t] += w * (f1[qx] * f1[qy] * f1[qz] - 1.0);
+        }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nth; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto &x : th) x.join();
+  double N = 0.0, D = 0.0;
+  for (int t = 0; t < nth; ++t) {
+    N += num[t];
+    D += den[t];
+  }
+  return D > 0.0 ? std::sqrt(std::max(N, 0.0) / D) : 0.0;
+}
+
+bool fft_size_supported(int M) {
+  switch (M) {
+    case 16: case 32: case 64: case 128: case 256: case 512: return true;
+    default: return false;
+  }
+}
+
+pse_status derive_params(const pse_params &p, Derived *d) {
+  if (p.n < 1 || !(p.box > 0) || !(p.a > 0) || !(p.eta > 0) || !(p.kT >= 0) || !(p.xi > 0) || !(p.rcut > 0))
+    return PSE_ERR_INVALID_ARG;
+  if (p.precision < PSE_FP64 || p.precision > PSE_MIXED) return PSE_ERR_INVALID_ARG;
+  if (!(p.tol >= 0)) return PSE_ERR_INVALID_ARG;
+  if (p.lanczos_max_iter < 1 || p.lanczos_max_iter > kMaxIter || !(p.lanczos_tol > 0)) return PSE_ERR_PARAMS;
+  if (!(p.rcut < 0.5 * p.box)) return PSE_ERR_PARAMS;
+  if (p.support < 2 || p.support % 2 || p.support > 16 || p.grid < p.support) return PSE_ERR_PARAMS;
+  if (!fft_size_supported(p.grid)) return PSE_ERR_PARAMS;
+  d->L = p.box;
+  d->h = p.box / p.grid;
+  d->gm = p.gauss_m > 0 ? p.gauss_m : std::sqrt(kPi * p.support);
+  d->sigma = p.support * d->h / (2.0 * d->gm);
+  d->eta_se = 4.0 * p.xi * p.xi * d->sigma * d->sigma;
+  if (!(d->eta_se < 1.0)) return PSE_ERR_PARAMS;
+  d->eps_real = std::exp(-p.xi * p.xi * p.rcut * p.rcut);
+  d->eps_wave = eps_wave_bound(kPi / d->h, p.xi, p.a);
+  d->eps_quad = eps_quad_bound(p.support, d->gm);
+  d->eps_alias = alias_estimate(p.box, p.grid, p.xi, p.a, d->sigma);
+  // (a relative slack of 1e-9 admits the chooser's rc = sqrt(-ln tol) / xi
+  // after rounding)
+  const double lim = p.tol * (1.0 + 1e-9);
+  if (p.tol > 0 && (d->eps_real > lim || d->eps_wave > lim || d->eps_quad + d->eps_alias > lim))
+    return PSE_ERR_PARAMS;
+  d->mu0 = 1.0 / (6.0 * kPi * p.eta * p.a);
+  d->self_r = fg_self(p.xi, p.a) * d->mu0;
+  int nc = (int)std::floor(p.box / p.rcut);
+  if (nc < 1) nc = 1;
+  if (nc > 128) nc = 128;
+  d->nc = nc;
+  d->cs = p.box / nc;
+  return PSE_OK;
+}
+
+// Work model of one Brownian step (eq. work, with the constants of this
+// implementation): n_iter + 1 near-field products (with forces) plus the
+// neighbour build, about two products' worth of pair work; spreading and
+// interpolation over N P^3 nodes; the FFT set over M^3 log2 M^3.
+static double model_seconds(const pse_tuning &t, double n, double pairs, int M, int P, bool forces) {
+  const double M3 = (double)M * M * M;
+  const double nprod = t.n_iter + (forces ? 1.0 : 0.0) + 2.0;
+  const double nquad = forces ? 2.0 : 1.0;
+  return t.c_pair * pairs * nprod + t.c_node * n * (double)P * P * P * nquad + t.c_fft * M3 * std::log2(M3) +
+         t.c_particle * n;
+}
+
+pse_status choose_params(const pse_params &base, const pse_tuning &tin, pse_params *out, pse_tuning_info *info) {
+  pse_tuning t = tin;
+  if (!(t.tol > 0 && t.tol < 1)) return PSE_ERR_INVALID_ARG;
+  if (base.n < 1 || !(base.box > 0) || !(base.a > 0)) return PSE_ERR_INVALID_ARG;
+  if (t.n_iter <= 0) t.n_iter = 5.0;
+  if (t.c_pair <= 0) t.c_pair = 1.96e-12;
+  if (t.c_node <= 0) t.c_node = 1.05e-12;
+  if (t.c_fft <= 0) t.c_fft = 1.5e-12;
+  if (t.c_particle < 0) t.c_particle = 0.0;
+  if (t.max_grid <= 0) t.max_grid = 512;
+  const double L = base.box, a = base.a, n = base.n;
+  const double dens = n / (L * L * L);
+  const double lntol = -std::log(t.tol);
+  static const int kGrids[] = {16, 32, 64, 128, 256, 512};
+  std::vector<double> xis;
+  if (t.xi > 0) xis.push_back(t.xi);
+  else
+    for (double xa = 0.15; xa <= 1.5 + 1e-9; xa += 0.01) xis.push_back(xa / a);
+  double best = 1e300;
+  pse_params bp = base;
+  pse_tuning_info bi{};
+  for (double xi : xis) {
+    const double rc = std::sqrt(lntol) / xi;
+    if (!(rc < 0.5 * L)) continue;
+    // ordered pairs at the mean density (hard-sphere structure, d_f = 3)
+    const double pairs = n * dens * 4.0 / 3.0 * kPi * rc * rc * rc;
+    const double kc = kcut_for(t.tol, xi, a);
+    for (int M : kGrids) {
+      if (M > t.max_grid || !fft_size_supported(M)) continue;
+      const double h = L / M;
+      if (kPi / h < kc) continue;
+      for (int P = 2; P <= 16 && P <= M; P += 2) {
+        const double m = std::sqrt(kPi * P), sigma = P * h / (2 * m);
+        if (!(4 * xi * xi * sigma * sigma < 1.0)) break;  // eta_SE grows with P
+        const double eq = eps_quad_bound(P, m);
+        if (eq > t.tol) continue;
+        const double cost = model_seconds(t, n, pairs, M, P, t.with_forces != 0);
+        if (cost >= best) break;  // a larger P at this M costs more
+        const double al = alias_estimate(L, M, xi, a, sigma);
+        if (eq + al > t.tol) continue;
+        best = cost;
+        bp = base;
+        bp.xi = xi;
+        bp.rcut = rc;
+        bp.grid = M;
+        bp.support = P;
+        bp.gauss_m = 0.0;
+        bp.lanczos_tol = t.tol;
+        bp.tol = t.tol;
+        bi.model_seconds = cost;
+        bi.eps_real = std::exp(-xi * xi * rc * rc);
+        bi.eps_wave = eps_wave_bound(kPi / h, xi, a);
+        bi.eps_quad = eq;
+        bi.eps_alias = al;
+        bi.pairs_per_particle = pairs / n;
+        break;
+      }
+    }
+  }
+  if (best >= 1e300) return PSE_ERR_PARAMS;
+  // eq. (xistar), the large-N asymptote of the optimum for these constants
+  // (hard spheres, d_f = 3).  In the form of eq. (work):
+  //   pair work  c_pair nprod N dens (4 pi / 3) rc^3 = C_R n_iter N phi xi^-3,
+  //              rc = sqrt(-ln tol) / xi, phi = dens (4 pi / 3) a^3;
+  //   FFT work   c_fft M^3 log2 M^3 = C_W xi^3 phi^-1 N ln(...),
+  //              M = kc L / pi with kc = kc1 xi (the bound depends on kc / xi
+  //              and xi a only weakly; kc1 taken at the chosen xi).
+  {
+    const double phi = dens * 4.0 / 3.0 * kPi * a * a * a;
+    const double nprod = t.n_iter + (t.with_forces ? 1.0 : 0.0) + 2.0;
+    const double crn = t.c_pair * nprod * std::pow(lntol, 1.5) / (a * a * a);
+    const double kc1 = kcut_for(t.tol, bp.xi, a) / bp.xi;
+    const double cw = t.c_fft * kc1 * kc1 * kc1 * (4.0 / 3.0 * kPi) * a * a * a / (kPi * kPi * kPi * std::log(2.0));
+    const double df = 3.0;
+    bi.xi_star = std::pow(3.0 * cw * std::log(n) / (crn * df * phi * phi), -1.0 / (df + 3.0));
+  }
+  *out = bp;
+  if (info) *info = bi;
+  return PSE_OK;
+}
+
+}  // namespace pse

@@ -15,6 +15,9 @@ constexpr int kMaxIter = 64;     // Lanczos basis capacity
 constexpr int kTableK = 1024;    // F/G table intervals on [0, rcut]
 constexpr int kSeriesTerms = 16; // small-r series terms of the wave complement
 constexpr int kRedBlock = 1024;  // workgroups (partial sums) of the vector reductions
+constexpr size_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit
+// largest dynamic + table LDS of one workgroup of the staged near-field kernels
+constexpr size_t kLdsBudget = 150 * 1024;
 // Learned preconditioner: 24 features, MLP 24 -> 64 -> 64 -> 9.  Weights are
 // one bf16 array: W1 [64][32] (inputs 24..31 zero), b1 [64], W2 [64][64],
 // b2 [64], W3 [16][64] (rows 9..15 zero), b3 [16] (entries 9..15 zero).
@@ -103,7 +106,7 @@ struct WaveCoef {
 
 // ---------------------------------------------------------------- host side
 struct Derived {
-  double L, h, sigma, gm, eta_se, eps_real, eps_wave, eps_quad;
+  double L, h, sigma, gm, eta_se, eps_real, eps_wave, eps_quad, eps_alias;
   double mu0;      // 1 / (6 pi eta a)
   double self_r;   // F_self * mu0
   double cs;       // cell side
@@ -117,7 +120,13 @@ void fg_series_coeffs(double xi, double a, double *serF, double *serG);
 double fg_small_r_threshold(double xi, double a);
 void fg_build_table(double xi, double a, double rc, double mu0, const double *serF, const double *serG,
                     float4 *tab);
+// error model and parameter choice (params_host.cpp)
 pse_status derive_params(const pse_params &p, Derived *d);
+double eps_wave_bound(double kc, double xi, double a);
+double eps_quad_bound(int P, double m);
+double kcut_for(double tol, double xi, double a);
+double alias_estimate(double L, int M, double xi, double a, double sigma);
+pse_status choose_params(const pse_params &base, const pse_tuning &t, pse_params *out, pse_tuning_info *info);
 // learned-preconditioner training targets (precond_host.cpp); false if a
 // patch matrix is not positive definite
 bool precond_targets(const double *x, int n, double L, double a, double xi, double rc, double mu0,

@@ -28,16 +28,14 @@ def se_aliasing_estimate(L, M, xi, P, a=1.0):
     j = np.fft.fftfreq(M, 1.0 / M)
     k1 = 2 * np.pi * j / L
     ok1 = np.abs(j) < M // 2
-    KX, KY, KZ = np.meshgrid(k1, k1, k1, indexing="ij")
-    K2 = KX**2 + KY**2 + KZ**2
+    # the shell sum factorises over the axes:
+    #   sum_{n != 0} prod_d r(k_d, n_d) = prod_d (1 + r(k_d, -1) + r(k_d, 1)) - 1
+    r1 = lambda k, n: np.exp(-((k + 2 * np.pi * n / h) ** 2 - k**2) * s * s)
+    f1 = 1.0 + r1(k1, -1) + r1(k1, 1)
+    K2 = (k1 * k1)[:, None, None] + (k1 * k1)[None, :, None] + (k1 * k1)[None, None, :]
     ok = ok1[:, None, None] & ok1[None, :, None] & ok1[None, None, :] & (K2 > 0)
     B = np.zeros_like(K2)
     B[ok] = ewald.B_kernel(K2[ok], a, xi)
-    r2 = lambda k, n: np.exp(-((k + 2 * np.pi * n / h) ** 2 - k**2) * s * s)
-    tot = np.zeros_like(K2)
-    for nx in (-1, 0, 1):
-        for ny in (-1, 0, 1):
-            for nz in (-1, 0, 1):
-                if nx or ny or nz:
-                    tot += r2(KX, nx) * r2(KY, ny) * r2(KZ, nz)
+    del K2
+    tot = f1[:, None, None] * f1[None, :, None] * f1[None, None, :] - 1.0
     return float(np.sqrt((B * tot)[ok].sum() / B[ok].sum()))

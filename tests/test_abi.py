@@ -40,7 +40,7 @@ def _params(**kw):
     import paper_1611_09322_amd as pse
 
     base = dict(n=10, box=20.0, a=1.0, eta=1.0, kT=1.0, xi=0.5, rcut=8.0, grid=32, support=8, gauss_m=0.0,
-                lanczos_tol=1e-4, lanczos_max_iter=32, precision=1, precond=0, flags=0)
+                lanczos_tol=1e-4, lanczos_max_iter=32, precision=1, precond=0, flags=0, tol=0.0)
     base.update(kw)
     return pse.Params(*[base[f] for f, _ in pse.Params._fields_])
 
@@ -51,6 +51,8 @@ def _params(**kw):
     (dict(support=7), -4),          # odd support
     (dict(grid=16, support=8, xi=2.0), -4),  # eta_SE = 4 xi^2 sigma^2 >= 1
     (dict(lanczos_max_iter=100), -4),
+    (dict(tol=1e-6), -4),           # aliasing of the 32^3 grid (h = 0.63a) is above 1e-6
+    (dict(tol=-1.0), -1),
     (dict(n=0), -1),
     (dict(box=-1.0), -1),
 ])

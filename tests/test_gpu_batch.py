@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import synth
+from parity import check
 from oracle import sampler
 
 pytestmark = pytest.mark.gpu
@@ -68,9 +69,7 @@ def test_batch_replica_matches_oracle(gpu_lib, systems):
     torch.cuda.synchronize()
     ref = sampler.displacement_philox(s["x"], sampler.Params(L=s["L"], xi=sp["xi"], rc=sp["rcut"], M=sp["grid"]),
                                       2024, 9, bits=53)
-    e = np.linalg.norm(out[0].cpu().numpy() - ref) / np.linalg.norm(ref)
-    print(f"batch replica 0 vs oracle: rel err {e:.2e}")
-    assert e < 1e-4
+    check(out[0].cpu().numpy(), ref, 1e-4, "batch replica 0 vs oracle")
     b.close()
 
 

@@ -16,10 +16,7 @@ from oracle import ewald, lanczos, philox, rpy, sampler
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    a = np.asarray(a, dtype=np.float64).ravel()
-    b = np.asarray(b, dtype=np.float64).ravel()
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import check
 
 
 def to_dev(x, dtype):
@@ -61,9 +58,7 @@ def test_real_matvec_matches_dense_oracle(gpu_lib, cfg0, precision, bar):
     s.set_positions(to_dev(x, s.dtype))
     v = synth.normals(1, (len(x), 3))
     w = host(s.real_matvec(to_dev(v, s.dtype)))
-    err = rel(w, Mr @ v.ravel())
-    print(f"real_matvec {precision}: rel err {err:.2e}", flush=True)
-    assert err < bar
+    check(w, Mr @ v.ravel(), bar, f"real_matvec {precision}")
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("mixed", 1e-4), ("fp32", 1e-4)])
@@ -76,10 +71,9 @@ def test_real_sample_matches_symmetric_root(gpu_lib, cfg0, precision, tol):
     y = host(y)
     y_ex = lanczos.sqrt_apply(Mr, z.ravel())
     _, it_ref, _ = lanczos.lanczos_sqrt(lambda v: Mr @ v, z.ravel(), tol)
-    err = rel(y, y_ex)
-    print(f"real_sample {precision}: rel err {err:.2e} iters gpu {st.lanczos_iters} oracle {it_ref}", flush=True)
+    print(f"real_sample {precision}: iters gpu {st.lanczos_iters} oracle {it_ref}", flush=True)
     assert st.converged == 1
-    assert err <= tol
+    check(y, y_ex, tol, f"real_sample {precision}")
     assert abs(st.lanczos_iters - it_ref) <= 1
 
 
@@ -91,9 +85,7 @@ def test_wave_sample_matches_direct_fourier_sum(gpu_lib, cfg0, precision):
     W = synth.normals(3, (3, M0, M0, M0))
     y = host(s.wave_sample(to_dev(W, s.dtype)))
     y_ref = ewald.wave_sample_direct(x, ewald.zeta_from_grid_noise(W), L, 1.0, 1.0, XI)
-    err = rel(y, y_ref)
-    print(f"wave_sample {precision}: rel err {err:.2e}", flush=True)
-    assert err < 1e-4
+    check(y, y_ref, 1e-4, f"wave_sample {precision}")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -104,11 +96,9 @@ def test_wave_apply_and_mobility_match_oracle(gpu_lib, cfg0, precision):
     F = synth.normals(4, (len(x), 3))
     uw = host(s.wave_apply(to_dev(F, s.dtype)))
     uw_ref = ewald.wave_apply_direct(x, F, M0, L, 1.0, 1.0, XI)
-    err = rel(uw, uw_ref)
+    check(uw, uw_ref, 1e-4, f"wave_apply {precision}")
     u = host(s.mobility_apply(to_dev(F, s.dtype)))
-    err2 = rel(u, uw_ref + (Mr @ F.ravel()).reshape(-1, 3))
-    print(f"wave_apply {precision}: {err:.2e}  mobility_apply: {err2:.2e}", flush=True)
-    assert err < 1e-4 and err2 < 1e-4
+    check(u, uw_ref + (Mr @ F.ravel()).reshape(-1, 3), 1e-4, f"mobility_apply {precision}")
 
 
 @pytest.mark.parametrize("precision,bits,tol", [("fp64", 53, 1e-7), ("mixed", 24, 1e-5)])
@@ -129,9 +119,8 @@ def test_full_sample_with_philox_noise(gpu_lib, cfg0, precision, bits, tol):
     yw = ewald.wave_sample_direct(x, zeta, L, 1.0, 1.0, XI)
     u = (Mr @ F.ravel()).reshape(-1, 3) + ewald.wave_apply_direct(x, F, M0, L, 1.0, 1.0, XI)
     ref = np.sqrt(2 * p.kT * dt) * (yr + yw) + dt * u
-    err = rel(d, ref)
-    print(f"sample/philox {precision}: rel err {err:.2e} iters {st.lanczos_iters}", flush=True)
-    assert err < 1e-4
+    print(f"sample/philox {precision}: iters {st.lanczos_iters}", flush=True)
+    check(d, ref, 1e-4, f"sample/philox {precision}")
 
 
 def test_grid_noise_sample_equals_parts(gpu_lib, cfg0):
@@ -144,9 +133,7 @@ def test_grid_noise_sample_equals_parts(gpu_lib, cfg0):
     F = synth.normals(8, (len(x), 3))
     d, _ = s.sample_with_noise(to_dev(z1, s.dtype), to_dev(W, s.dtype), dt=0.3, forces=to_dev(F, s.dtype))
     ref = sampler.displacement_from_grid_noise(x, z1, W, sampler.Params(L=L, xi=XI, rc=RC, M=M0), dt=0.3, forces=F)
-    err = rel(host(d), ref)
-    print(f"sample/grid-noise fp64: rel err {err:.2e}", flush=True)
-    assert err < 1e-4
+    check(host(d), ref, 1e-4, "sample/grid-noise fp64")
 
 
 # ------------------------------------------------------------- edge cases
@@ -167,12 +154,11 @@ def test_ragged_overlapping_unwrapped_positions(gpu_lib, precision, bar_r):
     s.set_positions(to_dev(x, s.dtype))
     Mr = rpy.real_block_dense(x, L, 1.0, 1.0, XI, RC)
     v = synth.normals(10, (len(x), 3))
-    err_r = rel(host(s.real_matvec(to_dev(v, s.dtype))), Mr @ v.ravel())
+    check(host(s.real_matvec(to_dev(v, s.dtype))), Mr @ v.ravel(), bar_r, f"ragged/overlap {precision} M_r v")
     W = synth.normals(11, (3, M, M, M))
     y = host(s.wave_sample(to_dev(W, s.dtype)))
-    err_w = rel(y, ewald.wave_sample_direct(x, ewald.zeta_from_grid_noise(W), L, 1.0, 1.0, XI))
-    print(f"ragged/overlap {precision}: real {err_r:.2e} wave {err_w:.2e}", flush=True)
-    assert err_r < bar_r and err_w < 1e-4
+    check(y, ewald.wave_sample_direct(x, ewald.zeta_from_grid_noise(W), L, 1.0, 1.0, XI), 1e-4,
+          f"ragged/overlap {precision} wave")
 
 
 def test_single_particle(gpu_lib):
@@ -182,9 +168,7 @@ def test_single_particle(gpu_lib):
     s.set_positions(to_dev(x, s.dtype))
     d, st = s.sample(7, 1, dt=1.0)
     ref = sampler.displacement_philox(x, sampler.Params(L=L, xi=XI, rc=RC, M=32), 7, 1, bits=53)
-    err = rel(host(d), ref)
-    print(f"N=1: rel err {err:.2e}", flush=True)
-    assert err < 1e-4
+    check(host(d), ref, 1e-4, "N=1")
 
 
 def test_nonfinite_positions_rejected(gpu_lib):
@@ -208,7 +192,7 @@ def test_not_converged_still_writes_best_iterate(gpu_lib, cfg0):
     assert st.converged == 0 and st.lanczos_iters == 2
     # the 2-step Krylov iterate of the oracle
     _, _, hist = lanczos.lanczos_sqrt(lambda v: Mr @ v, z.ravel(), 1e-30, max_iter=2)
-    assert rel(host(y), hist[-1]) < 1e-10
+    check(host(y), hist[-1], 1e-10, "2-step iterate")
 
 
 # ------------------------------------------------------------ statistics
@@ -246,8 +230,6 @@ def test_zero_temperature_gives_the_deterministic_drift(gpu_lib, cfg0, precision
     F = synth.normals(12, (len(x), 3))
     d, _ = s.sample(5, 9, dt=0.25, forces=to_dev(F, s.dtype))
     u = host(s.mobility_apply(to_dev(F, s.dtype)))
-    err = rel(host(d), 0.25 * u)
+    check(host(d), 0.25 * u, bar, f"kT = 0 {precision} drift")
     d0, _ = s.sample(5, 10, dt=0.25)
-    print(f"kT = 0 {precision}: drift rel err {err:.2e}", flush=True)
-    assert err < bar
     assert not np.any(host(d0))

@@ -2,11 +2,13 @@
 fraction 0.3, 256^3 grid, P = 8, xi a = 0.5, rc = 8a, the launch
 configuration bench.py times) on outputs the oracle computes one at a time,
 plus an independent 2000-sphere box at the same volume fraction checked
-against the full oracle.
+against the full oracle, and rows of the scale configuration (4 10^6 spheres
+at volume fraction 0.4, 512^3).
 
-- near-field rows: brute-force rows of M_r v (exact definition, eq. Mreal);
+- near-field rows: brute-force rows of M_r v (exact definition, eq. Mreal),
+  2000 random particles;
 - wave-space rows: direct non-uniform Fourier sums with the same k-space noise
-  (zeta = DFT(W)/M^{3/2} of the same grid noise W);
+  (zeta = DFT(W)/M^{3/2} of the same grid noise W), the same 2000 particles;
 - the Krylov sample at tol 1e-3 against the same sampler converged in FP64
   (self-convergence; no dense root exists at this size).
 The structure comes from RSA plus a few Monte Carlo sweeps (the kernels see
@@ -23,8 +25,9 @@ pytestmark = pytest.mark.gpu
 N, PHI, M, XI, RC = 1_000_000, 0.3, 256, 0.5, 8.0
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+from parity import FP32_NEAR_BAR, check, rel
+
+NROWS = 2000
 
 
 def host(t):
@@ -37,7 +40,7 @@ def host(t):
 @pytest.fixture(scope="module")
 def big():
     x, L = synth.hard_spheres(N, PHI, a=1.0, seed=1003, sweeps=5)
-    rows = np.random.default_rng(77).choice(N, 48, replace=False)
+    rows = np.sort(np.random.default_rng(77).choice(N, NROWS, replace=False))
     print(f"[scale] N={N} L={L:.3f}", flush=True)
     return x, L, rows
 
@@ -47,20 +50,18 @@ def make(gpu_lib, L, precision, tol=1e-3, n=N, grid=M):
                            max_iter=64, precision=precision)
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp32"])
-def test_near_field_rows_at_full_size(gpu_lib, big, precision):
+def test_near_field_rows_at_full_size(gpu_lib, big):
     import torch
 
     x, L, rows = big
-    s = make(gpu_lib, L, precision)
-    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
     v = synth.normals(31, (N, 3))
-    w = host(s.real_matvec(torch.as_tensor(v, dtype=torch.float32, device="cuda")))
     ref = rpy.real_matvec_rows(x, v, rows, L, 1.0, 1.0, XI, RC)
-    e = rel(w[rows], ref)
-    print(f"[scale] M_r v rows ({precision}): rel err {e:.2e}")
-    assert e < 1e-5
-    s.close()
+    for precision in ("mixed", "fp32"):
+        s = make(gpu_lib, L, precision)
+        s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+        w = host(s.real_matvec(torch.as_tensor(v, dtype=torch.float32, device="cuda")))
+        check(w[rows], ref, FP32_NEAR_BAR, f"[scale] M_r v, {NROWS} rows ({precision})")
+        s.close()
 
 
 def test_wave_rows_at_full_size(gpu_lib, big):
@@ -77,36 +78,68 @@ def test_wave_rows_at_full_size(gpu_lib, big):
     s.close()
     zeta = ewald.zeta_from_grid_noise(W.astype(np.float64))
     del W
-    ref = ewald.wave_sample_direct(x[rows[:24]], zeta, L, 1.0, 1.0, XI)
-    e = rel(y[rows[:24]], ref)
+    ref = ewald.wave_sample_direct(x[rows], zeta, L, 1.0, 1.0, XI)
     est = se_aliasing_estimate(L, M, XI, 8)
-    print(f"[scale] wave-space rows: rel err {e:.2e} (aliasing estimate {est:.2e})")
-    assert e < 1e-3
-    assert e < max(1e-4, 1.5 * est)
+    print(f"[scale] aliasing estimate {est:.2e}")
+    check(y[rows], ref, max(1e-4, 1.5 * est), f"[scale] wave sample, {NROWS} rows")
+    assert rel(y[rows], ref) < 1e-3
 
 
 def test_krylov_sample_at_full_size_converges(gpu_lib, big):
-    """The tol-1e-3 mixed sample against the FP64 sampler at tol 1e-8 on the
-    same z: the error of the stopped iterate stays below the tolerance."""
+    """The tol-1e-3 samples of both timed precisions (FP32 and mixed) against
+    the FP64 sampler at tol 1e-8 on the same z: the error of the stopped
+    iterate stays below the tolerance."""
     import torch
 
     x, L, _ = big
     z = synth.normals(33, (N, 3))
-    s = make(gpu_lib, L, "mixed", tol=1e-3)
-    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
-    y, st = s.real_sample(torch.as_tensor(z, dtype=torch.float32, device="cuda"))
-    y = host(y)
-    s.close()
     r = make(gpu_lib, L, "fp64", tol=1e-8)
     r.set_positions(torch.as_tensor(x, dtype=torch.float64, device="cuda"))
     yr, str_ = r.real_sample(torch.as_tensor(z, dtype=torch.float64, device="cuda"))
     yr = host(yr)
     r.close()
-    e = rel(y, yr)
-    print(f"[scale] Krylov sample: {st.lanczos_iters} iterations at tol 1e-3 vs {str_.lanczos_iters} at 1e-8,"
-          f" rel err {e:.2e}")
-    assert st.converged and str_.converged
-    assert e < 1e-3
+    assert str_.converged
+    for precision in ("mixed", "fp32"):
+        s = make(gpu_lib, L, precision, tol=1e-3)
+        s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+        y, st = s.real_sample(torch.as_tensor(z, dtype=torch.float32, device="cuda"))
+        y = host(y)
+        s.close()
+        print(f"[scale] Krylov sample ({precision}): {st.lanczos_iters} iterations at tol 1e-3 vs"
+              f" {str_.lanczos_iters} at 1e-8")
+        assert st.converged
+        check(y, yr, 1e-3, f"[scale] Krylov sample ({precision}, tol 1e-3) vs FP64 tol 1e-8")
+
+
+@pytest.mark.timeout(900)
+def test_scale_configuration_rows(gpu_lib):
+    """The scale configuration: 4 10^6 spheres at volume fraction 0.4 (FCC
+    start + MC sweeps), 512^3 grid, mixed precision: 256 brute-force rows of
+    M_r v and 256 rows of the wave sample against the direct Fourier sums
+    (bar: the aliasing estimate of this grid spacing, h = 0.68a, with the
+    quadrature bound, as at 256^3)."""
+    import torch
+
+    n4, phi4, m4 = 4_000_000, 0.4, 512
+    x, L = synth.hard_spheres(n4, phi4, a=1.0, seed=1004, sweeps=3)
+    rows = np.sort(np.random.default_rng(78).choice(n4, 256, replace=False))
+    print(f"[scale] N={n4} phi={phi4} L={L:.3f} M={m4}", flush=True)
+    s = make(gpu_lib, L, "mixed", n=n4, grid=m4)
+    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    v = synth.normals(41, (n4, 3))
+    w = host(s.real_matvec(torch.as_tensor(v, dtype=torch.float32, device="cuda")))[rows]
+    check(w, rpy.real_matvec_rows(x, v, rows, L, 1.0, 1.0, XI, RC), FP32_NEAR_BAR, "[scale 4M] M_r v, 256 rows")
+    del v
+    W = np.random.default_rng(42).standard_normal((3, m4, m4, m4), dtype=np.float32)
+    y = host(s.wave_sample(torch.as_tensor(W, device="cuda")))[rows]
+    s.close()
+    torch.cuda.empty_cache()
+    zeta = ewald.zeta_from_grid_noise(W)
+    del W
+    ref = ewald.wave_sample_direct(x[rows], zeta, L, 1.0, 1.0, XI)
+    del zeta
+    est = se_aliasing_estimate(L, m4, XI, 8)
+    check(y, ref, max(1e-4, 1.5 * est), f"[scale 4M] wave sample, 256 rows (aliasing estimate {est:.1e})")
 
 
 @pytest.mark.parametrize("phi", [PHI, 0.4])
@@ -124,9 +157,8 @@ def test_independent_2000_sphere_box_full_oracle(gpu_lib, phi):
     got = host(out)
     s.close()
     ref = sampler.displacement_philox(x, sampler.Params(L=L, xi=XI, rc=RC, M=64), 2024, 5, dt=1e-3, forces=F, bits=24)
-    e = rel(got, ref)
-    print(f"[scale] N=2000 box at phi={phi}: rel err {e:.2e} ({st.lanczos_iters} iterations)")
-    assert e < 1e-4
+    print(f"[scale] N=2000 box at phi={phi}: {st.lanczos_iters} iterations")
+    check(got, ref, 1e-4, f"[scale] N=2000 box at phi={phi}")
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
@@ -145,9 +177,7 @@ def test_largest_grid_512(gpu_lib, precision):
     u = host(s.wave_apply(torch.as_tensor(F, dtype=dt, device="cuda")))
     s.close()
     ref = ewald.wave_apply_direct(x, F, M, L, 1.0, 1.0, XI)
-    e = rel(u, ref)
-    print(f"[scale] 512^3 M_w F ({precision}): rel err {e:.2e}")
-    assert e < 1e-4
+    check(u, ref, 1e-4, f"[scale] 512^3 M_w F ({precision})")
 
 
 def test_products_symmetric_positive_at_full_size(gpu_lib, big):

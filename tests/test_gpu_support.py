@@ -24,10 +24,7 @@ XI, RC = 0.5, 8.0
 FLOOR = {"fp64": 1e-11, "fp32": 1e-5}
 
 
-def rel(a, b):
-    a = np.asarray(a, dtype=np.float64).ravel()
-    b = np.asarray(b, dtype=np.float64).ravel()
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import check
 
 
 def host(t):
@@ -67,9 +64,9 @@ def test_support_size_matches_direct_sums(gpu_lib, box64, P, precision):
     y = host(s.wave_sample(dev(W, s.dtype)))
     u = host(s.wave_apply(dev(F, s.dtype)))
     s.close()
-    ey, eu, b = rel(y, y_ref), rel(u, u_ref), bar(L, M, P, precision)
-    print(f"P={P} {precision}: sample {ey:.2e} apply {eu:.2e} (bar {b:.2e})", flush=True)
-    assert ey < b and eu < b
+    b = bar(L, M, P, precision)
+    check(y, y_ref, b, f"P={P} {precision} sample")
+    check(u, u_ref, b, f"P={P} {precision} apply")
 
 
 @pytest.mark.parametrize("P", [2, 4])
@@ -87,8 +84,8 @@ def test_atomic_spreading_on_small_grids(gpu_lib, P):
     y_ref = ewald.wave_sample_direct(x, ewald.zeta_from_grid_noise(W), L, 1.0, 1.0, XI)
     u_ref = ewald.wave_apply_direct(x, F, M, L, 1.0, 1.0, XI)
     (y64, u64), (y32, u32) = out["fp64"], out["fp32"]
-    ey, eu, b = rel(y64, y_ref), rel(u64, u_ref), bar(L, M, P, "fp64")
-    e32 = max(rel(y32, y64), rel(u32, u64))
-    print(f"M=16 P={P}: sample {ey:.2e} apply {eu:.2e} (bar {b:.2e}); fp32 vs fp64 {e32:.2e}", flush=True)
-    assert ey < b and eu < b
-    assert e32 < FLOOR["fp32"]
+    b = bar(L, M, P, "fp64")
+    check(y64, y_ref, b, f"M=16 P={P} sample")
+    check(u64, u_ref, b, f"M=16 P={P} apply")
+    check(y32, y64, FLOOR["fp32"], f"M=16 P={P} sample fp32 vs fp64")
+    check(u32, u64, FLOOR["fp32"], f"M=16 P={P} apply fp32 vs fp64")
