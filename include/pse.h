@@ -322,6 +322,22 @@ size_t pse_mlp_backward_workspace(int32_t n);
 pse_status pse_mlp_backward(const void *weights_dev, const void *x_dev, const void *act_cache_dev, const void *dy_dev,
                             int32_t n, void *dw_dev, void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* pse_mlp_backward without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation).  The partial gradients go to a fixed
+ * device array inside the library instead: 256 slots of PSE_MLP_NPARAM fp32
+ * (7.1 MiB), which every GPU the library runs on holds until the process
+ * ends.  The pass uses at most 256 slots, so every n >= 1 fits; a count
+ * that needed more would be rejected with PSE_ERR_INVALID_ARG.  Allocates
+ * nothing.  All calls on one GPU share its array, which keeps the last
+ * call's partial sums (each call rewrites every slot entry it reads, so no
+ * clearing is needed): calls that overlap on one GPU (other streams, other
+ * host threads) race and must be serialised by the caller.  dw as in
+ * pse_mlp_backward (same kernels, same summation order).
+ * Errors: INVALID_ARG (null pointer, n < 1), HIP. */
+pse_status pse_mlp_backward_noalloc(const void *weights_dev, const void *x_dev, const void *act_cache_dev,
+                                    const void *dy_dev, int32_t n, void *dw_dev, void *stream);
+
 /* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8, step
  * t >= 1) on the fp32 master weights, with the bf16 copy rewritten. */
 pse_status pse_mlp_adam(void *w_master_dev, void *w_bf16_dev, const void *dw_dev, void *m_dev, void *v_dev, float lr,

@@ -139,6 +139,7 @@ _SIGS = {
     "pse_mlp_forward": ([_VP, _VP, ctypes.c_int32, _VP, _VP, _VP], ctypes.c_int),
     "pse_mlp_backward_workspace": ([ctypes.c_int32], ctypes.c_size_t),
     "pse_mlp_backward": ([_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
+    "pse_mlp_backward_noalloc": ([_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP], ctypes.c_int),
     "pse_mlp_adam": ([_VP, _VP, _VP, _VP, _VP, ctypes.c_float, ctypes.c_int32, _VP], ctypes.c_int),
     "pse_batch_create": ([ctypes.POINTER(Params), ctypes.c_int32, _VP, ctypes.POINTER(_VP)], ctypes.c_int),
     "pse_batch_destroy": ([_VP], ctypes.c_int),
@@ -332,6 +333,11 @@ def pse_mlp_backward_workspace(n):
 def pse_mlp_backward(w_ptr, x_ptr, cache_ptr, dy_ptr, n, dw_ptr, work_ptr, work_bytes, stream=None):
     return _check(load().pse_mlp_backward(w_ptr, x_ptr, cache_ptr, dy_ptr, n, dw_ptr, work_ptr, work_bytes,
                                           _VP(stream or 0)), "pse_mlp_backward")
+
+
+def pse_mlp_backward_noalloc(w_ptr, x_ptr, cache_ptr, dy_ptr, n, dw_ptr, stream=None):
+    return _check(load().pse_mlp_backward_noalloc(w_ptr, x_ptr, cache_ptr, dy_ptr, n, dw_ptr, _VP(stream or 0)),
+                  "pse_mlp_backward_noalloc")
 
 
 def pse_mlp_adam(wm_ptr, wb_ptr, dw_ptr, m_ptr, v_ptr, lr, t, stream=None):

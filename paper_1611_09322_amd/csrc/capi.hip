@@ -1001,6 +1001,15 @@ pse_status pse_mlp_backward(const void *w, const void *x, const void *act_cache,
   return hip_status(hipGetLastError());
 }
 
+pse_status pse_mlp_backward_noalloc(const void *w, const void *x, const void *act_cache, const void *dy, int32_t n,
+                                    void *dw, void *stream) {
+  if (!w || !x || !act_cache || !dy || !dw || n < 1) return PSE_ERR_INVALID_ARG;
+  const pse_status st = launch_mlp_bwd_static((const uint16_t *)w, (const uint16_t *)x, (const uint16_t *)act_cache,
+                                              (const float *)dy, n, (float *)dw, (hipStream_t)stream);
+  if (st != PSE_OK) return st;
+  return hip_status(hipGetLastError());
+}
+
 pse_status pse_mlp_adam(void *w_master, void *w_bf16, const void *dw, void *m, void *v, float lr, int32_t t,
                         void *stream) {
   if (!w_master || !w_bf16 || !dw || !m || !v || t < 1 || !(lr >= 0)) return PSE_ERR_INVALID_ARG;

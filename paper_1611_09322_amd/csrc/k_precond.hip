@@ -8,6 +8,8 @@
 // particle's near field (computed from the neighbour list).  Blocks
 // that are not finite, nearly singular or ill conditioned fall back to I.
 // Training kernels (backward pass, Adam) run off the sampling path.
+#include <mutex>
+
 #include "launch.hpp"
 
 namespace pse {
@@ -418,6 +420,46 @@ void launch_mlp_bwd(const uint16_t *w, const uint16_t *x, const uint16_t *cache,
   const int parts = mlp_bwd_parts(n);
   k_mlp_bwd<<<parts / 4, 256, 0, stream>>>(w, x, cache, dy, n, work);
   k_mlp_reduce<<<nblk(kWTotal, 256), 256, 0, stream>>>(work, parts, dw);
+}
+
+// ------------------------------------------ allocation-free backward pass
+// The same two kernels with the partial-gradient slots in a fixed device
+// array instead of a caller workspace, for callers that cannot allocate.
+// Every GPU holds its own copy of the array (7.1 MiB) until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device (the array's name is a host-side stand-in).  The
+// backward kernel rewrites every entry of each slot it uses, so nothing has
+// to be cleared between calls.  Calls that overlap on one GPU share the
+// array and race.
+static __device__ __align__(256) float scratch[(size_t)kMlpStaticSlots * kWTotal];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+float *scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this GPU's scratch array, looked up once per device
+// with that device current (nullptr on failure).
+static float *static_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    scratch_dev[dev] = (float *)ptr;
+  }
+  return scratch_dev[dev];
+}
+
+pse_status launch_mlp_bwd_static(const uint16_t *w, const uint16_t *x, const uint16_t *cache, const float *dy, int n,
+                                 float *dw, hipStream_t stream) {
+  if (mlp_bwd_parts(n) > kMlpStaticSlots) return PSE_ERR_INVALID_ARG;
+  float *work = static_scratch();
+  if (!work) return PSE_ERR_HIP;
+  launch_mlp_bwd(w, x, cache, dy, n, dw, work, stream);
+  return PSE_OK;
 }
 
 void launch_mlp_adam(float *wm, uint16_t *wb, const float *g, float *m, float *v, float lr, int t,

@@ -38,6 +38,10 @@ void launch_mlp_fwd(const uint16_t *w, const uint16_t *x, int n, float *y, uint1
 int mlp_bwd_parts(int n);  // fp32 slots of kWTotal needed by launch_mlp_bwd's workspace
 void launch_mlp_bwd(const uint16_t *w, const uint16_t *x, const uint16_t *cache, const float *dy, int n, float *dw,
                     float *work, hipStream_t stream);
+// partial-gradient slots of the allocation-free backward pass (>= mlp_bwd_parts(n) for every n)
+constexpr int kMlpStaticSlots = 256;
+pse_status launch_mlp_bwd_static(const uint16_t *w, const uint16_t *x, const uint16_t *cache, const float *dy, int n,
+                                 float *dw, hipStream_t stream);
 void launch_mlp_adam(float *wm, uint16_t *wb, const float *g, float *m, float *v, float lr, int t, hipStream_t stream);
 template <typename T> void launch_pc_blocks(pse_ctx *c);           // features -> MLP -> P, P^-1 (fallbacks in flags[6])
 template <typename T, typename A> void launch_pc_pre(pse_ctx *c, const void *src, void *u);  // u = P^T src
