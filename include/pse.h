@@ -73,13 +73,33 @@ typedef struct {
   int32_t lanczos_max_iter; /* <= 64 */
   int32_t precision;        /* pse_precision */
   int32_t precond;          /* 0: none; 1: learned block preconditioner */
-  uint32_t flags;           /* reserved, 0 */
+  uint32_t flags;           /* PSE_FLAG_* bits below; other bits must be 0 */
   double tol;               /* requested relative error (Sec. II C); when > 0,
                                parameters whose estimates exceed it are
-                               rejected: eps_real, eps_wave, and
-                               eps_quad + eps_alias (pse_derived) must each be
-                               <= tol.  0: not checked */
+                               rejected: eps_real_tail, eps_wave, and
+                               3 eps_quad + eps_alias (pse_derived; the window
+                               error of one spreading or interpolation) must
+                               each be <= tol.  0: not checked */
 } pse_params;
+
+/* pse_params.flags */
+#define PSE_FLAG_NOISE_KSPACE 1u /* wave-noise arguments (pse_sample_with_noise,
+                                    pse_wave_sample) are zeta itself on the stored
+                                    half spectrum: complex [3][M][M][M/2]
+                                    (interleaved real, imaginary; element
+                                    ((c M + jx) M + jy)(M/2) + jz at the signed
+                                    indices of the DFT order), unit variance
+                                    E |zeta|^2 = 1.  On the plane jz = 0 only the
+                                    canonical member of each (k, -k) pair (signed
+                                    jy > 0, or jy = 0 and jx > 0) is read, its
+                                    partner is its conjugate; k = 0 and Nyquist
+                                    entries are not read.  Without the flag the
+                                    argument is real grid noise W and the context
+                                    holds one more 3 M^3 buffer for its spectrum */
+#define PSE_FLAG_FULL_LANCZOS 2u /* the context also holds the basis of
+                                    pse_full_sample (257 vectors of n x 4), and
+                                    lanczos_max_iter may be up to 256 there (the
+                                    near-field sample still stops at 64) */
 
 typedef struct {
   int32_t lanczos_iters;    /* Krylov iterations used by the last real-space sample */
@@ -90,6 +110,8 @@ typedef struct {
   int64_t neighbor_pairs;   /* ordered near-field pairs (sum of neighbour counts) */
   int32_t nbr_index_bytes;  /* bytes per stored neighbour index: 2 on the LDS-staged
                                FP32 path (halo-local), 4 otherwise (global) */
+  int32_t lds_block_edge;   /* cells per edge of the target blocks of the LDS-staged
+                               near-field kernels (1 ... 4), 0 on the global path */
 } pse_stats;
 
 /* Stages of the hot path, for GPU-time accounting (pse_profile). */
@@ -115,7 +137,8 @@ typedef struct {
   double eta_se;            /* 4 xi^2 sigma^2; must be < 1 */
   double eps_real;          /* exp(-xi^2 rcut^2)                (Sec. II C) */
   double eps_wave;          /* analytic k_cut bound, k_cut = pi/h (Sec. II D) */
-  double eps_quad;          /* exp(-pi^2 P^2/2m^2) + erfc(m/sqrt2) (Sec. II C) */
+  double eps_quad;          /* exp(-pi^2 P^2/2m^2) + erfc(m/sqrt2) (Sec. II C), per
+                               axis: the separable window loses about 3 eps_quad */
   int32_t cells;            /* linked cells per side for the near-field sum */
   double self_real;         /* real-space self mobility, eq. (self), / (6 pi eta a) */
   double eps_alias;         /* aliasing estimate of the Gaussian window on the
@@ -125,6 +148,15 @@ typedef struct {
                                the grid k-set and the first alias shell
                                n in {-1, 0, 1}^3 (grids above 96^3: summed on
                                blocks of ceil(M / 96) indices per axis) */
+  double eps_real_tail;     /* real-space truncation of a sample or of M F with
+                               random forces, relative to the Stokes mobility:
+                               sqrt(rho int_rc^inf 4 pi r^2 (2F^2 + G^2)/3 dr),
+                               rho = n / L^3 (F, G of eq. Mreal); exp(-xi^2 rc^2)
+                               above is its decay alone, without the number of
+                               pairs just past rc that multiplies it */
+  double eps_real_coherent; /* the same for M F with aligned forces (the pairs
+                               add in amplitude): rho int_rc^inf 4 pi r^2
+                               |2F + G| / 3 dr */
 } pse_derived;
 
 /* Status text for a pse_status value (static string). */
@@ -153,13 +185,22 @@ pse_status pse_get_derived(const pse_ctx *ctx, pse_derived *out);
  * parameter validation (PARAMS, INVALID_ARG); *out is filled on PSE_OK. */
 pse_status pse_derive(const pse_params *p, pse_derived *out);
 
-/* Parameter choice (Sec. II C-D): the four error sources are controlled
- * separately, so for a tolerance tol every one is held at or below it:
- *   rc = sqrt(-ln tol) / xi                         (eps_real = tol)
- *   k_cut: the smallest with the Sec. II D bound <= tol; the grid M is the
- *          smallest supported size with pi / h >= k_cut, or larger
- *   P: even, with eps_quad(P, m = sqrt(pi P)) + eps_alias <= tol and
- *      eta_SE = 4 xi^2 sigma^2 < 1
+/* Parameter choice (Sec. II C-D): the error sources are controlled
+ * separately.  For a sample (and M F with random forces) the real-space,
+ * wave-space and Krylov errors are independent and add in variance, so
+ * each is held at or below t_s = tol / sqrt 3; for aligned forces
+ * (deterministic) the real-space and wave-space errors are systematic and
+ * add linearly, t_s = tol / 2:
+ *   rc: the smallest with eps_real_tail <= t_s (eps_real_coherent when
+ *       deterministic), rho = n / L^3
+ *   M:  pi / h at or above the k_cut whose Sec. II D bound is t_s (any
+ *       supported size, smallest first)
+ *   P, m: even P and a width m in [max(2, P h xi), 1.4 sqrt(pi P)] with
+ *       eps_wave + w (3 eps_quad + eps_alias) <= t_s, w = 2 when the step
+ *       also spreads forces (with_forces, deterministic: spreading and
+ *       interpolation both err), else 1.  3 eps_quad: the separable window
+ *       is truncated on three axes.  m = sqrt(pi P) when it passes, else
+ *       the width minimising 3 eps_quad + eps_alias (golden section)
  * and xi minimises the work model of eq. (work) for this implementation:
  *   t = c_pair pairs (n_iter + [forces] + 2) + c_node N P^3 (1 + [forces])
  *       + c_fft M^3 log2 M^3 + c_particle N,
@@ -176,6 +217,9 @@ typedef struct {
   double c_pair, c_node, c_fft, c_particle;  /* work-model constants (0: built-in) */
   int32_t max_grid;    /* largest grid to consider (0: 512) */
   int32_t with_forces; /* 1: the step includes dt M F (spreading + one more product) */
+  int32_t deterministic; /* 1: tol bounds M F for aligned forces (sedimentation):
+                            coherent real-space tail, linear error budget; 0:
+                            tol bounds the sample (and M F with random forces) */
 } pse_tuning;
 
 typedef struct {
@@ -184,11 +228,14 @@ typedef struct {
   double pairs_per_particle;  /* model neighbour count (N / V)(4 pi / 3) rc^3 */
   double xi_star;             /* eq. (xistar): the large-N asymptote of the
                                  optimum for the same constants (d_f = 3) */
+  double eps_real_tail;       /* the real-space estimate rc was chosen by
+                                 (pse_derived.eps_real_tail, or
+                                 eps_real_coherent when deterministic) */
 } pse_tuning_info;
 
 /* base: n, box, a, eta, kT, lanczos_max_iter, precision, precond, flags are
- * kept; xi, rcut, grid, support, gauss_m (0), lanczos_tol and tol (= t->tol)
- * are chosen.  Errors: INVALID_ARG, PARAMS (no feasible choice, e.g. a box
+ * kept; xi, rcut, grid, support, gauss_m (0 when sqrt(pi P)), lanczos_tol
+ * (= t_s) and tol (= t->tol) are chosen.  Errors: INVALID_ARG, PARAMS (no feasible choice, e.g. a box
  * too small for rc < L/2 at any xi). */
 pse_status pse_choose_params(const pse_params *base, const pse_tuning *t, pse_params *out, pse_tuning_info *info);
 
@@ -224,11 +271,30 @@ pse_status pse_sample(pse_ctx *ctx, uint64_t seed, uint64_t counter, double dt,
 
 /* Same displacement with caller-supplied noise: z1_dev (n x 3 standard
  * normals) and W_dev (3 x M^3 real standard normals on the grid nodes; the
- * k-space noise is zeta = DFT(W)/M^{3/2}, fluctuating-hydrodynamics form).
+ * k-space noise is zeta = DFT(W)/M^{3/2}, fluctuating-hydrodynamics form;
+ * under PSE_FLAG_NOISE_KSPACE it is zeta itself, see the flag).
  * Either may be NULL (that part is omitted).  forces_dev may be NULL. */
 pse_status pse_sample_with_noise(pse_ctx *ctx, const void *z1_dev, const void *W_dev,
                                  double dt, const void *forces_dev, void *disp_dev,
                                  pse_stats *stats);
+
+/* One Euler-Maruyama step of eq. (langevin) (the divergence term vanishes
+ * in a periodic box, Sec. II B):
+ *   x <- x + dt M (F_ext + F_rep) + sqrt(2 kT dt) M^{1/2} dW,
+ * in place on pos_dev (n x 3, caller order; coordinates are not wrapped, the
+ * library wraps them internally).  Each step rebuilds the cell and
+ * neighbour lists at the current positions (pse_set_positions) and draws
+ * the noise as pse_sample does (key seed, counter step).  F_ext: forces_dev
+ * (n x 3) or NULL.  F_rep: the overlap repulsion of near-hard spheres,
+ *   F_rep,i = sum_{j: r_ij < 2a} krep (2a - r_ij) (x_i - x_j) / r_ij,
+ * accumulated by the neighbour-list scan itself (krep = 0: none).  The
+ * deterministic and stochastic wave terms share one FFT pair (Sec. III).
+ * disp_dev (n x 3) receives the displacement, or NULL.  Synchronises as
+ * pse_set_positions and pse_sample do.
+ * Errors: INVALID_ARG (dt <= 0, krep < 0), those of pse_set_positions and
+ * pse_sample (on NOT_CONVERGED the positions still move by the best iterate). */
+pse_status pse_bd_step(pse_ctx *ctx, void *pos_dev, const void *forces_dev, double dt, double krep, uint64_t seed,
+                       uint64_t step, void *disp_dev, pse_stats *stats);
 
 /* w = M_r v (near-field real-space product, eq. Mreal), v_dev/w_dev n x 3. */
 pse_status pse_real_matvec(pse_ctx *ctx, const void *v_dev, void *w_dev);
@@ -236,7 +302,20 @@ pse_status pse_real_matvec(pse_ctx *ctx, const void *v_dev, void *w_dev);
 /* y = M_r^{1/2} z1 by Lanczos (Sec. II B.1), z1_dev/y_dev n x 3. */
 pse_status pse_real_sample(pse_ctx *ctx, const void *z1_dev, void *y_dev, pse_stats *stats);
 
-/* y = M_w^{1/2} z2 with grid noise W_dev (3 x M^3), y_dev n x 3 (Sec. II B.2). */
+/* y = M^{1/2} z1 on the full mobility M = M_r + M_w by the Lanczos process
+ * (Chow-Saad, the same stopping rule and tolerance as the near-field
+ * sample), each product a near-field product plus a wave-space product
+ * M_w v through the FFT pair: the comparator of Sec. III (Lanczos applied to
+ * the whole mobility), whose iteration count grows with N as the condition
+ * number of M does.  Needs PSE_FLAG_FULL_LANCZOS (PSE_ERR_PARAMS otherwise);
+ * at most lanczos_max_iter (<= 256) iterations, NOT_CONVERGED with the best
+ * iterate written past that.  Synchronises once per iteration (the
+ * tridiagonal square root is solved on the host in FP64).
+ * z1_dev, y_dev: n x 3. */
+pse_status pse_full_sample(pse_ctx *ctx, const void *z1_dev, void *y_dev, pse_stats *stats);
+
+/* y = M_w^{1/2} z2 with grid noise W_dev (3 x M^3), or with zeta itself
+ * under PSE_FLAG_NOISE_KSPACE; y_dev n x 3 (Sec. II B.2). */
 pse_status pse_wave_sample(pse_ctx *ctx, const void *W_dev, void *y_dev);
 
 /* u = M_w F (spread, forward FFT, B(k), inverse FFT, interpolate), n x 3. */
@@ -290,6 +369,19 @@ pse_status pse_mobility_apply(pse_ctx *ctx, const void *forces_dev, void *u_dev)
  * the blocks of the current positions are recomputed.  PSE_ERR_PARAMS if
  * the context was created with precond = 0. */
 pse_status pse_precond_set_weights(pse_ctx *ctx, const void *weights_host, size_t bytes);
+
+/* Use the caller's blocks P_i (P_dev: n x 9 fp32 row-major, caller order,
+ * device; copied) in place of the network's, for the current positions and
+ * at every later pse_set_positions, until pse_precond_set_weights is called
+ * or P_dev is NULL (back to the network's blocks, or I without weights).
+ * Each block passes the same fallback rule.  The sample's covariance is M_r
+ * for any invertible blocks, so blocks computed for an earlier
+ * configuration remain valid: a Brownian-dynamics caller can refresh the
+ * network's blocks (pse_precond_blocks) every k steps and skip the feature
+ * pass and the network in between (pse_set_positions then only gathers the
+ * blocks into the new sorted order).  Synchronises once.
+ * Errors: PARAMS (context without precond = 1), HIP. */
+pse_status pse_precond_set_blocks(pse_ctx *ctx, const void *P_dev);
 
 /* Features of the current positions, n x 24 bf16 (device, caller order). */
 pse_status pse_precond_features(pse_ctx *ctx, void *feat_dev);

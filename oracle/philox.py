@@ -112,8 +112,19 @@ def wave_noise_full(M, seed, sample, bits=53):
     p = (e & np.uint64(1)).astype(np.int64)
     idx = np.arange(len(e))
     zh = (nb[idx, 2 * p] + 1j * nb[idx, 2 * p + 1]) / np.sqrt(2.0)
-    zh = zh.reshape(3, M, M, H)
+    return half_spectrum_to_full(zh.reshape(3, M, M, H))
 
+
+def half_spectrum_to_full(zh):
+    """The full conjugate-symmetric field [3, M, M, M] (DFT order) from values
+    on the stored half spectrum zh[3, M, M, M/2] (jz < M/2): on the plane
+    jz = 0 the canonical member of each (k, -k) pair (signed jy > 0, or
+    jy = 0 and jx > 0) keeps its value and its partner takes the conjugate;
+    k = 0 and the Nyquist entries are zero; entries at jz > M/2 are the
+    conjugates of their mirror images (-k)."""
+    zh = np.array(zh, dtype=np.complex128)
+    M = zh.shape[1]
+    H = M // 2
     s = np.fft.fftfreq(M, 1.0 / M).astype(np.int64)  # signed index per position
     nyq = np.abs(s) == H
     # plane jz = 0: keep canonical draws, partners get conjugates

@@ -19,6 +19,8 @@ PSE_ERR_NOT_CONVERGED = -6
 PSE_WARN_PRECOND_FALLBACK = 1
 MLP_NPARAM = 7312
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
+FLAG_NOISE_KSPACE = 1
+FLAG_FULL_LANCZOS = 2
 
 
 class Params(ctypes.Structure):
@@ -54,6 +56,7 @@ class Stats(ctypes.Structure):
         ("precond_fallbacks", ctypes.c_int32),
         ("neighbor_pairs", ctypes.c_int64),
         ("nbr_index_bytes", ctypes.c_int32),
+        ("lds_block_edge", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -72,6 +75,8 @@ class Derived(ctypes.Structure):
         ("cells", ctypes.c_int32),
         ("self_real", ctypes.c_double),
         ("eps_alias", ctypes.c_double),
+        ("eps_real_tail", ctypes.c_double),
+        ("eps_real_coherent", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -89,6 +94,7 @@ class Tuning(ctypes.Structure):
         ("c_particle", ctypes.c_double),
         ("max_grid", ctypes.c_int32),
         ("with_forces", ctypes.c_int32),
+        ("deterministic", ctypes.c_int32),
     ]
 
 
@@ -101,6 +107,7 @@ class TuningInfo(ctypes.Structure):
         ("eps_alias", ctypes.c_double),
         ("pairs_per_particle", ctypes.c_double),
         ("xi_star", ctypes.c_double),
+        ("eps_real_tail", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -127,12 +134,16 @@ _SIGS = {
     "pse_sample": ([_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, _VP, _VP, ctypes.POINTER(Stats)],
                    ctypes.c_int),
     "pse_sample_with_noise": ([_VP, _VP, _VP, ctypes.c_double, _VP, _VP, ctypes.POINTER(Stats)], ctypes.c_int),
+    "pse_bd_step": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, _VP,
+                     ctypes.POINTER(Stats)], ctypes.c_int),
+    "pse_full_sample": ([_VP, _VP, _VP, ctypes.POINTER(Stats)], ctypes.c_int),
     "pse_real_matvec": ([_VP, _VP, _VP], ctypes.c_int),
     "pse_real_sample": ([_VP, _VP, _VP, ctypes.POINTER(Stats)], ctypes.c_int),
     "pse_wave_sample": ([_VP, _VP, _VP], ctypes.c_int),
     "pse_wave_apply": ([_VP, _VP, _VP], ctypes.c_int),
     "pse_mobility_apply": ([_VP, _VP, _VP], ctypes.c_int),
     "pse_precond_set_weights": ([_VP, _VP, ctypes.c_size_t], ctypes.c_int),
+    "pse_precond_set_blocks": ([_VP, _VP], ctypes.c_int),
     "pse_precond_features": ([_VP, _VP], ctypes.c_int),
     "pse_precond_blocks": ([_VP, _VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "pse_precond_targets": ([ctypes.POINTER(Params), _VP, _VP, ctypes.c_int32, ctypes.c_double, _VP], ctypes.c_int),
@@ -267,6 +278,20 @@ def pse_sample_with_noise(ctx, z1_ptr, W_ptr, dt, forces_ptr, disp_ptr):
     return s, st
 
 
+def pse_bd_step(ctx, pos_ptr, forces_ptr, dt, krep, seed, step, disp_ptr):
+    st = Stats()
+    s = load().pse_bd_step(ctx, pos_ptr, forces_ptr, dt, krep, seed, step, disp_ptr, ctypes.byref(st))
+    _check(s, "pse_bd_step", allow=SAMPLE_OK)
+    return s, st
+
+
+def pse_full_sample(ctx, z_ptr, y_ptr):
+    st = Stats()
+    s = load().pse_full_sample(ctx, z_ptr, y_ptr, ctypes.byref(st))
+    _check(s, "pse_full_sample", allow=SAMPLE_OK)
+    return s, st
+
+
 def pse_real_matvec(ctx, v_ptr, w_ptr):
     return _check(load().pse_real_matvec(ctx, v_ptr, w_ptr), "pse_real_matvec")
 
@@ -298,6 +323,10 @@ def pse_precond_set_weights(ctx, w_bits):
     if w.size != MLP_NPARAM:
         raise ValueError(f"weights must have {MLP_NPARAM} entries")
     return _check(load().pse_precond_set_weights(ctx, w.ctypes.data_as(_VP), w.nbytes), "pse_precond_set_weights")
+
+
+def pse_precond_set_blocks(ctx, P_ptr):
+    return _check(load().pse_precond_set_blocks(ctx, P_ptr), "pse_precond_set_blocks")
 
 
 def pse_precond_features(ctx, feat_ptr):
@@ -482,11 +511,33 @@ class Sampler:
         s, st = pse_sample(self.ctx, seed, counter, dt, self._vec(forces, "forces"), self._vec(out, "out"))
         return out, st
 
+    def _noise(self, W, name="W"):
+        """Grid noise W (3, M, M, M) real, or with PSE_FLAG_NOISE_KSPACE zeta
+        on the half spectrum (3, M, M, M/2) complex."""
+        if W is None:
+            return None
+        if self.params.flags & FLAG_NOISE_KSPACE:
+            ct = self.torch.complex128 if self.dtype == self.torch.float64 else self.torch.complex64
+            return _ptr(W, ct, 3 * self.grid * self.grid * (self.grid // 2), name)
+        return _ptr(W, self.dtype, 3 * self.grid**3, name)
+
     def sample_with_noise(self, z1=None, W=None, dt=1.0, forces=None, out=None):
         out = self._new() if out is None else out
-        Wp = _ptr(W, self.dtype, 3 * self.grid**3, "W")
+        Wp = self._noise(W)
         s, st = pse_sample_with_noise(self.ctx, self._vec(z1, "z1"), Wp, dt, self._vec(forces, "forces"),
                                       self._vec(out, "out"))
+        return out, st
+
+    def bd_step(self, pos, seed, step, dt, krep=0.0, forces=None, disp=None):
+        """One Euler-Maruyama step in place on pos (n, 3); returns stats."""
+        s, st = pse_bd_step(self.ctx, self._vec(pos, "positions"), self._vec(forces, "forces"), dt, krep, seed,
+                            step, self._vec(disp, "disp"))
+        return st
+
+    def full_sample(self, z, out=None):
+        """M^{1/2} z by Lanczos on the whole mobility (flags FLAG_FULL_LANCZOS)."""
+        out = self._new() if out is None else out
+        s, st = pse_full_sample(self.ctx, self._vec(z, "z"), self._vec(out, "out"))
         return out, st
 
     def real_matvec(self, v, out=None):
@@ -501,7 +552,7 @@ class Sampler:
 
     def wave_sample(self, W, out=None):
         out = self._new() if out is None else out
-        pse_wave_sample(self.ctx, _ptr(W, self.dtype, 3 * self.grid**3, "W"), self._vec(out, "out"))
+        pse_wave_sample(self.ctx, self._noise(W), self._vec(out, "out"))
         return out
 
     def wave_apply(self, F, out=None):
@@ -517,6 +568,11 @@ class Sampler:
     # learned block preconditioner (precond=1)
     def set_precond_weights(self, w_bits):
         pse_precond_set_weights(self.ctx, w_bits)
+
+    def set_precond_blocks(self, P):
+        """Use the (n, 3, 3) float32 blocks P (caller order) in place of the
+        network's until set_precond_weights; None returns to the network."""
+        pse_precond_set_blocks(self.ctx, None if P is None else _ptr(P, self.torch.float32, 9 * self.n, "P"))
 
     def precond_features(self, out=None):
         """(n, 24) bfloat16 features of the current positions (caller order)."""

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpse.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["capi.hip", "k_particles.hip", "k_grid.hip", "k_precond.hip", "fg_host.cpp", "params_host.cpp", "precond_host.cpp"]
+SOURCES = ["capi.hip", "k_particles.hip", "k_grid.hip", "k_precond.hip", "k_full.hip", "fg_host.cpp", "params_host.cpp",
+           "precond_host.cpp", "lanczos_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-result", "-I" + os.path.join(ROOT, "include")]

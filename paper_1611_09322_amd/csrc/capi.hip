@@ -43,13 +43,18 @@ struct Alloc {
 };
 
 inline size_t tsize(const pse_ctx *c) { return c->dbl ? 8 : 4; }
+
+// The preconditioned iteration runs when blocks exist (weights or the
+// caller's blocks) and no global fallback is in progress.
+inline bool pc_active(const pse_ctx *c) { return c->pc_on && (c->pc_have_w || c->pc_fixed) && !c->pc_suspend; }
 inline size_t asize(const pse_ctx *c) { return c->acc_dbl ? 8 : 4; }
 
 void free_ctx(pse_ctx *c) {
   if (!c) return;
   void *dev[] = {c->pos_w, c->pos_s, c->perm, c->cell_of, c->cell_count, c->cell_start, c->nbr, c->nbr_cnt,
                  c->flags, c->V, c->lz, c->partials, c->counter, c->table, c->series, c->grid, c->rgrid, c->grid2, c->tw_M,
-                 c->tw_H, c->pc_w, c->pc_feat, c->pc_y, c->pc_P, c->pc_Pinv};
+                 c->tw_H, c->pc_w, c->pc_feat, c->pc_y, c->pc_P, c->pc_Pinv, c->pc_user, c->fl_V, c->fl_ab,
+                 c->fl_coef};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   for (void *p : c->vbuf)
@@ -58,6 +63,7 @@ void free_ctx(pse_ctx *c) {
   if (c->flags_h) (void)hipHostFree(c->flags_h);
   if (c->pc_fb_h) (void)hipHostFree(c->pc_fb_h);
   if (c->lz_h) (void)hipHostFree(c->lz_h);
+  if (c->fl_ab_h) (void)hipHostFree(c->fl_ab_h);
   delete c;
 }
 
@@ -135,8 +141,8 @@ template <typename T, typename A>
 pse_status lz_start(pse_ctx *c, const void *z_sorted) {
   launch_lz_init<T, A>(c, z_sorted);
   // without weights every block is I; pc_suspend: the global fallback below
-  const bool pc = c->pc_on && c->pc_have_w && !c->pc_suspend;
-  const int maxit = c->p.lanczos_max_iter;
+  const bool pc = pc_active(c);
+  const int maxit = c->lz_maxit;
   int k = c->last_iters < 2 ? 2 : c->last_iters;
   if (k > maxit) k = maxit;
   for (int i = 0; i < k; ++i) {
@@ -161,8 +167,8 @@ template <typename T, typename A>
 pse_status lz_finish(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
   take_pc_fallbacks(c, true);
   auto *h = (LzState<A> *)c->lz_h;
-  const bool pc = c->pc_on && c->pc_have_w && !c->pc_suspend;
-  const int maxit = c->p.lanczos_max_iter;
+  const bool pc = pc_active(c);
+  const int maxit = c->lz_maxit;
   while (!h->done && c->lz_launched < maxit) {
     if (pc) launch_lz_iter_pc<T, A>(c, c->lz_launched, z_sorted);
     else launch_lz_iter<T, A>(c, c->lz_launched, z_sorted);
@@ -187,6 +193,10 @@ pse_status lz_finish(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats
   if (pc) launch_pc_apply_inv<T>(c, y_sorted);  // y = P^-1 A^1/2 z
   c->last_iters = h->m;
   if (stats) {
+    stats->max_neighbors = c->flags_h[5];
+    stats->neighbor_pairs = c->pairs;
+    stats->nbr_index_bytes = c->lds_B ? 2 : 4;
+    stats->lds_block_edge = c->lds_B;
     stats->lanczos_iters = h->m;
     stats->converged = h->converged;
     stats->lanczos_rel_change = (double)h->rel_change;
@@ -215,23 +225,24 @@ pse_status wave_core(pse_ctx *c, const void *f_sorted, int noise, const void *W,
     ProfScope ps(c, PSE_STAGE_OTHER);
     return hip_status(hipMemsetAsync(out, 0, sizeof(T) * 4 * c->n, c->stream));
   }
-  if (noise == 2) {
-    if (!c->grid2) {
-      if (hipMalloc(&c->grid2, sizeof(T) * 3 * M3) != hipSuccess) {
-        c->grid2 = nullptr;
-        return PSE_ERR_OOM;
-      }
-    }
+  // caller noise: zeta on the half spectrum as given (NOISE_KSPACE), or
+  // the DFT of the grid noise W (scaled by M^{-3/2} in the x pass)
+  const bool kspace = (c->p.flags & PSE_FLAG_NOISE_KSPACE) != 0;
+  const void *spec = kspace ? W : c->grid2;
+  if (noise == 2 && !kspace) {
     launch_grid_op<T>(c, GridOp::FftZ, W, c->grid2, nullptr, -1, 0);
     launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid2, nullptr, 1, -1);
     launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid2, nullptr, 0, -1);
   }
+  (void)M3;
   if (f_sorted) {
     launch_spread_interp<T>(c, true, f_sorted, c->rgrid);
     launch_grid_op<T>(c, GridOp::FftZAos, c->rgrid, c->grid, nullptr, -1, 0);
     launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid, nullptr, 1, -1);
   }
-  launch_grid_op<T>(c, GridOp::XFused, noise == 2 ? c->grid2 : nullptr, c->grid, &wc, f_sorted ? 1 : 0, noise);
+  WaveCoef wk = wc;
+  if (noise == 2 && kspace) wk.w_scale = 1.0;
+  launch_grid_op<T>(c, GridOp::XFused, noise == 2 ? spec : nullptr, c->grid, &wk, f_sorted ? 1 : 0, noise);
   launch_grid_op<T>(c, GridOp::FftStrided, nullptr, c->grid, nullptr, 1, +1);
   launch_grid_op<T>(c, GridOp::FftZAos, c->grid, c->rgrid, nullptr, +1, 0);
   launch_spread_interp<T>(c, false, c->rgrid, out);
@@ -251,7 +262,7 @@ struct SampleState {
 
 template <typename T, typename A>
 pse_status sample_begin(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter, const void *z1, const void *W,
-                        double dt, const void *forces, SampleState &ss) {
+                        double dt, const void *forces, SampleState &ss, const void *f_add = nullptr) {
   if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
   if (!(dt >= 0)) return PSE_ERR_INVALID_ARG;
   ss.cr = std::sqrt(2.0 * c->p.kT * dt);
@@ -269,9 +280,11 @@ pse_status sample_begin(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter
     const pse_status st = lz_start<T, A>(c, z_s);
     if (st != PSE_OK) return st;
   }
-  ss.forces = forces && dt > 0;
+  ss.forces = (forces || f_add) && dt > 0;
   if (ss.forces) {
-    launch_gather3<T>(c, forces, f_s);
+    // caller-order forces, plus the sorted overlap repulsion of a Brownian step
+    if (f_add) launch_gather3_add<T>(c, forces, f_add, f_s);
+    else launch_gather3<T>(c, forces, f_s);
     launch_spmv<T, A>(c, f_s, ur, false, nullptr);
   }
   const double V = c->d.L * c->d.L * c->d.L;
@@ -299,6 +312,7 @@ pse_status sample_end(pse_ctx *c, const SampleState &ss, double dt, void *disp, 
     stats->max_neighbors = c->flags_h[5];
     stats->neighbor_pairs = c->pairs;
     stats->nbr_index_bytes = c->lds_B ? 2 : 4;
+    stats->lds_block_edge = c->lds_B;
   }
   const pse_status se = hip_status(hipGetLastError());
   return se != PSE_OK ? se : st;
@@ -346,27 +360,48 @@ template <typename T>
 pse_status set_positions_impl(pse_ctx *c, const void *pos) {
   c->have_pos = false;
   launch_bin<T>(c, pos);
-  // FP32 storage: stage the near-field halo in LDS when it fits
+  // FP32 storage: stage the near-field halo in LDS when it fits.  The block
+  // edge B (cells) is the largest whose halo leaves room for two workgroups
+  // per CU (one stages while the other computes), searched downwards from
+  // the previous choice; blocks of more cells keep enough targets per
+  // workgroup when cells hold few particles.  Without such a B, the largest
+  // whose halo fits the budget of one workgroup.
   c->lds_B = 0;
   if (sizeof(T) == 4) {
-    for (int B = 2; B >= 1; --B) {
-      if (c->d.nc < B + 2) continue;
+    auto lds_bytes = [](int hmax) {
+      // one halo slot more: the zero source read by padding entries
+      return (sizeof(float4) + sizeof(float2)) * (size_t)(hmax + 1) + sizeof(float2) * kTableN;
+    };
+    int hm[5] = {-1, -1, -1, -1, -1};
+    auto halo_max = [&](int B) -> pse_status {
       if (hipMemsetAsync(c->flags + 4, 0, sizeof(int), c->stream) != hipSuccess) return PSE_ERR_HIP;
       launch_halo_size(c, B);
       if (hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
           hipStreamSynchronize(c->stream) != hipSuccess)
         return PSE_ERR_HIP;
       if (c->flags_h[0]) return PSE_ERR_NONFINITE;
-      const int hmax = c->flags_h[4];
-      // one halo slot more: the zero source read by padding entries
-      if (hmax <= 65535 && (sizeof(float4) + sizeof(float2)) * (size_t)(hmax + 1) + sizeof(float4) * (kTableK + 1) <=
-                               kLdsBudget) {
-        c->lds_B = B;
-        c->hcap = hmax + 1;
-        const int nb = (c->d.nc + B - 1) / B;
-        c->lds_blocks = nb * nb * nb;
-        break;
+      hm[B] = c->flags_h[4];
+      return PSE_OK;
+    };
+    const int start = c->lds_B_pref ? c->lds_B_pref : 4;
+    int pick = 0;
+    // B >= 2 with two workgroups per CU, then B >= 2 with one, then B = 1
+    for (int pass = 0; pass < 3 && !pick; ++pass) {
+      for (int B = pass < 2 ? start : 1; B >= (pass < 2 ? 2 : 1) && !pick; --B) {
+        if (c->d.nc < B + 2) continue;
+        if (hm[B] < 0) {
+          const pse_status hs = halo_max(B);
+          if (hs != PSE_OK) return hs;
+        }
+        const size_t lim = pass == 0 ? kLdsPerCU / 2 - lds_static_extra(B) : kLdsBudget;
+        if (hm[B] <= 65535 && lds_bytes(hm[B]) <= lim) pick = B;
       }
+    }
+    if (pick) {
+      c->lds_B = c->lds_B_pref = pick;
+      c->hcap = hm[pick] + 1;
+      const int nb = (c->d.nc + pick - 1) / pick;
+      c->lds_blocks = nb * nb * nb;
     }
   }
   pse_status st = build_neighbors<T>(c);
@@ -393,8 +428,9 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
   }
   if (c->pc_on) {
     // features (the LDS path from the list and the staged halo; the global
-    // build accumulated them itself), network, blocks, fallbacks
-    if (c->lds_B) launch_feat_lds(c);
+    // build accumulated them itself), network, blocks, fallbacks; with the
+    // caller's blocks only their gather into the new sorted order
+    if (c->lds_B && !c->pc_fixed) launch_feat_lds(c);
     launch_pc_blocks<T>(c);
     // the count is taken after the next synchronisation (no wait here)
     if (hipMemcpyAsync(c->pc_fb_h, c->flags + 6, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
@@ -402,6 +438,111 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
     c->pc_fb_pending = true;
   }
   c->have_pos = true;
+  return hip_status(hipGetLastError());
+}
+
+// One Euler-Maruyama step of eq. (langevin): rebuild the cell and neighbour
+// lists at the current positions (with the overlap repulsion accumulated by
+// the same scan), draw the displacement dt M (F_ext + F_rep) + sqrt(2 kT dt)
+// M^{1/2} dW with the combined FFT pair, and move the particles.
+template <typename T, typename A>
+pse_status bd_step_impl(pse_ctx *c, void *pos, const void *fext, double dt, double krep, uint64_t seed,
+                        uint64_t step, void *disp, pse_stats *stats) {
+  c->rep_k = krep;
+  pse_status st = set_positions_impl<T>(c, pos);
+  c->rep_k = 0.0;
+  if (st != PSE_OK) return st;
+  void *out = disp ? disp : c->vbuf[5];  // caller-order 3n scratch when the caller keeps no displacement
+  SampleState ss;
+  st = sample_begin<T, A>(c, true, seed, step, nullptr, nullptr, dt, fext, ss, krep > 0 ? c->vbuf[kRepBuf] : nullptr);
+  if (st != PSE_OK) return st;
+  if (ss.real && hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+  st = sample_end<T, A>(c, ss, dt, out, stats);
+  if (st < 0 && st != PSE_ERR_NOT_CONVERGED) return st;
+  launch_advance<T>(c, pos, out);
+  const pse_status se = hip_status(hipGetLastError());
+  return se != PSE_OK ? se : st;
+}
+
+// Krylov sample y = M^{1/2} z on the full mobility M = M_r + M_w (the
+// comparator of Sec. III): the Lanczos process of Sec. II B.1 with each
+// product a near-field product plus a wave-space product M_w v (spread,
+// FFT, B(k), inverse FFT, interpolation), alpha and beta reduced on the
+// device, the tridiagonal square root solved on the host in FP64 after
+// every iteration, the same successive-iterate stopping rule.
+template <typename T, typename A>
+pse_status full_sample_impl(pse_ctx *c, const void *z, void *y, pse_stats *stats) {
+  using T4 = typename vec4<T>::type;
+  constexpr int K = kFullMaxIter;
+  const size_t n = (size_t)c->n;
+  T4 *V = (T4 *)c->fl_V;
+  A *ab = (A *)c->fl_ab, *abh = (A *)c->fl_ab_h;  // alpha_m at [m], beta_m at [K + m]
+  void *zs = c->vbuf[0], *t = c->vbuf[2], *w = c->vbuf[3], *u = c->vbuf[4], *ys = c->vbuf[1];
+  const int maxit = std::min(c->p.lanczos_max_iter, (int32_t)K);
+  auto read_ab = [&]() {
+    return hipMemcpyAsync(abh, ab, sizeof(A) * (2 * K + 2), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+           hipStreamSynchronize(c->stream) == hipSuccess;
+  };
+  launch_gather3<T>(c, z, zs);
+  launch_fl_norm<T, A>(c, zs, ab + K);
+  launch_fl_scale<T, A>(c, zs, ab + K, V);
+  if (!read_ab()) return PSE_ERR_HIP;
+  const double beta0 = (double)abh[K];
+  if (!std::isfinite(beta0)) return PSE_ERR_NONFINITE;
+  const double M3 = (double)c->p.grid * c->p.grid * c->p.grid;
+  const WaveCoef wc = wave_coef(c, 1.0 / (c->p.eta * M3), 0.0, 0, 0);
+  std::vector<double> d, e, sk, sold;
+  int m = 0;
+  bool conv = beta0 == 0.0, finite = true;
+  double rel = 1.0;
+  while (!conv && m < maxit) {
+    const T4 *vm = V + (size_t)m * n;
+    launch_spmv<T, A>(c, vm, t, false, nullptr);                                   // M_r v_m
+    const pse_status ws = wave_core<T>(c, vm, 0, nullptr, wc, u);                   // M_w v_m
+    if (ws != PSE_OK) return ws;
+    launch_fl_alpha<T, A>(c, t, u, vm, ab + m);                                     // t = M v_m, alpha_m
+    launch_fl_update<T, A>(c, t, vm, m ? V + (size_t)(m - 1) * n : nullptr, w, ab + m, ab + K + m,
+                           ab + K + m + 1);                                         // w, beta_{m+1}
+    if (!read_ab()) return PSE_ERR_HIP;
+    ++m;
+    d.assign(abh, abh + m);
+    e.assign(abh + K + 1, abh + K + m);  // beta_1 .. beta_{m-1}
+    const double bnext = (double)abh[K + m];
+    sk.assign(m, 0.0);
+    finite = std::isfinite(bnext) && tridiag_sqrt_e1_host(m, d.data(), e.data(), sk.data());
+    if (!finite) break;
+    double num = 0.0, den = 0.0, sc2 = bnext * bnext;
+    for (int j = 0; j < m; ++j) {
+      const double o = j < (int)sold.size() ? sold[j] : 0.0;
+      num += (sk[j] - o) * (sk[j] - o);
+      den += sk[j] * sk[j];
+      sc2 += d[j] * d[j];
+    }
+    rel = den > 0.0 ? std::sqrt(num / den) : 0.0;
+    conv = (m > 1 && rel <= c->p.lanczos_tol) || bnext <= 1e-11 * std::sqrt(sc2);
+    sold = sk;
+    if (!conv && m < maxit) launch_fl_scale<T, A>(c, w, ab + K + m, V + (size_t)m * n);  // v_m = w / beta_m
+  }
+  std::vector<A> coef(std::max(m, 1));
+  for (int j = 0; j < m; ++j) coef[j] = (A)(beta0 * sk[j]);
+  if (m > 0) {
+    if (hipMemcpyAsync(c->fl_coef, coef.data(), sizeof(A) * m, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return PSE_ERR_HIP;
+    launch_fl_combine<T, A>(c, m, ys);
+  } else if (hipMemsetAsync(ys, 0, sizeof(T) * 4 * n, c->stream) != hipSuccess) {
+    return PSE_ERR_HIP;
+  }
+  launch_finalize<T>(c, ys, 1.0, nullptr, 0.0, nullptr, y);
+  // the coefficients are read by the combine before this call returns
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+  if (stats) {
+    stats->lanczos_iters = m;
+    stats->converged = conv && finite;
+    stats->lanczos_rel_change = rel;
+    stats->precond_fallbacks = 0;
+  }
+  if (!finite) return PSE_ERR_NONFINITE;
+  if (!conv) return PSE_ERR_NOT_CONVERGED;
   return hip_status(hipGetLastError());
 }
 
@@ -580,6 +721,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   c->dbl = p->precision == PSE_FP64;
   c->acc_dbl = p->precision != PSE_FP32;
   c->n = p->n;
+  c->lz_maxit = std::min(p->lanczos_max_iter, (int32_t)kMaxIter);
   c->ncell = d.nc * d.nc * d.nc;
   Alloc al;
   const size_t n = (size_t)p->n, T = tsize(c), A = asize(c);
@@ -609,6 +751,14 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   const size_t M3 = (size_t)p->grid * p->grid * p->grid;
   c->grid = al.dev(3 * T * M3);
   c->rgrid = al.dev(4 * T * M3);
+  if (p->flags & PSE_FLAG_FULL_LANCZOS) {
+    c->fl_V = al.dev(4 * T * n * (size_t)(kFullMaxIter + 1));
+    c->fl_ab = al.dev(A * (2 * kFullMaxIter + 2));
+    c->fl_ab_h = al.host(A * (2 * kFullMaxIter + 2));
+    c->fl_coef = al.dev(A * kFullMaxIter);
+  }
+  // spectrum of caller grid noise W (not needed when the caller gives zeta)
+  if (!(p->flags & PSE_FLAG_NOISE_KSPACE)) c->grid2 = al.dev(3 * T * M3);
   if (p->precond == 1) {
     c->pc_on = true;
     c->pc_w = (uint16_t *)al.dev(sizeof(uint16_t) * kWTotal);
@@ -616,6 +766,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
     c->pc_y = (float *)al.dev(sizeof(float) * kNOut * n);
     c->pc_P = al.dev(12 * T * n);
     c->pc_Pinv = al.dev(12 * T * n);
+    c->pc_user = (float *)al.dev(sizeof(float) * 9 * n);
   }
   // real-space tables (FP64 host evaluation of Appendix A)
   double serF[kSeriesTerms], serG[kSeriesTerms];
@@ -627,7 +778,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   const double thr = fg_small_r_threshold(p->xi, p->a);
   c->small_r2 = thr * thr;
   c->series = (double *)al.dev(sizeof(double) * 2 * kSeriesTerms);
-  if (!c->dbl) c->table = (float4 *)al.dev(sizeof(float4) * (kTableK + 1));
+  if (!c->dbl) c->table = (float2 *)al.dev(sizeof(float2) * kTableN);
   if (c->dbl) upload_twiddles<double>(c, al);
   else upload_twiddles<float>(c, al);
   if (al.st != PSE_OK) {
@@ -636,9 +787,9 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   }
   hipError_t e = hipMemcpy(c->series, c->series_h, sizeof(double) * 2 * kSeriesTerms, hipMemcpyHostToDevice);
   if (!c->dbl && e == hipSuccess) {
-    std::vector<float4> tab(kTableK + 1);
+    std::vector<float2> tab(kTableN);
     fg_build_table(p->xi, p->a, p->rcut, d.mu0, serF, serG, tab.data());
-    e = hipMemcpy(c->table, tab.data(), sizeof(float4) * (kTableK + 1), hipMemcpyHostToDevice);
+    e = hipMemcpy(c->table, tab.data(), sizeof(float2) * kTableN, hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipMemset(c->counter, 0, sizeof(unsigned));
   if (e == hipSuccess && c->pc_w) e = hipMemset(c->pc_w, 0, sizeof(uint16_t) * kWTotal);
@@ -668,6 +819,8 @@ pse_status pse_get_derived(const pse_ctx *c, pse_derived *o) {
   o->cells = c->d.nc;
   o->self_real = c->d.self_r;
   o->eps_alias = c->d.eps_alias;
+  o->eps_real_tail = c->d.eps_real_tail;
+  o->eps_real_coherent = c->d.eps_real_coherent;
   return PSE_OK;
 }
 
@@ -686,6 +839,8 @@ pse_status pse_derive(const pse_params *p, pse_derived *o) {
   o->cells = d.nc;
   o->self_real = d.self_r;
   o->eps_alias = d.eps_alias;
+  o->eps_real_tail = d.eps_real_tail;
+  o->eps_real_coherent = d.eps_real_coherent;
   return PSE_OK;
 }
 
@@ -710,6 +865,19 @@ pse_status pse_sample_with_noise(pse_ctx *c, const void *z1, const void *W, doub
                                  pse_stats *stats) {
   if (!c) return PSE_ERR_INVALID_ARG;
   DISPATCH(c, (sample_impl<T, A>(c, false, 0, 0, z1, W, dt, forces, disp, stats)));
+}
+
+pse_status pse_bd_step(pse_ctx *c, void *pos, const void *forces, double dt, double krep, uint64_t seed,
+                       uint64_t step, void *disp, pse_stats *stats) {
+  if (!c || !pos || !(dt > 0) || !(krep >= 0)) return PSE_ERR_INVALID_ARG;
+  DISPATCH(c, (bd_step_impl<T, A>(c, pos, forces, dt, krep, seed, step, disp, stats)));
+}
+
+pse_status pse_full_sample(pse_ctx *c, const void *z, void *y, pse_stats *stats) {
+  if (!c || !z || !y) return PSE_ERR_INVALID_ARG;
+  if (!c->fl_V) return PSE_ERR_PARAMS;
+  if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  DISPATCH(c, (full_sample_impl<T, A>(c, z, y, stats)));
 }
 
 pse_status pse_real_matvec(pse_ctx *c, const void *v, void *w) {
@@ -925,8 +1093,38 @@ pse_status pse_precond_set_weights(pse_ctx *c, const void *w_host, size_t bytes)
       hipStreamSynchronize(c->stream) != hipSuccess)
     return PSE_ERR_HIP;
   c->pc_have_w = true;
+  const bool was_fixed = c->pc_fixed;
+  c->pc_fixed = false;
   if (!c->have_pos) return PSE_OK;
+  if (was_fixed && c->lds_B) launch_feat_lds(c);  // skipped while the caller's blocks were in use
   // blocks of the current configuration follow the new weights
+  if (hipMemsetAsync(c->flags + 6, 0, sizeof(int), c->stream) != hipSuccess) return PSE_ERR_HIP;
+  if (c->dbl) launch_pc_blocks<double>(c);
+  else launch_pc_blocks<float>(c);
+  if (hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return PSE_ERR_HIP;
+  c->pc_fallbacks = c->flags_h[6];
+  c->pc_fb_pending = false;
+  return hip_status(hipGetLastError());
+}
+
+pse_status pse_precond_set_blocks(pse_ctx *c, const void *P_dev) {
+  if (!c) return PSE_ERR_INVALID_ARG;
+  if (!c->pc_on) return PSE_ERR_PARAMS;
+  if (!P_dev) {
+    // back to the network's blocks (or I without weights)
+    const bool was_fixed = c->pc_fixed;
+    c->pc_fixed = false;
+    if (!c->have_pos || !was_fixed) return PSE_OK;
+    if (c->lds_B) launch_feat_lds(c);
+  } else {
+    if (hipMemcpyAsync(c->pc_user, P_dev, sizeof(float) * 9 * (size_t)c->n, hipMemcpyDeviceToDevice, c->stream) !=
+        hipSuccess)
+      return PSE_ERR_HIP;
+    c->pc_fixed = true;
+    if (!c->have_pos) return PSE_OK;
+  }
   if (hipMemsetAsync(c->flags + 6, 0, sizeof(int), c->stream) != hipSuccess) return PSE_ERR_HIP;
   if (c->dbl) launch_pc_blocks<double>(c);
   else launch_pc_blocks<float>(c);
@@ -942,6 +1140,7 @@ pse_status pse_precond_features(pse_ctx *c, void *feat_out) {
   if (!c || !feat_out) return PSE_ERR_INVALID_ARG;
   if (!c->pc_on) return PSE_ERR_PARAMS;
   if (!c->have_pos) return PSE_ERR_NO_POSITIONS;
+  if (c->pc_fixed && c->lds_B) launch_feat_lds(c);  // not kept up to date while the caller's blocks are in use
   launch_unsort_features(c, feat_out);
   return hip_status(hipGetLastError());
 }

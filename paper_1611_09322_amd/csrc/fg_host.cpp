@@ -148,11 +148,11 @@ void fg_eval_host(double r, double xi, double a, const double *serF, const doubl
   }
 }
 
-// FP32 table on r_k = k rc / K: (F mu0, (G - F) mu0, and their forward
-// differences) for linear interpolation in one 16-byte read.
-void fg_build_table(double xi, double a, double rc, double mu0, const double *serF, const double *serG, float4 *tab) {
-  std::vector<double> Fv(kTableK + 2), Dv(kTableK + 2);
-  for (int k = 0; k <= kTableK + 1; ++k) {
+// FP32 table nodes r_k = k rc / K, k = 0 ... K + 1: (mu0 F, mu0 (G - F)),
+// read two at a time for linear interpolation (the node past rc keeps the
+// interpolation at r = rc inside the table).
+void fg_build_table(double xi, double a, double rc, double mu0, const double *serF, const double *serG, float2 *tab) {
+  for (int k = 0; k < kTableN; ++k) {
     const double r = rc * k / kTableK;
     double F, G;
     if (k == 0) {
@@ -160,11 +160,7 @@ void fg_build_table(double xi, double a, double rc, double mu0, const double *se
     } else {
       fg_eval_host(r, xi, a, serF, serG, &F, &G);
     }
-    Fv[k] = F * mu0;
-    Dv[k] = (G - F) * mu0;
-  }
-  for (int k = 0; k <= kTableK; ++k) {
-    tab[k] = make_float4((float)Fv[k], (float)Dv[k], (float)(Fv[k + 1] - Fv[k]), (float)(Dv[k + 1] - Dv[k]));
+    tab[k] = make_float2((float)(F * mu0), (float)((G - F) * mu0));
   }
 }
 

@@ -163,6 +163,13 @@ template <> struct Plan<64> { static constexpr int n = 2, r[3] = {8, 8, 1}; };
 template <> struct Plan<128> { static constexpr int n = 2, r[3] = {16, 8, 1}; };
 template <> struct Plan<256> { static constexpr int n = 2, r[3] = {16, 16, 1}; };
 template <> struct Plan<512> { static constexpr int n = 3, r[3] = {8, 8, 8}; };
+// 3 x 2^k lengths (grids 24, 48, 96, 192, 384 and their half lengths)
+template <> struct Plan<12> { static constexpr int n = 2, r[3] = {4, 3, 1}; };
+template <> struct Plan<24> { static constexpr int n = 2, r[3] = {8, 3, 1}; };
+template <> struct Plan<48> { static constexpr int n = 2, r[3] = {16, 3, 1}; };
+template <> struct Plan<96> { static constexpr int n = 3, r[3] = {8, 4, 3}; };
+template <> struct Plan<192> { static constexpr int n = 3, r[3] = {16, 4, 3}; };
+template <> struct Plan<384> { static constexpr int n = 3, r[3] = {16, 8, 3}; };
 
 template <typename T, int N, int DIR, int NCOLS, int BLOCK>
 DI void fft_lds(C<T> *buf, const C<T> *tw) {
@@ -458,6 +465,11 @@ __global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, 
           for (int c = 0; c < 3; ++c) {
             C<T> z;
             if (NOISE == 1) z = zeta[hh][c];
+            else if (jz == 0 && !(sy > 0 || (sy == 0 && sx > 0)))
+              // jz = 0 outside the canonical half: the conjugate of the
+              // partner -k (exact Hermitian symmetry for any input spectrum)
+              z = cscale(cconj(specW[c * s_comp + (size_t)((M - jx) % M) * s_fft + (size_t)((M - jy) % M) * H]),
+                         (T)wc.w_scale);
             else z = cscale(specW[c * s_comp + (size_t)jx * s_fft + base + col], (T)wc.w_scale);
             v[c] = cadd(v[c], cscale(z, sto));
           }
@@ -551,14 +563,14 @@ __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *_
   const int by = __builtin_amdgcn_readfirstlane(min((int)(p.y * invh), M - 1));
   const int bz = __builtin_amdgcn_readfirstlane(min((int)(p.z * invh), M - 1));
   const int gx0 = bx - P / 2 + 1, gy0 = by - P / 2 + 1, gz0 = bz - P / 2 + 1;
-  // M is a power of two: wrap with a mask, node index (x, y, z) by shifts
-  const int wrap = M - 1, lg = __builtin_ctz((unsigned)M);
+  // support nodes lie within one period of the grid: one conditional wrap
+  auto wrapi = [M](int g) { return g < 0 ? g + M : (g >= M ? g - M : g); };
   auto *g4 = (const typename vec4<T>::type *)grid;  // interleaved nodes (c0, c1, c2, 0)
   // y weights of the equally spaced support nodes by the Gaussian
   // recurrence w_{k+1} = w_k r_k, r_{k+1} = r_k q (r_0 = e^{-(2 d_0 h + h^2) c},
   // q = e^{-2 h^2 c}, c = 1 / 2 sigma^2): three exponentials instead of P
   T wy[P];
-  unsigned ym[P];  // y offset of the node index, (y mod M) << lg
+  unsigned ym[P];  // y offset of the node index, (y mod M) M
   {
     const T dy0 = (T)gy0 * h - p.y;
     T w = gauss_exp(-dy0 * dy0 * inv2s2), r = gauss_exp(-(T(2) * dy0 + h) * h * inv2s2);
@@ -568,7 +580,7 @@ __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *_
       wy[iy] = w;
       w *= r;
       r *= q;
-      ym[iy] = (unsigned)((gy0 + iy + M) & wrap) << lg;
+      ym[iy] = (unsigned)wrapi(gy0 + iy) * (unsigned)M;
     }
   }
   T ax = 0, ay = 0, az = 0;
@@ -577,11 +589,11 @@ __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *_
     const int gx = gx0 + ix, gz = gz0 + iz;
     const T dx = (T)gx * h - p.x, dz = (T)gz * h - p.z;
     const T wxz = gauss_exp(-(dx * dx + dz * dz) * inv2s2);
-    const unsigned xz = ((unsigned)((gx + M) & wrap) << (2 * lg)) | (unsigned)((gz + M) & wrap);
+    const unsigned xz = (unsigned)wrapi(gx) * (unsigned)(M * M) + (unsigned)wrapi(gz);
 #pragma unroll
     for (int iy = 0; iy < P; ++iy) {
       const T w = wxz * wy[iy];
-      const auto v = g4[xz | ym[iy]];
+      const auto v = g4[xz + ym[iy]];
       ax += w * v.x;
       ay += w * v.y;
       az += w * v.z;
@@ -771,18 +783,31 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
 }
 
 // ----------------------------------------------------------- launchers
+// Largest divisor of n (a multiple of `step`) that is at most lim (at least step).
+constexpr int div_at_most(int n, int lim, int step) {
+  int best = step;
+  for (int d = step; d <= n && d <= lim; d += step)
+    if (n % d == 0) best = d;
+  return best;
+}
+constexpr int pow2_at_most(int lim) {
+  int p = 1;
+  while (2 * p <= lim) p *= 2;
+  return p;
+}
 template <typename T, int M> struct GridCfg {
   // fused x pass holds 3 components: TZ columns x M x 3 complex in LDS
   // (24 KB at M = 256 FP32; at least 4 columns, 32-byte row segments: at
-  // 512^3 4 columns beat 2, 2.1 against 2.6 ms)
-  static constexpr int TZ0 = (1024 / M) > 4 ? (1024 / M) : 4;
-  static constexpr int TZ = (sizeof(T) == 4) ? (TZ0 < (M / 2) ? TZ0 : (M / 2))
-                                             : ((1024 / M) < (M / 2) ? (1024 / M) : (M / 2));
+  // 512^3 4 columns beat 2, 2.1 against 2.6 ms); TZ divides M/2 and is even
+  static constexpr int TZ = (sizeof(T) == 4) ? div_at_most(M / 2, (1024 / M) > 4 ? (1024 / M) : 4, 2)
+                                             : div_at_most(M / 2, (1024 / M) > 2 ? (1024 / M) : 2, 2);
   // strided y pass: TZ1 columns x M complex in LDS (32 KB at M = 256 FP32:
-  // four workgroups per CU keep enough loads in flight)
-  static constexpr int TZ1 = (sizeof(T) == 4) ? ((4096 / M) < (M / 2) ? (4096 / M) : (M / 2))
-                                              : ((2048 / M) < (M / 2) ? (2048 / M) : (M / 2));
-  static constexpr int NL = (sizeof(T) == 4) ? ((8192 / M) < 64 ? (8192 / M) : 64) : ((4096 / M) < 64 ? (4096 / M) : 64);
+  // four workgroups per CU keep enough loads in flight); TZ1 divides M/2
+  static constexpr int TZ1 = div_at_most(M / 2, (sizeof(T) == 4) ? 4096 / M : 2048 / M, 1);
+  // z pass: NL lines per workgroup, a power of two (divides 3 M^2)
+  static constexpr int NL = pow2_at_most(((sizeof(T) == 4) ? 8192 / M : 4096 / M) < 64
+                                             ? ((sizeof(T) == 4) ? 8192 / M : 4096 / M) : 64);
+  static_assert((M / 2) % TZ == 0 && TZ % 2 == 0 && (M / 2) % TZ1 == 0 && (3 * M * M) % NL == 0, "tiles");
 };
 
 template <typename T, int M>
@@ -866,6 +891,11 @@ template <typename T>
 void launch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoef *wc, int x, int y) {
   switch (c->p.grid) {
     case 16: dispatch_grid_op<T, 16>(c, op, a, b, wc, x, y); break;
+    case 24: dispatch_grid_op<T, 24>(c, op, a, b, wc, x, y); break;
+    case 48: dispatch_grid_op<T, 48>(c, op, a, b, wc, x, y); break;
+    case 96: dispatch_grid_op<T, 96>(c, op, a, b, wc, x, y); break;
+    case 192: dispatch_grid_op<T, 192>(c, op, a, b, wc, x, y); break;
+    case 384: dispatch_grid_op<T, 384>(c, op, a, b, wc, x, y); break;
     case 32: dispatch_grid_op<T, 32>(c, op, a, b, wc, x, y); break;
     case 64: dispatch_grid_op<T, 64>(c, op, a, b, wc, x, y); break;
     case 128: dispatch_grid_op<T, 128>(c, op, a, b, wc, x, y); break;

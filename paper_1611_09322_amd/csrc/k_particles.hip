@@ -176,16 +176,16 @@ __global__ void k_gather_pos(const T4 *__restrict__ pos_w, const int *__restrict
 // ------------------------------------------------------- F, G evaluation
 // FP32 modes: linear interpolation in an LDS table of (mu0 F, mu0 (G-F)).
 struct FGTable {
-  const float4 *tab;  // LDS or global
+  const float2 *tab;  // nodes, LDS or global
   float inv_dr;
   __device__ __forceinline__ void eval(float r2, float rinv, float &Fm, float &Dm) const {
     const float u = r2 * rinv * inv_dr;
     int k = (int)u;
-    k = min(k, kTableK - 1);
+    k = min(k, kTableK);
     const float f = u - (float)k;
-    const float4 e = tab[k];
-    Fm = fmaf(f, e.z, e.x);
-    Dm = fmaf(f, e.w, e.y);
+    const float2 e0 = tab[k], e1 = tab[k + 1];
+    Fm = fmaf(f, e1.x - e0.x, e0.x);
+    Dm = fmaf(f, e1.y - e0.y, e0.y);
   }
 };
 
@@ -323,16 +323,19 @@ template <typename T> struct FeatAcc {
 // cells (fewer when a side has < 3 cells, so no cell is visited twice).
 // With FEAT the learned-preconditioner features of s are accumulated from
 // the same hits (fg gives mu0 F and mu0 (G - F); FeatAcc).
-template <typename T, bool FEAT, typename FG>
+// With REP the overlap repulsion f_s = sum_{t: r < 2a} krep (2a - r) d / r
+// (d = x_s - x_t) goes to frep[s].
+template <typename T, bool FEAT, typename FG, bool REP = false>
 __global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, const int *__restrict__ start, int n,
                             int nc, T L, T invL, T inv_cs, T rc2, int *__restrict__ nbr, int *__restrict__ cnt_out,
                             int cap, int *__restrict__ flags, FG fg, T inv_mu0, T fself, T a, T inv_rc,
-                            uint16_t *__restrict__ feat) {
+                            uint16_t *__restrict__ feat, T krep, typename vec4<T>::type *__restrict__ frep) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   int cnt = 0;
   if (s < n) {
   FeatAcc<T> acc;
   if (FEAT) acc.init(fself);
+  T fx = T(0), fy = T(0), fz = T(0);
   const auto p = pos[s];
   const int cx = min((int)(p.x * inv_cs), nc - 1);
   const int cy = min((int)(p.y * inv_cs), nc - 1);
@@ -352,6 +355,12 @@ __global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, cons
           const T ddy = min_image(p.y - q.y, L, invL);
           const T ddz = min_image(p.z - q.z, L, invL);
           const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          if (REP && r2 < T(4) * a * a && r2 > T(0)) {
+            const T r = sqrt(r2), m = krep * (T(2) * a - r) / r;
+            fx += m * ddx;
+            fy += m * ddy;
+            fz += m * ddz;
+          }
           if (r2 <= rc2) {
             if (cnt < cap) nbr[(size_t)cnt * n + s] = t;
             ++cnt;
@@ -370,6 +379,14 @@ __global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, cons
     }
   }
   if (FEAT) acc.store(feat + (size_t)s * kNFeat, cnt);
+  if (REP) {
+    typename vec4<T>::type f;
+    f.x = fx;
+    f.y = fy;
+    f.z = fz;
+    f.w = T(0);
+    frep[s] = f;
+  }
   cnt_out[s] = cnt;
   }
   // total ordered pairs and the largest count: one set of atomics per wavefront
@@ -448,18 +465,18 @@ __device__ __forceinline__ void spmv_body(const typename vec4<T>::type *__restri
 template <typename T, typename A, bool LZ>
 __global__ __launch_bounds__(256) void k_spmv_table(const float4 *__restrict__ pos, const int *__restrict__ nbr,
                                                     const int *__restrict__ cnt, int n, float L, float invL,
-                                                    const float4 *__restrict__ tab_g, float inv_dr, float self_r,
+                                                    const float2 *__restrict__ tab_g, float inv_dr, float self_r,
                                                     const float4 *__restrict__ src, float scale, float4 *__restrict__ out,
                                                     float4 *__restrict__ vm_out, LzState<A> *st, A *partials,
                                                     unsigned *counter) {
-  __shared__ float4 tab[kTableK + 1];
+  __shared__ float2 tab[kTableN];
   __shared__ A sh[16];
   __shared__ int last;
   if (LZ) {
     if (st->done) return;
     scale = (float)st->inv_beta;
   }
-  for (int i = threadIdx.x; i <= kTableK; i += blockDim.x) tab[i] = tab_g[i];
+  for (int i = threadIdx.x; i < kTableN; i += blockDim.x) tab[i] = tab_g[i];
   __syncthreads();
   FGTable fg{tab, inv_dr};
   A dot;
@@ -531,45 +548,55 @@ __global__ __launch_bounds__(256) void k_spmv_exact(const double4 *__restrict__ 
 // slot (q * n + s): one coalesced 16-byte load per lane per 8 neighbours.
 // The last chunk is padded with the index one past the halo (the product's
 // zero source).
-// Needs nc >= B + 2 (no halo cell appears twice).
+// Needs nc >= B + 2 (no halo cell appears twice).  B = 1 ... 4: blocks of
+// more cells keep enough targets per workgroup when cells hold few
+// particles (small rc).
 template <int B> struct Halo {
   static constexpr int HB = B + 2;
-  static constexpr int NH = HB * HB * HB;  // 27 or 64 (one wavefront scans it)
+  static constexpr int NH = HB * HB * HB;  // 27, 64, 125 or 216 halo cells
+  static constexpr int NT = B * B * B;     // target cells
 };
 
-struct HaloTab {
-  int start[64];  // global sorted index of each halo cell's first particle
-  int base[65];   // exclusive prefix of the halo cell counts (LDS offsets)
-  int tcell[8];   // halo index of each target cell
-  int tpre[9];    // exclusive prefix of the target cell counts
-  int ntc;        // number of target cells (< B^3 at the partial last block)
+template <int B> struct HaloTab {
+  int start[Halo<B>::NH];     // global sorted index of each halo cell's first particle
+  int base[Halo<B>::NH + 1];  // exclusive prefix of the halo cell counts (LDS offsets)
+  int tcell[Halo<B>::NT];     // halo index of each target cell
+  int tpre[Halo<B>::NT + 1];  // exclusive prefix of the target cell counts
+  int ntc;                    // number of target cells (< B^3 at the partial last block)
 };
 
 template <int B>
-__device__ __forceinline__ void halo_setup(const int *__restrict__ cell_start, int nc, HaloTab &ht) {
+__device__ __forceinline__ void halo_setup(const int *__restrict__ cell_start, int nc, HaloTab<B> &ht) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   const int nb = (nc + B - 1) / B;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
   if (threadIdx.x < 64) {
-    const int h = threadIdx.x;
-    int cnt = 0;
-    if (h < NH) {
-      const int hx = h / (HB * HB), hy = (h / HB) % HB, hz = h % HB;
-      const int gx = (bx * B - 1 + hx + nc) % nc, gy = (by * B - 1 + hy + nc) % nc, gz = (bz * B - 1 + hz + nc) % nc;
-      const int c = (gx * nc + gy) * nc + gz;
-      const int a = cell_start[c];
-      cnt = cell_start[c + 1] - a;
-      ht.start[h] = a;
-    }
-    int v = cnt;
+    // one wavefront scans the halo cells, 64 at a time, carrying the sum
+    const int lane = threadIdx.x;
+    int carry = 0;
+    for (int h0 = 0; h0 < NH; h0 += 64) {
+      const int h = h0 + lane;
+      int cnt = 0;
+      if (h < NH) {
+        const int hx = h / (HB * HB), hy = (h / HB) % HB, hz = h % HB;
+        const int gx = (bx * B - 1 + hx + nc) % nc, gy = (by * B - 1 + hy + nc) % nc,
+                  gz = (bz * B - 1 + hz + nc) % nc;
+        const int c = (gx * nc + gy) * nc + gz;
+        const int a = cell_start[c];
+        cnt = cell_start[c + 1] - a;
+        ht.start[h] = a;
+      }
+      int v = cnt;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int u = __shfl_up(v, off, 64);
-      if (h >= off) v += u;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+      }
+      if (h < NH) ht.base[h + 1] = carry + v;
+      carry += __shfl(v, 63, 64);
     }
-    if (h < NH) ht.base[h + 1] = v;
-    if (h == 0) ht.base[0] = 0;
+    if (lane == 0) ht.base[0] = 0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -591,8 +618,8 @@ __device__ __forceinline__ void halo_setup(const int *__restrict__ cell_start, i
 }
 
 // LDS index e -> halo cell (largest h with base[h] <= e).
-template <int NH> __device__ __forceinline__ int halo_cell_of(const HaloTab &ht, int e) {
-  int lo = 0, hi = NH;
+template <int B> __device__ __forceinline__ int halo_cell_of(const HaloTab<B> &ht, int e) {
+  int lo = 0, hi = Halo<B>::NH;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (ht.base[mid] <= e) lo = mid;
@@ -606,36 +633,43 @@ template <int NH> __device__ __forceinline__ int halo_cell_of(const HaloTab &ht,
 __device__ __forceinline__ void halo_put(float4 *l, int e, const float4 &q) { l[e] = q; }
 __device__ __forceinline__ void halo_put(float3 *l, int e, const float4 &q) { l[e] = make_float3(q.x, q.y, q.z); }
 
-template <int NH, typename LT>
-__device__ __forceinline__ void halo_stage(const float4 *__restrict__ g, LT *l, const HaloTab &ht) {
-  const int total = ht.base[NH];
+template <int B, typename LT>
+__device__ __forceinline__ void halo_stage(const float4 *__restrict__ g, LT *l, const HaloTab<B> &ht) {
+  const int total = ht.base[Halo<B>::NH];
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int h = halo_cell_of<NH>(ht, e);
+    const int h = halo_cell_of<B>(ht, e);
     halo_put(l, e, g[ht.start[h] + (e - ht.base[h])]);
   }
 }
 
-// Stage positions shifted by whole box lengths to the periodic image nearest
-// to the block centre c: pairs then need no minimum-image correction (valid
-// when the block half-width plus rc stays below L/2, i.e. nc >= B + 3).
-template <int NH, typename LT>
-__device__ __forceinline__ void halo_stage_unwrapped(const float4 *__restrict__ g, LT *l, const HaloTab &ht,
+// Stage positions relative to the block centre c, each at its periodic image
+// nearest to c: pairs then need no minimum-image correction (valid when the
+// block half-width plus rc stays below L/2, i.e. nc >= B + 3), and the
+// staged coordinates are small (a few cells), so that their differences
+// keep the precision of the relative position rather than of the box size.
+template <int B, typename LT>
+__device__ __forceinline__ void halo_stage_unwrapped(const float4 *__restrict__ g, LT *l, const HaloTab<B> &ht,
                                                      float cx, float cy, float cz, float L, float invL) {
-  const int total = ht.base[NH];
+  const int total = ht.base[Halo<B>::NH];
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int h = halo_cell_of<NH>(ht, e);
+    const int h = halo_cell_of<B>(ht, e);
     float4 q = g[ht.start[h] + (e - ht.base[h])];
-    q.x = cx + min_image(q.x - cx, L, invL);
-    q.y = cy + min_image(q.y - cy, L, invL);
-    q.z = cz + min_image(q.z - cz, L, invL);
+    q.x = min_image(q.x - cx, L, invL);
+    q.y = min_image(q.y - cy, L, invL);
+    q.z = min_image(q.z - cz, L, invL);
     halo_put(l, e, q);
   }
 }
 
 // target i of the block -> (halo cell index, LDS index, global sorted index)
-__device__ __forceinline__ void target_of(const HaloTab &ht, int i, int &h, int &li, int &s) {
-  int j = 0;
-  while (j + 1 < ht.ntc && ht.tpre[j + 1] <= i) ++j;
+template <int B> __device__ __forceinline__ void target_of(const HaloTab<B> &ht, int i, int &h, int &li, int &s) {
+  // largest target cell j with tpre[j] <= i
+  int j = 0, hi = ht.ntc;
+  while (hi - j > 1) {
+    const int mid = (j + hi) >> 1;
+    if (ht.tpre[mid] <= i) j = mid;
+    else hi = mid;
+  }
   h = ht.tcell[j];
   const int off = i - ht.tpre[j];
   li = ht.base[h] + off;
@@ -660,15 +694,20 @@ __global__ void k_halo_size(const int *__restrict__ cell_start, int nc, int *__r
   atomicMax(&flags[4], tot);
 }
 
-// flags[1]: list capacity needed; flags[5]: largest count.
-template <int B, bool UNWRAP>
+// flags[1]: list capacity needed; flags[5]: largest count.  With REP the
+// same scan accumulates the overlap repulsion of each target,
+//   f_s = sum_{t: r < 2a} krep (2a - r) d / r,  d = x_s - x_t,
+// into frep[s] (the candidates' distances are at hand; overlapping pairs
+// are rare, so the branch is almost never taken).
+template <int B, bool UNWRAP, bool REP = false>
 __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
                                                  int nc, float cs, int n, float L, float invL, float rc2,
                                                  uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
-                                                 int *__restrict__ flags) {
+                                                 int *__restrict__ flags, float contact, float krep,
+                                                 float4 *__restrict__ frep) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   extern __shared__ float3 hpos3[];  // coordinates only
-  __shared__ HaloTab ht;
+  __shared__ HaloTab<B> ht;
   // for each 4-bit hit mask: (offsets of the set bits in 16-bit fields, low
   // and high word; 0xFFFF in each used field, low and high word)
   __shared__ uint4 pack_tab[16];
@@ -689,9 +728,9 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
     const float c0 = 0.5f * B * cs;
-    halo_stage_unwrapped<NH>(pos, hpos3, ht, bx * B * cs + c0, by * B * cs + c0, bz * B * cs + c0, L, invL);
+    halo_stage_unwrapped<B>(pos, hpos3, ht, bx * B * cs + c0, by * B * cs + c0, bz * B * cs + c0, L, invL);
   } else {
-    halo_stage<NH>(pos, hpos3, ht);
+    halo_stage<B>(pos, hpos3, ht);
   }
   __syncthreads();
   const int ntarg = ht.tpre[ht.ntc];
@@ -704,6 +743,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
     const int ox = h / (HB * HB) - 1, oy = (h / HB) % HB - 1, oz = h % HB - 1;
     const float3 p = hpos3[li];
     int k = 0;
+    float fx = 0.f, fy = 0.f, fz = 0.f;  // overlap repulsion (REP)
     uint64_t lo = 0, hi = 0;  // the current chunk of 8 packed 16-bit indices
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy)
@@ -729,6 +769,12 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
               const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
               const int j = j0 + u;
               hit |= (j < e && j != li && r2 <= rc2) ? 1u << u : 0u;
+              if (REP && j < e && j != li && r2 < contact * contact && r2 > 0.f) {
+                const float r = sqrtf(r2), m = krep * (contact - r) / r;
+                fx += m * ddx;
+                fy += m * ddy;
+                fz += m * ddz;
+              }
             }
             // the hits of the step, compacted: field f of V is j0 plus the
             // offset of the f-th set bit (pattern table), then V is
@@ -768,6 +814,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
       row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
     }
     cnt_out[s] = k;
+    if (REP) frep[s] = make_float4(fx, fy, fz, 0.f);
     mine += (unsigned long long)k;
     mx = max(mx, k);
   }
@@ -812,24 +859,24 @@ template <int B, bool UNWRAP>
 __global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
                                                    int nc, float cs, int n, float L, float invL,
                                                    const uint16_t *__restrict__ nbr, const int *__restrict__ cnt,
-                                                   const float4 *__restrict__ tab, float inv_dr, float inv_mu0,
+                                                   const float2 *__restrict__ tab, float inv_dr, float inv_mu0,
                                                    float fself, float a, float near2, uint16_t *__restrict__ feat) {
   constexpr int NH = Halo<B>::NH;
   constexpr int G = 3, GPW = 64 / G;
   extern __shared__ float4 hpos[];
-  __shared__ HaloTab ht;
+  __shared__ HaloTab<B> ht;
   __shared__ uint16_t queue[kFeatQ * kFeatNT];
-  __shared__ float4 ftab[kTableK + 1];
-  for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) ftab[k] = tab[k];
+  __shared__ float2 ftab[kTableN];
+  for (int k = threadIdx.x; k < kTableN; k += blockDim.x) ftab[k] = tab[k];
   halo_setup<B>(cell_start, nc, ht);
   if (UNWRAP) {
     const int nb = (nc + B - 1) / B;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
     const float c0 = 0.5f * B * cs;
-    halo_stage_unwrapped<NH>(pos, hpos, ht, bx * B * cs + c0, by * B * cs + c0, bz * B * cs + c0, L, invL);
+    halo_stage_unwrapped<B>(pos, hpos, ht, bx * B * cs + c0, by * B * cs + c0, bz * B * cs + c0, L, invL);
   } else {
-    halo_stage<NH>(pos, hpos, ht);
+    halo_stage<B>(pos, hpos, ht);
   }
   __syncthreads();
   const FGTable fg{ftab, inv_dr};
@@ -937,7 +984,7 @@ template <int B, bool UNWRAP, typename A, bool LZ, bool PC = false, int G = 3>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
                                                    const int *__restrict__ cell_start, int nc, float cs, int n,
                                                    int hcap, float L, float invL, const uint16_t *__restrict__ nbr,
-                                                   const int *__restrict__ cnt, const float4 *__restrict__ tab,
+                                                   const int *__restrict__ cnt, const float2 *__restrict__ tab,
                                                    float inv_dr, float self_r, float scale, float4 *__restrict__ out,
                                                    float4 *__restrict__ vm_out, LzState<A> *st, A *partials,
                                                    unsigned *counter, const float4 *__restrict__ Pm = nullptr,
@@ -948,15 +995,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   extern __shared__ float4 smem[];
   float4 *hA = smem;                        // (x, y, z, v_x)
   float2 *hB = (float2 *)(smem + hcap);     // (v_y, v_z)
-  __shared__ float4 tabs[kTableK + 1];
-  __shared__ HaloTab ht;
+  __shared__ float2 tabs[kTableN];
+  __shared__ HaloTab<B> ht;
   __shared__ A sh[16];
   __shared__ int last;
   if (LZ) {
     if (st->done) return;
     scale = (float)st->inv_beta;
   }
-  for (int k = threadIdx.x; k <= kTableK; k += blockDim.x) tabs[k] = tab[k];
+  for (int k = threadIdx.x; k < kTableN; k += blockDim.x) tabs[k] = tab[k];
   halo_setup<B>(cell_start, nc, ht);
   {
     const int nb = (nc + B - 1) / B;
@@ -970,18 +1017,20 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     // coordinates are staged in units of the table spacing rc / kTableK:
     // r is then the table coordinate itself (the (G - F) term is invariant)
     if (threadIdx.x == 0) {
-      hA[total] = make_float4(cx * inv_dr, cy * inv_dr, cz * inv_dr, 0.0f);
+      // (UNWRAP: coordinates relative to the block centre)
+      hA[total] = UNWRAP ? make_float4(0.0f, 0.0f, 0.0f, 0.0f)
+                         : make_float4(cx * inv_dr, cy * inv_dr, cz * inv_dr, 0.0f);
       hB[total] = make_float2(0.0f, 0.0f);
     }
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      const int h = halo_cell_of<NH>(ht, e);
+      const int h = halo_cell_of<B>(ht, e);
       const int gi = ht.start[h] + (e - ht.base[h]);
       float4 q = pos[gi];
       const float4 v = src[gi];
       if (UNWRAP) {
-        q.x = cx + min_image(q.x - cx, L, invL);
-        q.y = cy + min_image(q.y - cy, L, invL);
-        q.z = cz + min_image(q.z - cz, L, invL);
+        q.x = min_image(q.x - cx, L, invL);
+        q.y = min_image(q.y - cy, L, invL);
+        q.z = min_image(q.z - cz, L, invL);
       }
       q.x *= inv_dr;
       q.y *= inv_dr;
@@ -1046,14 +1095,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
           kk[u] = min((int)uu, kTableK);
           fr[u] = __builtin_amdgcn_fractf(uu);
         }
-        float4 e[4];
+        float2 e0[4], e1[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) e[u] = tabs[kk[u]];
+        for (int u = 0; u < 4; ++u) {
+          e0[u] = tabs[kk[u]];
+          e1[u] = tabs[kk[u] + 1];
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const float wx = q[u].w, wy = wb[u].x, wz = wb[u].y;
-          const float Fm = fmaf(fr[u], e[u].z, e[u].x);
-          const float Dm = fmaf(fr[u], e[u].w, e[u].y);
+          const float Fm = fmaf(fr[u], e1[u].x - e0[u].x, e0[u].x);
+          const float Dm = fmaf(fr[u], e1[u].y - e0[u].y, e0[u].y);
           const float pr = Dm * rinv[u] * rinv[u] * (dx[u] * wx + dy[u] * wy + dz[u] * wz);
           ax = fmaf(pr, dx[u], fmaf(Fm, wx, ax));
           ay = fmaf(pr, dy[u], fmaf(Fm, wy, ay));
@@ -1375,6 +1427,37 @@ __global__ void k_gather3(const T *__restrict__ in, const int *__restrict__ perm
   out[s] = v;
 }
 
+// Caller-order n x 3 (or none) -> sorted (x, y, z, 0), plus a sorted
+// vector `add` (or none).
+template <typename T>
+__global__ void k_gather3_add(const T *__restrict__ in, const int *__restrict__ perm,
+                              const typename vec4<T>::type *__restrict__ add, typename vec4<T>::type *__restrict__ out,
+                              int n) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  typename vec4<T>::type v;
+  v.x = v.y = v.z = v.w = T(0);
+  if (in) {
+    const int i = perm[s];
+    v.x = in[3 * i];
+    v.y = in[3 * i + 1];
+    v.z = in[3 * i + 2];
+  }
+  if (add) {
+    const auto a = add[s];
+    v.x += a.x;
+    v.y += a.y;
+    v.z += a.z;
+  }
+  out[s] = v;
+}
+
+// x += dx over len scalars (caller order, the Euler-Maruyama update).
+template <typename T> __global__ void k_advance(T *__restrict__ x, const T *__restrict__ dx, int len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) x[i] += dx[i];
+}
+
 // out[perm[s]] = cr * yr[s] + dt * ur[s] + wv[s]   (null terms omitted;
 // sorted inputs are (x, y, z, 0), the output is caller-order n x 3)
 template <typename T>
@@ -1508,19 +1591,20 @@ void launch_nbr(pse_ctx *c) {
   ProfScope ps(c, PSE_STAGE_NBR);
   const T inv_mu0 = (T)(1.0 / c->d.mu0), fself = (T)(c->d.self_r / c->d.mu0), a = (T)c->p.a,
           inv_rc = (T)(1.0 / c->p.rcut);
+  const bool rep = c->rep_k > 0;
   auto go = [&](auto kern, auto fg) {
     kern<<<nblk(n, 128), 128, 0, c->stream>>>((const T4 *)c->pos_s, c->cell_start, n, c->d.nc, L, invL, inv_cs, rc2,
                                               c->nbr, c->nbr_cnt, c->nbr_cap, c->flags, fg, inv_mu0, fself, a, inv_rc,
-                                              c->pc_feat);
+                                              c->pc_feat, (T)c->rep_k, (T4 *)c->vbuf[kRepBuf]);
   };
   if constexpr (sizeof(T) == 8) {
     const FGExact fg{c->series, c->p.xi, c->p.a, c->d.mu0, c->small_r2};
-    if (c->pc_on) go(k_nbr_build<double, true, FGExact>, fg);
-    else go(k_nbr_build<double, false, FGExact>, fg);
+    if (c->pc_on) rep ? go(k_nbr_build<double, true, FGExact, true>, fg) : go(k_nbr_build<double, true, FGExact>, fg);
+    else rep ? go(k_nbr_build<double, false, FGExact, true>, fg) : go(k_nbr_build<double, false, FGExact>, fg);
   } else {
     const FGTable fg{c->table, (float)(kTableK / c->p.rcut)};
-    if (c->pc_on) go(k_nbr_build<float, true, FGTable>, fg);
-    else go(k_nbr_build<float, false, FGTable>, fg);
+    if (c->pc_on) rep ? go(k_nbr_build<float, true, FGTable, true>, fg) : go(k_nbr_build<float, true, FGTable>, fg);
+    else rep ? go(k_nbr_build<float, false, FGTable, true>, fg) : go(k_nbr_build<float, false, FGTable>, fg);
   }
 }
 
@@ -1529,11 +1613,23 @@ static int lds_nblocks(int nc, int B) {
   return nb * nb * nb;
 }
 
+// f(std::integral_constant<int, B>) for the block edge B = 1 ... 4.
+template <typename F> static void with_block_edge(int B, F f) {
+  switch (B) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    default: f(std::integral_constant<int, 1>{}); break;
+  }
+}
+
 void launch_halo_size(pse_ctx *c, int B) {
   ProfScope ps(c, PSE_STAGE_NBR);
   const int nblocks = lds_nblocks(c->d.nc, B);
-  if (B == 2) k_halo_size<2><<<nblk(nblocks, 256), 256, 0, c->stream>>>(c->cell_start, c->d.nc, c->flags);
-  else k_halo_size<1><<<nblk(nblocks, 256), 256, 0, c->stream>>>(c->cell_start, c->d.nc, c->flags);
+  with_block_edge(B, [&](auto b) {
+    constexpr int BE = decltype(b)::value;
+    k_halo_size<BE><<<nblk(nblocks, 256), 256, 0, c->stream>>>(c->cell_start, c->d.nc, c->flags);
+  });
 }
 
 // Dynamic LDS above 64 KB needs a per-kernel attribute.  It is set once per
@@ -1561,15 +1657,20 @@ void launch_nbr_lds(pse_ctx *c) {
   auto go = [&](auto kern) {
     allow_lds(kern, smem);
     kern<<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
-                                                  c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags);
+                                                  c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags,
+                                                  (float)(2.0 * c->p.a), (float)c->rep_k, (float4 *)c->vbuf[kRepBuf]);
   };
-  if (c->lds_B == 2) {
-    if (unwrap) go(k_nbr_lds<2, true>);
-    else go(k_nbr_lds<2, false>);
-  } else {
-    if (unwrap) go(k_nbr_lds<1, true>);
-    else go(k_nbr_lds<1, false>);
-  }
+  const bool rep = c->rep_k > 0;
+  with_block_edge(c->lds_B, [&](auto b) {
+    constexpr int BE = decltype(b)::value;
+    if (rep) {
+      if (unwrap) go(k_nbr_lds<BE, true, true>);
+      else go(k_nbr_lds<BE, false, true>);
+    } else {
+      if (unwrap) go(k_nbr_lds<BE, true>);
+      else go(k_nbr_lds<BE, false>);
+    }
+  });
 }
 
 // Preconditioner features on the LDS path, from the list and the staged halo.
@@ -1584,16 +1685,14 @@ void launch_feat_lds(pse_ctx *c) {
     allow_lds(kern, smem);
     kern<<<c->lds_blocks, kFeatNT, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc,
                                                      (float)c->d.cs, c->n, L, invL, (const uint16_t *)c->nbr, c->nbr_cnt,
-                                                  (const float4 *)c->table, (float)(kTableK / c->p.rcut), inv_mu0,
+                                                  (const float2 *)c->table, (float)(kTableK / c->p.rcut), inv_mu0,
                                                   fself, (float)c->p.a, near2, c->pc_feat);
   };
-  if (c->lds_B == 2) {
-    if (unwrap) go(k_feat_lds<2, true>);
-    else go(k_feat_lds<2, false>);
-  } else {
-    if (unwrap) go(k_feat_lds<1, true>);
-    else go(k_feat_lds<1, false>);
-  }
+  with_block_edge(c->lds_B, [&](auto b) {
+    constexpr int BE = decltype(b)::value;
+    if (unwrap) go(k_feat_lds<BE, true>);
+    else go(k_feat_lds<BE, false>);
+  });
 }
 
 template <typename A, bool LZ, bool PC = false>
@@ -1613,13 +1712,11 @@ static void spmv_lds(pse_ctx *c, const float4 *src, float4 *out, float4 *vm_out,
   };
   auto pick = [&](auto g) {
     constexpr int G = decltype(g)::value;
-    if (c->lds_B == 2) {
-      if (unwrap) go(k_spmv_lds<2, true, A, LZ, PC, G>);
-      else go(k_spmv_lds<2, false, A, LZ, PC, G>);
-    } else {
-      if (unwrap) go(k_spmv_lds<1, true, A, LZ, PC, G>);
-      else go(k_spmv_lds<1, false, A, LZ, PC, G>);
-    }
+    with_block_edge(c->lds_B, [&](auto b) {
+      constexpr int BE = decltype(b)::value;
+      if (unwrap) go(k_spmv_lds<BE, true, A, LZ, PC, G>);
+      else go(k_spmv_lds<BE, false, A, LZ, PC, G>);
+    });
   };
   // lanes per target: 3 built in (the best measured at phi = 0.3 with
   // r_c = 8a), 2 or 4 when pse_autotune found them faster
@@ -1753,7 +1850,7 @@ void launch_lz_iter(pse_ctx *c, int m, const void *z) {
   ProfScope ps(c, PSE_STAGE_LANCZOS);
   k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * n, vprev, w, n, st, (A *)c->partials);
   k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, st, (A)c->p.lanczos_tol,
-                                         c->p.lanczos_max_iter);
+                                         c->lz_maxit);
 }
 
 // Lanczos step on A = P M_r P^T: u = P^T r, t' = M_r u, then the basis
@@ -1787,7 +1884,7 @@ void launch_lz_iter_pc(pse_ctx *c, int m, const void *z) {
       k_lz_update_pc<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * c->n, vprev, w, (const T *)c->pc_P,
                                                              u, c->n, (LzState<A> *)c->lz, (A *)c->partials);
       k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, (LzState<A> *)c->lz,
-                                             (A)c->p.lanczos_tol, c->p.lanczos_max_iter);
+                                             (A)c->p.lanczos_tol, c->lz_maxit);
       return;
     }
   }
@@ -1802,7 +1899,7 @@ void launch_lz_iter_pc(pse_ctx *c, int m, const void *z) {
   k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * c->n, vprev, w, c->n, (LzState<A> *)c->lz,
                                                       (A *)c->partials);
   k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, (LzState<A> *)c->lz,
-                                         (A)c->p.lanczos_tol, c->p.lanczos_max_iter);
+                                         (A)c->p.lanczos_tol, c->lz_maxit);
 }
 
 template <typename T, typename A>
@@ -1817,6 +1914,17 @@ template <typename T>
 void launch_gather3(pse_ctx *c, const void *in, void *out) {
   ProfScope ps(c, PSE_STAGE_OTHER);
   k_gather3<T><<<nblk(c->n, 256), 256, 0, c->stream>>>((const T *)in, c->perm, (typename vec4<T>::type *)out, c->n);
+}
+
+template <typename T> void launch_gather3_add(pse_ctx *c, const void *in, const void *add, void *out) {
+  ProfScope ps(c, PSE_STAGE_OTHER);
+  using T4 = typename vec4<T>::type;
+  k_gather3_add<T><<<nblk(c->n, 256), 256, 0, c->stream>>>((const T *)in, c->perm, (const T4 *)add, (T4 *)out, c->n);
+}
+
+template <typename T> void launch_advance(pse_ctx *c, void *x, const void *dx) {
+  ProfScope ps(c, PSE_STAGE_OTHER);
+  k_advance<T><<<nblk(3 * (long)c->n, 256), 256, 0, c->stream>>>((T *)x, (const T *)dx, 3 * c->n);
 }
 
 template <typename T>
@@ -1838,6 +1946,8 @@ void launch_real_noise(pse_ctx *c, void *z_sorted, uint64_t seed, uint64_t sampl
   template void launch_bin<T>(pse_ctx *, const void *);                                            \
   template void launch_nbr<T>(pse_ctx *);                                                          \
   template void launch_gather3<T>(pse_ctx *, const void *, void *);                                \
+  template void launch_gather3_add<T>(pse_ctx *, const void *, const void *, void *);              \
+  template void launch_advance<T>(pse_ctx *, void *, const void *);                                \
   template void launch_finalize<T>(pse_ctx *, const void *, double, const void *, double, const void *, void *); \
   template void launch_real_noise<T>(pse_ctx *, void *, uint64_t, uint64_t);
 INST_T(float)

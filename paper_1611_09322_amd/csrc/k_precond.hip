@@ -210,10 +210,12 @@ __global__ void k_mlp_adam(float *__restrict__ wm, uint16_t *__restrict__ wb, co
 // ------------------------------------------------------------- the blocks
 // P_i = I + y_i (row-major), rows stored as (x, y, z, 0); P^{-1} likewise.
 // Fallback to I: not finite, |det| < 1e-6, or |P|_F |P^-1|_F > 1e3.
-// y == nullptr gives I everywhere (no weights: global fallback).
-template <typename T>
+// y == nullptr gives I everywhere (no weights: global fallback).  USER: y
+// holds the caller's blocks P_i themselves (n x 9, caller order), gathered
+// through perm into the sorted order.
+template <typename T, bool USER = false>
 __global__ void k_pc_blocks(const float *__restrict__ y, int n, T *__restrict__ P, T *__restrict__ Pinv,
-                            int *__restrict__ flags) {
+                            int *__restrict__ flags, const int *__restrict__ perm = nullptr) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   int bad = 0;
   if (s < n) {
@@ -222,9 +224,10 @@ __global__ void k_pc_blocks(const float *__restrict__ y, int n, T *__restrict__ 
     if (y) {
       T a[9];
       bool fin = true;
+      const size_t row = USER ? (size_t)perm[s] : (size_t)s;
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        a[k] = (T)y[(size_t)s * kNOut + k] + ((k % 4 == 0) ? T(1) : T(0));
+        a[k] = USER ? (T)y[row * kNOut + k] : (T)y[row * kNOut + k] + ((k % 4 == 0) ? T(1) : T(0));
         fin = fin && isfinite(a[k]);
       }
       T det = T(0), nf = T(0), ni = T(0);
@@ -472,6 +475,12 @@ void launch_mlp_adam(float *wm, uint16_t *wb, const float *g, float *m, float *v
 template <typename T> void launch_pc_blocks(pse_ctx *c) {
   ProfScope ps(c, PSE_STAGE_PRECOND);
   const int n = c->n;
+  if (c->pc_fixed) {
+    // the caller's blocks, in the current sorted order
+    k_pc_blocks<T, true><<<nblk(n, 256), 256, 0, c->stream>>>(c->pc_user, n, (T *)c->pc_P, (T *)c->pc_Pinv,
+                                                             c->flags, c->perm);
+    return;
+  }
   if (c->pc_have_w) launch_mlp_fwd(c->pc_w, c->pc_feat, n, c->pc_y, nullptr, c->stream);
   k_pc_blocks<T><<<nblk(n, 256), 256, 0, c->stream>>>(c->pc_have_w ? c->pc_y : nullptr, n, (T *)c->pc_P,
                                                        (T *)c->pc_Pinv, c->flags);

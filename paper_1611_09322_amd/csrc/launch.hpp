@@ -29,9 +29,22 @@ template <typename T, typename A> void launch_lz_init(pse_ctx *c, const void *z)
 template <typename T, typename A> void launch_lz_iter(pse_ctx *c, int m, const void *z);
 template <typename T, typename A> void launch_lz_combine(pse_ctx *c, void *y);
 template <typename T> void launch_gather3(pse_ctx *c, const void *in, void *out);
+// out (sorted) = gather(in, caller order; may be null) + add (sorted; may be null)
+template <typename T> void launch_gather3_add(pse_ctx *c, const void *in, const void *add, void *out);
+// x += dx over 3n scalars (caller order)
+template <typename T> void launch_advance(pse_ctx *c, void *x, const void *dx);
 template <typename T>
 void launch_finalize(pse_ctx *c, const void *yr, double cr, const void *ur, double dt, const void *wv, void *out);
 template <typename T> void launch_real_noise(pse_ctx *c, void *z, uint64_t seed, uint64_t sample);
+
+// full-mobility Krylov sample (k_full.hip); alpha, beta live in device memory
+template <typename T, typename A> void launch_fl_norm(pse_ctx *c, const void *v, void *dst);
+template <typename T, typename A> void launch_fl_alpha(pse_ctx *c, void *t, const void *u, const void *v, void *dst);
+template <typename T, typename A>
+void launch_fl_update(pse_ctx *c, const void *t, const void *vm, const void *vprev, void *w, const void *alpha,
+                      const void *beta, void *beta_next);
+template <typename T, typename A> void launch_fl_scale(pse_ctx *c, const void *src, const void *beta, void *dst);
+template <typename T, typename A> void launch_fl_combine(pse_ctx *c, int m, void *y);
 
 // learned block preconditioner (k_precond.hip)
 void launch_mlp_fwd(const uint16_t *w, const uint16_t *x, int n, float *y, uint16_t *cache, hipStream_t stream);

@@ -12,12 +12,22 @@
 namespace pse {
 
 constexpr int kMaxIter = 64;     // Lanczos basis capacity
-constexpr int kTableK = 1024;    // F/G table intervals on [0, rcut]
+constexpr int kFullMaxIter = 256;  // basis capacity of the full-mobility Krylov sample
+constexpr int kTableK = 2048;    // F/G table intervals on [0, rcut]
+constexpr int kTableN = kTableK + 2;  // table nodes (float2 (mu0 F, mu0 (G - F)) at r = k rcut / kTableK)
 constexpr int kSeriesTerms = 16; // small-r series terms of the wave complement
-constexpr int kRedBlock = 1024;  // workgroups (partial sums) of the vector reductions
+constexpr uint32_t kKnownFlags = PSE_FLAG_NOISE_KSPACE | PSE_FLAG_FULL_LANCZOS;
+constexpr int kRedBlock = 1024;
+constexpr int kRepBuf = 10;      // work vector holding the overlap repulsion of the Brownian step  // workgroups (partial sums) of the vector reductions
 constexpr size_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit
 // largest dynamic + table LDS of one workgroup of the staged near-field kernels
 constexpr size_t kLdsBudget = 150 * 1024;
+// static LDS of the staged near-field product beside its F/G table: the
+// halo table of block edge B (cell starts and prefix sums of the (B+2)^3 halo
+// cells and the B^3 target cells) plus reduction slots
+constexpr size_t lds_static_extra(int B) {
+  return 4 * (2 * (size_t)(B + 2) * (B + 2) * (B + 2) + 2 * (size_t)B * B * B + 3) + 256;
+}
 // Learned preconditioner: 24 features, MLP 24 -> 64 -> 64 -> 9.  Weights are
 // one bf16 array: W1 [64][32] (inputs 24..31 zero), b1 [64], W2 [64][64],
 // b2 [64], W3 [16][64] (rows 9..15 zero), b3 [16] (entries 9..15 zero).
@@ -107,6 +117,7 @@ struct WaveCoef {
 // ---------------------------------------------------------------- host side
 struct Derived {
   double L, h, sigma, gm, eta_se, eps_real, eps_wave, eps_quad, eps_alias;
+  double eps_real_tail, eps_real_coherent;  // shell-integral real-space estimates
   double mu0;      // 1 / (6 pi eta a)
   double self_r;   // F_self * mu0
   double cs;       // cell side
@@ -119,19 +130,23 @@ double fg_self(double xi, double a);
 void fg_series_coeffs(double xi, double a, double *serF, double *serG);
 double fg_small_r_threshold(double xi, double a);
 void fg_build_table(double xi, double a, double rc, double mu0, const double *serF, const double *serG,
-                    float4 *tab);
+                    float2 *tab);
 // error model and parameter choice (params_host.cpp)
 pse_status derive_params(const pse_params &p, Derived *d);
 double eps_wave_bound(double kc, double xi, double a);
+void real_tail(double rc, double xi, double a, double rho, double *inc, double *coh);
 double eps_quad_bound(int P, double m);
 double kcut_for(double tol, double xi, double a);
-double alias_estimate(double L, int M, double xi, double a, double sigma);
+// (sums on blocks of indices above max_freq frequencies per axis)
+double alias_estimate(double L, int M, double xi, double a, double sigma, int max_freq = 96);
 pse_status choose_params(const pse_params &base, const pse_tuning &t, pse_params *out, pse_tuning_info *info);
 // learned-preconditioner training targets (precond_host.cpp); false if a
 // patch matrix is not positive definite
 bool precond_targets(const double *x, int n, double L, double a, double xi, double rc, double mu0,
                      const double *serF, const double *serG, const int *idx, int m, double radius, double *out);
 bool fft_size_supported(int M);
+// s = T^{1/2} e_1 of an m x m symmetric tridiagonal (lanczos_host.cpp)
+bool tridiag_sqrt_e1_host(int m, const double *d, const double *e, double *s);
 
 }  // namespace pse
 
@@ -145,6 +160,12 @@ struct pse_ctx {
   int ncell = 0;
   bool have_pos = false;
   int last_iters = 4;
+  int lz_maxit = 0;         // near-field Lanczos iterations at most: min(lanczos_max_iter, kMaxIter)
+  // full-mobility Krylov sample (PSE_FLAG_FULL_LANCZOS)
+  void *fl_V = nullptr;     // T4 [(kFullMaxIter + 1) n] basis
+  void *fl_ab = nullptr;    // A [2 kFullMaxIter + 2]: alpha_m, then beta_m
+  void *fl_ab_h = nullptr;  // pinned copy
+  void *fl_coef = nullptr;  // A [kFullMaxIter]: combination coefficients
   int lz_launched = 0;      // Lanczos iterations launched in the current sample
   // device buffers
   void *pos_w = nullptr;    // T4 [n], caller order, wrapped
@@ -159,19 +180,20 @@ struct pse_ctx {
   int *flags = nullptr;     // [0] nonfinite, [1] list slots needed, [2..3] pairs, [4] max halo,
                             // [5] max neighbours, [6] preconditioner fallbacks
   int *flags_h = nullptr;   // pinned copy
-  void *vbuf[10] = {};      // T4 [n] work vectors (sorted order, (x, y, z, 0))
+  void *vbuf[11] = {};      // T4 [n] work vectors (sorted order, (x, y, z, 0)); [kRepBuf]: overlap repulsion
+  double rep_k = 0.0;       // > 0: the neighbour build also accumulates the overlap repulsion (Brownian step)
   void *V = nullptr;        // T4 [(kMaxIter+1) n] Lanczos basis
   void *lz = nullptr;       // LzState<A>
   void *lz_h = nullptr;     // pinned copy
   void *partials = nullptr; // A [max blocks]
   unsigned *counter = nullptr;
-  float4 *table = nullptr;  // F/G table (FP32 modes)
+  float2 *table = nullptr;  // F/G table nodes (FP32 modes)
   double *series = nullptr; // [2*kSeriesTerms] series coefficients (device)
   double series_h[2 * pse::kSeriesTerms];
   double small_r2 = 0;      // r^2 below which the series is used
   void *grid = nullptr;     // T [3 M^3]: planar half spectrum [c][jx][jy][jz < M/2] (complex)
   void *rgrid = nullptr;    // T4 [M^3]: interleaved real grid, nodes [x][y][z] of (c0, c1, c2, 0)
-  void *grid2 = nullptr;    // T [3 M^3] (grid-noise path, lazily)
+  void *grid2 = nullptr;    // T [3 M^3]: spectrum of caller grid noise W (absent with PSE_FLAG_NOISE_KSPACE)
   void *tw_M = nullptr;     // T2 [M] twiddles exp(-2 pi i k / M)
   void *tw_H = nullptr;     // T2 [M/2]
   // GPU-time accounting (pse_profile)
@@ -191,6 +213,7 @@ struct pse_ctx {
   // lanes per target of the LDS near-field product (2, 3 or 4; 0: 3)
   int tune_spmv_lanes = 0;
   int lds_B = 0;
+  int lds_B_pref = 0;  // block edge of the last configuration (the search starts there)
   int hcap = 0;
   int lds_blocks = 0;
   // learned block preconditioner (params.precond == 1); pc_suspend is set
@@ -198,6 +221,8 @@ struct pse_ctx {
   bool pc_suspend = false;
   bool pc_on = false;
   bool pc_have_w = false;
+  bool pc_fixed = false;       // the caller's blocks (pse_precond_set_blocks) in place of the network's
+  float *pc_user = nullptr;    // [n][9] the caller's blocks, caller order
   uint16_t *pc_w = nullptr;    // bf16 [kWTotal]
   uint16_t *pc_feat = nullptr; // bf16 [n][24], sorted order
   float *pc_y = nullptr;       // [n][9] network output, sorted order

@@ -14,17 +14,17 @@ def se_quadrature_bound(P):
     return float(np.exp(-np.pi**2 * P**2 / (2 * m * m)) + erfc(m / np.sqrt(2.0)))
 
 
-def se_aliasing_estimate(L, M, xi, P, a=1.0):
+def se_aliasing_estimate(L, M, xi, P, a=1.0, m=None):
     """Relative error of a spectral-Ewald wave sample from aliasing: the
     interpolation with the Gaussian window g (std sigma = P h / 2m,
-    m = sqrt(pi P)) sees each grid mode k also at k + 2 pi n / h, with
+    m = sqrt(pi P) unless given) sees each grid mode k also at k + 2 pi n / h, with
     amplitude ratio ghat(k + 2 pi n / h) / ghat(k).  Weighted by B(k) over the
     k-set, with the first alias shell (n in {-1, 0, 1}^3, n != 0):
         err^2 ~ sum_k B(k) sum_n (ghat(k + 2 pi n/h) / ghat(k))^2 / sum_k B(k).
     At h = 0.94a (256^3 in a 240.8a box) the modes near the Nyquist frequency
     still carry weight and this is ~5e-4; at h = 0.54a it is ~3e-5."""
     h = L / M
-    s = P * h / (2.0 * np.sqrt(np.pi * P))
+    s = P * h / (2.0 * (np.sqrt(np.pi * P) if not m else m))
     j = np.fft.fftfreq(M, 1.0 / M)
     k1 = 2 * np.pi * j / L
     ok1 = np.abs(j) < M // 2

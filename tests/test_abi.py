@@ -47,7 +47,7 @@ def _params(**kw):
 
 @pytest.mark.parametrize("bad,code", [
     (dict(rcut=10.0), -4),          # rcut must be < L/2 (minimum image)
-    (dict(grid=24), -4),            # unsupported FFT size
+    (dict(grid=40), -4),            # unsupported FFT size (5 x 2^3)
     (dict(support=7), -4),          # odd support
     (dict(grid=16, support=8, xi=2.0), -4),  # eta_SE = 4 xi^2 sigma^2 >= 1
     (dict(lanczos_max_iter=100), -4),

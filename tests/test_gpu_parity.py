@@ -16,7 +16,7 @@ from oracle import ewald, lanczos, philox, rpy, sampler
 pytestmark = pytest.mark.gpu
 
 
-from parity import check
+from parity import FP32_NEAR_BAR, FP32_NEAR_BAR_DENSE, check
 
 
 def to_dev(x, dtype):
@@ -48,10 +48,9 @@ def make(gpu_lib, n, L, precision, grid=M0, tol=1e-6, xi=XI, rc=RC, support=P, m
                            max_iter=max_iter, precision=precision)
 
 
-# FP32 bar: linear interpolation in a 1024-interval table of F, G on [0, rc]
-# errs by at most max|F''| dr^2 / 8 ~ 0.4 (8/1024)^2 / 8 ~ 3e-6, plus FP32
-# rounding; 1e-5 leaves margin and stays far below the 1e-4 sample tolerance.
-@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("fp32", 1e-5), ("mixed", 1e-5)])
+# FP32 bar: linear interpolation between the 2050 nodes of the F, G table on
+# [0, rc] (see parity.FP32_NEAR_BAR).
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("fp32", FP32_NEAR_BAR), ("mixed", FP32_NEAR_BAR)])
 def test_real_matvec_matches_dense_oracle(gpu_lib, cfg0, precision, bar):
     x, L, Mr = cfg0
     s = make(gpu_lib, len(x), L, precision)
@@ -136,8 +135,38 @@ def test_grid_noise_sample_equals_parts(gpu_lib, cfg0):
     check(host(d), ref, 1e-4, "sample/grid-noise fp64")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_kspace_noise_sample_matches_direct_fourier_sum(gpu_lib, cfg0, precision):
+    """Caller-supplied zeta on the stored half spectrum (PSE_FLAG_NOISE_KSPACE):
+    the wave sample against the direct Fourier sum with the full field the
+    half spectrum stands for (canonical pairs on jz = 0, Nyquist and k = 0
+    dropped); then zeta = DFT(W)/M^{3/2} gives the grid-noise sample."""
+    import torch
+
+    x, L, _ = cfg0
+    H = M0 // 2
+    rng = np.random.default_rng(14)
+    zh = (rng.standard_normal((3, M0, M0, H)) + 1j * rng.standard_normal((3, M0, M0, H))) / np.sqrt(2.0)
+    ctype = torch.complex128 if precision == "fp64" else torch.complex64
+    s = gpu_lib.Sampler(len(x), L, xi=XI, rcut=RC, grid=M0, support=P, tol=1e-6, precision=precision,
+                        flags=gpu_lib.FLAG_NOISE_KSPACE)
+    s.set_positions(to_dev(x, s.dtype))
+    y = host(s.wave_sample(torch.as_tensor(zh, dtype=ctype, device="cuda")))
+    ref = ewald.wave_sample_direct(x, philox.half_spectrum_to_full(zh), L, 1.0, 1.0, XI)
+    check(y, ref, 1e-4, f"k-space noise wave sample {precision}")
+    # the same sample through the grid-noise path
+    W = synth.normals(15, (3, M0, M0, M0))
+    zW = (np.fft.fftn(W, axes=(1, 2, 3)) / M0**1.5)[..., :H]
+    yk = host(s.wave_sample(torch.as_tensor(zW, dtype=ctype, device="cuda")))
+    g = make(gpu_lib, len(x), L, precision)
+    g.set_positions(to_dev(x, g.dtype))
+    yw = host(g.wave_sample(to_dev(W, g.dtype)))
+    check(yk, yw, 1e-12 if precision == "fp64" else 1e-5, f"k-space vs grid noise {precision}")
+
+
 # ------------------------------------------------------------- edge cases
-@pytest.mark.parametrize("precision,bar_r", [("fp64", 1e-12), ("fp32", 1e-5), ("mixed", 1e-5)])
+@pytest.mark.parametrize("precision,bar_r", [("fp64", 1e-12), ("fp32", FP32_NEAR_BAR_DENSE),
+                                             ("mixed", FP32_NEAR_BAR_DENSE)])
 def test_ragged_overlapping_unwrapped_positions(gpu_lib, precision, bar_r):
     """N = 1001 (ragged against every block size), uniform positions with
     overlaps and one coincident pair, coordinates outside [0, L) and exactly

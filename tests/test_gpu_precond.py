@@ -277,3 +277,47 @@ def test_global_fallback_when_the_preconditioned_sample_fails(gpu_lib):
     assert torch.equal(out, ref)
     plain.close()
     pc.close()
+
+
+def test_caller_blocks_reproduce_and_persist(gpu_lib, dense):
+    """pse_precond_set_blocks: the network's own blocks fed back give the
+    same sample bit for bit (FP32 storage: the same P and P^-1 arithmetic);
+    the blocks follow their particles through a new configuration; an FP64
+    context with the same blocks reproduces the oracle's preconditioned root
+    P^-1 (P M_r P^T)^1/2 z; None returns to the network's blocks."""
+    import torch
+
+    x, L, Mr = dense
+    bits, _ = weights(11, 0.06)
+    s = sampler(gpu_lib, x, L, "mixed", tol=1e-6)
+    s.set_precond_weights(bits)
+    P, nf = s.precond_blocks()
+    z = torch.as_tensor(synth.normals(15, (len(x), 3)), dtype=torch.float32, device="cuda")
+    y0, _ = s.real_sample(z)
+    y0 = y0.clone()
+    s.set_precond_blocks(P)
+    P1, nf1 = s.precond_blocks()
+    assert nf1 == nf and torch.equal(P1, P)
+    y1, _ = s.real_sample(z)
+    assert torch.equal(y1, y0)
+    # a new configuration (particles moved, order shuffled by the re-sort):
+    # each particle keeps its own block
+    xm = x + 0.05 * synth.normals(16, x.shape)
+    s.set_positions(torch.as_tensor(xm, dtype=torch.float32, device="cuda"))
+    P2, _ = s.precond_blocks()
+    assert torch.equal(P2, P)
+    # back to the network: the blocks of the new configuration differ
+    s.set_precond_blocks(None)
+    P3, _ = s.precond_blocks()
+    assert not torch.equal(P3, P)
+    s.close()
+    # FP64 with the same blocks against the oracle
+    r = sampler(gpu_lib, x, L, "fp64", tol=1e-10)
+    r.set_precond_blocks(P)
+    zd = z.double()
+    yr, st = r.real_sample(zd)
+    Pg = host(P)
+    ref = opc.precond_real_sample(Mr, Pg, host(zd).ravel())
+    check(host(yr), ref, 1e-8, "FP64 sample with the caller's blocks vs oracle")
+    check(host(y0), ref, 1e-5, "mixed sample (network blocks, tol 1e-6) vs oracle")
+    r.close()

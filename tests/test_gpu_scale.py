@@ -25,7 +25,7 @@ pytestmark = pytest.mark.gpu
 N, PHI, M, XI, RC = 1_000_000, 0.3, 256, 0.5, 8.0
 
 
-from parity import FP32_NEAR_BAR, check, rel
+from parity import FP32_NEAR_BAR_DENSE, check, rel
 
 NROWS = 2000
 
@@ -60,7 +60,7 @@ def test_near_field_rows_at_full_size(gpu_lib, big):
         s = make(gpu_lib, L, precision)
         s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
         w = host(s.real_matvec(torch.as_tensor(v, dtype=torch.float32, device="cuda")))
-        check(w[rows], ref, FP32_NEAR_BAR, f"[scale] M_r v, {NROWS} rows ({precision})")
+        check(w[rows], ref, FP32_NEAR_BAR_DENSE, f"[scale] M_r v, {NROWS} rows ({precision})")
         s.close()
 
 
@@ -128,7 +128,7 @@ def test_scale_configuration_rows(gpu_lib):
     s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
     v = synth.normals(41, (n4, 3))
     w = host(s.real_matvec(torch.as_tensor(v, dtype=torch.float32, device="cuda")))[rows]
-    check(w, rpy.real_matvec_rows(x, v, rows, L, 1.0, 1.0, XI, RC), FP32_NEAR_BAR, "[scale 4M] M_r v, 256 rows")
+    check(w, rpy.real_matvec_rows(x, v, rows, L, 1.0, 1.0, XI, RC), FP32_NEAR_BAR_DENSE, "[scale 4M] M_r v, 256 rows")
     del v
     W = np.random.default_rng(42).standard_normal((3, m4, m4, m4), dtype=np.float32)
     y = host(s.wave_sample(torch.as_tensor(W, device="cuda")))[rows]
