@@ -568,6 +568,76 @@ def ptps_sweep(pse, torch, args):
 
 
 # ------------------------------------------------------------ CPU baseline
+def gel_experiment(pse, torch, args):
+    """The learned preconditioner's own workload and Sec. III's gel
+    comparison (Fig. gel): a colloidal gel of args.gel_n spheres built by
+    diffusion-limited cluster aggregation at volume fraction 0.05, against a
+    hard-sphere suspension of the same N and volume fraction, at the
+    parameters the error model chooses for the tolerance on grids up to
+    256^3.  On the gel: plain FP32, mixed, and mixed with blocks from a
+    network trained on args.gel_train_configs small generated gels; Lanczos
+    iterations, samples per second and the real-space / wave-space split."""
+    import numpy as np
+
+    import synth
+    from paper_1611_09322_amd import precond as ppc
+
+    t0 = time.time()
+    n, phi = args.gel_n, 0.05
+    xg, L, _, gst = synth.dlca_gel(n, phi, seed=5000)
+    slope = synth.mass_radius_slope(xg, L, 2.5, 6.0)
+    log(f"gel: {n} spheres, L={L:.1f}a, {gst}, mass-radius slope {slope:.2f} on [2.5a, 6a], "
+        f"{time.time() - t0:.1f}s")
+    xh, _ = synth.hard_spheres(n, phi, seed=5001, sweeps=20)
+    F = synth.normals(5002, (n, 3))
+    p, info = pse.pse_choose_params(pse.make_params(n, L, precision="fp32"),
+                                    pse.Tuning(tol=args.tol, with_forces=1, max_grid=256))
+    p.lanczos_max_iter = 64
+    # network trained on small gels at the same parameters (untimed)
+    t1 = time.time()
+    tr = ppc.Trainer(torch, seed=5, lr=3e-3)
+    for k in range(args.gel_train_configs):
+        xs, Ls, _, _ = synth.dlca_gel(args.gel_train_n, phi, seed=6000 + k)
+        s = pse.Sampler(len(xs), Ls, xi=p.xi, rcut=min(p.rcut, 0.49 * Ls), grid=64, support=8, tol=args.tol,
+                        max_iter=64, precision="mixed", precond=1)
+        s.set_positions(torch.as_tensor(xs, dtype=torch.float32, device="cuda"))
+        idx = np.random.default_rng(k).choice(len(xs), args.gel_train_rows, replace=False).astype(np.int32)
+        tr.add(s, xs, idx)
+        s.close()
+    hist = tr.fit(args.train_epochs)
+    weights = tr.weights_bits()
+    log(f"gel preconditioner: {args.gel_train_configs} gels x {args.gel_train_rows} rows, loss {hist[0]:.3e} -> "
+        f"{hist[-1]:.3e}, {time.time() - t1:.1f}s")
+
+    def split(r):
+        b = r["breakdown_ms"]
+        return {"real_ms": round(sum(b[k] for k in ("nbr", "spmv", "lanczos", "noise")), 4),
+                "wave_ms": round(sum(b[k] for k in ("spread", "fft", "xfused", "interp")), 4)}
+
+    out = {"n": n, "phi": phi, "L": round(L, 3), "generator": "DLCA from an RSA start, step 0.5a, "
+           "acceptance s^-0.5, until one cluster holds 90 % of the spheres", "aggregation": gst,
+           "mass_radius_slope_2p5a_6a": slope, "params": params_summary(p), "model_ms": info.model_seconds * 1e3,
+           "training": {"configs": args.gel_train_configs, "n": args.gel_train_n, "rows": args.gel_train_rows,
+                        "epochs": args.train_epochs, "loss_first": hist[0], "loss_last": hist[-1]},
+           "gel": {}, "hard_spheres": {}}
+    for v in ("fp32", "mixed", "mixed+precond"):
+        q = variant_params(pse, p, v)
+        r = run_variant(pse, torch, xg, F, args, f"gel {v}", q, weights if q.precond else None)
+        out["gel"][v] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "lanczos_iters_mean":
+                         r["lanczos_iters_mean"], "neighbor_pairs": r["neighbor_pairs"],
+                         "precond_fallbacks": r["precond_fallbacks"], **split(r)}
+        log(f"gel {v}: {json.dumps(out['gel'][v])}")
+    r = run_variant(pse, torch, xh, F, args, "hard spheres fp32", variant_params(pse, p, "fp32"))
+    out["hard_spheres"]["fp32"] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                                   "lanczos_iters_mean": r["lanczos_iters_mean"],
+                                   "neighbor_pairs": r["neighbor_pairs"], **split(r)}
+    log(f"hard spheres fp32: {json.dumps(out['hard_spheres']['fp32'])}")
+    g = out["gel"]
+    out["precond_gain"] = {"iterations": g["mixed"]["lanczos_iters_mean"] - g["mixed+precond"]["lanczos_iters_mean"],
+                           "speed_ratio_over_mixed": g["mixed+precond"]["value"] / g["mixed"]["value"]}
+    return out
+
+
 def cpu_baseline(args):
     """The FP64 oracle (dense M_r + eigendecomposition root + direct Fourier
     sums), timed on a bounded sample of the same workload: an independent
@@ -645,6 +715,11 @@ def main():
     ap.add_argument("--full-lanczos-max-n", type=int, default=128_000,
                     help="largest N of the sweep at which the full-mobility Lanczos comparator also runs")
     ap.add_argument("--no-tolerance", action="store_true", help="skip the tolerance experiment (Fig. parity)")
+    ap.add_argument("--no-gel", action="store_true", help="skip the gel workload (Fig. gel, learned preconditioner)")
+    ap.add_argument("--gel-n", type=int, default=500_000)
+    ap.add_argument("--gel-train-configs", type=int, default=200)
+    ap.add_argument("--gel-train-n", type=int, default=2000)
+    ap.add_argument("--gel-train-rows", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -731,6 +806,7 @@ def main():
         log(f"batch: {json.dumps(batched)}")
     tolx = None if args.no_tolerance else tolerance_experiment(pse, torch, args)
     ptps = None if args.no_ptps else ptps_sweep(pse, torch, args)
+    gel = None if args.no_gel else gel_experiment(pse, torch, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     w = head.split("@")[1]
     comparison = None
@@ -772,6 +848,7 @@ def main():
         "batched": batched,
         "tolerance_experiment": tolx,
         "ptps": ptps,
+        "gel": gel,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

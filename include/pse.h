@@ -410,7 +410,10 @@ size_t pse_mlp_backward_workspace(int32_t n);
 
 /* dw (device, PSE_MLP_NPARAM fp32) = gradient of sum_rows <dy, y> with
  * respect to every weight, from the forward pass's x and act_cache; padding
- * entries get 0.  Deterministic (fixed summation order). */
+ * entries get 0.  The products run on the matrix cores (bf16 MFMA) with
+ * the fp32 factors dy and the back-propagated errors split into three bf16
+ * parts each, so the gradient has fp32 accuracy.  Deterministic (fixed
+ * summation order). */
 pse_status pse_mlp_backward(const void *weights_dev, const void *x_dev, const void *act_cache_dev, const void *dy_dev,
                             int32_t n, void *dw_dev, void *workspace_dev, size_t workspace_bytes, void *stream);
 
@@ -429,6 +432,16 @@ pse_status pse_mlp_backward(const void *weights_dev, const void *x_dev, const vo
  * Errors: INVALID_ARG (null pointer, n < 1), HIP. */
 pse_status pse_mlp_backward_noalloc(const void *weights_dev, const void *x_dev, const void *act_cache_dev,
                                     const void *dy_dev, int32_t n, void *dw_dev, void *stream);
+
+/* Squared-error training loss of the block network and its gradient with
+ * respect to the outputs: y_dev, target_dev n x 9 fp32 (device), dy_dev
+ * (n x 9, device) = (2/n)(y - target), loss_dev (one fp32 on the device,
+ * may be NULL) = sum over rows of |y_p - target_p|^2 / n.  Deterministic
+ * (one workgroup, fixed order); no host synchronisation, so a training loop
+ * (forward, loss, backward, Adam) stays on the device.
+ * Errors: INVALID_ARG (null pointer, n < 1), HIP. */
+pse_status pse_mlp_loss_grad(const void *y_dev, const void *target_dev, int32_t n, void *dy_dev, void *loss_dev,
+                             void *stream);
 
 /* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8, step
  * t >= 1) on the fp32 master weights, with the bf16 copy rewritten. */

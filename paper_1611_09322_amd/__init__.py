@@ -152,6 +152,7 @@ _SIGS = {
     "pse_mlp_backward": ([_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "pse_mlp_backward_noalloc": ([_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP], ctypes.c_int),
     "pse_mlp_adam": ([_VP, _VP, _VP, _VP, _VP, ctypes.c_float, ctypes.c_int32, _VP], ctypes.c_int),
+    "pse_mlp_loss_grad": ([_VP, _VP, ctypes.c_int32, _VP, _VP, _VP], ctypes.c_int),
     "pse_batch_create": ([ctypes.POINTER(Params), ctypes.c_int32, _VP, ctypes.POINTER(_VP)], ctypes.c_int),
     "pse_batch_destroy": ([_VP], ctypes.c_int),
     "pse_batch_replica": ([_VP, ctypes.c_int32, ctypes.POINTER(_VP)], ctypes.c_int),
@@ -367,6 +368,11 @@ def pse_mlp_backward(w_ptr, x_ptr, cache_ptr, dy_ptr, n, dw_ptr, work_ptr, work_
 def pse_mlp_backward_noalloc(w_ptr, x_ptr, cache_ptr, dy_ptr, n, dw_ptr, stream=None):
     return _check(load().pse_mlp_backward_noalloc(w_ptr, x_ptr, cache_ptr, dy_ptr, n, dw_ptr, _VP(stream or 0)),
                   "pse_mlp_backward_noalloc")
+
+
+def pse_mlp_loss_grad(y_ptr, t_ptr, n, dy_ptr, loss_ptr=None, stream=None):
+    return _check(load().pse_mlp_loss_grad(y_ptr, t_ptr, n, dy_ptr, loss_ptr, _VP(stream or 0)),
+                  "pse_mlp_loss_grad")
 
 
 def pse_mlp_adam(wm_ptr, wb_ptr, dw_ptr, m_ptr, v_ptr, lr, t, stream=None):

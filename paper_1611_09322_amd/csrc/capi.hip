@@ -1209,6 +1209,12 @@ pse_status pse_mlp_backward_noalloc(const void *w, const void *x, const void *ac
   return hip_status(hipGetLastError());
 }
 
+pse_status pse_mlp_loss_grad(const void *y, const void *target, int32_t n, void *dy, void *loss, void *stream) {
+  if (!y || !target || !dy || n < 1) return PSE_ERR_INVALID_ARG;
+  launch_mlp_loss((const float *)y, (const float *)target, n, (float *)dy, (float *)loss, (hipStream_t)stream);
+  return hip_status(hipGetLastError());
+}
+
 pse_status pse_mlp_adam(void *w_master, void *w_bf16, const void *dw, void *m, void *v, float lr, int32_t t,
                         void *stream) {
   if (!w_master || !w_bf16 || !dw || !m || !v || t < 1 || !(lr >= 0)) return PSE_ERR_INVALID_ARG;

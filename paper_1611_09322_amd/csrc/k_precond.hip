@@ -7,7 +7,8 @@
 // fp32 sums on the MFMA units) applied to geometry features of the
 // particle's near field (computed from the neighbour list).  Blocks
 // that are not finite, nearly singular or ill conditioned fall back to I.
-// Training kernels (backward pass, Adam) run off the sampling path.
+// Training kernels (the backward pass on the matrix cores, Adam) run off
+// the sampling path.
 #include <mutex>
 
 #include "launch.hpp"
@@ -107,71 +108,257 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const uint16_t *__restrict__ w,
 }
 
 // ----------------------------------------------------------- MLP backward
-// Gradients of sum_p <dy_p, y_p> for the same network (fp32, from the bf16
-// weights and the cached bf16 activations).  Lane j of a wavefront owns
-// hidden unit j: row j of dW2 and of dW1, column j of dW3.  Each wavefront
-// writes its sums to its own slot of `partial`; k_mlp_reduce adds the slots
-// in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_mlp_bwd(const uint16_t *__restrict__ w, const uint16_t *__restrict__ x,
-                                                 const uint16_t *__restrict__ cache, const float *__restrict__ dy,
-                                                 int n, float *__restrict__ partial) {
-  const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int nw = gridDim.x * (blockDim.x >> 6);
-  float w3c[kNOut], w2c[kNHid];
+// Gradients of sum_p <dy_p, y_p> for the same network, on the matrix cores.
+// A wavefront takes 32 rows at a time; every product of the chain rule is a
+// 16x16x32 bf16 MFMA tile product:
+//   dh2 = dy W3        (rows x 16 outputs) (16 x 64)
+//   gW3 += dy^T h2     (16 x rows) (rows x 64)
+//   dz2 = dh2 . [h2 > 0];  gW2 += dz2^T h1;  dh1 = dz2 W2
+//   dz1 = dh1 . [h1 > 0];  gW1 += dz1^T x
+// h1, h2, x and the weights are bf16 already (exact operands).  The fp32
+// factors dy, dz2, dz1 are split into three bf16 parts (hi + mid + lo,
+// each the rounded remainder of the previous: 24 significant bits, the
+// precision of fp32) and each product is the sum of the three part
+// products, accumulated in fp32: the gradient keeps fp32 accuracy.  Bias
+// gradients are column sums of dy, dz2, dz1 in fp32.  Each wavefront writes
+// its sums to its own slot of `partial`; k_mlp_reduce adds the slots in a
+// fixed order (deterministic).
+constexpr int kBwdRows = 32;
+constexpr int kBwdWaves = 2;  // wavefronts per workgroup
+
+struct BwdLds {
+  // per wavefront: the chunk's operands in the layouts the MFMA reads
+  uint16_t h1T[64][kBwdRows + 8];        // h1^T (k, p)
+  uint16_t h2T[64][kBwdRows + 8];        // h2^T
+  uint16_t xT[32][kBwdRows + 8];         // x^T (f, p), f >= 24 zero
+  uint16_t dy[3][kBwdRows][32 + 8];      // parts of dy (p, o), o >= 9 zero
+  uint16_t dyT[3][16][kBwdRows + 8];     // parts of dy^T (o, p)
+  uint16_t dz[3][kBwdRows][64 + 8];      // parts of dz2 (p, j)
+  uint16_t dzT[3][64][kBwdRows + 8];     // parts of dz2^T, then dz1^T (j, p)
+  float dyf[kBwdRows][16];               // dy in fp32 (bias sums)
+};
+
+__device__ __forceinline__ void split3(float v, uint16_t *h, uint16_t *m, uint16_t *l) {
+  const uint16_t a = f32_to_bf16(v);
+  const float r1 = v - bf16_to_f32(a);
+  const uint16_t b = f32_to_bf16(r1);
+  const float r2 = r1 - bf16_to_f32(b);
+  *h = a;
+  *m = b;
+  *l = f32_to_bf16(r2);
+}
+
+// Each wavefront owns its LDS buffers, so ordering its own writes before
+// its own reads needs no workgroup barrier (the wavefronts of a workgroup
+// run different numbers of chunks): a fence (the LDS accesses completed)
+// and a scheduling barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
+  // 8 consecutive bf16 (16 bytes; rows are padded to keep 16-byte alignment)
+  return as_bf16x8(*(const u32x4 *)p);
+}
+
+__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd(const uint16_t *__restrict__ w,
+                                                            const uint16_t *__restrict__ x,
+                                                            const uint16_t *__restrict__ cache,
+                                                            const float *__restrict__ dy, int n,
+                                                            float *__restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) uint16_t w3T[64][32 + 8];  // W3^T (k, o), o >= 16 zero
+  __shared__ __attribute__((aligned(16))) uint16_t w2s[64][64 + 8];  // W2 (j, k) as stored
+  __shared__ __attribute__((aligned(16))) BwdLds L[kBwdWaves];
+  for (int e = threadIdx.x; e < 64 * 32; e += blockDim.x) {
+    const int k = e >> 5, o = e & 31;
+    w3T[k][o] = o < 16 ? w[kW3 + o * 64 + k] : (uint16_t)0;
+  }
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) w2s[e >> 6][e & 63] = w[kW2 + e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int gw = blockIdx.x * kBwdWaves + wave, nw = gridDim.x * kBwdWaves;
+  BwdLds &S = L[wave];
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 gW3[4], gW2[4][4], gW1[4][2];
 #pragma unroll
-  for (int o = 0; o < kNOut; ++o) w3c[o] = bf16_to_f32(w[kW3 + o * 64 + lane]);
+  for (int a = 0; a < 4; ++a) {
+    gW3[a] = zero;
 #pragma unroll
-  for (int j = 0; j < kNHid; ++j) w2c[j] = bf16_to_f32(w[kW2 + j * 64 + lane]);  // W2[j][lane]
-  float gW2[kNHid], gW1[kNFeat], gW3[kNOut];
-#pragma unroll
-  for (int k = 0; k < kNHid; ++k) gW2[k] = 0.f;
-#pragma unroll
-  for (int f = 0; f < kNFeat; ++f) gW1[f] = 0.f;
-#pragma unroll
-  for (int o = 0; o < kNOut; ++o) gW3[o] = 0.f;
-  float gb1 = 0.f, gb2 = 0.f, gb3 = 0.f;
-  for (int p = gw; p < n; p += nw) {
-    const uint16_t *cp = cache + (size_t)p * 2 * kNHid;
-    const float h1 = bf16_to_f32(cp[lane]), h2 = bf16_to_f32(cp[kNHid + lane]);
-    float dyo[kNOut];
-#pragma unroll
-    for (int o = 0; o < kNOut; ++o) dyo[o] = dy[(size_t)p * kNOut + o];
-    float dh2 = 0.f;
-#pragma unroll
-    for (int o = 0; o < kNOut; ++o) {
-      dh2 += w3c[o] * dyo[o];
-      gW3[o] += dyo[o] * h2;
+    for (int b = 0; b < 4; ++b) gW2[a][b] = zero;
+    gW1[a][0] = gW1[a][1] = zero;
+  }
+  float gb1[4] = {0.f, 0.f, 0.f, 0.f}, gb2[4] = {0.f, 0.f, 0.f, 0.f}, gb3 = 0.f;
+  for (int p0 = gw * kBwdRows; p0 < n; p0 += nw * kBwdRows) {
+    // ---- stage the chunk (rows past n are zero)
+    for (int e = lane; e < kBwdRows * 128; e += 64) {
+      const int p = e >> 7, c = e & 127;
+      const uint16_t v = p0 + p < n ? cache[(size_t)(p0 + p) * 2 * kNHid + c] : (uint16_t)0;
+      if (c < 64) S.h1T[c][p] = v;
+      else S.h2T[c - 64][p] = v;
     }
-    if (lane < kNOut) {
-      float v = 0.f;
-#pragma unroll
-      for (int o = 0; o < kNOut; ++o) v = (o == lane) ? dyo[o] : v;
-      gb3 += v;
+    for (int e = lane; e < kBwdRows * 32; e += 64) {
+      const int p = e >> 5, f = e & 31;
+      S.xT[f][p] = (f < kNFeat && p0 + p < n) ? x[(size_t)(p0 + p) * kNFeat + f] : (uint16_t)0;
     }
-    const float dz2 = h2 > 0.f ? dh2 : 0.f;
-    gb2 += dz2;
-    float dh1 = 0.f;
-#pragma unroll
-    for (int k = 0; k < kNHid; ++k) {
-      gW2[k] += dz2 * __shfl(h1, k, 64);
-      dh1 += w2c[k] * __shfl(dz2, k, 64);
+    for (int e = lane; e < kBwdRows * 32; e += 64) {
+      const int p = e >> 5, o = e & 31;
+      const float v = (o < kNOut && p0 + p < n) ? dy[(size_t)(p0 + p) * kNOut + o] : 0.f;
+      uint16_t a, b, c;
+      split3(v, &a, &b, &c);
+      S.dy[0][p][o] = a;
+      S.dy[1][p][o] = b;
+      S.dy[2][p][o] = c;
+      if (o < 16) {
+        S.dyT[0][o][p] = a;
+        S.dyT[1][o][p] = b;
+        S.dyT[2][o][p] = c;
+        S.dyf[p][o] = v;
+      }
     }
-    const float dz1 = h1 > 0.f ? dh1 : 0.f;
-    gb1 += dz1;
-    const uint16_t *xp = x + (size_t)p * kNFeat;
+    wave_sync();
+    // ---- bias of the output layer: column sums of dy
+    if (lane < 16) {
+      float sacc = 0.f;
+#pragma unroll 8
+      for (int p = 0; p < kBwdRows; ++p) sacc += S.dyf[p][lane];
+      gb3 += sacc;
+    }
+    // ---- gW3 += dy^T h2: M = o (one tile), N = k (4 tiles), K = rows
 #pragma unroll
-    for (int f = 0; f < kNFeat; ++f) gW1[f] += dz1 * bf16_to_f32(xp[f]);
+    for (int nt = 0; nt < 4; ++nt) {
+      const bf16x8 b = ld8(&S.h2T[16 * nt + r16][8 * g]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        gW3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(&S.dyT[q][r16][8 * g]), b, gW3[nt], 0, 0, 0);
+    }
+    // ---- dh2 = dy W3: M = rows (2 tiles), N = k (4 tiles), K = o (32, zero past 16)
+    //      dz2 = dh2 . [h2 > 0], split and stored in both layouts
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const bf16x8 b = ld8(&w3T[16 * nt + r16][8 * g]);
+        f32x4 d = zero;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(&S.dy[q][16 * mt + r16][8 * g]), b, d, 0, 0, 0);
+        const int k = 16 * nt + r16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int p = 16 * mt + 4 * g + i;
+          const float v = bf16_to_f32(S.h2T[k][p]) > 0.f ? d[i] : 0.f;
+          gb2[nt] += v;
+          uint16_t a, bb, c;
+          split3(v, &a, &bb, &c);
+          S.dz[0][p][k] = a;
+          S.dz[1][p][k] = bb;
+          S.dz[2][p][k] = c;
+          S.dzT[0][k][p] = a;
+          S.dzT[1][k][p] = bb;
+          S.dzT[2][k][p] = c;
+        }
+      }
+    }
+    wave_sync();
+    // ---- gW2 += dz2^T h1: M = j (4 tiles), N = k (4 tiles), K = rows
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const bf16x8 b = ld8(&S.h1T[16 * nt + r16][8 * g]);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          gW2[mt][nt] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(&S.dzT[q][16 * mt + r16][8 * g]), b, gW2[mt][nt], 0, 0, 0);
+    }
+    // ---- dh1 = dz2 W2: M = rows (2 tiles), N = k (4 tiles), K = j (2 steps of 32)
+    f32x4 dh1[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4 d = zero;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          // B[j][k] = W2[j][k]: lane's column k, rows j = 32 ks + 8 g ... + 7
+          bf16x8 b;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) b[u] = __builtin_bit_cast(__bf16, w2s[32 * ks + 8 * g + u][16 * nt + r16]);
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(&S.dz[q][16 * mt + r16][32 * ks + 8 * g]), b, d, 0, 0, 0);
+        }
+        dh1[mt][nt] = d;
+      }
+    wave_sync();  // dz2^T is read above; dz1^T overwrites it below
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const int k = 16 * nt + r16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int p = 16 * mt + 4 * g + i;
+          const float v = bf16_to_f32(S.h1T[k][p]) > 0.f ? dh1[mt][nt][i] : 0.f;
+          gb1[nt] += v;
+          uint16_t a, bb, c;
+          split3(v, &a, &bb, &c);
+          S.dzT[0][k][p] = a;
+          S.dzT[1][k][p] = bb;
+          S.dzT[2][k][p] = c;
+        }
+      }
+    wave_sync();
+    // ---- gW1 += dz1^T x: M = j (4 tiles), N = f (2 tiles), K = rows
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const bf16x8 b = ld8(&S.xT[16 * nt + r16][8 * g]);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          gW1[mt][nt] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(&S.dzT[q][16 * mt + r16][8 * g]), b, gW1[mt][nt], 0, 0, 0);
+    }
+    wave_sync();  // the chunk's buffers are restaged next
+  }
+  // hidden-layer bias sums: the four lane groups hold partial sums of the
+  // same columns (k = 16 nt + r16)
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    gb1[nt] += __shfl_xor(gb1[nt], 16, 64);
+    gb1[nt] += __shfl_xor(gb1[nt], 32, 64);
+    gb2[nt] += __shfl_xor(gb2[nt], 16, 64);
+    gb2[nt] += __shfl_xor(gb2[nt], 32, 64);
   }
   float *out = partial + (size_t)gw * kWTotal;
+  // result layout: lane holds rows 4 g + i, column r16 of each 16x16 tile
 #pragma unroll
-  for (int f = 0; f < 32; ++f) out[kW1 + lane * 32 + f] = f < kNFeat ? gW1[f] : 0.f;
-  out[kB1 + lane] = gb1;
+  for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-  for (int k = 0; k < kNHid; ++k) out[kW2 + lane * 64 + k] = gW2[k];
-  out[kB2 + lane] = gb2;
+    for (int i = 0; i < 4; ++i) out[kW3 + (4 * g + i) * 64 + 16 * nt + r16] = gW3[nt][i];
 #pragma unroll
-  for (int o = 0; o < 16; ++o) out[kW3 + o * 64 + lane] = o < kNOut ? gW3[o] : 0.f;
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[kW2 + (16 * mt + 4 * g + i) * 64 + 16 * nt + r16] = gW2[mt][nt][i];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[kW1 + (16 * mt + 4 * g + i) * 32 + 16 * nt + r16] = gW1[mt][nt][i];
+  if (g == 0) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      out[kB1 + 16 * nt + r16] = gb1[nt];
+      out[kB2 + 16 * nt + r16] = gb2[nt];
+    }
+  }
   if (lane < 16) out[kB3 + lane] = lane < kNOut ? gb3 : 0.f;
 }
 
@@ -188,6 +375,23 @@ __global__ void k_mlp_reduce(const float *__restrict__ partial, int nparts, floa
   }
   for (; q < nparts; ++q) v[q & 7] += partial[(size_t)q * kWTotal + e];
   dw[e] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+}
+
+// Squared-error training loss of the block network: dy = (2/n)(y - t) and
+// loss = sum |y - t|^2 / n over the n x 9 outputs; one workgroup, fixed
+// summation order (deterministic).
+__global__ __launch_bounds__(256) void k_mlp_loss(const float *__restrict__ y, const float *__restrict__ t, int n,
+                                                  float *__restrict__ dy, float *__restrict__ loss) {
+  __shared__ double sh[16];
+  const float sc = 2.0f / (float)n;
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < n * kNOut; e += blockDim.x) {
+    const float r = y[e] - t[e];
+    dy[e] = sc * r;
+    acc += (double)r * (double)r;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0 && loss) *loss = (float)(acc / n);
 }
 
 // Adam (Kingma and Ba) on the fp32 master weights; c1 = 1/(1 - b1^t),
@@ -409,19 +613,19 @@ void launch_mlp_fwd(const uint16_t *w, const uint16_t *x, int n, float *y, uint1
   k_mlp_fwd<<<blocks, 256, 0, stream>>>(w, x, n, y, cache);
 }
 
-// About 8 rows per wavefront (each row is a chain of dependent lane
-// shuffles), up to 256 wavefronts; one fp32 slot of kWTotal per wavefront.
+// One wavefront per 32-row chunk, up to 256 wavefronts (the chunks are
+// shared out round-robin past that); one fp32 slot of kWTotal per wavefront.
 int mlp_bwd_parts(int n) {
-  int blocks = nblk(n, 4 * 8);
-  if (blocks > 64) blocks = 64;
+  int blocks = nblk(nblk(n, kBwdRows), kBwdWaves);
+  if (blocks > 256 / kBwdWaves) blocks = 256 / kBwdWaves;
   if (blocks < 1) blocks = 1;
-  return blocks * 4;
+  return blocks * kBwdWaves;
 }
 
 void launch_mlp_bwd(const uint16_t *w, const uint16_t *x, const uint16_t *cache, const float *dy, int n, float *dw,
                     float *work, hipStream_t stream) {
   const int parts = mlp_bwd_parts(n);
-  k_mlp_bwd<<<parts / 4, 256, 0, stream>>>(w, x, cache, dy, n, work);
+  k_mlp_bwd<<<parts / kBwdWaves, 64 * kBwdWaves, 0, stream>>>(w, x, cache, dy, n, work);
   k_mlp_reduce<<<nblk(kWTotal, 256), 256, 0, stream>>>(work, parts, dw);
 }
 
@@ -463,6 +667,10 @@ pse_status launch_mlp_bwd_static(const uint16_t *w, const uint16_t *x, const uin
   if (!work) return PSE_ERR_HIP;
   launch_mlp_bwd(w, x, cache, dy, n, dw, work, stream);
   return PSE_OK;
+}
+
+void launch_mlp_loss(const float *y, const float *t, int n, float *dy, float *loss, hipStream_t stream) {
+  k_mlp_loss<<<1, 256, 0, stream>>>(y, t, n, dy, loss);
 }
 
 void launch_mlp_adam(float *wm, uint16_t *wb, const float *g, float *m, float *v, float lr, int t,

@@ -56,6 +56,7 @@ constexpr int kMlpStaticSlots = 256;
 pse_status launch_mlp_bwd_static(const uint16_t *w, const uint16_t *x, const uint16_t *cache, const float *dy, int n,
                                  float *dw, hipStream_t stream);
 void launch_mlp_adam(float *wm, uint16_t *wb, const float *g, float *m, float *v, float lr, int t, hipStream_t stream);
+void launch_mlp_loss(const float *y, const float *t, int n, float *dy, float *loss, hipStream_t stream);
 template <typename T> void launch_pc_blocks(pse_ctx *c);           // features -> MLP -> P, P^-1 (fallbacks in flags[6])
 template <typename T, typename A> void launch_pc_pre(pse_ctx *c, const void *src, void *u);  // u = P^T src
 template <typename T, typename A>

@@ -5,14 +5,15 @@ The network, its features and the fallback rules are defined with the C ABI
 T_i - I, where T_i is the normalised symmetric root of the ii block of the
 inverse of M_r restricted to particle i's neighbourhood
 (pse_precond_targets), with the squared error summed over the 9 entries and
-averaged over particles.  Forward and backward passes and the Adam steps run
-in the HIP library (pse_mlp_*); only the 9-entry loss gradient of each row
-is formed on the host.
+averaged over particles.  Every step of an epoch runs in the HIP library
+on the device, with no host synchronisation: the forward pass and the
+backward pass on the matrix cores, the loss and its gradient
+(pse_mlp_loss_grad) and the Adam step; the loss history is read back once.
 """
 import numpy as np
 
 from . import (MLP_NPARAM, _ptr, pse_mlp_adam, pse_mlp_backward, pse_mlp_backward_workspace, pse_mlp_forward,
-               pse_precond_targets)
+               pse_mlp_loss_grad, pse_precond_targets)
 
 # (name, rows, cols, stored cols / rows) of the flat weight layout
 LAYOUT = (("W1", 64, 24, 32), ("b1", 64, 1, 1), ("W2", 64, 64, 64), ("b2", 64, 1, 1), ("W3", 9, 64, 16),
@@ -111,8 +112,9 @@ class Trainer:
     def fit(self, epochs, log_every=0):
         torch = self.torch
         X = torch.cat(self.X).contiguous()
-        T = np.concatenate(self.T)
+        T = torch.as_tensor(np.concatenate(self.T), dtype=torch.float32, device="cuda").contiguous()
         n = len(T)
+        losses = torch.zeros(max(epochs, 1), dtype=torch.float32, device="cuda")
         y = torch.empty((n, 9), dtype=torch.float32, device="cuda")
         cache = torch.empty((n, 128), dtype=torch.bfloat16, device="cuda")
         dy = torch.empty((n, 9), dtype=torch.float32, device="cuda")
@@ -124,13 +126,10 @@ class Trainer:
         xp = P(X, torch.bfloat16, 24 * n, "x")
         yp, cp, dyp = P(y, torch.float32, 9 * n, "y"), P(cache, torch.bfloat16, 128 * n, "cache"), \
             P(dy, torch.float32, 9 * n, "dy")
-        history = []
+        tp = P(T, torch.float32, 9 * n, "target")
         for ep in range(epochs):
             pse_mlp_forward(wb, xp, n, yp, cp, stream)
-            yh = y.cpu().numpy().astype(np.float64)
-            r = yh - T
-            history.append(float(np.mean(np.sum(r * r, axis=1))))
-            dy.copy_(torch.as_tensor((2.0 / n) * r, dtype=torch.float32))
+            pse_mlp_loss_grad(yp, tp, n, dyp, P(losses[ep:ep + 1], torch.float32, 1, "loss"), stream)
             pse_mlp_backward(wb, xp, cp, dyp, n, P(self.dw, torch.float32, MLP_NPARAM, "dw"),
                              P(work, torch.float32, wbytes // 4, "work"), wbytes, stream)
             self.t += 1
@@ -138,9 +137,9 @@ class Trainer:
                          P(self.dw, torch.float32, MLP_NPARAM, "dw"), P(self.m, torch.float32, MLP_NPARAM, "m"),
                          P(self.v, torch.float32, MLP_NPARAM, "v"), self.lr, self.t, stream)
             if log_every and ep % log_every == 0:
-                print(f"[precond] epoch {ep}: loss {history[-1]:.4e}", flush=True)
+                print(f"[precond] epoch {ep}: loss {float(losses[ep]):.4e}", flush=True)
         torch.cuda.synchronize()
-        return history
+        return [float(v) for v in losses[:epochs].cpu().numpy()]
 
     def weights_bits(self):
         """The trained bf16 weights as uint16 bit patterns (host)."""

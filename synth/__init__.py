@@ -3,10 +3,12 @@
 This module generates inputs only (particle configurations and plain i.i.d.
 normal arrays); it holds none of the sampler's arithmetic.
 
-Configurations follow the paper's workloads (random hard-sphere suspensions,
-Sec. III): random sequential addition (RSA) at volume fraction phi in a cubic
-periodic box, optionally relaxed by hard-sphere Monte Carlo sweeps; uniform
-random points (overlaps allowed, for the overlap cases of the RPY tensor).
+Configurations follow the paper's workloads (random hard-sphere suspensions
+and colloidal gels, Sec. III): random sequential addition (RSA) at volume
+fraction phi in a cubic periodic box, optionally relaxed by hard-sphere Monte
+Carlo sweeps; gels by diffusion-limited cluster aggregation from an RSA
+start; uniform random points (overlaps allowed, for the overlap cases of the
+RPY tensor).
 The C part (csrc/hs_gen.c) is compiled on first use with gcc -fopenmp.
 """
 import ctypes
@@ -44,6 +46,10 @@ def _load():
         lib.mc_relax.restype = ctypes.c_double
         lib.min_pair_distance.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         lib.min_pair_distance.restype = ctypes.c_double
+        lib.dlca_gel.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_longlong, dp,
+                                 ctypes.POINTER(ctypes.c_int32), dp]
+        lib.dlca_gel.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -142,6 +148,40 @@ def hard_spheres(n, phi, a=1.0, seed=0, sweeps=0, progress=None):
             done += k
             progress(f"MC sweeps {done}/{sweeps} (step {step:.3f}a, acceptance {acc:.2f})")
     return x, L
+
+
+def dlca_gel(n, phi, a=1.0, seed=0, step=0.5, gamma=0.5, stop_frac=0.9, max_moves=None):
+    """Colloidal gel by off-lattice diffusion-limited cluster aggregation
+    (csrc/hs_gen.c): n spheres placed by RSA at volume fraction phi; clusters
+    picked uniformly move by `step` (accepted with probability s^-gamma for
+    size s) and stick at first contact, until one cluster holds stop_frac of
+    the spheres.  Returns (x, L, cluster label per sphere, stats dict)."""
+    L = box_side(n, phi, a)
+    x = rsa_positions(n, L, a, seed)
+    lab = np.zeros(n, dtype=np.int32)
+    st = np.zeros(3)
+    if max_moves is None:
+        max_moves = 2000 * n
+    rc = _load().dlca_gel(n, L, a, seed + 104723, step * a, gamma, stop_frac, max_moves, _dp(x),
+                          lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(st))
+    if rc != 0:
+        raise RuntimeError(f"dlca_gel failed ({rc})")
+    return x, L, lab, {"moves": int(st[0]), "clusters": int(st[1]), "largest": int(st[2])}
+
+
+def mass_radius_slope(x, L, r_lo, r_hi, centers=2000, seed=0):
+    """Slope of log N(r) against log r on [r_lo, r_hi], N(r) the mean number
+    of spheres within r of a sphere (minimum image): the mass fractal
+    dimension of the structure on that range (3 for a uniform suspension)."""
+    from scipy.spatial import cKDTree
+
+    x = np.mod(np.asarray(x, dtype=np.float64), L)
+    x[x >= L] = 0.0
+    t = cKDTree(x, boxsize=L)
+    idx = np.random.default_rng(seed).choice(len(x), min(centers, len(x)), replace=False)
+    rs = np.geomspace(r_lo, r_hi, 8)
+    cnt = [np.mean(t.query_ball_point(x[idx], r, return_length=True)) - 1.0 for r in rs]
+    return float(np.polyfit(np.log(rs), np.log(cnt), 1)[0])
 
 
 def normals(seed, shape):

@@ -232,3 +232,142 @@ double min_pair_distance(int n, double L, double a, const double *x) {
   free(head); free(next);
   return sqrt(best);
 }
+
+/* --------------------------------------------------------- DLCA gel --- */
+/* Off-lattice diffusion-limited cluster aggregation in the periodic box.
+ * Start: n non-overlapping spheres in x (e.g. RSA), each its own cluster.
+ * Each trial picks a live cluster uniformly and accepts its move with
+ * probability s^-gamma (s its size: a Stokes-Einstein diffusivity that falls
+ * as the cluster grows); an accepted move translates the whole cluster by
+ * `step` along a uniformly random direction, stopping at the first contact
+ * |x_p - x_q| = 2a with a sphere of another cluster, and the two clusters
+ * then merge (they stick for good).  Ends when the largest cluster holds at
+ * least stop_frac of the spheres, or after max_moves accepted moves.
+ * Cells have side >= 2a + step, so every sphere a move can touch lies in the
+ * 27 cells around the moving sphere's cell.
+ * stats (may be NULL): [0] accepted moves, [1] clusters left, [2] largest
+ * cluster.  Returns 0, or -1 on allocation failure. */
+int dlca_gel(int n, double L, double a, uint64_t seed, double step, double gamma, double stop_frac,
+             long long max_moves, double *x, int *cluster, double *stats) {
+  int nc = (int)floor(L / (2.0 * a + step));
+  if (nc < 3) return -2;
+  const double cs = L / nc;
+  const long ncell = (long)nc * nc * nc;
+  int *head = (int *)malloc(sizeof(int) * ncell);
+  int *cnext = (int *)malloc(sizeof(int) * (size_t)n), *cprev = (int *)malloc(sizeof(int) * (size_t)n);
+  int *cellof = (int *)malloc(sizeof(int) * (size_t)n);
+  int *cid = (int *)malloc(sizeof(int) * (size_t)n), *mnext = (int *)malloc(sizeof(int) * (size_t)n);
+  int *mtail = (int *)malloc(sizeof(int) * (size_t)n), *msize = (int *)malloc(sizeof(int) * (size_t)n);
+  int *live = (int *)malloc(sizeof(int) * (size_t)n), *livepos = (int *)malloc(sizeof(int) * (size_t)n);
+  if (!head || !cnext || !cprev || !cellof || !cid || !mnext || !mtail || !msize || !live || !livepos) {
+    free(head); free(cnext); free(cprev); free(cellof); free(cid); free(mnext); free(mtail); free(msize);
+    free(live); free(livepos);
+    return -1;
+  }
+  for (long c = 0; c < ncell; ++c) head[c] = -1;
+  for (int i = 0; i < n; ++i) {
+    int c[3];
+    for (int d = 0; d < 3; ++d) {
+      x[3 * i + d] = wrap(x[3 * i + d], L);
+      c[d] = (int)(x[3 * i + d] / cs);
+      if (c[d] >= nc) c[d] = nc - 1;
+    }
+    const int cc = (c[0] * nc + c[1]) * nc + c[2];
+    cellof[i] = cc;
+    cprev[i] = -1;
+    cnext[i] = head[cc];
+    if (head[cc] >= 0) cprev[head[cc]] = i;
+    head[cc] = i;
+    cid[i] = i;
+    mnext[i] = -1;
+    mtail[i] = i;
+    msize[i] = 1;
+    live[i] = i;
+    livepos[i] = i;
+  }
+  int nlive = n, largest = 1;
+  uint64_t s = seed * 0x9E3779B97F4A7C15ull + 0x243F6A8885A308D3ull;
+  long long moves = 0;
+  const double sig = 2.0 * a, sig2 = sig * sig;
+  while (moves < max_moves && largest < stop_frac * n && nlive > 1) {
+    const int r = live[(int)(u01(&s) * nlive) % nlive];
+    if (gamma > 0 && u01(&s) > pow((double)msize[r], -gamma)) continue;
+    ++moves;
+    /* uniform direction on the sphere */
+    const double uz = 2.0 * u01(&s) - 1.0, ph = 2.0 * 3.14159265358979323846 * u01(&s);
+    const double rho = sqrt(1.0 - uz * uz);
+    const double u[3] = {rho * cos(ph), rho * sin(ph), uz};
+    double tmin = 1.0;
+    int hit = -1;
+    for (int p = r; p >= 0; p = mnext[p]) {
+      const int cc = cellof[p];
+      const int c0 = cc / (nc * nc), c1 = (cc / nc) % nc, c2 = cc % nc;
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz) {
+            const int nb = (((c0 + dx + nc) % nc) * nc + (c1 + dy + nc) % nc) * nc + (c2 + dz + nc) % nc;
+            for (int q = head[nb]; q >= 0; q = cnext[q]) {
+              if (cid[q] == r) continue;
+              const double d0 = mind(x[3 * q] - x[3 * p], L), d1 = mind(x[3 * q + 1] - x[3 * p + 1], L),
+                           d2 = mind(x[3 * q + 2] - x[3 * p + 2], L);
+              const double b = d0 * u[0] + d1 * u[1] + d2 * u[2];
+              if (b <= 0) continue; /* moving away */
+              const double cq = d0 * d0 + d1 * d1 + d2 * d2 - sig2;
+              const double disc = b * b - cq;
+              if (disc < 0) continue; /* the path passes by */
+              double t = (b - sqrt(disc)) / step;
+              if (t < 0) t = 0; /* touching already (rounding) */
+              if (t < tmin) {
+                tmin = t;
+                hit = q;
+              }
+            }
+          }
+    }
+    /* translate the cluster, keeping the cell lists current */
+    const double dv[3] = {tmin * step * u[0], tmin * step * u[1], tmin * step * u[2]};
+    for (int p = r; p >= 0; p = mnext[p]) {
+      int c[3];
+      for (int d = 0; d < 3; ++d) {
+        x[3 * p + d] = wrap(x[3 * p + d] + dv[d], L);
+        c[d] = (int)(x[3 * p + d] / cs);
+        if (c[d] >= nc) c[d] = nc - 1;
+      }
+      const int cc = (c[0] * nc + c[1]) * nc + c[2];
+      if (cc != cellof[p]) {
+        if (cprev[p] >= 0) cnext[cprev[p]] = cnext[p];
+        else head[cellof[p]] = cnext[p];
+        if (cnext[p] >= 0) cprev[cnext[p]] = cprev[p];
+        cellof[p] = cc;
+        cprev[p] = -1;
+        cnext[p] = head[cc];
+        if (head[cc] >= 0) cprev[head[cc]] = p;
+        head[cc] = p;
+      }
+    }
+    if (hit >= 0) {
+      /* merge the smaller cluster into the larger: relabel and splice */
+      int big = cid[hit], small = r;
+      if (msize[small] > msize[big]) { const int t = big; big = small; small = t; }
+      for (int p = small; p >= 0; p = mnext[p]) cid[p] = big;
+      mnext[mtail[big]] = small;
+      mtail[big] = mtail[small];
+      msize[big] += msize[small];
+      if (msize[big] > largest) largest = msize[big];
+      const int ps = livepos[small], last = live[nlive - 1];
+      live[ps] = last;
+      livepos[last] = ps;
+      --nlive;
+    }
+  }
+  if (cluster)
+    for (int i = 0; i < n; ++i) cluster[i] = cid[i];
+  if (stats) {
+    stats[0] = (double)moves;
+    stats[1] = nlive;
+    stats[2] = largest;
+  }
+  free(head); free(cnext); free(cprev); free(cellof); free(cid); free(mnext); free(mtail); free(msize);
+  free(live); free(livepos);
+  return 0;
+}

@@ -106,11 +106,15 @@ def ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def test_mlp_backward_and_adam_match_oracle(gpu_lib):
+@pytest.mark.parametrize("n", [777, 9001])
+def test_mlp_backward_and_adam_match_oracle(gpu_lib, n):
+    """The backward pass (matrix cores, fp32 factors split into three bf16
+    parts) against the oracle's FP64 chain rule; 9001 rows are more 32-row
+    chunks than wavefronts, so chunks are shared round-robin and the last
+    one is ragged."""
     import torch
     from paper_1611_09322_amd import precond as ppc
 
-    n = 777
     bits, wr = weights(7, 0.3)
     xf = opc.bf16_round(np.random.default_rng(8).standard_normal((n, 24)))
     X, w = bits_tensor(bits_of(xf)), bits_tensor(bits)
@@ -129,7 +133,8 @@ def test_mlp_backward_and_adam_match_oracle(gpu_lib):
     for k in g:
         e = rel(gg[k], g[k])
         print(f"grad {k}: rel err {e:.2e}")
-        assert e < 1e-4, k
+        # fp32 sums over n rows: a few 1e-7
+        assert e < 2e-6, k
     flat = host(dw)
     assert not np.any(flat[0:2048].reshape(64, 32)[:, 24:]) and not np.any(flat[6272:7296].reshape(16, 64)[9:])
     # three Adam steps against the oracle's update
@@ -148,6 +153,23 @@ def test_mlp_backward_and_adam_match_oracle(gpu_lib):
     print(f"adam: max abs diff {e:.2e}")
     assert e < 1e-5
     np.testing.assert_array_equal(host(wb), opc.bf16_round(host(wm)))
+
+
+def test_mlp_loss_grad(gpu_lib):
+    """dy = (2/n)(y - t) and the mean squared error, on the device."""
+    import torch
+
+    n = 5003
+    rng = np.random.default_rng(21)
+    yh, th = rng.standard_normal((n, 9)), rng.standard_normal((n, 9))
+    y = torch.as_tensor(yh, dtype=torch.float32, device="cuda")
+    t = torch.as_tensor(th, dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(y)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    gpu_lib.pse_mlp_loss_grad(ptr(y), ptr(t), n, ptr(dy), ptr(loss))
+    r = yh.astype(np.float32).astype(np.float64) - th.astype(np.float32).astype(np.float64)
+    assert rel(host(dy), 2.0 / n * r) < 1e-6
+    assert abs(float(host(loss)[0]) - np.mean(np.sum(r * r, axis=1))) < 1e-6 * np.mean(np.sum(r * r, axis=1))
 
 
 @pytest.mark.parametrize("precision,tol,bar", [("fp64", 1e-9, 1e-6), ("mixed", 1e-6, 1e-4), ("fp32", 1e-5, 3e-4)])
@@ -243,6 +265,49 @@ def test_training_fits_the_targets(gpu_lib):
     assert st.converged and st.precond_fallbacks < len(x) // 10
     s.close()
     s0.close()
+
+
+def test_gel_trained_blocks_against_the_plain_sample(gpu_lib):
+    """The learned preconditioner on its own workload: a network trained on
+    twelve small DLCA gels (volume fraction 0.05, xi a = 0.3, where kappa(M_r)
+    is largest among the benchmark's choices) against P = I on a held-out
+    gel.  Even the ideal blocks leave the iteration count unchanged on such
+    gels (the oracle experiment in test_oracle_precond), so the claim checked
+    is the one that holds: the trained blocks converge, keep almost every
+    particle (fallbacks below 10 %), and cost at most one iteration more than
+    the plain sample; the counts are printed."""
+    import torch
+    from paper_1611_09322_amd import precond as ppc
+
+    xi, rc = 0.3, 8.9
+    tr = ppc.Trainer(torch, seed=2, lr=3e-3)
+    for k in range(12):
+        x, L, _, _ = synth.dlca_gel(1500, 0.05, seed=2200 + k)
+        s = gpu_lib.Sampler(len(x), L, xi=xi, rcut=rc, grid=64, support=8, tol=1e-3, precision="mixed", precond=1)
+        s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+        tr.add(s, x, np.arange(0, len(x), 15, dtype=np.int32))
+        s.close()
+    hist = tr.fit(300)
+    print(f"gel training loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    assert hist[-1] < 0.5 * hist[0]
+    x, L, _, _ = synth.dlca_gel(6000, 0.05, seed=2299)
+    z = torch.as_tensor(synth.normals(15, (len(x), 3)), dtype=torch.float32, device="cuda")
+    its = {}
+    for tol in (1e-3, 1e-5):
+        sp = gpu_lib.Sampler(len(x), L, xi=xi, rcut=rc, grid=96, support=8, tol=tol, precision="mixed", precond=1)
+        sp.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+        sp.set_precond_weights(tr.weights_bits())
+        _, st = sp.real_sample(z)
+        s0 = gpu_lib.Sampler(len(x), L, xi=xi, rcut=rc, grid=96, support=8, tol=tol, precision="mixed")
+        s0.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+        _, st0 = s0.real_sample(z)
+        its[tol] = (st.lanczos_iters, st0.lanczos_iters)
+        print(f"held-out gel, tol {tol:.0e}: {st.lanczos_iters} iterations with the trained blocks, "
+              f"{st0.lanczos_iters} plain, fallbacks {st.precond_fallbacks}")
+        assert st.converged and st0.converged and st.precond_fallbacks < len(x) // 10
+        assert st.lanczos_iters <= st0.lanczos_iters + 1
+        sp.close()
+        s0.close()
 
 
 def test_global_fallback_when_the_preconditioned_sample_fails(gpu_lib):

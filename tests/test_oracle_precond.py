@@ -177,18 +177,25 @@ def test_target_pair_closed_form():
     np.testing.assert_allclose(T, exp, atol=1e-12)
 
 
-def test_ideal_block_preconditioner_leaves_the_krylov_work_unchanged():
-    """Hard spheres at phi = 0.3 (xi a = 0.5, rc = 8a): every diagonal block
-    of M_r is the self term, and the spread of its spectrum comes from pair
-    coupling.  Even the ideal block preconditioner, the symmetric root of the
-    ii block of M_r^{-1}, leaves kappa(P M_r P^T) no smaller than kappa(M_r),
-    and the tol-1e-3 Krylov sample needs as many iterations.  This is why
-    the learned blocks cannot pay for themselves at the benchmark's
-    parameters."""
+@pytest.mark.parametrize("kind,phi,xi", [("hard spheres", 0.3, 0.5), ("gel", 0.05, 0.5), ("gel", 0.05, 0.2)])
+def test_ideal_block_preconditioner_leaves_the_krylov_work_unchanged(kind, phi, xi):
+    """Hard spheres at phi = 0.3 and a DLCA gel at phi = 0.05 (contact
+    chains, d_f ~ 2), at xi a = 0.5 and, for the gel, 0.2 (a smaller xi moves
+    work into real space and raises kappa(M_r)), rc from exp(-xi^2 rc^2) =
+    1e-3.  Every diagonal block of M_r is the self term plus a little, and
+    the spread of its spectrum comes from pair coupling.  Even the ideal
+    block preconditioner, the symmetric root of the ii block of M_r^{-1},
+    lowers kappa(P M_r P^T) by at most ~12 % and the tol-1e-3 Krylov sample
+    needs as many iterations.  This is why the learned blocks cannot pay for
+    themselves on these structures."""
     import synth
 
-    x, Lb = synth.hard_spheres(300, 0.3, a=1.0, seed=3, sweeps=20)
-    Mr = rpy.real_block_dense(x, Lb, A, ETA, XI, RC)
+    if kind == "gel":
+        x, Lb, _, _ = synth.dlca_gel(500, phi, seed=3)
+    else:
+        x, Lb = synth.hard_spheres(300, phi, a=1.0, seed=3, sweeps=20)
+    rc = min(np.sqrt(-np.log(1e-3)) / xi * 1.1, 0.49 * Lb)
+    Mr = rpy.real_block_dense(x, Lb, A, ETA, xi, rc)
     Minv = np.linalg.inv(Mr)
     P = np.array([precond._sqrtm_spd(Minv[3 * i:3 * i + 3, 3 * i:3 * i + 3]) for i in range(len(x))])
     B = precond.block_diag(P)
@@ -199,6 +206,6 @@ def test_ideal_block_preconditioner_leaves_the_krylov_work_unchanged():
     z = np.random.default_rng(1).standard_normal(3 * len(x))
     _, m0, _ = lanczos.lanczos_sqrt(lambda v: Mr @ v, z, 1e-3)
     _, m1, _ = lanczos.lanczos_sqrt(lambda v: Ap @ v, z, 1e-3)
-    print(f"kappa {k0:.3f} -> {k1:.3f}, iterations {m0} -> {m1}")
-    assert k1 >= 0.95 * k0
+    print(f"{kind} phi {phi} xi {xi}: kappa {k0:.3f} -> {k1:.3f}, iterations {m0} -> {m1}")
+    assert k1 >= 0.85 * k0
     assert m1 >= m0
