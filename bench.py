@@ -282,11 +282,14 @@ def measured_constants(res, n, params):
     pairs = res["neighbor_pairs"]
     M3 = float(params.grid) ** 3
     P3 = float(params.support) ** 3
+    # two significant digits: run-to-run noise of a few percent then rarely
+    # moves the parameters chosen from them
+    r2 = lambda v: float(f"{v:.2g}")
     return {
-        "c_pair": 1e-3 * b["spmv"] / max(c["spmv"], 1) / pairs,
-        "c_node": 1e-3 * (b["spread"] + b["interp"]) / (2 * n * P3),
-        "c_fft": 1e-3 * (b["fft"] + b["xfused"]) / (M3 * math.log2(M3)),
-        "c_particle": 1e-3 * (b["bin"] + b["lanczos"] + b["noise"] + b["other"]) / n,
+        "c_pair": r2(1e-3 * b["spmv"] / max(c["spmv"], 1) / pairs),
+        "c_node": r2(1e-3 * (b["spread"] + b["interp"]) / (2 * n * P3)),
+        "c_fft": r2(1e-3 * (b["fft"] + b["xfused"]) / (M3 * math.log2(M3))),
+        "c_particle": r2(1e-3 * (b["bin"] + b["lanczos"] + b["noise"] + b["other"]) / n),
     }
 
 
@@ -380,7 +383,8 @@ def run_batch(pse, torch, args):
     rc, grid (at most 96^3, radix 2 and 3 sizes) and support chosen by the
     error model and work model for the tolerance.  Each step sets new
     positions and samples every replica; compared with the same replicas
-    sampled one after another through their own contexts."""
+    sampled one after another through their own contexts, and with the
+    whole batch step captured once in a HIP graph and replayed."""
     import numpy as np
 
     import synth
@@ -413,6 +417,21 @@ def run_batch(pse, torch, args):
     torch.cuda.synchronize()
     dt_b = (time.perf_counter() - t1) / args.batch_steps
     lat = np.array(b.latency())
+    # the same step captured once into a HIP graph and replayed: one launch
+    # and one synchronisation per step for the whole batch
+    gout = [torch.empty((sp["n"], 3), dtype=torch.float32, device="cuda") for sp in specs]
+    b.graph_create(pos, gout, 1e-3, extra_iters=2, headroom=0.25)
+    for k in range(args.warmup):
+        b.graph_step(11, 3000 + k)
+    torch.cuda.synchronize()
+    g_ms, redone = [], 0
+    for k in range(args.batch_steps):
+        ta = time.perf_counter()
+        _, gst, red = b.graph_step(11, 1000 + k)
+        g_ms.append(1e3 * (time.perf_counter() - ta))
+        redone += red
+    dt_g = float(np.median(g_ms)) / 1e3
+    b.graph_destroy()
     # the same replicas one after another, each through its own context
     ctxs = [pse.pse_batch_replica(b.b, r) for r in range(len(specs))]
     outs = [torch.empty((sp["n"], 3), dtype=torch.float32, device="cuda") for sp in specs]
@@ -437,6 +456,10 @@ def run_batch(pse, torch, args):
         "value": total / dt_b, "unit": "samples·particles/s", "ms_per_step": 1e3 * dt_b,
         "completion_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "lanczos_iters_mean": float(np.mean([s.lanczos_iters for s in st])),
+        "graph": {"kind": "whole batch step captured in one HIP graph (pse_batch_graph_*), replayed per step",
+                  "value": total / dt_g, "ms_per_step": {"p50": float(np.median(g_ms)), "p10": pct(g_ms, 10),
+                                                         "p90": pct(g_ms, 90)},
+                  "replicas_redone": redone, "lanczos_iters_mean": float(np.mean([s.lanczos_iters for s in gst]))},
         "sequential": {"value": total / dt_s, "ms_per_step": 1e3 * dt_s,
                        "service_ms": {"p50": pct(seq, 50), "p99": pct(seq, 99)},
                        "completion_ms": {"p50": pct(cum, 50), "p99": pct(cum, 99)}},

@@ -486,6 +486,42 @@ pse_status pse_batch_autotune(pse_batch *batch);
  * of each replica's displacement (host array of n_rep; waits for them). */
 pse_status pse_batch_latency(pse_batch *batch, float *ms);
 
+/* A whole batch step captured once into a HIP graph and replayed per step:
+ * for every replica, pse_set_positions on pos[r] followed by its sample
+ * (Philox noise, key seed + r, counter; dt; forces[r] or none) into
+ * disp[r].  The buffers are the caller's device arrays, fixed for the life
+ * of the graph (the caller rewrites the positions in place between steps,
+ * e.g. by moving the particles by disp).  One replay is one graph launch
+ * and one synchronisation for the whole batch, against about 45 launches
+ * and two host waits per replica on the eager path.
+ *
+ * pse_batch_graph_create runs one eager step on the buffers (seed 0,
+ * counter 0), then fixes for each replica its block edge, a halo capacity
+ * and a neighbour-list capacity `headroom` (e.g. 0.25) above what that step
+ * needed, and a Krylov iteration count `extra_iters` above the iterations
+ * it needed (the iteration kernels stop themselves once converged), and
+ * captures the step.  No host decision and no synchronisation is taken
+ * inside a replay: the kernels flag a halo or list that outgrows its
+ * capacity (they then skip the work, never write past it), the Krylov
+ * state and the flags are copied back, and pse_batch_graph_step, after its
+ * one synchronisation, redoes on the eager path every replica whose step
+ * overflowed, did not converge within the captured iterations, or met
+ * non-finite positions; the next step then captures the batch anew with
+ * capacities from the new positions.  The result of every step therefore
+ * equals the eager pse_batch_set_positions + pse_batch_sample with the same
+ * seed and counter (bit for bit while the block edge stays that of the
+ * capture).  stats (n_rep, may be NULL) as pse_batch_sample; *redone (may
+ * be NULL) receives the number of replicas redone.  Captured work uses
+ * fill kernels, no memset nodes.
+ * Errors: INVALID_ARG (null buffers, dt <= 0, extra_iters < 0, headroom
+ * < 0), NO_POSITIONS (step without a graph), OOM, HIP, and those of the
+ * eager step. */
+pse_status pse_batch_graph_create(pse_batch *batch, const void *const *pos_dev, const void *const *forces_dev,
+                                  void *const *disp_dev, double dt, int32_t extra_iters, double headroom);
+pse_status pse_batch_graph_step(pse_batch *batch, uint64_t seed, uint64_t counter, pse_stats *stats,
+                                int32_t *redone);
+pse_status pse_batch_graph_destroy(pse_batch *batch);
+
 /* Launch-shape autotuning.  Times, on the context's current positions
  * (pse_set_positions first; PSE_ERR_NO_POSITIONS otherwise), every valid
  * depth of the owner-computes spreading tiles (8 x 8 x D nodes, D in 8, 16,

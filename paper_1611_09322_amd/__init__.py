@@ -160,6 +160,11 @@ _SIGS = {
     "pse_batch_sample": ([_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_VP),
                           ctypes.POINTER(_VP), ctypes.POINTER(Stats)], ctypes.c_int),
     "pse_batch_latency": ([_VP, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "pse_batch_graph_create": ([_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.c_double,
+                                ctypes.c_int32, ctypes.c_double], ctypes.c_int),
+    "pse_batch_graph_step": ([_VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Stats),
+                              ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "pse_batch_graph_destroy": ([_VP], ctypes.c_int),
     "pse_batch_autotune": ([_VP], ctypes.c_int),
     "pse_autotune": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "pse_set_launch_shape": ([_VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -412,6 +417,27 @@ def pse_batch_sample(b, seed, counter, dt, force_ptrs, disp_ptrs):
     return s, list(st)
 
 
+def pse_batch_graph_create(b, pos_ptrs, force_ptrs, disp_ptrs, dt, extra_iters=4, headroom=0.25):
+    n = len(disp_ptrs)
+    parr = (_VP * n)(*pos_ptrs)
+    farr = None if force_ptrs is None else (_VP * n)(*force_ptrs)
+    darr = (_VP * n)(*disp_ptrs)
+    _check(load().pse_batch_graph_create(b, parr, farr, darr, dt, extra_iters, headroom), "pse_batch_graph_create")
+
+
+def pse_batch_graph_step(b, n, seed, counter):
+    """One replay; returns (status, per-replica Stats, replicas redone)."""
+    st = (Stats * n)()
+    red = ctypes.c_int32(0)
+    s = load().pse_batch_graph_step(b, seed, counter, st, ctypes.byref(red))
+    _check(s, "pse_batch_graph_step", allow=SAMPLE_OK)
+    return s, list(st), int(red.value)
+
+
+def pse_batch_graph_destroy(b):
+    _check(load().pse_batch_graph_destroy(b), "pse_batch_graph_destroy")
+
+
 def pse_batch_latency(b, n):
     ms = (ctypes.c_float * n)()
     _check(load().pse_batch_latency(b, ms), "pse_batch_latency")
@@ -644,6 +670,22 @@ class Batch:
 
     def latency(self):
         return pse_batch_latency(self.b, len(self.n))
+
+    def graph_create(self, pos, out, dt, forces=None, extra_iters=4, headroom=0.25):
+        """Capture one step (set positions + sample) on these buffers
+        (pse_batch_graph_create); the tensors must outlive the graph."""
+        fp = None if forces is None else self._ptrs(forces, "forces")
+        self._graph_bufs = (pos, out, forces)
+        pse_batch_graph_create(self.b, self._ptrs(pos, "positions"), fp, self._ptrs(out, "out"), dt, extra_iters,
+                               headroom)
+
+    def graph_step(self, seed, counter):
+        """One replay: (status, stats, replicas redone)."""
+        return pse_batch_graph_step(self.b, len(self.n), seed, counter)
+
+    def graph_destroy(self):
+        pse_batch_graph_destroy(self.b)
+        self._graph_bufs = None
 
     def autotune(self):
         """pse_batch_autotune (after set_positions)."""

@@ -115,6 +115,7 @@ WaveCoef wave_coef(const pse_ctx *c, double det_scale, double sto_scale, uint64_
   w.seed = seed;
   w.counter = counter;
   w.use_philox = 1;
+  w.rng = c->rng_dev;
   (void)M;
   return w;
 }
@@ -144,6 +145,7 @@ pse_status lz_start(pse_ctx *c, const void *z_sorted) {
   const bool pc = pc_active(c);
   const int maxit = c->lz_maxit;
   int k = c->last_iters < 2 ? 2 : c->last_iters;
+  if (c->graph) k = c->graph_iters;  // no host decision: the kernels stop themselves once converged
   if (k > maxit) k = maxit;
   for (int i = 0; i < k; ++i) {
     if (pc) launch_lz_iter_pc<T, A>(c, i, z_sorted);
@@ -165,6 +167,14 @@ void take_pc_fallbacks(pse_ctx *c, bool synced) {
 
 template <typename T, typename A>
 pse_status lz_finish(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
+  if (c->graph) {
+    // captured: the iterate of the iterations queued by lz_start; the
+    // state copied back by lz_start tells the host after the replay
+    // whether they sufficed
+    launch_lz_combine<T, A>(c, y_sorted);
+    if (pc_active(c)) launch_pc_apply_inv<T>(c, y_sorted);
+    return hip_status(hipGetLastError());
+  }
   take_pc_fallbacks(c, true);
   auto *h = (LzState<A> *)c->lz_h;
   const bool pc = pc_active(c);
@@ -223,7 +233,8 @@ pse_status wave_core(pse_ctx *c, const void *f_sorted, int noise, const void *W,
   const size_t M3 = (size_t)c->p.grid * c->p.grid * c->p.grid;
   if (!f_sorted && noise == 0) {
     ProfScope ps(c, PSE_STAGE_OTHER);
-    return hip_status(hipMemsetAsync(out, 0, sizeof(T) * 4 * c->n, c->stream));
+    launch_zero_words(c->stream, out, sizeof(T) * c->n);  // 4 components
+    return hip_status(hipGetLastError());
   }
   // caller noise: zeta on the half spectrum as given (NOISE_KSPACE), or
   // the DFT of the grid noise W (scaled by M^{-3/2} in the x pass)
@@ -308,6 +319,11 @@ pse_status sample_end(pse_ctx *c, const SampleState &ss, double dt, void *disp, 
     stats->precond_fallbacks = 0;
   }
   launch_finalize<T>(c, ss.real ? yr : nullptr, ss.cr, ss.forces ? ur : nullptr, dt, wave, disp);
+  if (c->graph) {
+    // the device flags of this step (list and halo overflow, non-finite
+    // positions) for the host's check after the replay
+    return hip_status(hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
+  }
   if (stats) {
     stats->max_neighbors = c->flags_h[5];
     stats->neighbor_pairs = c->pairs;
@@ -360,6 +376,21 @@ template <typename T>
 pse_status set_positions_impl(pse_ctx *c, const void *pos) {
   c->have_pos = false;
   launch_bin<T>(c, pos);
+  if (c->graph) {
+    // captured: block edge, halo capacity and list capacity stay as fixed
+    // at capture; the kernels flag what does not fit
+    if (c->lds_B) launch_nbr_lds(c);
+    else launch_nbr<T>(c);
+    if (c->pc_on) {
+      if (c->lds_B && !c->pc_fixed) launch_feat_lds(c);
+      launch_pc_blocks<T>(c);
+      if (hipMemcpyAsync(c->pc_fb_h, c->flags + 6, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return PSE_ERR_HIP;
+      c->pc_fb_pending = true;
+    }
+    c->have_pos = true;
+    return hip_status(hipGetLastError());
+  }
   // FP32 storage: stage the near-field halo in LDS when it fits.  The block
   // edge B (cells) is the largest whose halo leaves room for two workgroups
   // per CU (one stages while the other computes), searched downwards from
@@ -409,6 +440,7 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
   if (c->flags_h[0]) return PSE_ERR_NONFINITE;
   if (c->flags_h[1] > c->nbr_cap) {
     const int cap = (c->flags_h[1] + 32 + 7) & ~7;
+    c->graph_stale = true;  // a captured graph holds the old list
     (void)hipFree(c->nbr);
     c->nbr = nullptr;
     if (hipMalloc(&c->nbr, sizeof(int) * (size_t)cap * c->n) != hipSuccess) {
@@ -619,6 +651,17 @@ struct pse_batch {
   hipEvent_t start = nullptr;
   std::vector<hipEvent_t> done;  // per replica: end of its last sample
   std::vector<hipEvent_t> join;  // per stream
+  // captured step (pse_batch_graph_*)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t gstream = nullptr;  // capture and replay stream (the caller's may be the null stream)
+  hipEvent_t g_in = nullptr, g_out = nullptr;
+  uint64_t *rng_h = nullptr, *rng_d = nullptr;  // (seed + r, counter) per replica, pinned host / device
+  std::vector<const void *> g_pos, g_forces;
+  std::vector<void *> g_disp;
+  std::vector<int> g_hcap;  // halo capacity each replica was captured with
+  double g_dt = 0.0, g_headroom = 0.0;
+  int g_extra = 0;
 };
 
 namespace pse {
@@ -662,23 +705,39 @@ template <typename F> static pse_status for_streams(pse_batch *b, F fn) {
   return w;
 }
 
-static pse_status fork(pse_batch *b) {
-  if (hipEventRecord(b->start, b->user) != hipSuccess) return PSE_ERR_HIP;
+// The replica streams wait for `from` (by default the caller's stream),
+// and `from` waits for them.
+static pse_status fork(pse_batch *b, hipStream_t from) {
+  if (hipEventRecord(b->start, from) != hipSuccess) return PSE_ERR_HIP;
   for (hipStream_t s : b->streams)
     if (hipStreamWaitEvent(s, b->start, 0) != hipSuccess) return PSE_ERR_HIP;
   return PSE_OK;
 }
+static pse_status fork(pse_batch *b) { return fork(b, b->user); }
 
-static pse_status join(pse_batch *b) {
+static pse_status join(pse_batch *b, hipStream_t to) {
   for (size_t q = 0; q < b->streams.size(); ++q)
-    if (hipEventRecord(b->join[q], b->streams[q]) != hipSuccess ||
-        hipStreamWaitEvent(b->user, b->join[q], 0) != hipSuccess)
+    if (hipEventRecord(b->join[q], b->streams[q]) != hipSuccess || hipStreamWaitEvent(to, b->join[q], 0) != hipSuccess)
       return PSE_ERR_HIP;
   return PSE_OK;
+}
+static pse_status join(pse_batch *b) { return join(b, b->user); }
+
+static void free_graph(pse_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
 }
 
 static void free_batch(pse_batch *b) {
   if (!b) return;
+  free_graph(b);
+  if (b->rng_h) (void)hipHostFree(b->rng_h);
+  if (b->rng_d) (void)hipFree(b->rng_d);
+  if (b->g_in) (void)hipEventDestroy(b->g_in);
+  if (b->g_out) (void)hipEventDestroy(b->g_out);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
   for (pse_ctx *c : b->ctx) free_ctx(c);
   for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
@@ -1072,6 +1131,222 @@ pse_status pse_batch_autotune(pse_batch *b) {
     const pse_status st = autotune_spmv(c, nullptr);
     if (st != PSE_OK) return st;
   }
+  return PSE_OK;
+}
+
+}  // extern "C"
+
+namespace pse {
+
+struct LzView {
+  int m, done, converged, nonfinite;
+  double rel;
+};
+static LzView lz_view(const pse_ctx *c) {
+  if (c->dbl || c->acc_dbl) {
+    const auto *h = (const LzState<double> *)c->lz_h;
+    return {h->m, h->done, h->converged, h->nonfinite, h->rel_change};
+  }
+  const auto *h = (const LzState<float> *)c->lz_h;
+  return {h->m, h->done, h->converged, h->nonfinite, (double)h->rel_change};
+}
+
+static pse_status ctx_set_positions(pse_ctx *c, const void *pos) {
+  return c->dbl ? set_positions_impl<double>(c, pos) : set_positions_impl<float>(c, pos);
+}
+
+// Capture one batch step (every replica's set_positions and sample, on the
+// replicas' streams) into b->gexec.  Capacities get the headroom first
+// (outside the capture: the list may be reallocated); inside the capture no
+// host decision and no synchronisation is taken.
+static pse_status batch_capture(pse_batch *b) {
+  const int R = (int)b->ctx.size();
+  const int hcap_lds = (int)((kLdsBudget - sizeof(float2) * kTableN) / (sizeof(float4) + sizeof(float2)));
+  for (int r = 0; r < R; ++r) {
+    pse_ctx *c = b->ctx[r];
+    if (c->lds_B) {
+      int want = (int)std::ceil((c->hcap - 1) * (1.0 + b->g_headroom)) + 1;
+      if (want > hcap_lds) want = hcap_lds;
+      if (want > 65536) want = 65536;  // 16-bit halo-local indices
+      if (want > c->hcap) c->hcap = want;
+    }
+    b->g_hcap[r] = c->hcap;
+    const int cap = ((int)std::ceil(c->flags_h[1] * (1.0 + b->g_headroom)) + 32 + 7) & ~7;
+    if (cap > c->nbr_cap) {
+      if (hipStreamSynchronize(c->stream) != hipSuccess) return PSE_ERR_HIP;
+      (void)hipFree(c->nbr);
+      c->nbr = nullptr;
+      if (hipMalloc(&c->nbr, sizeof(int) * (size_t)cap * c->n) != hipSuccess) {
+        c->nbr_cap = 0;
+        return PSE_ERR_OOM;
+      }
+      c->nbr_cap = cap;
+    }
+    int it = (c->last_iters < 2 ? 2 : c->last_iters) + b->g_extra;
+    c->graph_iters = it > c->lz_maxit ? c->lz_maxit : it;
+    c->graph_stale = false;
+  }
+  std::vector<uint32_t> prof(R);
+  for (int r = 0; r < R; ++r) {
+    pse_ctx *c = b->ctx[r];
+    prof[r] = c->prof_mask;
+    c->prof_mask = 0;
+    c->graph = true;
+    c->rng_dev = b->rng_d + 2 * r;
+  }
+  pse_status st = hip_status(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeRelaxed));
+  if (st == PSE_OK)
+    st = hip_status(hipMemcpyAsync(b->rng_d, b->rng_h, sizeof(uint64_t) * 2 * R, hipMemcpyHostToDevice, b->gstream));
+  if (st == PSE_OK) st = fork(b, b->gstream);
+  for (int r = 0; r < R && st == PSE_OK; ++r) {
+    pse_ctx *c = b->ctx[r];
+    st = ctx_set_positions(c, b->g_pos[r]);
+    SampleState ss;
+    if (st == PSE_OK) st = ctx_begin(c, 0, 0, b->g_dt, b->g_forces.empty() ? nullptr : b->g_forces[r], ss);
+    if (st == PSE_OK) st = ctx_end(c, ss, b->g_dt, b->g_disp[r], nullptr);
+  }
+  if (st == PSE_OK) st = join(b, b->gstream);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(b->gstream, &g);
+  for (int r = 0; r < R; ++r) {
+    pse_ctx *c = b->ctx[r];
+    c->prof_mask = prof[r];
+    c->graph = false;
+    c->rng_dev = nullptr;
+  }
+  if (st == PSE_OK && ec != hipSuccess) st = PSE_ERR_HIP;
+  if (st != PSE_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+    b->gexec = nullptr;
+    free_graph(b);
+    return PSE_ERR_HIP;
+  }
+  return PSE_OK;
+}
+
+}  // namespace pse
+
+extern "C" {
+
+pse_status pse_batch_graph_create(pse_batch *b, const void *const *pos, const void *const *forces,
+                                  void *const *disp, double dt, int32_t extra_iters, double headroom) {
+  if (!b || !pos || !disp || !(dt > 0) || extra_iters < 0 || !(headroom >= 0)) return PSE_ERR_INVALID_ARG;
+  const int R = (int)b->ctx.size();
+  for (int r = 0; r < R; ++r)
+    if (!pos[r] || !disp[r]) return PSE_ERR_INVALID_ARG;
+  free_graph(b);
+  b->g_pos.assign(pos, pos + R);
+  b->g_forces.clear();
+  if (forces) b->g_forces.assign(forces, forces + R);
+  b->g_disp.assign(disp, disp + R);
+  b->g_hcap.assign(R, 0);
+  b->g_dt = dt;
+  b->g_extra = extra_iters;
+  b->g_headroom = headroom;
+  if (!b->gstream) {
+    if (hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess) {
+      b->gstream = nullptr;
+      return PSE_ERR_HIP;
+    }
+    if (hipEventCreateWithFlags(&b->g_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->g_out, hipEventDisableTiming) != hipSuccess)
+      return PSE_ERR_HIP;
+  }
+  if (!b->rng_h) {
+    if (hipHostMalloc((void **)&b->rng_h, sizeof(uint64_t) * 2 * R, hipHostMallocDefault) != hipSuccess) {
+      b->rng_h = nullptr;
+      return PSE_ERR_OOM;
+    }
+    if (hipMalloc((void **)&b->rng_d, sizeof(uint64_t) * 2 * R) != hipSuccess) {
+      b->rng_d = nullptr;
+      return PSE_ERR_OOM;
+    }
+  }
+  // one eager step on these buffers: block edges, halo sizes, list
+  // capacities and iteration counts of the positions, and the kernels'
+  // launch attributes, before anything is captured
+  pse_status st = pse_batch_set_positions(b, pos);
+  if (st < 0) return st;
+  std::vector<pse_stats> stv(R);
+  st = pse_batch_sample(b, 0, 0, dt, forces, disp, stv.data());
+  if (st < 0 && st != PSE_ERR_NOT_CONVERGED) return st;
+  if (hipStreamSynchronize(b->user) != hipSuccess) return PSE_ERR_HIP;
+  return batch_capture(b);
+}
+
+pse_status pse_batch_graph_step(pse_batch *b, uint64_t seed, uint64_t counter, pse_stats *stats, int32_t *redone) {
+  if (!b) return PSE_ERR_INVALID_ARG;
+  if (!b->gexec) return PSE_ERR_NO_POSITIONS;
+  const int R = (int)b->ctx.size();
+  bool stale = false;
+  for (pse_ctx *c : b->ctx) stale = stale || c->graph_stale;
+  if (stale) {
+    if (hipStreamSynchronize(b->gstream) != hipSuccess) return PSE_ERR_HIP;
+    free_graph(b);
+    const pse_status sc = batch_capture(b);
+    if (sc != PSE_OK) return sc;
+  }
+  if (hipStreamSynchronize(b->gstream) != hipSuccess) return PSE_ERR_HIP;  // the previous replay has read rng_h
+  for (int r = 0; r < R; ++r) {
+    b->rng_h[2 * r] = seed + (uint64_t)r;
+    b->rng_h[2 * r + 1] = counter;
+  }
+  // ordered after earlier work on the caller's stream, and later work there after it
+  if (hipEventRecord(b->g_in, b->user) != hipSuccess || hipStreamWaitEvent(b->gstream, b->g_in, 0) != hipSuccess ||
+      hipGraphLaunch(b->gexec, b->gstream) != hipSuccess || hipEventRecord(b->g_out, b->gstream) != hipSuccess ||
+      hipStreamWaitEvent(b->user, b->g_out, 0) != hipSuccess || hipStreamSynchronize(b->gstream) != hipSuccess)
+    return PSE_ERR_HIP;
+  pse_status w = PSE_OK;
+  int nredo = 0;
+  for (int r = 0; r < R; ++r) {
+    pse_ctx *c = b->ctx[r];
+    const bool real = c->p.kT > 0;
+    const LzView v = lz_view(c);
+    const bool halo_ovf = c->flags_h[7] != 0, list_ovf = c->flags_h[1] > c->nbr_cap;
+    const bool lz_bad = real && !(v.done && v.converged && !v.nonfinite);
+    const int fb = c->pc_on ? *c->pc_fb_h : 0;
+    if (halo_ovf || list_ovf || lz_bad || c->flags_h[0]) {
+      // this replica again, eagerly: capacities from its own positions, the
+      // Krylov loop continued as far as needed; the next step captures anew
+      ++nredo;
+      c->graph_stale = c->graph_stale || halo_ovf || list_ovf || lz_bad;
+      pse_status x = ctx_set_positions(c, b->g_pos[r]);
+      SampleState ss;
+      if (x == PSE_OK)
+        x = ctx_begin(c, seed + (uint64_t)r, counter, b->g_dt, b->g_forces.empty() ? nullptr : b->g_forces[r], ss);
+      if (x == PSE_OK && hipStreamSynchronize(c->stream) != hipSuccess) x = PSE_ERR_HIP;
+      if (x == PSE_OK) x = ctx_end(c, ss, b->g_dt, b->g_disp[r], stats ? &stats[r] : nullptr);
+      if (hipStreamSynchronize(c->stream) != hipSuccess) x = worse(x, PSE_ERR_HIP);
+      w = worse(w, x);
+      continue;
+    }
+    if (real) c->last_iters = v.m;
+    if (stats) {
+      pse_stats &o = stats[r];
+      o.lanczos_iters = real ? v.m : 0;
+      o.converged = 1;
+      o.lanczos_rel_change = real ? v.rel : 0.0;
+      o.max_neighbors = c->flags_h[5];
+      int64_t pairs;
+      std::memcpy(&pairs, c->flags_h + 2, sizeof pairs);
+      o.neighbor_pairs = pairs;
+      o.precond_fallbacks = fb;
+      o.nbr_index_bytes = c->lds_B ? 2 : 4;
+      o.lds_block_edge = c->lds_B;
+    }
+  }
+  if (redone) *redone = nredo;
+  return w;
+}
+
+pse_status pse_batch_graph_destroy(pse_batch *b) {
+  if (!b) return PSE_ERR_INVALID_ARG;
+  if (b->gstream && hipStreamSynchronize(b->gstream) != hipSuccess) return PSE_ERR_HIP;
+  free_graph(b);
   return PSE_OK;
 }
 

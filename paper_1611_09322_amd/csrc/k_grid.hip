@@ -404,6 +404,11 @@ __global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, 
   constexpr int NCOLS = 3 * TZ;
   __shared__ C<T> buf[M * NCOLS];
   __shared__ C<T> tw[M];
+  if (NOISE == 1 && wc.rng) {
+    // key and counter from device memory (a graph replayed per step)
+    wc.seed = wc.rng[0];
+    wc.counter = wc.rng[1];
+  }
   for (int i = threadIdx.x; i < M; i += BLOCK) tw[i] = tw_g[i];
   const size_t s_fft = (size_t)M * H, s_comp = (size_t)M * M * H;
   // adjacent z tiles share cache lines: keep them on one XCD
@@ -939,7 +944,7 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
       else if (nw == 2) go(std::integral_constant<int, 2>{});
       else go(std::integral_constant<int, 1>{});
     } else {
-      (void)hipMemsetAsync(grid_or_out, 0, sizeof(T) * 4 * (size_t)M * M * M, c->stream);
+      launch_zero_words(c->stream, grid_or_out, sizeof(T) * (size_t)M * M * M);  // 4 components
       k_spread<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T4 *)vec, n, (T *)grid_or_out, M,
                                                     (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)norm);
     }

@@ -387,7 +387,7 @@ __global__ void k_nbr_build(const typename vec4<T>::type *__restrict__ pos, cons
     f.w = T(0);
     frep[s] = f;
   }
-  cnt_out[s] = cnt;
+  cnt_out[s] = min(cnt, cap);  // entries stored; flags[1] carries the capacity needed
   }
   // total ordered pairs and the largest count: one set of atomics per wavefront
   const unsigned long long tot = wave_sum((unsigned long long)cnt);
@@ -617,6 +617,17 @@ __device__ __forceinline__ void halo_setup(const int *__restrict__ cell_start, i
   __syncthreads();
 }
 
+// The staged halo plus the zero-source slot fit the `hcap` records the
+// launch reserved.  A launch whose capacity was fixed in advance (a
+// captured graph replayed on new positions) may meet a larger halo: the
+// workgroup then stages nothing, raises *ovf and returns, and the caller
+// redoes that system with capacities sized for it.  Uniform per workgroup.
+template <int B> __device__ __forceinline__ bool halo_fits(const HaloTab<B> &ht, int hcap, int *ovf) {
+  const bool ok = ht.base[Halo<B>::NH] + 1 <= hcap;
+  if (!ok && threadIdx.x == 0) atomicOr(ovf, 1);
+  return ok;
+}
+
 // LDS index e -> halo cell (largest h with base[h] <= e).
 template <int B> __device__ __forceinline__ int halo_cell_of(const HaloTab<B> &ht, int e) {
   int lo = 0, hi = Halo<B>::NH;
@@ -704,7 +715,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
                                                  int nc, float cs, int n, float L, float invL, float rc2,
                                                  uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
                                                  int *__restrict__ flags, float contact, float krep,
-                                                 float4 *__restrict__ frep) {
+                                                 float4 *__restrict__ frep, int hcap) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   extern __shared__ float3 hpos3[];  // coordinates only
   __shared__ HaloTab<B> ht;
@@ -723,6 +734,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
     pack_tab[threadIdx.x] = make_uint4((uint32_t)pat, (uint32_t)(pat >> 32), (uint32_t)msk, (uint32_t)(msk >> 32));
   }
   halo_setup<B>(cell_start, nc, ht);
+  if (!halo_fits<B>(ht, hcap, flags + 7)) return;
   if (UNWRAP) {
     const int nb = (nc + B - 1) / B;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -813,7 +825,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
       }
       row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
     }
-    cnt_out[s] = k;
+    cnt_out[s] = min(k, cap);  // entries stored; flags[1] carries the capacity needed
     if (REP) frep[s] = make_float4(fx, fy, fz, 0.f);
     mine += (unsigned long long)k;
     mx = max(mx, k);
@@ -860,7 +872,8 @@ __global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__
                                                    int nc, float cs, int n, float L, float invL,
                                                    const uint16_t *__restrict__ nbr, const int *__restrict__ cnt,
                                                    const float2 *__restrict__ tab, float inv_dr, float inv_mu0,
-                                                   float fself, float a, float near2, uint16_t *__restrict__ feat) {
+                                                   float fself, float a, float near2, uint16_t *__restrict__ feat,
+                                                   int hcap, int *__restrict__ ovf) {
   constexpr int NH = Halo<B>::NH;
   constexpr int G = 3, GPW = 64 / G;
   extern __shared__ float4 hpos[];
@@ -869,6 +882,7 @@ __global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__
   __shared__ float2 ftab[kTableN];
   for (int k = threadIdx.x; k < kTableN; k += blockDim.x) ftab[k] = tab[k];
   halo_setup<B>(cell_start, nc, ht);
+  if (!halo_fits<B>(ht, hcap, ovf)) return;
   if (UNWRAP) {
     const int nb = (nc + B - 1) / B;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -987,7 +1001,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
                                                    const int *__restrict__ cnt, const float2 *__restrict__ tab,
                                                    float inv_dr, float self_r, float scale, float4 *__restrict__ out,
                                                    float4 *__restrict__ vm_out, LzState<A> *st, A *partials,
-                                                   unsigned *counter, const float4 *__restrict__ Pm = nullptr,
+                                                   unsigned *counter, int *__restrict__ ovf,
+                                                   const float4 *__restrict__ Pm = nullptr,
                                                    const float4 *__restrict__ rsrc = nullptr) {
   constexpr int NH = Halo<B>::NH;
   static_assert(G >= 2 && G <= 4, "lanes per target");
@@ -1005,7 +1020,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   }
   for (int k = threadIdx.x; k < kTableN; k += blockDim.x) tabs[k] = tab[k];
   halo_setup<B>(cell_start, nc, ht);
-  {
+  // a halo past the capacity stages nothing and computes no target, but
+  // the workgroup still takes part in the alpha reduction below (its
+  // counter must complete)
+  const bool fits = halo_fits<B>(ht, hcap, ovf);
+  if (fits) {
     const int nb = (nc + B - 1) / B;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
@@ -1041,7 +1060,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     }
   }
   __syncthreads();
-  const int ntarg = ht.tpre[ht.ntc];
+  const int ntarg = fits ? ht.tpre[ht.ntc] : 0;
   const float Ls = L * inv_dr, invLs = invL / inv_dr;  // box in table units
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / G, g = lane - grp * G;
@@ -1536,9 +1555,14 @@ template <> __device__ __forceinline__ void box_muller<float>(uint64_t wa, uint6
 // they straddle, of the next.
 template <typename T>
 __global__ void k_real_noise_sorted(const int *__restrict__ perm, int n, uint64_t seed, uint64_t sample,
-                                    typename vec4<T>::type *__restrict__ z) {
+                                    typename vec4<T>::type *__restrict__ z, const uint64_t *__restrict__ rng) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
+  if (rng) {
+    // key and counter from device memory (a graph replayed per step)
+    seed = rng[0];
+    sample = rng[1];
+  }
   const uint64_t e0 = 3ull * (uint64_t)perm[s];
   const uint64_t b0 = e0 >> 2;
   const int off = (int)(e0 & 3);
@@ -1566,14 +1590,31 @@ __global__ void k_real_noise_sorted(const int *__restrict__ perm, int n, uint64_
 // ----------------------------------------------------------- launchers
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
+__global__ void k_zero_words(uint32_t *__restrict__ p, size_t nw) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+void launch_zero_words(hipStream_t s, void *p, size_t nwords) {
+  if (!nwords) return;
+  const size_t b = (nwords + 255) / 256;
+  k_zero_words<<<(int)(b < 4096 ? b : 4096), 256, 0, s>>>((uint32_t *)p, nwords);
+}
+
+// a[0 .. na) = 0 and b[0 .. nb) = 0.
+__global__ void k_zero_i32(int *__restrict__ a, int na, int *__restrict__ b, int nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < na) a[i] = 0;
+  else if (i - na < nb) b[i - na] = 0;
+}
+
 template <typename T>
 void launch_bin(pse_ctx *c, const void *pos) {
   using T4 = typename vec4<T>::type;
   const int n = c->n;
   const T L = (T)c->d.L, invL = (T)(1.0 / c->d.L), inv_cs = (T)(1.0 / c->d.cs);
   ProfScope ps(c, PSE_STAGE_BIN);
-  (void)hipMemsetAsync(c->cell_count, 0, sizeof(int) * c->ncell, c->stream);
-  (void)hipMemsetAsync(c->flags, 0, sizeof(int) * 8, c->stream);
+  // a fill kernel rather than a memset: the same code runs under graph capture
+  k_zero_i32<<<nblk(c->ncell + 8, 256), 256, 0, c->stream>>>(c->cell_count, c->ncell, c->flags, 8);
   k_wrap_bin<T><<<nblk(n, 256), 256, 0, c->stream>>>((const T *)pos, n, L, invL, inv_cs, c->d.nc, (T4 *)c->pos_w,
                                                      c->cell_of, c->cell_count, c->flags);
   k_scan_cells<<<1, 1024, 0, c->stream>>>(c->cell_count, c->cell_start, c->cell_count + c->ncell, c->ncell);
@@ -1658,7 +1699,8 @@ void launch_nbr_lds(pse_ctx *c) {
     allow_lds(kern, smem);
     kern<<<c->lds_blocks, 512, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc, (float)c->d.cs,
                                                   c->n, L, invL, rc2, nb, c->nbr_cnt, c->nbr_cap, c->flags,
-                                                  (float)(2.0 * c->p.a), (float)c->rep_k, (float4 *)c->vbuf[kRepBuf]);
+                                                  (float)(2.0 * c->p.a), (float)c->rep_k, (float4 *)c->vbuf[kRepBuf],
+                                                  c->hcap);
   };
   const bool rep = c->rep_k > 0;
   with_block_edge(c->lds_B, [&](auto b) {
@@ -1686,7 +1728,7 @@ void launch_feat_lds(pse_ctx *c) {
     kern<<<c->lds_blocks, kFeatNT, smem, c->stream>>>((const float4 *)c->pos_s, c->cell_start, c->d.nc,
                                                      (float)c->d.cs, c->n, L, invL, (const uint16_t *)c->nbr, c->nbr_cnt,
                                                   (const float2 *)c->table, (float)(kTableK / c->p.rcut), inv_mu0,
-                                                  fself, (float)c->p.a, near2, c->pc_feat);
+                                                  fself, (float)c->p.a, near2, c->pc_feat, c->hcap, c->flags + 7);
   };
   with_block_edge(c->lds_B, [&](auto b) {
     constexpr int BE = decltype(b)::value;
@@ -1708,7 +1750,8 @@ static void spmv_lds(pse_ctx *c, const float4 *src, float4 *out, float4 *vm_out,
     kernel<<<c->lds_blocks, 1024, smem, c->stream>>>((const float4 *)c->pos_s, src, c->cell_start, c->d.nc,
                                                       (float)c->d.cs, c->n, c->hcap, L, invL, nb, c->nbr_cnt,
                                                       c->table, inv_dr, self_r, 1.0f, out, vm_out, st,
-                                                      (A *)c->partials, c->counter, (const float4 *)c->pc_P, rsrc);
+                                                      (A *)c->partials, c->counter, c->flags + 7,
+                                                      (const float4 *)c->pc_P, rsrc);
   };
   auto pick = [&](auto g) {
     constexpr int G = decltype(g)::value;
@@ -1939,7 +1982,7 @@ template <typename T>
 void launch_real_noise(pse_ctx *c, void *z_sorted, uint64_t seed, uint64_t sample) {
   ProfScope ps(c, PSE_STAGE_NOISE);
   k_real_noise_sorted<T><<<nblk(c->n, 256), 256, 0, c->stream>>>(c->perm, c->n, seed, sample,
-                                                                  (typename vec4<T>::type *)z_sorted);
+                                                                  (typename vec4<T>::type *)z_sorted, c->rng_dev);
 }
 
 #define INST_T(T)                                                                                  \

@@ -18,6 +18,8 @@ struct ProfScope {
 
 // particle side (k_particles.hip)
 template <typename T> void launch_bin(pse_ctx *c, const void *pos);
+// nwords 32-bit words of p set to 0 by a kernel (capturable in a graph)
+void launch_zero_words(hipStream_t s, void *p, size_t nwords);
 template <typename T> void launch_nbr(pse_ctx *c);
 // LDS-staged near-field path (FP32): halo sizes into flags[4] for block edge B;
 // neighbour build with 16-bit LDS indices

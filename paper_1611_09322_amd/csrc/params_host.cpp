@@ -10,7 +10,7 @@
 // xi with every source within its share of the tolerance.
 #include <algorithm>
 #include <cmath>
-#include <thread>
+#include <map>
 #include <vector>
 
 #include "pse_internal.hpp"
@@ -51,7 +51,7 @@ double window_error(double eps_quad, double eps_alias) { return 3.0 * eps_quad +
 // [rc, rc + 12 / xi].
 void real_tail(double rc, double xi, double a, double rho, double *inc, double *coh) {
   const double zero[kSeriesTerms] = {};  // the series serves r < 0.3a only
-  const int nq = 400;
+  const int nq = 400;  // even: Simpson's rule
   const double hi = rc + 12.0 / xi, dr = (hi - rc) / nq;
   double s2 = 0.0, s1 = 0.0;
   for (int q = 0; q <= nq; ++q) {
@@ -78,12 +78,40 @@ double rcut_for(double tol, double xi, double a, double rho, bool coherent, doub
   double lo = 2.0 * a, hi = rc_max;
   if (!(lo < hi) || tail(hi) > tol) return INFINITY;
   if (tail(lo) <= tol) return lo;
-  for (int it = 0; it < 60; ++it) {
+  for (int it = 0; it < 40 && hi - lo > 1e-9 * rc_max; ++it) {
     const double mid = 0.5 * (lo + hi);
     if (tail(mid) > tol) lo = mid;
     else hi = mid;
   }
   return hi;
+}
+
+// rcut_for to about 1e-4 of rc, for scanning many xi: the tail integral
+// accumulated once from the top of [2a, rc_max + 12 / xi] on a step of
+// 0.02 / xi (trapezoid), its crossing of tol interpolated.
+double rcut_scan(double tol, double xi, double a, double rho, bool coherent, double rc_max) {
+  const double zero[kSeriesTerms] = {};
+  const double lo = 2.0 * a;
+  if (!(lo < rc_max)) return INFINITY;
+  const double dr = 0.02 / xi, top = rc_max + 12.0 / xi;
+  const int n = (int)std::ceil((top - lo) / dr) + 1;
+  std::vector<double> g(n), C(n);
+  for (int i = 0; i < n; ++i) {
+    const double r = lo + i * dr;
+    double F, G;
+    fg_eval_host(r, xi, a, zero, zero, &F, &G);
+    g[i] = 4.0 * kPi * r * r * (coherent ? std::fabs(2.0 * F + G) : 2.0 * F * F + G * G) / 3.0;
+  }
+  C[n - 1] = 0.0;
+  for (int i = n - 2; i >= 0; --i) C[i] = C[i + 1] + 0.5 * dr * (g[i] + g[i + 1]);
+  auto tail = [&](int i) { return coherent ? rho * C[i] : std::sqrt(rho * C[i]); };
+  const int imax = (int)std::floor((rc_max - lo) / dr);
+  if (tail(imax) > tol) return INFINITY;
+  if (tail(0) <= tol) return lo;
+  int i = 1;
+  while (tail(i) > tol) ++i;  // tail decreases with r; tail(imax) <= tol ends the scan
+  const double t0 = std::log(tail(i - 1)), t1 = std::log(std::max(tail(i), 1e-300)), lt = std::log(tol);
+  return lo + (i - 1 + (t0 - lt) / (t0 - t1)) * dr;
 }
 
 // Smallest kc with eps_wave_bound(kc) <= tol (the bound decreases with kc).
@@ -113,50 +141,58 @@ double kcut_for(double tol, double xi, double a) {
 // at the midpoints of blocks of s consecutive indices (s = ceil(M / 96)),
 // each weighted by its index count.  Returns the relative error (the square
 // root).
-double alias_estimate(double L, int M, double xi, double a, double sigma, int max_freq) {
+AliasWeights::AliasWeights(double L_, int M_, double xi, double a, int max_freq) : L(L_), M(M_) {
   const int H = M / 2;  // signed indices 0 .. H - 1 per axis (Nyquist excluded)
   const int s = std::max(1, (M + max_freq - 1) / max_freq);
-  const int nq = (H + s - 1) / s;
-  std::vector<double> k(nq), wt(nq), f1(nq);
-  const double dk = 2.0 * kPi / L, h = L / M, s2 = sigma * sigma;
+  nq = (H + s - 1) / s;
+  k.resize(nq);
+  std::vector<double> wt(nq);
+  const double dk = 2.0 * kPi / L;
   for (int q = 0; q < nq; ++q) {
     const int j0 = q * s, j1 = std::min(H, j0 + s);
     const double jm = s == 1 ? (double)j0 : 0.5 * (j0 + j1 - 1);
     k[q] = jm * dk;
     // +-j for j > 0, j = 0 once
     wt[q] = 2.0 * (j1 - j0) - (j0 == 0 ? 1.0 : 0.0);
-    const double g = 2.0 * kPi / h;
+  }
+  // B(k) times the index multiplicities, over the octant (the sigma-free part)
+  const double inv4x2 = 1.0 / (4.0 * xi * xi);
+  w.assign((size_t)nq * nq * nq, 0.0);
+  sum = 0.0;
+  for (int qx = 0; qx < nq; ++qx)
+    for (int qy = 0; qy < nq; ++qy)
+      for (int qz = 0; qz < nq; ++qz) {
+        const double k2 = k[qx] * k[qx] + k[qy] * k[qy] + k[qz] * k[qz];
+        if (k2 <= 0.0) continue;
+        const double kk = std::sqrt(k2), ka = kk * a;
+        const double sinc = std::sin(ka) / ka;
+        const double B = sinc * sinc * (1.0 + k2 * inv4x2) * std::exp(-k2 * inv4x2) / k2;
+        const double v = wt[qx] * wt[qy] * wt[qz] * B;
+        w[((size_t)qx * nq + qy) * nq + qz] = v;
+        sum += v;
+      }
+}
+
+double AliasWeights::estimate(double sigma) const {
+  const double h = L / M, s2 = sigma * sigma, g = 2.0 * kPi / h;
+  std::vector<double> f1(nq);
+  for (int q = 0; q < nq; ++q) {
     const double rm = std::exp(-s2 * ((k[q] - g) * (k[q] - g) - k[q] * k[q]));
     const double rp = std::exp(-s2 * ((k[q] + g) * (k[q] + g) - k[q] * k[q]));
     f1[q] = 1.0 + rm + rp;
   }
-  const double inv4x2 = 1.0 / (4.0 * xi * xi);
-  const int nth = std::max(1, std::min(8, nq));
-  std::vector<double> num(nth, 0.0), den(nth, 0.0);
-  auto work = [&](int t) {
-    for (int qx = t; qx < nq; qx += nth)
-      for (int qy = 0; qy < nq; ++qy)
-        for (int qz = 0; qz < nq; ++qz) {
-          const double k2 = k[qx] * k[qx] + k[qy] * k[qy] + k[qz] * k[qz];
-          if (k2 <= 0.0) continue;
-          const double kk = std::sqrt(k2), ka = kk * a;
-          const double sinc = std::sin(ka) / ka;
-          const double B = sinc * sinc * (1.0 + k2 * inv4x2) * std::exp(-k2 * inv4x2) / k2;
-          const double w = wt[qx] * wt[qy] * wt[qz] * B;
-          den[t] += w;
-          num[t] += w * (f1[qx] * f1[qy] * f1[qz] - 1.0);
-        }
-  };
-  std::vector<std::thread> th;
-  for (int t = 1; t < nth; ++t) th.emplace_back(work, t);
-  work(0);
-  for (auto &x : th) x.join();
-  double N = 0.0, D = 0.0;
-  for (int t = 0; t < nth; ++t) {
-    N += num[t];
-    D += den[t];
-  }
-  return D > 0.0 ? std::sqrt(std::max(N, 0.0) / D) : 0.0;
+  double N = 0.0;
+  for (int qx = 0; qx < nq; ++qx)
+    for (int qy = 0; qy < nq; ++qy) {
+      const double fxy = f1[qx] * f1[qy];
+      const double *row = &w[((size_t)qx * nq + qy) * nq];
+      for (int qz = 0; qz < nq; ++qz) N += row[qz] * (fxy * f1[qz] - 1.0);
+    }
+  return sum > 0.0 ? std::sqrt(std::max(N, 0.0) / sum) : 0.0;
+}
+
+double alias_estimate(double L, int M, double xi, double a, double sigma, int max_freq) {
+  return AliasWeights(L, M, xi, a, max_freq).estimate(sigma);
 }
 
 // FFT lengths with a plan: 2^k and 3 x 2^k from 16 to 512.
@@ -249,7 +285,7 @@ pse_status choose_params(const pse_params &base, const pse_tuning &tin, pse_para
   };
   std::vector<Cand> cands;
   for (double xi : xis) {
-    const double rc = rcut_for(ts, xi, a, dens, t.deterministic != 0, 0.499 * L);
+    const double rc = rcut_scan(ts, xi, a, dens, t.deterministic != 0, 0.499 * L);
     if (!(rc < 0.5 * L)) continue;
     // ordered pairs at the mean density (hard-sphere structure, d_f = 3)
     const double pairs = n * dens * 4.0 / 3.0 * kPi * rc * rc * rc;
@@ -265,6 +301,17 @@ pse_status choose_params(const pse_params &base, const pse_tuning &tin, pse_para
     }
   }
   std::sort(cands.begin(), cands.end(), [](const Cand &u, const Cand &v) { return u.cost < v.cost; });
+  // B(k) weights of the aliasing estimate per (xi, M): coarse (32
+  // frequencies per axis, for the width search) and full (96, to confirm)
+  std::map<std::pair<double, int>, AliasWeights> coarse_cache, fine_cache;
+  auto weights = [&](std::map<std::pair<double, int>, AliasWeights> &cache, double xi, int M,
+                     int nf) -> const AliasWeights & {
+    auto key = std::make_pair(xi, M);
+    auto it = cache.find(key);
+    if (it == cache.end()) it = cache.emplace(key, AliasWeights(L, M, xi, a, nf)).first;
+    return it->second;
+  };
+  auto coarse = [&](double xi, int M) -> const AliasWeights & { return weights(coarse_cache, xi, M, 32); };
   double best = 1e300;
   pse_params bp = base;
   pse_tuning_info bi{};
@@ -285,9 +332,11 @@ pse_status choose_params(const pse_params &base, const pse_tuning &tin, pse_para
     const double tw = ts - eps_wave_bound(kPi / h, xi, a);
     // the search runs on a coarser sub-lattice (at most 32 frequencies per
     // axis); the width found is confirmed with the full estimate below
+    // the B(k) weights of the coarse estimate, once per (xi, M)
+    const AliasWeights &aw = coarse(cd.xi, M);
     auto total = [&](double m, double *e1, double *e2) {
       *e1 = eps_quad_bound(P, m);
-      *e2 = w * window_error(*e1, 0.0) > tw ? 1.0 : alias_estimate(L, M, xi, a, P * h / (2 * m), 32);
+      *e2 = w * window_error(*e1, 0.0) > tw ? 1.0 : aw.estimate(P * h / (2 * m));
       return w * window_error(*e1, *e2);
     };
     double e0q, e0a, mk = 0.0, eq = 0.0, al = 0.0;
@@ -326,22 +375,26 @@ pse_status choose_params(const pse_params &base, const pse_tuning &tin, pse_para
       }
     }
     if (mk == 0.0) continue;
-    al = alias_estimate(L, M, xi, a, P * h / (2 * mk));
+    al = weights(fine_cache, xi, M, 96).estimate(P * h / (2 * mk));
     if (w * window_error(eq, al) > tw) continue;
     best = cd.cost;
     bp = base;
     bp.xi = xi;
-    bp.rcut = cd.rc;
+    // the cutoff of the scan, refined on the tail estimate derive_params reports
+    {
+      const double r1 = rcut_for(ts, xi, a, dens, t.deterministic != 0, std::min(0.499 * L, cd.rc * 1.01 + 0.05));
+      bp.rcut = std::isfinite(r1) ? r1 : cd.rc;
+    }
     bp.grid = M;
     bp.support = P;
     bp.gauss_m = mk == m0 ? 0.0 : mk;
     bp.lanczos_tol = ts;
     bp.tol = t.tol;
     bi.model_seconds = cd.cost;
-    bi.eps_real = std::exp(-xi * xi * cd.rc * cd.rc);
+    bi.eps_real = std::exp(-xi * xi * bp.rcut * bp.rcut);
     {
       double inc, coh;
-      real_tail(cd.rc, xi, a, dens, &inc, &coh);
+      real_tail(bp.rcut, xi, a, dens, &inc, &coh);
       bi.eps_real_tail = t.deterministic ? coh : inc;
     }
     bi.eps_wave = eps_wave_bound(kPi / h, xi, a);

@@ -112,6 +112,7 @@ struct WaveCoef {
   double w_scale;        // M^{-3/2}: grid noise DFT normalisation
   uint64_t seed, counter;
   int use_philox;        // noise from Philox (key (seed,1))
+  const uint64_t *rng;   // device (seed, counter) read in place of the two above, or null
 };
 
 // ---------------------------------------------------------------- host side
@@ -139,6 +140,16 @@ double eps_quad_bound(int P, double m);
 double kcut_for(double tol, double xi, double a);
 // (sums on blocks of indices above max_freq frequencies per axis)
 double alias_estimate(double L, int M, double xi, double a, double sigma, int max_freq = 96);
+// The sigma-free part of alias_estimate (B(k) over the sampled octant),
+// reusable across window widths.
+struct AliasWeights {
+  double L;
+  int M, nq;
+  std::vector<double> k, w;
+  double sum;
+  AliasWeights(double L, int M, double xi, double a, int max_freq);
+  double estimate(double sigma) const;
+};
 pse_status choose_params(const pse_params &base, const pse_tuning &t, pse_params *out, pse_tuning_info *info);
 // learned-preconditioner training targets (precond_host.cpp); false if a
 // patch matrix is not positive definite
@@ -159,6 +170,14 @@ struct pse_ctx {
   int n = 0;
   int ncell = 0;
   bool have_pos = false;
+  // graph mode (a batch step captured once, replayed per step): no host
+  // decision inside set_positions or the sample; capacities fixed at
+  // capture, overflows flagged on the device (flags[7], flags[1]) and the
+  // replica redone after the replay
+  bool graph = false;
+  int graph_iters = 0;              // Lanczos iterations queued per sample in graph mode
+  const uint64_t *rng_dev = nullptr;  // device (seed, counter) of the Philox noise, or null
+  bool graph_stale = false;         // a buffer the captured graph uses was reallocated
   int last_iters = 4;
   int lz_maxit = 0;         // near-field Lanczos iterations at most: min(lanczos_max_iter, kMaxIter)
   // full-mobility Krylov sample (PSE_FLAG_FULL_LANCZOS)

@@ -108,3 +108,88 @@ def test_batch_with_a_preconditioned_replica(gpu_lib):
         assert st[r].lanczos_iters == st1.lanczos_iters and st[r].precond_fallbacks == st1.precond_fallbacks
         one.close()
     b.close()
+
+
+def _eager_reference(gpu_lib, systems, pos, F, seed, counter):
+    """The same replicas stepped eagerly by a batch of their own."""
+    import torch
+
+    b = gpu_lib.Batch([s["spec"] for s in systems])
+    b.set_positions(pos)
+    out, st = b.sample(seed, counter, dt=0.01, forces=F)
+    torch.cuda.synchronize()
+    return b, [o.clone() for o in out], st
+
+
+def test_graph_replay_equals_eager_steps(gpu_lib, systems):
+    """A captured batch step (pse_batch_graph_*) replayed with new counters
+    and with the positions moved in place between replays: every replay
+    equals the eager step with the same key and counter (bit for bit while
+    the block edge stays that of the capture), and no replica is redone."""
+    import torch
+
+    b = gpu_lib.Batch([s["spec"] for s in systems])
+    dts = [torch.float64 if s["spec"]["precision"] == "fp64" else torch.float32 for s in systems]
+    pos = [torch.as_tensor(s["x"], dtype=dt, device="cuda") for s, dt in zip(systems, dts)]
+    F = [torch.as_tensor(synth.normals(80 + r, (s["spec"]["n"], 3)), dtype=dt, device="cuda")
+         for r, (s, dt) in enumerate(zip(systems, dts))]
+    out = [torch.empty_like(p) for p in pos]
+    b.graph_create(pos, out, 0.01, forces=F, extra_iters=4, headroom=0.25)
+    ref_b = None
+    for step, counter in enumerate((11, 12, 13)):
+        if step == 2:
+            # move every particle a little, in place (the graph reads the same buffers)
+            for r, p in enumerate(pos):
+                p.add_(torch.as_tensor(0.05 * synth.normals(90 + r, tuple(p.shape)), dtype=p.dtype, device="cuda"))
+        status, st, redone = b.graph_step(5, counter)
+        torch.cuda.synchronize()
+        got = [o.clone() for o in out]
+        ref_b, ref, st_e = _eager_reference(gpu_lib, systems, pos, F, 5, counter)
+        print(f"step {step}: redone {redone}, iterations {[s.lanczos_iters for s in st]}, "
+              f"block edges {[s.lds_block_edge for s in st]} / eager {[s.lds_block_edge for s in st_e]}", flush=True)
+        assert redone == 0
+        for r in range(len(systems)):
+            if st[r].lds_block_edge == st_e[r].lds_block_edge:
+                assert torch.equal(got[r], ref[r]), (step, r)
+            else:
+                check(got[r].double().cpu().numpy(), ref[r].double().cpu().numpy(), 1e-6, f"replica {r}")
+            assert st[r].lanczos_iters == st_e[r].lanczos_iters
+        ref_b.close()
+    b.graph_destroy()
+    b.close()
+
+
+def test_graph_replay_redoes_overflowing_replicas(gpu_lib, systems):
+    """Captured with no headroom; then 300 spheres of one replica are
+    gathered into a dense lattice: its neighbour list and the halo of the
+    blocks around the lattice outgrow the captured capacities, the kernels
+    skip that work and flag it, and the step redoes the replica eagerly;
+    every result equals the eager step.  The next replay captures anew and
+    needs no redo."""
+    import torch
+
+    b = gpu_lib.Batch([s["spec"] for s in systems])
+    dts = [torch.float64 if s["spec"]["precision"] == "fp64" else torch.float32 for s in systems]
+    pos = [torch.as_tensor(s["x"], dtype=dt, device="cuda") for s, dt in zip(systems, dts)]
+    out = [torch.empty_like(p) for p in pos]
+    b.graph_create(pos, out, 0.01, extra_iters=2, headroom=0.0)
+    # 300 spheres of the dilute replica (volume fraction 0.05, 7 cells per
+    # side) on a simple cubic lattice of spacing 2.05a: a local volume
+    # fraction near 0.5, about ten times the neighbours per sphere
+    g = np.arange(7, dtype=np.float64)
+    lat = 2.05 * np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)[:300]
+    x3 = systems[3]["x"].copy()
+    x3[:300] = x3[0] + lat
+    pos[3].copy_(torch.as_tensor(x3, dtype=pos[3].dtype, device="cuda"))
+    for counter, want_redo in ((21, True), (22, False)):
+        status, st, redone = b.graph_step(9, counter)
+        torch.cuda.synchronize()
+        got = [o.clone() for o in out]
+        ref_b, ref, st_e = _eager_reference(gpu_lib, systems, pos, None, 9, counter)
+        print(f"counter {counter}: redone {redone}, iterations {[s.lanczos_iters for s in st]}", flush=True)
+        assert (redone == 1) if want_redo else (redone == 0)
+        for r in range(len(systems)):
+            assert torch.equal(got[r], ref[r]), (counter, r)
+        ref_b.close()
+    b.graph_destroy()
+    b.close()
