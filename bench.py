@@ -38,6 +38,10 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFS = 157.3
 SPMV_FLOPS_PER_PAIR = 35
 REF_TOL = 1e-7
+# work-model constants of this implementation measured on MI355X at the
+# default workload (two significant digits): the tuned parameters follow
+# from them reproducibly
+WORK_CONSTS = [2.1e-12, 1.1e-12, 1.5e-12, 4.2e-10]
 # HBM bytes per launch of the near-field product, from rocprofv3 FETCH_SIZE
 # and WRITE_SIZE passes scaled by the same counters on a copy of known size;
 # the summary records the hash of the kernel source and the workload.
@@ -745,6 +749,12 @@ def main():
     ap.add_argument("--gel-train-rows", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--consts", type=lambda v: [float(t) for t in v.split(",")], default=WORK_CONSTS,
+                    help="work-model constants c_pair,c_node,c_fft,c_particle (s per pair-product, per "
+                         "particle-node, per M^3 log2 M^3, per particle) for the tuned parameters; default: "
+                         "measured on MI355X at this workload (the run measures them again and reports both)")
+    ap.add_argument("--measure-consts", action="store_true",
+                    help="tune with the constants measured in this run instead of --consts")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 512 MiB elementwise copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -782,11 +792,13 @@ def main():
             log(f"variant {key}: warmup {args.warmup}, steps {args.steps}")
             runs[key] = run_variant(pse, torch, x, F, args, key, plist[key], weights_for(plist[key]))
             log(f"variant {key}: {json.dumps(runs[key])}")
-    consts = None
+    consts, measured = None, None
     if not args.no_tuned:
         ref_run = runs.get("fp32@default") or next(iter(runs.values()), None)
-        if ref_run:
-            consts = measured_constants(ref_run, n, default)
+        measured = measured_constants(ref_run, n, default) if ref_run else None
+        consts = dict(zip(("c_pair", "c_node", "c_fft", "c_particle"), args.consts))
+        if args.measure_consts and measured:
+            consts = measured
         for v in names:
             key = f"{v}@tuned"
             niter = runs.get(f"{v}@default", {}).get("lanczos_iters_mean", 5.0)
@@ -863,7 +875,7 @@ def main():
                                                "precond_fallbacks", "autotune", "breakdown_ms", "error", "model",
                                                "kernels", "neighbor_pairs") if kk in v}
                      for k, v in runs.items()},
-        "work_model_constants": consts,
+        "work_model_constants": {"used": consts, "measured_this_run": measured if not args.no_tuned else None},
         "precond_training": [{"xi": k[0], "rc": k[1], "boxes": args.train_boxes, "n": args.train_n,
                               "rows_per_box": args.train_rows, "epochs": args.train_epochs,
                               "loss_first": h[0], "loss_last": h[-1]} for k, (_, h) in trained.items()],

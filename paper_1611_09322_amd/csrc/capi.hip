@@ -805,7 +805,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   // partial sums: one per block of the widest reduction (256-particle
   // blocks, or one per LDS target block of edge 1 cell)
   const size_t nparts = std::max<size_t>(std::max<size_t>(kRedBlock, (n + 255) / 256), (size_t)c->ncell);
-  c->partials = al.dev(A * nparts);
+  c->partials = al.dev(A * (nparts + kRedBlock));  // + the alpha partial sums of a Lanczos step
   c->counter = (unsigned *)al.dev(sizeof(unsigned));
   const size_t M3 = (size_t)p->grid * p->grid * p->grid;
   c->grid = al.dev(3 * T * M3);

@@ -982,8 +982,8 @@ __global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__
 
 // Near-field product from the staged halo.  The halo is packed as
 // (x, y, z, v_x) + (v_y, v_z) (24 bytes per particle) together with the F/G
-// table (mu0 F, mu0 (G - F) and their forward differences, one 16-byte read
-// per pair).  G lanes per target (lane q of the group takes neighbour chunks
+// table (mu0 F, mu0 (G - F) at nodes rc / 2048 apart; two 8-byte reads per
+// pair for the linear interpolation).  G lanes per target (lane q of the group takes neighbour chunks
 // q, q + G, ...; 64 / G groups per wavefront; 3 unless pse_autotune picks 2
 // or 4) are combined with lane shuffles; each chunk of 8 neighbours is processed branch-free in two
 // halves of 4 (padding entries read the zero source), the LDS reads of a half
@@ -991,18 +991,19 @@ __global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__
 // workgroups share a compute unit: one stages its halo while the other
 // computes.  With UNWRAP the staged positions are the images nearest the
 // block centre.
+// With LZ (a Lanczos step) the epilogue scales by 1 / beta_m and stores the
+// basis vector v_m; alpha_m = <v_m, out> is formed by the update step.
 // With PC (Lanczos on A = P M_r P^T): src holds u = P^T r, and the
-// epilogue forms out = P (M_r u) / beta, v_m = r / beta (r from rsrc) and
-// alpha_m = <v_m, out>; Pm holds the rows of P_i as (x, y, z, 0).
+// epilogue forms out = P (M_r u) / beta and v_m = r / beta (r from rsrc);
+// Pm holds the rows of P_i as (x, y, z, 0).
 template <int B, bool UNWRAP, typename A, bool LZ, bool PC = false, int G = 3>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
                                                    const int *__restrict__ cell_start, int nc, float cs, int n,
                                                    int hcap, float L, float invL, const uint16_t *__restrict__ nbr,
                                                    const int *__restrict__ cnt, const float2 *__restrict__ tab,
                                                    float inv_dr, float self_r, float scale, float4 *__restrict__ out,
-                                                   float4 *__restrict__ vm_out, LzState<A> *st, A *partials,
-                                                   unsigned *counter, int *__restrict__ ovf,
-                                                   const float4 *__restrict__ Pm = nullptr,
+                                                   float4 *__restrict__ vm_out, const LzState<A> *st,
+                                                   int *__restrict__ ovf, const float4 *__restrict__ Pm = nullptr,
                                                    const float4 *__restrict__ rsrc = nullptr) {
   constexpr int NH = Halo<B>::NH;
   static_assert(G >= 2 && G <= 4, "lanes per target");
@@ -1012,17 +1013,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   float2 *hB = (float2 *)(smem + hcap);     // (v_y, v_z)
   __shared__ float2 tabs[kTableN];
   __shared__ HaloTab<B> ht;
-  __shared__ A sh[16];
-  __shared__ int last;
   if (LZ) {
     if (st->done) return;
     scale = (float)st->inv_beta;
   }
   for (int k = threadIdx.x; k < kTableN; k += blockDim.x) tabs[k] = tab[k];
   halo_setup<B>(cell_start, nc, ht);
-  // a halo past the capacity stages nothing and computes no target, but
-  // the workgroup still takes part in the alpha reduction below (its
-  // counter must complete)
+  // a halo past the capacity stages nothing and computes no target
   const bool fits = halo_fits<B>(ht, hcap, ovf);
   if (fits) {
     const int nb = (nc + B - 1) / B;
@@ -1065,7 +1062,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / G, g = lane - grp * G;
   const bool ingrp = grp < GPW;
-  A dot = 0;
+  
   for (int i0 = 0; i0 < ntarg; i0 += (int)(blockDim.x >> 6) * GPW) {
     const int i = i0 + wave * GPW + grp;
     const bool act = ingrp && i < ntarg;
@@ -1161,29 +1158,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
         u4 = make_float4(vx * scale, vy * scale, vz * scale, 0.0f);
       }
       out[s] = make_float4(sx, sy, sz, 0.0f);
-      if (LZ) {
-        vm_out[s] = u4;
-        dot += (A)u4.x * (A)sx + (A)u4.y * (A)sy + (A)u4.z * (A)sz;
-      }
-    }
-  }
-  if (!LZ) return;
-  const A bs = block_sum(dot, sh);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = bs;
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    A vv = 0;
-    for (int t = threadIdx.x; t < (int)gridDim.x; t += blockDim.x) vv += partials[t];
-    vv = block_sum(vv, sh);
-    if (threadIdx.x == 0) {
-      st->alpha[st->m] = vv;
-      *counter = 0u;
+      if (LZ) vm_out[s] = u4;
     }
   }
 }
@@ -1220,14 +1195,50 @@ __global__ void k_lz_init(const A *__restrict__ partials, int nparts, LzState<A>
 
 // w = t - alpha_m v_m - beta_m v_{m-1}, one particle (x, y, z, 0) per
 // step; block partials of |w|^2.
+// alpha_m = <v_m, t> of the step.  k_lz_alpha_part writes block partial
+// sums; lz_alpha (inside the update kernels) adds them in a fixed order in
+// every block, and block 0 stores alpha_m.  Computed here rather than in
+// the LDS product's epilogue: without the reduction the product needs no
+// register spills (64 VGPRs), which costs far more than this extra pass
+// over two vectors.
+template <typename T, typename A>
+__global__ void k_lz_alpha_part(const typename vec4<T>::type *__restrict__ t,
+                                const typename vec4<T>::type *__restrict__ vm, int n, const LzState<A> *st,
+                                A *__restrict__ partials) {
+  __shared__ A sh[16];
+  if (st->done) return;
+  A v = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const auto a = t[i], b = vm[i];
+    v += (A)a.x * (A)b.x + (A)a.y * (A)b.y + (A)a.z * (A)b.z;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+template <typename A> __device__ A lz_alpha(LzState<A> *st, const A *apart, int napart, A *sh) {
+  __shared__ A alpha_s;
+  if (!apart) return st->alpha[st->m];
+  A v = 0;
+  for (int i = threadIdx.x; i < napart; i += blockDim.x) v += apart[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    alpha_s = v;
+    if (blockIdx.x == 0) st->alpha[st->m] = v;
+  }
+  __syncthreads();
+  return alpha_s;
+}
+
 template <typename T, typename A>
 __global__ void k_lz_update(const typename vec4<T>::type *__restrict__ t, const typename vec4<T>::type *__restrict__ vm,
                             const typename vec4<T>::type *__restrict__ vprev, typename vec4<T>::type *__restrict__ w,
-                            int n, LzState<A> *st, A *__restrict__ partials) {
+                            int n, LzState<A> *st, A *__restrict__ partials, const A *__restrict__ apart = nullptr,
+                            int napart = 0) {
   __shared__ A sh[16];
   if (st->done) return;
   const int m = st->m;
-  const T al = (T)st->alpha[m];
+  const T al = (T)lz_alpha(st, apart, napart, sh);
   const T be = m > 0 ? (T)st->beta[m] : T(0);
   A v = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1257,11 +1268,12 @@ __global__ void k_lz_update_pc(const typename vec4<T>::type *__restrict__ t,
                                const typename vec4<T>::type *__restrict__ vm,
                                const typename vec4<T>::type *__restrict__ vprev, typename vec4<T>::type *__restrict__ w,
                                const T *__restrict__ P, typename vec4<T>::type *__restrict__ u, int n,
-                               LzState<A> *st, A *__restrict__ partials) {
+                               LzState<A> *st, A *__restrict__ partials, const A *__restrict__ apart = nullptr,
+                               int napart = 0) {
   __shared__ A sh[16];
   if (st->done) return;
   const int m = st->m;
-  const T al = (T)st->alpha[m];
+  const T al = (T)lz_alpha(st, apart, napart, sh);
   const T be = m > 0 ? (T)st->beta[m] : T(0);
   A v = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1750,8 +1762,7 @@ static void spmv_lds(pse_ctx *c, const float4 *src, float4 *out, float4 *vm_out,
     kernel<<<c->lds_blocks, 1024, smem, c->stream>>>((const float4 *)c->pos_s, src, c->cell_start, c->d.nc,
                                                       (float)c->d.cs, c->n, c->hcap, L, invL, nb, c->nbr_cnt,
                                                       c->table, inv_dr, self_r, 1.0f, out, vm_out, st,
-                                                      (A *)c->partials, c->counter, c->flags + 7,
-                                                      (const float4 *)c->pc_P, rsrc);
+                                                      c->flags + 7, (const float4 *)c->pc_P, rsrc);
   };
   auto pick = [&](auto g) {
     constexpr int G = decltype(g)::value;
@@ -1891,7 +1902,15 @@ void launch_lz_iter(pse_ctx *c, int m, const void *z) {
   prof_end(c, PSE_STAGE_SPMV);
   const T4 *vprev = m > 0 ? V + (size_t)(m - 1) * n : V;
   ProfScope ps(c, PSE_STAGE_LANCZOS);
-  k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * n, vprev, w, n, st, (A *)c->partials);
+  if (sizeof(T) == 4 && c->lds_B) {
+    // the LDS product leaves alpha_m to its own pass
+    A *ap = (A *)c->partials + kRedBlock;
+    k_lz_alpha_part<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * n, n, st, ap);
+    k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * n, vprev, w, n, st, (A *)c->partials,
+                                                        ap, kRedBlock);
+  } else {
+    k_lz_update<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * n, vprev, w, n, st, (A *)c->partials);
+  }
   k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, st, (A)c->p.lanczos_tol,
                                          c->lz_maxit);
 }
@@ -1924,8 +1943,11 @@ void launch_lz_iter_pc(pse_ctx *c, int m, const void *z) {
       }
       ProfScope ps(c, PSE_STAGE_LANCZOS);
       const T4 *vprev = m > 0 ? V + (size_t)(m - 1) * c->n : V;
+      A *ap = (A *)c->partials + kRedBlock;
+      k_lz_alpha_part<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * c->n, c->n, (LzState<A> *)c->lz, ap);
       k_lz_update_pc<T, A><<<kRedBlock, 256, 0, c->stream>>>(t, V + (size_t)m * c->n, vprev, w, (const T *)c->pc_P,
-                                                             u, c->n, (LzState<A> *)c->lz, (A *)c->partials);
+                                                             u, c->n, (LzState<A> *)c->lz, (A *)c->partials, ap,
+                                                             kRedBlock);
       k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, (LzState<A> *)c->lz,
                                              (A)c->p.lanczos_tol, c->lz_maxit);
       return;
