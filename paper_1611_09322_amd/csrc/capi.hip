@@ -787,7 +787,7 @@ pse_status pse_create(const pse_params *p, void *stream, pse_ctx **out) {
   c->pos_w = al.dev(4 * T * n);
   c->pos_s = al.dev(4 * T * n);
   c->perm = (int *)al.dev(sizeof(int) * n);
-  c->cell_of = (int *)al.dev(sizeof(int) * n);
+  c->cell_of = (int *)al.dev(sizeof(int) * 2 * n);  // cells, then slots
   c->cell_count = (int *)al.dev(sizeof(int) * 2 * c->ncell);
   c->cell_start = (int *)al.dev(sizeof(int) * (c->ncell + 1));
   c->nbr_cap = nbr_capacity(c);

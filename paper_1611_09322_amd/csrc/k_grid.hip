@@ -232,11 +232,13 @@ __global__ __launch_bounds__(BLOCK) void k_fft_z(const C<T> *__restrict__ src, C
   }
 }
 
-// z pass between the interleaved real grid (one (c0, c1, c2, 0) vector per
-// node, nodes [x][y][z]) and the planar half spectrum: the three component
-// lines of NXY (x, y) columns are transformed together, so every node vector
-// is read or written once, whole.  Forward (DIR < 0): real -> spectrum;
-// inverse (DIR > 0): spectrum -> real, with the same packing as k_fft_z.
+// z pass between the real grid (nodes [x][y][z]) and the planar half
+// spectrum: the three component lines of NXY (x, y) columns are transformed
+// together, so every node vector is read or written once, whole.  Forward
+// (DIR < 0): real -> spectrum, from the interleaved grid that spreading
+// writes (one (c0, c1, c2, 0) vector per node); inverse (DIR > 0): spectrum
+// -> real, into the packed grid that interpolation reads (c0, c1, c2 per
+// node, no padding).  Same packing of the half spectrum as k_fft_z.
 template <typename T, int M, int DIR, int NXY, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_fft_z_aos(const void *__restrict__ src, void *__restrict__ dst,
                                                      const C<T> *__restrict__ twH_g, const C<T> *__restrict__ twM_g) {
@@ -289,21 +291,15 @@ __global__ __launch_bounds__(BLOCK) void k_fft_z_aos(const void *__restrict__ sr
       ln[k] = cmk<T>((T)0.5 * (sm.x + t.y), (T)0.5 * (sm.y - t.x));
     }
   } else {
+    // packed output: nodes 2k and 2k + 1 are six consecutive values
+    // (c0, c1, c2, c0, c1, c2), written as three pairs
     for (int e = threadIdx.x; e < H * NXY; e += BLOCK) {
       const int k = e % H, l = e / H;
       const C<T> u0 = buf[k * NL + l], u1 = buf[k * NL + NXY + l], u2 = buf[k * NL + 2 * NXY + l];
-      T4 *ln = (T4 *)dst + (xy0 + l) * M;
-      T4 a, b;
-      a.x = u0.x;
-      a.y = u1.x;
-      a.z = u2.x;
-      a.w = T(0);
-      b.x = u0.y;
-      b.y = u1.y;
-      b.z = u2.y;
-      b.w = T(0);
-      ln[2 * k] = a;
-      ln[2 * k + 1] = b;
+      C<T> *ln = (C<T> *)dst + (xy0 + l) * (3 * H) + 3 * k;
+      ln[0] = cmk<T>(u0.x, u1.x);
+      ln[1] = cmk<T>(u2.x, u0.y);
+      ln[2] = cmk<T>(u1.y, u2.y);
     }
   }
 }
@@ -550,8 +546,8 @@ __global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__
 
 // Interpolation: one wavefront per particle (16 per workgroup, neighbours in
 // cell order, so their support rows are shared in the L1); lane -> (iz, ix) of the support
-// (consecutive lanes read consecutive z nodes of one grid row, one
-// (c0, c1, c2, 0) vector per node of the interleaved grid), loop over iy.
+// (consecutive lanes read consecutive z nodes of one grid row, one packed
+// (c0, c1, c2) vector per node), loop over iy.
 template <typename T, int P>
 __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *__restrict__ pos,
                                                 const T *__restrict__ grid, int n,
@@ -570,7 +566,10 @@ __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *_
   const int gx0 = bx - P / 2 + 1, gy0 = by - P / 2 + 1, gz0 = bz - P / 2 + 1;
   // support nodes lie within one period of the grid: one conditional wrap
   auto wrapi = [M](int g) { return g < 0 ? g + M : (g >= M ? g - M : g); };
-  auto *g4 = (const typename vec4<T>::type *)grid;  // interleaved nodes (c0, c1, c2, 0)
+  struct P3 {
+    T x, y, z;
+  };
+  auto *g3 = (const P3 *)grid;  // packed nodes (c0, c1, c2)
   // y weights of the equally spaced support nodes by the Gaussian
   // recurrence w_{k+1} = w_k r_k, r_{k+1} = r_k q (r_0 = e^{-(2 d_0 h + h^2) c},
   // q = e^{-2 h^2 c}, c = 1 / 2 sigma^2): three exponentials instead of P
@@ -598,7 +597,7 @@ __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *_
 #pragma unroll
     for (int iy = 0; iy < P; ++iy) {
       const T w = wxz * wy[iy];
-      const auto v = g4[xz + ym[iy]];
+      const P3 v = g3[xz + ym[iy]];
       ax += w * v.x;
       ay += w * v.y;
       az += w * v.z;

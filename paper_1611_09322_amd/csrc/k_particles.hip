@@ -21,7 +21,7 @@ template <typename T> __device__ __forceinline__ T min_image(T d, T L, T invL) {
 template <typename T>
 __global__ void k_wrap_bin(const T *__restrict__ pos, int n, T L, T invL, T inv_cs, int nc,
                            typename vec4<T>::type *__restrict__ pos_w, int *__restrict__ cell_of,
-                           int *__restrict__ cell_count, int *__restrict__ flags) {
+                           int *__restrict__ slot, int *__restrict__ cell_count, int *__restrict__ flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
@@ -37,113 +37,118 @@ __global__ void k_wrap_bin(const T *__restrict__ pos, int n, T L, T invL, T inv_
   const int cz = min((int)(z * inv_cs), nc - 1);
   const int c = (cx * nc + cy) * nc + cz;
   cell_of[i] = c;
-  // one atomic per distinct cell of the wavefront (consecutive particles
-  // often share cells): the lanes of the lowest pending lane's cell go
-  // together
+  // The particle's slot in its cell (arrival order; k_cell_sort fixes the
+  // final order).  Lanes holding the same cell as the lane before them join
+  // its run, and the first lane of each run reserves the run's slots with
+  // one atomic: all runs of the wavefront in a single instruction, one per
+  // particle for shuffled callers, a few for spatially ordered ones.  The
+  // active lanes are 0 .. k-1 (only the last wavefront is partial).
   const int lane = threadIdx.x & 63;
-  bool done = false;
-  while (true) {
-    const unsigned long long rem = __ballot(!done);
-    if (!rem) break;
-    const int leader = __ffsll((long long)rem) - 1;
-    const int c0 = __shfl(c, leader, 64);
-    const bool mine = !done && c == c0;
-    const unsigned long long m = __ballot(mine);
-    if (lane == leader) atomicAdd(&cell_count[c0], __popcll(m));
-    done = done || mine;
-  }
+  const unsigned long long act = __ballot(1);
+  const int prev = __shfl_up(c, 1, 64);
+  const bool head = lane == 0 || prev != c;
+  const unsigned long long H = __ballot(head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes 0 .. lane
+  const int hl = 63 - __clzll((long long)(H & upto));                             // first lane of my run
+  const unsigned long long later = H & ~upto;
+  const int next = later ? __ffsll((long long)later) - 1 : 64 - __clzll((long long)act);
+  int b = 0;
+  if (head) b = atomicAdd(&cell_count[c], next - lane);
+  slot[i] = __shfl(b, hl, 64) + (lane - hl);
   typename vec4<T>::type q;
   q.x = x; q.y = y; q.z = z; q.w = T(0);
   pos_w[i] = q;
 }
 
-// Exclusive scan of the cell counts, one workgroup of 1024 threads: the
-// counts pass through LDS in tiles of 16 per thread (coalesced loads and
-// stores), each thread sums its 16, the 1024 sums are scanned across
-// wavefronts, and a running carry links the tiles.  Also clears fill[].
-constexpr int kScanPer = 16;
-__global__ __launch_bounds__(1024) void k_scan_cells(const int *__restrict__ count, int *__restrict__ start,
-                                                     int *__restrict__ fill, int ncell) {
-  constexpr int TILE = 1024 * kScanPer;
-  __shared__ int tile[TILE];
-  __shared__ int wsum[16];
-  __shared__ int carry_sh;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  int carry = 0;
-  for (int base = 0; base < ncell; base += TILE) {
-    for (int k = t; k < TILE; k += 1024) {
-      const int i = base + k;
-      tile[k] = i < ncell ? count[i] : 0;
-      if (i < ncell) fill[i] = 0;
-    }
-    __syncthreads();
-    int loc = 0;
+// Exclusive scan of the cell counts in tiles of 4096 cells: k_scan_tiles
+// sums each tile, k_scan_apply adds the sums of the tiles before its own
+// (a few thousand at most) and scans its tile (16 consecutive cells per
+// thread through LDS, the 256 thread sums scanned across wavefronts).
+constexpr int kScanPer = 16, kScanNT = 256, kScanTile = kScanPer * kScanNT;
+__device__ __forceinline__ int block_sum_i32(int v, int *sh) {
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) loc += tile[t * kScanPer + k];
-    // inclusive scan of the per-thread sums: within the wavefront, then
-    // across the 16 wavefronts
-    int v = loc;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int u = __shfl_up(v, off, 64);
-      if (lane >= off) v += u;
-    }
-    if (lane == 63) wsum[wave] = v;
-    __syncthreads();
-    int wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre += wsum[w];
-    int run = carry + wpre + v - loc;  // exclusive prefix of this thread's first cell
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      const int cnt = tile[t * kScanPer + k];
-      tile[t * kScanPer + k] = run;
-      run += cnt;
-    }
-    if (t == 1023) carry_sh = run;
-    __syncthreads();
-    for (int k = t; k < TILE; k += 1024) {
-      const int i = base + k;
-      if (i < ncell) start[i] = tile[k];
-    }
-    carry = carry_sh;
-    __syncthreads();  // the tile and carry_sh are rewritten next
-  }
-  if (t == 0) start[ncell] = carry;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  int t = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  return t;
 }
 
-__global__ void k_scatter(const int *__restrict__ cell_of, const int *__restrict__ start, int *__restrict__ fill,
+__global__ __launch_bounds__(kScanNT) void k_scan_tiles(const int *__restrict__ count, int ncell,
+                                                        int *__restrict__ tile_sum) {
+  __shared__ int sh[kScanNT / 64];
+  const int base = blockIdx.x * kScanTile;
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int i = base + k * kScanNT + (int)threadIdx.x;
+    if (i < ncell) v += count[i];
+  }
+  v = block_sum_i32(v, sh);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kScanNT) void k_scan_apply(const int *__restrict__ count, const int *__restrict__ tile_sum,
+                                                        int ncell, int *__restrict__ start) {
+  __shared__ int tile[kScanTile];
+  __shared__ int sh[kScanNT / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int base = blockIdx.x * kScanTile;
+  int off = 0;
+  for (int k = t; k < (int)blockIdx.x; k += kScanNT) off += tile_sum[k];
+  off = block_sum_i32(off, sh);
+  for (int k = t; k < kScanTile; k += kScanNT) {
+    const int i = base + k;
+    tile[k] = i < ncell ? count[i] : 0;
+  }
+  __syncthreads();
+  int loc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) loc += tile[t * kScanPer + k];
+  int v = loc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  __syncthreads();  // sh is reused
+  if (lane == 63) sh[wave] = v;
+  __syncthreads();
+  int wpre = 0;
+  for (int w = 0; w < wave; ++w) wpre += sh[w];
+  int run = off + wpre + v - loc;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int cnt = tile[t * kScanPer + k];
+    tile[t * kScanPer + k] = run;
+    run += cnt;
+  }
+  __syncthreads();
+  for (int k = t; k < kScanTile; k += kScanNT) {
+    const int i = base + k;
+    if (i < ncell) start[i] = tile[k];
+  }
+  if (t == kScanNT - 1 && base + kScanTile >= ncell) start[ncell] = run;
+}
+
+__global__ void k_scatter(const int *__restrict__ cell_of, const int *__restrict__ slot, const int *__restrict__ start,
                           int *__restrict__ perm, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = cell_of[i];
-  // slots reserved per distinct cell of the wavefront (as in k_wrap_bin);
-  // the order inside a cell is fixed afterwards by k_cell_sort
-  const int lane = threadIdx.x & 63;
-  const unsigned long long below = (1ull << lane) - 1ull;
-  bool done = false;
-  int slot = 0;
-  while (true) {
-    const unsigned long long rem = __ballot(!done);
-    if (!rem) break;
-    const int leader = __ffsll((long long)rem) - 1;
-    const int c0 = __shfl(c, leader, 64);
-    const bool mine = !done && c == c0;
-    const unsigned long long m = __ballot(mine);
-    int b = 0;
-    if (lane == leader) b = atomicAdd(&fill[c0], __popcll(m));
-    b = __shfl(b, leader, 64);
-    if (mine) slot = b + __popcll(m & below);
-    done = done || mine;
-  }
-  perm[start[c] + slot] = i;
+  if (i < n) perm[start[cell_of[i]] + slot[i]] = i;
 }
 
 // Order each cell's members by caller index: the sorted order (and with it
 // every summation order downstream) is then deterministic.  One wavefront
 // per cell: with at most 64 members each lane holds one and its rank is the
 // number of smaller indices (the indices are distinct); larger cells fall
-// back to an insertion sort by lane 0.
-__global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start, int *__restrict__ perm, int ncell) {
+// back to an insertion sort by lane 0.  The sorted positions are gathered in
+// the same pass.
+template <typename T4>
+__global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start, int *__restrict__ perm, int ncell,
+                                                   const T4 *__restrict__ pos_w, T4 *__restrict__ pos_s) {
   const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= ncell) return;
@@ -152,7 +157,10 @@ __global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start
     const int v = lane < m ? perm[b + lane] : 0x7FFFFFFF;
     int rank = 0;
     for (int j = 0; j < m; ++j) rank += __shfl(v, j, 64) < v ? 1 : 0;
-    if (lane < m) perm[b + rank] = v;
+    if (lane < m) {
+      perm[b + rank] = v;
+      pos_s[b + rank] = pos_w[v];
+    }
     return;
   }
   if (lane != 0) return;
@@ -165,12 +173,7 @@ __global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start
     }
     perm[j + 1] = v;
   }
-}
-
-template <typename T4>
-__global__ void k_gather_pos(const T4 *__restrict__ pos_w, const int *__restrict__ perm, T4 *__restrict__ pos_s, int n) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < n) pos_s[s] = pos_w[perm[s]];
+  for (int i = b; i < e; ++i) pos_s[i] = pos_w[perm[i]];
 }
 
 // ------------------------------------------------------- F, G evaluation
@@ -687,22 +690,29 @@ template <int B> __device__ __forceinline__ void target_of(const HaloTab<B> &ht,
   s = ht.start[h] + off;
 }
 
-// Per-block halo sizes (largest goes to flags[4]) for sizing the LDS.
+// Per-block halo sizes (largest goes to flags[4]) for sizing the LDS: one
+// wavefront per block, lane (hx, hy) sums its column of HB halo cells.
 template <int B>
-__global__ void k_halo_size(const int *__restrict__ cell_start, int nc, int *__restrict__ flags) {
-  constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
+__global__ __launch_bounds__(256) void k_halo_size(const int *__restrict__ cell_start, int nc, int *__restrict__ flags) {
+  constexpr int HB = Halo<B>::HB;
+  static_assert(HB * HB <= 64, "one lane per halo column");
   const int nb = (nc + B - 1) / B;
-  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blk >= nb * nb * nb) return;
+  const int blk = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+  if (blk >= nb * nb * nb) return;  // uniform across the wavefront
   const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
   int tot = 0;
-  for (int h = 0; h < NH; ++h) {
-    const int hx = h / (HB * HB), hy = (h / HB) % HB, hz = h % HB;
-    const int gx = (bx * B - 1 + hx + nc) % nc, gy = (by * B - 1 + hy + nc) % nc, gz = (bz * B - 1 + hz + nc) % nc;
-    const int c = (gx * nc + gy) * nc + gz;
-    tot += cell_start[c + 1] - cell_start[c];
+  if (lane < HB * HB) {
+    const int hx = lane / HB, hy = lane % HB;
+    const int gx = (bx * B - 1 + hx + nc) % nc, gy = (by * B - 1 + hy + nc) % nc;
+    const int row = (gx * nc + gy) * nc;
+    for (int hz = 0; hz < HB; ++hz) {
+      const int gz = (bz * B - 1 + hz + nc) % nc;
+      tot += cell_start[row + gz + 1] - cell_start[row + gz];
+    }
   }
-  atomicMax(&flags[4], tot);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+  if (lane == 0) atomicMax(&flags[4], tot);
 }
 
 // flags[1]: list capacity needed; flags[5]: largest count.  With REP the
@@ -1627,12 +1637,16 @@ void launch_bin(pse_ctx *c, const void *pos) {
   ProfScope ps(c, PSE_STAGE_BIN);
   // a fill kernel rather than a memset: the same code runs under graph capture
   k_zero_i32<<<nblk(c->ncell + 8, 256), 256, 0, c->stream>>>(c->cell_count, c->ncell, c->flags, 8);
+  // cell_of holds the cells [0, n) and the slots [n, 2n); cell_count the
+  // counts [0, ncell) and the tile sums of the scan after them
   k_wrap_bin<T><<<nblk(n, 256), 256, 0, c->stream>>>((const T *)pos, n, L, invL, inv_cs, c->d.nc, (T4 *)c->pos_w,
-                                                     c->cell_of, c->cell_count, c->flags);
-  k_scan_cells<<<1, 1024, 0, c->stream>>>(c->cell_count, c->cell_start, c->cell_count + c->ncell, c->ncell);
-  k_scatter<<<nblk(n, 256), 256, 0, c->stream>>>(c->cell_of, c->cell_start, c->cell_count + c->ncell, c->perm, n);
-  k_cell_sort<<<nblk(c->ncell, 4), 256, 0, c->stream>>>(c->cell_start, c->perm, c->ncell);
-  k_gather_pos<T4><<<nblk(n, 256), 256, 0, c->stream>>>((const T4 *)c->pos_w, c->perm, (T4 *)c->pos_s, n);
+                                                     c->cell_of, c->cell_of + n, c->cell_count, c->flags);
+  const int ntiles = nblk(c->ncell, kScanTile);
+  k_scan_tiles<<<ntiles, kScanNT, 0, c->stream>>>(c->cell_count, c->ncell, c->cell_count + c->ncell);
+  k_scan_apply<<<ntiles, kScanNT, 0, c->stream>>>(c->cell_count, c->cell_count + c->ncell, c->ncell, c->cell_start);
+  k_scatter<<<nblk(n, 256), 256, 0, c->stream>>>(c->cell_of, c->cell_of + n, c->cell_start, c->perm, n);
+  k_cell_sort<T4><<<nblk(c->ncell, 4), 256, 0, c->stream>>>(c->cell_start, c->perm, c->ncell, (const T4 *)c->pos_w,
+                                                           (T4 *)c->pos_s);
 }
 
 template <typename T>
@@ -1681,7 +1695,7 @@ void launch_halo_size(pse_ctx *c, int B) {
   const int nblocks = lds_nblocks(c->d.nc, B);
   with_block_edge(B, [&](auto b) {
     constexpr int BE = decltype(b)::value;
-    k_halo_size<BE><<<nblk(nblocks, 256), 256, 0, c->stream>>>(c->cell_start, c->d.nc, c->flags);
+    k_halo_size<BE><<<nblk(64L * nblocks, 256), 256, 0, c->stream>>>(c->cell_start, c->d.nc, c->flags);
   });
 }
 
