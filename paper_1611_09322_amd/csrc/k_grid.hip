@@ -544,6 +544,19 @@ __global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__
   }
 }
 
+// Sum of v over the 64 lanes of the wavefront, valid in lane 63: quad sums
+// by quad permutes, row sums by row shifts (4, 8), then the row totals by
+// the row-15 and row-31 broadcasts; disabled lanes contribute 0.
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1, 0, 3, 2]
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2, 3, 0, 1]
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x114, 0xF, 0xF, true);  // row_shr 4
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x118, 0xF, 0xF, true);  // row_shr 8
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xA, 0xF, true);  // row_bcast 15 -> rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xC, 0xF, true);  // row_bcast 31 -> rows 2, 3
+  return v;
+}
+
 // Interpolation: one wavefront per particle (16 per workgroup, neighbours in
 // cell order, so their support rows are shared in the L1); lane -> (iz, ix) of the support
 // (consecutive lanes read consecutive z nodes of one grid row, one packed
@@ -570,46 +583,85 @@ __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *_
     T x, y, z;
   };
   auto *g3 = (const P3 *)grid;  // packed nodes (c0, c1, c2)
-  // y weights of the equally spaced support nodes by the Gaussian
-  // recurrence w_{k+1} = w_k r_k, r_{k+1} = r_k q (r_0 = e^{-(2 d_0 h + h^2) c},
-  // q = e^{-2 h^2 c}, c = 1 / 2 sigma^2): three exponentials instead of P
-  T wy[P];
   unsigned ym[P];  // y offset of the node index, (y mod M) M
-  {
-    const T dy0 = (T)gy0 * h - p.y;
-    T w = gauss_exp(-dy0 * dy0 * inv2s2), r = gauss_exp(-(T(2) * dy0 + h) * h * inv2s2);
-    const T q = gauss_exp(T(-2) * h * h * inv2s2);
 #pragma unroll
-    for (int iy = 0; iy < P; ++iy) {
-      wy[iy] = w;
-      w *= r;
-      r *= q;
-      ym[iy] = (unsigned)wrapi(gy0 + iy) * (unsigned)M;
-    }
-  }
+  for (int iy = 0; iy < P; ++iy) ym[iy] = (unsigned)wrapi(gy0 + iy) * (unsigned)M;
   T ax = 0, ay = 0, az = 0;
-  for (int pr = lane; pr < P * P; pr += 64) {
-    const int iz = pr % P, ix = pr / P;
-    const int gx = gx0 + ix, gz = gz0 + iz;
-    const T dx = (T)gx * h - p.x, dz = (T)gz * h - p.z;
-    const T wxz = gauss_exp(-(dx * dx + dz * dz) * inv2s2);
-    const unsigned xz = (unsigned)wrapi(gx) * (unsigned)(M * M) + (unsigned)wrapi(gz);
+  if constexpr (std::is_same<T, float>::value) {
+    // y weights: lane iy evaluates the weight of support row iy, and every
+    // lane reads the P values as scalars
+    static_assert(P <= 64, "one lane per support row");
+    const float dyl = (float)(gy0 + lane % P) * h - p.y;
+    const float wl = gauss_exp(-dyl * dyl * inv2s2);
+    float wy[P];
 #pragma unroll
-    for (int iy = 0; iy < P; ++iy) {
-      const T w = wxz * wy[iy];
-      const P3 v = g3[xz + ym[iy]];
-      ax += w * v.x;
-      ay += w * v.y;
-      az += w * v.z;
+    for (int iy = 0; iy < P; ++iy) wy[iy] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wl), iy));
+    // buffer loads: the lane's (x, z) offset in the address register and
+    // the row's y offset (a scalar) in the scalar offset; the grid's byte
+    // size bounds every access
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)grid, 0, (int)(12u * (unsigned)M * M * M), 0x00020000);
+    for (int pr = lane; pr < P * P; pr += 64) {
+      const int iz = pr % P, ix = pr / P;
+      const int gx = gx0 + ix, gz = gz0 + iz;
+      const float dx = (float)gx * h - p.x, dz = (float)gz * h - p.z;
+      const float wxz = gauss_exp(-(dx * dx + dz * dz) * inv2s2);
+      const unsigned xz = (unsigned)wrapi(gx) * (unsigned)(M * M) + (unsigned)wrapi(gz);
+      float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+      for (int iy = 0; iy < P; ++iy) {
+        typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
+        const u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(rs, (int)(12u * xz), (int)(12u * ym[iy]), 0);
+        sx = fmaf(wy[iy], __uint_as_float(v.x), sx);
+        sy = fmaf(wy[iy], __uint_as_float(v.y), sy);
+        sz = fmaf(wy[iy], __uint_as_float(v.z), sz);
+      }
+      ax = fmaf(wxz, sx, ax);
+      ay = fmaf(wxz, sy, ay);
+      az = fmaf(wxz, sz, az);
+    }
+    ax = wave_sum_lane63(ax);
+    ay = wave_sum_lane63(ay);
+    az = wave_sum_lane63(az);
+  } else {
+    // y weights of the equally spaced support nodes by the Gaussian
+    // recurrence w_{k+1} = w_k r_k, r_{k+1} = r_k q (r_0 = e^{-(2 d_0 h + h^2) c},
+    // q = e^{-2 h^2 c}, c = 1 / 2 sigma^2): three exponentials instead of P
+    T wy[P];
+    {
+      const T dy0 = (T)gy0 * h - p.y;
+      T w = gauss_exp(-dy0 * dy0 * inv2s2), r = gauss_exp(-(T(2) * dy0 + h) * h * inv2s2);
+      const T q = gauss_exp(T(-2) * h * h * inv2s2);
+#pragma unroll
+      for (int iy = 0; iy < P; ++iy) {
+        wy[iy] = w;
+        w *= r;
+        r *= q;
+      }
+    }
+    for (int pr = lane; pr < P * P; pr += 64) {
+      const int iz = pr % P, ix = pr / P;
+      const int gx = gx0 + ix, gz = gz0 + iz;
+      const T dx = (T)gx * h - p.x, dz = (T)gz * h - p.z;
+      const T wxz = gauss_exp(-(dx * dx + dz * dz) * inv2s2);
+      const unsigned xz = (unsigned)wrapi(gx) * (unsigned)(M * M) + (unsigned)wrapi(gz);
+#pragma unroll
+      for (int iy = 0; iy < P; ++iy) {
+        const T w = wxz * wy[iy];
+        const P3 v = g3[xz + ym[iy]];
+        ax += w * v.x;
+        ay += w * v.y;
+        az += w * v.z;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      ax += __shfl_xor(ax, off, 64);
+      ay += __shfl_xor(ay, off, 64);
+      az += __shfl_xor(az, off, 64);
     }
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    ax += __shfl_xor(ax, off, 64);
-    ay += __shfl_xor(ay, off, 64);
-    az += __shfl_xor(az, off, 64);
-  }
-  if (lane == 0) {
+  if (lane == (std::is_same<T, float>::value ? 63 : 0)) {
     typename vec4<T>::type o;
     o.x = norm_h3 * ax;
     o.y = norm_h3 * ay;
