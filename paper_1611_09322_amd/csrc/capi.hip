@@ -141,6 +141,12 @@ hipEvent_t next_event(pse_ctx *c) {
 template <typename T, typename A>
 pse_status lz_start(pse_ctx *c, const void *z_sorted) {
   launch_lz_init<T, A>(c, z_sorted);
+  if (c->lz_external) {
+    // captured batch step: the batch launches the iterations of all its
+    // replicas together, and lz_finish reads the state back
+    c->lz_launched = c->graph_iters;
+    return hip_status(hipGetLastError());
+  }
   // without weights every block is I; pc_suspend: the global fallback below
   const bool pc = pc_active(c);
   const int maxit = c->lz_maxit;
@@ -168,9 +174,12 @@ void take_pc_fallbacks(pse_ctx *c, bool synced) {
 template <typename T, typename A>
 pse_status lz_finish(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats *stats) {
   if (c->graph) {
-    // captured: the iterate of the iterations queued by lz_start; the
-    // state copied back by lz_start tells the host after the replay
+    // captured: the iterate of the iterations queued by lz_start (or by the
+    // batch); the state copied back tells the host after the replay
     // whether they sufficed
+    if (c->lz_external &&
+        hipMemcpyAsync(c->lz_h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      return PSE_ERR_HIP;
     launch_lz_combine<T, A>(c, y_sorted);
     if (pc_active(c)) launch_pc_apply_inv<T>(c, y_sorted);
     return hip_status(hipGetLastError());
@@ -662,6 +671,17 @@ struct pse_batch {
   std::vector<int> g_hcap;  // halo capacity each replica was captured with
   double g_dt = 0.0, g_headroom = 0.0;
   int g_extra = 0;
+  // batched Krylov loops of the captured step: the replicas on the LDS
+  // product (FP32 storage) without the preconditioner iterate together, one
+  // loop per Lanczos scalar type ([0] FP32, [1] FP64)
+  struct LzBatch {
+    void *reps = nullptr;              // LzRep<A> [nrep], device
+    int2 *maps = nullptr;              // product blocks of every group, then the vector blocks
+    std::vector<pse::LzGroup> groups;  // pmap pointers into maps
+    const int2 *vmap = nullptr;
+    int nrep = 0, nv = 0, iters = 0;
+    std::vector<int> members;  // replica of each LzRep
+  } lzb[2];
 };
 
 namespace pse {
@@ -728,6 +748,11 @@ static void free_graph(pse_batch *b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->gexec = nullptr;
   b->graph = nullptr;
+  for (auto &z : b->lzb) {
+    if (z.reps) (void)hipFree(z.reps);
+    if (z.maps) (void)hipFree(z.maps);
+    z = pse_batch::LzBatch{};
+  }
 }
 
 static void free_batch(pse_batch *b) {
@@ -1155,6 +1180,96 @@ static pse_status ctx_set_positions(pse_ctx *c, const void *pos) {
   return c->dbl ? set_positions_impl<double>(c, pos) : set_positions_impl<float>(c, pos);
 }
 
+// The batched Krylov loop of a captured step: every replica that runs the
+// LDS product (FP32 storage) without the preconditioner, as LzRep records,
+// its product blocks grouped by kernel form, and its vector blocks.  Built
+// before the capture (device allocation and copies); the loop runs as many
+// iterations as the replica that queued the most, the others stop
+// themselves once converged.
+template <typename A> static pse_status lzb_setup(pse_batch *b) {
+  const int R = (int)b->ctx.size();
+  pse_batch::LzBatch &z = b->lzb[sizeof(A) == 8 ? 1 : 0];
+  std::vector<LzRep<A>> reps;
+  std::vector<std::vector<int2>> pm;
+  std::vector<LzGroup> gr;
+  std::vector<int2> vm;
+  int iters = 0;
+  for (int r = 0; r < R; ++r) {
+    pse_ctx *c = b->ctx[r];
+    if (c->dbl || c->acc_dbl != (sizeof(A) == 8) || !c->lds_B || pc_active(c) || !(c->p.kT > 0) ||
+        c->n > kRedBlock * 256)
+      continue;
+    const int k = (int)reps.size();
+    LzRep<A> q{};
+    q.pos = (const float4 *)c->pos_s;
+    q.cell_start = c->cell_start;
+    q.nbr = (const uint16_t *)c->nbr;
+    q.cnt = c->nbr_cnt;
+    q.tab = c->table;
+    q.ovf = c->flags + 7;
+    q.z = (const float4 *)c->vbuf[0];
+    q.t = (float4 *)c->vbuf[2];
+    q.w = (float4 *)c->vbuf[3];
+    q.V = (float4 *)c->V;
+    q.st = (LzState<A> *)c->lz;
+    q.partials = (A *)c->partials;
+    q.cs = (float)c->d.cs;
+    q.L = (float)c->d.L;
+    q.invL = (float)(1.0 / c->d.L);
+    q.inv_dr = (float)(kTableK / c->p.rcut);
+    q.self_r = (float)c->d.self_r;
+    q.nc = c->d.nc;
+    q.n = c->n;
+    q.hcap = c->hcap;
+    q.maxit = c->lz_maxit;
+    q.tol = (A)c->p.lanczos_tol;
+    reps.push_back(q);
+    z.members.push_back(r);
+    const int G = c->tune_spmv_lanes ? c->tune_spmv_lanes : 3, unwrap = c->d.nc >= c->lds_B + 3 ? 1 : 0;
+    size_t g = 0;
+    while (g < gr.size() && !(gr[g].B == c->lds_B && gr[g].G == G && gr[g].unwrap == unwrap)) ++g;
+    if (g == gr.size()) {
+      gr.push_back(LzGroup{c->lds_B, G, unwrap, 0, 0, nullptr});
+      pm.emplace_back();
+    }
+    for (int blk = 0; blk < c->lds_blocks; ++blk) pm[g].push_back(make_int2(k, blk));
+    const size_t smem = (sizeof(float4) + sizeof(float2)) * (size_t)c->hcap;
+    if (smem > gr[g].smem) gr[g].smem = smem;
+    for (int v = 0; v < (c->n + 255) / 256; ++v) vm.push_back(make_int2(k, v));
+    iters = std::max(iters, c->graph_iters);
+  }
+  if (reps.empty()) return PSE_OK;
+  size_t nmap = vm.size();
+  for (auto &x : pm) nmap += x.size();
+  if (hipMalloc(&z.reps, sizeof(LzRep<A>) * reps.size()) != hipSuccess ||
+      hipMalloc((void **)&z.maps, sizeof(int2) * nmap) != hipSuccess)
+    return PSE_ERR_OOM;
+  std::vector<int2> all;
+  all.reserve(nmap);
+  for (size_t g = 0; g < gr.size(); ++g) {
+    gr[g].pmap = z.maps + all.size();
+    gr[g].nblk = (int)pm[g].size();
+    all.insert(all.end(), pm[g].begin(), pm[g].end());
+  }
+  z.vmap = z.maps + all.size();
+  all.insert(all.end(), vm.begin(), vm.end());
+  if (hipMemcpy(z.reps, reps.data(), sizeof(LzRep<A>) * reps.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(z.maps, all.data(), sizeof(int2) * nmap, hipMemcpyHostToDevice) != hipSuccess)
+    return PSE_ERR_HIP;
+  z.groups = gr;
+  z.nrep = (int)reps.size();
+  z.nv = (int)vm.size();
+  z.iters = iters;
+  return PSE_OK;
+}
+
+template <typename A> static void lzb_launch(pse_batch *b) {
+  const pse_batch::LzBatch &z = b->lzb[sizeof(A) == 8 ? 1 : 0];
+  for (int m = 0; m < z.iters; ++m)
+    launch_lz_batch_iter<A>(b->gstream, (const LzRep<A> *)z.reps, z.nrep, z.groups.data(), (int)z.groups.size(),
+                            z.vmap, z.nv, m);
+}
+
 // Capture one batch step (every replica's set_positions and sample, on the
 // replicas' streams) into b->gexec.  Capacities get the headroom first
 // (outside the capture: the list may be reallocated); inside the capture no
@@ -1186,6 +1301,9 @@ static pse_status batch_capture(pse_batch *b) {
     c->graph_iters = it > c->lz_maxit ? c->lz_maxit : it;
     c->graph_stale = false;
   }
+  pse_status st0 = lzb_setup<float>(b);
+  if (st0 == PSE_OK) st0 = lzb_setup<double>(b);
+  if (st0 != PSE_OK) return st0;
   std::vector<uint32_t> prof(R);
   for (int r = 0; r < R; ++r) {
     pse_ctx *c = b->ctx[r];
@@ -1194,17 +1312,31 @@ static pse_status batch_capture(pse_batch *b) {
     c->graph = true;
     c->rng_dev = b->rng_d + 2 * r;
   }
+  for (const auto &z : b->lzb)
+    for (int r : z.members) b->ctx[r]->lz_external = true;
   pse_status st = hip_status(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeRelaxed));
   if (st == PSE_OK)
     st = hip_status(hipMemcpyAsync(b->rng_d, b->rng_h, sizeof(uint64_t) * 2 * R, hipMemcpyHostToDevice, b->gstream));
   if (st == PSE_OK) st = fork(b, b->gstream);
+  // every replica's positions and the first part of its sample; then the
+  // batched Krylov loop on the capture stream; then the rest of each sample
+  std::vector<SampleState> ss(R);
   for (int r = 0; r < R && st == PSE_OK; ++r) {
     pse_ctx *c = b->ctx[r];
     st = ctx_set_positions(c, b->g_pos[r]);
-    SampleState ss;
-    if (st == PSE_OK) st = ctx_begin(c, 0, 0, b->g_dt, b->g_forces.empty() ? nullptr : b->g_forces[r], ss);
-    if (st == PSE_OK) st = ctx_end(c, ss, b->g_dt, b->g_disp[r], nullptr);
+    if (st == PSE_OK) st = ctx_begin(c, 0, 0, b->g_dt, b->g_forces.empty() ? nullptr : b->g_forces[r], ss[r]);
   }
+  if (st == PSE_OK && (b->lzb[0].nrep || b->lzb[1].nrep)) {
+    st = join(b, b->gstream);
+    if (st == PSE_OK) {
+      lzb_launch<float>(b);
+      lzb_launch<double>(b);
+      st = hip_status(hipGetLastError());
+    }
+    if (st == PSE_OK) st = fork(b, b->gstream);
+  }
+  for (int r = 0; r < R && st == PSE_OK; ++r)
+    st = ctx_end(b->ctx[r], ss[r], b->g_dt, b->g_disp[r], nullptr);
   if (st == PSE_OK) st = join(b, b->gstream);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(b->gstream, &g);
@@ -1213,6 +1345,7 @@ static pse_status batch_capture(pse_batch *b) {
     c->prof_mask = prof[r];
     c->graph = false;
     c->rng_dev = nullptr;
+    c->lz_external = false;
   }
   if (st == PSE_OK && ec != hipSuccess) st = PSE_ERR_HIP;
   if (st != PSE_OK) {

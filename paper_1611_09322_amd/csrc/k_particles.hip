@@ -568,11 +568,12 @@ template <int B> struct HaloTab {
   int ntc;                    // number of target cells (< B^3 at the partial last block)
 };
 
+// blk: the block of B^3 cells this workgroup serves (by default the
+// XCD-renumbered workgroup index)
 template <int B>
-__device__ __forceinline__ void halo_setup(const int *__restrict__ cell_start, int nc, HaloTab<B> &ht) {
+__device__ __forceinline__ void halo_setup(const int *__restrict__ cell_start, int nc, HaloTab<B> &ht, int blk) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   const int nb = (nc + B - 1) / B;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
   if (threadIdx.x < 64) {
     // one wavefront scans the halo cells, 64 at a time, carrying the sum
@@ -743,7 +744,7 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
       }
     pack_tab[threadIdx.x] = make_uint4((uint32_t)pat, (uint32_t)(pat >> 32), (uint32_t)msk, (uint32_t)(msk >> 32));
   }
-  halo_setup<B>(cell_start, nc, ht);
+  halo_setup<B>(cell_start, nc, ht, xcd_block(blockIdx.x, gridDim.x));
   if (!halo_fits<B>(ht, hcap, flags + 7)) return;
   if (UNWRAP) {
     const int nb = (nc + B - 1) / B;
@@ -891,7 +892,7 @@ __global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__
   __shared__ uint16_t queue[kFeatQ * kFeatNT];
   __shared__ float2 ftab[kTableN];
   for (int k = threadIdx.x; k < kTableN; k += blockDim.x) ftab[k] = tab[k];
-  halo_setup<B>(cell_start, nc, ht);
+  halo_setup<B>(cell_start, nc, ht, xcd_block(blockIdx.x, gridDim.x));
   if (!halo_fits<B>(ht, hcap, ovf)) return;
   if (UNWRAP) {
     const int nb = (nc + B - 1) / B;
@@ -1006,15 +1007,15 @@ __global__ __launch_bounds__(kFeatNT) void k_feat_lds(const float4 *__restrict__
 // With PC (Lanczos on A = P M_r P^T): src holds u = P^T r, and the
 // epilogue forms out = P (M_r u) / beta and v_m = r / beta (r from rsrc);
 // Pm holds the rows of P_i as (x, y, z, 0).
-template <int B, bool UNWRAP, typename A, bool LZ, bool PC = false, int G = 3>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmv_lds(const float4 *__restrict__ pos, const float4 *__restrict__ src,
-                                                   const int *__restrict__ cell_start, int nc, float cs, int n,
-                                                   int hcap, float L, float invL, const uint16_t *__restrict__ nbr,
-                                                   const int *__restrict__ cnt, const float2 *__restrict__ tab,
-                                                   float inv_dr, float self_r, float scale, float4 *__restrict__ out,
-                                                   float4 *__restrict__ vm_out, const LzState<A> *st,
-                                                   int *__restrict__ ovf, const float4 *__restrict__ Pm = nullptr,
-                                                   const float4 *__restrict__ rsrc = nullptr) {
+template <int B, bool UNWRAP, typename A, bool LZ, bool PC, int G>
+__device__ __forceinline__ void spmv_lds_block(const float4 *__restrict__ pos, const float4 *__restrict__ src,
+                                               const int *__restrict__ cell_start, int nc, float cs, int n, int hcap,
+                                               float L, float invL, const uint16_t *__restrict__ nbr,
+                                               const int *__restrict__ cnt, const float2 *__restrict__ tab,
+                                               float inv_dr, float self_r, float scale, float4 *__restrict__ out,
+                                               float4 *__restrict__ vm_out, const LzState<A> *st,
+                                               int *__restrict__ ovf, const float4 *__restrict__ Pm,
+                                               const float4 *__restrict__ rsrc, int blk) {
   constexpr int NH = Halo<B>::NH;
   static_assert(G >= 2 && G <= 4, "lanes per target");
   constexpr int GPW = 64 / G;               // groups per wavefront (lane 63 idle at G = 3)
@@ -1028,12 +1029,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     scale = (float)st->inv_beta;
   }
   for (int k = threadIdx.x; k < kTableN; k += blockDim.x) tabs[k] = tab[k];
-  halo_setup<B>(cell_start, nc, ht);
+  halo_setup<B>(cell_start, nc, ht, blk);
   // a halo past the capacity stages nothing and computes no target
   const bool fits = halo_fits<B>(ht, hcap, ovf);
   if (fits) {
     const int nb = (nc + B - 1) / B;
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
     const float c0 = 0.5f * B * cs;
     const float cx = bx * B * cs + c0, cy = by * B * cs + c0, cz = bz * B * cs + c0;
@@ -1173,6 +1173,18 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   }
 }
 
+template <int B, bool UNWRAP, typename A, bool LZ, bool PC = false, int G = 3>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmv_lds(
+    const float4 *__restrict__ pos, const float4 *__restrict__ src, const int *__restrict__ cell_start, int nc, float cs,
+    int n, int hcap, float L, float invL, const uint16_t *__restrict__ nbr, const int *__restrict__ cnt,
+    const float2 *__restrict__ tab, float inv_dr, float self_r, float scale, float4 *__restrict__ out,
+    float4 *__restrict__ vm_out, const LzState<A> *st, int *__restrict__ ovf, const float4 *__restrict__ Pm = nullptr,
+    const float4 *__restrict__ rsrc = nullptr) {
+  spmv_lds_block<B, UNWRAP, A, LZ, PC, G>(pos, src, cell_start, nc, cs, n, hcap, L, invL, nbr, cnt, tab, inv_dr,
+                                          self_r, scale, out, vm_out, st, ovf, Pm, rsrc,
+                                          xcd_block(blockIdx.x, gridDim.x));
+}
+
 // ------------------------------------------------------------- Lanczos
 // Block partial sums of |z|^2 (sorted order vector of length 3n).
 template <typename T, typename A>
@@ -1226,7 +1238,7 @@ __global__ void k_lz_alpha_part(const typename vec4<T>::type *__restrict__ t,
   if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }
 
-template <typename A> __device__ A lz_alpha(LzState<A> *st, const A *apart, int napart, A *sh) {
+template <typename A> __device__ A lz_alpha(LzState<A> *st, const A *apart, int napart, A *sh, bool store) {
   __shared__ A alpha_s;
   if (!apart) return st->alpha[st->m];
   A v = 0;
@@ -1234,7 +1246,7 @@ template <typename A> __device__ A lz_alpha(LzState<A> *st, const A *apart, int 
   v = block_sum(v, sh);
   if (threadIdx.x == 0) {
     alpha_s = v;
-    if (blockIdx.x == 0) st->alpha[st->m] = v;
+    if (store) st->alpha[st->m] = v;
   }
   __syncthreads();
   return alpha_s;
@@ -1248,7 +1260,7 @@ __global__ void k_lz_update(const typename vec4<T>::type *__restrict__ t, const 
   __shared__ A sh[16];
   if (st->done) return;
   const int m = st->m;
-  const T al = (T)lz_alpha(st, apart, napart, sh);
+  const T al = (T)lz_alpha(st, apart, napart, sh, blockIdx.x == 0);
   const T be = m > 0 ? (T)st->beta[m] : T(0);
   A v = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1283,7 +1295,7 @@ __global__ void k_lz_update_pc(const typename vec4<T>::type *__restrict__ t,
   __shared__ A sh[16];
   if (st->done) return;
   const int m = st->m;
-  const T al = (T)lz_alpha(st, apart, napart, sh);
+  const T al = (T)lz_alpha(st, apart, napart, sh, blockIdx.x == 0);
   const T be = m > 0 ? (T)st->beta[m] : T(0);
   A v = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1390,8 +1402,8 @@ __device__ A tridiag_sqrt_e1(int n, A d, A e, A *Q, int &ok) {
 // |s_{m+1} - s_m| <= tol |s_{m+1}| (successive iterates; V orthonormal), and
 // the scale 1/beta_{m+1} of the next Lanczos vector.  One wavefront.
 template <typename A>
-__global__ __launch_bounds__(64) void k_lz_check(const A *__restrict__ partials, int nparts, LzState<A> *st, A tol,
-                                                 int max_iter) {
+__device__ __forceinline__ void lz_check_body(const A *__restrict__ partials, int nparts, LzState<A> *st, A tol,
+                                              int max_iter) {
   __shared__ A Q[kMaxIter * 64];
   if (st->done) return;
   const int lane = threadIdx.x;
@@ -1436,6 +1448,95 @@ __global__ __launch_bounds__(64) void k_lz_check(const A *__restrict__ partials,
     st->done = conv || !finite || nn >= max_iter;
     st->inv_beta = bb > A(0) ? A(1) / bb : A(0);
   }
+}
+
+template <typename A>
+__global__ __launch_bounds__(64) void k_lz_check(const A *__restrict__ partials, int nparts, LzState<A> *st, A tol,
+                                                 int max_iter) {
+  lz_check_body<A>(partials, nparts, st, tol, max_iter);
+}
+
+// ------------------------------------------------- batched Krylov loop
+// Iteration m of the Lanczos process on many systems at once (a batch of
+// replicas): the same arithmetic, in the same order, as the single-system
+// kernels above, so that every system's iterate is bit-identical to its own
+// run.  pmap / vmap list (system, block of that system) per workgroup: the
+// product's blocks of B^3 cells, and the vector kernels' blocks of 256
+// particles (n <= kRedBlock 256 per system, so that each thread owns at most
+// one particle, as in the single-system kernels).
+template <int B, bool UNWRAP, typename A, int G>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmv_lds_batch(
+    const LzRep<A> *__restrict__ reps, const int2 *__restrict__ pmap, int m) {
+  const int2 rb = pmap[blockIdx.x];
+  const LzRep<A> &r = reps[rb.x];
+  spmv_lds_block<B, UNWRAP, A, true, false, G>(r.pos, m == 0 ? r.z : r.w, r.cell_start, r.nc, r.cs, r.n, r.hcap,
+                                               r.L, r.invL, r.nbr, r.cnt, r.tab, r.inv_dr, r.self_r, 1.0f, r.t,
+                                               r.V + (size_t)m * r.n, r.st, r.ovf, nullptr, nullptr, rb.y);
+}
+
+template <typename A>
+__global__ __launch_bounds__(256) void k_lz_alpha_batch(const LzRep<A> *__restrict__ reps,
+                                                        const int2 *__restrict__ vmap, int m) {
+  __shared__ A sh[16];
+  const int2 rb = vmap[blockIdx.x];
+  const LzRep<A> &r = reps[rb.x];
+  if (r.st->done) return;
+  const float4 *vm = r.V + (size_t)m * r.n;
+  A *part = r.partials + kRedBlock;
+  A v = 0;
+  const int i = rb.y * 256 + (int)threadIdx.x;
+  if (i < r.n) {
+    const float4 a = r.t[i], b = vm[i];
+    v += (A)a.x * (A)b.x + (A)a.y * (A)b.y + (A)a.z * (A)b.z;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[rb.y] = v;
+  if (rb.y == 0)  // the blocks past the system's particles hold 0, as a single-system launch writes them
+    for (int k = (r.n + 255) / 256 + (int)threadIdx.x; k < kRedBlock; k += 256) part[k] = A(0);
+}
+
+template <typename A>
+__global__ __launch_bounds__(256) void k_lz_update_batch(const LzRep<A> *__restrict__ reps,
+                                                         const int2 *__restrict__ vmap, int m) {
+  __shared__ A sh[16];
+  const int2 rb = vmap[blockIdx.x];
+  const LzRep<A> &r = reps[rb.x];
+  LzState<A> *st = r.st;
+  if (st->done) return;
+  const int mm = st->m;
+  const float al = (float)lz_alpha(st, r.partials + kRedBlock, kRedBlock, sh, rb.y == 0);
+  const float be = mm > 0 ? (float)st->beta[mm] : 0.0f;
+  const float4 *vm = r.V + (size_t)m * r.n;
+  const float4 *vprev = m > 0 ? r.V + (size_t)(m - 1) * r.n : r.V;
+  A v = 0;
+  const int i = rb.y * 256 + (int)threadIdx.x;
+  if (i < r.n) {
+    const float4 a = r.t[i], b = vm[i];
+    float4 x;
+    x.x = a.x - al * b.x;
+    x.y = a.y - al * b.y;
+    x.z = a.z - al * b.z;
+    if (mm > 0) {
+      const float4 c = vprev[i];
+      x.x -= be * c.x;
+      x.y -= be * c.y;
+      x.z -= be * c.z;
+    }
+    x.w = 0.0f;
+    r.w[i] = x;
+    v += (A)x.x * (A)x.x + (A)x.y * (A)x.y + (A)x.z * (A)x.z;
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) r.partials[rb.y] = v;
+  if (rb.y == 0)
+    for (int k = (r.n + 255) / 256 + (int)threadIdx.x; k < kRedBlock; k += 256) r.partials[k] = A(0);
+}
+
+// one wavefront per system
+template <typename A>
+__global__ __launch_bounds__(64) void k_lz_check_batch(const LzRep<A> *__restrict__ reps) {
+  const LzRep<A> &r = reps[blockIdx.x];
+  lz_check_body<A>(r.partials, kRedBlock, r.st, r.tol, r.maxit);
 }
 
 // y = beta_0 sum_{j < m} V_j s_j  (sorted order, length 3n)
@@ -1980,6 +2081,40 @@ void launch_lz_iter_pc(pse_ctx *c, int m, const void *z) {
   k_lz_check<A><<<1, 64, 0, c->stream>>>((const A *)c->partials, kRedBlock, (LzState<A> *)c->lz,
                                          (A)c->p.lanczos_tol, c->lz_maxit);
 }
+
+// One iteration of the batched Krylov loop: the product of every group of
+// systems sharing a block edge, halo form and lanes per target, then the
+// vector kernels and the checks of all systems.
+template <typename A>
+void launch_lz_batch_iter(hipStream_t s, const LzRep<A> *reps, int nrep, const LzGroup *groups, int ngroups,
+                          const int2 *vmap, int nvblk, int m) {
+  for (int g = 0; g < ngroups; ++g) {
+    const LzGroup &gr = groups[g];
+    with_block_edge(gr.B, [&](auto b) {
+      constexpr int BE = decltype(b)::value;
+      auto go = [&](auto kernel) {
+        allow_lds(kernel, gr.smem);
+        kernel<<<gr.nblk, 1024, gr.smem, s>>>(reps, gr.pmap, m);
+      };
+      auto pick = [&](auto gl) {
+        constexpr int GL = decltype(gl)::value;
+        if (gr.unwrap) go(k_spmv_lds_batch<BE, true, A, GL>);
+        else go(k_spmv_lds_batch<BE, false, A, GL>);
+      };
+      if (gr.G == 2) pick(std::integral_constant<int, 2>{});
+      else if (gr.G == 4) pick(std::integral_constant<int, 4>{});
+      else pick(std::integral_constant<int, 3>{});
+    });
+  }
+  k_lz_alpha_batch<A><<<nvblk, 256, 0, s>>>(reps, vmap, m);
+  k_lz_update_batch<A><<<nvblk, 256, 0, s>>>(reps, vmap, m);
+  k_lz_check_batch<A><<<nrep, 64, 0, s>>>(reps);
+}
+template void launch_lz_batch_iter<float>(hipStream_t, const LzRep<float> *, int, const LzGroup *, int, const int2 *,
+                                          int, int);
+template void launch_lz_batch_iter<double>(hipStream_t, const LzRep<double> *, int, const LzGroup *, int,
+                                           const int2 *, int, int);
+
 
 template <typename T, typename A>
 void launch_lz_combine(pse_ctx *c, void *y) {

@@ -67,11 +67,17 @@ template <typename T> void launch_pc_apply_inv(pse_ctx *c, void *y);  // y = P^-
 void launch_unsort_features(pse_ctx *c, void *out);
 template <typename T> void launch_unsort_blocks(pse_ctx *c, float *out);
 template <typename T, typename A> void launch_lz_iter_pc(pse_ctx *c, int m, const void *z);
+// iteration m of the Lanczos process on nrep systems at once (FP32 storage,
+// LDS product, no preconditioner): bit-identical to launch_lz_iter per system
+template <typename A>
+void launch_lz_batch_iter(hipStream_t s, const LzRep<A> *reps, int nrep, const LzGroup *groups, int ngroups,
+                          const int2 *vmap, int nvblk, int m);
 
 // grid side (k_grid.hip)
 //   FftZ:       a = src, b = dst, x = direction (-1 forward R2C, +1 inverse C2R)
-//   FftZAos:    as FftZ with the real side interleaved (one (c0, c1, c2, 0)
-//               vector per node): forward reads it, inverse writes it
+//   FftZAos:    as FftZ with the real side one vector per node: forward
+//               reads the interleaved grid ((c0, c1, c2, 0) per node),
+//               inverse writes the packed grid ((c0, c1, c2) per node)
 //   FftStrided: b = data, x = axis (0: x, 1: y), y = direction
 //   XFused:     a = transformed grid-noise spectrum (or null), b = data,
 //               x = forces present, y = noise (0 none, 1 Philox, 2 grid noise)
@@ -79,7 +85,8 @@ template <typename T> void launch_grid_op(pse_ctx *c, GridOp op, const void *a, 
 template <typename T> void launch_spread_interp(pse_ctx *c, bool spread, const void *vec, void *grid_or_out);
 // Spreading writes the interleaved real grid (one (c0, c1, c2, 0) vector per
 // node) and clears it itself (every node written once, or cleared before the
-// atomic fallback): no separate clear is needed.  Interpolation reads it.
+// atomic fallback): no separate clear is needed.  Interpolation reads the
+// packed grid that the inverse z pass writes.
 bool spread_writes_whole_grid(int M, int P);
 // times the valid spreading tile depths and interpolation workgroup sizes on
 // the current positions and keeps the fastest (c->tune_*)

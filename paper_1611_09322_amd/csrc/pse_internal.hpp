@@ -101,6 +101,34 @@ template <typename A> struct LzState {
   int nonfinite;
 };
 
+// One system of a batched Krylov loop: what the LDS product and the
+// Lanczos vector kernels of a single system take as arguments (FP32
+// storage, sorted order).
+template <typename A> struct LzRep {
+  const float4 *pos;        // sorted positions (x, y, z, 0)
+  const int *cell_start;    // [ncell + 1]
+  const uint16_t *nbr;      // halo-local neighbour list (chunks of 8)
+  const int *cnt;           // entries per target
+  const float2 *tab;        // (mu0 F, mu0 (G - F)) table
+  int *ovf;                 // halo overflow flag
+  const float4 *z;          // start vector
+  float4 *t, *w, *V;        // product, residual, basis [maxit][n]
+  LzState<A> *st;
+  A *partials;              // [0, kRedBlock): |w|^2; [kRedBlock, 2 kRedBlock): alpha_m
+  float cs, L, invL, inv_dr, self_r;
+  int nc, n, hcap, maxit;
+  A tol;
+};
+
+// The systems of a batched Krylov loop whose LDS products share one kernel:
+// block edge B, lanes per target G, halo form; pmap lists (system, block)
+// for each of the nblk workgroups, smem the largest halo's LDS.
+struct LzGroup {
+  int B, G, unwrap, nblk;
+  size_t smem;
+  const int2 *pmap;
+};
+
 // Coefficients of the wave-space scaling applied per k (fused x pass).
 struct WaveCoef {
   double two_pi_over_L;  // k = 2 pi j / L
@@ -178,6 +206,7 @@ struct pse_ctx {
   int graph_iters = 0;              // Lanczos iterations queued per sample in graph mode
   const uint64_t *rng_dev = nullptr;  // device (seed, counter) of the Philox noise, or null
   bool graph_stale = false;         // a buffer the captured graph uses was reallocated
+  bool lz_external = false;         // graph mode: the Lanczos iterations run in the batch's batched loop
   int last_iters = 4;
   int lz_maxit = 0;         // near-field Lanczos iterations at most: min(lanczos_max_iter, kMaxIter)
   // full-mobility Krylov sample (PSE_FLAG_FULL_LANCZOS)
@@ -211,7 +240,8 @@ struct pse_ctx {
   double series_h[2 * pse::kSeriesTerms];
   double small_r2 = 0;      // r^2 below which the series is used
   void *grid = nullptr;     // T [3 M^3]: planar half spectrum [c][jx][jy][jz < M/2] (complex)
-  void *rgrid = nullptr;    // T4 [M^3]: interleaved real grid, nodes [x][y][z] of (c0, c1, c2, 0)
+  void *rgrid = nullptr;    // T4 [M^3]: real grid, nodes [x][y][z]: interleaved (c0, c1, c2, 0) after
+                            // spreading, packed (c0, c1, c2) after the inverse z pass
   void *grid2 = nullptr;    // T [3 M^3]: spectrum of caller grid noise W (absent with PSE_FLAG_NOISE_KSPACE)
   void *tw_M = nullptr;     // T2 [M] twiddles exp(-2 pi i k / M)
   void *tw_H = nullptr;     // T2 [M/2]
