@@ -158,6 +158,7 @@ pse_status lz_start(pse_ctx *c, const void *z_sorted) {
     else launch_lz_iter<T, A>(c, i, z_sorted);
   }
   c->lz_launched = k;
+  if (c->status_external) return hip_status(hipGetLastError());  // read back with the batch's status
   return hip_status(hipMemcpyAsync(c->lz_h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream));
 }
 
@@ -177,7 +178,7 @@ pse_status lz_finish(pse_ctx *c, const void *z_sorted, void *y_sorted, pse_stats
     // captured: the iterate of the iterations queued by lz_start (or by the
     // batch); the state copied back tells the host after the replay
     // whether they sufficed
-    if (c->lz_external &&
+    if (c->lz_external && !c->status_external &&
         hipMemcpyAsync(c->lz_h, c->lz, sizeof(LzState<A>), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
       return PSE_ERR_HIP;
     launch_lz_combine<T, A>(c, y_sorted);
@@ -331,6 +332,7 @@ pse_status sample_end(pse_ctx *c, const SampleState &ss, double dt, void *disp, 
   if (c->graph) {
     // the device flags of this step (list and halo overflow, non-finite
     // positions) for the host's check after the replay
+    if (c->status_external) return hip_status(hipGetLastError());
     return hip_status(hipMemcpyAsync(c->flags_h, c->flags, sizeof(int) * 8, hipMemcpyDeviceToHost, c->stream));
   }
   if (stats) {
@@ -393,7 +395,8 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
     if (c->pc_on) {
       if (c->lds_B && !c->pc_fixed) launch_feat_lds(c);
       launch_pc_blocks<T>(c);
-      if (hipMemcpyAsync(c->pc_fb_h, c->flags + 6, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      if (!c->status_external &&
+          hipMemcpyAsync(c->pc_fb_h, c->flags + 6, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
         return PSE_ERR_HIP;
       c->pc_fb_pending = true;
     }
@@ -682,6 +685,9 @@ struct pse_batch {
     int nrep = 0, nv = 0, iters = 0;
     std::vector<int> members;  // replica of each LzRep
   } lzb[2];
+  // status of every replica after a replay (one kernel, one copy)
+  pse::RepStatusSrc *stat_src = nullptr;
+  pse::RepStatus *stat_d = nullptr, *stat_h = nullptr;
 };
 
 namespace pse {
@@ -753,6 +759,11 @@ static void free_graph(pse_batch *b) {
     if (z.maps) (void)hipFree(z.maps);
     z = pse_batch::LzBatch{};
   }
+  if (b->stat_src) (void)hipFree(b->stat_src);
+  if (b->stat_d) (void)hipFree(b->stat_d);
+  if (b->stat_h) (void)hipHostFree(b->stat_h);
+  b->stat_src = nullptr;
+  b->stat_d = b->stat_h = nullptr;
 }
 
 static void free_batch(pse_batch *b) {
@@ -1304,6 +1315,16 @@ static pse_status batch_capture(pse_batch *b) {
   pse_status st0 = lzb_setup<float>(b);
   if (st0 == PSE_OK) st0 = lzb_setup<double>(b);
   if (st0 != PSE_OK) return st0;
+  {
+    std::vector<RepStatusSrc> src(R);
+    for (int r = 0; r < R; ++r) src[r] = RepStatusSrc{b->ctx[r]->flags, b->ctx[r]->lz, b->ctx[r]->acc_dbl ? 1 : 0};
+    if (hipMalloc((void **)&b->stat_src, sizeof(RepStatusSrc) * R) != hipSuccess ||
+        hipMalloc((void **)&b->stat_d, sizeof(RepStatus) * R) != hipSuccess ||
+        hipHostMalloc((void **)&b->stat_h, sizeof(RepStatus) * R, hipHostMallocDefault) != hipSuccess)
+      return PSE_ERR_OOM;
+    if (hipMemcpy(b->stat_src, src.data(), sizeof(RepStatusSrc) * R, hipMemcpyHostToDevice) != hipSuccess)
+      return PSE_ERR_HIP;
+  }
   std::vector<uint32_t> prof(R);
   for (int r = 0; r < R; ++r) {
     pse_ctx *c = b->ctx[r];
@@ -1314,6 +1335,7 @@ static pse_status batch_capture(pse_batch *b) {
   }
   for (const auto &z : b->lzb)
     for (int r : z.members) b->ctx[r]->lz_external = true;
+  for (pse_ctx *c : b->ctx) c->status_external = true;
   pse_status st = hip_status(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeRelaxed));
   if (st == PSE_OK)
     st = hip_status(hipMemcpyAsync(b->rng_d, b->rng_h, sizeof(uint64_t) * 2 * R, hipMemcpyHostToDevice, b->gstream));
@@ -1338,6 +1360,10 @@ static pse_status batch_capture(pse_batch *b) {
   for (int r = 0; r < R && st == PSE_OK; ++r)
     st = ctx_end(b->ctx[r], ss[r], b->g_dt, b->g_disp[r], nullptr);
   if (st == PSE_OK) st = join(b, b->gstream);
+  if (st == PSE_OK) {
+    launch_batch_status(b->gstream, b->stat_src, R, b->stat_d);
+    st = hip_status(hipMemcpyAsync(b->stat_h, b->stat_d, sizeof(RepStatus) * R, hipMemcpyDeviceToHost, b->gstream));
+  }
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(b->gstream, &g);
   for (int r = 0; r < R; ++r) {
@@ -1346,6 +1372,7 @@ static pse_status batch_capture(pse_batch *b) {
     c->graph = false;
     c->rng_dev = nullptr;
     c->lz_external = false;
+    c->status_external = false;
   }
   if (st == PSE_OK && ec != hipSuccess) st = PSE_ERR_HIP;
   if (st != PSE_OK) {
@@ -1433,6 +1460,28 @@ pse_status pse_batch_graph_step(pse_batch *b, uint64_t seed, uint64_t counter, p
       hipGraphLaunch(b->gexec, b->gstream) != hipSuccess || hipEventRecord(b->g_out, b->gstream) != hipSuccess ||
       hipStreamWaitEvent(b->user, b->g_out, 0) != hipSuccess || hipStreamSynchronize(b->gstream) != hipSuccess)
     return PSE_ERR_HIP;
+  // the replay's status into each replica's host copies
+  for (int r = 0; r < R; ++r) {
+    pse_ctx *c = b->ctx[r];
+    const RepStatus &q = b->stat_h[r];
+    std::memcpy(c->flags_h, q.flags, sizeof(int) * 8);
+    if (c->pc_on) *c->pc_fb_h = q.flags[6];
+    if (c->dbl || c->acc_dbl) {
+      auto *h = (LzState<double> *)c->lz_h;
+      h->m = q.m;
+      h->done = q.done;
+      h->converged = q.converged;
+      h->nonfinite = q.nonfinite;
+      h->rel_change = q.rel_change;
+    } else {
+      auto *h = (LzState<float> *)c->lz_h;
+      h->m = q.m;
+      h->done = q.done;
+      h->converged = q.converged;
+      h->nonfinite = q.nonfinite;
+      h->rel_change = (float)q.rel_change;
+    }
+  }
   pse_status w = PSE_OK;
   int nredo = 0;
   for (int r = 0; r < R; ++r) {

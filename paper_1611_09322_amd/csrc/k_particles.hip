@@ -2110,6 +2110,34 @@ void launch_lz_batch_iter(hipStream_t s, const LzRep<A> *reps, int nrep, const L
   k_lz_update_batch<A><<<nvblk, 256, 0, s>>>(reps, vmap, m);
   k_lz_check_batch<A><<<nrep, 64, 0, s>>>(reps);
 }
+__global__ void k_batch_status(const RepStatusSrc *__restrict__ src, int nrep, RepStatus *__restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrep) return;
+  const RepStatusSrc q = src[r];
+  RepStatus o;
+  for (int k = 0; k < 8; ++k) o.flags[k] = q.flags[k];
+  if (q.acc_dbl) {
+    const auto *st = (const LzState<double> *)q.lz;
+    o.m = st->m;
+    o.done = st->done;
+    o.converged = st->converged;
+    o.nonfinite = st->nonfinite;
+    o.rel_change = st->rel_change;
+  } else {
+    const auto *st = (const LzState<float> *)q.lz;
+    o.m = st->m;
+    o.done = st->done;
+    o.converged = st->converged;
+    o.nonfinite = st->nonfinite;
+    o.rel_change = (double)st->rel_change;
+  }
+  out[r] = o;
+}
+
+void launch_batch_status(hipStream_t s, const RepStatusSrc *src, int nrep, RepStatus *out) {
+  k_batch_status<<<(nrep + 63) / 64, 64, 0, s>>>(src, nrep, out);
+}
+
 template void launch_lz_batch_iter<float>(hipStream_t, const LzRep<float> *, int, const LzGroup *, int, const int2 *,
                                           int, int);
 template void launch_lz_batch_iter<double>(hipStream_t, const LzRep<double> *, int, const LzGroup *, int,

@@ -72,6 +72,8 @@ template <typename T, typename A> void launch_lz_iter_pc(pse_ctx *c, int m, cons
 template <typename A>
 void launch_lz_batch_iter(hipStream_t s, const LzRep<A> *reps, int nrep, const LzGroup *groups, int ngroups,
                           const int2 *vmap, int nvblk, int m);
+// out[r] = flags and Krylov outcome of replica r
+void launch_batch_status(hipStream_t s, const RepStatusSrc *src, int nrep, RepStatus *out);
 
 // grid side (k_grid.hip)
 //   FftZ:       a = src, b = dst, x = direction (-1 forward R2C, +1 inverse C2R)

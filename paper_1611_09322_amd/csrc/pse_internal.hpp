@@ -129,6 +129,20 @@ struct LzGroup {
   const int2 *pmap;
 };
 
+// What the host reads back from each replica after a captured batch step:
+// the device flags and the Krylov state's outcome, gathered into one array
+// by one kernel so that the step needs a single copy.
+struct RepStatusSrc {
+  const int *flags;  // [8]
+  const void *lz;    // LzState<double> (acc_dbl) or LzState<float>
+  int acc_dbl;
+};
+struct RepStatus {
+  int flags[8];
+  int m, done, converged, nonfinite;
+  double rel_change;
+};
+
 // Coefficients of the wave-space scaling applied per k (fused x pass).
 struct WaveCoef {
   double two_pi_over_L;  // k = 2 pi j / L
@@ -207,6 +221,7 @@ struct pse_ctx {
   const uint64_t *rng_dev = nullptr;  // device (seed, counter) of the Philox noise, or null
   bool graph_stale = false;         // a buffer the captured graph uses was reallocated
   bool lz_external = false;         // graph mode: the Lanczos iterations run in the batch's batched loop
+  bool status_external = false;     // graph mode: the batch reads flags and Krylov state back for all replicas
   int last_iters = 4;
   int lz_maxit = 0;         // near-field Lanczos iterations at most: min(lanczos_max_iter, kMaxIter)
   // full-mobility Krylov sample (PSE_FLAG_FULL_LANCZOS)
