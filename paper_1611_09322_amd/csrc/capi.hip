@@ -120,6 +120,15 @@ WaveCoef wave_coef(const pse_ctx *c, double det_scale, double sto_scale, uint64_
   return w;
 }
 
+// The wave-space coefficients of a step of length dt: deterministic factor
+// dt / (eta M^3), stochastic factor sqrt(2 kT dt) / sqrt(eta V).
+WaveCoef step_wave_coef(const pse_ctx *c, double dt, uint64_t seed, uint64_t counter) {
+  const double cr = std::sqrt(2.0 * c->p.kT * dt);
+  const double V = c->d.L * c->d.L * c->d.L;
+  const double M3 = (double)c->p.grid * c->p.grid * c->p.grid;
+  return wave_coef(c, dt / (c->p.eta * M3), cr / std::sqrt(c->p.eta * V), seed, counter);
+}
+
 pse_status hip_status(hipError_t e) { return e == hipSuccess ? PSE_OK : PSE_ERR_HIP; }
 
 hipEvent_t next_event(pse_ctx *c) {
@@ -308,10 +317,9 @@ pse_status sample_begin(pse_ctx *c, bool philox, uint64_t seed, uint64_t counter
     else launch_gather3<T>(c, forces, f_s);
     launch_spmv<T, A>(c, f_s, ur, false, nullptr);
   }
-  const double V = c->d.L * c->d.L * c->d.L;
-  const double M3 = (double)c->p.grid * c->p.grid * c->p.grid;
-  WaveCoef wc = wave_coef(c, dt / (c->p.eta * M3), ss.cr / std::sqrt(c->p.eta * V), seed, counter);
+  const WaveCoef wc = step_wave_coef(c, dt, seed, counter);
   const int noise = (ss.cr > 0) ? (philox ? 1 : (W ? 2 : 0)) : 0;
+  if (c->wave_external) return hip_status(hipGetLastError());  // the batch launches it
   return wave_core<T>(c, ss.forces ? f_s : nullptr, noise, W, wc, wave);
 }
 
@@ -685,6 +693,12 @@ struct pse_batch {
     int nrep = 0, nv = 0, iters = 0;
     std::vector<int> members;  // replica of each LzRep
   } lzb[2];
+  // batched wave-space part of the captured step (replicas without forces,
+  // FP32 storage, kT > 0)
+  pse::WaveRep *wv_reps = nullptr;
+  int2 *wv_imap = nullptr;
+  std::vector<pse::WaveGroup> wv_groups;
+  std::vector<int> wv_members;
   // status of every replica after a replay (one kernel, one copy)
   pse::RepStatusSrc *stat_src = nullptr;
   pse::RepStatus *stat_d = nullptr, *stat_h = nullptr;
@@ -759,6 +773,12 @@ static void free_graph(pse_batch *b) {
     if (z.maps) (void)hipFree(z.maps);
     z = pse_batch::LzBatch{};
   }
+  if (b->wv_reps) (void)hipFree(b->wv_reps);
+  if (b->wv_imap) (void)hipFree(b->wv_imap);
+  b->wv_reps = nullptr;
+  b->wv_imap = nullptr;
+  b->wv_groups.clear();
+  b->wv_members.clear();
   if (b->stat_src) (void)hipFree(b->stat_src);
   if (b->stat_d) (void)hipFree(b->stat_d);
   if (b->stat_h) (void)hipHostFree(b->stat_h);
@@ -1281,6 +1301,80 @@ template <typename A> static void lzb_launch(pse_batch *b) {
                             z.vmap, z.nv, m);
 }
 
+// The batched wave-space part of a captured step: every replica with FP32
+// storage, kT > 0 and no forces, grouped by grid size, support and
+// interpolation workgroup size, with the coefficients sample_begin would
+// use (key and counter from the replica's device pair).  After the
+// replicas' rng_dev is set, before the capture.
+static pse_status wave_setup(pse_batch *b) {
+  const int R = (int)b->ctx.size();
+  if (!b->g_forces.empty()) return PSE_OK;
+  struct Key {
+    int M, P, nt;
+  };
+  std::vector<Key> keys;
+  std::vector<std::vector<int>> mem;
+  for (int r = 0; r < R; ++r) {
+    pse_ctx *c = b->ctx[r];
+    if (c->dbl || !(c->p.kT > 0)) continue;
+    const Key k{c->p.grid, c->p.support, c->tune_interp_threads ? c->tune_interp_threads : 1024};
+    size_t g = 0;
+    while (g < keys.size() && !(keys[g].M == k.M && keys[g].P == k.P && keys[g].nt == k.nt)) ++g;
+    if (g == keys.size()) {
+      keys.push_back(k);
+      mem.emplace_back();
+    }
+    mem[g].push_back(r);
+  }
+  if (keys.empty()) return PSE_OK;
+  const double pi = 3.14159265358979323846;
+  std::vector<WaveRep> reps;
+  std::vector<int2> imap;
+  std::vector<std::pair<size_t, size_t>> span;  // (first rep, first map entry) per group
+  for (size_t g = 0; g < keys.size(); ++g) {
+    span.emplace_back(reps.size(), imap.size());
+    for (int r : mem[g]) {
+      pse_ctx *c = b->ctx[r];
+      const int k = (int)(reps.size() - span[g].first);
+      const double h = c->d.h, s2 = c->d.sigma * c->d.sigma;
+      const double norm = std::pow(2.0 * pi * s2, -1.5);
+      WaveRep w{};
+      w.spec = (float2 *)c->grid;
+      w.rgrid = (float *)c->rgrid;
+      w.tw_M = (const float2 *)c->tw_M;
+      w.tw_H = (const float2 *)c->tw_H;
+      w.pos = (const float4 *)c->pos_s;
+      w.out = (float4 *)c->vbuf[4];
+      w.wc = step_wave_coef(c, b->g_dt, 0, 0);
+      w.n = c->n;
+      w.M = c->p.grid;
+      w.h = (float)h;
+      w.invh = (float)(1.0 / h);
+      w.inv2s2 = (float)(0.5 / s2);
+      w.norm_h3 = (float)(norm * h * h * h);
+      reps.push_back(w);
+      b->wv_members.push_back(r);
+      const int nt = keys[g].nt;
+      const int nb = (int)(((long)c->n * 64 + nt - 1) / nt);
+      for (int q = 0; q < nb; ++q) imap.push_back(make_int2(k, q));
+    }
+  }
+  if (hipMalloc((void **)&b->wv_reps, sizeof(WaveRep) * reps.size()) != hipSuccess ||
+      hipMalloc((void **)&b->wv_imap, sizeof(int2) * imap.size()) != hipSuccess)
+    return PSE_ERR_OOM;
+  if (hipMemcpy(b->wv_reps, reps.data(), sizeof(WaveRep) * reps.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->wv_imap, imap.data(), sizeof(int2) * imap.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return PSE_ERR_HIP;
+  for (size_t g = 0; g < keys.size(); ++g) {
+    const size_t r1 = g + 1 < keys.size() ? span[g + 1].first : reps.size();
+    const size_t m1 = g + 1 < keys.size() ? span[g + 1].second : imap.size();
+    b->wv_groups.push_back(WaveGroup{keys[g].M, keys[g].P, keys[g].nt, (int)(r1 - span[g].first),
+                                     (int)(m1 - span[g].second), b->wv_reps + span[g].first,
+                                     b->wv_imap + span[g].second});
+  }
+  return PSE_OK;
+}
+
 // Capture one batch step (every replica's set_positions and sample, on the
 // replicas' streams) into b->gexec.  Capacities get the headroom first
 // (outside the capture: the list may be reallocated); inside the capture no
@@ -1333,8 +1427,18 @@ static pse_status batch_capture(pse_batch *b) {
     c->graph = true;
     c->rng_dev = b->rng_d + 2 * r;
   }
+  st0 = wave_setup(b);
+  if (st0 != PSE_OK) {
+    for (int r = 0; r < R; ++r) {
+      b->ctx[r]->prof_mask = prof[r];
+      b->ctx[r]->graph = false;
+      b->ctx[r]->rng_dev = nullptr;
+    }
+    return st0;
+  }
   for (const auto &z : b->lzb)
     for (int r : z.members) b->ctx[r]->lz_external = true;
+  for (int r : b->wv_members) b->ctx[r]->wave_external = true;
   for (pse_ctx *c : b->ctx) c->status_external = true;
   pse_status st = hip_status(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeRelaxed));
   if (st == PSE_OK)
@@ -1348,11 +1452,12 @@ static pse_status batch_capture(pse_batch *b) {
     st = ctx_set_positions(c, b->g_pos[r]);
     if (st == PSE_OK) st = ctx_begin(c, 0, 0, b->g_dt, b->g_forces.empty() ? nullptr : b->g_forces[r], ss[r]);
   }
-  if (st == PSE_OK && (b->lzb[0].nrep || b->lzb[1].nrep)) {
+  if (st == PSE_OK && (b->lzb[0].nrep || b->lzb[1].nrep || !b->wv_groups.empty())) {
     st = join(b, b->gstream);
     if (st == PSE_OK) {
       lzb_launch<float>(b);
       lzb_launch<double>(b);
+      launch_wave_batch(b->gstream, b->wv_groups.data(), (int)b->wv_groups.size());
       st = hip_status(hipGetLastError());
     }
     if (st == PSE_OK) st = fork(b, b->gstream);
@@ -1373,6 +1478,7 @@ static pse_status batch_capture(pse_batch *b) {
     c->rng_dev = nullptr;
     c->lz_external = false;
     c->status_external = false;
+    c->wave_external = false;
   }
   if (st == PSE_OK && ec != hipSuccess) st = PSE_ERR_HIP;
   if (st != PSE_OK) {

@@ -240,8 +240,8 @@ __global__ __launch_bounds__(BLOCK) void k_fft_z(const C<T> *__restrict__ src, C
 // -> real, into the packed grid that interpolation reads (c0, c1, c2 per
 // node, no padding).  Same packing of the half spectrum as k_fft_z.
 template <typename T, int M, int DIR, int NXY, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_fft_z_aos(const void *__restrict__ src, void *__restrict__ dst,
-                                                     const C<T> *__restrict__ twH_g, const C<T> *__restrict__ twM_g) {
+DI void fft_z_aos_block(const void *__restrict__ src, void *__restrict__ dst, const C<T> *__restrict__ twH_g,
+                        const C<T> *__restrict__ twM_g, int bx) {
   using T4 = typename vec4<T>::type;
   constexpr int H = M / 2, NL = 3 * NXY;
   __shared__ C<T> buf[H * NL];
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(BLOCK) void k_fft_z_aos(const void *__restrict__ sr
     twH[i] = twH_g[i];
     twM[i] = twM_g[i];
   }
-  const size_t xy0 = (size_t)blockIdx.x * NXY;
+  const size_t xy0 = (size_t)bx * NXY;
   const size_t s_comp = (size_t)M * M;  // spectrum lines per component
   __syncthreads();
   if (DIR < 0) {
@@ -304,6 +304,12 @@ __global__ __launch_bounds__(BLOCK) void k_fft_z_aos(const void *__restrict__ sr
   }
 }
 
+template <typename T, int M, int DIR, int NXY, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fft_z_aos(const void *__restrict__ src, void *__restrict__ dst,
+                                                     const C<T> *__restrict__ twH_g, const C<T> *__restrict__ twM_g) {
+  fft_z_aos_block<T, M, DIR, NXY, BLOCK>(src, dst, twH_g, twM_g, blockIdx.x);
+}
+
 // ------------------------------------------------------- strided passes
 // 1D FFTs of length N along a strided axis for a tile of TZ consecutive jz
 // columns and NCOMP components: element n of column (comp, col) is at
@@ -326,16 +332,22 @@ DI void tile_store(const C<T> *buf, C<T> *data, size_t base, size_t s_fft, size_
 }
 
 template <typename T, int N, int DIR, int TZ, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_fft_strided(C<T> *__restrict__ data, size_t s_fft, size_t s_outer,
-                                                       size_t s_comp, const C<T> *__restrict__ tw_g) {
+DI void fft_strided_block(C<T> *__restrict__ data, size_t s_fft, size_t s_outer, size_t s_comp,
+                          const C<T> *__restrict__ tw_g, int bx, int by, int bz) {
   __shared__ C<T> buf[N * TZ];
   __shared__ C<T> tw[N];
   for (int i = threadIdx.x; i < N; i += BLOCK) tw[i] = tw_g[i];
-  const size_t base = (size_t)blockIdx.z * s_comp + (size_t)blockIdx.y * s_outer + (size_t)blockIdx.x * TZ;
+  const size_t base = (size_t)bz * s_comp + (size_t)by * s_outer + (size_t)bx * TZ;
   tile_load<T, N, TZ, 1>(buf, data, base, s_fft, s_comp, BLOCK);
   __syncthreads();
   fft_lds<T, N, DIR, TZ, BLOCK>(buf, tw);
   tile_store<T, N, TZ, 1>(buf, data, base, s_fft, s_comp, BLOCK);
+}
+
+template <typename T, int N, int DIR, int TZ, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fft_strided(C<T> *__restrict__ data, size_t s_fft, size_t s_outer,
+                                                       size_t s_comp, const C<T> *__restrict__ tw_g) {
+  fft_strided_block<T, N, DIR, TZ, BLOCK>(data, s_fft, s_outer, s_comp, tw_g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // --------------------------------------------------- Philox k-space noise
@@ -394,8 +406,8 @@ template <typename T> DI C<T> zeta_at(uint64_t e, uint64_t seed, uint64_t sample
 //   inverse x-FFT; store.  zeta: Philox (NOISE = 1) or the transformed grid
 //   noise times M^{-3/2} (NOISE = 2).  k = 0 and Nyquist indices give 0.
 template <typename T, int M, int TZ, int BLOCK, bool FORCES, int NOISE>
-__global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, const C<T> *__restrict__ specW,
-                                                       WaveCoef wc, const C<T> *__restrict__ tw_g) {
+DI void xpass_block(C<T> *__restrict__ data, const C<T> *__restrict__ specW, WaveCoef wc,
+                    const C<T> *__restrict__ tw_g, int bx, int by, int gx, int gy) {
   constexpr int H = M / 2;
   constexpr int NCOLS = 3 * TZ;
   __shared__ C<T> buf[M * NCOLS];
@@ -408,8 +420,8 @@ __global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, 
   for (int i = threadIdx.x; i < M; i += BLOCK) tw[i] = tw_g[i];
   const size_t s_fft = (size_t)M * H, s_comp = (size_t)M * M * H;
   // adjacent z tiles share cache lines: keep them on one XCD
-  const int lin = xcd_block(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-  const int jy = lin / gridDim.x, z0 = (lin % gridDim.x) * TZ;
+  const int lin = xcd_block(bx + by * gx, gx * gy);
+  const int jy = lin / gx, z0 = (lin % gx) * TZ;
   const size_t base = (size_t)jy * H + z0;
   if (FORCES) {
     tile_load<T, M, TZ, 3>(buf, data, base, s_fft, s_comp, BLOCK);
@@ -490,6 +502,12 @@ __global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, 
   tile_store<T, M, TZ, 3>(buf, data, base, s_fft, s_comp, BLOCK);
 }
 
+template <typename T, int M, int TZ, int BLOCK, bool FORCES, int NOISE>
+__global__ __launch_bounds__(BLOCK) void k_xpass_fused(C<T> *__restrict__ data, const C<T> *__restrict__ specW,
+                                                       WaveCoef wc, const C<T> *__restrict__ tw_g) {
+  xpass_block<T, M, TZ, BLOCK, FORCES, NOISE>(data, specW, wc, tw_g, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+}
+
 // e^x for the Gaussian weights (x <= 0).  FP32: the hardware base-2
 // exponential of x log2(e); the scaling adds a relative error of about
 // |x| 2^-24, below 1e-6 over a support (|x| <= pi P / 2).
@@ -562,14 +580,8 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 // (consecutive lanes read consecutive z nodes of one grid row, one packed
 // (c0, c1, c2) vector per node), loop over iy.
 template <typename T, int P>
-__global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *__restrict__ pos,
-                                                const T *__restrict__ grid, int n,
-                                                typename vec4<T>::type *__restrict__ out, int M, T h,
-                                                T invh, T inv2s2, T norm_h3) {
-  // particles are in cell order: XCD-contiguous ranges keep the grid
-  // nodes of neighbouring particles within one L2.  The particle is the
-  // wavefront's: its index and support origin are scalar values.
-  const int s = __builtin_amdgcn_readfirstlane((xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6);
+DI void interp_particle(const typename vec4<T>::type *__restrict__ pos, const T *__restrict__ grid, int n,
+                        typename vec4<T>::type *__restrict__ out, int M, T h, T invh, T inv2s2, T norm_h3, int s) {
   const int lane = threadIdx.x & 63;
   if (s >= n) return;
   const auto p = pos[s];
@@ -669,6 +681,18 @@ __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *_
     o.w = T(0);
     out[s] = o;
   }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *__restrict__ pos,
+                                                const T *__restrict__ grid, int n,
+                                                typename vec4<T>::type *__restrict__ out, int M, T h,
+                                                T invh, T inv2s2, T norm_h3) {
+  // particles are in cell order: XCD-contiguous ranges keep the grid
+  // nodes of neighbouring particles within one L2.  The particle is the
+  // wavefront's: its index and support origin are scalar values.
+  const int s = __builtin_amdgcn_readfirstlane((xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6);
+  interp_particle<T, P>(pos, grid, n, out, M, h, invh, inv2s2, norm_h3, s);
 }
 
 // Spreading, owner computes, no atomics: one workgroup owns a tile of
@@ -1021,6 +1045,82 @@ void launch_spread_interp(pse_ctx *c, bool spread, const void *vec, void *grid_o
     case 14: spread_interp_P<T, 14>(c, spread, vec, grid_or_out); break;
     case 16: spread_interp_P<T, 16>(c, spread, vec, grid_or_out); break;
     default: break;
+  }
+}
+
+// ------------------------------------------------- batched wave space
+// The launches of a system's wave-space part without forces, for every
+// system of a group at once: the system index is the last grid dimension
+// (x pass, z pass; y pass: component + 3 system) or comes from the block
+// map (interpolation).  Same block bodies as the single-system kernels.
+template <int M, int TZ>
+__global__ __launch_bounds__(256) void k_xpass_batch(const WaveRep *__restrict__ reps) {
+  const WaveRep &r = reps[blockIdx.z];
+  xpass_block<float, M, TZ, 256, false, 1>((C<float> *)r.spec, nullptr, r.wc, (const C<float> *)r.tw_M, blockIdx.x,
+                                           blockIdx.y, gridDim.x, gridDim.y);
+}
+
+template <int M, int TZ>
+__global__ __launch_bounds__(256) void k_fft_y_inv_batch(const WaveRep *__restrict__ reps) {
+  constexpr int H = M / 2;
+  const WaveRep &r = reps[blockIdx.z / 3];
+  fft_strided_block<float, M, +1, TZ, 256>((C<float> *)r.spec, (size_t)H, (size_t)M * H, (size_t)M * M * H,
+                                           (const C<float> *)r.tw_M, blockIdx.x, blockIdx.y, blockIdx.z % 3);
+}
+
+template <int M, int NXY>
+__global__ __launch_bounds__(256) void k_fft_z_inv_batch(const WaveRep *__restrict__ reps) {
+  const WaveRep &r = reps[blockIdx.y];
+  fft_z_aos_block<float, M, +1, NXY, 256>(r.spec, r.rgrid, (const C<float> *)r.tw_H, (const C<float> *)r.tw_M,
+                                          blockIdx.x);
+}
+
+template <int P>
+__global__ __launch_bounds__(1024) void k_interp_batch(const WaveRep *__restrict__ reps, const int2 *__restrict__ imap) {
+  const int2 rb = imap[xcd_block(blockIdx.x, gridDim.x)];
+  const WaveRep &r = reps[rb.x];
+  const int s = __builtin_amdgcn_readfirstlane((rb.y * (int)blockDim.x + (int)threadIdx.x) >> 6);
+  interp_particle<float, P>(r.pos, r.rgrid, r.n, r.out, r.M, r.h, r.invh, r.inv2s2, r.norm_h3, s);
+}
+
+template <int M> static void wave_batch_M(hipStream_t s, const WaveGroup &g) {
+  constexpr int H = M / 2;
+  constexpr int TZ = GridCfg<float, M>::TZ, TZ1 = GridCfg<float, M>::TZ1;
+  constexpr int NX0 = 24576 / (3 * M * (int)sizeof(float));
+  constexpr int NXY = NX0 >= 16 ? 16 : (NX0 >= 8 ? 8 : (NX0 >= 4 ? 4 : (NX0 >= 2 ? 2 : 1)));
+  k_xpass_batch<M, TZ><<<dim3(H / TZ, M, g.nrep), 256, 0, s>>>(g.reps);
+  k_fft_y_inv_batch<M, TZ1><<<dim3(H / TZ1, M, 3 * g.nrep), 256, 0, s>>>(g.reps);
+  k_fft_z_inv_batch<M, NXY><<<dim3(M * M / NXY, g.nrep), 256, 0, s>>>(g.reps);
+  switch (g.P) {
+    case 2: k_interp_batch<2><<<g.nimap, g.nt, 0, s>>>(g.reps, g.imap); break;
+    case 4: k_interp_batch<4><<<g.nimap, g.nt, 0, s>>>(g.reps, g.imap); break;
+    case 6: k_interp_batch<6><<<g.nimap, g.nt, 0, s>>>(g.reps, g.imap); break;
+    case 8: k_interp_batch<8><<<g.nimap, g.nt, 0, s>>>(g.reps, g.imap); break;
+    case 10: k_interp_batch<10><<<g.nimap, g.nt, 0, s>>>(g.reps, g.imap); break;
+    case 12: k_interp_batch<12><<<g.nimap, g.nt, 0, s>>>(g.reps, g.imap); break;
+    case 14: k_interp_batch<14><<<g.nimap, g.nt, 0, s>>>(g.reps, g.imap); break;
+    case 16: k_interp_batch<16><<<g.nimap, g.nt, 0, s>>>(g.reps, g.imap); break;
+    default: break;
+  }
+}
+
+void launch_wave_batch(hipStream_t s, const WaveGroup *groups, int ngroups) {
+  for (int i = 0; i < ngroups; ++i) {
+    const WaveGroup &g = groups[i];
+    switch (g.M) {
+      case 16: wave_batch_M<16>(s, g); break;
+      case 24: wave_batch_M<24>(s, g); break;
+      case 32: wave_batch_M<32>(s, g); break;
+      case 48: wave_batch_M<48>(s, g); break;
+      case 64: wave_batch_M<64>(s, g); break;
+      case 96: wave_batch_M<96>(s, g); break;
+      case 128: wave_batch_M<128>(s, g); break;
+      case 192: wave_batch_M<192>(s, g); break;
+      case 256: wave_batch_M<256>(s, g); break;
+      case 384: wave_batch_M<384>(s, g); break;
+      case 512: wave_batch_M<512>(s, g); break;
+      default: break;
+    }
   }
 }
 

@@ -72,6 +72,9 @@ template <typename T, typename A> void launch_lz_iter_pc(pse_ctx *c, int m, cons
 template <typename A>
 void launch_lz_batch_iter(hipStream_t s, const LzRep<A> *reps, int nrep, const LzGroup *groups, int ngroups,
                           const int2 *vmap, int nvblk, int m);
+// the wave-space part without forces of every system of the groups
+// (bit-identical to each system's own launches)
+void launch_wave_batch(hipStream_t s, const WaveGroup *groups, int ngroups);
 // out[r] = flags and Krylov outcome of replica r
 void launch_batch_status(hipStream_t s, const RepStatusSrc *src, int nrep, RepStatus *out);
 

@@ -157,6 +157,29 @@ struct WaveCoef {
   const uint64_t *rng;   // device (seed, counter) read in place of the two above, or null
 };
 
+// One system of a batched wave-space part without forces (FP32 storage):
+// the Philox k-space noise through the fused x pass, the inverse y and z
+// passes and the interpolation, with the system's own buffers and
+// coefficients.
+struct WaveRep {
+  float2 *spec;              // half spectrum [3][M][M][M/2]
+  float *rgrid;              // real grid (packed after the inverse z pass)
+  const float2 *tw_M, *tw_H;  // twiddles
+  const float4 *pos;         // sorted positions
+  float4 *out;               // wave-space displacement, sorted
+  WaveCoef wc;
+  int n, M;
+  float h, invh, inv2s2, norm_h3;
+};
+// The systems of one grid size, support and interpolation workgroup size:
+// nrep consecutive WaveRep records; imap lists (system, block) for the
+// interpolation's nimap workgroups.
+struct WaveGroup {
+  int M, P, nt, nrep, nimap;
+  const WaveRep *reps;
+  const int2 *imap;
+};
+
 // ---------------------------------------------------------------- host side
 struct Derived {
   double L, h, sigma, gm, eta_se, eps_real, eps_wave, eps_quad, eps_alias;
@@ -222,6 +245,7 @@ struct pse_ctx {
   bool graph_stale = false;         // a buffer the captured graph uses was reallocated
   bool lz_external = false;         // graph mode: the Lanczos iterations run in the batch's batched loop
   bool status_external = false;     // graph mode: the batch reads flags and Krylov state back for all replicas
+  bool wave_external = false;       // graph mode: the wave-space part runs in the batch's batched launches
   int last_iters = 4;
   int lz_maxit = 0;         // near-field Lanczos iterations at most: min(lanczos_max_iter, kMaxIter)
   // full-mobility Krylov sample (PSE_FLAG_FULL_LANCZOS)
