@@ -398,8 +398,11 @@ pse_status set_positions_impl(pse_ctx *c, const void *pos) {
   if (c->graph) {
     // captured: block edge, halo capacity and list capacity stay as fixed
     // at capture; the kernels flag what does not fit
-    if (c->lds_B) launch_nbr_lds(c);
-    else launch_nbr<T>(c);
+    if (c->lds_B) {
+      if (!c->nbr_external) launch_nbr_lds(c);  // else the batch's batched launch
+    } else {
+      launch_nbr<T>(c);
+    }
     if (c->pc_on) {
       if (c->lds_B && !c->pc_fixed) launch_feat_lds(c);
       launch_pc_blocks<T>(c);
@@ -693,6 +696,20 @@ struct pse_batch {
     int nrep = 0, nv = 0, iters = 0;
     std::vector<int> members;  // replica of each LzRep
   } lzb[2];
+  // replicas whose whole captured step is batched ([0] FP32, [1] FP64
+  // Lanczos scalars)
+  struct FullBatch {
+    pse::SampRep *reps = nullptr;
+    int2 *maps = nullptr;
+    pse::SampMaps m{};
+    std::vector<int> members;
+  } full[2];
+  std::vector<char> is_full;  // per replica
+  // batched neighbour build of the captured step (LDS path)
+  pse::NbrRep *nb_reps = nullptr;
+  int2 *nb_maps = nullptr;
+  std::vector<pse::NbrGroup> nb_groups;
+  std::vector<int> nb_members;
   // batched wave-space part of the captured step (replicas without forces,
   // FP32 storage, kT > 0)
   pse::WaveRep *wv_reps = nullptr;
@@ -773,6 +790,18 @@ static void free_graph(pse_batch *b) {
     if (z.maps) (void)hipFree(z.maps);
     z = pse_batch::LzBatch{};
   }
+  for (auto &f : b->full) {
+    if (f.reps) (void)hipFree(f.reps);
+    if (f.maps) (void)hipFree(f.maps);
+    f = pse_batch::FullBatch{};
+  }
+  b->is_full.clear();
+  if (b->nb_reps) (void)hipFree(b->nb_reps);
+  if (b->nb_maps) (void)hipFree(b->nb_maps);
+  b->nb_reps = nullptr;
+  b->nb_maps = nullptr;
+  b->nb_groups.clear();
+  b->nb_members.clear();
   if (b->wv_reps) (void)hipFree(b->wv_reps);
   if (b->wv_imap) (void)hipFree(b->wv_imap);
   b->wv_reps = nullptr;
@@ -1301,6 +1330,149 @@ template <typename A> static void lzb_launch(pse_batch *b) {
                             z.vmap, z.nv, m);
 }
 
+// The batched neighbour build of a captured step: every replica on the LDS
+// path without the overlap repulsion and without the preconditioner (whose
+// features follow the build inside its set_positions), grouped by block
+// edge and halo form.
+static pse_status nbr_setup(pse_batch *b) {
+  const int R = (int)b->ctx.size();
+  std::vector<NbrRep> reps;
+  std::vector<NbrGroup> gr;
+  std::vector<std::vector<int2>> pm;
+  for (int r = 0; r < R; ++r) {
+    pse_ctx *c = b->ctx[r];
+    if (c->dbl || !c->lds_B || c->rep_k > 0 || c->pc_on) continue;
+    const int k = (int)reps.size();
+    NbrRep q{};
+    q.pos = (const float4 *)c->pos_s;
+    q.cell_start = c->cell_start;
+    q.nbr = (uint16_t *)c->nbr;
+    q.cnt = c->nbr_cnt;
+    q.flags = c->flags;
+    q.cs = (float)c->d.cs;
+    q.L = (float)c->d.L;
+    q.invL = (float)(1.0 / c->d.L);
+    q.rc2 = (float)(c->p.rcut * c->p.rcut);
+    q.nc = c->d.nc;
+    q.n = c->n;
+    q.cap = c->nbr_cap;
+    q.hcap = c->hcap;
+    reps.push_back(q);
+    b->nb_members.push_back(r);
+    const int unwrap = c->d.nc >= c->lds_B + 3 ? 1 : 0;
+    size_t g = 0;
+    while (g < gr.size() && !(gr[g].B == c->lds_B && gr[g].unwrap == unwrap)) ++g;
+    if (g == gr.size()) {
+      gr.push_back(NbrGroup{c->lds_B, unwrap, 0, 0, nullptr});
+      pm.emplace_back();
+    }
+    for (int blk = 0; blk < c->lds_blocks; ++blk) pm[g].push_back(make_int2(k, blk));
+    const size_t smem = sizeof(float3) * (size_t)(c->hcap + 3);  // 3 slots read past the last cell
+    if (smem > gr[g].smem) gr[g].smem = smem;
+  }
+  if (reps.empty()) return PSE_OK;
+  size_t nmap = 0;
+  for (auto &x : pm) nmap += x.size();
+  if (hipMalloc((void **)&b->nb_reps, sizeof(NbrRep) * reps.size()) != hipSuccess ||
+      hipMalloc((void **)&b->nb_maps, sizeof(int2) * nmap) != hipSuccess)
+    return PSE_ERR_OOM;
+  std::vector<int2> all;
+  all.reserve(nmap);
+  for (size_t g = 0; g < gr.size(); ++g) {
+    gr[g].pmap = b->nb_maps + all.size();
+    gr[g].nblk = (int)pm[g].size();
+    all.insert(all.end(), pm[g].begin(), pm[g].end());
+  }
+  if (hipMemcpy(b->nb_reps, reps.data(), sizeof(NbrRep) * reps.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->nb_maps, all.data(), sizeof(int2) * nmap, hipMemcpyHostToDevice) != hipSuccess)
+    return PSE_ERR_HIP;
+  b->nb_groups = gr;
+  return PSE_OK;
+}
+
+// The replicas whose whole captured step runs in batched launches: members
+// of the batched Krylov loop, neighbour build and wave-space part alike
+// (FP32 storage, LDS path, no preconditioner, no repulsion, no forces,
+// kT > 0).  Their binning, noise, Krylov start, combination and final sum
+// are batched too, and the capture issues nothing per replica for them.
+// After the replicas' rng_dev is set, before the capture.
+static pse_status full_setup(pse_batch *b) {
+  const int R = (int)b->ctx.size();
+  b->is_full.assign(R, 0);
+  if (!b->g_forces.empty()) return PSE_OK;
+  std::vector<char> in_lz(R, 0), in_nb(R, 0), in_wv(R, 0);
+  for (const auto &z : b->lzb)
+    for (int r : z.members) in_lz[r] = 1;
+  for (int r : b->nb_members) in_nb[r] = 1;
+  for (int r : b->wv_members) in_wv[r] = 1;
+  for (int a = 0; a < 2; ++a) {
+    pse_batch::FullBatch &f = b->full[a];
+    std::vector<SampRep> reps;
+    std::vector<int2> mz, mp, mt, mc, mf;
+    for (int r = 0; r < R; ++r) {
+      pse_ctx *c = b->ctx[r];
+      if (!(in_lz[r] && in_nb[r] && in_wv[r]) || c->dbl || (c->acc_dbl ? 1 : 0) != a) continue;
+      const int k = (int)reps.size(), n = c->n;
+      SampRep q{};
+      q.pos_in = (const float *)b->g_pos[r];
+      q.pos_w = (float4 *)c->pos_w;
+      q.pos_s = (float4 *)c->pos_s;
+      q.cell_of = c->cell_of;
+      q.slot = c->cell_of + n;
+      q.cell_count = c->cell_count;
+      q.tile_sum = c->cell_count + c->ncell;
+      q.cell_start = c->cell_start;
+      q.perm = c->perm;
+      q.flags = c->flags;
+      q.L = (float)c->d.L;
+      q.invL = (float)(1.0 / c->d.L);
+      q.inv_cs = (float)(1.0 / c->d.cs);
+      q.nc = c->d.nc;
+      q.ncell = c->ncell;
+      q.n = n;
+      q.rng = c->rng_dev;
+      q.z = (float4 *)c->vbuf[0];
+      q.partials = c->partials;
+      q.st = c->lz;
+      q.V = (const float4 *)c->V;
+      q.yr = (float4 *)c->vbuf[1];
+      q.wave = (const float4 *)c->vbuf[4];
+      q.out = (float *)b->g_disp[r];
+      q.cr = (float)std::sqrt(2.0 * c->p.kT * b->g_dt);
+      reps.push_back(q);
+      f.members.push_back(r);
+      b->is_full[r] = 1;
+      for (int q2 = 0; q2 < (c->ncell + 8 + 255) / 256; ++q2) mz.push_back(make_int2(k, q2));
+      for (int q2 = 0; q2 < (n + 255) / 256; ++q2) mp.push_back(make_int2(k, q2));
+      for (int q2 = 0; q2 < (c->ncell + kScanTile - 1) / kScanTile; ++q2) mt.push_back(make_int2(k, q2));
+      for (int q2 = 0; q2 < (c->ncell + 3) / 4; ++q2) mc.push_back(make_int2(k, q2));
+      for (int q2 = 0; q2 < (4 * n + 255) / 256; ++q2) mf.push_back(make_int2(k, q2));
+    }
+    if (reps.empty()) continue;
+    const size_t nmap = mz.size() + mp.size() + mt.size() + mc.size() + mf.size();
+    if (hipMalloc((void **)&f.reps, sizeof(SampRep) * reps.size()) != hipSuccess ||
+        hipMalloc((void **)&f.maps, sizeof(int2) * nmap) != hipSuccess)
+      return PSE_ERR_OOM;
+    std::vector<int2> all;
+    all.reserve(nmap);
+    auto put = [&](const std::vector<int2> &v, const int2 *&ptr, int &cnt) {
+      ptr = f.maps + all.size();
+      cnt = (int)v.size();
+      all.insert(all.end(), v.begin(), v.end());
+    };
+    put(mz, f.m.zero, f.m.nzero);
+    put(mp, f.m.part, f.m.npart);
+    put(mt, f.m.tile, f.m.ntile);
+    put(mc, f.m.cell, f.m.ncell);
+    put(mf, f.m.flat, f.m.nflat);
+    f.m.nrep = (int)reps.size();
+    if (hipMemcpy(f.reps, reps.data(), sizeof(SampRep) * reps.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(f.maps, all.data(), sizeof(int2) * nmap, hipMemcpyHostToDevice) != hipSuccess)
+      return PSE_ERR_HIP;
+  }
+  return PSE_OK;
+}
+
 // The batched wave-space part of a captured step: every replica with FP32
 // storage, kT > 0 and no forces, grouped by grid size, support and
 // interpolation workgroup size, with the coefficients sample_begin would
@@ -1408,6 +1580,7 @@ static pse_status batch_capture(pse_batch *b) {
   }
   pse_status st0 = lzb_setup<float>(b);
   if (st0 == PSE_OK) st0 = lzb_setup<double>(b);
+  if (st0 == PSE_OK) st0 = nbr_setup(b);
   if (st0 != PSE_OK) return st0;
   {
     std::vector<RepStatusSrc> src(R);
@@ -1428,6 +1601,7 @@ static pse_status batch_capture(pse_batch *b) {
     c->rng_dev = b->rng_d + 2 * r;
   }
   st0 = wave_setup(b);
+  if (st0 == PSE_OK) st0 = full_setup(b);
   if (st0 != PSE_OK) {
     for (int r = 0; r < R; ++r) {
       b->ctx[r]->prof_mask = prof[r];
@@ -1439,19 +1613,33 @@ static pse_status batch_capture(pse_batch *b) {
   for (const auto &z : b->lzb)
     for (int r : z.members) b->ctx[r]->lz_external = true;
   for (int r : b->wv_members) b->ctx[r]->wave_external = true;
+  for (int r : b->nb_members) b->ctx[r]->nbr_external = true;
   for (pse_ctx *c : b->ctx) c->status_external = true;
   pse_status st = hip_status(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeRelaxed));
   if (st == PSE_OK)
     st = hip_status(hipMemcpyAsync(b->rng_d, b->rng_h, sizeof(uint64_t) * 2 * R, hipMemcpyHostToDevice, b->gstream));
   if (st == PSE_OK) st = fork(b, b->gstream);
-  // every replica's positions and the first part of its sample; then the
-  // batched Krylov loop on the capture stream; then the rest of each sample
+  // every replica's binning; the batched neighbour build on the capture
+  // stream; every replica's first part of the sample; the batched Krylov
+  // loops and wave-space part on the capture stream; the rest of each sample
   std::vector<SampleState> ss(R);
-  for (int r = 0; r < R && st == PSE_OK; ++r) {
-    pse_ctx *c = b->ctx[r];
-    st = ctx_set_positions(c, b->g_pos[r]);
-    if (st == PSE_OK) st = ctx_begin(c, 0, 0, b->g_dt, b->g_forces.empty() ? nullptr : b->g_forces[r], ss[r]);
+  auto full = [&](int r) { return !b->is_full.empty() && b->is_full[r]; };
+  for (const auto &f : b->full)
+    if (f.m.nrep) launch_samp_batch_bin(b->gstream, f.reps, f.m);
+  for (int r = 0; r < R && st == PSE_OK; ++r)
+    if (!full(r)) st = ctx_set_positions(b->ctx[r], b->g_pos[r]);
+  if (st == PSE_OK && !b->nb_groups.empty()) {
+    st = join(b, b->gstream);
+    if (st == PSE_OK) {
+      launch_nbr_batch(b->gstream, b->nb_reps, b->nb_groups.data(), (int)b->nb_groups.size());
+      st = hip_status(hipGetLastError());
+    }
+    if (st == PSE_OK) st = fork(b, b->gstream);
   }
+  if (b->full[0].m.nrep) launch_samp_batch_start<float>(b->gstream, b->full[0].reps, b->full[0].m);
+  if (b->full[1].m.nrep) launch_samp_batch_start<double>(b->gstream, b->full[1].reps, b->full[1].m);
+  for (int r = 0; r < R && st == PSE_OK; ++r)
+    if (!full(r)) st = ctx_begin(b->ctx[r], 0, 0, b->g_dt, b->g_forces.empty() ? nullptr : b->g_forces[r], ss[r]);
   if (st == PSE_OK && (b->lzb[0].nrep || b->lzb[1].nrep || !b->wv_groups.empty())) {
     st = join(b, b->gstream);
     if (st == PSE_OK) {
@@ -1462,8 +1650,10 @@ static pse_status batch_capture(pse_batch *b) {
     }
     if (st == PSE_OK) st = fork(b, b->gstream);
   }
+  if (b->full[0].m.nrep) launch_samp_batch_end<float>(b->gstream, b->full[0].reps, b->full[0].m);
+  if (b->full[1].m.nrep) launch_samp_batch_end<double>(b->gstream, b->full[1].reps, b->full[1].m);
   for (int r = 0; r < R && st == PSE_OK; ++r)
-    st = ctx_end(b->ctx[r], ss[r], b->g_dt, b->g_disp[r], nullptr);
+    if (!full(r)) st = ctx_end(b->ctx[r], ss[r], b->g_dt, b->g_disp[r], nullptr);
   if (st == PSE_OK) st = join(b, b->gstream);
   if (st == PSE_OK) {
     launch_batch_status(b->gstream, b->stat_src, R, b->stat_d);
@@ -1479,6 +1669,7 @@ static pse_status batch_capture(pse_batch *b) {
     c->lz_external = false;
     c->status_external = false;
     c->wave_external = false;
+    c->nbr_external = false;
   }
   if (st == PSE_OK && ec != hipSuccess) st = PSE_ERR_HIP;
   if (st != PSE_OK) {

@@ -19,10 +19,10 @@ template <typename T> __device__ __forceinline__ T min_image(T d, T L, T invL) {
 
 // --------------------------------------------------------------- binning
 template <typename T>
-__global__ void k_wrap_bin(const T *__restrict__ pos, int n, T L, T invL, T inv_cs, int nc,
-                           typename vec4<T>::type *__restrict__ pos_w, int *__restrict__ cell_of,
-                           int *__restrict__ slot, int *__restrict__ cell_count, int *__restrict__ flags) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void wrap_bin_at(const T *__restrict__ pos, int n, T L, T invL, T inv_cs, int nc,
+                                            typename vec4<T>::type *__restrict__ pos_w, int *__restrict__ cell_of,
+                                            int *__restrict__ slot, int *__restrict__ cell_count,
+                                            int *__restrict__ flags, int i) {
   if (i >= n) return;
   T x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
   if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
@@ -60,11 +60,18 @@ __global__ void k_wrap_bin(const T *__restrict__ pos, int n, T L, T invL, T inv_
   pos_w[i] = q;
 }
 
+template <typename T>
+__global__ void k_wrap_bin(const T *__restrict__ pos, int n, T L, T invL, T inv_cs, int nc,
+                           typename vec4<T>::type *__restrict__ pos_w, int *__restrict__ cell_of,
+                           int *__restrict__ slot, int *__restrict__ cell_count, int *__restrict__ flags) {
+  wrap_bin_at<T>(pos, n, L, invL, inv_cs, nc, pos_w, cell_of, slot, cell_count, flags,
+                 blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Exclusive scan of the cell counts in tiles of 4096 cells: k_scan_tiles
 // sums each tile, k_scan_apply adds the sums of the tiles before its own
 // (a few thousand at most) and scans its tile (16 consecutive cells per
 // thread through LDS, the 256 thread sums scanned across wavefronts).
-constexpr int kScanPer = 16, kScanNT = 256, kScanTile = kScanPer * kScanNT;
 __device__ __forceinline__ int block_sum_i32(int v, int *sh) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -77,10 +84,10 @@ __device__ __forceinline__ int block_sum_i32(int v, int *sh) {
   return t;
 }
 
-__global__ __launch_bounds__(kScanNT) void k_scan_tiles(const int *__restrict__ count, int ncell,
-                                                        int *__restrict__ tile_sum) {
+__device__ __forceinline__ void scan_tiles_at(const int *__restrict__ count, int ncell, int *__restrict__ tile_sum,
+                                              int tile) {
   __shared__ int sh[kScanNT / 64];
-  const int base = blockIdx.x * kScanTile;
+  const int base = tile * kScanTile;
   int v = 0;
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
@@ -88,17 +95,22 @@ __global__ __launch_bounds__(kScanNT) void k_scan_tiles(const int *__restrict__ 
     if (i < ncell) v += count[i];
   }
   v = block_sum_i32(v, sh);
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = v;
+  if (threadIdx.x == 0) tile_sum[tile] = v;
 }
 
-__global__ __launch_bounds__(kScanNT) void k_scan_apply(const int *__restrict__ count, const int *__restrict__ tile_sum,
-                                                        int ncell, int *__restrict__ start) {
+__global__ __launch_bounds__(kScanNT) void k_scan_tiles(const int *__restrict__ count, int ncell,
+                                                        int *__restrict__ tile_sum) {
+  scan_tiles_at(count, ncell, tile_sum, blockIdx.x);
+}
+
+__device__ __forceinline__ void scan_apply_at(const int *__restrict__ count, const int *__restrict__ tile_sum,
+                                              int ncell, int *__restrict__ start, int tb) {
   __shared__ int tile[kScanTile];
   __shared__ int sh[kScanNT / 64];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int base = blockIdx.x * kScanTile;
+  const int base = tb * kScanTile;
   int off = 0;
-  for (int k = t; k < (int)blockIdx.x; k += kScanNT) off += tile_sum[k];
+  for (int k = t; k < tb; k += kScanNT) off += tile_sum[k];
   off = block_sum_i32(off, sh);
   for (int k = t; k < kScanTile; k += kScanNT) {
     const int i = base + k;
@@ -134,6 +146,11 @@ __global__ __launch_bounds__(kScanNT) void k_scan_apply(const int *__restrict__ 
   if (t == kScanNT - 1 && base + kScanTile >= ncell) start[ncell] = run;
 }
 
+__global__ __launch_bounds__(kScanNT) void k_scan_apply(const int *__restrict__ count, const int *__restrict__ tile_sum,
+                                                        int ncell, int *__restrict__ start) {
+  scan_apply_at(count, tile_sum, ncell, start, blockIdx.x);
+}
+
 __global__ void k_scatter(const int *__restrict__ cell_of, const int *__restrict__ slot, const int *__restrict__ start,
                           int *__restrict__ perm, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -147,9 +164,8 @@ __global__ void k_scatter(const int *__restrict__ cell_of, const int *__restrict
 // back to an insertion sort by lane 0.  The sorted positions are gathered in
 // the same pass.
 template <typename T4>
-__global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start, int *__restrict__ perm, int ncell,
-                                                   const T4 *__restrict__ pos_w, T4 *__restrict__ pos_s) {
-  const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+__device__ __forceinline__ void cell_sort_at(const int *__restrict__ start, int *__restrict__ perm, int ncell,
+                                             const T4 *__restrict__ pos_w, T4 *__restrict__ pos_s, int c) {
   const int lane = threadIdx.x & 63;
   if (c >= ncell) return;
   const int b = start[c], e = start[c + 1], m = e - b;
@@ -174,6 +190,12 @@ __global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start
     perm[j + 1] = v;
   }
   for (int i = b; i < e; ++i) pos_s[i] = pos_w[perm[i]];
+}
+
+template <typename T4>
+__global__ __launch_bounds__(256) void k_cell_sort(const int *__restrict__ start, int *__restrict__ perm, int ncell,
+                                                   const T4 *__restrict__ pos_w, T4 *__restrict__ pos_s) {
+  cell_sort_at<T4>(start, perm, ncell, pos_w, pos_s, (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
 }
 
 // ------------------------------------------------------- F, G evaluation
@@ -721,12 +743,12 @@ __global__ __launch_bounds__(256) void k_halo_size(const int *__restrict__ cell_
 //   f_s = sum_{t: r < 2a} krep (2a - r) d / r,  d = x_s - x_t,
 // into frep[s] (the candidates' distances are at hand; overlapping pairs
 // are rare, so the branch is almost never taken).
-template <int B, bool UNWRAP, bool REP = false>
-__global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
-                                                 int nc, float cs, int n, float L, float invL, float rc2,
-                                                 uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
-                                                 int *__restrict__ flags, float contact, float krep,
-                                                 float4 *__restrict__ frep, int hcap) {
+template <int B, bool UNWRAP, bool REP>
+__device__ __forceinline__ void nbr_lds_block(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
+                                              int nc, float cs, int n, float L, float invL, float rc2,
+                                              uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
+                                              int *__restrict__ flags, float contact, float krep,
+                                              float4 *__restrict__ frep, int hcap, int blk) {
   constexpr int HB = Halo<B>::HB, NH = Halo<B>::NH;
   extern __shared__ float3 hpos3[];  // coordinates only
   __shared__ HaloTab<B> ht;
@@ -744,11 +766,10 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
       }
     pack_tab[threadIdx.x] = make_uint4((uint32_t)pat, (uint32_t)(pat >> 32), (uint32_t)msk, (uint32_t)(msk >> 32));
   }
-  halo_setup<B>(cell_start, nc, ht, xcd_block(blockIdx.x, gridDim.x));
+  halo_setup<B>(cell_start, nc, ht, blk);
   if (!halo_fits<B>(ht, hcap, flags + 7)) return;
   if (UNWRAP) {
     const int nb = (nc + B - 1) / B;
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int bz = blk % nb, by = (blk / nb) % nb, bx = blk / (nb * nb);
     const float c0 = 0.5f * B * cs;
     halo_stage_unwrapped<B>(pos, hpos3, ht, bx * B * cs + c0, by * B * cs + c0, bz * B * cs + c0, L, invL);
@@ -865,6 +886,26 @@ __global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos,
     atomicMax(&flags[1], m);
     atomicMax(&flags[5], m);
   }
+}
+
+template <int B, bool UNWRAP, bool REP = false>
+__global__ __launch_bounds__(512) void k_nbr_lds(const float4 *__restrict__ pos, const int *__restrict__ cell_start,
+                                                 int nc, float cs, int n, float L, float invL, float rc2,
+                                                 uint16_t *__restrict__ nbr, int *__restrict__ cnt_out, int cap,
+                                                 int *__restrict__ flags, float contact, float krep,
+                                                 float4 *__restrict__ frep, int hcap) {
+  nbr_lds_block<B, UNWRAP, REP>(pos, cell_start, nc, cs, n, L, invL, rc2, nbr, cnt_out, cap, flags, contact, krep,
+                                frep, hcap, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// The neighbour build of many systems (a batch of replicas) in one launch:
+// pmap lists (system, block of that system) per workgroup.
+template <int B, bool UNWRAP>
+__global__ __launch_bounds__(512) void k_nbr_lds_batch(const NbrRep *__restrict__ reps, const int2 *__restrict__ pmap) {
+  const int2 rb = pmap[blockIdx.x];
+  const NbrRep &r = reps[rb.x];
+  nbr_lds_block<B, UNWRAP, false>(r.pos, r.cell_start, r.nc, r.cs, r.n, r.L, r.invL, r.rc2, r.nbr, r.cnt, r.cap,
+                                  r.flags, 0.0f, 0.0f, nullptr, r.hcap, rb.y);
 }
 
 // Preconditioner features (FeatAcc; F, G from the LDS table).  Three lanes
@@ -1197,7 +1238,7 @@ __global__ void k_norm2_partial(const T *__restrict__ z, int len, A *__restrict_
 }
 
 template <typename A>
-__global__ void k_lz_init(const A *__restrict__ partials, int nparts, LzState<A> *st) {
+__device__ __forceinline__ void lz_init_body(const A *__restrict__ partials, int nparts, LzState<A> *st) {
   __shared__ A sh[16];
   A v = 0;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += partials[i];
@@ -1213,6 +1254,11 @@ __global__ void k_lz_init(const A *__restrict__ partials, int nparts, LzState<A>
     if (b0 == A(0)) st->converged = 1;
     st->inv_beta = b0 > A(0) ? A(1) / b0 : A(0);
   }
+}
+
+template <typename A>
+__global__ void k_lz_init(const A *__restrict__ partials, int nparts, LzState<A> *st) {
+  lz_init_body<A>(partials, nparts, st);
 }
 
 // w = t - alpha_m v_m - beta_m v_{m-1}, one particle (x, y, z, 0) per
@@ -1540,17 +1586,22 @@ __global__ __launch_bounds__(64) void k_lz_check_batch(const LzRep<A> *__restric
 }
 
 // y = beta_0 sum_{j < m} V_j s_j  (sorted order, length 3n)
+// one element of y from the coefficients sc[0 .. m)
+template <typename T, typename A>
+__device__ __forceinline__ T lz_combine_at(const T *__restrict__ V, size_t ld, const A *sc, int m, int i) {
+  A acc = 0;
+  for (int j = 0; j < m; ++j) acc += sc[j] * (A)V[(size_t)j * ld + i];
+  return (T)acc;
+}
+
 template <typename T, typename A>
 __global__ void k_lz_combine(const T *__restrict__ V, size_t ld, int len, const LzState<A> *st, T *__restrict__ y) {
   __shared__ A sc[kMaxIter];
   const int m = st->m;
   if (threadIdx.x < (unsigned)m) sc[threadIdx.x] = st->beta[0] * st->s[threadIdx.x];
   __syncthreads();
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
-    A acc = 0;
-    for (int j = 0; j < m; ++j) acc += sc[j] * (A)V[(size_t)j * ld + i];
-    y[i] = (T)acc;
-  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x)
+    y[i] = lz_combine_at<T, A>(V, ld, sc, m, i);
 }
 
 // ------------------------------------------------------------- vectors
@@ -1603,10 +1654,10 @@ template <typename T> __global__ void k_advance(T *__restrict__ x, const T *__re
 // out[perm[s]] = cr * yr[s] + dt * ur[s] + wv[s]   (null terms omitted;
 // sorted inputs are (x, y, z, 0), the output is caller-order n x 3)
 template <typename T>
-__global__ void k_finalize(const int *__restrict__ perm, const typename vec4<T>::type *__restrict__ yr, T cr,
-                           const typename vec4<T>::type *__restrict__ ur, T dt,
-                           const typename vec4<T>::type *__restrict__ wv, T *__restrict__ out, int n) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void finalize_at(const int *__restrict__ perm, const typename vec4<T>::type *__restrict__ yr,
+                                            T cr, const typename vec4<T>::type *__restrict__ ur, T dt,
+                                            const typename vec4<T>::type *__restrict__ wv, T *__restrict__ out, int n,
+                                            int s) {
   if (s >= n) return;
   const int i = perm[s];
   T x = 0, y = 0, z = 0;
@@ -1631,6 +1682,13 @@ __global__ void k_finalize(const int *__restrict__ perm, const typename vec4<T>:
   out[3 * i] = x;
   out[3 * i + 1] = y;
   out[3 * i + 2] = z;
+}
+
+template <typename T>
+__global__ void k_finalize(const int *__restrict__ perm, const typename vec4<T>::type *__restrict__ yr, T cr,
+                           const typename vec4<T>::type *__restrict__ ur, T dt,
+                           const typename vec4<T>::type *__restrict__ wv, T *__restrict__ out, int n) {
+  finalize_at<T>(perm, yr, cr, ur, dt, wv, out, n, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------ Philox noise for z1
@@ -1677,9 +1735,9 @@ template <> __device__ __forceinline__ void box_muller<float>(uint64_t wa, uint6
 // takes elements 3i .. 3i+2, i.e. the normals of block (3i) >> 2 and, when
 // they straddle, of the next.
 template <typename T>
-__global__ void k_real_noise_sorted(const int *__restrict__ perm, int n, uint64_t seed, uint64_t sample,
-                                    typename vec4<T>::type *__restrict__ z, const uint64_t *__restrict__ rng) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void real_noise_at(const int *__restrict__ perm, int n, uint64_t seed, uint64_t sample,
+                                              typename vec4<T>::type *__restrict__ z, const uint64_t *__restrict__ rng,
+                                              int s) {
   if (s >= n) return;
   if (rng) {
     // key and counter from device memory (a graph replayed per step)
@@ -1708,6 +1766,12 @@ __global__ void k_real_noise_sorted(const int *__restrict__ perm, int n, uint64_
   o.z = off == 0 ? v[2] : (off == 1 ? v[3] : (off == 2 ? v[4] : v[5]));
   o.w = T(0);
   z[s] = o;
+}
+
+template <typename T>
+__global__ void k_real_noise_sorted(const int *__restrict__ perm, int n, uint64_t seed, uint64_t sample,
+                                    typename vec4<T>::type *__restrict__ z, const uint64_t *__restrict__ rng) {
+  real_noise_at<T>(perm, n, seed, sample, z, rng, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ----------------------------------------------------------- launchers
@@ -1840,6 +1904,21 @@ void launch_nbr_lds(pse_ctx *c) {
       else go(k_nbr_lds<BE, false>);
     }
   });
+}
+
+void launch_nbr_batch(hipStream_t s, const NbrRep *reps, const NbrGroup *groups, int ngroups) {
+  for (int g = 0; g < ngroups; ++g) {
+    const NbrGroup &gr = groups[g];
+    with_block_edge(gr.B, [&](auto b) {
+      constexpr int BE = decltype(b)::value;
+      auto go = [&](auto kern) {
+        allow_lds(kern, gr.smem);
+        kern<<<gr.nblk, 512, gr.smem, s>>>(reps, gr.pmap);
+      };
+      if (gr.unwrap) go(k_nbr_lds_batch<BE, true>);
+      else go(k_nbr_lds_batch<BE, false>);
+    });
+  }
 }
 
 // Preconditioner features on the LDS path, from the list and the staged halo.
@@ -2137,6 +2216,111 @@ __global__ void k_batch_status(const RepStatusSrc *__restrict__ src, int nrep, R
 void launch_batch_status(hipStream_t s, const RepStatusSrc *src, int nrep, RepStatus *out) {
   k_batch_status<<<(nrep + 63) / 64, 64, 0, s>>>(src, nrep, out);
 }
+
+// ------------------------------------------ fully batched systems
+// The per-system kernels of a captured step (binning, noise, Krylov start,
+// combination, final sum) for many systems in one launch each: the same
+// bodies as the single-system kernels, the system and block from a map.
+__global__ __launch_bounds__(256) void k_zero_batch(const SampRep *__restrict__ reps, const int2 *__restrict__ map) {
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  const int i = rb.y * 256 + (int)threadIdx.x;
+  if (i < r.ncell) r.cell_count[i] = 0;
+  else if (i - r.ncell < 8) r.flags[i - r.ncell] = 0;
+}
+__global__ __launch_bounds__(256) void k_wrap_bin_batch(const SampRep *__restrict__ reps, const int2 *__restrict__ map) {
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  wrap_bin_at<float>(r.pos_in, r.n, r.L, r.invL, r.inv_cs, r.nc, r.pos_w, r.cell_of, r.slot, r.cell_count, r.flags,
+                     rb.y * 256 + (int)threadIdx.x);
+}
+__global__ __launch_bounds__(kScanNT) void k_scan_tiles_batch(const SampRep *__restrict__ reps,
+                                                              const int2 *__restrict__ map) {
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  scan_tiles_at(r.cell_count, r.ncell, r.tile_sum, rb.y);
+}
+__global__ __launch_bounds__(kScanNT) void k_scan_apply_batch(const SampRep *__restrict__ reps,
+                                                              const int2 *__restrict__ map) {
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  scan_apply_at(r.cell_count, r.tile_sum, r.ncell, r.cell_start, rb.y);
+}
+__global__ __launch_bounds__(256) void k_scatter_batch(const SampRep *__restrict__ reps, const int2 *__restrict__ map) {
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  const int i = rb.y * 256 + (int)threadIdx.x;
+  if (i < r.n) r.perm[r.cell_start[r.cell_of[i]] + r.slot[i]] = i;
+}
+__global__ __launch_bounds__(256) void k_cell_sort_batch(const SampRep *__restrict__ reps, const int2 *__restrict__ map) {
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  cell_sort_at<float4>(r.cell_start, r.perm, r.ncell, r.pos_w, r.pos_s, rb.y * 4 + (int)(threadIdx.x >> 6));
+}
+__global__ __launch_bounds__(256) void k_noise_batch(const SampRep *__restrict__ reps, const int2 *__restrict__ map) {
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  real_noise_at<float>(r.perm, r.n, 0ull, 0ull, r.z, r.rng, rb.y * 256 + (int)threadIdx.x);
+}
+template <typename A>
+__global__ __launch_bounds__(256) void k_norm2_batch(const SampRep *__restrict__ reps, const int2 *__restrict__ map) {
+  __shared__ A sh[16];
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  const float *zf = (const float *)r.z;
+  A *part = (A *)r.partials;
+  const int len = 4 * r.n, i = rb.y * 256 + (int)threadIdx.x;
+  A v = 0;
+  if (i < len) v += (A)zf[i] * (A)zf[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[rb.y] = v;
+  if (rb.y == 0)
+    for (int k = (len + 255) / 256 + (int)threadIdx.x; k < kRedBlock; k += 256) part[k] = A(0);
+}
+template <typename A>
+__global__ __launch_bounds__(256) void k_lz_init_batch(const SampRep *__restrict__ reps) {
+  const SampRep &r = reps[blockIdx.x];
+  lz_init_body<A>((const A *)r.partials, kRedBlock, (LzState<A> *)r.st);
+}
+template <typename A>
+__global__ __launch_bounds__(256) void k_combine_batch(const SampRep *__restrict__ reps, const int2 *__restrict__ map) {
+  __shared__ A sc[kMaxIter];
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  const LzState<A> *st = (const LzState<A> *)r.st;
+  const int m = st->m;
+  if (threadIdx.x < (unsigned)m) sc[threadIdx.x] = st->beta[0] * st->s[threadIdx.x];
+  __syncthreads();
+  const int len = 4 * r.n, i = rb.y * 256 + (int)threadIdx.x;
+  if (i < len) ((float *)r.yr)[i] = lz_combine_at<float, A>((const float *)r.V, (size_t)len, sc, m, i);
+}
+__global__ __launch_bounds__(256) void k_finalize_batch(const SampRep *__restrict__ reps, const int2 *__restrict__ map) {
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  finalize_at<float>(r.perm, r.yr, r.cr, nullptr, 0.0f, r.wave, r.out, r.n, rb.y * 256 + (int)threadIdx.x);
+}
+
+void launch_samp_batch_bin(hipStream_t s, const SampRep *reps, const SampMaps &m) {
+  k_zero_batch<<<m.nzero, 256, 0, s>>>(reps, m.zero);
+  k_wrap_bin_batch<<<m.npart, 256, 0, s>>>(reps, m.part);
+  k_scan_tiles_batch<<<m.ntile, kScanNT, 0, s>>>(reps, m.tile);
+  k_scan_apply_batch<<<m.ntile, kScanNT, 0, s>>>(reps, m.tile);
+  k_scatter_batch<<<m.npart, 256, 0, s>>>(reps, m.part);
+  k_cell_sort_batch<<<m.ncell, 256, 0, s>>>(reps, m.cell);
+}
+template <typename A> void launch_samp_batch_start(hipStream_t s, const SampRep *reps, const SampMaps &m) {
+  k_noise_batch<<<m.npart, 256, 0, s>>>(reps, m.part);
+  k_norm2_batch<A><<<m.nflat, 256, 0, s>>>(reps, m.flat);
+  k_lz_init_batch<A><<<m.nrep, 256, 0, s>>>(reps);
+}
+template <typename A> void launch_samp_batch_end(hipStream_t s, const SampRep *reps, const SampMaps &m) {
+  k_combine_batch<A><<<m.nflat, 256, 0, s>>>(reps, m.flat);
+  k_finalize_batch<<<m.npart, 256, 0, s>>>(reps, m.part);
+}
+template void launch_samp_batch_start<float>(hipStream_t, const SampRep *, const SampMaps &);
+template void launch_samp_batch_start<double>(hipStream_t, const SampRep *, const SampMaps &);
+template void launch_samp_batch_end<float>(hipStream_t, const SampRep *, const SampMaps &);
+template void launch_samp_batch_end<double>(hipStream_t, const SampRep *, const SampMaps &);
 
 template void launch_lz_batch_iter<float>(hipStream_t, const LzRep<float> *, int, const LzGroup *, int, const int2 *,
                                           int, int);

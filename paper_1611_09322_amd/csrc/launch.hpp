@@ -25,6 +25,8 @@ template <typename T> void launch_nbr(pse_ctx *c);
 // neighbour build with 16-bit LDS indices
 void launch_halo_size(pse_ctx *c, int B);
 void launch_nbr_lds(pse_ctx *c);
+// the LDS neighbour build of every system of the groups in one launch per group
+void launch_nbr_batch(hipStream_t s, const NbrRep *reps, const NbrGroup *groups, int ngroups);
 void launch_feat_lds(pse_ctx *c);  // preconditioner features from the list and the staged halo
 template <typename T, typename A> void launch_spmv(pse_ctx *c, const void *src, void *out, bool lz, void *vm_out);
 template <typename T, typename A> void launch_lz_init(pse_ctx *c, const void *z);
@@ -75,6 +77,11 @@ void launch_lz_batch_iter(hipStream_t s, const LzRep<A> *reps, int nrep, const L
 // the wave-space part without forces of every system of the groups
 // (bit-identical to each system's own launches)
 void launch_wave_batch(hipStream_t s, const WaveGroup *groups, int ngroups);
+// the fully batched systems of a captured step: binning; noise and Krylov
+// start; combination and final sum (A: the Lanczos scalar type)
+void launch_samp_batch_bin(hipStream_t s, const SampRep *reps, const SampMaps &m);
+template <typename A> void launch_samp_batch_start(hipStream_t s, const SampRep *reps, const SampMaps &m);
+template <typename A> void launch_samp_batch_end(hipStream_t s, const SampRep *reps, const SampMaps &m);
 // out[r] = flags and Krylov outcome of replica r
 void launch_batch_status(hipStream_t s, const RepStatusSrc *src, int nrep, RepStatus *out);
 

@@ -18,6 +18,8 @@ constexpr int kTableN = kTableK + 2;  // table nodes (float2 (mu0 F, mu0 (G - F)
 constexpr int kSeriesTerms = 16; // small-r series terms of the wave complement
 constexpr uint32_t kKnownFlags = PSE_FLAG_NOISE_KSPACE | PSE_FLAG_FULL_LANCZOS;
 constexpr int kRedBlock = 1024;
+// cell-count scan: tiles of kScanTile cells, kScanPer per thread of kScanNT
+constexpr int kScanPer = 16, kScanNT = 256, kScanTile = kScanPer * kScanNT;
 constexpr int kRepBuf = 10;      // work vector holding the overlap repulsion of the Brownian step  // workgroups (partial sums) of the vector reductions
 constexpr size_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit
 // largest dynamic + table LDS of one workgroup of the staged near-field kernels
@@ -99,6 +101,51 @@ template <typename A> struct LzState {
   int done;              // 1: converged (or broke down / max_iter reached)
   int converged;         // 1: tolerance met or invariant subspace
   int nonfinite;
+};
+
+// One system whose whole captured step runs in batched launches (FP32
+// storage, LDS path, Philox noise, no forces, no preconditioner): the
+// buffers of its binning, noise, Krylov start, combination and final sum.
+struct SampRep {
+  const float *pos_in;  // caller positions n x 3
+  float4 *pos_w, *pos_s;
+  int *cell_of, *slot, *cell_count, *tile_sum, *cell_start, *perm, *flags;
+  float L, invL, inv_cs;
+  int nc, ncell, n;
+  const uint64_t *rng;  // (seed, counter) of the Philox noise
+  float4 *z;            // real-space noise, sorted
+  void *partials;       // A [kRedBlock]
+  void *st;             // LzState<A>
+  const float4 *V;      // Krylov basis
+  float4 *yr;           // Krylov sample, sorted
+  const float4 *wave;   // wave-space part, sorted
+  float *out;           // displacement, caller order n x 3
+  float cr;             // sqrt(2 kT dt)
+};
+// Workgroup maps (system, block) of the batched launches: zero (blocks of
+// 256 over ncell + 8), part (256 particles), tile (scan tiles), cell (4
+// cells), flat (256 of the 4n vector scalars).
+struct SampMaps {
+  const int2 *zero, *part, *tile, *cell, *flat;
+  int nzero, npart, ntile, ncell, nflat, nrep;
+};
+
+// One system of a batched neighbour build (LDS path, no repulsion), and the
+// systems sharing one kernel (block edge, halo form): pmap lists (system,
+// block) for each of the nblk workgroups, smem the largest halo's LDS.
+struct NbrRep {
+  const float4 *pos;
+  const int *cell_start;
+  uint16_t *nbr;
+  int *cnt;
+  int *flags;
+  float cs, L, invL, rc2;
+  int nc, n, cap, hcap;
+};
+struct NbrGroup {
+  int B, unwrap, nblk;
+  size_t smem;
+  const int2 *pmap;
 };
 
 // One system of a batched Krylov loop: what the LDS product and the
@@ -246,6 +293,7 @@ struct pse_ctx {
   bool lz_external = false;         // graph mode: the Lanczos iterations run in the batch's batched loop
   bool status_external = false;     // graph mode: the batch reads flags and Krylov state back for all replicas
   bool wave_external = false;       // graph mode: the wave-space part runs in the batch's batched launches
+  bool nbr_external = false;        // graph mode: the neighbour build runs in the batch's batched launch
   int last_iters = 4;
   int lz_maxit = 0;         // near-field Lanczos iterations at most: min(lanczos_max_iter, kMaxIter)
   // full-mobility Krylov sample (PSE_FLAG_FULL_LANCZOS)
