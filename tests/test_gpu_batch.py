@@ -1,7 +1,8 @@
 """Batched replicas (pse_batch_*): every replica's displacement equals the
 one its own context gives alone with key seed + r (same kernels, same
-order: bit-identical), one replica against the FP64 oracle, and the
-per-replica completion times."""
+order: bit-identical), one replica against the FP64 oracle, the
+per-replica completion times, and the captured step (per-replica and
+batched launches) against the eager step."""
 import numpy as np
 import pytest
 
@@ -191,5 +192,63 @@ def test_graph_replay_redoes_overflowing_replicas(gpu_lib, systems):
         for r in range(len(systems)):
             assert torch.equal(got[r], ref[r]), (counter, r)
         ref_b.close()
+    b.graph_destroy()
+    b.close()
+
+
+def test_batched_graph_of_many_mixed_replicas_equals_eager(gpu_lib):
+    """40 replicas of uneven size (N log-uniform in [300, 3000], volume
+    fraction in [0.05, 0.35]) with parameters chosen per replica for a 1e-3
+    error (radix-2 and radix-3 grids up to 96^3, xi per replica), FP32 and
+    mixed precision, one with the learned preconditioner, no forces: in the
+    captured step most replicas run entirely in launches shared by all of
+    them (binning, neighbour build, noise, Krylov loop, wave-space part,
+    final sum).  Every replay equals the eager step with the same key and
+    counter, bit for bit, also after the positions moved in place."""
+    import torch
+
+    from oracle import precond as opc
+    from paper_1611_09322_amd import precond as ppc
+
+    rng = np.random.default_rng(2600)
+    specs, pos = [], []
+    for r in range(40):
+        n = int(round(np.exp(rng.uniform(np.log(300), np.log(3000)))))
+        phi = float(rng.uniform(0.05, 0.35))
+        x, L = synth.hard_spheres(n, phi, seed=2600 + r, sweeps=10)
+        prec = "mixed" if r % 2 else "fp32"
+        p, _ = gpu_lib.pse_choose_params(gpu_lib.make_params(n, L, precision=prec),
+                                         gpu_lib.Tuning(tol=1e-3, max_grid=96, with_forces=0))
+        specs.append(dict(n=n, box=L, xi=p.xi, rcut=p.rcut, grid=p.grid, support=p.support, gauss_m=p.gauss_m,
+                          tol=1e-3, precision=prec, precond=1 if r == 5 else 0))
+        pos.append(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    print("grids:", sorted({s["grid"] for s in specs}), "supports:", sorted({s["support"] for s in specs}), flush=True)
+    bits = ppc.bf16_bits(ppc.pack(opc.init_weights(43, scale=0.1)))
+    b = gpu_lib.Batch(specs)
+    b.set_precond_weights(5, bits)
+    out = [torch.empty_like(p) for p in pos]
+    b.graph_create(pos, out, 1e-3, extra_iters=2, headroom=0.25)
+    ref_b = gpu_lib.Batch(specs)
+    ref_b.set_precond_weights(5, bits)
+    for step, counter in enumerate((31, 32, 33)):
+        if step == 2:
+            for r, p in enumerate(pos):
+                p.add_(torch.as_tensor(0.03 * synth.normals(2700 + r, tuple(p.shape)), dtype=p.dtype, device="cuda"))
+        status, st, redone = b.graph_step(8, counter)
+        torch.cuda.synchronize()
+        got = [o.clone() for o in out]
+        ref_b.set_positions(pos)
+        ref, st_e = ref_b.sample(8, counter, dt=1e-3)
+        torch.cuda.synchronize()
+        print(f"step {step}: redone {redone}, mean iterations {np.mean([s.lanczos_iters for s in st]):.2f}",
+              flush=True)
+        assert redone == 0
+        for r in range(len(specs)):
+            if st[r].lds_block_edge == st_e[r].lds_block_edge:
+                assert torch.equal(got[r], ref[r]), (step, r)
+                assert st[r].lanczos_iters == st_e[r].lanczos_iters, (step, r)
+            else:  # the eager step picked another block edge for the moved positions
+                check(got[r].double().cpu().numpy(), ref[r].double().cpu().numpy(), 1e-5, f"replica {r}")
+    ref_b.close()
     b.graph_destroy()
     b.close()
