@@ -789,61 +789,63 @@ __device__ __forceinline__ void nbr_lds_block(const float4 *__restrict__ pos, co
     int k = 0;
     float fx = 0.f, fy = 0.f, fz = 0.f;  // overlap repulsion (REP)
     uint64_t lo = 0, hi = 0;  // the current chunk of 8 packed 16-bit indices
+    // the three cells dz = -1, 0, 1 of a (dx, dy) column are consecutive
+    // halo cells, staged contiguously: one run of candidates per column, in
+    // the same order as cell by cell
     for (int dx = -1; dx <= 1; ++dx)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dz = -1; dz <= 1; ++dz) {
-          const int hh = ((ox + 1 + dx) * HB + (oy + 1 + dy)) * HB + (oz + 1 + dz);
-          const int e = ht.base[hh + 1];
-          // four candidates per step: their LDS reads are in flight together
-          // (up to 3 past the cell, into the next cell or the 3 padding slots
-          // after the halo; masked out below)
-          for (int j0 = ht.base[hh]; j0 < e; j0 += 4) {
-            float3 q[4];
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int hh = ((ox + 1 + dx) * HB + (oy + 1 + dy)) * HB + oz;
+        const int e = ht.base[hh + 3];
+        // four candidates per step: their LDS reads are in flight together
+        // (up to 3 past the run, into the next cell or the 3 padding slots
+        // after the halo; masked out below)
+        for (int j0 = ht.base[hh]; j0 < e; j0 += 4) {
+          float3 q[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) q[u] = hpos3[j0 + u];
-            unsigned hit = 0;
+          for (int u = 0; u < 4; ++u) q[u] = hpos3[j0 + u];
+          unsigned hit = 0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              float ddx = p.x - q[u].x, ddy = p.y - q[u].y, ddz = p.z - q[u].z;
-              if (!UNWRAP) {
-                ddx = min_image(ddx, L, invL);
-                ddy = min_image(ddy, L, invL);
-                ddz = min_image(ddz, L, invL);
-              }
-              const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-              const int j = j0 + u;
-              hit |= (j < e && j != li && r2 <= rc2) ? 1u << u : 0u;
-              if (REP && j < e && j != li && r2 < contact * contact && r2 > 0.f) {
-                const float r = sqrtf(r2), m = krep * (contact - r) / r;
-                fx += m * ddx;
-                fy += m * ddy;
-                fz += m * ddz;
-              }
+          for (int u = 0; u < 4; ++u) {
+            float ddx = p.x - q[u].x, ddy = p.y - q[u].y, ddz = p.z - q[u].z;
+            if (!UNWRAP) {
+              ddx = min_image(ddx, L, invL);
+              ddy = min_image(ddy, L, invL);
+              ddz = min_image(ddz, L, invL);
             }
-            // the hits of the step, compacted: field f of V is j0 plus the
-            // offset of the f-th set bit (pattern table), then V is
-            // shifted into the chunk at field k & 7; fields past 8 carry
-            // into the next chunk
-            const uint4 tb = pack_tab[hit];
-            const uint32_t X = (uint32_t)j0 * 0x10001u;
-            const uint64_t V = ((uint64_t)((X & tb.w) + tb.y) << 32) | (uint64_t)((X & tb.z) + tb.x);
-            const int sh = 16 * (k & 7);
-            const bool upper = sh >= 64;
-            const int s2 = upper ? sh - 64 : sh;
-            const uint64_t vs = V << s2, spill = s2 ? V >> (64 - s2) : 0ull;
-            lo |= upper ? 0ull : vs;
-            hi |= upper ? vs : spill;
-            const int k1 = k + __builtin_popcount(hit);
-            if ((k1 >> 3) != (k >> 3)) {
-              if ((k >> 3) < (cap >> 3))
-                row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
-                                                           (uint32_t)(hi >> 32));
-              lo = upper ? spill : 0ull;
-              hi = 0;
+            const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            const int j = j0 + u;
+            hit |= (j < e && j != li && r2 <= rc2) ? 1u << u : 0u;
+            if (REP && j < e && j != li && r2 < contact * contact && r2 > 0.f) {
+              const float r = sqrtf(r2), m = krep * (contact - r) / r;
+              fx += m * ddx;
+              fy += m * ddy;
+              fz += m * ddz;
             }
-            k = k1;
           }
+          // the hits of the step, compacted: field f of V is j0 plus the
+          // offset of the f-th set bit (pattern table), then V is
+          // shifted into the chunk at field k & 7; fields past 8 carry
+          // into the next chunk
+          const uint4 tb = pack_tab[hit];
+          const uint32_t X = (uint32_t)j0 * 0x10001u;
+          const uint64_t V = ((uint64_t)((X & tb.w) + tb.y) << 32) | (uint64_t)((X & tb.z) + tb.x);
+          const int sh = 16 * (k & 7);
+          const bool upper = sh >= 64;
+          const int s2 = upper ? sh - 64 : sh;
+          const uint64_t vs = V << s2, spill = s2 ? V >> (64 - s2) : 0ull;
+          lo |= upper ? 0ull : vs;
+          hi |= upper ? vs : spill;
+          const int k1 = k + __builtin_popcount(hit);
+          if ((k1 >> 3) != (k >> 3)) {
+            if ((k >> 3) < (cap >> 3))
+              row[(size_t)(k >> 3) * n + s] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
+                                                         (uint32_t)(hi >> 32));
+            lo = upper ? spill : 0ull;
+            hi = 0;
+          }
+          k = k1;
         }
+      }
     if ((k & 7) && (k >> 3) < (cap >> 3)) {
       // the rest of the last chunk points at the zero-source slot the
       // product stages after the halo (index = halo size)
