@@ -1411,7 +1411,10 @@ static pse_status full_setup(pse_batch *b) {
     std::vector<int2> mz, mp, mt, mc, mf;
     for (int r = 0; r < R; ++r) {
       pse_ctx *c = b->ctx[r];
-      if (!(in_lz[r] && in_nb[r] && in_wv[r]) || c->dbl || (c->acc_dbl ? 1 : 0) != a) continue;
+      // 4n vector scalars in at most kRedBlock blocks of 256: the Krylov
+      // start's partial sums are laid out as in a single-system launch
+      if (!(in_lz[r] && in_nb[r] && in_wv[r]) || c->dbl || (c->acc_dbl ? 1 : 0) != a || c->n > kRedBlock * 64)
+        continue;
       const int k = (int)reps.size(), n = c->n;
       SampRep q{};
       q.pos_in = (const float *)b->g_pos[r];

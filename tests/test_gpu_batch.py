@@ -252,3 +252,39 @@ def test_batched_graph_of_many_mixed_replicas_equals_eager(gpu_lib):
     ref_b.close()
     b.graph_destroy()
     b.close()
+
+
+def test_batched_graph_with_a_large_replica(gpu_lib):
+    """A replica of 70000 spheres next to two small ones: too large for the
+    fully batched form (its Krylov start's partial sums would not fit the
+    single-system layout), it keeps its own binning, noise, start and final
+    sum inside the captured step while sharing the batched neighbour build,
+    Krylov loop and wave-space part.  Every replay equals the eager step."""
+    import torch
+
+    specs, pos = [], []
+    for k, (n, phi) in enumerate([(70000, 0.2), (800, 0.1), (2500, 0.3)]):
+        x, L = synth.hard_spheres(n, phi, seed=2800 + k, sweeps=5)
+        p, _ = gpu_lib.pse_choose_params(gpu_lib.make_params(n, L, precision="mixed"),
+                                         gpu_lib.Tuning(tol=1e-3, max_grid=128, with_forces=0))
+        specs.append(dict(n=n, box=L, xi=p.xi, rcut=p.rcut, grid=p.grid, support=p.support, gauss_m=p.gauss_m,
+                          tol=1e-3, precision="mixed"))
+        pos.append(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    b = gpu_lib.Batch(specs)
+    out = [torch.empty_like(p) for p in pos]
+    b.graph_create(pos, out, 1e-3, extra_iters=2, headroom=0.25)
+    ref_b = gpu_lib.Batch(specs)
+    for counter in (41, 42):
+        status, st, redone = b.graph_step(6, counter)
+        torch.cuda.synchronize()
+        got = [o.clone() for o in out]
+        ref_b.set_positions(pos)
+        ref, st_e = ref_b.sample(6, counter, dt=1e-3)
+        torch.cuda.synchronize()
+        print(f"counter {counter}: redone {redone}, iterations {[s.lanczos_iters for s in st]}", flush=True)
+        assert redone == 0
+        for r in range(len(specs)):
+            assert torch.equal(got[r], ref[r]), (counter, r)
+    ref_b.close()
+    b.graph_destroy()
+    b.close()
