@@ -493,7 +493,16 @@ pse_status pse_batch_latency(pse_batch *batch, float *ms);
  * of the graph (the caller rewrites the positions in place between steps,
  * e.g. by moving the particles by disp).  One replay is one graph launch
  * and one synchronisation for the whole batch, against about 45 launches
- * and two host waits per replica on the eager path.
+ * and two host waits per replica on the eager path.  Inside the graph each
+ * stage of the step is one launch for all replicas that share its kernel:
+ * binning, neighbour build (block edge, halo form), noise, Krylov start,
+ * every Lanczos iteration (product per block edge, halo form and lanes per
+ * target; vector kernels and checks for all), wave-space part (grid size,
+ * support), combination, final sum and the read-back of every replica's
+ * flags and Krylov state, each workgroup finding its replica and block in
+ * a table built at capture.  Replicas with FP64 storage, the learned
+ * preconditioner, forces, or more than 65536 particles keep some or all of
+ * their own launches inside the same graph.
  *
  * pse_batch_graph_create runs one eager step on the buffers (seed 0,
  * counter 0), then fixes for each replica its block edge, a halo capacity
