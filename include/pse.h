@@ -478,8 +478,11 @@ pse_status pse_batch_sample(pse_batch *batch, uint64_t seed, uint64_t counter, d
 
 /* pse_autotune for the batch: the grid shapes are tuned on the first
  * replica of each (grid, support, precision) group (pse_batch_set_positions
- * first) and the others take its choice; the near-field product is tuned
- * on every replica's own positions.  Synchronises every stream. */
+ * first) and the others take its choice; the near-field product's lanes per
+ * target are tuned on every replica's own positions, and then every replica
+ * of one product kernel form (block edge, halo form, Lanczos scalar type)
+ * takes the choice of most of the form's particles, so that a captured step
+ * runs each form in one launch.  Synchronises every stream. */
 pse_status pse_batch_autotune(pse_batch *batch);
 
 /* GPU milliseconds from the start of the last pse_batch_sample to the end

@@ -1216,6 +1216,35 @@ pse_status pse_batch_autotune(pse_batch *b) {
     const pse_status st = autotune_spmv(c, nullptr);
     if (st != PSE_OK) return st;
   }
+  // then one choice per kernel form (block edge, halo form, Lanczos scalar
+  // type): the one most particles of the form chose.  A captured step runs
+  // each form's replicas in one launch per iteration, so fewer forms mean
+  // fewer, fuller launches; the eager path uses the same choice.
+  struct Tally {
+    int B, unwrap, dbl;
+    long w[5];
+  };
+  std::vector<Tally> t;
+  for (pse_ctx *c : b->ctx) {
+    if (c->dbl || !c->lds_B) continue;
+    const int uw = c->d.nc >= c->lds_B + 3 ? 1 : 0, ad = c->acc_dbl ? 1 : 0;
+    const int G = c->tune_spmv_lanes ? c->tune_spmv_lanes : 3;
+    size_t g = 0;
+    while (g < t.size() && !(t[g].B == c->lds_B && t[g].unwrap == uw && t[g].dbl == ad)) ++g;
+    if (g == t.size()) t.push_back(Tally{c->lds_B, uw, ad, {0, 0, 0, 0, 0}});
+    t[g].w[G] += c->n;
+  }
+  for (pse_ctx *c : b->ctx) {
+    if (c->dbl || !c->lds_B) continue;
+    const int uw = c->d.nc >= c->lds_B + 3 ? 1 : 0, ad = c->acc_dbl ? 1 : 0;
+    for (const Tally &x : t)
+      if (x.B == c->lds_B && x.unwrap == uw && x.dbl == ad) {
+        int best = 3;
+        for (int G = 2; G <= 4; ++G)
+          if (x.w[G] > x.w[best]) best = G;
+        c->tune_spmv_lanes = best;
+      }
+  }
   return PSE_OK;
 }
 
