@@ -902,7 +902,7 @@ def main():
         "comparison": comparison,
         "variants": {k: {kk: v[kk] for kk in ("value", "ms_per_step", "step_ms", "params", "lanczos_iters_mean",
                                                "precond_fallbacks", "autotune", "breakdown_ms", "error", "model",
-                                               "kernels", "neighbor_pairs") if kk in v}
+                                               "kernels", "neighbor_pairs", "fixed_configuration") if kk in v}
                      for k, v in runs.items()},
         "work_model_constants": {"used": consts, "measured_this_run": measured if not args.no_tuned else None},
         "precond_training": [{"xi": k[0], "rc": k[1], "boxes": args.train_boxes, "n": args.train_n,
