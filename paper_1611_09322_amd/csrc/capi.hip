@@ -1269,8 +1269,25 @@ static pse_status ctx_set_positions(pse_ctx *c, const void *pos) {
   return c->dbl ? set_positions_impl<double>(c, pos) : set_positions_impl<float>(c, pos);
 }
 
-// The batched Krylov loop of a captured step: every replica that runs the
-// LDS product (FP32 storage) without the preconditioner, as LzRep records,
+// The forces of replica r in the captured step (null: none).
+static const void *batch_forces(const pse_batch *b, int r) {
+  return b->g_forces.empty() ? nullptr : b->g_forces[r];
+}
+
+// A replica whose whole captured step can run in batched launches: FP32
+// storage on the LDS path, no preconditioner, no repulsion, kT > 0, at most
+// 65536 particles (the Krylov start's partial sums in the single-system
+// layout), and with forces a grid that the tiled spreading covers.
+static bool full_candidate(const pse_batch *b, int r) {
+  const pse_ctx *c = b->ctx[r];
+  if (c->dbl || !c->lds_B || c->pc_on || c->rep_k > 0 || !(c->p.kT > 0) || c->n > kRedBlock * 64) return false;
+  if (batch_forces(b, r) && b->g_dt > 0 && !spread_writes_whole_grid(c->p.grid, c->p.support)) return false;
+  return true;
+}
+
+// A batched Krylov loop of a captured step: every replica with Lanczos
+// scalars of type A that runs the LDS product (FP32 storage) without the
+// preconditioner, as LzRep records,
 // its product blocks grouped by kernel form, and its vector blocks.  Built
 // before the capture (device allocation and copies); the loop runs as many
 // iterations as the replica that queued the most, the others stop
@@ -1302,6 +1319,10 @@ template <typename A> static pse_status lzb_setup(pse_batch *b) {
     q.V = (float4 *)c->V;
     q.st = (LzState<A> *)c->lz;
     q.partials = (A *)c->partials;
+    // the fully batched replicas' M_r F runs in the batched plain product
+    const bool fr = !b->is_full.empty() && b->is_full[r] && batch_forces(b, r) && b->g_dt > 0;
+    q.fs = fr ? (const float4 *)c->vbuf[6] : nullptr;
+    q.ur = (float4 *)c->vbuf[7];
     q.cs = (float)c->d.cs;
     q.L = (float)c->d.L;
     q.invL = (float)(1.0 / c->d.L);
@@ -1427,8 +1448,6 @@ static pse_status nbr_setup(pse_batch *b) {
 // After the replicas' rng_dev is set, before the capture.
 static pse_status full_setup(pse_batch *b) {
   const int R = (int)b->ctx.size();
-  b->is_full.assign(R, 0);
-  if (!b->g_forces.empty()) return PSE_OK;
   std::vector<char> in_lz(R, 0), in_nb(R, 0), in_wv(R, 0);
   for (const auto &z : b->lzb)
     for (int r : z.members) in_lz[r] = 1;
@@ -1442,8 +1461,8 @@ static pse_status full_setup(pse_batch *b) {
       pse_ctx *c = b->ctx[r];
       // 4n vector scalars in at most kRedBlock blocks of 256: the Krylov
       // start's partial sums are laid out as in a single-system launch
-      if (!(in_lz[r] && in_nb[r] && in_wv[r]) || c->dbl || (c->acc_dbl ? 1 : 0) != a || c->n > kRedBlock * 64)
-        continue;
+      if (!b->is_full[r] || (c->acc_dbl ? 1 : 0) != a) continue;
+      if (!(in_lz[r] && in_nb[r] && in_wv[r])) return PSE_ERR_INVALID_ARG;  // the candidate test and the batched sets disagree
       const int k = (int)reps.size(), n = c->n;
       SampRep q{};
       q.pos_in = (const float *)b->g_pos[r];
@@ -1471,9 +1490,12 @@ static pse_status full_setup(pse_batch *b) {
       q.wave = (const float4 *)c->vbuf[4];
       q.out = (float *)b->g_disp[r];
       q.cr = (float)std::sqrt(2.0 * c->p.kT * b->g_dt);
+      q.f_in = b->g_dt > 0 ? (const float *)batch_forces(b, r) : nullptr;
+      q.f_s = (float4 *)c->vbuf[6];
+      q.ur = (float4 *)c->vbuf[7];
+      q.dt = (float)b->g_dt;
       reps.push_back(q);
       f.members.push_back(r);
-      b->is_full[r] = 1;
       for (int q2 = 0; q2 < (c->ncell + 8 + 255) / 256; ++q2) mz.push_back(make_int2(k, q2));
       for (int q2 = 0; q2 < (n + 255) / 256; ++q2) mp.push_back(make_int2(k, q2));
       for (int q2 = 0; q2 < (c->ncell + kScanTile - 1) / kScanTile; ++q2) mt.push_back(make_int2(k, q2));
@@ -1512,18 +1534,22 @@ static pse_status full_setup(pse_batch *b) {
 // replicas' rng_dev is set, before the capture.
 static pse_status wave_setup(pse_batch *b) {
   const int R = (int)b->ctx.size();
-  if (!b->g_forces.empty()) return PSE_OK;
   struct Key {
-    int M, P, nt;
+    int M, P, nt, nw, forces;
   };
   std::vector<Key> keys;
   std::vector<std::vector<int>> mem;
   for (int r = 0; r < R; ++r) {
     pse_ctx *c = b->ctx[r];
     if (c->dbl || !(c->p.kT > 0)) continue;
-    const Key k{c->p.grid, c->p.support, c->tune_interp_threads ? c->tune_interp_threads : 1024};
+    const int M = c->p.grid, forces = batch_forces(b, r) && b->g_dt > 0 ? 1 : 0;
+    if (forces && !spread_writes_whole_grid(M, c->p.support)) continue;  // the atomic spreading stays per replica
+    const int nw = c->tune_spread_nw ? c->tune_spread_nw : (M >= 128 ? 4 : (M >= 64 ? 2 : 1));
+    const Key k{M, c->p.support, c->tune_interp_threads ? c->tune_interp_threads : 1024, nw, forces};
     size_t g = 0;
-    while (g < keys.size() && !(keys[g].M == k.M && keys[g].P == k.P && keys[g].nt == k.nt)) ++g;
+    while (g < keys.size() && !(keys[g].M == k.M && keys[g].P == k.P && keys[g].nt == k.nt && keys[g].nw == k.nw &&
+                                keys[g].forces == k.forces))
+      ++g;
     if (g == keys.size()) {
       keys.push_back(k);
       mem.emplace_back();
@@ -1556,6 +1582,11 @@ static pse_status wave_setup(pse_batch *b) {
       w.invh = (float)(1.0 / h);
       w.inv2s2 = (float)(0.5 / s2);
       w.norm_h3 = (float)(norm * h * h * h);
+      w.f = keys[g].forces ? (const float4 *)c->vbuf[6] : nullptr;
+      w.cell_start = c->cell_start;
+      w.nc = c->d.nc;
+      w.cs = (float)c->d.cs;
+      w.norm = (float)norm;
       reps.push_back(w);
       b->wv_members.push_back(r);
       const int nt = keys[g].nt;
@@ -1572,9 +1603,9 @@ static pse_status wave_setup(pse_batch *b) {
   for (size_t g = 0; g < keys.size(); ++g) {
     const size_t r1 = g + 1 < keys.size() ? span[g + 1].first : reps.size();
     const size_t m1 = g + 1 < keys.size() ? span[g + 1].second : imap.size();
-    b->wv_groups.push_back(WaveGroup{keys[g].M, keys[g].P, keys[g].nt, (int)(r1 - span[g].first),
-                                     (int)(m1 - span[g].second), b->wv_reps + span[g].first,
-                                     b->wv_imap + span[g].second});
+    b->wv_groups.push_back(WaveGroup{keys[g].M, keys[g].P, keys[g].nt, keys[g].nw, keys[g].forces,
+                                     (int)(r1 - span[g].first), (int)(m1 - span[g].second),
+                                     b->wv_reps + span[g].first, b->wv_imap + span[g].second});
   }
   return PSE_OK;
 }
@@ -1610,6 +1641,8 @@ static pse_status batch_capture(pse_batch *b) {
     c->graph_iters = it > c->lz_maxit ? c->lz_maxit : it;
     c->graph_stale = false;
   }
+  b->is_full.assign(R, 0);
+  for (int r = 0; r < R; ++r) b->is_full[r] = full_candidate(b, r) ? 1 : 0;
   pse_status st0 = lzb_setup<float>(b);
   if (st0 == PSE_OK) st0 = lzb_setup<double>(b);
   if (st0 == PSE_OK) st0 = nbr_setup(b);
@@ -1670,6 +1703,17 @@ static pse_status batch_capture(pse_batch *b) {
   }
   if (b->full[0].m.nrep) launch_samp_batch_start<float>(b->gstream, b->full[0].reps, b->full[0].m);
   if (b->full[1].m.nrep) launch_samp_batch_start<double>(b->gstream, b->full[1].reps, b->full[1].m);
+  if (!b->g_forces.empty() && b->g_dt > 0) {
+    // the fully batched replicas' forces in sorted order, and their M_r F
+    for (const auto &f : b->full)
+      if (f.m.nrep) launch_samp_batch_forces(b->gstream, f.reps, f.m);
+    for (int a = 0; a < 2; ++a) {
+      const auto &z = b->lzb[a];
+      if (!z.nrep) continue;
+      if (a) launch_lz_batch_plain<double>(b->gstream, (const LzRep<double> *)z.reps, z.groups.data(), (int)z.groups.size());
+      else launch_lz_batch_plain<float>(b->gstream, (const LzRep<float> *)z.reps, z.groups.data(), (int)z.groups.size());
+    }
+  }
   for (int r = 0; r < R && st == PSE_OK; ++r)
     if (!full(r)) st = ctx_begin(b->ctx[r], 0, 0, b->g_dt, b->g_forces.empty() ? nullptr : b->g_forces[r], ss[r]);
   if (st == PSE_OK && (b->lzb[0].nrep || b->lzb[1].nrep || !b->wv_groups.empty())) {

@@ -708,11 +708,11 @@ __global__ __launch_bounds__(1024) void k_interp(const typename vec4<T>::type *_
 // (fixed particle order), with no grid clear.  Needs M >= 2 max(8, 8 NW) + P
 // so that the nearest periodic image of a base node relative to the tile is
 // unique.
+// lin: the tile (XCD-renumbered linear index over the gx x gy x gz tiles)
 template <typename T, int P, int NW>
-__global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>::type *__restrict__ pos,
-                                                         const typename vec4<T>::type *__restrict__ f,
-                                                         const int *__restrict__ cell_start, int nc, T cs, int M,
-                                                         T h, T invh, T inv2s2, T norm, T *__restrict__ grid) {
+DI void spread_tile_block(const typename vec4<T>::type *__restrict__ pos, const typename vec4<T>::type *__restrict__ f,
+                          const int *__restrict__ cell_start, int nc, T cs, int M, T h, T invh, T inv2s2, T norm,
+                          T *__restrict__ grid, int lin, int gx, int gy) {
   constexpr int TX = 8, TY = 8, TZ = 8 * NW;
   constexpr int NT = 64 * NW;
   using T4 = typename vec4<T>::type;
@@ -721,11 +721,7 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
   __shared__ int ls0[NT];  // first support node per axis (tile-local) + 64, 8 bits each
   __shared__ uint16_t sidx[NW][NT];  // per z slab: list entries whose support reaches it
   __shared__ int scnt[NW][NW];       // [slab][wavefront that listed them]
-  // neighbouring tiles read the same cells: keep them on one XCD
-  const int lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
-                            gridDim.x * gridDim.y * gridDim.z);
-  const int t0x = (lin / (gridDim.x * gridDim.y)) * TX, t0y = ((lin / gridDim.x) % gridDim.y) * TY,
-            t0z = (lin % gridDim.x) * TZ;
+  const int t0x = (lin / (gx * gy)) * TX, t0y = ((lin / gx) % gy) * TY, t0z = (lin % gx) * TZ;
   const int t0[3] = {t0x, t0y, t0z}, tt[3] = {TX, TY, TZ};
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -860,6 +856,17 @@ __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>:
     v.w = T(0);
     g4[col + q] = v;
   }
+}
+
+template <typename T, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>::type *__restrict__ pos,
+                                                         const typename vec4<T>::type *__restrict__ f,
+                                                         const int *__restrict__ cell_start, int nc, T cs, int M,
+                                                         T h, T invh, T inv2s2, T norm, T *__restrict__ grid) {
+  // neighbouring tiles read the same cells: keep them on one XCD
+  const int lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                            gridDim.x * gridDim.y * gridDim.z);
+  spread_tile_block<T, P, NW>(pos, f, cell_start, nc, cs, M, h, invh, inv2s2, norm, grid, lin, gridDim.x, gridDim.y);
 }
 
 // ----------------------------------------------------------- launchers
@@ -1053,11 +1060,36 @@ void launch_spread_interp(pse_ctx *c, bool spread, const void *vec, void *grid_o
 // system of a group at once: the system index is the last grid dimension
 // (x pass, z pass; y pass: component + 3 system) or comes from the block
 // map (interpolation).  Same block bodies as the single-system kernels.
-template <int M, int TZ>
+template <int M, int TZ, bool FORCES>
 __global__ __launch_bounds__(256) void k_xpass_batch(const WaveRep *__restrict__ reps) {
   const WaveRep &r = reps[blockIdx.z];
-  xpass_block<float, M, TZ, 256, false, 1>((C<float> *)r.spec, nullptr, r.wc, (const C<float> *)r.tw_M, blockIdx.x,
-                                           blockIdx.y, gridDim.x, gridDim.y);
+  xpass_block<float, M, TZ, 256, FORCES, 1>((C<float> *)r.spec, nullptr, r.wc, (const C<float> *)r.tw_M, blockIdx.x,
+                                            blockIdx.y, gridDim.x, gridDim.y);
+}
+
+// spreading: grid (M / 8 nw, M / 8, M / 8 per system)
+template <int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_spread_batch(const WaveRep *__restrict__ reps, int gz) {
+  const WaveRep &r = reps[blockIdx.z / gz];
+  const int bz = blockIdx.z % gz;
+  const int lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * bz), gridDim.x * gridDim.y * gz);
+  spread_tile_block<float, P, NW>(r.pos, r.f, r.cell_start, r.nc, r.cs, r.M, r.h, r.invh, r.inv2s2, r.norm, r.rgrid,
+                                  lin, gridDim.x, gridDim.y);
+}
+
+template <int M, int TZ>
+__global__ __launch_bounds__(256) void k_fft_y_fwd_batch(const WaveRep *__restrict__ reps) {
+  constexpr int H = M / 2;
+  const WaveRep &r = reps[blockIdx.z / 3];
+  fft_strided_block<float, M, -1, TZ, 256>((C<float> *)r.spec, (size_t)H, (size_t)M * H, (size_t)M * M * H,
+                                           (const C<float> *)r.tw_M, blockIdx.x, blockIdx.y, blockIdx.z % 3);
+}
+
+template <int M, int NXY>
+__global__ __launch_bounds__(256) void k_fft_z_fwd_batch(const WaveRep *__restrict__ reps) {
+  const WaveRep &r = reps[blockIdx.y];
+  fft_z_aos_block<float, M, -1, NXY, 256>(r.rgrid, r.spec, (const C<float> *)r.tw_H, (const C<float> *)r.tw_M,
+                                          blockIdx.x);
 }
 
 template <int M, int TZ>
@@ -1088,7 +1120,35 @@ template <int M> static void wave_batch_M(hipStream_t s, const WaveGroup &g) {
   constexpr int TZ = GridCfg<float, M>::TZ, TZ1 = GridCfg<float, M>::TZ1;
   constexpr int NX0 = 24576 / (3 * M * (int)sizeof(float));
   constexpr int NXY = NX0 >= 16 ? 16 : (NX0 >= 8 ? 8 : (NX0 >= 4 ? 4 : (NX0 >= 2 ? 2 : 1)));
-  k_xpass_batch<M, TZ><<<dim3(H / TZ, M, g.nrep), 256, 0, s>>>(g.reps);
+  if (g.forces) {
+    auto spread = [&](auto pp, auto ww) {
+      constexpr int PP = decltype(pp)::value, NW = decltype(ww)::value;
+      if constexpr (M % (8 * NW) == 0)
+        k_spread_batch<PP, NW><<<dim3(M / (8 * NW), M / 8, (M / 8) * g.nrep), 64 * NW, 0, s>>>(g.reps, M / 8);
+    };
+    auto by_nw = [&](auto pp) {
+      if (g.nw == 8) spread(pp, std::integral_constant<int, 8>{});
+      else if (g.nw == 4) spread(pp, std::integral_constant<int, 4>{});
+      else if (g.nw == 2) spread(pp, std::integral_constant<int, 2>{});
+      else spread(pp, std::integral_constant<int, 1>{});
+    };
+    switch (g.P) {
+      case 2: by_nw(std::integral_constant<int, 2>{}); break;
+      case 4: by_nw(std::integral_constant<int, 4>{}); break;
+      case 6: by_nw(std::integral_constant<int, 6>{}); break;
+      case 8: by_nw(std::integral_constant<int, 8>{}); break;
+      case 10: by_nw(std::integral_constant<int, 10>{}); break;
+      case 12: by_nw(std::integral_constant<int, 12>{}); break;
+      case 14: by_nw(std::integral_constant<int, 14>{}); break;
+      case 16: by_nw(std::integral_constant<int, 16>{}); break;
+      default: break;
+    }
+    k_fft_z_fwd_batch<M, NXY><<<dim3(M * M / NXY, g.nrep), 256, 0, s>>>(g.reps);
+    k_fft_y_fwd_batch<M, TZ1><<<dim3(H / TZ1, M, 3 * g.nrep), 256, 0, s>>>(g.reps);
+    k_xpass_batch<M, TZ, true><<<dim3(H / TZ, M, g.nrep), 256, 0, s>>>(g.reps);
+  } else {
+    k_xpass_batch<M, TZ, false><<<dim3(H / TZ, M, g.nrep), 256, 0, s>>>(g.reps);
+  }
   k_fft_y_inv_batch<M, TZ1><<<dim3(H / TZ1, M, 3 * g.nrep), 256, 0, s>>>(g.reps);
   k_fft_z_inv_batch<M, NXY><<<dim3(M * M / NXY, g.nrep), 256, 0, s>>>(g.reps);
   switch (g.P) {

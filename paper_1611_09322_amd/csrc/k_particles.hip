@@ -1522,6 +1522,18 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
                                                r.V + (size_t)m * r.n, r.st, r.ovf, nullptr, nullptr, rb.y);
 }
 
+// M_r F of the systems whose record carries forces (the others' blocks exit)
+template <int B, bool UNWRAP, typename A, int G>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmv_lds_batch_plain(
+    const LzRep<A> *__restrict__ reps, const int2 *__restrict__ pmap) {
+  const int2 rb = pmap[blockIdx.x];
+  const LzRep<A> &r = reps[rb.x];
+  if (!r.fs) return;
+  spmv_lds_block<B, UNWRAP, A, false, false, G>(r.pos, r.fs, r.cell_start, r.nc, r.cs, r.n, r.hcap, r.L, r.invL,
+                                                r.nbr, r.cnt, r.tab, r.inv_dr, r.self_r, 1.0f, r.ur, nullptr, nullptr,
+                                                r.ovf, nullptr, nullptr, rb.y);
+}
+
 template <typename A>
 __global__ __launch_bounds__(256) void k_lz_alpha_batch(const LzRep<A> *__restrict__ reps,
                                                         const int2 *__restrict__ vmap, int m) {
@@ -2299,7 +2311,22 @@ __global__ __launch_bounds__(256) void k_combine_batch(const SampRep *__restrict
 __global__ __launch_bounds__(256) void k_finalize_batch(const SampRep *__restrict__ reps, const int2 *__restrict__ map) {
   const int2 rb = map[blockIdx.x];
   const SampRep &r = reps[rb.x];
-  finalize_at<float>(r.perm, r.yr, r.cr, nullptr, 0.0f, r.wave, r.out, r.n, rb.y * 256 + (int)threadIdx.x);
+  finalize_at<float>(r.perm, r.yr, r.cr, r.f_in ? r.ur : nullptr, r.dt, r.wave, r.out, r.n,
+                     rb.y * 256 + (int)threadIdx.x);
+}
+__global__ __launch_bounds__(256) void k_gather_forces_batch(const SampRep *__restrict__ reps,
+                                                             const int2 *__restrict__ map) {
+  const int2 rb = map[blockIdx.x];
+  const SampRep &r = reps[rb.x];
+  const int s = rb.y * 256 + (int)threadIdx.x;
+  if (!r.f_in || s >= r.n) return;
+  const int i = r.perm[s];
+  float4 v;
+  v.x = r.f_in[3 * i];
+  v.y = r.f_in[3 * i + 1];
+  v.z = r.f_in[3 * i + 2];
+  v.w = 0.0f;
+  r.f_s[s] = v;
 }
 
 void launch_samp_batch_bin(hipStream_t s, const SampRep *reps, const SampMaps &m) {
@@ -2309,6 +2336,9 @@ void launch_samp_batch_bin(hipStream_t s, const SampRep *reps, const SampMaps &m
   k_scan_apply_batch<<<m.ntile, kScanNT, 0, s>>>(reps, m.tile);
   k_scatter_batch<<<m.npart, 256, 0, s>>>(reps, m.part);
   k_cell_sort_batch<<<m.ncell, 256, 0, s>>>(reps, m.cell);
+}
+void launch_samp_batch_forces(hipStream_t s, const SampRep *reps, const SampMaps &m) {
+  k_gather_forces_batch<<<m.npart, 256, 0, s>>>(reps, m.part);
 }
 template <typename A> void launch_samp_batch_start(hipStream_t s, const SampRep *reps, const SampMaps &m) {
   k_noise_batch<<<m.npart, 256, 0, s>>>(reps, m.part);
@@ -2323,6 +2353,30 @@ template void launch_samp_batch_start<float>(hipStream_t, const SampRep *, const
 template void launch_samp_batch_start<double>(hipStream_t, const SampRep *, const SampMaps &);
 template void launch_samp_batch_end<float>(hipStream_t, const SampRep *, const SampMaps &);
 template void launch_samp_batch_end<double>(hipStream_t, const SampRep *, const SampMaps &);
+
+template <typename A>
+void launch_lz_batch_plain(hipStream_t s, const LzRep<A> *reps, const LzGroup *groups, int ngroups) {
+  for (int g = 0; g < ngroups; ++g) {
+    const LzGroup &gr = groups[g];
+    with_block_edge(gr.B, [&](auto b) {
+      constexpr int BE = decltype(b)::value;
+      auto go = [&](auto kernel) {
+        allow_lds(kernel, gr.smem);
+        kernel<<<gr.nblk, 1024, gr.smem, s>>>(reps, gr.pmap);
+      };
+      auto pick = [&](auto gl) {
+        constexpr int GL = decltype(gl)::value;
+        if (gr.unwrap) go(k_spmv_lds_batch_plain<BE, true, A, GL>);
+        else go(k_spmv_lds_batch_plain<BE, false, A, GL>);
+      };
+      if (gr.G == 2) pick(std::integral_constant<int, 2>{});
+      else if (gr.G == 4) pick(std::integral_constant<int, 4>{});
+      else pick(std::integral_constant<int, 3>{});
+    });
+  }
+}
+template void launch_lz_batch_plain<float>(hipStream_t, const LzRep<float> *, const LzGroup *, int);
+template void launch_lz_batch_plain<double>(hipStream_t, const LzRep<double> *, const LzGroup *, int);
 
 template void launch_lz_batch_iter<float>(hipStream_t, const LzRep<float> *, int, const LzGroup *, int, const int2 *,
                                           int, int);

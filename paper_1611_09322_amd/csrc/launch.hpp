@@ -80,6 +80,11 @@ void launch_wave_batch(hipStream_t s, const WaveGroup *groups, int ngroups);
 // the fully batched systems of a captured step: binning; noise and Krylov
 // start; combination and final sum (A: the Lanczos scalar type)
 void launch_samp_batch_bin(hipStream_t s, const SampRep *reps, const SampMaps &m);
+// the forces' gather into sorted order (systems with forces)
+void launch_samp_batch_forces(hipStream_t s, const SampRep *reps, const SampMaps &m);
+// M_r F of every system of the groups whose LzRep carries forces
+template <typename A>
+void launch_lz_batch_plain(hipStream_t s, const LzRep<A> *reps, const LzGroup *groups, int ngroups);
 template <typename A> void launch_samp_batch_start(hipStream_t s, const SampRep *reps, const SampMaps &m);
 template <typename A> void launch_samp_batch_end(hipStream_t s, const SampRep *reps, const SampMaps &m);
 // out[r] = flags and Krylov outcome of replica r

@@ -121,6 +121,10 @@ struct SampRep {
   const float4 *wave;   // wave-space part, sorted
   float *out;           // displacement, caller order n x 3
   float cr;             // sqrt(2 kT dt)
+  const float *f_in;    // caller forces n x 3, or null
+  float4 *f_s;          // forces, sorted
+  float4 *ur;           // M_r F, sorted
+  float dt;
 };
 // Workgroup maps (system, block) of the batched launches: zero (blocks of
 // 256 over ncell + 8), part (256 particles), tile (scan tiles), cell (4
@@ -160,6 +164,8 @@ template <typename A> struct LzRep {
   int *ovf;                 // halo overflow flag
   const float4 *z;          // start vector
   float4 *t, *w, *V;        // product, residual, basis [maxit][n]
+  const float4 *fs;         // forces (sorted) of the batched M_r F, or null
+  float4 *ur;               // M_r F
   LzState<A> *st;
   A *partials;              // [0, kRedBlock): |w|^2; [kRedBlock, 2 kRedBlock): alpha_m
   float cs, L, invL, inv_dr, self_r;
@@ -204,8 +210,9 @@ struct WaveCoef {
   const uint64_t *rng;   // device (seed, counter) read in place of the two above, or null
 };
 
-// One system of a batched wave-space part without forces (FP32 storage):
-// the Philox k-space noise through the fused x pass, the inverse y and z
+// One system of a batched wave-space part (FP32 storage): with forces the
+// spreading and the forward z and y passes, then the Philox k-space noise
+// (and the forces' scaling) through the fused x pass, the inverse y and z
 // passes and the interpolation, with the system's own buffers and
 // coefficients.
 struct WaveRep {
@@ -217,12 +224,18 @@ struct WaveRep {
   WaveCoef wc;
   int n, M;
   float h, invh, inv2s2, norm_h3;
+  // with forces: the sorted forces spread onto the interleaved grid
+  const float4 *f;
+  const int *cell_start;
+  int nc;
+  float cs, norm;
 };
-// The systems of one grid size, support and interpolation workgroup size:
-// nrep consecutive WaveRep records; imap lists (system, block) for the
-// interpolation's nimap workgroups.
+// The systems of one grid size, support, interpolation workgroup size,
+// spreading tile depth (8 nw) and forces flag: nrep consecutive WaveRep
+// records; imap lists (system, block) for the interpolation's nimap
+// workgroups.
 struct WaveGroup {
-  int M, P, nt, nrep, nimap;
+  int M, P, nt, nw, forces, nrep, nimap;
   const WaveRep *reps;
   const int2 *imap;
 };
