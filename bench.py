@@ -454,6 +454,19 @@ def run_batch(pse, torch, args):
         redone += red
     dt_g = float(np.median(g_ms)) / 1e3
     b.graph_destroy()
+    # the same step with forces (dt M F joins the sample), captured alike
+    F = [torch.as_tensor(synth.normals(21000 + r, (sp["n"], 3)), dtype=torch.float32, device="cuda")
+         for r, sp in enumerate(specs)]
+    b.graph_create(pos, gout, 1e-3, forces=F, extra_iters=2, headroom=0.25)
+    for k in range(args.warmup):
+        b.graph_step(11, 5000 + k)
+    torch.cuda.synchronize()
+    gf_ms = []
+    for k in range(4 * args.batch_steps):
+        ta = time.perf_counter()
+        b.graph_step(11, 6000 + k)
+        gf_ms.append(1e3 * (time.perf_counter() - ta))
+    b.graph_destroy()
     # the same replicas one after another, each through its own context
     ctxs = [pse.pse_batch_replica(b.b, r) for r in range(len(specs))]
     outs = [torch.empty((sp["n"], 3), dtype=torch.float32, device="cuda") for sp in specs]
@@ -482,6 +495,8 @@ def run_batch(pse, torch, args):
         # every replica of a replay completes with the replay
         "completion_ms": {"p50": float(np.median(g_ms)), "p99": pct(g_ms, 99)},
         "replicas_redone": redone, "lanczos_iters_mean": float(np.mean([s.lanczos_iters for s in gst])),
+        "with_forces": {"value": total / (float(np.median(gf_ms)) / 1e3), "ms_per_step": float(np.median(gf_ms)),
+                        "step_ms": {"p10": pct(gf_ms, 10), "p90": pct(gf_ms, 90)}},
         "multi_stream": {"kind": "eager steps, 8 streams with one host thread each, each replica's own launches",
                          "value": total / dt_b, "ms_per_step": 1e3 * dt_b, "steps": args.batch_steps,
                          "completion_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
