@@ -503,9 +503,13 @@ pse_status pse_batch_latency(pse_batch *batch, float *ms);
  * target; vector kernels and checks for all), wave-space part (grid size,
  * support), combination, final sum and the read-back of every replica's
  * flags and Krylov state, each workgroup finding its replica and block in
- * a table built at capture.  Replicas with FP64 storage, the learned
- * preconditioner, forces, or more than 65536 particles keep some or all of
- * their own launches inside the same graph.
+ * a table built at capture; with forces, the gather of each replica's
+ * forces, its M_r F, its spreading (per grid size and support) and the
+ * forward z and y passes join those launches.  Replicas with FP64 storage,
+ * the learned preconditioner, more than 65536 particles, or forces on a
+ * grid below 32^3 (whose spreading adds with atomics and is therefore not
+ * bit-reproducible) keep some or all of their own launches inside the
+ * same graph.
  *
  * pse_batch_graph_create runs one eager step on the buffers (seed 0,
  * counter 0), then fixes for each replica its block edge, a halo capacity
