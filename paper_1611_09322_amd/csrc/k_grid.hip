@@ -858,6 +858,225 @@ DI void spread_tile_block(const typename vec4<T>::type *__restrict__ pos, const 
   }
 }
 
+// Spreading as a contraction on the matrix cores (FP32).  The window is a
+// product of one-dimensional Gaussians, so over a block of nodes the spread
+// grid is
+//   G_c[x][(y, z)] = sum_p wx_p(x) * (wy_p(y) wz_p(z) f_p,c),
+// a product of a (16 x K) matrix of x weights with a (K x 16) matrix of
+// per-particle (y, z) terms, K the particles whose support reaches the
+// block.  One workgroup owns a tile of 16 x 8 x (8 NW) nodes and lists the
+// particles overlapping it (from the linked cells, as the VALU form does);
+// each of its 4 NW wavefronts owns a 16 x 4 x 4 sub-tile, keeps its own list
+// of the particles that reach it (contiguous, in candidate order) and runs
+// three v_mfma_f32_16x16x4_f32 (one per component) per four listed
+// particles.  Operand layout: lane l holds A[x = l % 16][particle l / 16]
+// and B[particle l / 16][column l % 16], column = 4 y + z; the result gives
+// lane l rows 4 (l / 16) .. + 3 of column l % 16.  Weights outside a
+// particle's P-node support along an axis are exactly zero, so every
+// product outside the P^3 support adds +0.  The particle order, and with it
+// the result, is fixed: no atomics, every node written once.  Needs M a
+// multiple of 16 and 8 NW, M >= 2 max(16, 8 NW) + P.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+template <int P, int NW>
+DI void spread_mfma_block(const float4 *__restrict__ pos, const float4 *__restrict__ f,
+                          const int *__restrict__ cell_start, int nc, float cs, int M, float h, float invh,
+                          float inv2s2, float norm, float *__restrict__ grid, int lin, int gx, int gy) {
+  constexpr int TX = 16, TY = 8, TZ = 8 * NW;
+  constexpr int NV = 4 * NW;  // wavefronts = sub-tiles: 2 along y, 2 NW along z
+  constexpr int NT = 64 * NV;
+  __shared__ float4 lpu[NT + 1];     // image coordinate of the particle nearest the tile
+  __shared__ float4 lf[NT + 1];      // its force
+  __shared__ int ls0[NT + 1];        // first support node per axis (tile-local) + 64, 8 bits each
+  __shared__ uint16_t sidx[NV][NT];  // per sub-tile, contiguous over the listing wavefronts
+  __shared__ __attribute__((aligned(16))) int scnt[NV][NV];  // [sub-tile][wavefront that listed them]
+  __shared__ int colA1[64], colN1[64], colA2[64], colEnd[64];
+  const int t0x = (lin / (gx * gy)) * TX, t0y = ((lin / gx) % gy) * TY, t0z = (lin % gx) * TZ;
+  const int t0[3] = {t0x, t0y, t0z}, tt[3] = {TX, TY, TZ};
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int y0 = 4 * (wave & 1), z0 = 4 * (wave >> 1);  // this wavefront's sub-tile (tile-local)
+  const int half = M / 2;
+  // operand coordinates: particle slot kp of a step; x row (A); column
+  // (B) = node (y0 + yc, z0 + zc)
+  const int kp = lane >> 4, col = lane & 15, yc = col >> 2, zc = col & 3;
+  f32x4_t acc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  if (threadIdx.x == 0) {  // the empty entry: support offsets -64 reach no node of the tile
+    lpu[NT] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    lf[NT] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    ls0[NT] = 0;
+  }
+  int cl[3], cn[3];
+  {
+    const float inv_cs = 1.0f / cs;
+    for (int d = 0; d < 3; ++d) {
+      const float lo = (float)(t0[d] - P / 2) * h, hi = (float)(t0[d] + tt[d] - 1 + P / 2) * h;
+      const int a = (int)floorf(lo * inv_cs - 1e-4f), b = (int)floorf(hi * inv_cs + 1e-4f);
+      if (b - a + 1 >= nc) {
+        cl[d] = 0;
+        cn[d] = nc;
+      } else {
+        cl[d] = ((a % nc) + nc) % nc;
+        cn[d] = b - a + 1;
+      }
+    }
+  }
+  // the (x, y) cell columns covering the tile, taken 64 at a time; their
+  // z runs are concatenated so that each listing round takes NT candidates
+  const int ncol = cn[0] * cn[1];
+  for (int cb = 0; cb < ncol; cb += 64) {
+    const int nb = min(64, ncol - cb);
+    __syncthreads();  // the previous batch's columns are no longer read
+    if (threadIdx.x < 64) {
+      int a1 = 0, n1 = 0, a2 = 0, nt = 0;
+      if ((int)threadIdx.x < nb) {
+        const int cidx = cb + (int)threadIdx.x;
+        const int cx = (cl[0] + cidx / cn[1]) % nc, cy = (cl[1] + cidx % cn[1]) % nc;
+        const int base = (cx * nc + cy) * nc;
+        // z cells cl[2] .. cl[2]+cn[2]-1 (mod nc): one or two contiguous runs
+        const int z1 = cl[2] + cn[2] - 1;
+        a1 = cell_start[base + cl[2]];
+        const int b1 = cell_start[base + (z1 >= nc ? nc - 1 : z1) + 1];
+        a2 = cell_start[base];
+        const int b2 = z1 >= nc ? cell_start[base + (z1 - nc) + 1] : a2;
+        n1 = b1 - a1;
+        nt = n1 + (b2 - a2);
+      }
+      // inclusive prefix of the run lengths over the 64 lanes
+      int pre = nt;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(pre, o, 64);
+        if (lane >= o) pre += v;
+      }
+      colA1[lane] = a1;
+      colN1[lane] = n1;
+      colA2[lane] = a2;
+      colEnd[lane] = pre;
+    }
+    __syncthreads();
+    const int ntot = colEnd[63];
+    {
+      for (int c0 = 0; c0 < ntot; c0 += NT) {
+        const int ci = c0 + (int)threadIdx.x;
+        int t = 0, s0[3] = {0, 0, 0};
+        float pu[3] = {0.0f, 0.0f, 0.0f};
+        bool hit = false;
+        if (ci < ntot) {
+          // the column holding candidate ci: the first with colEnd > ci
+          int j = 0;
+#pragma unroll
+          for (int st = 32; st > 0; st >>= 1)
+            if (colEnd[j + st - 1] <= ci) j += st;
+          const int loc = ci - (j > 0 ? colEnd[j - 1] : 0);
+          t = loc < colN1[j] ? colA1[j] + loc : colA2[j] + (loc - colN1[j]);
+          const float4 q = pos[t];
+          const float qc[3] = {q.x, q.y, q.z};
+          hit = true;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const int b = min((int)(qc[d] * invh), M - 1);
+            // nearest image in [-M/2, M/2): b - t0 + M/2 lies in (-M/2, 3M/2)
+            int r = b - t0[d] + half;
+            r += r < 0 ? M : 0;
+            r -= r >= M ? M : 0;
+            const int dd = r - half;
+            s0[d] = dd - P / 2 + 1;
+            pu[d] = qc[d] + (float)(t0[d] + dd - b) * h;
+            hit = hit && (s0[d] <= tt[d] - 1) && (s0[d] + P - 1 >= 0);
+          }
+        }
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const unsigned long long bal = __ballot(hit);
+        const int e = 64 * wave + __popcll(bal & below);
+        // sub-tiles reached: y quarters ylo..yhi, z quarters zlo..zhi
+        const int ylo = s0[1] > 0 ? s0[1] >> 2 : 0, yhi = min(1, (s0[1] + P - 1) >> 2);
+        const int zlo = s0[2] > 0 ? s0[2] >> 2 : 0, zhi = min(2 * NW - 1, (s0[2] + P - 1) >> 2);
+        unsigned long long bw[NV];
+#pragma unroll
+        for (int w = 0; w < NV; ++w) {
+          const int qy = w & 1, qz = w >> 1;
+          bw[w] = __ballot(hit && qy >= ylo && qy <= yhi && qz >= zlo && qz <= zhi);
+          if (lane == 0) scnt[w][wave] = __popcll(bw[w]);
+        }
+        if (hit) {
+          lpu[e] = make_float4(pu[0], pu[1], pu[2], 0.0f);
+          const float4 fv = f[t];
+          lf[e] = make_float4(fv.x, fv.y, fv.z, 0.0f);
+          ls0[e] = (s0[0] + 64) | ((s0[1] + 64) << 8) | ((s0[2] + 64) << 16);
+        }
+        __syncthreads();
+        // sub-tile lists in listing-wavefront order: lane w < NV sums the
+        // counts of sub-tile w (its offset for this wavefront and its total)
+        int offl = 0, totl = 0;
+        if (lane < NV) {
+#pragma unroll
+          for (int from = 0; from < NV; ++from) {
+            const int cw = scnt[lane][from];
+            totl += cw;
+            offl += from < wave ? cw : 0;
+          }
+        }
+#pragma unroll
+        for (int w = 0; w < NV; ++w) {
+          const int off = __builtin_amdgcn_readlane(offl, w);
+          if ((bw[w] >> lane) & 1ull) sidx[w][off + __popcll(bw[w] & below)] = (uint16_t)e;
+        }
+        const int total = __builtin_amdgcn_readlane(totl, wave);
+        __syncthreads();
+        // steps of four list entries; slots past the end read the empty
+        // entry NT (zero force, support out of reach), so the loop is
+        // branch-free.  The next step's entry is read while this one runs.
+        auto entry = [&](int k) {
+          const int idx = k + kp;
+          const int ee = sidx[wave][min(idx, total - 1)];
+          return idx < total ? ee : NT;
+        };
+        int ee_n = entry(0);
+        float4 pv_n = lpu[ee_n], fv_n = lf[ee_n];
+        int sp_n = ls0[ee_n];
+        for (int k = 0; k < total; k += 4) {
+          const float4 pv = pv_n, fv = fv_n;
+          const int sp = sp_n;
+          ee_n = entry(k + 4);
+          pv_n = lpu[ee_n];
+          fv_n = lf[ee_n];
+          sp_n = ls0[ee_n];
+          const int ix = col - ((sp & 255) - 64), iy = y0 + yc - (((sp >> 8) & 255) - 64),
+                    iz = z0 + zc - (((sp >> 16) & 255) - 64);
+          const float dx = (float)(t0x + col) * h - pv.x, dy = (float)(t0y + y0 + yc) * h - pv.y,
+                      dz = (float)(t0z + z0 + zc) * h - pv.z;
+          const float ex = norm * gauss_exp(-dx * dx * inv2s2), eyz = gauss_exp(-(dy * dy + dz * dz) * inv2s2);
+          const float wx = (unsigned)ix < (unsigned)P ? ex : 0.0f;
+          const float wyz = ((unsigned)iy < (unsigned)P && (unsigned)iz < (unsigned)P) ? eyz : 0.0f;
+          acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx, wyz * fv.x, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx, wyz * fv.y, acc[1], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx, wyz * fv.z, acc[2], 0, 0, 0);
+        }
+        __syncthreads();  // the list and the counts are rewritten next
+      }
+    }
+  }
+  auto *g4 = (float4 *)grid;  // interleaved nodes
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const size_t node = ((size_t)(t0x + 4 * kp + v) * M + (t0y + y0 + yc)) * M + t0z + z0 + zc;
+    g4[node] = make_float4(acc[0][v], acc[1][v], acc[2][v], 0.0f);
+  }
+}
+
+template <int P, int NW>
+__global__ __launch_bounds__(256 * NW) void k_spread_mfma(const float4 *__restrict__ pos,
+                                                          const float4 *__restrict__ f,
+                                                          const int *__restrict__ cell_start, int nc, float cs, int M,
+                                                          float h, float invh, float inv2s2, float norm,
+                                                          float *__restrict__ grid) {
+  const int lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                            gridDim.x * gridDim.y * gridDim.z);
+  spread_mfma_block<P, NW>(pos, f, cell_start, nc, cs, M, h, invh, inv2s2, norm, grid, lin, gridDim.x, gridDim.y);
+}
+
 template <typename T, int P, int NW>
 __global__ __launch_bounds__(64 * NW) void k_spread_tile(const typename vec4<T>::type *__restrict__ pos,
                                                          const typename vec4<T>::type *__restrict__ f,
@@ -1001,6 +1220,24 @@ static bool spread_tiled(int M, int P) {
 }
 bool spread_writes_whole_grid(int M, int P) { return spread_tiled(M, P); }
 
+// FP32 spreading runs on the matrix cores (k_spread_mfma: tiles 16 x 8 x
+// 8 nw, 4 nw wavefronts, nw <= 4) where the grid allows, the VALU tiles
+// (8 x 8 x 8 nw) elsewhere.
+constexpr bool kSpreadOnMatrixCores = true;
+static bool spread_mfma_valid(int M, int P, int nw) {
+  const int tz = 8 * nw, tmax = tz > 16 ? tz : 16;
+  return kSpreadOnMatrixCores && nw <= 4 && M % 16 == 0 && M % tz == 0 && M >= 2 * tmax + P;
+}
+
+// Built-in tile depth (8 nw): the matrix-core form is fastest with the
+// smallest tiles (16 x 8 x 8, measured at 256^3 to 512^3); the VALU tiles
+// with 8 x 8 x 32 from 128^3 up (measured best at 256^3 against depths 16
+// and 64).
+int spread_default_nw(int M, int P, bool fp32) {
+  if (fp32 && spread_mfma_valid(M, P, 1)) return 1;
+  return M >= 128 ? 4 : (M >= 64 ? 2 : 1);
+}
+
 template <typename T, int P>
 static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid_or_out) {
   using T4 = typename vec4<T>::type;
@@ -1013,14 +1250,21 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
     if (spread_tiled(M, P)) {
       auto go = [&](auto nw) {
         constexpr int NW = decltype(nw)::value;
+        if constexpr (std::is_same<T, float>::value && NW <= 4) {
+          if (spread_mfma_valid(M, P, NW)) {
+            k_spread_mfma<P, NW><<<dim3(M / (8 * NW), M / 8, M / 16), 256 * NW, 0, c->stream>>>(
+                (const float4 *)c->pos_s, (const float4 *)vec, c->cell_start, c->d.nc, (float)c->d.cs, M, (float)h,
+                (float)(1.0 / h), (float)(0.5 / s2), (float)norm, (float *)grid_or_out);
+            return;
+          }
+        }
         const dim3 g(M / (8 * NW), M / 8, M / 8);
         k_spread_tile<T, P, NW><<<g, 64 * NW, 0, c->stream>>>(
             (const T4 *)c->pos_s, (const T4 *)vec, c->cell_start, c->d.nc, (T)c->d.cs, M, (T)h, (T)(1.0 / h),
             (T)(0.5 / s2), (T)norm, (T *)grid_or_out);
       };
-      // built-in: tiles 8 x 8 x 32 from 128^3 up (measured best at 256^3
-      // against depths 16 and 64); pse_autotune may pick another valid depth
-      const int nw = c->tune_spread_nw ? c->tune_spread_nw : (M >= 128 ? 4 : (M >= 64 ? 2 : 1));
+      // pse_autotune may pick another valid depth than the built-in one
+      const int nw = c->tune_spread_nw ? c->tune_spread_nw : spread_default_nw(M, P, std::is_same<T, float>::value);
       if (nw == 8) go(std::integral_constant<int, 8>{});
       else if (nw == 4) go(std::integral_constant<int, 4>{});
       else if (nw == 2) go(std::integral_constant<int, 2>{});
@@ -1077,6 +1321,16 @@ __global__ __launch_bounds__(64 * NW) void k_spread_batch(const WaveRep *__restr
                                   lin, gridDim.x, gridDim.y);
 }
 
+// the matrix-core form: grid (M / 8 nw, M / 8, M / 16 per system)
+template <int P, int NW>
+__global__ __launch_bounds__(256 * NW) void k_spread_mfma_batch(const WaveRep *__restrict__ reps, int gz) {
+  const WaveRep &r = reps[blockIdx.z / gz];
+  const int bz = blockIdx.z % gz;
+  const int lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * bz), gridDim.x * gridDim.y * gz);
+  spread_mfma_block<P, NW>(r.pos, r.f, r.cell_start, r.nc, r.cs, r.M, r.h, r.invh, r.inv2s2, r.norm, r.rgrid, lin,
+                           gridDim.x, gridDim.y);
+}
+
 template <int M, int TZ>
 __global__ __launch_bounds__(256) void k_fft_y_fwd_batch(const WaveRep *__restrict__ reps) {
   constexpr int H = M / 2;
@@ -1123,8 +1377,16 @@ template <int M> static void wave_batch_M(hipStream_t s, const WaveGroup &g) {
   if (g.forces) {
     auto spread = [&](auto pp, auto ww) {
       constexpr int PP = decltype(pp)::value, NW = decltype(ww)::value;
-      if constexpr (M % (8 * NW) == 0)
+      if constexpr (M % (8 * NW) == 0) {
+        if constexpr (NW <= 4 && M % 16 == 0) {
+          if (spread_mfma_valid(M, PP, NW)) {
+            k_spread_mfma_batch<PP, NW><<<dim3(M / (8 * NW), M / 8, (M / 16) * g.nrep), 256 * NW, 0, s>>>(g.reps,
+                                                                                                       M / 16);
+            return;
+          }
+        }
         k_spread_batch<PP, NW><<<dim3(M / (8 * NW), M / 8, (M / 8) * g.nrep), 64 * NW, 0, s>>>(g.reps, M / 8);
+      }
     };
     auto by_nw = [&](auto pp) {
       if (g.nw == 8) spread(pp, std::integral_constant<int, 8>{});
@@ -1262,7 +1524,7 @@ template <typename T> pse_status autotune_grid(pse_ctx *c, int32_t *choice) {
   c->tune_spread_nw = st == PSE_OK && best_nw ? best_nw : keep_nw;
   c->tune_interp_threads = st == PSE_OK && best_nt ? best_nt : keep_nt;
   if (choice) {
-    choice[0] = 8 * (c->tune_spread_nw ? c->tune_spread_nw : (M >= 128 ? 4 : (M >= 64 ? 2 : 1)));
+    choice[0] = 8 * (c->tune_spread_nw ? c->tune_spread_nw : spread_default_nw(M, P, std::is_same<T, float>::value));
     choice[1] = c->tune_interp_threads ? c->tune_interp_threads : 1024;
     if (!spread_tiled(M, P)) choice[0] = 0;
   }

@@ -105,6 +105,8 @@ template <typename T> void launch_spread_interp(pse_ctx *c, bool spread, const v
 // atomic fallback): no separate clear is needed.  Interpolation reads the
 // packed grid that the inverse z pass writes.
 bool spread_writes_whole_grid(int M, int P);
+// built-in spreading tile depth / 8 for a grid, support and precision
+int spread_default_nw(int M, int P, bool fp32);
 // times the valid spreading tile depths and interpolation workgroup sizes on
 // the current positions and keeps the fastest (c->tune_*)
 template <typename T> pse_status autotune_grid(pse_ctx *c, int32_t *choice);
