@@ -5,7 +5,10 @@ the oracle's direct Fourier sums on the same inputs and noise:
   then interpolation) at N = 1000, phi = 0.1, 64^3 (owner-computes spreading
   tiles), P = 2 ... 16;
 - a 16^3 grid, where the tiles do not fit and spreading uses atomics, at
-  P = 2 and 4 (FP64 against the oracle, FP32 against FP64).
+  P = 2 and 4 (FP64 against the oracle, FP32 against FP64);
+- radix-3 grids, and a clustered configuration (a dense blob in a sparse
+  box: tiles with several listing rounds beside empty tiles) on the
+  matrix-core (FP32) and VALU (FP64) spreading tiles.
 
 Bar: the window's error is the paper's quadrature bound at m = sqrt(pi P)
 plus the aliasing estimate of the grid spacing (both computed on the host
@@ -114,3 +117,29 @@ def test_radix3_grids_match_direct_sums(gpu_lib, M, precision):
     b = bar(L, M, 8, precision)
     check(y, y_ref, b, f"M={M} {precision} sample")
     check(u, u_ref, b, f"M={M} {precision} apply")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_clustered_particles_and_empty_tiles(gpu_lib, precision):
+    """A dense blob (1200 spheres at phi = 0.45 in a 22a cube) in a 48a box
+    with 300 spheres scattered around it, 64^3: the tiles over the blob list
+    several hundred candidates (several listing rounds of the tiled
+    spreading), most other tiles none.  M_w F and the wave sample against
+    the direct Fourier sums."""
+    blob, L0 = synth.hard_spheres(1200, 0.45, seed=1400)
+    L, M = 48.0, 64
+    x = np.concatenate([blob + 3.0, synth.uniform_positions(300, L, seed=1401)])
+    n = len(x)
+    W = synth.normals(1402, (3, M, M, M))
+    F = synth.normals(1403, (n, 3))
+    s = gpu_lib.Sampler(n, L, xi=XI, rcut=RC, grid=M, support=8, tol=1e-6, precision=precision)
+    s.set_positions(dev(x, s.dtype))
+    y = host(s.wave_sample(dev(W, s.dtype)))
+    u = host(s.wave_apply(dev(F, s.dtype)))
+    s.close()
+    y_ref = ewald.wave_sample_direct(x, ewald.zeta_from_grid_noise(W), L, 1.0, 1.0, XI)
+    u_ref = ewald.wave_apply_direct(x, F, M, L, 1.0, 1.0, XI)
+    b = bar(L, M, 8, precision)
+    print(f"blob side {L0:.1f}a", flush=True)
+    check(y, y_ref, b, f"clustered {precision} sample")
+    check(u, u_ref, b, f"clustered {precision} apply")
