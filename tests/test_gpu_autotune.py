@@ -161,3 +161,38 @@ def test_block_edge_follows_cell_occupancy(gpu_lib, n, rc, edge):
     check(host(y), host(yr), 1e-5, f"block edge {edge}: Krylov sample vs FP64", skip_rows=cutoff_rows(x, L, rc))
     s.close()
     r.close()
+
+
+def test_spreading_tile_depths_agree(gpu_lib):
+    """M_w F (FP32) at every valid spreading tile depth: the matrix-core
+    tiles (16 x 8 x depth, depths 8 to 32) against the direct Fourier sums
+    and against each other (each sub-tile lists its particles in candidate
+    order at every depth; they agree to rounding, or exactly); on a 192^3
+    grid the VALU tiles (8 x 8 x 64) against the matrix-core ones."""
+    import torch
+
+    x, L = synth.hard_spheres(2000, 0.2, seed=2300, sweeps=5)
+    F = synth.normals(2301, (len(x), 3))
+    Fd = torch.as_tensor(F, dtype=torch.float32, device="cuda")
+    u_ref = ewald.wave_apply_direct(x, F, 128, L, 1.0, 1.0, XI)
+    out = {}
+    s = gpu_lib.Sampler(len(x), L, xi=XI, rcut=RC, grid=128, support=P, tol=1e-6, precision="fp32")
+    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    for depth in (8, 16, 32):
+        s.set_launch_shape(depth, 0, 0)
+        out[depth] = host(s.wave_apply(Fd))
+        check(out[depth], u_ref, 1e-4, f"M_w F, 128^3, tile depth {depth}, vs direct sums")
+    s.close()
+    for depth in (16, 32):
+        check(out[depth], out[8], 1e-6, f"M_w F, tile depth {depth} vs 8")
+    # 192^3: depth 64 takes the VALU tiles, depth 8 the matrix cores
+    s = gpu_lib.Sampler(len(x), L, xi=XI, rcut=RC, grid=192, support=P, tol=1e-6, precision="fp32")
+    s.set_positions(torch.as_tensor(x, dtype=torch.float32, device="cuda"))
+    u = {}
+    for depth in (8, 64):
+        s.set_launch_shape(depth, 0, 0)
+        u[depth] = host(s.wave_apply(Fd))
+    s.close()
+    # two FP32 summation schemes for every node (per-lane FMAs against 4-term
+    # matrix-core steps): the FP32 rounding floor of the other wave tests
+    check(u[64], u[8], 1e-5, "M_w F, 192^3, VALU tiles (depth 64) vs matrix-core tiles (depth 8)")
