@@ -631,6 +631,60 @@ def ptps_sweep(pse, torch, args):
     return out
 
 
+def phi_sweep(pse, torch, args):
+    """Sec. III (Fig. phiall): time of one step (neighbour rebuild and one
+    Brownian sample, mixed precision, tolerance 1e-3) against xi for hard
+    spheres at several volume fractions and fixed N.  At each xi the error
+    model picks rc, the grid and the support; the work model's own xi* is
+    reported beside the measured optimum.  The paper finds the optimum
+    moving to larger xi as phi grows while the optimal time stays about
+    the same."""
+    import synth
+
+    out = []
+    n = args.phi_sweep_n
+    for phi in args.phi_sweep_phis:
+        t0 = time.time()
+        x, L = synth.hard_spheres(n, phi, seed=3300 + int(round(100 * phi)), sweeps=0 if phi <= synth.RSA_MAX_PHI else 10)
+        pos = torch.as_tensor(x, dtype=torch.float32, device="cuda")
+        out_v = torch.empty_like(pos)
+        base = pse.make_params(n, L, precision="mixed")
+        p_star, info = pse.pse_choose_params(base, pse.Tuning(tol=1e-3, max_grid=512))
+        rows = []
+        for xi in args.phi_sweep_xis:
+            try:
+                p, _ = pse.pse_choose_params(base, pse.Tuning(tol=1e-3, xi=xi, max_grid=512))
+            except pse.PSEError as e:
+                rows.append({"xi": xi, "rejected": str(e)})
+                continue
+            p.lanczos_max_iter = 64
+            s = pse.Sampler(n, L, params=p)
+
+            def step(k=0):
+                s.set_positions(pos)
+                return s.sample(11, k, out=out_v)[1]
+
+            step()
+            torch.cuda.synchronize()
+            reps = 5
+            ta = time.perf_counter()
+            for k in range(reps):
+                st = step(k + 1)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - ta) / reps
+            rows.append({**params_summary(p), "ms": 1e3 * t, "ptps": n / t, "lanczos_iters": st.lanczos_iters})
+            s.close()
+        ok = [r for r in rows if "ms" in r]
+        best = min(ok, key=lambda r: r["ms"]) if ok else None
+        entry = {"phi": phi, "L": round(L, 3), "start": start_of(phi), "rows": rows,
+                 "measured_optimum": {"xi": best["xi"], "ms": best["ms"], "ptps": best["ptps"]} if best else None,
+                 "work_model_optimum": {"xi": round(p_star.xi, 4), "model_ms": 1e3 * info.model_seconds}}
+        out.append(entry)
+        log(f"phi sweep phi={phi}: optimum {entry['measured_optimum']}, model {entry['work_model_optimum']} "
+            f"({time.time() - t0:.1f}s)")
+    return {"n": n, "tol": 1e-3, "precision": "mixed", "per_phi": out}
+
+
 # ------------------------------------------------------------ CPU baseline
 def gel_experiment(pse, torch, args):
     """The learned preconditioner's own workload and Sec. III's gel
@@ -778,6 +832,11 @@ def main():
                     default=[8_000, 16_000, 32_000, 64_000, 128_000, 256_000, 512_000, 1_024_000, 2_048_000])
     ap.add_argument("--full-lanczos-max-n", type=int, default=128_000,
                     help="largest N of the sweep at which the full-mobility Lanczos comparator also runs")
+    ap.add_argument("--no-phi-sweep", action="store_true", help="skip the xi sweep at several volume fractions (Fig. phiall)")
+    ap.add_argument("--phi-sweep-n", type=int, default=512_000)
+    ap.add_argument("--phi-sweep-phis", type=lambda v: [float(t) for t in v.split(",")], default=[0.1, 0.2, 0.3, 0.4])
+    ap.add_argument("--phi-sweep-xis", type=lambda v: [float(t) for t in v.split(",")],
+                    default=[0.25, 0.3, 0.35, 0.4, 0.45, 0.5, 0.55, 0.6, 0.7, 0.8])
     ap.add_argument("--no-tolerance", action="store_true", help="skip the tolerance experiment (Fig. parity)")
     ap.add_argument("--no-gel", action="store_true", help="skip the gel workload (Fig. gel, learned preconditioner)")
     ap.add_argument("--gel-n", type=int, default=500_000)
@@ -882,6 +941,7 @@ def main():
         log(f"batch: {json.dumps(batched)}")
     tolx = None if args.no_tolerance else tolerance_experiment(pse, torch, args)
     ptps = None if args.no_ptps else ptps_sweep(pse, torch, args)
+    phis = None if args.no_phi_sweep else phi_sweep(pse, torch, args)
     gel = None if args.no_gel else gel_experiment(pse, torch, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     w = head.split("@")[1]
@@ -927,6 +987,7 @@ def main():
         "batched": batched,
         "tolerance_experiment": tolx,
         "ptps": ptps,
+        "phi_sweep": phis,
         "gel": gel,
         "cpu_baseline": cpu,
     }

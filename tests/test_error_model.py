@@ -208,6 +208,25 @@ def test_fixed_xi_and_the_work_model_optimum():
     assert p2.xi >= p.xi
 
 
+def test_optimum_moves_to_larger_xi_with_volume_fraction():
+    """Sec. III (Fig. phiall) through eq. (work): real-space work grows
+    as phi xi^-3 and the grid as xi^3 / phi at fixed N, so the work model's
+    xi* grows with phi (as phi^(1/3) without the grid sizes' steps) while
+    the optimal time, 2 sqrt of the product of the two coefficients, does
+    not depend on phi.  512,000 hard spheres, tolerance 1e-3."""
+    pse = lib()
+    n = 512_000
+    xs, ts = [], []
+    for phi in (0.1, 0.2, 0.3, 0.4):
+        L = (n * 4.0 * math.pi / (3.0 * phi)) ** (1.0 / 3.0)
+        p, info = pse.pse_choose_params(pse.make_params(n, L, precision="mixed"), pse.Tuning(tol=1e-3, max_grid=512))
+        xs.append(p.xi)
+        ts.append(info.model_seconds)
+    assert all(b >= a for a, b in zip(xs, xs[1:])), xs
+    assert xs[-1] / xs[0] > 1.3, xs
+    assert max(ts) / min(ts) < 1.25, ts
+
+
 def test_infeasible_box_is_rejected():
     pse = lib()
     # in a 3a box the cutoff must stay below 1.5a, where the real-space tail
