@@ -540,8 +540,10 @@ pse_status pse_batch_graph_destroy(pse_batch *batch);
 
 /* Launch-shape autotuning.  Times, on the context's current positions
  * (pse_set_positions first; PSE_ERR_NO_POSITIONS otherwise), every valid
- * depth of the owner-computes spreading tiles (8 x 8 x D nodes, D in 8, 16,
- * 32, 64: D divides M and M >= 2 max(8, D) + P), the interpolation
+ * depth D of the owner-computes spreading tiles (D in 8, 16, 32, 64: D
+ * divides M and M >= 2 max(8, D) + P; tiles of 8 x 8 x D nodes, or in FP32
+ * the matrix-core tiles of 16 x 8 x D where D <= 32, 16 divides M and
+ * M >= 2 max(16, D) + P), the interpolation
  * workgroup sizes 256, 512 and 1024 lanes, and 2, 3 and 4 lanes per target
  * particle in the LDS near-field product (FP32 storage), three timed
  * launches each after a warm-up, and keeps the fastest for later calls
