@@ -888,7 +888,9 @@ DI void spread_mfma_block(const float4 *__restrict__ pos, const float4 *__restri
   __shared__ float4 lf[NT + 1];      // its force
   __shared__ int ls0[NT + 1];        // first support node per axis (tile-local) + 64, 8 bits each
   __shared__ uint16_t sidx[NV][NT];  // per sub-tile, contiguous over the listing wavefronts
-  __shared__ __attribute__((aligned(16))) int scnt[NV][NV];  // [sub-tile][wavefront that listed them]
+  __shared__ int scnt[NV][NV];       // [sub-tile][wavefront that listed them]
+  // the cell columns of one batch: start and length of the first z run,
+  // start of the wrapped second run, inclusive prefix of the run lengths
   __shared__ int colA1[64], colN1[64], colA2[64], colEnd[64];
   const int t0x = (lin / (gx * gy)) * TX, t0y = ((lin / gx) % gy) * TY, t0z = (lin % gx) * TZ;
   const int t0[3] = {t0x, t0y, t0z}, tt[3] = {TX, TY, TZ};
