@@ -209,7 +209,7 @@ pse_status pse_derive(const pse_params *p, pse_derived *out);
  * are seconds per near-field pair per product, per particle-node of one
  * spreading or interpolation, per M^3 log2 M^3 of the FFT set, per
  * particle; 0 selects values measured on MI355X at 10^6 spheres
- * (1.5e-12, 7.4e-13, 1.5e-12, 3.8e-10).  Host only, no GPU. */
+ * (1.8e-12, 7.4e-13, 1.5e-12, 3.8e-10).  Host only, no GPU. */
 typedef struct {
   double tol;          /* target relative error of every source, (0, 1) */
   double xi;           /* > 0: keep this xi; 0: choose it */

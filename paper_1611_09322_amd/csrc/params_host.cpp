@@ -259,7 +259,7 @@ pse_status choose_params(const pse_params &base, const pse_tuning &tin, pse_para
   if (!(t.tol > 0 && t.tol < 1)) return PSE_ERR_INVALID_ARG;
   if (base.n < 1 || !(base.box > 0) || !(base.a > 0)) return PSE_ERR_INVALID_ARG;
   if (t.n_iter <= 0) t.n_iter = 5.0;
-  if (t.c_pair <= 0) t.c_pair = 1.5e-12;
+  if (t.c_pair <= 0) t.c_pair = 1.8e-12;
   if (t.c_node <= 0) t.c_node = 7.4e-13;
   if (t.c_fft <= 0) t.c_fft = 1.5e-12;
   if (t.c_particle <= 0) t.c_particle = 3.8e-10;
