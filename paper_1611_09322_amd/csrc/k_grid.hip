@@ -232,17 +232,15 @@ __global__ __launch_bounds__(BLOCK) void k_fft_z(const C<T> *__restrict__ src, C
   }
 }
 
-// z pass between the real grid (nodes [x][y][z]) and the planar half
-// spectrum: the three component lines of NXY (x, y) columns are transformed
-// together, so every node vector is read or written once, whole.  Forward
-// (DIR < 0): real -> spectrum, from the interleaved grid that spreading
-// writes (one (c0, c1, c2, 0) vector per node); inverse (DIR > 0): spectrum
-// -> real, into the packed grid that interpolation reads (c0, c1, c2 per
-// node, no padding).  Same packing of the half spectrum as k_fft_z.
+// z pass between the real grid (nodes [x][y][z], packed: c0, c1, c2 per
+// node, no padding) and the planar half spectrum: the three component lines
+// of NXY (x, y) columns are transformed together, so every node is read or
+// written once, whole.  Forward (DIR < 0): real -> spectrum, from the grid
+// that spreading writes; inverse (DIR > 0): spectrum -> real, into the grid
+// that interpolation reads.  Same packing of the half spectrum as k_fft_z.
 template <typename T, int M, int DIR, int NXY, int BLOCK>
 DI void fft_z_aos_block(const void *__restrict__ src, void *__restrict__ dst, const C<T> *__restrict__ twH_g,
                         const C<T> *__restrict__ twM_g, int bx) {
-  using T4 = typename vec4<T>::type;
   constexpr int H = M / 2, NL = 3 * NXY;
   __shared__ C<T> buf[H * NL];
   __shared__ C<T> twH[H];
@@ -255,13 +253,15 @@ DI void fft_z_aos_block(const void *__restrict__ src, void *__restrict__ dst, co
   const size_t s_comp = (size_t)M * M;  // spectrum lines per component
   __syncthreads();
   if (DIR < 0) {
+    // packed input: nodes 2k and 2k + 1 are six consecutive values
+    // (c0, c1, c2, c0, c1, c2), read as three pairs
     for (int e = threadIdx.x; e < H * NXY; e += BLOCK) {
       const int k = e % H, l = e / H;
-      const T4 *ln = (const T4 *)src + (xy0 + l) * M;
-      const T4 a = ln[2 * k], b = ln[2 * k + 1];
-      buf[k * NL + l] = cmk<T>(a.x, b.x);
-      buf[k * NL + NXY + l] = cmk<T>(a.y, b.y);
-      buf[k * NL + 2 * NXY + l] = cmk<T>(a.z, b.z);
+      const C<T> *ln = (const C<T> *)src + (xy0 + l) * (3 * H) + 3 * k;
+      const C<T> p0 = ln[0], p1 = ln[1], p2 = ln[2];
+      buf[k * NL + l] = cmk<T>(p0.x, p1.y);
+      buf[k * NL + NXY + l] = cmk<T>(p0.y, p2.x);
+      buf[k * NL + 2 * NXY + l] = cmk<T>(p1.x, p2.y);
     }
   } else {
     for (int e = threadIdx.x; e < H * NL; e += BLOCK) {
@@ -555,9 +555,9 @@ __global__ __launch_bounds__(256) void k_spread(const typename vec4<T>::type *__
     for (int iz = 0; iz < P; ++iz) {
       const T w = wxy * wz[iz];
       const size_t g = row + iz_m[iz];
-      unsafeAtomicAdd(&grid[4 * g], w * fx);  // interleaved nodes (c0, c1, c2, 0)
-      unsafeAtomicAdd(&grid[4 * g + 1], w * fy);
-      unsafeAtomicAdd(&grid[4 * g + 2], w * fz);
+      unsafeAtomicAdd(&grid[3 * g], w * fx);  // packed nodes (c0, c1, c2)
+      unsafeAtomicAdd(&grid[3 * g + 1], w * fy);
+      unsafeAtomicAdd(&grid[3 * g + 2], w * fz);
     }
   }
 }
@@ -846,15 +846,12 @@ DI void spread_tile_block(const typename vec4<T>::type *__restrict__ pos, const 
     }
   }
   const size_t col = ((size_t)(t0x + lx) * M + (t0y + ly)) * M + t0z + zw;
-  auto *g4 = (typename vec4<T>::type *)grid;  // interleaved nodes
+  // packed nodes (c0, c1, c2): the column's 8 nodes are 24 consecutive values
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    typename vec4<T>::type v;
-    v.x = acc[0][q];
-    v.y = acc[1][q];
-    v.z = acc[2][q];
-    v.w = T(0);
-    g4[col + q] = v;
+    grid[3 * (col + q)] = acc[0][q];
+    grid[3 * (col + q) + 1] = acc[1][q];
+    grid[3 * (col + q) + 2] = acc[2][q];
   }
 }
 
@@ -1060,11 +1057,13 @@ DI void spread_mfma_block(const float4 *__restrict__ pos, const float4 *__restri
       }
     }
   }
-  auto *g4 = (float4 *)grid;  // interleaved nodes
+  // packed nodes (c0, c1, c2)
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const size_t node = ((size_t)(t0x + 4 * kp + v) * M + (t0y + y0 + yc)) * M + t0z + z0 + zc;
-    g4[node] = make_float4(acc[0][v], acc[1][v], acc[2][v], 0.0f);
+    grid[3 * node] = acc[0][v];
+    grid[3 * node + 1] = acc[1][v];
+    grid[3 * node + 2] = acc[2][v];
   }
 }
 
@@ -1133,7 +1132,7 @@ static void fft_z(pse_ctx *c, const void *src, void *dst, int dir) {
                                                          (const CT *)c->tw_M);
 }
 
-// z pass on the interleaved real grid: NXY (x, y) columns (3 NXY lines) per
+// z pass on the packed real grid: NXY (x, y) columns (3 NXY lines) per
 // workgroup, at most 24 KB of LDS (six workgroups per CU)
 template <typename T, int M>
 static void fft_z_aos(pse_ctx *c, const void *src, void *dst, int dir) {
@@ -1272,7 +1271,7 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
       else if (nw == 2) go(std::integral_constant<int, 2>{});
       else go(std::integral_constant<int, 1>{});
     } else {
-      launch_zero_words(c->stream, grid_or_out, sizeof(T) * (size_t)M * M * M);  // 4 components
+      launch_zero_words(c->stream, grid_or_out, sizeof(T) * (size_t)M * M * M * 3 / 4);  // 3 components
       k_spread<T, P><<<blocks, 256, 0, c->stream>>>((const T4 *)c->pos_s, (const T4 *)vec, n, (T *)grid_or_out, M,
                                                     (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)norm);
     }

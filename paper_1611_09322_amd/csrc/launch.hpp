@@ -92,18 +92,18 @@ void launch_batch_status(hipStream_t s, const RepStatusSrc *src, int nrep, RepSt
 
 // grid side (k_grid.hip)
 //   FftZ:       a = src, b = dst, x = direction (-1 forward R2C, +1 inverse C2R)
-//   FftZAos:    as FftZ with the real side one vector per node: forward
-//               reads the interleaved grid ((c0, c1, c2, 0) per node),
-//               inverse writes the packed grid ((c0, c1, c2) per node)
+//   FftZAos:    as FftZ with the real side one packed vector (c0, c1, c2)
+//               per node: forward reads the grid that spreading writes,
+//               inverse writes the grid that interpolation reads
 //   FftStrided: b = data, x = axis (0: x, 1: y), y = direction
 //   XFused:     a = transformed grid-noise spectrum (or null), b = data,
 //               x = forces present, y = noise (0 none, 1 Philox, 2 grid noise)
 template <typename T> void launch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoef *wc, int x, int y);
 template <typename T> void launch_spread_interp(pse_ctx *c, bool spread, const void *vec, void *grid_or_out);
-// Spreading writes the interleaved real grid (one (c0, c1, c2, 0) vector per
-// node) and clears it itself (every node written once, or cleared before the
-// atomic fallback): no separate clear is needed.  Interpolation reads the
-// packed grid that the inverse z pass writes.
+// Spreading writes the packed real grid ((c0, c1, c2) per node) and clears
+// it itself (every node written once, or cleared before the atomic
+// fallback): no separate clear is needed.  Interpolation reads the packed
+// grid that the inverse z pass writes.
 bool spread_writes_whole_grid(int M, int P);
 // built-in spreading tile depth / 8 for a grid, support and precision
 int spread_default_nw(int M, int P, bool fp32);

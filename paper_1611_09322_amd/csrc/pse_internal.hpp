@@ -224,7 +224,7 @@ struct WaveRep {
   WaveCoef wc;
   int n, M;
   float h, invh, inv2s2, norm_h3;
-  // with forces: the sorted forces spread onto the interleaved grid
+  // with forces: the sorted forces spread onto the packed grid
   const float4 *f;
   const int *cell_start;
   int nc;
@@ -340,8 +340,8 @@ struct pse_ctx {
   double series_h[2 * pse::kSeriesTerms];
   double small_r2 = 0;      // r^2 below which the series is used
   void *grid = nullptr;     // T [3 M^3]: planar half spectrum [c][jx][jy][jz < M/2] (complex)
-  void *rgrid = nullptr;    // T4 [M^3]: real grid, nodes [x][y][z]: interleaved (c0, c1, c2, 0) after
-                            // spreading, packed (c0, c1, c2) after the inverse z pass
+  void *rgrid = nullptr;    // T [3 M^3] (allocated 4 M^3): real grid, nodes [x][y][z], packed
+                            // (c0, c1, c2) per node
   void *grid2 = nullptr;    // T [3 M^3]: spectrum of caller grid noise W (absent with PSE_FLAG_NOISE_KSPACE)
   void *tw_M = nullptr;     // T2 [M] twiddles exp(-2 pi i k / M)
   void *tw_H = nullptr;     // T2 [M/2]
