@@ -507,9 +507,9 @@ pse_status pse_batch_latency(pse_batch *batch, float *ms);
  * forces, its M_r F, its spreading (per grid size and support) and the
  * forward z and y passes join those launches.  Replicas with FP64 storage,
  * the learned preconditioner, more than 65536 particles, or forces on a
- * grid below 32^3 (whose spreading adds with atomics and is therefore not
- * bit-reproducible) keep some or all of their own launches inside the
- * same graph.
+ * grid too small for the 8 x 8 x 8 spreading tiles (M < 16 + P, whose
+ * spreading adds with atomics and is therefore not bit-reproducible) keep
+ * some or all of their own launches inside the same graph.
  *
  * pse_batch_graph_create runs one eager step on the buffers (seed 0,
  * counter 0), then fixes for each replica its block edge, a halo capacity

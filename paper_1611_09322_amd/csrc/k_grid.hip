@@ -1212,14 +1212,18 @@ void launch_grid_op(pse_ctx *c, GridOp op, const void *a, void *b, const WaveCoe
   }
 }
 
-// Tiled spreading needs M >= 2 max(TX, TY, TZ) + P (unique nearest image);
-// the tile edge along z is min(64, M/4) and 8 along x and y.
-static bool spread_tiled(int M, int P) {
-  const int tz = M >= 128 ? 32 : (M >= 64 ? 16 : 8);  // tile depth 8 NW of the launch below
-  const int tmax = tz > 8 ? tz : 8;
-  return M >= 32 && M >= 2 * tmax + P;
-}
+// Tiled spreading needs M >= 2 max(TX, TY, TZ) + P (unique nearest image):
+// the smallest tiles, 8 x 8 x 8 nodes, need M >= 16 + P; smaller grids
+// spread with atomics.
+static bool spread_tiled(int M, int P) { return M % 8 == 0 && M >= 16 + P; }
 bool spread_writes_whole_grid(int M, int P) { return spread_tiled(M, P); }
+
+// Spreading tile depth nw is valid when the tile (8 x 8 x 8 nw) divides the
+// grid and the nearest periodic image stays unique: M >= 2 max(8, 8 nw) + P.
+static bool spread_nw_valid(int M, int P, int nw) {
+  const int tz = 8 * nw, tmax = tz > 8 ? tz : 8;
+  return M % tz == 0 && M >= 2 * tmax + P;
+}
 
 // FP32 spreading runs on the matrix cores (k_spread_mfma: tiles 16 x 8 x
 // 8 nw, 4 nw wavefronts, nw <= 4) where the grid allows, the VALU tiles
@@ -1236,7 +1240,9 @@ static bool spread_mfma_valid(int M, int P, int nw) {
 // and 64).
 int spread_default_nw(int M, int P, bool fp32) {
   if (fp32 && spread_mfma_valid(M, P, 1)) return 1;
-  return M >= 128 ? 4 : (M >= 64 ? 2 : 1);
+  int nw = M >= 128 ? 4 : (M >= 64 ? 2 : 1);
+  while (nw > 1 && !spread_nw_valid(M, P, nw)) nw >>= 1;
+  return nw;
 }
 
 template <typename T, int P>
@@ -1450,13 +1456,6 @@ void launch_wave_batch(hipStream_t s, const WaveGroup *groups, int ngroups) {
 template void launch_grid_op<float>(pse_ctx *, GridOp, const void *, void *, const WaveCoef *, int, int);
 template void launch_grid_op<double>(pse_ctx *, GridOp, const void *, void *, const WaveCoef *, int, int);
 template void launch_spread_interp<float>(pse_ctx *, bool, const void *, void *);
-
-// Spreading tile depth nw is valid when the tile (8 x 8 x 8 nw) divides the
-// grid and the nearest periodic image stays unique: M >= 2 max(8, 8 nw) + P.
-static bool spread_nw_valid(int M, int P, int nw) {
-  const int tz = 8 * nw, tmax = tz > 8 ? tz : 8;
-  return M % tz == 0 && M >= 2 * tmax + P;
-}
 
 bool grid_shape_valid(int M, int P, int depth, int interp_lanes) {
   if (depth != 0) {

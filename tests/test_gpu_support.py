@@ -99,8 +99,8 @@ def test_atomic_spreading_on_small_grids(gpu_lib, P):
 def test_radix3_grids_match_direct_sums(gpu_lib, M, precision):
     """Grids of 3 x 2^k points (mixed radix-2/3 FFT plans): the wave sample
     and M_w F against the direct Fourier sums over the same k-set; boxes sized
-    so that h is about 0.6a (spreading tiles where the grid allows them,
-    atomics on 24^3)."""
+    so that h is about 0.6a (VALU spreading tiles on 24^3 and in FP64,
+    matrix-core tiles from 48^3 up in FP32)."""
     n = {24: 60, 48: 400, 96: 1000, 192: 800}[M]
     L = 0.6 * M
     x = synth.uniform_positions(n, L, seed=1300 + M)
