@@ -1228,10 +1228,9 @@ static bool spread_nw_valid(int M, int P, int nw) {
 // FP32 spreading runs on the matrix cores (k_spread_mfma: tiles 16 x 8 x
 // 8 nw, 4 nw wavefronts, nw <= 4) where the grid allows, the VALU tiles
 // (8 x 8 x 8 nw) elsewhere.
-constexpr bool kSpreadOnMatrixCores = true;
 static bool spread_mfma_valid(int M, int P, int nw) {
   const int tz = 8 * nw, tmax = tz > 16 ? tz : 16;
-  return kSpreadOnMatrixCores && nw <= 4 && M % 16 == 0 && M % tz == 0 && M >= 2 * tmax + P;
+  return nw <= 4 && M % 16 == 0 && M % tz == 0 && M >= 2 * tmax + P;
 }
 
 // Built-in tile depth (8 nw): the matrix-core form is fastest with the
