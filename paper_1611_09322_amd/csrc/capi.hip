@@ -1545,7 +1545,7 @@ static pse_status wave_setup(pse_batch *b) {
     const int M = c->p.grid, forces = batch_forces(b, r) && b->g_dt > 0 ? 1 : 0;
     if (forces && !spread_writes_whole_grid(M, c->p.support)) continue;  // the atomic spreading stays per replica
     const int nw = c->tune_spread_nw ? c->tune_spread_nw : spread_default_nw(M, c->p.support, true);
-    const Key k{M, c->p.support, c->tune_interp_threads ? c->tune_interp_threads : 1024, nw, forces};
+    const Key k{M, c->p.support, c->tune_interp_threads ? c->tune_interp_threads : kInterpLanes, nw, forces};
     size_t g = 0;
     while (g < keys.size() && !(keys[g].M == k.M && keys[g].P == k.P && keys[g].nt == k.nt && keys[g].nw == k.nw &&
                                 keys[g].forces == k.forces))

@@ -1281,9 +1281,10 @@ static void spread_interp_P(pse_ctx *c, bool spread, const void *vec, void *grid
                                                     (T)h, (T)(1.0 / h), (T)(0.5 / s2), (T)norm);
     }
   } else {
-    // built-in: 16 particles (consecutive in cell order) per workgroup share
-    // the L1
-    const int nt = c->tune_interp_threads ? c->tune_interp_threads : 1024;
+    // built-in: 8 particles (consecutive in cell order) per workgroup share
+    // the L1 (the autotuner's choice at 64^3 to 384^3; 1024 lanes took 2.0
+    // against 1.5 ms at 384^3 with 4 10^6 spheres)
+    const int nt = c->tune_interp_threads ? c->tune_interp_threads : kInterpLanes;
     k_interp<T, P><<<(int)(((long)n * 64 + nt - 1) / nt), nt, 0, c->stream>>>(
         (const T4 *)c->pos_s, (const T *)vec, n, (T4 *)grid_or_out, M, (T)h, (T)(1.0 / h), (T)(0.5 / s2),
         (T)(norm * h * h * h));
@@ -1524,7 +1525,7 @@ template <typename T> pse_status autotune_grid(pse_ctx *c, int32_t *choice) {
   c->tune_interp_threads = st == PSE_OK && best_nt ? best_nt : keep_nt;
   if (choice) {
     choice[0] = 8 * (c->tune_spread_nw ? c->tune_spread_nw : spread_default_nw(M, P, std::is_same<T, float>::value));
-    choice[1] = c->tune_interp_threads ? c->tune_interp_threads : 1024;
+    choice[1] = c->tune_interp_threads ? c->tune_interp_threads : kInterpLanes;
     if (!spread_tiled(M, P)) choice[0] = 0;
   }
   return st;

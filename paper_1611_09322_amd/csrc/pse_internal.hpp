@@ -22,6 +22,7 @@ constexpr int kRedBlock = 1024;
 constexpr int kScanPer = 16, kScanNT = 256, kScanTile = kScanPer * kScanNT;
 constexpr int kRepBuf = 10;      // work vector holding the overlap repulsion of the Brownian step  // workgroups (partial sums) of the vector reductions
 constexpr size_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit
+constexpr int kInterpLanes = 512;         // built-in interpolation workgroup (one wavefront per particle)
 // largest dynamic + table LDS of one workgroup of the staged near-field kernels
 constexpr size_t kLdsBudget = 150 * 1024;
 // static LDS of the staged near-field product beside its F/G table: the
