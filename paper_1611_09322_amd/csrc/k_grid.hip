@@ -405,6 +405,14 @@ template <typename T> DI C<T> zeta_at(uint64_t e, uint64_t seed, uint64_t sample
 //   with B = sinc^2(ka) H(k, xi) / k^2 (eq. Mwave), ghat = exp(-k^2 sigma^2 / 2);
 //   inverse x-FFT; store.  zeta: Philox (NOISE = 1) or the transformed grid
 //   noise times M^{-3/2} (NOISE = 2).  k = 0 and Nyquist indices give 0.
+// k-space scaling functions: FP64 takes the library's exponential and
+// division; FP32 the hardware base-2 exponential (exponents <= 0) and
+// reciprocal, each within about an ulp, far below the window's error
+template <typename T> DI T ks_exp(T x) { return exp(x); }
+template <typename T> DI T ks_rcp(T x) { return T(1) / x; }
+template <> DI float ks_exp<float>(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+template <> DI float ks_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <typename T, int M, int TZ, int BLOCK, bool FORCES, int NOISE>
 DI void xpass_block(C<T> *__restrict__ data, const C<T> *__restrict__ specW, WaveCoef wc,
                     const C<T> *__restrict__ tw_g, int bx, int by, int gx, int gy) {
@@ -461,19 +469,21 @@ DI void xpass_block(C<T> *__restrict__ data, const C<T> *__restrict__ specW, Wav
         const T k2 = kx * kx + ky * ky + kz * kz;
         const T kk = sqrt(k2);
         const T ka = kk * (T)wc.a;
-        const T sinc = sin(ka) / ka;
+        const T sinc = sin(ka) * ks_rcp(ka);
         const T q = k2 * (T)wc.inv_4xi2;
         const T gs = k2 * (T)wc.sigma2;
+        // e^{(gs - q) / 2}: its square scales the deterministic term
+        const T eh = ks_exp(T(0.5) * (gs - q));
         C<T> v[3];
         for (int c = 0; c < 3; ++c) v[c] = cmk<T>(0, 0);
         if (FORCES) {
-          const T det = (T)wc.det_scale * sinc * sinc * (T(1) + q) / k2 * exp(gs - q);
+          const T det = (T)wc.det_scale * sinc * sinc * (T(1) + q) * ks_rcp(k2) * (eh * eh);
 #pragma unroll
           for (int c = 0; c < 3; ++c) v[c] = cscale(buf[jx * NCOLS + c * TZ + col], det);
         }
         if (NOISE) {
           // B^{1/2} is the non-negative root: |sinc(ka)| (sinc changes sign for ka > pi)
-          const T sto = (T)wc.sto_scale * fabs(sinc) * sqrt(T(1) + q) / kk * exp(T(0.5) * (gs - q));
+          const T sto = (T)wc.sto_scale * fabs(sinc) * sqrt(T(1) + q) * ks_rcp(kk) * eh;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             C<T> z;
